@@ -1,0 +1,220 @@
+"""FP64 CPU oracle for the GB template + likelihood hot path (arXiv:2405.04690).
+
+TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the benchmark's
+CPU-baseline leg may import this package; the product path never does.  It
+shares no code with the HIP library.  The C source is ``gbl_oracle.c``; this
+module compiles it with gcc and exposes numpy-level wrappers.
+
+Every function follows the paper's statement of the problem (Sec. 2,
+eqs. like/inner/addsource/swapsource; Sec. 3, eq. psd) plus the waveform
+reading documented in ``gbl_oracle.c``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "gbl_oracle.c")
+_LIB = os.path.join(_HERE, "libgbl_oracle.so")
+
+C_LIGHT = 299792458.0
+AU = 1.495978707e11
+YEAR = 31557600.0
+
+
+def build() -> str:
+    """Compile the oracle with gcc (plain -O2, OpenMP over templates only)."""
+    cmd = ["gcc", "-O2", "-std=gnu11", "-fPIC", "-shared", "-fopenmp", "-o", _LIB + ".tmp", _SRC, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+class Config(ctypes.Structure):
+    _fields_ = [("T", ctypes.c_double), ("dt", ctypes.c_double), ("L", ctypes.c_double),
+                ("f_lo", ctypes.c_double), ("f_hi", ctypes.c_double)]
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build()
+        lib = ctypes.CDLL(_LIB)
+        D = ctypes.POINTER(ctypes.c_double)
+        I32 = ctypes.POINTER(ctypes.c_int32)
+        I64 = ctypes.POINTER(ctypes.c_int64)
+        C = ctypes.POINTER(Config)
+        sig = {
+            "gblo_set_threads": (ctypes.c_int, [ctypes.c_int]),
+            "gblo_band": (ctypes.c_int, [C, I64, I64]),
+            "gblo_orbit_position": (None, [C, ctypes.c_int, ctypes.c_double, D]),
+            "gblo_source_frame": (None, [D, D, D]),
+            "gblo_link_response": (ctypes.c_double, [C, D, ctypes.c_int, ctypes.c_int, ctypes.c_double]),
+            "gblo_link_envelope": (None, [C, D, ctypes.c_int64, ctypes.c_int, ctypes.c_int, ctypes.c_double, D]),
+            "gblo_fft": (ctypes.c_int, [ctypes.c_int, D]),
+            "gblo_waveform": (ctypes.c_int, [C, D, ctypes.c_int64, ctypes.c_int, D, D, D, I64]),
+            "gblo_psd_value": (ctypes.c_double, [C, ctypes.c_double, ctypes.c_double, ctypes.c_double]),
+            "gblo_psd_eval": (ctypes.c_int, [C, D, ctypes.c_int64, D]),
+            "gblo_loglike": (ctypes.c_double, [C, D, D]),
+            "gblo_psd_loglike": (ctypes.c_int, [C, D, ctypes.c_int32, D, I32, ctypes.c_int64, D]),
+            "gblo_delta_loglike": (ctypes.c_int, [C, D, ctypes.c_int32, D, ctypes.c_int32, ctypes.c_int32, D, D,
+                                                  ctypes.c_int32, I32, I32, ctypes.c_int64, D, D]),
+            "gblo_scatter_add": (ctypes.c_int, [C, D, ctypes.c_int64, ctypes.c_int32, ctypes.c_double, D,
+                                                ctypes.c_int32, I32]),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def _d(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _i32(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+
+
+def _i64(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _check(rc, what):
+    if rc != 0:
+        raise ValueError(f"oracle {what} failed with status {rc}")
+
+
+class Oracle:
+    """Oracle bound to one run configuration (T, dt, L, band)."""
+
+    def __init__(self, T: float, dt: float, L: float = 2.5e9, f_lo: float = 1e-4, f_hi: float = 3e-2):
+        self.lib = _load()
+        self.cfg = Config(T, dt, L, f_lo, f_hi)
+        kmin = np.zeros(1, np.int64)
+        nb = np.zeros(1, np.int64)
+        self.lib.gblo_band(ctypes.byref(self.cfg), _i64(kmin), _i64(nb))
+        self.k_min = int(kmin[0])
+        self.n_bins = int(nb[0])
+        self.T, self.dt, self.L = T, dt, L
+        self.df = 1.0 / T
+
+    # threads used by the batched calls (OpenMP over templates)
+    def set_threads(self, n: int) -> int:
+        return int(self.lib.gblo_set_threads(int(n)))
+
+    def orbit_position(self, i: int, t: float) -> np.ndarray:
+        x = np.zeros(3)
+        self.lib.gblo_orbit_position(ctypes.byref(self.cfg), int(i), float(t), _d(x))
+        return x
+
+    def source_frame(self, p):
+        p = _f64(p)
+        k = np.zeros(3)
+        H = np.zeros((3, 3, 2))
+        self.lib.gblo_source_frame(_d(p), _d(k), _d(H))
+        return k, H[..., 0] + 1j * H[..., 1]
+
+    def link_response(self, p, s: int, r: int, t: float) -> float:
+        p = _f64(p)
+        return float(self.lib.gblo_link_response(ctypes.byref(self.cfg), _d(p), s, r, float(t)))
+
+    def link_envelope(self, p, q: int, s: int, r: int, t: float) -> complex:
+        p = _f64(p)
+        out = np.zeros(2)
+        self.lib.gblo_link_envelope(ctypes.byref(self.cfg), _d(p), int(q), s, r, float(t), _d(out))
+        return complex(out[0], out[1])
+
+    def fft(self, x) -> np.ndarray:
+        x = np.ascontiguousarray(x, dtype=np.complex128).copy()
+        v = x.view(np.float64)
+        _check(self.lib.gblo_fft(len(x), _d(v)), "fft")
+        return x
+
+    def waveform(self, params, N: int, with_T: bool = True):
+        params = _f64(params).reshape(-1, 8)
+        B = params.shape[0]
+        A = np.zeros((B, N), np.complex128)
+        E = np.zeros((B, N), np.complex128)
+        Tc = np.zeros((B, N), np.complex128) if with_T else None
+        sb = np.zeros(B, np.int64)
+        rc = self.lib.gblo_waveform(ctypes.byref(self.cfg), _d(params), B, int(N), _d(A.view(np.float64)),
+                                    _d(E.view(np.float64)),
+                                    _d(Tc.view(np.float64)) if with_T else None, _i64(sb))
+        _check(rc, "waveform")
+        return A, E, Tc, sb
+
+    def psd_value(self, f: float, sqrt_oms: float, sqrt_acc: float) -> float:
+        return float(self.lib.gblo_psd_value(ctypes.byref(self.cfg), float(f), float(sqrt_oms), float(sqrt_acc)))
+
+    def psd_eval(self, noise) -> np.ndarray:
+        noise = _f64(noise).reshape(-1, 4)
+        P = noise.shape[0]
+        S = np.zeros((P, 2, self.n_bins))
+        _check(self.lib.gblo_psd_eval(ctypes.byref(self.cfg), _d(noise), P, _d(S)), "psd_eval")
+        return S
+
+    def loglike(self, R, S) -> float:
+        R = np.ascontiguousarray(R, dtype=np.complex128).reshape(2, self.n_bins)
+        S = _f64(S).reshape(2, self.n_bins)
+        return float(self.lib.gblo_loglike(ctypes.byref(self.cfg), _d(R.view(np.float64)), _d(S)))
+
+    def psd_loglike(self, residual, noise, res_idx) -> np.ndarray:
+        residual = np.ascontiguousarray(residual, dtype=np.complex128).reshape(-1, 2, self.n_bins)
+        noise = _f64(noise).reshape(-1, 4)
+        res_idx = np.ascontiguousarray(res_idx, dtype=np.int32)
+        P = noise.shape[0]
+        out = np.zeros(P)
+        rc = self.lib.gblo_psd_loglike(ctypes.byref(self.cfg), _d(residual.view(np.float64)), residual.shape[0],
+                                       _d(noise), _i32(res_idx), P, _d(out))
+        _check(rc, "psd_loglike")
+        return out
+
+    def delta_loglike(self, residual, psd, params_old, params_new, N: int, res_idx=None, psd_idx=None,
+                      psd_is_inverse: bool = False, return_terms: bool = False):
+        residual = np.ascontiguousarray(residual, dtype=np.complex128).reshape(-1, 2, self.n_bins)
+        psd = _f64(psd).reshape(-1, 2, self.n_bins)
+        po = _f64(params_old).reshape(-1, 8)
+        pn = _f64(params_new).reshape(-1, 8)
+        B = po.shape[0]
+        if res_idx is None:
+            res_idx = np.zeros(B, np.int32)
+        if psd_idx is None:
+            psd_idx = np.zeros(B, np.int32)
+        res_idx = np.ascontiguousarray(res_idx, dtype=np.int32)
+        psd_idx = np.ascontiguousarray(psd_idx, dtype=np.int32)
+        out = np.zeros(B)
+        terms = np.zeros((B, 6))
+        rc = self.lib.gblo_delta_loglike(ctypes.byref(self.cfg), _d(residual.view(np.float64)), residual.shape[0],
+                                         _d(psd), psd.shape[0], int(bool(psd_is_inverse)), _d(po), _d(pn), int(N),
+                                         _i32(res_idx), _i32(psd_idx), B, _d(out), _d(terms))
+        _check(rc, "delta_loglike")
+        return (out, terms) if return_terms else out
+
+    def scatter_add(self, params, N: int, sign: float, residual, res_idx=None):
+        """In place: residual[res_idx[b]] += sign * template b (A, E)."""
+        params = _f64(params).reshape(-1, 8)
+        B = params.shape[0]
+        assert residual.dtype == np.complex128 and residual.flags.c_contiguous
+        res3 = residual.reshape(-1, 2, self.n_bins)
+        if res_idx is None:
+            res_idx = np.zeros(B, np.int32)
+        res_idx = np.ascontiguousarray(res_idx, dtype=np.int32)
+        rc = self.lib.gblo_scatter_add(ctypes.byref(self.cfg), _d(params), B, int(N), float(sign),
+                                       _d(res3.view(np.float64)), res3.shape[0], _i32(res_idx))
+        _check(rc, "scatter_add")
+        return residual
