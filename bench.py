@@ -1,0 +1,175 @@
+#!/usr/bin/env python3
+"""Benchmark: GB template dlogL evaluations per second at 1 yr, N = 256.
+
+Workload (the paper-scale configuration): 1 yr of A/E data at 5 s cadence
+(943,573 analysis bins in 0.1-30 mHz), 32 walker residuals (each its own
+noise realisation + 130 injected binaries - that walker's cold-chain
+templates), and a batch of 32 walkers x 24 temperatures x 130 sources = 99,840
+swap proposals (old, new) at template width N = 256.  One step = one batched
+gb_delta_loglike launch over the whole batch.  Inputs are synthetic and seeded
+and are resident in HBM before the timed region starts.
+
+Prints one JSON line with the metric, a roofline entry for the dominant kernel
+(timed on its own stream with HIP events) and the CPU oracle's rate on a
+bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, HERE)
+
+FP64_PEAK_TFLOPS = 78.6   # MI355X FP64 vector (256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz)
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--mix", default="inmodel", choices=["inmodel", "full"])
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    return ap.parse_args()
+
+
+def build_workload(ctx, torch, mix):
+    from paper_2405_04690_amd import inputs
+    cfg = inputs.PAPER
+    dev = ctx.device
+    batch = inputs.paper_swap_batch(mix=mix)
+    nw, ns = batch.n_walkers, len(batch.sources)
+    noise = torch.tensor([[cfg.sqrt_oms, cfg.sqrt_acc, cfg.sqrt_oms, cfg.sqrt_acc]], dtype=torch.float64,
+                         device=dev)
+    S = ctx.gb_psd_eval(noise)                    # [1, 2, nb]
+    invS = ctx.gb_psd_eval(noise, inverse=True)
+    R = torch.empty((nw, 2, ctx.n_bins), dtype=torch.complex128, device=dev)
+    for w in range(nw):
+        g = torch.from_numpy(inputs.complex_normals(3 + w, (1, 2, ctx.n_bins))).to(dev)
+        R[w:w + 1] = ctx.gb_make_noise(S, g)
+    inj = torch.from_numpy(np.tile(batch.sources, (nw, 1))).to(dev)
+    ridx = torch.from_numpy(np.repeat(np.arange(nw), ns).astype(np.int32)).to(dev)
+    ctx.gb_scatter_add(inj, cfg.N, 1.0, R, ridx)
+    cold = torch.from_numpy(np.ascontiguousarray(batch.params_old[: nw * ns])).to(dev)
+    ctx.gb_scatter_add(cold, cfg.N, -1.0, R, torch.from_numpy(batch.res_idx[: nw * ns]).to(dev))
+    po = torch.from_numpy(batch.params_old).to(dev)
+    pn = torch.from_numpy(batch.params_new).to(dev)
+    ri = torch.from_numpy(batch.res_idx).to(dev)
+    pi = torch.zeros_like(ri)
+    torch.cuda.synchronize()
+    return cfg, batch, R, invS, po, pn, ri, pi
+
+
+def cpu_baseline(batch, cfg, target_s):
+    """The FP64 oracle on a bounded sample of the same swap batch."""
+    import oracle
+    from paper_2405_04690_amd import inputs
+    cores = len(os.sched_getaffinity(0))
+    orc = oracle.Oracle(T=cfg.T, dt=cfg.dt, L=cfg.L, f_lo=cfg.f_lo, f_hi=cfg.f_hi)
+    threads = orc.set_threads(cores)
+    # residuals for 4 walkers (the oracle touches only the template windows)
+    nw = 4
+    S = orc.psd_eval(np.array([cfg.sqrt_oms, cfg.sqrt_acc, cfg.sqrt_oms, cfg.sqrt_acc]))
+    amp = np.sqrt(S[0] / (4 * orc.df))
+    R = np.empty((nw, 2, orc.n_bins), np.complex128)
+    for w in range(nw):
+        R[w] = amp * inputs.complex_normals(3 + w, (2, orc.n_bins))
+    sel = np.nonzero(batch.res_idx < nw)[0]
+    po, pn, ri = batch.params_old[sel], batch.params_new[sel], batch.res_idx[sel]
+    pz = np.zeros(len(sel), np.int32)
+    n = 16 * threads
+    t0 = time.perf_counter()
+    orc.delta_loglike(R, S, po[:n], pn[:n], cfg.N, ri[:n], pz[:n])
+    dt = time.perf_counter() - t0
+    n2 = int(min(len(sel), max(n, n * target_s / max(dt, 1e-6))))
+    t0 = time.perf_counter()
+    orc.delta_loglike(R, S, po[:n2], pn[:n2], cfg.N, ri[:n2], pz[:n2])
+    dt2 = time.perf_counter() - t0
+    return {"value": n2 / dt2, "unit": "evals/s", "cores": threads, "kind": "oracle",
+            "sample": f"{n2} swap pairs of the same batch (first walkers), N=256, 1 yr / 5 s, "
+                      f"{dt2:.1f} s on {threads} OpenMP threads"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(the sharded design is described, not built)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2405_04690_amd import workmodel
+    from paper_2405_04690_amd.gbl import Context
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.Stream(device=dev)
+    with torch.cuda.stream(stream):
+        from paper_2405_04690_amd import inputs
+        cfg = inputs.PAPER
+        ctx = Context(T=cfg.T, dt=cfg.dt, L=cfg.L, f_lo=cfg.f_lo, f_hi=cfg.f_hi, device=dev, stream=stream)
+        cfg, batch, R, invS, po, pn, ri, pi = build_workload(ctx, torch, args.mix)
+        out = torch.empty(po.shape[0], dtype=torch.float64, device=dev)
+        B = po.shape[0]
+
+        def step():
+            ctx.gb_delta_loglike(R, invS, po, pn, cfg.N, ri, pi, psd_inverse=True, out=out)
+
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(args.steps)]
+        t0 = time.perf_counter()
+        for s, e in ev:
+            s.record(stream)
+            step()
+            e.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+    per_launch_ms = float(np.mean([s.elapsed_time(e) for s, e in ev]))
+    total_ms = ev[0][0].elapsed_time(ev[-1][1])
+    value = B * args.steps / (total_ms / 1e3)
+    bytes_l, flops_l = workmodel.launch_work(batch.params_old, batch.params_new, cfg.T, cfg.N)
+    achieved = flops_l / (per_launch_ms / 1e3) / 1e12
+    roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": None,
+            "kernel": "k_delta_loglike<256>", "avg_launch_ms": round(per_launch_ms, 4),
+            "algorithmic_gbs": round(bytes_l / (per_launch_ms / 1e3) / 1e9, 1),
+            "algorithmic_hbm_frac": round(bytes_l / (per_launch_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(batch, cfg, args.cpu_seconds)
+    line = {
+        "metric": "GB template dlogL evals/s at 1 yr (N=256)",
+        "value": round(value, 1),
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(total_ms / args.steps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"1 yr, dt=5 s, 943573 bins/channel, 32 walker residuals, "
+                               f"{B} swap pairs (32 walkers x 24 temps x 130 sources, {args.mix}), N=256",
+                   "global_batch": B, "template_width": cfg.N, "parallelism": "single-gpu"},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "wall_s": round(wall, 3),
+    }
+    print(json.dumps(line), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

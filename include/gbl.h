@@ -1,0 +1,163 @@
+/*
+ * gbl.h -- C ABI of the MI355X (gfx950) Galactic-Binary likelihood library.
+ *
+ * The library computes, on one GPU, the data-parallel hot path of the LISA
+ * global-fit GB sampler of arXiv:2405.04690:
+ *   - heterodyned, frequency-domain GB templates (A/E/T band slices) for a
+ *     rigid equal-arm constellation with first-generation Michelson TDI
+ *     (Sec. 2, "Input Template Models" and appendix "GB Waveform Generation";
+ *     the TDI channels A, E, T of Sec. 2);
+ *   - noise-weighted likelihood changes for swapping, adding or removing one
+ *     source (Sec. 2, eqs. addsource and swapsource, with the inner product of
+ *     eq. inner summed over channels A and E);
+ *   - the log-likelihood of the instrument-noise parameters (Sec. 2 eq. like
+ *     with Sec. 3 eq. psd).
+ *
+ * Conventions shared by every call
+ *   Pointers   All array arguments are DEVICE pointers owned by the caller
+ *              (e.g. PyTorch allocations on the same GPU).  The library
+ *              allocates device memory only inside gbl_create (constant tables,
+ *              PSD basis, reduction workspace) and frees it in gbl_destroy.
+ *   Streams    Compute calls only enqueue work on the context's stream and
+ *              return; outputs are valid once the caller synchronises that
+ *              stream.  Compute calls never allocate, synchronise or print.
+ *   Errors     Calls return GBL_OK (0) or a negative status.  Argument errors
+ *              are detected on the host before anything is launched;
+ *              gbl_last_error() returns a message for the last failure.
+ *   Values     Non-finite template parameters give NaN outputs (not an error).
+ *              Template bins outside the analysis band [k_min, k_min+n_bins)
+ *              are clipped: they contribute zero to every sum.
+ *   Threading  A context is not thread-safe; use one context per host thread.
+ *   Complex    Complex values are interleaved (re, im) doubles.
+ *
+ * Units and parameters
+ *   params[b][8] = (A, f0 [Hz], fdot [Hz/s], phi0, iota, psi, lambda, beta):
+ *   strain amplitude, initial frequency and its derivative, initial phase,
+ *   inclination, polarisation angle, ecliptic longitude and latitude.
+ *   Frequency bin k is f_k = k / T; the analysis band is
+ *   k in [ceil(f_lo T), floor(f_hi T)].
+ *   A template of width N has carrier bin q = floor(f0 T); its bin j
+ *   (0 <= j < N) is global bin start_bin + j with start_bin = q - N/2.
+ *   Supported widths: N in {128, 256, 512, 1024}.
+ *
+ * Array layouts (row-major)
+ *   residual  [n_res][2][n_bins] complex  channel 0 = A, 1 = E; index k - k_min
+ *   psd       [n_psd][2][n_bins] double   S_n (or 1/S_n with GBL_PSD_INVERSE)
+ *   noise     [P][4] double  (sqrt S_oms^A, sqrt S_acc^A, sqrt S_oms^E, sqrt S_acc^E)
+ *             in m/sqrt(Hz) and m s^-2/sqrt(Hz)
+ */
+#ifndef GBL_H
+#define GBL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GBL_OK 0
+#define GBL_EINVAL (-1)       /* null pointer, negative size, index out of range, bad flag */
+#define GBL_EUNSUPPORTED (-2) /* template width or configuration not supported */
+#define GBL_EHIP (-3)         /* HIP runtime or launch error */
+
+/* precision modes */
+#define GBL_FP64 0
+
+/* psd flags */
+#define GBL_PSD_INVERSE 1 /* the psd array holds 1/S_n instead of S_n */
+
+typedef struct gbl_ctx gbl_ctx;
+
+typedef struct {
+  double T;          /* observation time [s] */
+  double dt;         /* sampling cadence [s]; sets the Nyquist limit 1/(2 dt) */
+  double L;          /* arm length [m] */
+  double f_lo;       /* analysis band [Hz] */
+  double f_hi;
+  int32_t precision; /* GBL_FP64 */
+  int32_t flags;     /* reserved, must be 0 */
+} gbl_config;
+
+/* Create a context for one configuration on the current HIP device.
+ * hip_stream: a hipStream_t (NULL = the default stream).  Builds the orbit,
+ * twiddle and per-bin tables for every supported N, the PSD basis over the
+ * band and the reduction workspace.  Errors: GBL_EINVAL for a null ctx/cfg,
+ * non-positive T/dt/L, f_lo <= 0, f_hi <= f_lo or f_hi above Nyquist;
+ * GBL_EUNSUPPORTED for an unknown precision; GBL_EHIP on allocation failure.
+ * On failure *ctx is NULL. */
+int gbl_create(gbl_ctx** ctx, const gbl_config* cfg, void* hip_stream);
+
+/* Release everything gbl_create allocated.  Synchronises the context's stream
+ * first.  A NULL ctx is a no-op. */
+int gbl_destroy(gbl_ctx* ctx);
+
+/* Change the stream later calls enqueue on. */
+int gbl_set_stream(gbl_ctx* ctx, void* hip_stream);
+
+/* Message for the last failed call on this context ("" if none). */
+const char* gbl_last_error(const gbl_ctx* ctx);
+
+/* First bin and number of bins of the analysis band. */
+int gbl_band(const gbl_ctx* ctx, int64_t* k_min, int64_t* n_bins);
+
+/* Heterodyned GB templates (Sec. 2 and appendix "GB Waveform Generation";
+ * the response is the rigid equal-arm, first-generation-TDI reading described
+ * in the library's design notes).  For every template b writes
+ *   A[b][N], E[b][N], Tch[b][N]  complex band slices of the TDI channels,
+ *   start_bin[b]                 global bin of slice element 0.
+ * T and dt must equal the context's (they are part of the problem statement
+ * and checked).  Tch may be NULL (the T channel is then not computed).
+ * Errors: GBL_EINVAL (null pointers, B < 0, T/dt mismatch),
+ * GBL_EUNSUPPORTED (N not supported). */
+int gb_waveform(gbl_ctx* ctx, const double* params, int64_t B, int32_t N, double T, double dt, double* A,
+                double* E, double* Tch, int64_t* start_bin);
+
+/* Likelihood change for swapping one source (Sec. 2 eq. swapsource):
+ *   dlogl[b] = -1/2 [<a|a> + <r|r> - 2<a|r> - 2<R|a> + 2<R|r>]
+ *            = <R|a - r> - 1/2 <a - r|a - r>         (the form evaluated)
+ * with a = template(params_new[b]), r = template(params_old[b]),
+ * R = residual[res_idx[b]] (= d - H, H containing r) and the inner product of
+ * eq. inner over channels A, E weighted by psd[psd_idx[b]], restricted to the
+ * union of the two template windows clipped to the band.  A birth
+ * (eq. addsource) has params_old amplitude 0, a death params_new amplitude 0.
+ * psd_flags: 0 or GBL_PSD_INVERSE.  All templates have width N.
+ * Errors: GBL_EINVAL (null pointers, B < 0, n_res/n_psd < 1, bad flags),
+ * GBL_EUNSUPPORTED (N).  Indices res_idx/psd_idx must lie in [0, n_res) and
+ * [0, n_psd); they are not checked on the host (they live on the device), and
+ * an out-of-range index gives a NaN output for that template, never an
+ * out-of-bounds access. */
+int gb_delta_loglike(gbl_ctx* ctx, const double* residual, int32_t n_res, const double* psd, int32_t n_psd,
+                     int32_t psd_flags, const double* params_old, const double* params_new, int32_t N,
+                     const int32_t* res_idx, const int32_t* psd_idx, int64_t B, double* dlogl);
+
+/* Instrument PSD of eq. psd over the band for P noise-parameter sets:
+ *   S[p][c][k - k_min] = S_n(f_k; sqrt S_oms^c, sqrt S_acc^c), c = A, E
+ * (or 1/S_n with GBL_PSD_INVERSE).  Errors: GBL_EINVAL. */
+int gb_psd_eval(gbl_ctx* ctx, const double* noise, int64_t P, int32_t psd_flags, double* S);
+
+/* Noise-parameter log-likelihood (Sec. 2 eq. like with Sec. 3 eq. psd):
+ *   logl[p] = sum_{c in A,E} [ -2 df sum_k |R_c,k|^2 / S_c,k - sum_k ln S_c,k ]
+ * with R = residual[res_idx[p]] and S from noise[p].  The sum over bins is a
+ * fixed-order two-pass reduction, so results are bitwise reproducible.
+ * Errors: GBL_EINVAL.  Out-of-range res_idx gives NaN for that set. */
+int gb_psd_loglike(gbl_ctx* ctx, const double* residual, int32_t n_res, const double* noise,
+                   const int32_t* res_idx, int64_t P, double* logl);
+
+/* residual[res_idx[b]] += sign * (A, E) of template b, clipped to the band
+ * (the residual updates of the sampling algorithm's write-back step).  Uses
+ * FP64 atomic adds, so overlapping templates are summed in an unspecified
+ * order.  Errors: GBL_EINVAL, GBL_EUNSUPPORTED (N). */
+int gb_scatter_add(gbl_ctx* ctx, const double* params, int64_t B, int32_t N, double sign, double* residual,
+                   int32_t n_res, const int32_t* res_idx);
+
+/* Stationary Gaussian noise with PSD S (Sec. 3): for n series,
+ *   out[i][c][k] = sqrt(S[i][c][k] / (4 df)) * normals[i][c][k]
+ * with normals complex standard normal draws supplied by the caller, so that
+ * E[<n|n>] = 2 per bin and channel.  Errors: GBL_EINVAL. */
+int gb_make_noise(gbl_ctx* ctx, const double* S, const double* normals, int64_t n, double* out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GBL_H */

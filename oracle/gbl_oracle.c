@@ -275,8 +275,24 @@ int gblo_fft(int n_len, double* data /*[n_len][2], in place*/) {
 /* out_A/out_E/out_T are [N][2]; out_T may be NULL.                         */
 /* ------------------------------------------------------------------------ */
 
+/* Boundary reading: any non-finite parameter, or |f0 T| >= 2^52, makes the
+ * template undefined; its slices are NaN and its start bin 0. */
+static int params_finite(const gblo_config* cfg, const double* p) {
+  for (int i = 0; i < 8; i++)
+    if (!isfinite(p[i])) return 0;
+  return fabs(p[1] * cfg->T) < 4503599627370496.0; /* 2^52: the carrier bin is an exact integer */
+}
+
 static void waveform_one(const gblo_config* cfg, const double* p, int N, cplx* oA, cplx* oE, cplx* oT,
                          int64_t* start) {
+  if (!params_finite(cfg, p)) {
+    for (int j = 0; j < N; j++) {
+      oA[j] = oE[j] = NAN + I * NAN;
+      if (oT) oT[j] = NAN + I * NAN;
+    }
+    *start = 0;
+    return;
+  }
   double khat[3];
   cplx H[3][3];
   source_frame(p, khat, H);
@@ -427,6 +443,12 @@ int gblo_delta_loglike(const gblo_config* cfg, const double* residual, int32_t n
   double df = 1.0 / cfg->T;
 #pragma omp parallel for schedule(dynamic, 4)
   for (int64_t b = 0; b < B; b++) {
+    if (!params_finite(cfg, params_new + 8 * b) || !params_finite(cfg, params_old + 8 * b)) {
+      dlogl[b] = NAN;
+      if (terms)
+        for (int i = 0; i < 6; i++) terms[6 * b + i] = NAN;
+      continue;
+    }
     cplx* a = (cplx*)malloc(sizeof(cplx) * 2 * N);
     cplx* r = (cplx*)malloc(sizeof(cplx) * 2 * N);
     int64_t ka, kr;
@@ -492,6 +514,7 @@ int gblo_scatter_add(const gblo_config* cfg, const double* params, int64_t B, in
       free(a);
       return -1;
     }
+    if (!params_finite(cfg, params + 8 * b)) continue; /* undefined templates add nothing */
     int64_t k0;
     waveform_one(cfg, params + 8 * b, N, a, a + N, NULL, &k0);
     cplx* R = (cplx*)(residual + (int64_t)res_idx[b] * 2 * nb * 2);

@@ -1,0 +1,298 @@
+// gbl.hip -- host side of the C ABI declared in include/gbl.h.
+//
+// Argument checking, context set-up (tables, PSD basis, workspace) and kernel
+// launches.  Every compute entry point only enqueues on the context stream.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "../../include/gbl.h"
+#include "gbl_kernels.hpp"
+
+using gbl::cd;
+
+namespace {
+
+constexpr int kNumWidths = 4;
+constexpr int kWidths[kNumWidths] = {128, 256, 512, 1024};
+constexpr int64_t kMaxGrid = (int64_t)1 << 30;  // blocks per launch (grid.x limit is 2^31 - 1)
+constexpr int64_t kPsdBatch = 4096;             // parameter sets per PSD-likelihood launch pair
+
+int width_slot(int N) {
+  for (int i = 0; i < kNumWidths; i++)
+    if (kWidths[i] == N) return i;
+  return -1;
+}
+
+}  // namespace
+
+struct gbl_ctx {
+  gbl_config cfg;
+  hipStream_t stream;
+  gbl::Geo geo;
+  void* table_mem[kNumWidths];
+  gbl::WaveTables tables[kNumWidths];
+  double* psd_P1;
+  double* psd_P2;
+  double* psd_work;
+  std::string err;
+};
+
+static int fail(gbl_ctx* ctx, int code, const char* fmt, const char* detail = "") {
+  if (ctx) {
+    char buf[512];
+    snprintf(buf, sizeof(buf), fmt, detail);
+    ctx->err = buf;
+  }
+  return code;
+}
+
+static int check_launch(gbl_ctx* ctx, const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    ctx->err = std::string(what) + ": " + hipGetErrorString(e);
+    return GBL_EHIP;
+  }
+  return GBL_OK;
+}
+
+static void release(gbl_ctx* ctx) {
+  for (int i = 0; i < kNumWidths; i++)
+    if (ctx->table_mem[i]) (void)hipFree(ctx->table_mem[i]);
+  if (ctx->psd_P1) (void)hipFree(ctx->psd_P1);
+  if (ctx->psd_P2) (void)hipFree(ctx->psd_P2);
+  if (ctx->psd_work) (void)hipFree(ctx->psd_work);
+}
+
+extern "C" int gbl_create(gbl_ctx** out, const gbl_config* cfg, void* hip_stream) {
+  if (!out) return GBL_EINVAL;
+  *out = nullptr;
+  if (!cfg) return GBL_EINVAL;
+  if (!(cfg->T > 0) || !(cfg->dt > 0) || !(cfg->L > 0) || !(cfg->f_lo > 0) || !(cfg->f_hi > cfg->f_lo) ||
+      cfg->f_hi > 0.5 / cfg->dt || cfg->flags != 0)
+    return GBL_EINVAL;
+  if (cfg->precision != GBL_FP64) return GBL_EUNSUPPORTED;
+
+  gbl_ctx* ctx = new gbl_ctx();
+  ctx->cfg = *cfg;
+  ctx->stream = (hipStream_t)hip_stream;
+  int64_t k_min = (int64_t)std::ceil(cfg->f_lo * cfg->T);
+  int64_t k_max = (int64_t)std::floor(cfg->f_hi * cfg->T);
+  if (k_max < k_min) {
+    delete ctx;
+    return GBL_EINVAL;
+  }
+  gbl::Geo& g = ctx->geo;
+  g.T = cfg->T;
+  g.L = cfg->L;
+  g.Lc = cfg->L / gbl::kC;
+  g.inv_L = 1.0 / cfg->L;
+  double e = cfg->L / (2.0 * std::sqrt(3.0) * gbl::kAU);
+  g.eh = 0.5 * e * gbl::kAU;
+  g.ez = std::sqrt(3.0) * e * gbl::kAU;
+  g.df4 = 4.0 / cfg->T;
+  g.k_min = k_min;
+  g.n_bins = k_max - k_min + 1;
+
+  for (int i = 0; i < kNumWidths; i++) {
+    int N = kWidths[i];
+    size_t bytes = sizeof(double) * 4 * N + sizeof(cd) * 3 * N;
+    if (hipMalloc(&ctx->table_mem[i], bytes) != hipSuccess) {
+      release(ctx);
+      delete ctx;
+      return GBL_EHIP;
+    }
+    double* basis = (double*)ctx->table_mem[i];
+    cd* tw = (cd*)(basis + 4 * N);
+    cd* bF = tw + N;
+    cd* bE = bF + N;
+    ctx->tables[i] = {basis, tw, bF, bE};
+    hipLaunchKernelGGL(gbl::k_init_wave_tables, dim3((N + 255) / 256), dim3(256), 0, ctx->stream, N, g.T, g.Lc,
+                       basis, tw, bF, bE);
+  }
+  size_t nbb = sizeof(double) * (size_t)g.n_bins;
+  if (hipMalloc(&ctx->psd_P1, nbb) != hipSuccess || hipMalloc(&ctx->psd_P2, nbb) != hipSuccess ||
+      hipMalloc(&ctx->psd_work, sizeof(double) * 2 * gbl::kPsdChunks * kPsdBatch) != hipSuccess) {
+    release(ctx);
+    delete ctx;
+    return GBL_EHIP;
+  }
+  hipLaunchKernelGGL(gbl::k_init_psd_basis, dim3((unsigned)((g.n_bins + 255) / 256)), dim3(256), 0, ctx->stream,
+                     g.k_min, g.n_bins, g.T, g.L, ctx->psd_P1, ctx->psd_P2);
+  if (hipGetLastError() != hipSuccess || hipStreamSynchronize(ctx->stream) != hipSuccess) {
+    release(ctx);
+    delete ctx;
+    return GBL_EHIP;
+  }
+  *out = ctx;
+  return GBL_OK;
+}
+
+extern "C" int gbl_destroy(gbl_ctx* ctx) {
+  if (!ctx) return GBL_OK;
+  (void)hipStreamSynchronize(ctx->stream);
+  release(ctx);
+  delete ctx;
+  return GBL_OK;
+}
+
+extern "C" int gbl_set_stream(gbl_ctx* ctx, void* hip_stream) {
+  if (!ctx) return GBL_EINVAL;
+  ctx->stream = (hipStream_t)hip_stream;
+  return GBL_OK;
+}
+
+extern "C" const char* gbl_last_error(const gbl_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+extern "C" int gbl_band(const gbl_ctx* ctx, int64_t* k_min, int64_t* n_bins) {
+  if (!ctx || !k_min || !n_bins) return GBL_EINVAL;
+  *k_min = ctx->geo.k_min;
+  *n_bins = ctx->geo.n_bins;
+  return GBL_OK;
+}
+
+// ---------------------------------------------------------------------------
+// dispatch helpers over the supported widths
+// ---------------------------------------------------------------------------
+template <template <int> class F, typename... Args>
+static void dispatch_width(int N, Args&&... args) {
+  switch (N) {
+    case 128: F<128>::run(args...); break;
+    case 256: F<256>::run(args...); break;
+    case 512: F<512>::run(args...); break;
+    case 1024: F<1024>::run(args...); break;
+    default: break;
+  }
+}
+
+template <int N>
+struct LaunchWaveform {
+  static void run(gbl_ctx* ctx, const double* params, int64_t b0, int64_t nb, cd* A, cd* E, cd* Tc, int64_t* sb) {
+    const gbl::WaveTables& tb = ctx->tables[width_slot(N)];
+    if (Tc)
+      hipLaunchKernelGGL((gbl::k_waveform<N, 6>), dim3((unsigned)nb), dim3(64), 0, ctx->stream, ctx->geo, tb, params,
+                         b0, A, E, Tc, sb);
+    else
+      hipLaunchKernelGGL((gbl::k_waveform<N, 4>), dim3((unsigned)nb), dim3(64), 0, ctx->stream, ctx->geo, tb, params,
+                         b0, A, E, Tc, sb);
+  }
+};
+
+template <int N>
+struct LaunchDelta {
+  static void run(gbl_ctx* ctx, const cd* residual, int n_res, const double* psd, int n_psd, int inv,
+                  const double* po, const double* pn, const int32_t* ri, const int32_t* pi, int64_t b0, int64_t nb,
+                  double* out) {
+    const gbl::WaveTables& tb = ctx->tables[width_slot(N)];
+    hipLaunchKernelGGL((gbl::k_delta_loglike<N>), dim3((unsigned)nb), dim3(64), 0, ctx->stream, ctx->geo, tb,
+                       residual, n_res, psd, n_psd, inv, po, pn, ri, pi, b0, out);
+  }
+};
+
+template <int N>
+struct LaunchScatter {
+  static void run(gbl_ctx* ctx, const double* params, int64_t b0, int64_t nb, double sign, cd* residual, int n_res,
+                  const int32_t* ri) {
+    const gbl::WaveTables& tb = ctx->tables[width_slot(N)];
+    hipLaunchKernelGGL((gbl::k_scatter_add<N>), dim3((unsigned)nb), dim3(64), 0, ctx->stream, ctx->geo, tb, params,
+                       b0, sign, residual, n_res, ri);
+  }
+};
+
+// ---------------------------------------------------------------------------
+// compute entry points
+// ---------------------------------------------------------------------------
+extern "C" int gb_waveform(gbl_ctx* ctx, const double* params, int64_t B, int32_t N, double T, double dt, double* A,
+                           double* E, double* Tch, int64_t* start_bin) {
+  if (!ctx) return GBL_EINVAL;
+  if (B < 0) return fail(ctx, GBL_EINVAL, "gb_waveform: B < 0%s");
+  if (width_slot(N) < 0) return fail(ctx, GBL_EUNSUPPORTED, "gb_waveform: unsupported N%s");
+  if (T != ctx->cfg.T || dt != ctx->cfg.dt) return fail(ctx, GBL_EINVAL, "gb_waveform: T/dt differ from the context%s");
+  if (B == 0) return GBL_OK;
+  if (!params || !A || !E || !start_bin) return fail(ctx, GBL_EINVAL, "gb_waveform: null pointer%s");
+  for (int64_t b0 = 0; b0 < B; b0 += kMaxGrid) {
+    int64_t nb = B - b0 < kMaxGrid ? B - b0 : kMaxGrid;
+    dispatch_width<LaunchWaveform>(N, ctx, params, b0, nb, (cd*)A, (cd*)E, (cd*)Tch, start_bin);
+  }
+  return check_launch(ctx, "gb_waveform");
+}
+
+extern "C" int gb_delta_loglike(gbl_ctx* ctx, const double* residual, int32_t n_res, const double* psd,
+                                int32_t n_psd, int32_t psd_flags, const double* params_old, const double* params_new,
+                                int32_t N, const int32_t* res_idx, const int32_t* psd_idx, int64_t B, double* dlogl) {
+  if (!ctx) return GBL_EINVAL;
+  if (B < 0 || n_res < 1 || n_psd < 1) return fail(ctx, GBL_EINVAL, "gb_delta_loglike: bad sizes%s");
+  if (psd_flags & ~GBL_PSD_INVERSE) return fail(ctx, GBL_EINVAL, "gb_delta_loglike: unknown psd flag%s");
+  if (width_slot(N) < 0) return fail(ctx, GBL_EUNSUPPORTED, "gb_delta_loglike: unsupported N%s");
+  if (B == 0) return GBL_OK;
+  if (!residual || !psd || !params_old || !params_new || !res_idx || !psd_idx || !dlogl)
+    return fail(ctx, GBL_EINVAL, "gb_delta_loglike: null pointer%s");
+  const int inv = (psd_flags & GBL_PSD_INVERSE) ? 1 : 0;
+  for (int64_t b0 = 0; b0 < B; b0 += kMaxGrid) {
+    int64_t nb = B - b0 < kMaxGrid ? B - b0 : kMaxGrid;
+    dispatch_width<LaunchDelta>(N, ctx, (const cd*)residual, (int)n_res, psd, (int)n_psd, inv, params_old,
+                                params_new, res_idx, psd_idx, b0, nb, dlogl);
+  }
+  return check_launch(ctx, "gb_delta_loglike");
+}
+
+extern "C" int gb_psd_eval(gbl_ctx* ctx, const double* noise, int64_t P, int32_t psd_flags, double* S) {
+  if (!ctx) return GBL_EINVAL;
+  if (P < 0) return fail(ctx, GBL_EINVAL, "gb_psd_eval: P < 0%s");
+  if (psd_flags & ~GBL_PSD_INVERSE) return fail(ctx, GBL_EINVAL, "gb_psd_eval: unknown psd flag%s");
+  if (P == 0) return GBL_OK;
+  if (!noise || !S) return fail(ctx, GBL_EINVAL, "gb_psd_eval: null pointer%s");
+  int64_t total = P * 2 * ctx->geo.n_bins;
+  int64_t blocks = (total + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(gbl::k_psd_eval, dim3((unsigned)blocks), dim3(256), 0, ctx->stream, ctx->geo.n_bins,
+                     ctx->psd_P1, ctx->psd_P2, noise, P, (psd_flags & GBL_PSD_INVERSE) ? 1 : 0, S);
+  return check_launch(ctx, "gb_psd_eval");
+}
+
+extern "C" int gb_psd_loglike(gbl_ctx* ctx, const double* residual, int32_t n_res, const double* noise,
+                              const int32_t* res_idx, int64_t P, double* logl) {
+  if (!ctx) return GBL_EINVAL;
+  if (P < 0 || n_res < 1) return fail(ctx, GBL_EINVAL, "gb_psd_loglike: bad sizes%s");
+  if (P == 0) return GBL_OK;
+  if (!residual || !noise || !res_idx || !logl) return fail(ctx, GBL_EINVAL, "gb_psd_loglike: null pointer%s");
+  for (int64_t p0 = 0; p0 < P; p0 += kPsdBatch) {
+    int64_t np = P - p0 < kPsdBatch ? P - p0 : kPsdBatch;
+    hipLaunchKernelGGL(gbl::k_psd_partial, dim3(gbl::kPsdChunks, (unsigned)np), dim3(gbl::kPsdBlock), 0,
+                       ctx->stream, ctx->geo.n_bins, ctx->psd_P1, ctx->psd_P2, (const cd*)residual, (int)n_res, noise,
+                       res_idx, p0, ctx->psd_work);
+    hipLaunchKernelGGL(gbl::k_psd_final, dim3((unsigned)np), dim3(64), 0, ctx->stream, 1.0 / ctx->cfg.T,
+                       ctx->psd_work, p0, logl);
+  }
+  return check_launch(ctx, "gb_psd_loglike");
+}
+
+extern "C" int gb_scatter_add(gbl_ctx* ctx, const double* params, int64_t B, int32_t N, double sign,
+                              double* residual, int32_t n_res, const int32_t* res_idx) {
+  if (!ctx) return GBL_EINVAL;
+  if (B < 0 || n_res < 1) return fail(ctx, GBL_EINVAL, "gb_scatter_add: bad sizes%s");
+  if (width_slot(N) < 0) return fail(ctx, GBL_EUNSUPPORTED, "gb_scatter_add: unsupported N%s");
+  if (B == 0) return GBL_OK;
+  if (!params || !residual || !res_idx) return fail(ctx, GBL_EINVAL, "gb_scatter_add: null pointer%s");
+  for (int64_t b0 = 0; b0 < B; b0 += kMaxGrid) {
+    int64_t nb = B - b0 < kMaxGrid ? B - b0 : kMaxGrid;
+    dispatch_width<LaunchScatter>(N, ctx, params, b0, nb, sign, (cd*)residual, (int)n_res, res_idx);
+  }
+  return check_launch(ctx, "gb_scatter_add");
+}
+
+extern "C" int gb_make_noise(gbl_ctx* ctx, const double* S, const double* normals, int64_t n, double* out) {
+  if (!ctx) return GBL_EINVAL;
+  if (n < 0) return fail(ctx, GBL_EINVAL, "gb_make_noise: n < 0%s");
+  if (n == 0) return GBL_OK;
+  if (!S || !normals || !out) return fail(ctx, GBL_EINVAL, "gb_make_noise: null pointer%s");
+  int64_t total = n * 2 * ctx->geo.n_bins;
+  int64_t blocks = (total + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(gbl::k_make_noise, dim3((unsigned)blocks), dim3(256), 0, ctx->stream, total,
+                     ctx->cfg.T / 4.0, S, (const cd*)normals, (cd*)out);
+  return check_launch(ctx, "gb_make_noise");
+}

@@ -1,0 +1,236 @@
+"""Thin Python binding of libgbl.so (the C ABI in include/gbl.h).
+
+Argument marshalling only: every step of the path runs in the library's HIP
+kernels.  Tensors must be CUDA (HIP) tensors on the context's device; outputs
+are allocated here and filled by the library on the current torch stream.
+There is no CPU fallback: if libgbl.so is missing, loading raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+from .build import LIB_PATH
+
+GBL_OK = 0
+GBL_EINVAL = -1
+GBL_EUNSUPPORTED = -2
+GBL_EHIP = -3
+GBL_FP64 = 0
+GBL_PSD_INVERSE = 1
+
+SUPPORTED_N = (128, 256, 512, 1024)
+
+EXPORTED = ("gbl_create", "gbl_destroy", "gbl_set_stream", "gbl_last_error", "gbl_band", "gb_waveform",
+            "gb_delta_loglike", "gb_psd_eval", "gb_psd_loglike", "gb_scatter_add", "gb_make_noise")
+
+
+class GblError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"gbl status {code}: {msg}")
+        self.code = code
+
+
+class Config(ctypes.Structure):
+    _fields_ = [("T", ctypes.c_double), ("dt", ctypes.c_double), ("L", ctypes.c_double),
+                ("f_lo", ctypes.c_double), ("f_hi", ctypes.c_double), ("precision", ctypes.c_int32),
+                ("flags", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """dlopen libgbl.so and declare the C signatures (no GPU work)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} not found: build the HIP library first (python -m paper_2405_04690_amd.build)")
+    lib = ctypes.CDLL(path)
+    vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    sigs = {
+        "gbl_create": [ctypes.POINTER(vp), ctypes.POINTER(Config), vp],
+        "gbl_destroy": [vp],
+        "gbl_set_stream": [vp, vp],
+        "gbl_band": [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)],
+        "gb_waveform": [vp, vp, i64, i32, dbl, dbl, vp, vp, vp, vp],
+        "gb_delta_loglike": [vp, vp, i32, vp, i32, i32, vp, vp, i32, vp, vp, i64, vp],
+        "gb_psd_eval": [vp, vp, i64, i32, vp],
+        "gb_psd_loglike": [vp, vp, i32, vp, vp, i64, vp],
+        "gb_scatter_add": [vp, vp, i64, i32, dbl, vp, i32, vp],
+        "gb_make_noise": [vp, vp, vp, i64, vp],
+    }
+    for name, args in sigs.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    lib.gbl_last_error.argtypes = [vp]
+    lib.gbl_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+class Context:
+    """One library context: a run configuration bound to a device and stream."""
+
+    def __init__(self, T: float, dt: float, L: float = 2.5e9, f_lo: float = 1e-4, f_hi: float = 3e-2,
+                 precision: int = GBL_FP64, device=None, stream=None):
+        self.lib = load_library()
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.cfg = Config(T, dt, L, f_lo, f_hi, precision, 0)
+        self._h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            s = stream if stream is not None else torch.cuda.current_stream(self.device)
+            rc = self.lib.gbl_create(ctypes.byref(self._h), ctypes.byref(self.cfg), ctypes.c_void_p(s.cuda_stream))
+        if rc != GBL_OK:
+            raise GblError(rc, "gbl_create failed")
+        kmin, nb = ctypes.c_int64(), ctypes.c_int64()
+        self.lib.gbl_band(self._h, ctypes.byref(kmin), ctypes.byref(nb))
+        self.k_min, self.n_bins = kmin.value, nb.value
+        self.T, self.dt, self.L = T, dt, L
+        self.df = 1.0 / T
+
+    def close(self):
+        if self._h:
+            self.lib.gbl_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- helpers ---------------------------------------------------------
+    def _sync_stream(self):
+        s = torch.cuda.current_stream(self.device)
+        self.lib.gbl_set_stream(self._h, ctypes.c_void_p(s.cuda_stream))
+
+    def _check(self, rc: int, what: str):
+        if rc != GBL_OK:
+            msg = self.lib.gbl_last_error(self._h)
+            raise GblError(rc, f"{what}: {msg.decode() if msg else ''}")
+
+    def _dev(self, t, dtype, name):
+        if not isinstance(t, torch.Tensor):
+            raise TypeError(f"{name} must be a torch tensor")
+        if t.device != self.device:
+            raise ValueError(f"{name} must be on {self.device}")
+        if t.dtype != dtype:
+            raise TypeError(f"{name} must be {dtype}")
+        if not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+        return t
+
+    def _params(self, p, name="params"):
+        p = self._dev(p, torch.float64, name)
+        if p.dim() != 2 or p.shape[1] != 8:
+            raise ValueError(f"{name} must have shape [B, 8]")
+        return p
+
+    def _residual(self, r):
+        r = self._dev(r, torch.complex128, "residual")
+        if r.dim() != 3 or r.shape[1] != 2 or r.shape[2] != self.n_bins:
+            raise ValueError(f"residual must have shape [n_res, 2, {self.n_bins}]")
+        return r
+
+    # -- C ABI calls -----------------------------------------------------
+    def gb_waveform(self, params, N: int, with_T: bool = True):
+        params = self._params(params)
+        B = params.shape[0]
+        kw = dict(device=self.device)
+        A = torch.empty((B, N), dtype=torch.complex128, **kw)
+        E = torch.empty((B, N), dtype=torch.complex128, **kw)
+        Tc = torch.empty((B, N), dtype=torch.complex128, **kw) if with_T else None
+        sb = torch.empty(B, dtype=torch.int64, **kw)
+        self._sync_stream()
+        rc = self.lib.gb_waveform(self._h, _ptr(params), B, int(N), self.T, self.dt, _ptr(A), _ptr(E), _ptr(Tc),
+                                  _ptr(sb))
+        self._check(rc, "gb_waveform")
+        return A, E, Tc, sb
+
+    def gb_delta_loglike(self, residual, psd, params_old, params_new, N: int, res_idx=None, psd_idx=None,
+                         psd_inverse: bool = False, out=None):
+        residual = self._residual(residual)
+        psd = self._dev(psd, torch.float64, "psd")
+        if psd.dim() != 3 or psd.shape[1] != 2 or psd.shape[2] != self.n_bins:
+            raise ValueError("psd must have shape [n_psd, 2, n_bins]")
+        po = self._params(params_old, "params_old")
+        pn = self._params(params_new, "params_new")
+        B = po.shape[0]
+        if pn.shape[0] != B:
+            raise ValueError("params_old and params_new differ in length")
+        if res_idx is None:
+            res_idx = torch.zeros(B, dtype=torch.int32, device=self.device)
+        if psd_idx is None:
+            psd_idx = torch.zeros(B, dtype=torch.int32, device=self.device)
+        res_idx = self._dev(res_idx, torch.int32, "res_idx")
+        psd_idx = self._dev(psd_idx, torch.int32, "psd_idx")
+        if res_idx.numel() != B or psd_idx.numel() != B:
+            raise ValueError("res_idx/psd_idx must have B entries")
+        if out is None:
+            out = torch.empty(B, dtype=torch.float64, device=self.device)
+        self._sync_stream()
+        rc = self.lib.gb_delta_loglike(self._h, _ptr(residual), residual.shape[0], _ptr(psd), psd.shape[0],
+                                       GBL_PSD_INVERSE if psd_inverse else 0, _ptr(po), _ptr(pn), int(N),
+                                       _ptr(res_idx), _ptr(psd_idx), B, _ptr(out))
+        self._check(rc, "gb_delta_loglike")
+        return out
+
+    def gb_psd_eval(self, noise, inverse: bool = False):
+        noise = self._dev(noise, torch.float64, "noise")
+        if noise.dim() != 2 or noise.shape[1] != 4:
+            raise ValueError("noise must have shape [P, 4]")
+        P = noise.shape[0]
+        S = torch.empty((P, 2, self.n_bins), dtype=torch.float64, device=self.device)
+        self._sync_stream()
+        rc = self.lib.gb_psd_eval(self._h, _ptr(noise), P, GBL_PSD_INVERSE if inverse else 0, _ptr(S))
+        self._check(rc, "gb_psd_eval")
+        return S
+
+    def gb_psd_loglike(self, residual, noise, res_idx=None):
+        residual = self._residual(residual)
+        noise = self._dev(noise, torch.float64, "noise")
+        if noise.dim() != 2 or noise.shape[1] != 4:
+            raise ValueError("noise must have shape [P, 4]")
+        P = noise.shape[0]
+        if res_idx is None:
+            res_idx = torch.zeros(P, dtype=torch.int32, device=self.device)
+        res_idx = self._dev(res_idx, torch.int32, "res_idx")
+        out = torch.empty(P, dtype=torch.float64, device=self.device)
+        self._sync_stream()
+        rc = self.lib.gb_psd_loglike(self._h, _ptr(residual), residual.shape[0], _ptr(noise), _ptr(res_idx), P,
+                                     _ptr(out))
+        self._check(rc, "gb_psd_loglike")
+        return out
+
+    def gb_scatter_add(self, params, N: int, sign: float, residual, res_idx=None):
+        params = self._params(params)
+        residual = self._residual(residual)
+        B = params.shape[0]
+        if res_idx is None:
+            res_idx = torch.zeros(B, dtype=torch.int32, device=self.device)
+        res_idx = self._dev(res_idx, torch.int32, "res_idx")
+        self._sync_stream()
+        rc = self.lib.gb_scatter_add(self._h, _ptr(params), B, int(N), float(sign), _ptr(residual),
+                                     residual.shape[0], _ptr(res_idx))
+        self._check(rc, "gb_scatter_add")
+        return residual
+
+    def gb_make_noise(self, S, normals):
+        S = self._dev(S, torch.float64, "S")
+        normals = self._dev(normals, torch.complex128, "normals")
+        if S.shape != normals.shape or S.dim() != 3 or S.shape[1] != 2 or S.shape[2] != self.n_bins:
+            raise ValueError("S and normals must both have shape [n, 2, n_bins]")
+        out = torch.empty_like(normals)
+        self._sync_stream()
+        rc = self.lib.gb_make_noise(self._h, _ptr(S), _ptr(normals), S.shape[0], _ptr(out))
+        self._check(rc, "gb_make_noise")
+        return out

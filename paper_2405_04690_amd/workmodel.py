@@ -1,0 +1,59 @@
+"""Algorithmic work per likelihood evaluation, for roofline reporting.
+
+Bytes: what one fused swap evaluation must move from HBM: both parameter
+vectors (2 x 64 B), the residual (16 B) and inverse-PSD (8 B) values of
+channels A and E over the union U of the two template windows, and the 8-byte
+result.  The templates themselves never leave the chip.
+
+FP64 flops (an FMA counts 2): counted by hand from the formulation the
+kernel evaluates, per template of width N:
+  slow part, per midpoint sample
+    receiver terms, 3 craft: position 15, k.x/c 5, phase 8, sin/cos
+      (octant reduction in cycles + degree-15/16 Taylor) 40, f_r 3  -> 71 each
+    arm terms, 3 arms: direction 15, k.n 5, p.n 3, q.n 5, G 13      -> 41 each
+    links, 6: amplitude/phase 6, sinc & cos Taylor (13 + 14 FMA) 54,
+      envelope products 17                                           -> 77 each
+    TDI pieces and A/E combinations                                  -> 48
+    common phase terms                                               -> 7
+  FFT: 5 N log2 N per series (the standard radix-2 count), 4 series
+  per bin: delay factors 14, per channel 20 (x2)                     -> 54
+inner products: 20 flops per union bin.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+PARAM_BYTES = 64
+BIN_BYTES = 2 * (16 + 8)  # A and E: complex128 residual + float64 inverse PSD
+
+
+def flops_per_sample() -> int:
+    return 7 + 3 * 71 + 3 * 41 + 6 * 77 + 48
+
+
+def flops_per_template(N: int, n_series: int = 4) -> int:
+    return N * flops_per_sample() + n_series * 5 * N * int(math.log2(N)) + N * 54
+
+
+def union_bins(params_old: np.ndarray, params_new: np.ndarray, T: float, N: int) -> np.ndarray:
+    """Union size U of the two windows per pair (a zero-amplitude side has none)."""
+    ko = np.floor(params_old[:, 1] * T)
+    kn = np.floor(params_new[:, 1] * T)
+    d = np.minimum(np.abs(kn - ko), N)
+    u = N + d
+    only_one = (params_old[:, 0] == 0) | (params_new[:, 0] == 0)
+    both_zero = (params_old[:, 0] == 0) & (params_new[:, 0] == 0)
+    u = np.where(only_one, N, u)
+    return np.where(both_zero, 0, u).astype(np.int64)
+
+
+def launch_work(params_old: np.ndarray, params_new: np.ndarray, T: float, N: int):
+    """(algorithmic bytes, algorithmic FP64 flops) of one batched launch."""
+    U = union_bins(params_old, params_new, T, N)
+    n_tmpl = int(np.sum(params_old[:, 0] != 0) + np.sum(params_new[:, 0] != 0))
+    B = params_old.shape[0]
+    bytes_ = int(B * (2 * PARAM_BYTES + 8) + BIN_BYTES * U.sum())
+    flops = int(n_tmpl * flops_per_template(N) + 20 * U.sum())
+    return bytes_, flops

@@ -1,0 +1,64 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports
+every entry point declared in include/gbl.h, and rejects a null context on
+the host before touching the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2405_04690_amd import build, gbl
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(build.LIB_PATH):
+        build.build()
+    return gbl.load_library()
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "gbl.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:int|const char\*)\s+(gbl?_\w+)\s*\(", txt, re.M)))
+
+
+def test_header_declares_expected_calls():
+    names = _declared()
+    assert names == sorted(gbl.EXPORTED)
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for name in _declared():
+        assert hasattr(lib, name), name
+
+
+def test_null_context_rejected_on_host(lib):
+    null = None
+    assert lib.gbl_set_stream(null, null) == gbl.GBL_EINVAL
+    assert lib.gbl_band(null, None, None) == gbl.GBL_EINVAL
+    assert lib.gb_waveform(null, null, 1, 256, 1.0, 1.0, null, null, null, null) == gbl.GBL_EINVAL
+    assert lib.gb_delta_loglike(null, null, 1, null, 1, 0, null, null, 256, null, null, 1, null) == gbl.GBL_EINVAL
+    assert lib.gb_psd_eval(null, null, 1, 0, null) == gbl.GBL_EINVAL
+    assert lib.gb_psd_loglike(null, null, 1, null, null, 1, null) == gbl.GBL_EINVAL
+    assert lib.gb_scatter_add(null, null, 1, 256, 1.0, null, 1, null) == gbl.GBL_EINVAL
+    assert lib.gb_make_noise(null, null, null, 1, null) == gbl.GBL_EINVAL
+    assert lib.gbl_destroy(null) == gbl.GBL_OK
+    assert lib.gbl_last_error(null) == b"null context"
+
+
+def test_create_rejects_bad_config_on_host(lib):
+    h = ctypes.c_void_p()
+    bad = [
+        gbl.Config(0.0, 5.0, 2.5e9, 1e-4, 3e-2, 0, 0),      # T <= 0
+        gbl.Config(1e7, 5.0, 2.5e9, 3e-2, 1e-4, 0, 0),      # f_hi < f_lo
+        gbl.Config(1e7, 50.0, 2.5e9, 1e-4, 3e-2, 0, 0),     # f_hi above Nyquist
+        gbl.Config(1e7, 5.0, 2.5e9, 1e-4, 3e-2, 0, 7),      # unknown flags
+    ]
+    for cfg in bad:
+        assert lib.gbl_create(ctypes.byref(h), ctypes.byref(cfg), None) == gbl.GBL_EINVAL
+        assert not h.value
+    cfg = gbl.Config(1e7, 5.0, 2.5e9, 1e-4, 3e-2, 99, 0)    # unknown precision
+    assert lib.gbl_create(ctypes.byref(h), ctypes.byref(cfg), None) == gbl.GBL_EUNSUPPORTED
+    assert lib.gbl_create(None, ctypes.byref(cfg), None) == gbl.GBL_EINVAL
