@@ -38,6 +38,8 @@ def parse():
     ap.add_argument("--mix", default="inmodel", choices=["inmodel", "full"])
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first run a plain 512 MiB device copy (counter calibration for profiles)")
     return ap.parse_args()
 
 
@@ -85,17 +87,23 @@ def cpu_baseline(batch, cfg, target_s):
     sel = np.nonzero(batch.res_idx < nw)[0]
     po, pn, ri = batch.params_old[sel], batch.params_new[sel], batch.res_idx[sel]
     pz = np.zeros(len(sel), np.int32)
-    n = 16 * threads
+    # calibrate on a small slice, then run whole passes over the sample until
+    # about target_s seconds of oracle work have been timed
+    n = min(len(sel), 16 * threads)
     t0 = time.perf_counter()
     orc.delta_loglike(R, S, po[:n], pn[:n], cfg.N, ri[:n], pz[:n])
-    dt = time.perf_counter() - t0
-    n2 = int(min(len(sel), max(n, n * target_s / max(dt, 1e-6))))
-    t0 = time.perf_counter()
-    orc.delta_loglike(R, S, po[:n2], pn[:n2], cfg.N, ri[:n2], pz[:n2])
-    dt2 = time.perf_counter() - t0
-    return {"value": n2 / dt2, "unit": "evals/s", "cores": threads, "kind": "oracle",
-            "sample": f"{n2} swap pairs of the same batch (first walkers), N=256, 1 yr / 5 s, "
-                      f"{dt2:.1f} s on {threads} OpenMP threads"}
+    rate = n / max(time.perf_counter() - t0, 1e-6)
+    total = int(max(n, min(rate * target_s, 50 * len(sel))))
+    done, t_all = 0, 0.0
+    while done < total:
+        m = min(len(sel), total - done)
+        t0 = time.perf_counter()
+        orc.delta_loglike(R, S, po[:m], pn[:m], cfg.N, ri[:m], pz[:m])
+        t_all += time.perf_counter() - t0
+        done += m
+    return {"value": done / t_all, "unit": "evals/s", "cores": threads, "kind": "oracle",
+            "sample": f"{done} evaluations over the first {len(sel)} swap pairs of the same batch "
+                      f"(walkers 0-3), N=256, 1 yr / 5 s; {t_all:.1f} s on {threads} OpenMP threads"}
 
 
 def main():
@@ -110,6 +118,13 @@ def main():
 
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    if args.calibrate_copy:
+        src = torch.ones(64 << 20, dtype=torch.float64, device=dev)  # 512 MiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     stream = torch.cuda.Stream(device=dev)
     with torch.cuda.stream(stream):
         from paper_2405_04690_amd import inputs
