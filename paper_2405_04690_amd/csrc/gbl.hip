@@ -173,10 +173,10 @@ struct LaunchWaveform {
   static void run(gbl_ctx* ctx, const double* params, int64_t b0, int64_t nb, cd* A, cd* E, cd* Tc, int64_t* sb) {
     const gbl::WaveTables& tb = ctx->tables[width_slot(N)];
     if (Tc)
-      hipLaunchKernelGGL((gbl::k_waveform<N, 6>), dim3((unsigned)nb), dim3(64), 0, ctx->stream, ctx->geo, tb, params,
+      hipLaunchKernelGGL((gbl::k_waveform<N, 6>), dim3((unsigned)nb), dim3(gbl::block_threads<N>()), 0, ctx->stream, ctx->geo, tb, params,
                          b0, A, E, Tc, sb);
     else
-      hipLaunchKernelGGL((gbl::k_waveform<N, 4>), dim3((unsigned)nb), dim3(64), 0, ctx->stream, ctx->geo, tb, params,
+      hipLaunchKernelGGL((gbl::k_waveform<N, 4>), dim3((unsigned)nb), dim3(gbl::block_threads<N>()), 0, ctx->stream, ctx->geo, tb, params,
                          b0, A, E, Tc, sb);
   }
 };
@@ -187,7 +187,7 @@ struct LaunchDelta {
                   const double* po, const double* pn, const int32_t* ri, const int32_t* pi, int64_t b0, int64_t nb,
                   double* out) {
     const gbl::WaveTables& tb = ctx->tables[width_slot(N)];
-    hipLaunchKernelGGL((gbl::k_delta_loglike<N>), dim3((unsigned)nb), dim3(64), 0, ctx->stream, ctx->geo, tb,
+    hipLaunchKernelGGL((gbl::k_delta_loglike<N>), dim3((unsigned)nb), dim3(gbl::block_threads<N>()), 0, ctx->stream, ctx->geo, tb,
                        residual, n_res, psd, n_psd, inv, po, pn, ri, pi, b0, out);
   }
 };
@@ -197,7 +197,7 @@ struct LaunchScatter {
   static void run(gbl_ctx* ctx, const double* params, int64_t b0, int64_t nb, double sign, cd* residual, int n_res,
                   const int32_t* ri) {
     const gbl::WaveTables& tb = ctx->tables[width_slot(N)];
-    hipLaunchKernelGGL((gbl::k_scatter_add<N>), dim3((unsigned)nb), dim3(64), 0, ctx->stream, ctx->geo, tb, params,
+    hipLaunchKernelGGL((gbl::k_scatter_add<N>), dim3((unsigned)nb), dim3(gbl::block_threads<N>()), 0, ctx->stream, ctx->geo, tb, params,
                        b0, sign, residual, n_res, ri);
   }
 };

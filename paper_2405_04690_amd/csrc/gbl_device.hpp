@@ -115,6 +115,25 @@ struct Src {
   int state;                   // 0 regular, 1 exactly zero amplitude, 2 non-finite parameters
 };
 
+// Validity and carrier bin only (cheap; used before the full decode).
+// state: 0 regular, 1 exactly zero amplitude, 2 undefined (non-finite or |f0 T| >= 2^52)
+struct SrcHead {
+  int state;
+  int64_t q;
+};
+
+__device__ __forceinline__ SrcHead source_head(const double* __restrict__ prm, const Geo& g) {
+  bool finite = true;
+#pragma unroll
+  for (int i = 0; i < 8; i++) finite = finite && isfinite(prm[i]);
+  double f0T = prm[1] * g.T;
+  finite = finite && fabs(f0T) < 4503599627370496.0;
+  SrcHead h;
+  h.state = finite ? (prm[0] == 0.0 ? 1 : 0) : 2;
+  h.q = finite ? (int64_t)floor(f0T) : 0;
+  return h;
+}
+
 __device__ __forceinline__ Src decode_source(const double* __restrict__ prm, const Geo& g) {
   Src s;
   double A = prm[0], f0 = prm[1], fdot = prm[2], phi0 = prm[3];
@@ -156,40 +175,38 @@ __device__ __forceinline__ Src decode_source(const double* __restrict__ prm, con
 }
 
 // ---------------------------------------------------------------------------
-// sin(u)/u and cos(u) for the link phase u = theta/2 in [0, ~1.6] (f < 30 mHz):
-// Taylor series in v = u^2 evaluated by Horner's rule, truncated where the
-// next term is below 2e-17 for |u| <= 2.7 (f up to ~51 mHz).  Larger |u|
-// (far outside the analysis band) falls back to the library sincos.
+// sin(u)/u and cos(u) for the link phase u = theta/2, which stays below 1.6
+// for every frequency in the analysis band (u < pi f (2L/c)): Taylor series in
+// v = u^2 by Horner's rule, truncated where the next term is below 5e-18 for
+// |u| <= 1.7 (f up to ~32 mHz).  Larger |u| (sources far above the band)
+// falls back to the library sincos.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void sinc_cos(double u, double& sinc, double& cosu) {
   double v = u * u;
-  if (v <= 7.29) {
-    double s = 1.0 / 15511210043330985984000000.0;   // +1/25!
-    s = s * v - 1.0 / 25852016738884976640000.0;     // -1/23!
-    s = s * v + 1.0 / 51090942171709440000.0;        // +1/21!
-    s = s * v - 1.0 / 121645100408832000.0;          // -1/19!
-    s = s * v + 1.0 / 355687428096000.0;             // +1/17!
-    s = s * v - 1.0 / 1307674368000.0;               // -1/15!
-    s = s * v + 1.0 / 6227020800.0;                  // +1/13!
-    s = s * v - 1.0 / 39916800.0;                    // -1/11!
-    s = s * v + 1.0 / 362880.0;                      // +1/9!
-    s = s * v - 1.0 / 5040.0;                        // -1/7!
-    s = s * v + 1.0 / 120.0;                         // +1/5!
-    s = s * v - 1.0 / 6.0;                           // -1/3!
-    s = s * v + 1.0;
-    double c = -1.0 / 403291461126605635584000000.0;  // -1/26!
-    c = c * v + 1.0 / 620448401733239439360000.0;     // +1/24!
-    c = c * v - 1.0 / 1124000727777607680000.0;       // -1/22!
-    c = c * v + 1.0 / 2432902008176640000.0;          // +1/20!
-    c = c * v - 1.0 / 6402373705728000.0;             // -1/18!
-    c = c * v + 1.0 / 20922789888000.0;               // +1/16!
-    c = c * v - 1.0 / 87178291200.0;                  // -1/14!
-    c = c * v + 1.0 / 479001600.0;                    // +1/12!
-    c = c * v - 1.0 / 3628800.0;                      // -1/10!
-    c = c * v + 1.0 / 40320.0;                        // +1/8!
-    c = c * v - 1.0 / 720.0;                          // -1/6!
-    c = c * v + 1.0 / 24.0;                           // +1/4!
-    c = c * v - 0.5;                                  // -1/2!
+  if (v <= 2.89) {
+    double s = -1.0 / 51090942171709440000.0;   // -1/21!
+    s = s * v + 1.0 / 121645100408832000.0;     // +1/19!
+    s = s * v - 1.0 / 355687428096000.0;        // -1/17!
+    s = s * v + 1.0 / 1307674368000.0;          // +1/15!
+    s = s * v - 1.0 / 6227020800.0;             // -1/13!
+    s = s * v + 1.0 / 39916800.0;               // +1/11!
+    s = s * v - 1.0 / 362880.0;                 // -1/9!
+    s = s * v + 1.0 / 5040.0;                   // +1/7!
+    s = s * v - 1.0 / 120.0;                    // -1/5!
+    s = s * v + 1.0 / 6.0;                      // +1/3!
+    s = 1.0 - s * v;
+    double c = 1.0 / 620448401733239439360000.0;  // +1/24!
+    c = c * v - 1.0 / 1124000727777607680000.0;   // -1/22!
+    c = c * v + 1.0 / 2432902008176640000.0;      // +1/20!
+    c = c * v - 1.0 / 6402373705728000.0;         // -1/18!
+    c = c * v + 1.0 / 20922789888000.0;           // +1/16!
+    c = c * v - 1.0 / 87178291200.0;              // -1/14!
+    c = c * v + 1.0 / 479001600.0;                // +1/12!
+    c = c * v - 1.0 / 3628800.0;                  // -1/10!
+    c = c * v + 1.0 / 40320.0;                    // +1/8!
+    c = c * v - 1.0 / 720.0;                      // -1/6!
+    c = c * v + 1.0 / 24.0;                       // +1/4!
+    c = c * v - 0.5;                              // -1/2!
     c = c * v + 1.0;
     sinc = s;
     cosu = c;
@@ -201,13 +218,107 @@ __device__ __forceinline__ void sinc_cos(double u, double& sinc, double& cosu) {
   }
 }
 
+// The same Taylor polynomials evaluated for K arguments in lockstep: each
+// coefficient is materialised once per step and reused K times (gfx9-class
+// VALU encodings take no 64-bit literal, so a lone Horner step costs two
+// register moves besides its FMA).
+template <int K>
+__device__ __forceinline__ void sinc_cos_k(const double* u, double* sinc, double* cosu) {
+  constexpr double cs_[11] = {-1.0 / 51090942171709440000.0, 1.0 / 121645100408832000.0,
+                              -1.0 / 355687428096000.0,      1.0 / 1307674368000.0,
+                              -1.0 / 6227020800.0,           1.0 / 39916800.0,
+                              -1.0 / 362880.0,               1.0 / 5040.0,
+                              -1.0 / 120.0,                  1.0 / 6.0,
+                              0.0};
+  constexpr double cc_[13] = {1.0 / 620448401733239439360000.0, -1.0 / 1124000727777607680000.0,
+                              1.0 / 2432902008176640000.0,      -1.0 / 6402373705728000.0,
+                              1.0 / 20922789888000.0,           -1.0 / 87178291200.0,
+                              1.0 / 479001600.0,                -1.0 / 3628800.0,
+                              1.0 / 40320.0,                    -1.0 / 720.0,
+                              1.0 / 24.0,                       -0.5,
+                              1.0};
+  double v[K], a[K], c[K];
+  bool in_range = true;
+#pragma unroll
+  for (int i = 0; i < K; i++) {
+    v[i] = u[i] * u[i];
+    in_range = in_range && (v[i] <= 2.89);
+    a[i] = cs_[0];
+    c[i] = cc_[0];
+  }
+#pragma unroll
+  for (int k = 1; k < 10; k++) {
+#pragma unroll
+    for (int i = 0; i < K; i++) a[i] = a[i] * v[i] + cs_[k];
+  }
+#pragma unroll
+  for (int k = 1; k < 13; k++) {
+#pragma unroll
+    for (int i = 0; i < K; i++) c[i] = c[i] * v[i] + cc_[k];
+  }
+#pragma unroll
+  for (int i = 0; i < K; i++) {
+    sinc[i] = 1.0 - a[i] * v[i];
+    cosu[i] = c[i];
+  }
+  if (!in_range) {
+    // sources far above the band: exact library evaluation
+#pragma unroll
+    for (int i = 0; i < K; i++) sinc_cos(u[i], sinc[i], cosu[i]);
+  }
+}
+
+template <int K>
+__device__ __forceinline__ void expi_cycles_k(const double* c, cd* out) {
+  constexpr double ps[8] = {-1.0 / 1307674368000.0, 1.0 / 6227020800.0, -1.0 / 39916800.0, 1.0 / 362880.0,
+                            -1.0 / 5040.0,          1.0 / 120.0,        -1.0 / 6.0,        0.0};
+  constexpr double pc[9] = {1.0 / 20922789888000.0, -1.0 / 87178291200.0, 1.0 / 479001600.0,
+                            -1.0 / 3628800.0,       1.0 / 40320.0,        -1.0 / 720.0,
+                            1.0 / 24.0,             -0.5,                 1.0};
+  double x[K], v[K], sn[K], cs[K];
+  int q[K];
+#pragma unroll
+  for (int i = 0; i < K; i++) {
+    double r = c[i] - rint(c[i]);
+    double n4 = rint(4.0 * r);
+    x[i] = kTwoPi * (r - 0.25 * n4);
+    v[i] = x[i] * x[i];
+    q[i] = ((int)n4) & 3;
+    sn[i] = ps[0];
+    cs[i] = pc[0];
+  }
+#pragma unroll
+  for (int k = 1; k < 7; k++) {
+#pragma unroll
+    for (int i = 0; i < K; i++) sn[i] = sn[i] * v[i] + ps[k];
+  }
+#pragma unroll
+  for (int k = 1; k < 9; k++) {
+#pragma unroll
+    for (int i = 0; i < K; i++) cs[i] = cs[i] * v[i] + pc[k];
+  }
+#pragma unroll
+  for (int i = 0; i < K; i++) {
+    double s_ = (sn[i] * v[i]) * x[i] + x[i];
+    double c_ = cs[i];
+    // rotate by q quarter turns
+    double re = (q[i] & 1) ? -s_ : c_;
+    double im = (q[i] & 1) ? c_ : s_;
+    if (q[i] & 2) {
+      re = -re;
+      im = -im;
+    }
+    out[i] = {re, im};
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Slow part: the A, E (and T) TDI pieces U, V at one midpoint sample.
 // Spacecraft i = 0, 1, 2 sit at orientation angle 2 pi i/3 of the rigid
 // equal-arm orbit; arm m joins craft m -> (m+1) mod 3.
-// out[0..5] = U_A, V_A, U_E, V_E, U_T, V_T  (T only when NS == 6).
+// out[0..5] = U_A, V_A, U_E, V_E, U_T, V_T  (T only when NSER == 6).
 // ---------------------------------------------------------------------------
-template <int NS>
+template <int NSER>
 __device__ __forceinline__ void slow_sample(const Src& s, const Geo& g, const double* __restrict__ basis, int n,
                                             double t, cd* out) {
   // orientation cosines/sines of the three craft
@@ -216,66 +327,84 @@ __device__ __forceinline__ void slow_sample(const Src& s, const Geo& g, const do
   const double ca = basis[4 * n + 0], sa = basis[4 * n + 1];
   const double c2a = basis[4 * n + 2], s2a = basis[4 * n + 3];
 
-  // receiver phases exp(i phi_r), instantaneous frequencies f_r
-  // phases in cycles: phi_r / (2 pi) = phi0/(2 pi) + dfq t + fdot t^2/2
-  //                                    - (f0 + fdot t) k.x_r/c + fdot (k.x_r/c)^2 / 2
-  cd P[3];
-  double fr[3];
-  double base = s.phi0_cyc + s.dfq * t + 0.5 * s.fdot * t * t;
-  double fwd = s.f0 + s.fdot * t;
+  // arm projections first: k.n and G = n^T H n for arm m (craft m -> m+1)
+  // (the arms close the triangle, n_0 + n_1 + n_2 = 0, so the third arm's
+  //  projections are minus the sum of the first two)
+  double kn[3], pn[3], qn[3];
 #pragma unroll
-  for (int i = 0; i < 3; i++) {
-    double x = kAU * ca + g.eh * (c2a * cbs[i] + s2a * sbs[i] - 3.0 * cbs[i]);
-    double y = kAU * sa + g.eh * (s2a * cbs[i] - c2a * sbs[i] - 3.0 * sbs[i]);
-    double z = -g.ez * (ca * cbs[i] + sa * sbs[i]);
-    double kx = s.kc[0] * x + s.kc[1] * y + s.kc[2] * z;  // k.x_i / c
-    P[i] = expi_cycles(base - fwd * kx + 0.5 * s.fdot * kx * kx);
-    fr[i] = s.f0 + s.fdot * (t - kx);
-  }
-
-  // arm projections: k.n, G = n^T H n for arm m (craft m -> m+1)
-  double kn[3];
-  cd G[3];
-#pragma unroll
-  for (int m = 0; m < 3; m++) {
-    const int j = (m + 1) % 3;
+  for (int m = 0; m < 2; m++) {
+    const int j = m + 1;
     double dcb = cbs[j] - cbs[m], dsb = sbs[j] - sbs[m];
     double nx = g.inv_L * g.eh * (c2a * dcb + s2a * dsb - 3.0 * dcb);
     double ny = g.inv_L * g.eh * (s2a * dcb - c2a * dsb - 3.0 * dsb);
     double nz = -g.inv_L * g.ez * (ca * dcb + sa * dsb);
     kn[m] = s.kh[0] * nx + s.kh[1] * ny + s.kh[2] * nz;
-    double pn = s.pv[0] * nx + s.pv[1] * ny;  // p has no z component
-    double qn = s.qv[0] * nx + s.qv[1] * ny + s.qv[2] * nz;
-    double ep = pn * pn - qn * qn;
-    double ex = 2.0 * pn * qn;
+    pn[m] = s.pv[0] * nx + s.pv[1] * ny;  // p has no z component
+    qn[m] = s.qv[0] * nx + s.qv[1] * ny + s.qv[2] * nz;
+  }
+  kn[2] = -(kn[0] + kn[1]);
+  pn[2] = -(pn[0] + pn[1]);
+  qn[2] = -(qn[0] + qn[1]);
+  cd G[3];
+#pragma unroll
+  for (int m = 0; m < 3; m++) {
+    double ep = pn[m] * pn[m] - qn[m] * qn[m];
+    double ex = 2.0 * pn[m] * qn[m];
     G[m] = {s.cp.re * ep + s.cx.re * ex, s.cp.im * ep + s.cx.im * ex};
   }
 
-  // link envelope s_{snd->rcv}: arm m traversed forward (sign +1) or backward
-  auto link = [&](int m, double sgn, int rcv) -> cd {
-    double om = 1.0 - sgn * kn[m];
-    double amp = kPi * fr[rcv] * g.Lc - 0.5 * kPi * s.fdot * g.Lc * g.Lc * om;
-    double u = om * amp;
-    double sc, cu;
-    sinc_cos(u, sc, cu);
-    double w = amp * sc;
-    cd z = {cu, -u * sc};  // exp(-i u)
-    cd t1 = z * P[rcv];
-    cd t2 = G[m] * t1;
-    return mul_negi(w * t2);
-  };
-  cd l12 = link(0, 1.0, 1), l21 = link(0, -1.0, 0);
-  cd l23 = link(1, 1.0, 2), l32 = link(1, -1.0, 1);
-  cd l31 = link(2, 1.0, 0), l13 = link(2, -1.0, 2);
+  // phases in cycles: phi_r / (2 pi) = phi0/(2 pi) + dfq t + fdot t^2/2
+  //                                    - (f0 + fdot t) k.x_r/c + fdot (k.x_r/c)^2 / 2
+  const double base = s.phi0_cyc + s.dfq * t + 0.5 * s.fdot * t * t;
+  const double fwd = s.f0 + s.fdot * t;
 
-  cd UX = l21 - l31, VX = l12 - l13;
-  cd UY = l32 - l12, VY = l23 - l21;
-  cd UZ = l13 - l23, VZ = l31 - l32;
+  // receivers: k.x_r/c, phase in cycles, instantaneous frequency
+  double cyc[3], fr[3];
+#pragma unroll
+  for (int r = 0; r < 3; r++) {
+    double x = kAU * ca + g.eh * (c2a * cbs[r] + s2a * sbs[r] - 3.0 * cbs[r]);
+    double y = kAU * sa + g.eh * (s2a * cbs[r] - c2a * sbs[r] - 3.0 * sbs[r]);
+    double z = -g.ez * (ca * cbs[r] + sa * sbs[r]);
+    double kx = s.kc[0] * x + s.kc[1] * y + s.kc[2] * z;  // k.x_r / c
+    cyc[r] = base - fwd * kx + 0.5 * s.fdot * kx * kx;
+    fr[r] = s.f0 + s.fdot * (t - kx);
+  }
+  cd P[3];
+  expi_cycles_k<3>(cyc, P);
+
+  // the six links, ordered by receiver: (arm, direction, receiver)
+  //   l21 = (0,-1,0)  l31 = (2,+1,0)  l12 = (0,+1,1)  l32 = (1,-1,1)
+  //   l23 = (1,+1,2)  l13 = (2,-1,2)
+  constexpr int arm_[6] = {0, 2, 0, 1, 1, 2};
+  constexpr double sgn_[6] = {-1.0, 1.0, 1.0, -1.0, 1.0, -1.0};
+  double amp[6], u[6], sc[6], cu[6];
+#pragma unroll
+  for (int l = 0; l < 6; l++) {
+    double om = 1.0 - sgn_[l] * kn[arm_[l]];
+    amp[l] = kPi * fr[l / 2] * g.Lc - 0.5 * kPi * s.fdot * g.Lc * g.Lc * om;
+    u[l] = om * amp[l];
+  }
+  sinc_cos_k<6>(u, sc, cu);
+  // s_{snd->rcv} = -i G w exp(-i u) P_rcv,  w = amp sinc(u)
+  cd lk[6];
+#pragma unroll
+  for (int l = 0; l < 6; l++) {
+    double w = amp[l] * sc[l];
+    cd z = {cu[l], -u[l] * sc[l]};
+    cd t1 = z * P[l / 2];
+    cd t2 = G[arm_[l]] * t1;
+    lk[l] = mul_negi(w * t2);
+  }
+  // TDI pieces: U_X = s21 - s31, V_X = s12 - s13, U_Y = s32 - s12,
+  //             V_Y = s23 - s21, U_Z = s13 - s23, V_Z = s31 - s32
+  const cd UX = lk[0] - lk[1], VX = lk[2] - lk[5];
+  const cd UY = lk[3] - lk[2], VY = lk[4] - lk[0];
+  const cd UZ = lk[5] - lk[4], VZ = lk[1] - lk[3];
   out[0] = kInvSqrt2 * (UZ - UX);
   out[1] = kInvSqrt2 * (VZ - VX);
   out[2] = kInvSqrt6 * (UX - 2.0 * UY + UZ);
   out[3] = kInvSqrt6 * (VX - 2.0 * VY + VZ);
-  if constexpr (NS == 6) {
+  if constexpr (NSER == 6) {
     out[4] = kInvSqrt3 * (UX + UY + UZ);
     out[5] = kInvSqrt3 * (VX + VY + VZ);
   }
@@ -303,106 +432,54 @@ __device__ __forceinline__ void dft4s(cd* x) {
 
 __device__ __forceinline__ void dft4(cd* x) { dft4s<1>(x); }
 
-// exp(-2 pi i m / 16), m = 0..15
-__device__ __forceinline__ cd w16(int m) {
-  constexpr double c1 = 0.92387953251128675613, s1 = 0.38268343236508977173, h = 0.70710678118654752440;
-  constexpr double re[16] = {1, c1, h, s1, 0, -s1, -h, -c1, -1, -c1, -h, -s1, 0, s1, h, c1};
-  constexpr double im[16] = {0, -s1, -h, -c1, -1, -c1, -h, -s1, 0, s1, h, c1, 1, c1, h, s1};
-  return {re[m & 15], im[m & 15]};
-}
-
-__device__ __forceinline__ void dft8(cd* x) {
-  // 8 = 4 x 2: n = n2 + 2 n1; X[k1 + 4 k2]
-  cd y0[4] = {x[0], x[2], x[4], x[6]};
-  cd y1[4] = {x[1], x[3], x[5], x[7]};
-  dft4(y0);
-  dft4(y1);
-#pragma unroll
-  for (int k1 = 1; k1 < 4; k1++) y1[k1] = y1[k1] * w16(2 * k1);
-#pragma unroll
-  for (int k1 = 0; k1 < 4; k1++) {
-    x[k1] = y0[k1] + y1[k1];
-    x[k1 + 4] = y0[k1] - y1[k1];
-  }
-}
-
-__device__ __forceinline__ void dft16(cd* x) {
-  // 16 = 4 x 4: n = n2 + 4 n1; X[k1 + 4 k2]
-  cd y[4][4];
-#pragma unroll
-  for (int n2 = 0; n2 < 4; n2++) {
-#pragma unroll
-    for (int n1 = 0; n1 < 4; n1++) y[n2][n1] = x[n2 + 4 * n1];
-    dft4(y[n2]);
-#pragma unroll
-    for (int k1 = 1; k1 < 4; k1++)
-      if (n2 > 0) y[n2][k1] = y[n2][k1] * w16(n2 * k1);
-  }
-#pragma unroll
-  for (int k1 = 0; k1 < 4; k1++) {
-    cd z[4] = {y[0][k1], y[1][k1], y[2][k1], y[3][k1]};
-    dft4(z);
-#pragma unroll
-    for (int k2 = 0; k2 < 4; k2++) x[k1 + 4 * k2] = z[k2];
-  }
-}
-
-template <int R>
-__device__ __forceinline__ void dft_small(cd* x) {
-  if constexpr (R == 2) dft2(x);
-  if constexpr (R == 4) dft4(x);
-  if constexpr (R == 8) dft8(x);
-  if constexpr (R == 16) dft16(x);
-}
-
 // ---------------------------------------------------------------------------
-// Wave-level in-place decimation-in-frequency FFT over NSER series of length N
-// stored in LDS with one padding element per 16 (bank-conflict avoidance).
-// Radix plan: 128 = 16x8, 256 = 16x16, 512 = 16x16x2, 1024 = 16x16x4.
+// Block-level in-place decimation-in-frequency FFT over NSER series of length
+// N held in LDS (one padding element per 16 against bank conflicts), with
+// radix-4 passes and a final radix-2 pass when log2 N is odd, so that every
+// pass offers NSER * N / 4 butterflies to the NT threads of the block.
 // Output X[k] sits at the digit-reversed position fft_pos<N>(k).
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int lds_pad(int i) { return i + (i >> 4); }
-
-template <int N>
-struct FftPlan;
-template <>
-struct FftPlan<128> {
-  static constexpr int R1 = 16, R2 = 8, R3 = 1;
-};
-template <>
-struct FftPlan<256> {
-  static constexpr int R1 = 16, R2 = 16, R3 = 1;
-};
-template <>
-struct FftPlan<512> {
-  static constexpr int R1 = 16, R2 = 16, R3 = 2;
-};
-template <>
-struct FftPlan<1024> {
-  static constexpr int R1 = 16, R2 = 16, R3 = 4;
-};
 
 template <int N>
 constexpr int series_pitch() {
   return N + N / 16;
 }
 
+// threads per block for template width N: one sample and one bin per thread
+// at N = 256, up to 4 of each at N = 1024
 template <int N>
-__device__ __forceinline__ int fft_pos(int k) {
-  using P = FftPlan<N>;
-  int k1 = k % P::R1;
-  int r = k / P::R1;
-  int k2 = r % P::R2;
-  int k3 = r / P::R2;
-  return k1 * (N / P::R1) + k2 * (N / (P::R1 * P::R2)) + k3;
+constexpr int block_threads() {
+  return N < 256 ? N : 256;
 }
 
-template <int N, int R, int ST, int NSER>
-__device__ __forceinline__ void fft_pass(cd* buf, const cd* __restrict__ tw, int lane) {
+template <int N>
+__device__ __forceinline__ int fft_pos(int k) {
+  int pos = 0, mult = N, m = N;
+#pragma unroll
+  for (int p = 0; p < 6; p++) {
+    if (m >= 4) {
+      mult >>= 2;
+      pos += (k & 3) * mult;
+      k >>= 2;
+      m >>= 2;
+    } else if (m == 2) {
+      mult >>= 1;
+      pos += (k & 1) * mult;
+      k >>= 1;
+      m = 1;
+    }
+  }
+  return pos;
+}
+
+template <int N, int R, int ST, int NSER, int NT>
+__device__ __forceinline__ void fft_pass(cd* buf, const cd* __restrict__ tw, int tid) {
   constexpr int NB = N / R;  // butterflies per series
   constexpr int SP = series_pitch<N>();
   constexpr int TWS = N / (R * ST);
-  for (int item = lane; item < NSER * NB; item += 64) {
+#pragma unroll 1
+  for (int item = tid; item < NSER * NB; item += NT) {
     int sidx = item / NB, beta = item % NB;
     int grp = beta / ST, i = beta % ST;
     int base = grp * R * ST + i;
@@ -410,7 +487,8 @@ __device__ __forceinline__ void fft_pass(cd* buf, const cd* __restrict__ tw, int
     cd x[R];
 #pragma unroll
     for (int r = 0; r < R; r++) x[r] = b[lds_pad(base + ST * r)];
-    dft_small<R>(x);
+    if constexpr (R == 4) dft4(x);
+    if constexpr (R == 2) dft2(x);
     if constexpr (ST > 1) {
 #pragma unroll
       for (int r = 1; r < R; r++) x[r] = x[r] * tw[TWS * i * r];
@@ -420,30 +498,30 @@ __device__ __forceinline__ void fft_pass(cd* buf, const cd* __restrict__ tw, int
   }
 }
 
-template <int N, int NSER>
-__device__ __forceinline__ void wave_fft(cd* buf, const cd* __restrict__ tw, int lane) {
-  using P = FftPlan<N>;
-  fft_pass<N, P::R1, N / P::R1, NSER>(buf, tw, lane);
-  __syncthreads();
-  fft_pass<N, P::R2, N / (P::R1 * P::R2), NSER>(buf, tw, lane);
-  __syncthreads();
-  if constexpr (P::R3 > 1) {
-    fft_pass<N, P::R3, 1, NSER>(buf, tw, lane);
+template <int N, int NT, int NSER, int M>
+__device__ __forceinline__ void fft_stages(cd* buf, const cd* __restrict__ tw, int tid) {
+  if constexpr (M >= 4) {
+    fft_pass<N, 4, M / 4, NSER, NT>(buf, tw, tid);
+    __syncthreads();
+    fft_stages<N, NT, NSER, M / 4>(buf, tw, tid);
+  } else if constexpr (M == 2) {
+    fft_pass<N, 2, 1, NSER, NT>(buf, tw, tid);
     __syncthreads();
   }
 }
 
 // ---------------------------------------------------------------------------
-// One template: slow part -> FFT -> per-bin TDI factors.  On return, for the
-// bins j = lane + 64 m (m < N/64) the lane may read channel c's spectrum with
-// bin_value(); the LDS workspace is left holding the transformed series.
+// One template: slow part -> FFT.  Afterwards bin_value() reads channel c's
+// spectrum at any window bin j from the transformed U/V series in LDS.
+// Ends with a barrier, so the caller may read the workspace immediately.
 // ---------------------------------------------------------------------------
 template <int N, int NSER>
 __device__ __forceinline__ void template_transform(const Src& s, const Geo& g, const WaveTables& tb, cd* buf,
-                                                   int lane) {
+                                                   int tid) {
   constexpr int SP = series_pitch<N>();
+  constexpr int NT = block_threads<N>();
 #pragma unroll 1
-  for (int n = lane; n < N; n += 64) {
+  for (int n = tid; n < N; n += NT) {
     double t = ((double)n + 0.5) * g.T / (double)N;
     cd v[6];
     slow_sample<NSER>(s, g, tb.basis, n, t, v);
@@ -451,7 +529,7 @@ __device__ __forceinline__ void template_transform(const Src& s, const Geo& g, c
     for (int c = 0; c < NSER; c++) buf[c * SP + lds_pad(n)] = v[c];
   }
   __syncthreads();
-  wave_fft<N, NSER>(buf, tb.fft_tw, lane);
+  fft_stages<N, NT, NSER, N>(buf, tb.fft_tw, tid);
 }
 
 // Spectrum of channel c (0 = A, 1 = E, 2 = T) at window bin j, from the

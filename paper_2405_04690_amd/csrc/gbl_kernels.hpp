@@ -62,22 +62,45 @@ __global__ void k_init_psd_basis(int64_t k_min, int64_t nb, double T, double L, 
   P2[i] = 16.0 * s2 * (3.0 + 2.0 * cx + c2x) / (wa * wa) * (1.0 + r_acc * r_acc) * (1.0 + r_hi * r_hi * r_hi * r_hi);
 }
 
+// Sum over the block (NT threads, NT/64 waves); valid in thread 0 only.
+template <int NT>
+__device__ __forceinline__ double block_sum(double v, double* red) {
+  v = wave_sum(v);
+  const int w = threadIdx.x / kWave;
+  if ((threadIdx.x & (kWave - 1)) == 0) red[w] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < NT / kWave; i++) t += red[i];
+  }
+  return t;
+}
+
 // ---------------------------------------------------------------------------
-// gb_waveform: one wave per template; writes A, E (and T) band slices.
+// gb_waveform: one block per template; writes A, E (and T) band slices.
 // ---------------------------------------------------------------------------
 template <int N, int NSER>
-__global__ __launch_bounds__(64) void k_waveform(Geo g, WaveTables tb, const double* __restrict__ params,
-                                                 int64_t b0, cd* __restrict__ A, cd* __restrict__ E,
-                                                 cd* __restrict__ Tc, int64_t* __restrict__ start) {
+__global__ __launch_bounds__(block_threads<N>()) void k_waveform(Geo g, WaveTables tb,
+                                                                 const double* __restrict__ params, int64_t b0,
+                                                                 cd* __restrict__ A, cd* __restrict__ E,
+                                                                 cd* __restrict__ Tc, int64_t* __restrict__ start) {
+  constexpr int NT = block_threads<N>();
   __shared__ cd buf[NSER * series_pitch<N>()];
+  __shared__ Src s_sh;
   const int64_t b = b0 + blockIdx.x;
-  const int lane = threadIdx.x;
-  const Src s = decode_source(params + 8 * b, g);
-  if (s.state == 0) template_transform<N, NSER>(s, g, tb, buf, lane);
+  const int tid = threadIdx.x;
+  if (tid < kWave) {  // one wave decodes, the block shares the result
+    Src d = decode_source(params + 8 * b, g);
+    if (tid == 0) s_sh = d;
+  }
+  __syncthreads();
+  const Src& s = s_sh;
+  if (s.state == 0) template_transform<N, NSER>(s, g, tb, buf, tid);
   cd* outs[3] = {A, E, Tc};
 #pragma unroll
   for (int c = 0; c < NSER / 2; c++) {
-    for (int j = lane; j < N; j += kWave) {
+    for (int j = tid; j < N; j += NT) {
       cd v;
       if (s.state == 0)
         v = bin_value<N>(s, tb, buf, c, j);
@@ -88,48 +111,82 @@ __global__ __launch_bounds__(64) void k_waveform(Geo g, WaveTables tb, const dou
       outs[c][b * N + j] = v;
     }
   }
-  if (lane == 0) start[b] = (s.state == 2) ? 0 : s.q - N / 2;
+  if (tid == 0) start[b] = (s.state == 2) ? 0 : s.q - N / 2;
 }
 
 // ---------------------------------------------------------------------------
-// gb_delta_loglike (FP64): per pair, the old template r into an LDS window,
-// the new template a through the FFT workspace, then
+// gb_delta_loglike (FP64): one block per (old, new) pair.  The old template r
+// goes into an LDS window, the new template a through the FFT workspace, then
 //   dlogl = 4 df [ sum Re(conj R) d / S - 1/2 sum |d|^2 / S ],  d = a - r,
 // over the union of the two windows clipped to the band (channels A, E).
+// The residual and PSD values of a's window are fetched before the templates
+// are built, so their HBM latency overlaps the arithmetic.
 // ---------------------------------------------------------------------------
 template <int N>
-__global__ __launch_bounds__(64) void k_delta_loglike(Geo g, WaveTables tb, const cd* __restrict__ residual,
-                                                      int n_res, const double* __restrict__ psd, int n_psd,
-                                                      int psd_inv, const double* __restrict__ p_old,
-                                                      const double* __restrict__ p_new,
-                                                      const int32_t* __restrict__ res_idx,
-                                                      const int32_t* __restrict__ psd_idx, int64_t b0,
-                                                      double* __restrict__ out) {
+__global__ __launch_bounds__(block_threads<N>()) void k_delta_loglike(
+    Geo g, WaveTables tb, const cd* __restrict__ residual, int n_res, const double* __restrict__ psd, int n_psd,
+    int psd_inv, const double* __restrict__ p_old, const double* __restrict__ p_new,
+    const int32_t* __restrict__ res_idx, const int32_t* __restrict__ psd_idx, int64_t b0, double* __restrict__ out) {
+  constexpr int NT = block_threads<N>();
+  constexpr int BPT = N / NT;  // window bins per thread
   constexpr int SP = series_pitch<N>();
   __shared__ cd buf[4 * SP];
   __shared__ cd rwin[2 * N];
+  __shared__ double red[2 * (NT / kWave)];
+  __shared__ Src src_sh[2];  // 0: old, 1: new
   const int64_t b = b0 + blockIdx.x;
-  const int lane = threadIdx.x;
-  const Src so = decode_source(p_old + 8 * b, g);
-  const Src sn = decode_source(p_new + 8 * b, g);
+  const int tid = threadIdx.x;
+  // validity and carrier bins first; each source is fully decoded only when
+  // its template is built, which keeps one decoded source live at a time
+  const SrcHead ho = source_head(p_old + 8 * b, g);
+  const SrcHead hn = source_head(p_new + 8 * b, g);
   const int ri = res_idx[b];
   const int pi = psd_idx[b];
-  if (so.state == 2 || sn.state == 2 || ri < 0 || ri >= n_res || pi < 0 || pi >= n_psd) {
-    if (lane == 0) out[b] = qnan();
-    return;
+  if (ho.state == 2 || hn.state == 2 || ri < 0 || ri >= n_res || pi < 0 || pi >= n_psd) {
+    if (tid == 0) out[b] = qnan();
+    return;  // uniform over the block
   }
   const int64_t nb = g.n_bins;
   const cd* RA = residual + (int64_t)ri * 2 * nb;
   const cd* RE = RA + nb;
   const double* SA = psd + (int64_t)pi * 2 * nb;
   const double* SE = SA + nb;
-  const int64_t ka = sn.q - N / 2;
-  const int64_t kr = so.q - N / 2;
+  const int64_t ka = hn.q - N / 2;
+  const int64_t kr = ho.q - N / 2;
+
+  auto weight = [&](const double* Sc, int64_t idx) { return psd_inv ? Sc[idx] : 1.0 / Sc[idx]; };
+
+  // wave 0 decodes the old source, wave 1 the new one; the block shares them
+  if (tid < 2 * kWave) {
+    const int which = tid / kWave;
+    Src d = decode_source((which ? p_new : p_old) + 8 * b, g);
+    if ((tid & (kWave - 1)) == 0) src_sh[which] = d;
+  }
+
+  // prefetch residual and weights over a's window
+  cd pR0[BPT], pR1[BPT];
+  double pW0[BPT], pW1[BPT];
+  if (hn.state == 0) {
+#pragma unroll
+    for (int m = 0; m < BPT; m++) {
+      int64_t k = ka + tid + NT * m;
+      if (k >= g.k_min && k < g.k_min + nb) {
+        int64_t idx = k - g.k_min;
+        pR0[m] = RA[idx];
+        pR1[m] = RE[idx];
+        pW0[m] = weight(SA, idx);
+        pW1[m] = weight(SE, idx);
+      }
+    }
+  }
+
+  __syncthreads();
 
   // old template into the LDS window
-  if (so.state == 0) {
-    template_transform<N, 4>(so, g, tb, buf, lane);
-    for (int j = lane; j < N; j += kWave) {
+  if (ho.state == 0) {
+    const Src& so = src_sh[0];
+    template_transform<N, 4>(so, g, tb, buf, tid);
+    for (int j = tid; j < N; j += NT) {
       rwin[j] = bin_value<N>(so, tb, buf, 0, j);
       rwin[N + j] = bin_value<N>(so, tb, buf, 1, j);
     }
@@ -137,63 +194,72 @@ __global__ __launch_bounds__(64) void k_delta_loglike(Geo g, WaveTables tb, cons
   __syncthreads();
 
   double acc_rd = 0.0, acc_dd = 0.0;
-  auto accumulate = [&](int64_t k, cd d0, cd d1) {
-    int64_t idx = k - g.k_min;
-    double w0 = psd_inv ? SA[idx] : 1.0 / SA[idx];
-    double w1 = psd_inv ? SE[idx] : 1.0 / SE[idx];
-    cd R0 = RA[idx], R1 = RE[idx];
+  auto accumulate = [&](cd R0, cd R1, double w0, double w1, cd d0, cd d1) {
     acc_rd += (R0.re * d0.re + R0.im * d0.im) * w0 + (R1.re * d1.re + R1.im * d1.im) * w1;
     acc_dd += (d0.re * d0.re + d0.im * d0.im) * w0 + (d1.re * d1.re + d1.im * d1.im) * w1;
   };
 
-  if (sn.state == 0) {
-    template_transform<N, 4>(sn, g, tb, buf, lane);
-    for (int j = lane; j < N; j += kWave) {
+  if (hn.state == 0) {
+    const Src& sn = src_sh[1];
+    template_transform<N, 4>(sn, g, tb, buf, tid);
+#pragma unroll
+    for (int m = 0; m < BPT; m++) {
+      const int j = tid + NT * m;
       int64_t k = ka + j;
       if (k < g.k_min || k >= g.k_min + nb) continue;
       cd a0 = bin_value<N>(sn, tb, buf, 0, j);
       cd a1 = bin_value<N>(sn, tb, buf, 1, j);
       int64_t jr = k - kr;
-      if (so.state == 0 && jr >= 0 && jr < N) {
+      if (ho.state == 0 && jr >= 0 && jr < N) {
         a0 = a0 - rwin[jr];
         a1 = a1 - rwin[N + jr];
       }
-      accumulate(k, a0, a1);
+      accumulate(pR0[m], pR1[m], pW0[m], pW1[m], a0, a1);
     }
   }
-  if (so.state == 0) {
+  if (ho.state == 0) {
     // bins of r's window not already covered by a's window
-    for (int j = lane; j < N; j += kWave) {
+    for (int j = tid; j < N; j += NT) {
       int64_t k = kr + j;
-      if (sn.state == 0 && k >= ka && k < ka + N) continue;
+      if (hn.state == 0 && k >= ka && k < ka + N) continue;
       if (k < g.k_min || k >= g.k_min + nb) continue;
+      int64_t idx = k - g.k_min;
       cd r0 = rwin[j], r1 = rwin[N + j];
-      accumulate(k, cd{-r0.re, -r0.im}, cd{-r1.re, -r1.im});
+      accumulate(RA[idx], RE[idx], weight(SA, idx), weight(SE, idx), cd{-r0.re, -r0.im}, cd{-r1.re, -r1.im});
     }
   }
-  acc_rd = wave_sum(acc_rd);
-  acc_dd = wave_sum(acc_dd);
-  if (lane == 0) out[b] = g.df4 * acc_rd - 0.5 * g.df4 * acc_dd;
+  acc_rd = block_sum<NT>(acc_rd, red);
+  acc_dd = block_sum<NT>(acc_dd, red + NT / kWave);
+  if (tid == 0) out[b] = g.df4 * acc_rd - 0.5 * g.df4 * acc_dd;
 }
 
 // ---------------------------------------------------------------------------
 // gb_scatter_add: residual[res_idx[b]] += sign * template b (A, E), FP64 atomics.
 // ---------------------------------------------------------------------------
 template <int N>
-__global__ __launch_bounds__(64) void k_scatter_add(Geo g, WaveTables tb, const double* __restrict__ params,
-                                                    int64_t b0, double sign, cd* residual, int n_res,
-                                                    const int32_t* __restrict__ res_idx) {
+__global__ __launch_bounds__(block_threads<N>()) void k_scatter_add(Geo g, WaveTables tb,
+                                                                    const double* __restrict__ params, int64_t b0,
+                                                                    double sign, cd* residual, int n_res,
+                                                                    const int32_t* __restrict__ res_idx) {
+  constexpr int NT = block_threads<N>();
   __shared__ cd buf[4 * series_pitch<N>()];
+  __shared__ Src s_sh;
   const int64_t b = b0 + blockIdx.x;
-  const int lane = threadIdx.x;
-  const Src s = decode_source(params + 8 * b, g);
+  const int tid = threadIdx.x;
+  const SrcHead h = source_head(params + 8 * b, g);
   const int ri = res_idx[b];
-  if (s.state != 0 || ri < 0 || ri >= n_res) return;  // zero or invalid templates add nothing
-  template_transform<N, 4>(s, g, tb, buf, lane);
+  if (h.state != 0 || ri < 0 || ri >= n_res) return;  // zero or invalid templates add nothing
+  if (tid < kWave) {
+    Src d = decode_source(params + 8 * b, g);
+    if (tid == 0) s_sh = d;
+  }
+  __syncthreads();
+  const Src& s = s_sh;
+  template_transform<N, 4>(s, g, tb, buf, tid);
   const int64_t nb = g.n_bins;
   const int64_t k0 = s.q - N / 2;
   cd* R = residual + (int64_t)ri * 2 * nb;
-  for (int j = lane; j < N; j += kWave) {
+  for (int j = tid; j < N; j += NT) {
     int64_t k = k0 + j;
     if (k < g.k_min || k >= g.k_min + nb) continue;
     int64_t idx = k - g.k_min;
