@@ -38,6 +38,7 @@ def parse():
     ap.add_argument("--mix", default="inmodel", choices=["inmodel", "full"])
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-secondary", action="store_true", help="skip the secondary measurements")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 512 MiB device copy (counter calibration for profiles)")
     return ap.parse_args()
@@ -68,6 +69,70 @@ def build_workload(ctx, torch, mix):
     pi = torch.zeros_like(ri)
     torch.cuda.synchronize()
     return cfg, batch, R, invS, po, pn, ri, pi
+
+
+def _time_launches(torch, stream, fn, reps):
+    fn()
+    torch.cuda.synchronize()
+    s = torch.cuda.Event(enable_timing=True)
+    e = torch.cuda.Event(enable_timing=True)
+    s.record(stream)
+    for _ in range(reps):
+        fn()
+    e.record(stream)
+    torch.cuda.synchronize()
+    return s.elapsed_time(e) / reps  # ms per call
+
+
+def secondary(ctx, torch, stream, cfg, R, invS, po, pn, ri, pi):
+    """Other shapes of the same path, timed the same way (not the headline)."""
+    from paper_2405_04690_amd import inputs
+    out = {}
+    dev = ctx.device
+    B = po.shape[0]
+    # uneven template widths by frequency: 128 (< 1 mHz), 256 (< 3 mHz), 512 (< 6 mHz), 1024
+    f0 = po[:, 1].cpu().numpy()
+    widths = np.where(f0 < 1e-3, 128, np.where(f0 < 3e-3, 256, np.where(f0 < 6e-3, 512, 1024))).astype(np.int32)
+    Nt = torch.from_numpy(widths).to(dev)
+    res = torch.empty(B, dtype=torch.float64, device=dev)
+    ms = _time_launches(torch, stream, lambda: ctx.gb_delta_loglike_var(R, invS, po, pn, Nt, ri, pi,
+                                                                         psd_inverse=True, out=res), 5)
+    counts = {int(w): int((widths == w).sum()) for w in (128, 256, 512, 1024)}
+    out["uneven_width"] = {"evals_per_s": round(B / (ms / 1e3), 1), "ms": round(ms, 4), "widths": counts}
+    # the full proposal mix: 10% births, 10% deaths
+    fb = inputs.paper_swap_batch(mix="full")
+    fo = torch.from_numpy(fb.params_old).to(dev)
+    fn_ = torch.from_numpy(fb.params_new).to(dev)
+    ms = _time_launches(torch, stream, lambda: ctx.gb_delta_loglike(R, invS, fo, fn_, cfg.N, ri, pi,
+                                                                     psd_inverse=True, out=res), 5)
+    out["full_mix_N256"] = {"evals_per_s": round(B / (ms / 1e3), 1), "ms": round(ms, 4)}
+    # mixed precision (FP64 phases and sums, FP32 response and FFT) on the same
+    # batch, with its error against the FP64 path
+    from paper_2405_04690_amd.gbl import GBL_MIXED, Context
+    ctx_m = Context(T=cfg.T, dt=cfg.dt, L=cfg.L, f_lo=cfg.f_lo, f_hi=cfg.f_hi, precision=GBL_MIXED, device=dev,
+                    stream=stream)
+    ref = torch.empty(B, dtype=torch.float64, device=dev)
+    ctx.gb_delta_loglike(R, invS, po, pn, cfg.N, ri, pi, psd_inverse=True, out=ref)
+    resm = torch.empty(B, dtype=torch.float64, device=dev)
+    ms = _time_launches(torch, stream, lambda: ctx_m.gb_delta_loglike(R, invS, po, pn, cfg.N, ri, pi,
+                                                                       psd_inverse=True, out=resm), 10)
+    err = (resm - ref).abs()
+    out["mixed_precision_N256"] = {"evals_per_s": round(B / (ms / 1e3), 1), "ms": round(ms, 4),
+                                   "max_abs_err_vs_fp64": float(err.max()),
+                                   "median_abs_err_vs_fp64": float(err.median()),
+                                   "frac_err_le_1e-3": float((err <= 1e-3).double().mean())}
+    ctx_m.close()
+    # PSD-parameter log-likelihood: one parameter set per walker residual
+    nw = R.shape[0]
+    noise = torch.tensor([[cfg.sqrt_oms, cfg.sqrt_acc, cfg.sqrt_oms, cfg.sqrt_acc]], dtype=torch.float64,
+                         device=dev).repeat(nw, 1)
+    ridx = torch.arange(nw, dtype=torch.int32, device=dev)
+    ms = _time_launches(torch, stream, lambda: ctx.gb_psd_loglike(R, noise, ridx), 10)
+    # algorithmic bytes per set: residual A+E (32 B/bin) + PSD basis P1, P2 (16 B/bin)
+    gbs = nw * ctx.n_bins * 48 / (ms / 1e3) / 1e9
+    out["psd_loglike"] = {"sets": nw, "ms": round(ms, 4), "sets_per_s": round(nw / (ms / 1e3), 1),
+                          "algorithmic_gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+    return out
 
 
 def cpu_baseline(batch, cfg, target_s):
@@ -149,6 +214,7 @@ def main():
             e.record(stream)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
+        sec = None if args.no_secondary else secondary(ctx, torch, stream, cfg, R, invS, po, pn, ri, pi)
     per_launch_ms = float(np.mean([s.elapsed_time(e) for s, e in ev]))
     total_ms = ev[0][0].elapsed_time(ev[-1][1])
     value = B * args.steps / (total_ms / 1e3)
@@ -180,6 +246,7 @@ def main():
                    "global_batch": B, "template_width": cfg.N, "parallelism": "single-gpu"},
         "roofline": roof,
         "cpu_baseline": cpu,
+        "secondary": sec,
         "wall_s": round(wall, 3),
     }
     print(json.dumps(line), flush=True)

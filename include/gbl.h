@@ -61,7 +61,10 @@ extern "C" {
 #define GBL_EHIP (-3)         /* HIP runtime or launch error */
 
 /* precision modes */
-#define GBL_FP64 0
+#define GBL_FP64 0  /* everything in double precision */
+#define GBL_MIXED 1 /* orbital and carrier phases, their reduction and all
+                       likelihood sums in double; link amplitudes, the TDI
+                       response, the FFT and the per-bin factor in float */
 
 /* psd flags */
 #define GBL_PSD_INVERSE 1 /* the psd array holds 1/S_n instead of S_n */
@@ -74,7 +77,7 @@ typedef struct {
   double L;          /* arm length [m] */
   double f_lo;       /* analysis band [Hz] */
   double f_hi;
-  int32_t precision; /* GBL_FP64 */
+  int32_t precision; /* GBL_FP64 or GBL_MIXED */
   int32_t flags;     /* reserved, must be 0 */
 } gbl_config;
 
@@ -129,6 +132,27 @@ int gb_waveform(gbl_ctx* ctx, const double* params, int64_t B, int32_t N, double
 int gb_delta_loglike(gbl_ctx* ctx, const double* residual, int32_t n_res, const double* psd, int32_t n_psd,
                      int32_t psd_flags, const double* params_old, const double* params_new, int32_t N,
                      const int32_t* res_idx, const int32_t* psd_idx, int64_t B, double* dlogl);
+
+/* Uneven template widths in one call (the paper's sub-band widths depend on
+ * frequency, Sec. 4): as gb_waveform, but template b has width N[b] (device
+ * array) and its slices start at element out_offset[b] (device array, in
+ * complex elements) of A, E and Tch.  Templates are bucketed by width on the
+ * device (atomic position counters) and each width runs as one launch over
+ * its bucket; nothing is synchronised on the host.  A template whose N[b] is not
+ * supported is skipped and gets start_bin[b] = INT64_MIN.  The caller owns the
+ * layout: slices of different templates must not overlap.
+ * Errors: GBL_EINVAL (null pointers, B < 0). */
+int gb_waveform_var(gbl_ctx* ctx, const double* params, const int32_t* N, const int64_t* out_offset, int64_t B,
+                    double* A, double* E, double* Tch, int64_t* start_bin);
+
+/* Uneven template widths in one call: as gb_delta_loglike with the width of
+ * pair b given by N[b] (device array; both templates of a pair share it).
+ * Bucketed on the device and run as one launch per width.  An unsupported
+ * N[b] gives dlogl[b] = NaN.
+ * Errors: GBL_EINVAL (null pointers, bad sizes or flags). */
+int gb_delta_loglike_var(gbl_ctx* ctx, const double* residual, int32_t n_res, const double* psd, int32_t n_psd,
+                         int32_t psd_flags, const double* params_old, const double* params_new, const int32_t* N,
+                         const int32_t* res_idx, const int32_t* psd_idx, int64_t B, double* dlogl);
 
 /* Instrument PSD of eq. psd over the band for P noise-parameter sets:
  *   S[p][c][k - k_min] = S_n(f_k; sqrt S_oms^c, sqrt S_acc^c), c = A, E

@@ -20,6 +20,7 @@ constexpr int kNumWidths = 4;
 constexpr int kWidths[kNumWidths] = {128, 256, 512, 1024};
 constexpr int64_t kMaxGrid = (int64_t)1 << 30;  // blocks per launch (grid.x limit is 2^31 - 1)
 constexpr int64_t kPsdBatch = 4096;             // parameter sets per PSD-likelihood launch pair
+constexpr int kBucketCap = 1 << 20;             // templates per bucketed (uneven-width) launch group
 
 int width_slot(int N) {
   for (int i = 0; i < kNumWidths; i++)
@@ -34,10 +35,13 @@ struct gbl_ctx {
   hipStream_t stream;
   gbl::Geo geo;
   void* table_mem[kNumWidths];
-  gbl::WaveTables tables[kNumWidths];
+  gbl::WaveTables<double> tables[kNumWidths];   // FP64 response
+  gbl::WaveTables<float> tables32[kNumWidths];  // mixed precision response
   double* psd_P1;
   double* psd_P2;
   double* psd_work;
+  int* counts;       // [4 widths] templates per width bucket
+  int32_t* perm;     // [4 widths][kBucketCap] template indices per width
   std::string err;
 };
 
@@ -65,6 +69,8 @@ static void release(gbl_ctx* ctx) {
   if (ctx->psd_P1) (void)hipFree(ctx->psd_P1);
   if (ctx->psd_P2) (void)hipFree(ctx->psd_P2);
   if (ctx->psd_work) (void)hipFree(ctx->psd_work);
+  if (ctx->counts) (void)hipFree(ctx->counts);
+  if (ctx->perm) (void)hipFree(ctx->perm);
 }
 
 extern "C" int gbl_create(gbl_ctx** out, const gbl_config* cfg, void* hip_stream) {
@@ -74,7 +80,7 @@ extern "C" int gbl_create(gbl_ctx** out, const gbl_config* cfg, void* hip_stream
   if (!(cfg->T > 0) || !(cfg->dt > 0) || !(cfg->L > 0) || !(cfg->f_lo > 0) || !(cfg->f_hi > cfg->f_lo) ||
       cfg->f_hi > 0.5 / cfg->dt || cfg->flags != 0)
     return GBL_EINVAL;
-  if (cfg->precision != GBL_FP64) return GBL_EUNSUPPORTED;
+  if (cfg->precision != GBL_FP64 && cfg->precision != GBL_MIXED) return GBL_EUNSUPPORTED;
 
   gbl_ctx* ctx = new gbl_ctx();
   ctx->cfg = *cfg;
@@ -99,7 +105,7 @@ extern "C" int gbl_create(gbl_ctx** out, const gbl_config* cfg, void* hip_stream
 
   for (int i = 0; i < kNumWidths; i++) {
     int N = kWidths[i];
-    size_t bytes = sizeof(double) * 4 * N + sizeof(cd) * 3 * N;
+    size_t bytes = sizeof(double) * 4 * N + sizeof(cd) * 2 * N + sizeof(gbl::cf) * 2 * N;
     if (hipMalloc(&ctx->table_mem[i], bytes) != hipSuccess) {
       release(ctx);
       delete ctx;
@@ -108,14 +114,18 @@ extern "C" int gbl_create(gbl_ctx** out, const gbl_config* cfg, void* hip_stream
     double* basis = (double*)ctx->table_mem[i];
     cd* tw = (cd*)(basis + 4 * N);
     cd* bF = tw + N;
-    cd* bE = bF + N;
-    ctx->tables[i] = {basis, tw, bF, bE};
-    hipLaunchKernelGGL(gbl::k_init_wave_tables, dim3((N + 255) / 256), dim3(256), 0, ctx->stream, N, g.T, g.Lc,
-                       basis, tw, bF, bE);
+    gbl::cf* tw32 = (gbl::cf*)(bF + N);
+    gbl::cf* bF32 = tw32 + N;
+    ctx->tables[i] = {basis, tw, bF};
+    ctx->tables32[i] = {basis, tw32, bF32};
+    hipLaunchKernelGGL(gbl::k_init_wave_tables, dim3((N + 255) / 256), dim3(256), 0, ctx->stream, N, g.T, basis,
+                       tw, bF, tw32, bF32);
   }
   size_t nbb = sizeof(double) * (size_t)g.n_bins;
   if (hipMalloc(&ctx->psd_P1, nbb) != hipSuccess || hipMalloc(&ctx->psd_P2, nbb) != hipSuccess ||
-      hipMalloc(&ctx->psd_work, sizeof(double) * 2 * gbl::kPsdChunks * kPsdBatch) != hipSuccess) {
+      hipMalloc(&ctx->psd_work, sizeof(double) * 2 * gbl::kPsdChunks * kPsdBatch) != hipSuccess ||
+      hipMalloc(&ctx->counts, sizeof(int) * kNumWidths) != hipSuccess ||
+      hipMalloc(&ctx->perm, sizeof(int32_t) * (size_t)kNumWidths * kBucketCap) != hipSuccess) {
     release(ctx);
     delete ctx;
     return GBL_EHIP;
@@ -168,27 +178,98 @@ static void dispatch_width(int N, Args&&... args) {
   }
 }
 
+// precision dispatch: FP64 response or the mixed-precision response
+template <int N, typename F>
+static const gbl::WaveTables<F>& tables_for(gbl_ctx* ctx);
+template <>
+const gbl::WaveTables<double>& tables_for<128, double>(gbl_ctx* ctx) { return ctx->tables[0]; }
+template <>
+const gbl::WaveTables<double>& tables_for<256, double>(gbl_ctx* ctx) { return ctx->tables[1]; }
+template <>
+const gbl::WaveTables<double>& tables_for<512, double>(gbl_ctx* ctx) { return ctx->tables[2]; }
+template <>
+const gbl::WaveTables<double>& tables_for<1024, double>(gbl_ctx* ctx) { return ctx->tables[3]; }
+template <>
+const gbl::WaveTables<float>& tables_for<128, float>(gbl_ctx* ctx) { return ctx->tables32[0]; }
+template <>
+const gbl::WaveTables<float>& tables_for<256, float>(gbl_ctx* ctx) { return ctx->tables32[1]; }
+template <>
+const gbl::WaveTables<float>& tables_for<512, float>(gbl_ctx* ctx) { return ctx->tables32[2]; }
+template <>
+const gbl::WaveTables<float>& tables_for<1024, float>(gbl_ctx* ctx) { return ctx->tables32[3]; }
+
+template <int N, typename F>
+static void launch_waveform(gbl_ctx* ctx, const double* params, int64_t b0, int64_t nb, cd* A, cd* E, cd* Tc,
+                            int64_t* sb) {
+  const auto& tb = tables_for<N, F>(ctx);
+  if (Tc)
+    hipLaunchKernelGGL((gbl::k_waveform<N, 6, F>), dim3((unsigned)nb), dim3(gbl::block_threads<N>()), 0,
+                       ctx->stream, ctx->geo, tb, params, b0, A, E, Tc, sb);
+  else
+    hipLaunchKernelGGL((gbl::k_waveform<N, 4, F>), dim3((unsigned)nb), dim3(gbl::block_threads<N>()), 0,
+                       ctx->stream, ctx->geo, tb, params, b0, A, E, Tc, sb);
+}
+
 template <int N>
 struct LaunchWaveform {
   static void run(gbl_ctx* ctx, const double* params, int64_t b0, int64_t nb, cd* A, cd* E, cd* Tc, int64_t* sb) {
-    const gbl::WaveTables& tb = ctx->tables[width_slot(N)];
-    if (Tc)
-      hipLaunchKernelGGL((gbl::k_waveform<N, 6>), dim3((unsigned)nb), dim3(gbl::block_threads<N>()), 0, ctx->stream, ctx->geo, tb, params,
-                         b0, A, E, Tc, sb);
+    if (ctx->cfg.precision == GBL_MIXED)
+      launch_waveform<N, float>(ctx, params, b0, nb, A, E, Tc, sb);
     else
-      hipLaunchKernelGGL((gbl::k_waveform<N, 4>), dim3((unsigned)nb), dim3(gbl::block_threads<N>()), 0, ctx->stream, ctx->geo, tb, params,
-                         b0, A, E, Tc, sb);
+      launch_waveform<N, double>(ctx, params, b0, nb, A, E, Tc, sb);
   }
 };
 
 template <int N>
 struct LaunchDelta {
-  static void run(gbl_ctx* ctx, const cd* residual, int n_res, const double* psd, int n_psd, int inv,
-                  const double* po, const double* pn, const int32_t* ri, const int32_t* pi, int64_t b0, int64_t nb,
-                  double* out) {
-    const gbl::WaveTables& tb = ctx->tables[width_slot(N)];
-    hipLaunchKernelGGL((gbl::k_delta_loglike<N>), dim3((unsigned)nb), dim3(gbl::block_threads<N>()), 0, ctx->stream, ctx->geo, tb,
-                       residual, n_res, psd, n_psd, inv, po, pn, ri, pi, b0, out);
+  static void run(gbl_ctx* ctx, const gbl::DeltaArgs& da, int64_t b0, int64_t nb) {
+    if (ctx->cfg.precision == GBL_MIXED)
+      hipLaunchKernelGGL((gbl::k_delta_loglike<N, float>), dim3((unsigned)nb), dim3(gbl::block_threads<N>()), 0,
+                         ctx->stream, ctx->geo, tables_for<N, float>(ctx), da, b0);
+    else
+      hipLaunchKernelGGL((gbl::k_delta_loglike<N, double>), dim3((unsigned)nb), dim3(gbl::block_threads<N>()), 0,
+                         ctx->stream, ctx->geo, tables_for<N, double>(ctx), da, b0);
+  }
+};
+
+template <int N>
+struct LaunchDeltaBucket {
+  static void run(gbl_ctx* ctx, const gbl::DeltaArgs& da, int64_t b0, int64_t nb) {
+    const int slot = width_slot(N);
+    const int* cnt = ctx->counts + slot;
+    const int32_t* perm = ctx->perm + (int64_t)slot * kBucketCap;
+    if (ctx->cfg.precision == GBL_MIXED)
+      hipLaunchKernelGGL((gbl::k_delta_loglike_bucket<N, float>), dim3((unsigned)nb), dim3(gbl::block_threads<N>()),
+                         0, ctx->stream, ctx->geo, tables_for<N, float>(ctx), da, b0, cnt, perm);
+    else
+      hipLaunchKernelGGL((gbl::k_delta_loglike_bucket<N, double>), dim3((unsigned)nb), dim3(gbl::block_threads<N>()),
+                         0, ctx->stream, ctx->geo, tables_for<N, double>(ctx), da, b0, cnt, perm);
+  }
+};
+
+template <int N, typename F>
+static void launch_waveform_bucket(gbl_ctx* ctx, const double* params, int64_t b0, int64_t nb, const int64_t* off,
+                                   cd* A, cd* E, cd* Tc, int64_t* sb) {
+  const int slot = width_slot(N);
+  const int* cnt = ctx->counts + slot;
+  const int32_t* perm = ctx->perm + (int64_t)slot * kBucketCap;
+  const auto& tb = tables_for<N, F>(ctx);
+  if (Tc)
+    hipLaunchKernelGGL((gbl::k_waveform_bucket<N, 6, F>), dim3((unsigned)nb), dim3(gbl::block_threads<N>()), 0,
+                       ctx->stream, ctx->geo, tb, params, b0, off, A, E, Tc, sb, cnt, perm);
+  else
+    hipLaunchKernelGGL((gbl::k_waveform_bucket<N, 4, F>), dim3((unsigned)nb), dim3(gbl::block_threads<N>()), 0,
+                       ctx->stream, ctx->geo, tb, params, b0, off, A, E, Tc, sb, cnt, perm);
+}
+
+template <int N>
+struct LaunchWaveformBucket {
+  static void run(gbl_ctx* ctx, const double* params, int64_t b0, int64_t nb, const int64_t* off, cd* A, cd* E,
+                  cd* Tc, int64_t* sb) {
+    if (ctx->cfg.precision == GBL_MIXED)
+      launch_waveform_bucket<N, float>(ctx, params, b0, nb, off, A, E, Tc, sb);
+    else
+      launch_waveform_bucket<N, double>(ctx, params, b0, nb, off, A, E, Tc, sb);
   }
 };
 
@@ -196,11 +277,22 @@ template <int N>
 struct LaunchScatter {
   static void run(gbl_ctx* ctx, const double* params, int64_t b0, int64_t nb, double sign, cd* residual, int n_res,
                   const int32_t* ri) {
-    const gbl::WaveTables& tb = ctx->tables[width_slot(N)];
-    hipLaunchKernelGGL((gbl::k_scatter_add<N>), dim3((unsigned)nb), dim3(gbl::block_threads<N>()), 0, ctx->stream, ctx->geo, tb, params,
-                       b0, sign, residual, n_res, ri);
+    if (ctx->cfg.precision == GBL_MIXED)
+      hipLaunchKernelGGL((gbl::k_scatter_add<N, float>), dim3((unsigned)nb), dim3(gbl::block_threads<N>()), 0,
+                         ctx->stream, ctx->geo, tables_for<N, float>(ctx), params, b0, sign, residual, n_res, ri);
+    else
+      hipLaunchKernelGGL((gbl::k_scatter_add<N, double>), dim3((unsigned)nb), dim3(gbl::block_threads<N>()), 0,
+                         ctx->stream, ctx->geo, tables_for<N, double>(ctx), params, b0, sign, residual, n_res, ri);
   }
 };
+
+// device-side bucketing of templates [b0, b0 + nb) by width
+static void bucket_widths(gbl_ctx* ctx, const int32_t* widths, int64_t b0, int64_t nb, double* bad_out,
+                          int64_t* bad_start) {
+  hipLaunchKernelGGL(gbl::k_bucket_reset, dim3(1), dim3(64), 0, ctx->stream, ctx->counts, kNumWidths);
+  hipLaunchKernelGGL(gbl::k_bucket_by_width, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, ctx->stream, widths,
+                     b0, nb, kBucketCap, ctx->counts, ctx->perm, bad_out, bad_start);
+}
 
 // ---------------------------------------------------------------------------
 // compute entry points
@@ -230,13 +322,55 @@ extern "C" int gb_delta_loglike(gbl_ctx* ctx, const double* residual, int32_t n_
   if (B == 0) return GBL_OK;
   if (!residual || !psd || !params_old || !params_new || !res_idx || !psd_idx || !dlogl)
     return fail(ctx, GBL_EINVAL, "gb_delta_loglike: null pointer%s");
-  const int inv = (psd_flags & GBL_PSD_INVERSE) ? 1 : 0;
+  const gbl::DeltaArgs da = {(const cd*)residual, (int)n_res, psd, (int)n_psd,
+                             (psd_flags & GBL_PSD_INVERSE) ? 1 : 0, params_old, params_new, res_idx, psd_idx, dlogl};
   for (int64_t b0 = 0; b0 < B; b0 += kMaxGrid) {
     int64_t nb = B - b0 < kMaxGrid ? B - b0 : kMaxGrid;
-    dispatch_width<LaunchDelta>(N, ctx, (const cd*)residual, (int)n_res, psd, (int)n_psd, inv, params_old,
-                                params_new, res_idx, psd_idx, b0, nb, dlogl);
+    dispatch_width<LaunchDelta>(N, ctx, da, b0, nb);
   }
   return check_launch(ctx, "gb_delta_loglike");
+}
+
+extern "C" int gb_delta_loglike_var(gbl_ctx* ctx, const double* residual, int32_t n_res, const double* psd,
+                                    int32_t n_psd, int32_t psd_flags, const double* params_old,
+                                    const double* params_new, const int32_t* N, const int32_t* res_idx,
+                                    const int32_t* psd_idx, int64_t B, double* dlogl) {
+  if (!ctx) return GBL_EINVAL;
+  if (B < 0 || n_res < 1 || n_psd < 1) return fail(ctx, GBL_EINVAL, "gb_delta_loglike_var: bad sizes%s");
+  if (psd_flags & ~GBL_PSD_INVERSE) return fail(ctx, GBL_EINVAL, "gb_delta_loglike_var: unknown psd flag%s");
+  if (B == 0) return GBL_OK;
+  if (!residual || !psd || !params_old || !params_new || !N || !res_idx || !psd_idx || !dlogl)
+    return fail(ctx, GBL_EINVAL, "gb_delta_loglike_var: null pointer%s");
+  const gbl::DeltaArgs da = {(const cd*)residual, (int)n_res, psd, (int)n_psd,
+                             (psd_flags & GBL_PSD_INVERSE) ? 1 : 0, params_old, params_new, res_idx, psd_idx, dlogl};
+  for (int64_t b0 = 0; b0 < B; b0 += kBucketCap) {
+    int64_t nb = B - b0 < kBucketCap ? B - b0 : kBucketCap;
+    bucket_widths(ctx, N, b0, nb, dlogl, nullptr);
+    // widest first, so the long blocks start early and the short ones fill in
+    LaunchDeltaBucket<1024>::run(ctx, da, b0, nb);
+    LaunchDeltaBucket<512>::run(ctx, da, b0, nb);
+    LaunchDeltaBucket<256>::run(ctx, da, b0, nb);
+    LaunchDeltaBucket<128>::run(ctx, da, b0, nb);
+  }
+  return check_launch(ctx, "gb_delta_loglike_var");
+}
+
+extern "C" int gb_waveform_var(gbl_ctx* ctx, const double* params, const int32_t* N, const int64_t* out_offset,
+                               int64_t B, double* A, double* E, double* Tch, int64_t* start_bin) {
+  if (!ctx) return GBL_EINVAL;
+  if (B < 0) return fail(ctx, GBL_EINVAL, "gb_waveform_var: B < 0%s");
+  if (B == 0) return GBL_OK;
+  if (!params || !N || !out_offset || !A || !E || !start_bin)
+    return fail(ctx, GBL_EINVAL, "gb_waveform_var: null pointer%s");
+  for (int64_t b0 = 0; b0 < B; b0 += kBucketCap) {
+    int64_t nb = B - b0 < kBucketCap ? B - b0 : kBucketCap;
+    bucket_widths(ctx, N, b0, nb, nullptr, start_bin);
+    LaunchWaveformBucket<1024>::run(ctx, params, b0, nb, out_offset, (cd*)A, (cd*)E, (cd*)Tch, start_bin);
+    LaunchWaveformBucket<512>::run(ctx, params, b0, nb, out_offset, (cd*)A, (cd*)E, (cd*)Tch, start_bin);
+    LaunchWaveformBucket<256>::run(ctx, params, b0, nb, out_offset, (cd*)A, (cd*)E, (cd*)Tch, start_bin);
+    LaunchWaveformBucket<128>::run(ctx, params, b0, nb, out_offset, (cd*)A, (cd*)E, (cd*)Tch, start_bin);
+  }
+  return check_launch(ctx, "gb_waveform_var");
 }
 
 extern "C" int gb_psd_eval(gbl_ctx* ctx, const double* noise, int64_t P, int32_t psd_flags, double* S) {

@@ -31,18 +31,43 @@ constexpr double kInvSqrt2 = 0.70710678118654752440;
 constexpr double kInvSqrt3 = 0.57735026918962576451;
 constexpr double kInvSqrt6 = 0.40824829046386301637;
 
-struct cd {
-  double re, im;
+// Complex numbers in the response precision F (double, or float in the mixed
+// mode).  Phases, their reduction and every likelihood sum stay in double.
+template <typename F>
+struct cx {
+  F re, im;
 };
+using cd = cx<double>;
+using cf = cx<float>;
 
-__device__ __forceinline__ cd operator+(cd a, cd b) { return {a.re + b.re, a.im + b.im}; }
-__device__ __forceinline__ cd operator-(cd a, cd b) { return {a.re - b.re, a.im - b.im}; }
-__device__ __forceinline__ cd operator*(cd a, cd b) {
+template <typename F>
+__device__ __forceinline__ cx<F> operator+(cx<F> a, cx<F> b) {
+  return {a.re + b.re, a.im + b.im};
+}
+template <typename F>
+__device__ __forceinline__ cx<F> operator-(cx<F> a, cx<F> b) {
+  return {a.re - b.re, a.im - b.im};
+}
+template <typename F>
+__device__ __forceinline__ cx<F> operator*(cx<F> a, cx<F> b) {
   return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
 }
-__device__ __forceinline__ cd operator*(double s, cd a) { return {s * a.re, s * a.im}; }
-__device__ __forceinline__ cd mul_negi(cd a) { return {a.im, -a.re}; }  // -i a
-__device__ __forceinline__ cd mul_posi(cd a) { return {-a.im, a.re}; }  // +i a
+template <typename F>
+__device__ __forceinline__ cx<F> operator*(F s, cx<F> a) {
+  return {s * a.re, s * a.im};
+}
+template <typename F>
+__device__ __forceinline__ cx<F> mul_negi(cx<F> a) {
+  return {a.im, -a.re};
+}  // -i a
+template <typename F>
+__device__ __forceinline__ cx<F> mul_posi(cx<F> a) {
+  return {-a.im, a.re};
+}  // +i a
+template <typename F, typename G>
+__device__ __forceinline__ cx<F> cvt(cx<G> a) {
+  return {(F)a.re, (F)a.im};
+}
 
 // Configuration-wide constants handed to every kernel by value.
 struct Geo {
@@ -57,12 +82,13 @@ struct Geo {
   int64_t n_bins; // number of analysis bins
 };
 
-// Tables for one template width N, built once per context.
+// Tables for one template width N, built once per context (the complex
+// tables exist in both precisions; the orbit basis is always double).
+template <typename F>
 struct WaveTables {
   const double* basis;  // [N][4] cos a, sin a, cos 2a, sin 2a at t_n = (n+1/2) T/N, a = 2 pi t/yr
-  const cd* fft_tw;     // [N]    exp(-2 pi i m / N)
-  const cd* bin_F;      // [N]    (1/2)(T/N) exp(-i pi k / N),   k = j - N/2
-  const cd* bin_E;      // [N]    exp(-2 pi i k L / (c T)),      k = j - N/2
+  const cx<F>* fft_tw;  // [N]    exp(-2 pi i m / N)
+  const cx<F>* bin_F;   // [N]    (1/2)(T/N) exp(-i pi k / N),   k = j - N/2
 };
 
 // ---------------------------------------------------------------------------
@@ -111,7 +137,6 @@ struct Src {
   double kh[3];                // khat = -(sky direction)
   double pv[3], qv[3];         // polarisation basis vectors
   cd cp, cx;                   // n^T H n = cp (p.n^2 - q.n^2) + cx 2 (p.n)(q.n)
-  cd eq;                       // exp(-2 pi i q L / (c T))
   int state;                   // 0 regular, 1 exactly zero amplitude, 2 non-finite parameters
 };
 
@@ -170,7 +195,6 @@ __device__ __forceinline__ Src decode_source(const double* __restrict__ prm, con
   double ax = 2.0 * A * ci;
   s.cp = {ap * c2p, -ax * s2p};
   s.cx = {ap * s2p, ax * c2p};
-  s.eq = expi_cycles(-qd * g.Lc / g.T);
   return s;
 }
 
@@ -221,15 +245,16 @@ __device__ __forceinline__ void sinc_cos(double u, double& sinc, double& cosu) {
 // The same Taylor polynomials evaluated for K arguments in lockstep: each
 // coefficient is materialised once per step and reused K times (gfx9-class
 // VALU encodings take no 64-bit literal, so a lone Horner step costs two
-// register moves besides its FMA).
+// register moves besides its FMA).  The float versions (mixed precision) use
+// the shortest truncations whose next term is below 2.5e-10 on the same
+// ranges.
 template <int K>
 __device__ __forceinline__ void sinc_cos_k(const double* u, double* sinc, double* cosu) {
-  constexpr double cs_[11] = {-1.0 / 51090942171709440000.0, 1.0 / 121645100408832000.0,
+  constexpr double cs_[10] = {-1.0 / 51090942171709440000.0, 1.0 / 121645100408832000.0,
                               -1.0 / 355687428096000.0,      1.0 / 1307674368000.0,
                               -1.0 / 6227020800.0,           1.0 / 39916800.0,
                               -1.0 / 362880.0,               1.0 / 5040.0,
-                              -1.0 / 120.0,                  1.0 / 6.0,
-                              0.0};
+                              -1.0 / 120.0,                  1.0 / 6.0};
   constexpr double cc_[13] = {1.0 / 620448401733239439360000.0, -1.0 / 1124000727777607680000.0,
                               1.0 / 2432902008176640000.0,      -1.0 / 6402373705728000.0,
                               1.0 / 20922789888000.0,           -1.0 / 87178291200.0,
@@ -269,41 +294,104 @@ __device__ __forceinline__ void sinc_cos_k(const double* u, double* sinc, double
 }
 
 template <int K>
-__device__ __forceinline__ void expi_cycles_k(const double* c, cd* out) {
-  constexpr double ps[8] = {-1.0 / 1307674368000.0, 1.0 / 6227020800.0, -1.0 / 39916800.0, 1.0 / 362880.0,
-                            -1.0 / 5040.0,          1.0 / 120.0,        -1.0 / 6.0,        0.0};
-  constexpr double pc[9] = {1.0 / 20922789888000.0, -1.0 / 87178291200.0, 1.0 / 479001600.0,
-                            -1.0 / 3628800.0,       1.0 / 40320.0,        -1.0 / 720.0,
-                            1.0 / 24.0,             -0.5,                 1.0};
-  double x[K], v[K], sn[K], cs[K];
+__device__ __forceinline__ void sinc_cos_k(const float* u, float* sinc, float* cosu) {
+  // sinc through u^14 (next 1.7^16/17! < 1.4e-11), cos through u^14 (next < 2.3e-10)
+  constexpr float cs_[7] = {-1.0f / 1307674368000.0f, 1.0f / 6227020800.0f, -1.0f / 39916800.0f,
+                            1.0f / 362880.0f,         -1.0f / 5040.0f,      1.0f / 120.0f,
+                            -1.0f / 6.0f};
+  constexpr float cc_[8] = {-1.0f / 87178291200.0f, 1.0f / 479001600.0f, -1.0f / 3628800.0f, 1.0f / 40320.0f,
+                            -1.0f / 720.0f,         1.0f / 24.0f,        -0.5f,              1.0f};
+  float v[K], a[K], c[K];
+  bool in_range = true;
+#pragma unroll
+  for (int i = 0; i < K; i++) {
+    v[i] = u[i] * u[i];
+    in_range = in_range && (v[i] <= 2.89f);
+    a[i] = cs_[0];
+    c[i] = cc_[0];
+  }
+#pragma unroll
+  for (int k = 1; k < 7; k++) {
+#pragma unroll
+    for (int i = 0; i < K; i++) a[i] = a[i] * v[i] + cs_[k];
+  }
+#pragma unroll
+  for (int k = 1; k < 8; k++) {
+#pragma unroll
+    for (int i = 0; i < K; i++) c[i] = c[i] * v[i] + cc_[k];
+  }
+#pragma unroll
+  for (int i = 0; i < K; i++) {
+    sinc[i] = a[i] * v[i] + 1.0f;
+    cosu[i] = c[i];
+  }
+  if (!in_range) {
+#pragma unroll
+    for (int i = 0; i < K; i++) {
+      float su, cu;
+      sincosf(u[i], &su, &cu);
+      sinc[i] = su / u[i];
+      cosu[i] = cu;
+    }
+  }
+}
+
+// Octant polynomials of exp(i x), x in [-pi/4, pi/4], per precision:
+// double: sin through x^15, cos through x^16 (next terms < 5e-17);
+// float:  sin through x^9,  cos through x^10 (next terms < 2e-9).
+template <typename F>
+struct OctantPoly;
+template <>
+struct OctantPoly<double> {
+  static constexpr int NS = 7, NC = 9;
+  static constexpr double ps[NS] = {-1.0 / 1307674368000.0, 1.0 / 6227020800.0, -1.0 / 39916800.0, 1.0 / 362880.0,
+                                    -1.0 / 5040.0,          1.0 / 120.0,        -1.0 / 6.0};
+  static constexpr double pc[NC] = {1.0 / 20922789888000.0, -1.0 / 87178291200.0, 1.0 / 479001600.0,
+                                    -1.0 / 3628800.0,       1.0 / 40320.0,        -1.0 / 720.0,
+                                    1.0 / 24.0,             -0.5,                 1.0};
+};
+template <>
+struct OctantPoly<float> {
+  static constexpr int NS = 4, NC = 6;
+  static constexpr float ps[NS] = {1.0f / 362880.0f, -1.0f / 5040.0f, 1.0f / 120.0f, -1.0f / 6.0f};
+  static constexpr float pc[NC] = {-1.0f / 3628800.0f, 1.0f / 40320.0f, -1.0f / 720.0f,
+                                   1.0f / 24.0f,       -0.5f,           1.0f};
+};
+
+// exp(2 pi i c) for K phases c given in cycles (double); the exact reduction
+// is done in double, the octant polynomial in F.
+template <int K, typename F>
+__device__ __forceinline__ void expi_cycles_k(const double* c, cx<F>* out) {
+  using P = OctantPoly<F>;
+  F x[K], v[K], sn[K], cs[K];
   int q[K];
 #pragma unroll
   for (int i = 0; i < K; i++) {
     double r = c[i] - rint(c[i]);
     double n4 = rint(4.0 * r);
-    x[i] = kTwoPi * (r - 0.25 * n4);
+    x[i] = (F)(kTwoPi * (r - 0.25 * n4));
     v[i] = x[i] * x[i];
     q[i] = ((int)n4) & 3;
-    sn[i] = ps[0];
-    cs[i] = pc[0];
+    sn[i] = P::ps[0];
+    cs[i] = P::pc[0];
   }
 #pragma unroll
-  for (int k = 1; k < 7; k++) {
+  for (int k = 1; k < P::NS; k++) {
 #pragma unroll
-    for (int i = 0; i < K; i++) sn[i] = sn[i] * v[i] + ps[k];
+    for (int i = 0; i < K; i++) sn[i] = sn[i] * v[i] + P::ps[k];
   }
 #pragma unroll
-  for (int k = 1; k < 9; k++) {
+  for (int k = 1; k < P::NC; k++) {
 #pragma unroll
-    for (int i = 0; i < K; i++) cs[i] = cs[i] * v[i] + pc[k];
+    for (int i = 0; i < K; i++) cs[i] = cs[i] * v[i] + P::pc[k];
   }
 #pragma unroll
   for (int i = 0; i < K; i++) {
-    double s_ = (sn[i] * v[i]) * x[i] + x[i];
-    double c_ = cs[i];
+    F s_ = (sn[i] * v[i]) * x[i] + x[i];
+    F c_ = cs[i];
     // rotate by q quarter turns
-    double re = (q[i] & 1) ? -s_ : c_;
-    double im = (q[i] & 1) ? c_ : s_;
+    F re = (q[i] & 1) ? -s_ : c_;
+    F im = (q[i] & 1) ? c_ : s_;
     if (q[i] & 2) {
       re = -re;
       im = -im;
@@ -317,10 +405,12 @@ __device__ __forceinline__ void expi_cycles_k(const double* c, cd* out) {
 // Spacecraft i = 0, 1, 2 sit at orientation angle 2 pi i/3 of the rigid
 // equal-arm orbit; arm m joins craft m -> (m+1) mod 3.
 // out[0..5] = U_A, V_A, U_E, V_E, U_T, V_T  (T only when NSER == 6).
+// The spacecraft positions, k.x/c and the receiver phases are always formed
+// in double; arm projections, link amplitudes and the TDI algebra in F.
 // ---------------------------------------------------------------------------
-template <int NSER>
+template <int NSER, typename F>
 __device__ __forceinline__ void slow_sample(const Src& s, const Geo& g, const double* __restrict__ basis, int n,
-                                            double t, cd* out) {
+                                            double t, cx<F>* out) {
   // orientation cosines/sines of the three craft
   constexpr double cbs[3] = {1.0, -0.5, -0.5};
   constexpr double sbs[3] = {0.0, 0.86602540378443864676, -0.86602540378443864676};
@@ -330,27 +420,32 @@ __device__ __forceinline__ void slow_sample(const Src& s, const Geo& g, const do
   // arm projections first: k.n and G = n^T H n for arm m (craft m -> m+1)
   // (the arms close the triangle, n_0 + n_1 + n_2 = 0, so the third arm's
   //  projections are minus the sum of the first two)
-  double kn[3], pn[3], qn[3];
+  F kn[3], pn[3], qn[3];
+  {
+    const F fca = (F)ca, fsa = (F)sa, fc2a = (F)c2a, fs2a = (F)s2a;
+    const F sh = (F)(g.inv_L * g.eh), sz = (F)(g.inv_L * g.ez);
 #pragma unroll
-  for (int m = 0; m < 2; m++) {
-    const int j = m + 1;
-    double dcb = cbs[j] - cbs[m], dsb = sbs[j] - sbs[m];
-    double nx = g.inv_L * g.eh * (c2a * dcb + s2a * dsb - 3.0 * dcb);
-    double ny = g.inv_L * g.eh * (s2a * dcb - c2a * dsb - 3.0 * dsb);
-    double nz = -g.inv_L * g.ez * (ca * dcb + sa * dsb);
-    kn[m] = s.kh[0] * nx + s.kh[1] * ny + s.kh[2] * nz;
-    pn[m] = s.pv[0] * nx + s.pv[1] * ny;  // p has no z component
-    qn[m] = s.qv[0] * nx + s.qv[1] * ny + s.qv[2] * nz;
+    for (int m = 0; m < 2; m++) {
+      const int j = m + 1;
+      const F dcb = (F)(cbs[j] - cbs[m]), dsb = (F)(sbs[j] - sbs[m]);
+      F nx = sh * (fc2a * dcb + fs2a * dsb - (F)3 * dcb);
+      F ny = sh * (fs2a * dcb - fc2a * dsb - (F)3 * dsb);
+      F nz = -sz * (fca * dcb + fsa * dsb);
+      kn[m] = (F)s.kh[0] * nx + (F)s.kh[1] * ny + (F)s.kh[2] * nz;
+      pn[m] = (F)s.pv[0] * nx + (F)s.pv[1] * ny;  // p has no z component
+      qn[m] = (F)s.qv[0] * nx + (F)s.qv[1] * ny + (F)s.qv[2] * nz;
+    }
   }
   kn[2] = -(kn[0] + kn[1]);
   pn[2] = -(pn[0] + pn[1]);
   qn[2] = -(qn[0] + qn[1]);
-  cd G[3];
+  cx<F> G[3];
+  const cx<F> cp = cvt<F>(s.cp), cxx = cvt<F>(s.cx);
 #pragma unroll
   for (int m = 0; m < 3; m++) {
-    double ep = pn[m] * pn[m] - qn[m] * qn[m];
-    double ex = 2.0 * pn[m] * qn[m];
-    G[m] = {s.cp.re * ep + s.cx.re * ex, s.cp.im * ep + s.cx.im * ex};
+    F ep = pn[m] * pn[m] - qn[m] * qn[m];
+    F ex = (F)2 * pn[m] * qn[m];
+    G[m] = {cp.re * ep + cxx.re * ex, cp.im * ep + cxx.im * ex};
   }
 
   // phases in cycles: phi_r / (2 pi) = phi0/(2 pi) + dfq t + fdot t^2/2
@@ -359,7 +454,8 @@ __device__ __forceinline__ void slow_sample(const Src& s, const Geo& g, const do
   const double fwd = s.f0 + s.fdot * t;
 
   // receivers: k.x_r/c, phase in cycles, instantaneous frequency
-  double cyc[3], fr[3];
+  double cyc[3];
+  F fr[3];
 #pragma unroll
   for (int r = 0; r < 3; r++) {
     double x = kAU * ca + g.eh * (c2a * cbs[r] + s2a * sbs[r] - 3.0 * cbs[r]);
@@ -367,70 +463,70 @@ __device__ __forceinline__ void slow_sample(const Src& s, const Geo& g, const do
     double z = -g.ez * (ca * cbs[r] + sa * sbs[r]);
     double kx = s.kc[0] * x + s.kc[1] * y + s.kc[2] * z;  // k.x_r / c
     cyc[r] = base - fwd * kx + 0.5 * s.fdot * kx * kx;
-    fr[r] = s.f0 + s.fdot * (t - kx);
+    fr[r] = (F)(s.f0 + s.fdot * (t - kx));
   }
-  cd P[3];
-  expi_cycles_k<3>(cyc, P);
+  cx<F> P[3];
+  expi_cycles_k<3, F>(cyc, P);
 
   // the six links, ordered by receiver: (arm, direction, receiver)
   //   l21 = (0,-1,0)  l31 = (2,+1,0)  l12 = (0,+1,1)  l32 = (1,-1,1)
   //   l23 = (1,+1,2)  l13 = (2,-1,2)
   constexpr int arm_[6] = {0, 2, 0, 1, 1, 2};
   constexpr double sgn_[6] = {-1.0, 1.0, 1.0, -1.0, 1.0, -1.0};
-  double amp[6], u[6], sc[6], cu[6];
+  const F piLc = (F)(kPi * g.Lc);
+  const F dterm = (F)(0.5 * kPi * s.fdot * g.Lc * g.Lc);
+  F amp[6], u[6], sc[6], cu[6];
 #pragma unroll
   for (int l = 0; l < 6; l++) {
-    double om = 1.0 - sgn_[l] * kn[arm_[l]];
-    amp[l] = kPi * fr[l / 2] * g.Lc - 0.5 * kPi * s.fdot * g.Lc * g.Lc * om;
+    F om = (F)1 - (F)sgn_[l] * kn[arm_[l]];
+    amp[l] = piLc * fr[l / 2] - dterm * om;
     u[l] = om * amp[l];
   }
   sinc_cos_k<6>(u, sc, cu);
   // s_{snd->rcv} = -i G w exp(-i u) P_rcv,  w = amp sinc(u)
-  cd lk[6];
+  cx<F> lk[6];
 #pragma unroll
   for (int l = 0; l < 6; l++) {
-    double w = amp[l] * sc[l];
-    cd z = {cu[l], -u[l] * sc[l]};
-    cd t1 = z * P[l / 2];
-    cd t2 = G[arm_[l]] * t1;
+    F w = amp[l] * sc[l];
+    cx<F> z = {cu[l], -u[l] * sc[l]};
+    cx<F> t1 = z * P[l / 2];
+    cx<F> t2 = G[arm_[l]] * t1;
     lk[l] = mul_negi(w * t2);
   }
   // TDI pieces: U_X = s21 - s31, V_X = s12 - s13, U_Y = s32 - s12,
   //             V_Y = s23 - s21, U_Z = s13 - s23, V_Z = s31 - s32
-  const cd UX = lk[0] - lk[1], VX = lk[2] - lk[5];
-  const cd UY = lk[3] - lk[2], VY = lk[4] - lk[0];
-  const cd UZ = lk[5] - lk[4], VZ = lk[1] - lk[3];
-  out[0] = kInvSqrt2 * (UZ - UX);
-  out[1] = kInvSqrt2 * (VZ - VX);
-  out[2] = kInvSqrt6 * (UX - 2.0 * UY + UZ);
-  out[3] = kInvSqrt6 * (VX - 2.0 * VY + VZ);
+  const cx<F> UX = lk[0] - lk[1], VX = lk[2] - lk[5];
+  const cx<F> UY = lk[3] - lk[2], VY = lk[4] - lk[0];
+  const cx<F> UZ = lk[5] - lk[4], VZ = lk[1] - lk[3];
+  out[0] = (F)kInvSqrt2 * (UZ - UX);
+  out[1] = (F)kInvSqrt2 * (VZ - VX);
+  out[2] = (F)kInvSqrt6 * (UX - (F)2 * UY + UZ);
+  out[3] = (F)kInvSqrt6 * (VX - (F)2 * VY + VZ);
   if constexpr (NSER == 6) {
-    out[4] = kInvSqrt3 * (UX + UY + UZ);
-    out[5] = kInvSqrt3 * (VX + VY + VZ);
+    out[4] = (F)kInvSqrt3 * (UX + UY + UZ);
+    out[5] = (F)kInvSqrt3 * (VX + VY + VZ);
   }
 }
 
 // ---------------------------------------------------------------------------
 // Small in-register DFTs (forward sign), natural-order output.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void dft2(cd* x) {
-  cd a = x[0], b = x[1];
+template <typename F>
+__device__ __forceinline__ void dft2(cx<F>* x) {
+  cx<F> a = x[0], b = x[1];
   x[0] = a + b;
   x[1] = a - b;
 }
 
-template <int S = 1>
-__device__ __forceinline__ void dft4s(cd* x) {
-  // elements x[0], x[S], x[2S], x[3S]
-  cd a0 = x[0], a1 = x[S], a2 = x[2 * S], a3 = x[3 * S];
-  cd t0 = a0 + a2, t1 = a0 - a2, t2 = a1 + a3, t3 = a1 - a3;
+template <typename F>
+__device__ __forceinline__ void dft4(cx<F>* x) {
+  cx<F> a0 = x[0], a1 = x[1], a2 = x[2], a3 = x[3];
+  cx<F> t0 = a0 + a2, t1 = a0 - a2, t2 = a1 + a3, t3 = a1 - a3;
   x[0] = t0 + t2;
-  x[2 * S] = t0 - t2;
-  x[S] = t1 + mul_negi(t3);
-  x[3 * S] = t1 + mul_posi(t3);
+  x[2] = t0 - t2;
+  x[1] = t1 + mul_negi(t3);
+  x[3] = t1 + mul_posi(t3);
 }
-
-__device__ __forceinline__ void dft4(cd* x) { dft4s<1>(x); }
 
 // ---------------------------------------------------------------------------
 // Block-level in-place decimation-in-frequency FFT over NSER series of length
@@ -473,8 +569,8 @@ __device__ __forceinline__ int fft_pos(int k) {
   return pos;
 }
 
-template <int N, int R, int ST, int NSER, int NT>
-__device__ __forceinline__ void fft_pass(cd* buf, const cd* __restrict__ tw, int tid) {
+template <int N, int R, int ST, int NSER, int NT, typename F>
+__device__ __forceinline__ void fft_pass(cx<F>* buf, const cx<F>* __restrict__ tw, int tid) {
   constexpr int NB = N / R;  // butterflies per series
   constexpr int SP = series_pitch<N>();
   constexpr int TWS = N / (R * ST);
@@ -483,8 +579,8 @@ __device__ __forceinline__ void fft_pass(cd* buf, const cd* __restrict__ tw, int
     int sidx = item / NB, beta = item % NB;
     int grp = beta / ST, i = beta % ST;
     int base = grp * R * ST + i;
-    cd* b = buf + sidx * SP;
-    cd x[R];
+    cx<F>* b = buf + sidx * SP;
+    cx<F> x[R];
 #pragma unroll
     for (int r = 0; r < R; r++) x[r] = b[lds_pad(base + ST * r)];
     if constexpr (R == 4) dft4(x);
@@ -498,8 +594,8 @@ __device__ __forceinline__ void fft_pass(cd* buf, const cd* __restrict__ tw, int
   }
 }
 
-template <int N, int NT, int NSER, int M>
-__device__ __forceinline__ void fft_stages(cd* buf, const cd* __restrict__ tw, int tid) {
+template <int N, int NT, int NSER, int M, typename F>
+__device__ __forceinline__ void fft_stages(cx<F>* buf, const cx<F>* __restrict__ tw, int tid) {
   if constexpr (M >= 4) {
     fft_pass<N, 4, M / 4, NSER, NT>(buf, tw, tid);
     __syncthreads();
@@ -511,20 +607,20 @@ __device__ __forceinline__ void fft_stages(cd* buf, const cd* __restrict__ tw, i
 }
 
 // ---------------------------------------------------------------------------
-// One template: slow part -> FFT.  Afterwards bin_value() reads channel c's
+// One template: slow part -> FFT.  Afterwards bin_spectrum() reads the
 // spectrum at any window bin j from the transformed U/V series in LDS.
 // Ends with a barrier, so the caller may read the workspace immediately.
 // ---------------------------------------------------------------------------
-template <int N, int NSER>
-__device__ __forceinline__ void template_transform(const Src& s, const Geo& g, const WaveTables& tb, cd* buf,
-                                                   int tid) {
+template <int N, int NSER, typename F>
+__device__ __forceinline__ void template_transform(const Src& s, const Geo& g, const WaveTables<F>& tb,
+                                                   cx<F>* buf, int tid) {
   constexpr int SP = series_pitch<N>();
   constexpr int NT = block_threads<N>();
 #pragma unroll 1
   for (int n = tid; n < N; n += NT) {
     double t = ((double)n + 0.5) * g.T / (double)N;
-    cd v[6];
-    slow_sample<NSER>(s, g, tb.basis, n, t, v);
+    cx<F> v[6];
+    slow_sample<NSER, F>(s, g, tb.basis, n, t, v);
 #pragma unroll
     for (int c = 0; c < NSER; c++) buf[c * SP + lds_pad(n)] = v[c];
   }
@@ -532,20 +628,30 @@ __device__ __forceinline__ void template_transform(const Src& s, const Geo& g, c
   fft_stages<N, NT, NSER, N>(buf, tb.fft_tw, tid);
 }
 
-// Spectrum of channel c (0 = A, 1 = E, 2 = T) at window bin j, from the
-// transformed U/V series in LDS: C = (1 - D^2) F (U + D V), D = exp(-i x),
+// Spectra of channels 0..NCH-1 (A, E[, T]) at window bin j, from the
+// transformed U/V series in LDS: C = (1 - D^2) F (U + D V) with D = exp(-i x),
 // x = 2 pi (q + k) L/(c T), F = (1/2)(T/N) exp(-i pi k/N), k = j - N/2.
-template <int N>
-__device__ __forceinline__ cd bin_value(const Src& s, const WaveTables& tb, const cd* buf, int c, int j) {
+// D comes from the bin's phase in cycles through the exact reduction, and
+// 1 - D^2 = 2 sin x (sin x, cos x) is formed without cancellation (at 0.1 mHz
+// x ~ 5e-3, where 1 - cos 2x would lose three digits in single precision).
+template <int N, int NCH, typename F>
+__device__ __forceinline__ void bin_spectrum(const Src& s, const Geo& g, const WaveTables<F>& tb, const cx<F>* buf,
+                                             int j, cx<F>* out) {
   constexpr int SP = series_pitch<N>();
-  int kk = (j + N / 2) & (N - 1);
-  int pos = lds_pad(fft_pos<N>(kk));
-  cd U = buf[(2 * c) * SP + pos];
-  cd V = buf[(2 * c + 1) * SP + pos];
-  cd D = s.eq * tb.bin_E[j];
-  cd D2 = D * D;
-  cd one_m = {1.0 - D2.re, -D2.im};
-  return one_m * (tb.bin_F[j] * (U + D * V));
+  const int kk = (j + N / 2) & (N - 1);
+  const int pos = lds_pad(fft_pos<N>(kk));
+  const double cyc = -(double)(s.q + (int64_t)(j - N / 2)) * (g.Lc / g.T);
+  cx<F> D;
+  expi_cycles_k<1, F>(&cyc, &D);
+  // D = (cos x, -sin x):  1 - D^2 = (2 sin^2 x, 2 sin x cos x)
+  const cx<F> one_m = {(F)2 * D.im * D.im, (F)(-2) * D.im * D.re};
+  const cx<F> Fj = tb.bin_F[j];
+#pragma unroll
+  for (int c = 0; c < NCH; c++) {
+    cx<F> U = buf[(2 * c) * SP + pos];
+    cx<F> V = buf[(2 * c + 1) * SP + pos];
+    out[c] = one_m * (Fj * (U + D * V));
+  }
 }
 
 }  // namespace gbl

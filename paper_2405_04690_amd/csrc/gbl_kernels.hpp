@@ -18,7 +18,8 @@ __device__ __forceinline__ double qnan() { return __builtin_nan(""); }
 // ---------------------------------------------------------------------------
 // Table construction (once per context)
 // ---------------------------------------------------------------------------
-__global__ void k_init_wave_tables(int N, double T, double Lc, double* basis, cd* fft_tw, cd* bin_F, cd* bin_E) {
+__global__ void k_init_wave_tables(int N, double T, double* basis, cd* fft_tw, cd* bin_F, cf* fft_tw32,
+                                   cf* bin_F32) {
   int n = blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= N) return;
   double t = ((double)n + 0.5) * T / (double)N;
@@ -37,8 +38,8 @@ __global__ void k_init_wave_tables(int N, double T, double Lc, double* basis, cd
   sincospi(-(double)k / (double)N, &s, &c);
   double h = 0.5 * T / (double)N;
   bin_F[n] = {h * c, h * s};
-  sincos(-kTwoPi * (double)k * Lc / T, &s, &c);
-  bin_E[n] = {c, s};
+  fft_tw32[n] = cvt<float>(fft_tw[n]);
+  bin_F32[n] = cvt<float>(bin_F[n]);
 }
 
 // PSD basis of eq. psd, linear in (S_oms, S_acc):  S_n = S_oms P1 + S_acc P2,
@@ -78,40 +79,58 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
 }
 
 // ---------------------------------------------------------------------------
-// gb_waveform: one block per template; writes A, E (and T) band slices.
+// gb_waveform: one block per template; writes A, E (and T) band slices of
+// width N starting at element `off` of each output array.
 // ---------------------------------------------------------------------------
-template <int N, int NSER>
-__global__ __launch_bounds__(block_threads<N>()) void k_waveform(Geo g, WaveTables tb,
+template <int N, int NSER, typename F>
+struct WaveSmem {
+  cx<F> buf[NSER * series_pitch<N>()];
+  Src src;
+};
+
+template <int N, int NSER, typename F>
+__device__ __forceinline__ void waveform_one(const Geo& g, const WaveTables<F>& tb, const double* __restrict__ prm,
+                                             int64_t off, cd* __restrict__ A, cd* __restrict__ E,
+                                             cd* __restrict__ Tc, int64_t* __restrict__ start,
+                                             WaveSmem<N, NSER, F>& sm) {
+  constexpr int NT = block_threads<N>();
+  const int tid = threadIdx.x;
+  if (tid < kWave) {  // one wave decodes, the block shares the result
+    Src d = decode_source(prm, g);
+    if (tid == 0) sm.src = d;
+  }
+  __syncthreads();
+  const Src& s = sm.src;
+  if (s.state == 0) template_transform<N, NSER, F>(s, g, tb, sm.buf, tid);
+  cd* outs[3] = {A, E, Tc};
+  constexpr int NCH = NSER / 2;
+  for (int j = tid; j < N; j += NT) {
+    cx<F> v[NCH];
+    if (s.state == 0) bin_spectrum<N, NCH, F>(s, g, tb, sm.buf, j, v);
+#pragma unroll
+    for (int c = 0; c < NCH; c++) {
+      cd o;
+      if (s.state == 0)
+        o = cvt<double>(v[c]);
+      else if (s.state == 1)
+        o = {0.0, 0.0};
+      else
+        o = {qnan(), qnan()};
+      outs[c][off + j] = o;
+    }
+  }
+  if (tid == 0) *start = (s.state == 2) ? 0 : s.q - N / 2;
+  __syncthreads();  // the shared decode may be overwritten afterwards
+}
+
+template <int N, int NSER, typename F>
+__global__ __launch_bounds__(block_threads<N>()) void k_waveform(Geo g, WaveTables<F> tb,
                                                                  const double* __restrict__ params, int64_t b0,
                                                                  cd* __restrict__ A, cd* __restrict__ E,
                                                                  cd* __restrict__ Tc, int64_t* __restrict__ start) {
-  constexpr int NT = block_threads<N>();
-  __shared__ cd buf[NSER * series_pitch<N>()];
-  __shared__ Src s_sh;
+  __shared__ WaveSmem<N, NSER, F> sm;
   const int64_t b = b0 + blockIdx.x;
-  const int tid = threadIdx.x;
-  if (tid < kWave) {  // one wave decodes, the block shares the result
-    Src d = decode_source(params + 8 * b, g);
-    if (tid == 0) s_sh = d;
-  }
-  __syncthreads();
-  const Src& s = s_sh;
-  if (s.state == 0) template_transform<N, NSER>(s, g, tb, buf, tid);
-  cd* outs[3] = {A, E, Tc};
-#pragma unroll
-  for (int c = 0; c < NSER / 2; c++) {
-    for (int j = tid; j < N; j += NT) {
-      cd v;
-      if (s.state == 0)
-        v = bin_value<N>(s, tb, buf, c, j);
-      else if (s.state == 1)
-        v = {0.0, 0.0};
-      else
-        v = {qnan(), qnan()};
-      outs[c][b * N + j] = v;
-    }
-  }
-  if (tid == 0) start[b] = (s.state == 2) ? 0 : s.q - N / 2;
+  waveform_one<N, NSER, F>(g, tb, params + 8 * b, b * N, A, E, Tc, start + b, sm);
 }
 
 // ---------------------------------------------------------------------------
@@ -122,45 +141,59 @@ __global__ __launch_bounds__(block_threads<N>()) void k_waveform(Geo g, WaveTabl
 // The residual and PSD values of a's window are fetched before the templates
 // are built, so their HBM latency overlaps the arithmetic.
 // ---------------------------------------------------------------------------
-template <int N>
-__global__ __launch_bounds__(block_threads<N>()) void k_delta_loglike(
-    Geo g, WaveTables tb, const cd* __restrict__ residual, int n_res, const double* __restrict__ psd, int n_psd,
-    int psd_inv, const double* __restrict__ p_old, const double* __restrict__ p_new,
-    const int32_t* __restrict__ res_idx, const int32_t* __restrict__ psd_idx, int64_t b0, double* __restrict__ out) {
+struct DeltaArgs {
+  const cd* residual;
+  int n_res;
+  const double* psd;
+  int n_psd;
+  int psd_inv;
+  const double* p_old;
+  const double* p_new;
+  const int32_t* res_idx;
+  const int32_t* psd_idx;
+  double* out;
+};
+
+template <int N, typename F>
+struct DeltaSmem {
+  cx<F> buf[4 * series_pitch<N>()];
+  cx<F> rwin[2 * N];
+  double red[2 * (block_threads<N>() / kWave)];
+  Src src[2];  // 0: old, 1: new
+};
+
+template <int N, typename F>
+__device__ __forceinline__ void delta_one(const Geo& g, const WaveTables<F>& tb, const DeltaArgs& da, int64_t b,
+                                          DeltaSmem<N, F>& sm) {
   constexpr int NT = block_threads<N>();
   constexpr int BPT = N / NT;  // window bins per thread
-  constexpr int SP = series_pitch<N>();
-  __shared__ cd buf[4 * SP];
-  __shared__ cd rwin[2 * N];
-  __shared__ double red[2 * (NT / kWave)];
-  __shared__ Src src_sh[2];  // 0: old, 1: new
-  const int64_t b = b0 + blockIdx.x;
   const int tid = threadIdx.x;
-  // validity and carrier bins first; each source is fully decoded only when
-  // its template is built, which keeps one decoded source live at a time
-  const SrcHead ho = source_head(p_old + 8 * b, g);
-  const SrcHead hn = source_head(p_new + 8 * b, g);
-  const int ri = res_idx[b];
-  const int pi = psd_idx[b];
-  if (ho.state == 2 || hn.state == 2 || ri < 0 || ri >= n_res || pi < 0 || pi >= n_psd) {
-    if (tid == 0) out[b] = qnan();
+  // validity and carrier bins first; each source is fully decoded by one
+  // wave into LDS, which keeps the decoded sources out of the registers
+  const SrcHead ho = source_head(da.p_old + 8 * b, g);
+  const SrcHead hn = source_head(da.p_new + 8 * b, g);
+  const int ri = da.res_idx[b];
+  const int pi = da.psd_idx[b];
+  if (ho.state == 2 || hn.state == 2 || ri < 0 || ri >= da.n_res || pi < 0 || pi >= da.n_psd) {
+    if (tid == 0) da.out[b] = qnan();
     return;  // uniform over the block
   }
   const int64_t nb = g.n_bins;
-  const cd* RA = residual + (int64_t)ri * 2 * nb;
+  const cd* RA = da.residual + (int64_t)ri * 2 * nb;
   const cd* RE = RA + nb;
-  const double* SA = psd + (int64_t)pi * 2 * nb;
+  const double* SA = da.psd + (int64_t)pi * 2 * nb;
   const double* SE = SA + nb;
   const int64_t ka = hn.q - N / 2;
   const int64_t kr = ho.q - N / 2;
+  const int psd_inv = da.psd_inv;
 
   auto weight = [&](const double* Sc, int64_t idx) { return psd_inv ? Sc[idx] : 1.0 / Sc[idx]; };
 
   // wave 0 decodes the old source, wave 1 the new one; the block shares them
   if (tid < 2 * kWave) {
     const int which = tid / kWave;
-    Src d = decode_source((which ? p_new : p_old) + 8 * b, g);
-    if ((tid & (kWave - 1)) == 0) src_sh[which] = d;
+    Src d = decode_source((which ? da.p_new : da.p_old) + 8 * b, g);
+    if ((tid & (kWave - 1)) == 0) sm.src[which] = d;
   }
 
   // prefetch residual and weights over a's window
@@ -184,11 +217,13 @@ __global__ __launch_bounds__(block_threads<N>()) void k_delta_loglike(
 
   // old template into the LDS window
   if (ho.state == 0) {
-    const Src& so = src_sh[0];
-    template_transform<N, 4>(so, g, tb, buf, tid);
+    const Src& so = sm.src[0];
+    template_transform<N, 4, F>(so, g, tb, sm.buf, tid);
     for (int j = tid; j < N; j += NT) {
-      rwin[j] = bin_value<N>(so, tb, buf, 0, j);
-      rwin[N + j] = bin_value<N>(so, tb, buf, 1, j);
+      cx<F> v[2];
+      bin_spectrum<N, 2, F>(so, g, tb, sm.buf, j, v);
+      sm.rwin[j] = v[0];
+      sm.rwin[N + j] = v[1];
     }
   }
   __syncthreads();
@@ -200,19 +235,21 @@ __global__ __launch_bounds__(block_threads<N>()) void k_delta_loglike(
   };
 
   if (hn.state == 0) {
-    const Src& sn = src_sh[1];
-    template_transform<N, 4>(sn, g, tb, buf, tid);
+    const Src& sn = sm.src[1];
+    template_transform<N, 4, F>(sn, g, tb, sm.buf, tid);
 #pragma unroll
     for (int m = 0; m < BPT; m++) {
       const int j = tid + NT * m;
       int64_t k = ka + j;
       if (k < g.k_min || k >= g.k_min + nb) continue;
-      cd a0 = bin_value<N>(sn, tb, buf, 0, j);
-      cd a1 = bin_value<N>(sn, tb, buf, 1, j);
+      cx<F> v[2];
+      bin_spectrum<N, 2, F>(sn, g, tb, sm.buf, j, v);
+      cd a0 = cvt<double>(v[0]);
+      cd a1 = cvt<double>(v[1]);
       int64_t jr = k - kr;
       if (ho.state == 0 && jr >= 0 && jr < N) {
-        a0 = a0 - rwin[jr];
-        a1 = a1 - rwin[N + jr];
+        a0 = a0 - cvt<double>(sm.rwin[jr]);
+        a1 = a1 - cvt<double>(sm.rwin[N + jr]);
       }
       accumulate(pR0[m], pR1[m], pW0[m], pW1[m], a0, a1);
     }
@@ -224,25 +261,86 @@ __global__ __launch_bounds__(block_threads<N>()) void k_delta_loglike(
       if (hn.state == 0 && k >= ka && k < ka + N) continue;
       if (k < g.k_min || k >= g.k_min + nb) continue;
       int64_t idx = k - g.k_min;
-      cd r0 = rwin[j], r1 = rwin[N + j];
+      cd r0 = cvt<double>(sm.rwin[j]), r1 = cvt<double>(sm.rwin[N + j]);
       accumulate(RA[idx], RE[idx], weight(SA, idx), weight(SE, idx), cd{-r0.re, -r0.im}, cd{-r1.re, -r1.im});
     }
   }
-  acc_rd = block_sum<NT>(acc_rd, red);
-  acc_dd = block_sum<NT>(acc_dd, red + NT / kWave);
-  if (tid == 0) out[b] = g.df4 * acc_rd - 0.5 * g.df4 * acc_dd;
+  acc_rd = block_sum<NT>(acc_rd, sm.red);
+  acc_dd = block_sum<NT>(acc_dd, sm.red + NT / kWave);
+  if (tid == 0) da.out[b] = g.df4 * acc_rd - 0.5 * g.df4 * acc_dd;
+}
+
+template <int N, typename F>
+__global__ __launch_bounds__(block_threads<N>()) void k_delta_loglike(Geo g, WaveTables<F> tb, DeltaArgs da,
+                                                                      int64_t b0) {
+  __shared__ DeltaSmem<N, F> sm;
+  delta_one<N, F>(g, tb, da, b0 + blockIdx.x, sm);
+}
+
+// ---------------------------------------------------------------------------
+// Uneven template widths in one call: bucket the templates by N on the
+// device (atomic position counters, no host round trip), then one launch per
+// width whose grid covers the whole batch; block i takes the i-th template of
+// its bucket and blocks past the bucket's count exit at once, so the hardware
+// dispatcher balances the work and the host never waits.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int width_bucket(int N) {
+  return N == 128 ? 0 : N == 256 ? 1 : N == 512 ? 2 : N == 1024 ? 3 : -1;
+}
+
+__global__ void k_bucket_reset(int* counts, int n) {
+  if (threadIdx.x < n) counts[threadIdx.x] = 0;
+}
+
+// Templates whose width is not supported are not queued; they get a NaN
+// output (bad_out) or the start-bin sentinel INT64_MIN (bad_start).
+__global__ void k_bucket_by_width(const int32_t* __restrict__ widths, int64_t b0, int64_t nb, int cap,
+                                  int* __restrict__ counts, int32_t* __restrict__ perm, double* __restrict__ bad_out,
+                                  int64_t* __restrict__ bad_start) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nb) return;
+  int slot = width_bucket(widths[b0 + i]);
+  if (slot < 0) {
+    if (bad_out) bad_out[b0 + i] = qnan();
+    if (bad_start) bad_start[b0 + i] = INT64_MIN;
+    return;
+  }
+  int pos = atomicAdd(&counts[slot], 1);
+  perm[(int64_t)slot * cap + pos] = (int32_t)i;
+}
+
+template <int N, typename F>
+__global__ __launch_bounds__(block_threads<N>()) void k_delta_loglike_bucket(Geo g, WaveTables<F> tb, DeltaArgs da,
+                                                                             int64_t b0, const int* __restrict__ count,
+                                                                             const int32_t* __restrict__ perm) {
+  __shared__ DeltaSmem<N, F> sm;
+  if ((int)blockIdx.x >= *count) return;
+  delta_one<N, F>(g, tb, da, b0 + perm[blockIdx.x], sm);
+}
+
+template <int N, int NSER, typename F>
+__global__ __launch_bounds__(block_threads<N>()) void k_waveform_bucket(Geo g, WaveTables<F> tb,
+                                                                        const double* __restrict__ params, int64_t b0,
+                                                                        const int64_t* __restrict__ out_offset,
+                                                                        cd* A, cd* E, cd* Tc, int64_t* start,
+                                                                        const int* __restrict__ count,
+                                                                        const int32_t* __restrict__ perm) {
+  __shared__ WaveSmem<N, NSER, F> sm;
+  if ((int)blockIdx.x >= *count) return;
+  const int64_t b = b0 + perm[blockIdx.x];
+  waveform_one<N, NSER, F>(g, tb, params + 8 * b, out_offset[b], A, E, Tc, start + b, sm);
 }
 
 // ---------------------------------------------------------------------------
 // gb_scatter_add: residual[res_idx[b]] += sign * template b (A, E), FP64 atomics.
 // ---------------------------------------------------------------------------
-template <int N>
-__global__ __launch_bounds__(block_threads<N>()) void k_scatter_add(Geo g, WaveTables tb,
+template <int N, typename F>
+__global__ __launch_bounds__(block_threads<N>()) void k_scatter_add(Geo g, WaveTables<F> tb,
                                                                     const double* __restrict__ params, int64_t b0,
                                                                     double sign, cd* residual, int n_res,
                                                                     const int32_t* __restrict__ res_idx) {
   constexpr int NT = block_threads<N>();
-  __shared__ cd buf[4 * series_pitch<N>()];
+  __shared__ cx<F> buf[4 * series_pitch<N>()];
   __shared__ Src s_sh;
   const int64_t b = b0 + blockIdx.x;
   const int tid = threadIdx.x;
@@ -255,7 +353,7 @@ __global__ __launch_bounds__(block_threads<N>()) void k_scatter_add(Geo g, WaveT
   }
   __syncthreads();
   const Src& s = s_sh;
-  template_transform<N, 4>(s, g, tb, buf, tid);
+  template_transform<N, 4, F>(s, g, tb, buf, tid);
   const int64_t nb = g.n_bins;
   const int64_t k0 = s.q - N / 2;
   cd* R = residual + (int64_t)ri * 2 * nb;
@@ -263,12 +361,13 @@ __global__ __launch_bounds__(block_threads<N>()) void k_scatter_add(Geo g, WaveT
     int64_t k = k0 + j;
     if (k < g.k_min || k >= g.k_min + nb) continue;
     int64_t idx = k - g.k_min;
+    cx<F> v[2];
+    bin_spectrum<N, 2, F>(s, g, tb, buf, j, v);
 #pragma unroll
     for (int c = 0; c < 2; c++) {
-      cd v = bin_value<N>(s, tb, buf, c, j);
       double* dst = reinterpret_cast<double*>(R + c * nb + idx);
-      atomicAdd(dst, sign * v.re);
-      atomicAdd(dst + 1, sign * v.im);
+      atomicAdd(dst, sign * (double)v[c].re);
+      atomicAdd(dst + 1, sign * (double)v[c].im);
     }
   }
 }

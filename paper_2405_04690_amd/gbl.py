@@ -19,12 +19,14 @@ GBL_EINVAL = -1
 GBL_EUNSUPPORTED = -2
 GBL_EHIP = -3
 GBL_FP64 = 0
+GBL_MIXED = 1
 GBL_PSD_INVERSE = 1
 
 SUPPORTED_N = (128, 256, 512, 1024)
 
 EXPORTED = ("gbl_create", "gbl_destroy", "gbl_set_stream", "gbl_last_error", "gbl_band", "gb_waveform",
-            "gb_delta_loglike", "gb_psd_eval", "gb_psd_loglike", "gb_scatter_add", "gb_make_noise")
+            "gb_waveform_var", "gb_delta_loglike", "gb_delta_loglike_var", "gb_psd_eval", "gb_psd_loglike",
+            "gb_scatter_add", "gb_make_noise")
 
 
 class GblError(RuntimeError):
@@ -57,7 +59,9 @@ def load_library(path: str = LIB_PATH):
         "gbl_set_stream": [vp, vp],
         "gbl_band": [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)],
         "gb_waveform": [vp, vp, i64, i32, dbl, dbl, vp, vp, vp, vp],
+        "gb_waveform_var": [vp, vp, vp, vp, i64, vp, vp, vp, vp],
         "gb_delta_loglike": [vp, vp, i32, vp, i32, i32, vp, vp, i32, vp, vp, i64, vp],
+        "gb_delta_loglike_var": [vp, vp, i32, vp, i32, i32, vp, vp, vp, vp, vp, i64, vp],
         "gb_psd_eval": [vp, vp, i64, i32, vp],
         "gb_psd_loglike": [vp, vp, i32, vp, vp, i64, vp],
         "gb_scatter_add": [vp, vp, i64, i32, dbl, vp, i32, vp],
@@ -156,6 +160,33 @@ class Context:
         self._check(rc, "gb_waveform")
         return A, E, Tc, sb
 
+    def gb_waveform_var(self, params, N, with_T: bool = True):
+        """Templates of per-template width N[b]; slices packed back to back.
+
+        Returns (A, E, T, start_bin, offsets) with A/E/T flat complex arrays of
+        length sum(N) and offsets[b] the first element of template b."""
+        params = self._params(params)
+        N = self._dev(N, torch.int32, "N")
+        B = params.shape[0]
+        if N.numel() != B:
+            raise ValueError("N must have B entries")
+        Nl = N.to(torch.int64)
+        # widths outside the supported set occupy no output space
+        ok = (Nl == 128) | (Nl == 256) | (Nl == 512) | (Nl == 1024)
+        sizes = torch.where(ok, Nl, torch.zeros_like(Nl))
+        offsets = torch.cumsum(sizes, 0) - sizes
+        total = int(sizes.sum().item()) if B else 0
+        kw = dict(device=self.device, dtype=torch.complex128)
+        A = torch.empty(max(total, 1), **kw)
+        E = torch.empty(max(total, 1), **kw)
+        Tc = torch.empty(max(total, 1), **kw) if with_T else None
+        sb = torch.empty(B, dtype=torch.int64, device=self.device)
+        self._sync_stream()
+        rc = self.lib.gb_waveform_var(self._h, _ptr(params), _ptr(N), _ptr(offsets), B, _ptr(A), _ptr(E), _ptr(Tc),
+                                      _ptr(sb))
+        self._check(rc, "gb_waveform_var")
+        return A[:total], E[:total], (Tc[:total] if with_T else None), sb, offsets
+
     def gb_delta_loglike(self, residual, psd, params_old, params_new, N: int, res_idx=None, psd_idx=None,
                          psd_inverse: bool = False, out=None):
         residual = self._residual(residual)
@@ -182,6 +213,34 @@ class Context:
                                        GBL_PSD_INVERSE if psd_inverse else 0, _ptr(po), _ptr(pn), int(N),
                                        _ptr(res_idx), _ptr(psd_idx), B, _ptr(out))
         self._check(rc, "gb_delta_loglike")
+        return out
+
+    def gb_delta_loglike_var(self, residual, psd, params_old, params_new, N, res_idx=None, psd_idx=None,
+                             psd_inverse: bool = False, out=None):
+        """As gb_delta_loglike with a per-pair template width N[b] (int32 tensor)."""
+        residual = self._residual(residual)
+        psd = self._dev(psd, torch.float64, "psd")
+        if psd.dim() != 3 or psd.shape[1] != 2 or psd.shape[2] != self.n_bins:
+            raise ValueError("psd must have shape [n_psd, 2, n_bins]")
+        po = self._params(params_old, "params_old")
+        pn = self._params(params_new, "params_new")
+        B = po.shape[0]
+        N = self._dev(N, torch.int32, "N")
+        if pn.shape[0] != B or N.numel() != B:
+            raise ValueError("params_old, params_new and N differ in length")
+        if res_idx is None:
+            res_idx = torch.zeros(B, dtype=torch.int32, device=self.device)
+        if psd_idx is None:
+            psd_idx = torch.zeros(B, dtype=torch.int32, device=self.device)
+        res_idx = self._dev(res_idx, torch.int32, "res_idx")
+        psd_idx = self._dev(psd_idx, torch.int32, "psd_idx")
+        if out is None:
+            out = torch.empty(B, dtype=torch.float64, device=self.device)
+        self._sync_stream()
+        rc = self.lib.gb_delta_loglike_var(self._h, _ptr(residual), residual.shape[0], _ptr(psd), psd.shape[0],
+                                           GBL_PSD_INVERSE if psd_inverse else 0, _ptr(po), _ptr(pn), _ptr(N),
+                                           _ptr(res_idx), _ptr(psd_idx), B, _ptr(out))
+        self._check(rc, "gb_delta_loglike_var")
         return out
 
     def gb_psd_eval(self, noise, inverse: bool = False):

@@ -40,6 +40,8 @@ def test_null_context_rejected_on_host(lib):
     assert lib.gbl_band(null, None, None) == gbl.GBL_EINVAL
     assert lib.gb_waveform(null, null, 1, 256, 1.0, 1.0, null, null, null, null) == gbl.GBL_EINVAL
     assert lib.gb_delta_loglike(null, null, 1, null, 1, 0, null, null, 256, null, null, 1, null) == gbl.GBL_EINVAL
+    assert lib.gb_delta_loglike_var(null, null, 1, null, 1, 0, null, null, null, null, null, 1, null) == gbl.GBL_EINVAL
+    assert lib.gb_waveform_var(null, null, null, null, 1, null, null, null, null) == gbl.GBL_EINVAL
     assert lib.gb_psd_eval(null, null, 1, 0, null) == gbl.GBL_EINVAL
     assert lib.gb_psd_loglike(null, null, 1, null, null, 1, null) == gbl.GBL_EINVAL
     assert lib.gb_scatter_add(null, null, 1, 256, 1.0, null, 1, null) == gbl.GBL_EINVAL

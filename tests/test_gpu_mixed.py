@@ -1,0 +1,94 @@
+"""Mixed-precision mode (orbital/carrier phases and all sums in FP64; link
+amplitudes, TDI response, FFT and per-bin factors in FP32) against the FP64
+CPU oracle.
+
+Bars, derived from the arithmetic: a template carries a relative error of a
+few FP32 roundings (eps32 = 2^-24 ~ 6e-8 per operation; ~30 operations in the
+slow part and log2 N FFT stages), so waveform slices must agree within 2e-6
+of the template's peak.  The likelihood change then errs by up to about
+eps32 times its largest inner-product term (~SNR x mismatch SNR), so
+|dlogL_mixed - dlogL_oracle| <= 1e-3 + 20 eps32 max|terms|: 1e-3 absolute for
+every pair whose terms stay below ~800, and a relative bound for louder ones.
+Integer outputs are exact."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2405_04690_amd import inputs
+from paper_2405_04690_amd.gbl import GBL_MIXED, Context
+
+pytestmark = pytest.mark.gpu
+
+DLOGL_ABS_TOL = 1e-3
+EPS32 = 2.0 ** -24
+WAVE_REL_TOL = 2e-6
+
+
+def _t(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(torch.device("cuda", 0))
+
+
+@pytest.fixture(scope="module")
+def mixed():
+    cfg = inputs.TINY
+    ctx = Context(T=cfg.T, dt=cfg.dt, L=cfg.L, f_lo=cfg.f_lo, f_hi=cfg.f_hi, precision=GBL_MIXED)
+    orc = oracle.Oracle(T=cfg.T, dt=cfg.dt, L=cfg.L, f_lo=cfg.f_lo, f_hi=cfg.f_hi)
+    yield cfg, ctx, orc
+    ctx.close()
+
+
+@pytest.mark.parametrize("N", [128, 256, 512, 1024])
+def test_mixed_waveform_error(mixed, N):
+    cfg, ctx, orc = mixed
+    params = inputs.draw_sources(300 + N, 40, log10_fdot_range=(-19, -15))
+    A, E, Tc, sb = ctx.gb_waveform(_t(params), N)
+    oA, oE, oT, osb = orc.waveform(params, N)
+    assert np.array_equal(sb.cpu().numpy(), osb)
+    gA, gE = A.cpu().numpy(), E.cpu().numpy()
+    worst = 0.0
+    for b in range(len(params)):
+        scale = max(np.abs(oA[b]).max(), np.abs(oE[b]).max())
+        worst = max(worst, np.abs(gA[b] - oA[b]).max() / scale, np.abs(gE[b] - oE[b]).max() / scale)
+    print(f"mixed waveform N={N}: max error / peak = {worst:.2e}")
+    assert worst <= WAVE_REL_TOL
+
+
+@pytest.mark.parametrize("N", [128, 256, 1024])
+def test_mixed_delta_loglike_error(mixed, N):
+    cfg, ctx, orc = mixed
+    S = orc.psd_eval(np.array([cfg.sqrt_oms, cfg.sqrt_acc, cfg.sqrt_oms, cfg.sqrt_acc]))
+    src = inputs.draw_sources(400, 48, log10_fdot_range=(-19, -15))
+    R = np.sqrt(S[0] / (4 * orc.df)) * inputs.complex_normals(401, (2, orc.n_bins))
+    orc.scatter_add(src, N, 1.0, R)
+    old = inputs.perturb(402, src, orc.T, "jitter")
+    orc.scatter_add(old, N, -1.0, R)
+    new = inputs.perturb(403, old, orc.T, "inmodel")
+    # births (old amplitude 0) and deaths (new amplitude 0) besides the in-model moves
+    born = new[:8].copy()
+    empty_b = born.copy(); empty_b[:, 0] = 0.0
+    dying = old[8:16].copy()
+    empty_d = dying.copy(); empty_d[:, 0] = 0.0
+    old2 = np.vstack([old, empty_b, dying])
+    new2 = np.vstack([new, born, empty_d])
+    got = ctx.gb_delta_loglike(_t(R[None]), _t(S), _t(old2), _t(new2), N).cpu().numpy()
+    ref, terms = orc.delta_loglike(R[None], S, old2, new2, N, return_terms=True)
+    err = np.abs(got - ref)
+    scale = np.abs(terms[:, :5]).max(axis=1)
+    snr = np.sqrt(np.maximum(terms[:, 0], terms[:, 1]))
+    print(f"mixed dlogL N={N}: max |err| = {err.max():.2e} (max SNR {snr.max():.1f}), "
+          f"median {np.median(err):.1e}, within 1e-3: {np.mean(err <= DLOGL_ABS_TOL):.3f}, "
+          f"max err/scale {np.max(err / np.maximum(scale, 1)):.2e}")
+    assert np.all(err <= DLOGL_ABS_TOL + 20 * EPS32 * scale)
+    quiet = scale < 800
+    assert np.all(err[quiet] <= DLOGL_ABS_TOL)
+
+
+def test_mixed_psd_and_scatter_paths_run(mixed):
+    cfg, ctx, orc = mixed
+    params = inputs.draw_sources(500, 10)
+    res = torch.zeros((1, 2, ctx.n_bins), dtype=torch.complex128, device="cuda:0")
+    ctx.gb_scatter_add(_t(params), 256, 1.0, res)
+    exp = np.zeros((1, 2, orc.n_bins), np.complex128)
+    orc.scatter_add(params, 256, 1.0, exp)
+    assert np.max(np.abs(res.cpu().numpy() - exp)) <= WAVE_REL_TOL * np.abs(exp).max()

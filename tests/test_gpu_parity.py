@@ -160,6 +160,57 @@ def test_delta_loglike_parity(tiny, tiny_likelihood_data, N, inverse):
     assert np.all(got[ident] == 0.0)
 
 
+def _width_rule(f0):
+    """Template width by frequency: 128 (< 1 mHz), 256 (< 3 mHz), 512 (< 6 mHz), 1024 above."""
+    return np.where(f0 < 1e-3, 128, np.where(f0 < 3e-3, 256, np.where(f0 < 6e-3, 512, 1024))).astype(np.int32)
+
+
+def test_waveform_var_parity(tiny):
+    cfg, ctx, orc = tiny
+    params = inputs.draw_sources(61, 150, log10_fdot_range=(-19, -15))
+    N = _width_rule(params[:, 1])
+    N[7] = 300  # unsupported width: skipped, sentinel start bin
+    print(f"waveform_var B={len(params)} widths={np.unique(N, return_counts=True)}", flush=True)
+    A, E, Tc, sb, off = ctx.gb_waveform_var(_t(params), _t(N))
+    A, E, Tc, sb, off = (x.cpu().numpy() for x in (A, E, Tc, sb, off))
+    assert sb[7] == np.iinfo(np.int64).min
+    for w in (128, 256, 512, 1024):
+        idx = np.nonzero(N == w)[0]
+        oA, oE, oT, osb = orc.waveform(params[idx], w)
+        assert np.array_equal(sb[idx], osb)
+        for r, b in enumerate(idx):
+            sl = slice(off[b], off[b] + w)
+            scale = max(np.abs(oA[r]).max(), np.abs(oE[r]).max())
+            assert np.abs(A[sl] - oA[r]).max() <= TOL * scale
+            assert np.abs(E[sl] - oE[r]).max() <= TOL * scale
+            assert np.abs(Tc[sl] - oT[r]).max() <= TOL * scale
+
+
+def test_delta_loglike_var_parity(tiny, tiny_likelihood_data):
+    cfg, ctx, orc = tiny
+    S, R, src = tiny_likelihood_data
+    old, new = _pairs(orc, src, 900)
+    N = _width_rule(old[:, 1])
+    N[5] = 64  # unsupported width -> NaN
+    B = len(old)
+    rng = np.random.default_rng(3)
+    ri = rng.integers(0, 3, B).astype(np.int32)
+    pi = rng.integers(0, 2, B).astype(np.int32)
+    print(f"delta_loglike_var B={B} widths={np.unique(N, return_counts=True)}", flush=True)
+    got = ctx.gb_delta_loglike_var(_t(R), _t(S), _t(old), _t(new), _t(N), _t(ri), _t(pi)).cpu().numpy()
+    assert np.isnan(got[5])
+    for w in (128, 256, 512, 1024):
+        idx = np.nonzero(N == w)[0]
+        ref, terms = orc.delta_loglike(R, S, old[idx], new[idx], w, ri[idx], pi[idx], return_terms=True)
+        scale = np.maximum(1.0, np.abs(terms[:, :5]).max(axis=1))
+        assert np.max(np.abs(got[idx] - ref) / scale) <= TOL, w
+    # the fixed-width entry point gives bitwise the same results per width
+    for w in (256, 1024):
+        idx = np.nonzero(N == w)[0]
+        fixed = ctx.gb_delta_loglike(_t(R), _t(S), _t(old[idx]), _t(new[idx]), w, _t(ri[idx]), _t(pi[idx]))
+        assert np.array_equal(fixed.cpu().numpy(), got[idx])
+
+
 def test_delta_loglike_invalid_inputs_give_nan(tiny, tiny_likelihood_data):
     cfg, ctx, orc = tiny
     S, R, src = tiny_likelihood_data
