@@ -30,6 +30,26 @@ FP64_PEAK_TFLOPS = 78.6   # MI355X FP64 vector (256 CU x 4 SIMD x 16 lanes x 2 f
 HBM_PEAK_GBS = 8000.0
 
 
+def measured_traffic():
+    """HBM-side bytes per launch of the fused FP64 N=256 kernel from the two
+    rocprofv3 counter runs recorded under profiles/ (FETCH_SIZE, WRITE_SIZE,
+    scaled by a plain copy of known size), or None once the kernel sources
+    differ from the profiled ones."""
+    import glob
+    import hashlib
+    path = os.path.join(HERE, "profiles", "k_delta_loglike_fp64_N256_traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    files = sorted(glob.glob(os.path.join(HERE, "paper_2405_04690_amd", "csrc", "*.hpp")) +
+                   glob.glob(os.path.join(HERE, "paper_2405_04690_amd", "csrc", "*.hip")))
+    h = hashlib.sha256()
+    for f in files:
+        h.update(os.path.basename(f).encode())
+        h.update(open(f, "rb").read())
+    return rec["traffic_bytes_per_launch"] if h.hexdigest() == rec["source_sha256"] else None
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -221,7 +241,7 @@ def main():
     bytes_l, flops_l = workmodel.launch_work(batch.params_old, batch.params_new, cfg.T, cfg.N)
     achieved = flops_l / (per_launch_ms / 1e3) / 1e12
     roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-            "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": None,
+            "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": measured_traffic(),
             "kernel": "k_delta_loglike<256>", "avg_launch_ms": round(per_launch_ms, 4),
             "algorithmic_gbs": round(bytes_l / (per_launch_ms / 1e3) / 1e9, 1),
             "algorithmic_hbm_frac": round(bytes_l / (per_launch_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
