@@ -180,6 +180,81 @@ int gb_scatter_add(gbl_ctx* ctx, const double* params, int64_t B, int32_t N, dou
  * E[<n|n>] = 2 per bin and channel.  Errors: GBL_EINVAL. */
 int gb_make_noise(gbl_ctx* ctx, const double* S, const double* normals, int64_t n, double* out);
 
+/* ------------------------------------------------------------------------
+ * Sampler sweep (Sec. 4 "Galactic binary search and parameter estimation";
+ * appendix algorithms gb1 "Galaxy sampling" and gb2 "Galaxy tempering";
+ * eqs. rj-acceptance, stretch, temp-final).
+ *
+ * Sub-band b covers bins [k_band0 + b N, k_band0 + (b+1) N) (N = template
+ * width, 128/256/512); its analysis window is sub-bands b-1..b+1.  A sweep is:
+ * stationary-group refresh (every group_every sweeps), in-model group-stretch
+ * band loops (odd bands, then even), the reversible-jump pass that flips every
+ * slot (odd, even), residual-aware parallel tempering (odd, even), and
+ * sweep_counter += 1.  Bands of one parity run in parallel: they read the
+ * opposite-parity cold-chain buffer and write only their own.
+ * Sampling coordinates u = (log10 A, f0 [Hz], fdot [Hz/s], phi0, cos iota,
+ * psi, lambda, sin beta) with a uniform prior on a box: prior_lo/hi give the
+ * bounds of log10 A, fdot, cos iota and sin beta; f0 ranges over the band
+ * widened by N/2 per side; phi0, psi, lambda are periodic (2 pi, pi, 2 pi).
+ * Random numbers: Philox4x64-10 keyed by seed with counter
+ * (sweep, move << 40 | unit, draw / 4, 0).
+ * ------------------------------------------------------------------------ */
+#define GBL_MOVE_INMODEL 0
+#define GBL_MOVE_RJ 1
+#define GBL_MOVE_PT 2
+
+typedef struct {
+  int32_t n_temps, n_walkers, n_bands, n_slots; /* n_slots <= 64, n_temps and n_walkers <= 256 */
+  int32_t N;                                   /* template width = sub-band width */
+  int32_t n_prop;                              /* in-model proposals per band per sweep */
+  int32_t n_friends;                           /* group-stretch friends */
+  int32_t group_every;                         /* stationary-group refresh period (sweeps); 0 = never */
+  int64_t k_band0;                             /* first bin of sub-band 0 */
+  double stretch_a;                            /* stretch scale a > 1 */
+  uint64_t seed;
+  double prior_lo[8], prior_hi[8];
+} gbl_sweep_config;
+
+/* Sampler state: caller-owned device arrays (checkpointable as they are). */
+typedef struct {
+  double* u;              /* [n_temps][n_walkers][n_bands][n_slots][8] sampling coordinates */
+  int32_t* exists;        /* [n_temps][n_walkers][n_bands][n_slots] 0/1 */
+  double* betas;          /* [n_bands][n_temps] inverse temperatures, betas[b][0] = 1 */
+  double* resid;          /* [2][n_walkers][2][n_bins] complex: parity-p buffer = data minus the
+                             cold-chain sources of the bands with b % 2 == p */
+  const double* inv_psd;  /* [n_walkers][2][n_bins] 1/S per walker */
+  double* group;          /* [n_bands][n_walkers * n_slots][8] stationary groups (sorted by f0) */
+  int32_t* group_count;   /* [n_bands] */
+  int64_t* stats;         /* [8] in-model proposed/accepted, births, deaths, swaps (proposed/accepted) */
+  int64_t* sweep_counter; /* [1] current sweep index */
+} gbl_sweep_state;
+
+typedef struct gbl_graph gbl_graph;
+
+/* One move type over the bands of one parity, using *sweep_counter for the
+ * random streams.  Errors: GBL_EINVAL (null pointers, out-of-range config),
+ * GBL_EUNSUPPORTED (N = 1024 or a mixed-precision context). */
+int gb_sweep_step(gbl_ctx* ctx, const gbl_sweep_config* cfg, const gbl_sweep_state* st, int32_t move,
+                  int32_t parity);
+
+/* Rebuild the stationary groups from the cold chain (t = 0) of every walker. */
+int gb_sweep_group(gbl_ctx* ctx, const gbl_sweep_config* cfg, const gbl_sweep_state* st);
+
+/* *sweep_counter += 1 on the device. */
+int gb_sweep_advance(gbl_ctx* ctx, const gbl_sweep_state* st);
+
+/* n_sweeps full sweeps (see above), enqueued without any host synchronisation. */
+int gb_sweep_run(gbl_ctx* ctx, const gbl_sweep_config* cfg, const gbl_sweep_state* st, int32_t n_sweeps);
+
+/* Capture n_sweeps full sweeps into a HIP graph on the context's stream (which
+ * must not be the default stream); gb_graph_launch replays it (each replay
+ * advances the sweep counter, so replays draw fresh random numbers).
+ * The captured launches keep the state pointers given here. */
+int gb_sweep_graph_create(gbl_ctx* ctx, const gbl_sweep_config* cfg, const gbl_sweep_state* st, int32_t n_sweeps,
+                          gbl_graph** graph);
+int gb_graph_launch(gbl_graph* graph);
+int gb_graph_destroy(gbl_graph* graph);
+
 #ifdef __cplusplus
 }
 #endif

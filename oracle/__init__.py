@@ -39,6 +39,18 @@ class Config(ctypes.Structure):
                 ("f_lo", ctypes.c_double), ("f_hi", ctypes.c_double)]
 
 
+class SweepConfig(ctypes.Structure):
+    """Sampler configuration (field order of gblo_sweep_config)."""
+    _fields_ = [("n_temps", ctypes.c_int32), ("n_walkers", ctypes.c_int32), ("n_bands", ctypes.c_int32),
+                ("n_slots", ctypes.c_int32), ("N", ctypes.c_int32), ("n_prop", ctypes.c_int32),
+                ("n_friends", ctypes.c_int32), ("group_every", ctypes.c_int32), ("k_band0", ctypes.c_int64),
+                ("stretch_a", ctypes.c_double), ("seed", ctypes.c_uint64),
+                ("prior_lo", ctypes.c_double * 8), ("prior_hi", ctypes.c_double * 8)]
+
+
+MOVE_INMODEL, MOVE_RJ, MOVE_PT = 0, 1, 2
+
+
 _lib = None
 
 
@@ -69,6 +81,14 @@ def _load():
                                                   ctypes.c_int32, I32, I32, ctypes.c_int64, D, D]),
             "gblo_scatter_add": (ctypes.c_int, [C, D, ctypes.c_int64, ctypes.c_int32, ctypes.c_double, D,
                                                 ctypes.c_int32, I32]),
+            "gblo_philox": (None, [ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64),
+                                   ctypes.POINTER(ctypes.c_uint64)]),
+            "gblo_rng_uniform": (ctypes.c_double, [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int, ctypes.c_uint64,
+                                                   ctypes.c_uint64]),
+            "gblo_pt_log_alpha": (ctypes.c_double, [ctypes.c_double] * 6),
+            "gblo_sweep_step": (ctypes.c_int, [C, ctypes.POINTER(SweepConfig), ctypes.c_int, ctypes.c_int,
+                                               ctypes.c_int64, D, I32, D, D, D, D, I32, I64]),
+            "gblo_sweep_group": (ctypes.c_int, [ctypes.POINTER(SweepConfig), D, I32, D, I32]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(lib, name)
@@ -218,3 +238,58 @@ class Oracle:
                                        _d(res3.view(np.float64)), res3.shape[0], _i32(res_idx))
         _check(rc, "scatter_add")
         return residual
+
+
+def philox(ctr, key):
+    """Philox4x64-10 block for a 4-word counter and 2-word key."""
+    lib = _load()
+    c = (ctypes.c_uint64 * 4)(*[int(x) for x in ctr])
+    k = (ctypes.c_uint64 * 2)(*[int(x) for x in key])
+    o = (ctypes.c_uint64 * 4)()
+    lib.gblo_philox(c, k, o)
+    return [int(x) for x in o]
+
+
+def rng_uniform(seed, sweep, move, unit, idx):
+    return float(_load().gblo_rng_uniform(int(seed), int(sweep), int(move), int(unit), int(idx)))
+
+
+def pt_log_alpha(bI, bII, lnL_im, lnL_in, lnL_jn, lnL_jm):
+    return float(_load().gblo_pt_log_alpha(bI, bII, lnL_im, lnL_in, lnL_jn, lnL_jm))
+
+
+class SweepState:
+    """Host arrays of the sampler state (layouts as documented in gbl_oracle.c)."""
+
+    def __init__(self, sc: SweepConfig, n_bins: int):
+        nt, nw, nb, ns = sc.n_temps, sc.n_walkers, sc.n_bands, sc.n_slots
+        self.u = np.zeros((nt, nw, nb, ns, 8))
+        self.exists = np.zeros((nt, nw, nb, ns), np.int32)
+        self.betas = np.ones((nb, nt))
+        self.resid = np.zeros((2, nw, 2, n_bins), np.complex128)
+        self.inv_psd = np.zeros((nw, 2, n_bins))
+        self.group = np.zeros((nb, nw * ns, 8))
+        self.group_count = np.zeros(nb, np.int32)
+        self.stats = np.zeros(8, np.int64)
+
+
+def sweep_step(orc: "Oracle", sc: SweepConfig, st: SweepState, move: int, parity: int, sweep: int):
+    rc = orc.lib.gblo_sweep_step(ctypes.byref(orc.cfg), ctypes.byref(sc), int(move), int(parity), int(sweep),
+                                 _d(st.u), _i32(st.exists), _d(st.betas), _d(st.resid.view(np.float64)),
+                                 _d(st.inv_psd), _d(st.group), _i32(st.group_count), _i64(st.stats))
+    _check(rc, "sweep_step")
+
+
+def sweep_group(sc: SweepConfig, st: SweepState):
+    rc = _load().gblo_sweep_group(ctypes.byref(sc), _d(st.u), _i32(st.exists), _d(st.group), _i32(st.group_count))
+    _check(rc, "sweep_group")
+
+
+def sweep_full(orc: "Oracle", sc: SweepConfig, st: SweepState, sweep: int):
+    """One full sweep in the library's order: group refresh (when due),
+    in-model (odd, even), RJ (odd, even), tempering (odd, even)."""
+    if sc.group_every > 0 and sweep % sc.group_every == 0:
+        sweep_group(sc, st)
+    for move in (MOVE_INMODEL, MOVE_RJ, MOVE_PT):
+        for parity in (1, 0):
+            sweep_step(orc, sc, st, move, parity, sweep)

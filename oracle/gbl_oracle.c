@@ -528,3 +528,522 @@ int gblo_scatter_add(const gblo_config* cfg, const double* params, int64_t B, in
   free(a);
   return 0;
 }
+
+/* ======================================================================== */
+/* Sampler arithmetic (Sec. 4 and the appendix algorithms gb1 / gb2).        */
+/* ======================================================================== */
+
+/* Counter-based random numbers: Philox4x64-10 (Salmon, Moraes, Dror, Shaw,
+ * SC'11), written from its published definition: ten rounds of
+ * (hi0, lo0) = X0 * M0, (hi1, lo1) = X2 * M1 (128-bit products),
+ * X <- (hi1 ^ X1 ^ K0, lo1, hi0 ^ X3 ^ K1, lo0), keys bumped by the Weyl
+ * constants between rounds. */
+static void philox4x64_10(const uint64_t ctr_in[4], const uint64_t key_in[2], uint64_t out[4]) {
+  const uint64_t M0 = 0xD2E7470EE14C6C93ULL, M1 = 0xCA5A826395121157ULL;
+  const uint64_t W0 = 0x9E3779B97F4A7C15ULL, W1 = 0xBB67AE8584CAA73BULL;
+  uint64_t x[4] = {ctr_in[0], ctr_in[1], ctr_in[2], ctr_in[3]};
+  uint64_t k0 = key_in[0], k1 = key_in[1];
+  for (int r = 0; r < 10; r++) {
+    unsigned __int128 p0 = (unsigned __int128)M0 * x[0];
+    unsigned __int128 p1 = (unsigned __int128)M1 * x[2];
+    uint64_t hi0 = (uint64_t)(p0 >> 64), lo0 = (uint64_t)p0;
+    uint64_t hi1 = (uint64_t)(p1 >> 64), lo1 = (uint64_t)p1;
+    uint64_t y0 = hi1 ^ x[1] ^ k0, y2 = hi0 ^ x[3] ^ k1;
+    x[0] = y0;
+    x[1] = lo1;
+    x[2] = y2;
+    x[3] = lo0;
+    k0 += W0;
+    k1 += W1;
+  }
+  for (int i = 0; i < 4; i++) out[i] = x[i];
+}
+
+void gblo_philox(const uint64_t* ctr, const uint64_t* key, uint64_t* out) { philox4x64_10(ctr, key, out); }
+
+/* Uniform in (0, 1) for draw `idx` of stream (sweep, move, unit):
+ * counter = (sweep, move << 40 | unit, idx / 4, 0), word idx % 4,
+ * u = (top 53 bits + 1/2) 2^-53. */
+static double rng_uniform(uint64_t seed, int64_t sweep, int move, uint64_t unit, uint64_t idx) {
+  uint64_t ctr[4] = {(uint64_t)sweep, ((uint64_t)move << 40) | unit, idx >> 2, 0};
+  uint64_t key[2] = {seed, 0};
+  uint64_t o[4];
+  philox4x64_10(ctr, key, o);
+  return ((double)(o[idx & 3] >> 11) + 0.5) * (1.0 / 9007199254740992.0);
+}
+
+double gblo_rng_uniform(uint64_t seed, int64_t sweep, int move, uint64_t unit, uint64_t idx) {
+  return rng_uniform(seed, sweep, move, unit, idx);
+}
+
+/* Sampler configuration (readings where the paper is silent):
+ *  - sub-band b covers bins [k_band0 + b W, k_band0 + (b+1) W) with W = N,
+ *    the template width; its analysis window is bands b-1..b+1;
+ *  - sampling coordinates u = (log10 A, f0, fdot, phi0, cos iota, psi,
+ *    lambda, sin beta) with a uniform prior on a box; f0 of band b ranges over
+ *    the band widened by W/2 on each side (samples may move halfway into the
+ *    neighbours); phi0, psi, lambda are periodic (periods 2 pi, pi, 2 pi);
+ *  - group stretch: z ~ g(z) ~ 1/sqrt(z) on [1/a, a], u' = X + z (u - X) with
+ *    the friend X drawn uniformly from the n_friends entries of the band's
+ *    stationary group (cold-chain sources of all walkers, sorted by f0) that
+ *    surround the current f0; proposal factor z^(d-1), d = 8; periodic
+ *    differences are taken on the circle and the result wrapped;
+ *  - reversible jump: every slot is flipped once per RJ step, in random order
+ *    (birth from the prior: q = p, so the prior/proposal ratio is 1);
+ *  - only the likelihood is tempered: accept iff ln u < beta dlnL + ln(prior
+ *    ratio) + ln(proposal ratio). */
+typedef struct {
+  int32_t n_temps, n_walkers, n_bands, n_slots, N, n_prop, n_friends, group_every;
+  int64_t k_band0;
+  double stretch_a;
+  uint64_t seed;
+  double prior_lo[8], prior_hi[8]; /* f0 bounds unused (per band) */
+} gblo_sweep_config;
+
+#define MOVE_INMODEL 0
+#define MOVE_RJ 1
+#define MOVE_PT 2
+#define MOVE_PTPERM 3
+
+static const double PERIOD[8] = {0, 0, 0, 2.0 * ORC_PI, 0, ORC_PI, 2.0 * ORC_PI, 0};
+
+static void band_f0_range(const gblo_config* cfg, const gblo_sweep_config* sc, int b, double* lo, double* hi) {
+  double W = (double)sc->N;
+  *lo = ((double)sc->k_band0 + ((double)b - 0.5) * W) / cfg->T;
+  *hi = ((double)sc->k_band0 + ((double)b + 1.5) * W) / cfg->T;
+}
+
+/* sampling coordinates -> physical parameters */
+static void u_to_params(const double* u, double* p) {
+  p[0] = pow(10.0, u[0]);
+  p[1] = u[1];
+  p[2] = u[2];
+  p[3] = u[3];
+  p[4] = acos(u[4]);
+  p[5] = u[5];
+  p[6] = u[6];
+  p[7] = asin(u[7]);
+}
+
+static int in_prior(const gblo_config* cfg, const gblo_sweep_config* sc, int b, const double* u) {
+  double flo, fhi;
+  band_f0_range(cfg, sc, b, &flo, &fhi);
+  if (!(u[1] >= flo && u[1] < fhi)) return 0;
+  for (int i = 0; i < 8; i++) {
+    if (i == 1 || PERIOD[i] > 0) continue;
+    if (!(u[i] >= sc->prior_lo[i] && u[i] <= sc->prior_hi[i])) return 0;
+  }
+  return 1;
+}
+
+/* Residual window of one walker: bins [k_band0 + (b-1) W, k_band0 + (b+2) W)
+ * clipped to the analysis band, channels A and E. */
+typedef struct {
+  int64_t k0;   /* first global bin of the window */
+  int len;      /* 3 W */
+  cplx* r[2];   /* per channel */
+} window_t;
+
+static int64_t win_start(const gblo_sweep_config* sc, int b) { return sc->k_band0 + (int64_t)(b - 1) * sc->N; }
+
+/* add s * template(u) to the window (bins outside the window or the band are dropped) */
+static void window_add_template(const gblo_config* cfg, int64_t k_min, int64_t nb, window_t* w, const double* u,
+                                double s) {
+  int N = w->len / 3;
+  double p[8];
+  u_to_params(u, p);
+  cplx* a = (cplx*)malloc(sizeof(cplx) * 2 * N);
+  int64_t ks;
+  waveform_one(cfg, p, N, a, a + N, NULL, &ks);
+  for (int c = 0; c < 2; c++)
+    for (int j = 0; j < N; j++) {
+      int64_t k = ks + j;
+      if (k < w->k0 || k >= w->k0 + w->len || k < k_min || k >= k_min + nb) continue;
+      w->r[c][k - w->k0] += s * a[c * N + j];
+    }
+  free(a);
+}
+
+/* swap likelihood change against the window residual R (eq. swapsource, in
+ * the cancellation-free form <R|a - r> - 1/2 <a - r|a - r>); a null u means a
+ * zero template (birth / death). */
+static double window_dlogl(const gblo_config* cfg, int64_t k_min, int64_t nb, const window_t* w,
+                           const double* inv_psd /*[2][nb]*/, const double* u_old, const double* u_new) {
+  int N = w->len / 3;
+  window_t d;
+  d.k0 = w->k0;
+  d.len = w->len;
+  d.r[0] = (cplx*)calloc(w->len, sizeof(cplx));
+  d.r[1] = (cplx*)calloc(w->len, sizeof(cplx));
+  if (u_new) window_add_template(cfg, k_min, nb, &d, u_new, 1.0);
+  if (u_old) window_add_template(cfg, k_min, nb, &d, u_old, -1.0);
+  double Rd = 0, dd = 0;
+  for (int c = 0; c < 2; c++)
+    for (int i = 0; i < w->len; i++) {
+      int64_t k = w->k0 + i;
+      if (k < k_min || k >= k_min + nb) continue;
+      double wgt = inv_psd[c * nb + (k - k_min)];
+      Rd += creal(conj(w->r[c][i]) * d.r[c][i]) * wgt;
+      dd += creal(conj(d.r[c][i]) * d.r[c][i]) * wgt;
+    }
+  free(d.r[0]);
+  free(d.r[1]);
+  (void)N;
+  return 4.0 / cfg->T * (Rd - 0.5 * dd);
+}
+
+static void window_load(int64_t k_min, int64_t nb, window_t* w, const cplx* buf /*[2][nb]*/) {
+  for (int c = 0; c < 2; c++)
+    for (int i = 0; i < w->len; i++) {
+      int64_t k = w->k0 + i;
+      w->r[c][i] = (k >= k_min && k < k_min + nb) ? buf[c * nb + (k - k_min)] : 0.0;
+    }
+}
+
+static void window_store_add(int64_t k_min, int64_t nb, const window_t* w, cplx* buf) {
+  for (int c = 0; c < 2; c++)
+    for (int i = 0; i < w->len; i++) {
+      int64_t k = w->k0 + i;
+      if (k >= k_min && k < k_min + nb) buf[c * nb + (k - k_min)] += w->r[c][i];
+    }
+}
+
+static double wrap(double x, double P) {
+  double y = fmod(x, P);
+  return y < 0 ? y + P : y;
+}
+
+/* group stretch draw (see the configuration comment) */
+static int stretch_propose(const gblo_sweep_config* sc, const double* u, const double* group /*[G][8]*/, int G,
+                           double uf, double uz, double* u_new, double* log_ratio) {
+  if (G <= 0) return 0;
+  /* lower bound of u's f0 in the sorted group, then the n_friends window around it */
+  int lo = 0, hi = G;
+  while (lo < hi) {
+    int mid = (lo + hi) / 2;
+    if (group[8 * mid + 1] < u[1])
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  int nf = sc->n_friends < G ? sc->n_friends : G;
+  int start = lo - nf / 2;
+  if (start < 0) start = 0;
+  if (start > G - nf) start = G - nf;
+  int j = start + (int)floor(uf * nf);
+  const double* X = group + 8 * j;
+  double a = sc->stretch_a;
+  double z = ((a - 1.0) * uz + 1.0) * ((a - 1.0) * uz + 1.0) / a;
+  for (int i = 0; i < 8; i++) {
+    double diff = u[i] - X[i];
+    if (PERIOD[i] > 0) {
+      diff = wrap(diff + 0.5 * PERIOD[i], PERIOD[i]) - 0.5 * PERIOD[i];
+      u_new[i] = wrap(X[i] + z * diff, PERIOD[i]);
+    } else {
+      u_new[i] = X[i] + z * diff;
+    }
+  }
+  *log_ratio = 7.0 * log(z);
+  return 1;
+}
+
+/* state layout: u [n_t][n_w][n_b][n_slot][8], exists [n_t][n_w][n_b][n_slot],
+ * betas [n_b][n_t], resid [2 parity][n_w][2][nb] (parity p buffer holds the
+ * data minus the cold-chain sources of the bands with b % 2 == p),
+ * inv_psd [n_w][2][nb], group [n_b][n_w * n_slot][8] + group_count [n_b],
+ * stats [8] = in-model (proposed, accepted), births (proposed, accepted),
+ * deaths (proposed, accepted), swaps (proposed, accepted). */
+#define UIDX(sc, t, w, b, s) ((((int64_t)(t) * (sc)->n_walkers + (w)) * (sc)->n_bands + (b)) * (sc)->n_slots + (s))
+
+/* Alg. gb1 for one (t, w, b): in-model (move 0) or RJ (move 1) band loop. */
+static void band_loop(const gblo_config* cfg, const gblo_sweep_config* sc, int move, int64_t sweep, int t, int w,
+                      int b, double* u, int32_t* exists, const double* betas, double* resid, const double* inv_psd,
+                      const double* group, const int32_t* group_count, int64_t* stats) {
+  int64_t k_min, nb;
+  gblo_band(cfg, &k_min, &nb);
+  int par = b & 1;
+  int S = sc->n_slots;
+  window_t win;
+  win.k0 = win_start(sc, b);
+  win.len = 3 * sc->N;
+  win.r[0] = (cplx*)malloc(sizeof(cplx) * win.len);
+  win.r[1] = (cplx*)malloc(sizeof(cplx) * win.len);
+  window_t dsum = {win.k0, win.len, {(cplx*)calloc(win.len, sizeof(cplx)), (cplx*)calloc(win.len, sizeof(cplx))}};
+  const cplx* opp = (const cplx*)(resid + ((int64_t)(1 - par) * sc->n_walkers + w) * 2 * nb * 2);
+  window_load(k_min, nb, &win, opp);
+  /* residual of the band: subtract the band's current sources */
+  for (int s = 0; s < S; s++)
+    if (exists[UIDX(sc, t, w, b, s)]) window_add_template(cfg, k_min, nb, &win, u + 8 * UIDX(sc, t, w, b, s), -1.0);
+  const double beta = betas[(int64_t)b * sc->n_temps + t];
+  const double* ipsd = inv_psd + (int64_t)w * 2 * nb;
+  const uint64_t unit = ((uint64_t)t * sc->n_walkers + w) * sc->n_bands + b;
+  double un[8];
+  if (move == MOVE_INMODEL) {
+    const double* grp = group + (int64_t)b * sc->n_walkers * S * 8;
+    int G = group_count[b];
+    for (int p = 0; p < sc->n_prop; p++) {
+      double r_pick = rng_uniform(sc->seed, sweep, move, unit, 8 * (uint64_t)p + 0);
+      double r_friend = rng_uniform(sc->seed, sweep, move, unit, 8 * (uint64_t)p + 1);
+      double r_z = rng_uniform(sc->seed, sweep, move, unit, 8 * (uint64_t)p + 2);
+      double r_acc = rng_uniform(sc->seed, sweep, move, unit, 8 * (uint64_t)p + 3);
+      int g = 0;
+      for (int s = 0; s < S; s++) g += exists[UIDX(sc, t, w, b, s)] != 0;
+      if (g == 0) continue;
+      int pick = (int)floor(r_pick * g), s_k = -1;
+      for (int s = 0, c = 0; s < S; s++)
+        if (exists[UIDX(sc, t, w, b, s)]) {
+          if (c == pick) {
+            s_k = s;
+            break;
+          }
+          c++;
+        }
+      double* uk = u + 8 * UIDX(sc, t, w, b, s_k);
+      double lr;
+      stats[0]++;
+      if (!stretch_propose(sc, uk, grp, G, r_friend, r_z, un, &lr)) continue;
+      if (!in_prior(cfg, sc, b, un)) continue;
+      double dl = window_dlogl(cfg, k_min, nb, &win, ipsd, uk, un);
+      if (log(r_acc) < beta * dl + lr) {
+        window_add_template(cfg, k_min, nb, &win, uk, 1.0);
+        window_add_template(cfg, k_min, nb, &win, un, -1.0);
+        if (t == 0) {
+          window_add_template(cfg, k_min, nb, &dsum, uk, 1.0);
+          window_add_template(cfg, k_min, nb, &dsum, un, -1.0);
+        }
+        for (int i = 0; i < 8; i++) uk[i] = un[i];
+        stats[1]++;
+      }
+    }
+  } else {
+    /* flip every slot once, in a random order (Fisher-Yates) */
+    int order[64];
+    for (int s = 0; s < S; s++) order[s] = s;
+    for (int j = S - 1; j >= 1; j--) {
+      int r = (int)floor(rng_uniform(sc->seed, sweep, move, unit, (uint64_t)j) * (j + 1));
+      int tmp = order[j];
+      order[j] = order[r];
+      order[r] = tmp;
+    }
+    double flo, fhi;
+    band_f0_range(cfg, sc, b, &flo, &fhi);
+    for (int i = 0; i < S; i++) {
+      int s = order[i];
+      uint64_t base = 64 + 16 * (uint64_t)i;
+      double r_acc = rng_uniform(sc->seed, sweep, move, unit, base);
+      int64_t ui = UIDX(sc, t, w, b, s);
+      double* us = u + 8 * ui;
+      if (exists[ui]) {
+        /* death: new template zero; prior and proposal densities cancel (q = p) */
+        stats[4]++;
+        double dl = window_dlogl(cfg, k_min, nb, &win, ipsd, us, NULL);
+        if (log(r_acc) < beta * dl) {
+          window_add_template(cfg, k_min, nb, &win, us, 1.0);
+          if (t == 0) window_add_template(cfg, k_min, nb, &dsum, us, 1.0);
+          exists[ui] = 0;
+          stats[5]++;
+        }
+      } else {
+        /* birth from the prior */
+        stats[2]++;
+        for (int k = 0; k < 8; k++) {
+          double r = rng_uniform(sc->seed, sweep, move, unit, base + 1 + k);
+          double lo = sc->prior_lo[k], hi = sc->prior_hi[k];
+          if (k == 1) {
+            lo = flo;
+            hi = fhi;
+          } else if (PERIOD[k] > 0) {
+            lo = 0.0;
+            hi = PERIOD[k];
+          }
+          un[k] = lo + (hi - lo) * r;
+        }
+        double dl = window_dlogl(cfg, k_min, nb, &win, ipsd, NULL, un);
+        if (log(r_acc) < beta * dl) {
+          window_add_template(cfg, k_min, nb, &win, un, -1.0);
+          if (t == 0) window_add_template(cfg, k_min, nb, &dsum, un, -1.0);
+          for (int k = 0; k < 8; k++) us[k] = un[k];
+          exists[ui] = 1;
+          stats[3]++;
+        }
+      }
+    }
+  }
+  /* cold chain: write the change of the band's sources back to its own buffer */
+  if (t == 0) {
+    cplx* own = (cplx*)(resid + ((int64_t)par * sc->n_walkers + w) * 2 * nb * 2);
+    window_store_add(k_min, nb, &dsum, own);
+  }
+  free(win.r[0]);
+  free(win.r[1]);
+  free(dsum.r[0]);
+  free(dsum.r[1]);
+}
+
+/* band log-likelihood of the source set (t, w_src, b) against walker w_res's
+ * residual (the opposite-parity cold-chain buffer over bands b-1..b+1):
+ * -1/2 <r'|r'> over the window, r' = buffer - sum h (Alg. gb2). */
+static double band_loglike(const gblo_config* cfg, const gblo_sweep_config* sc, int t, int w_src, int b, int w_res,
+                           const double* u, const int32_t* exists, const double* resid, const double* inv_psd) {
+  int64_t k_min, nb;
+  gblo_band(cfg, &k_min, &nb);
+  window_t win;
+  win.k0 = win_start(sc, b);
+  win.len = 3 * sc->N;
+  win.r[0] = (cplx*)malloc(sizeof(cplx) * win.len);
+  win.r[1] = (cplx*)malloc(sizeof(cplx) * win.len);
+  int par = b & 1;
+  window_load(k_min, nb, &win, (const cplx*)(resid + ((int64_t)(1 - par) * sc->n_walkers + w_res) * 2 * nb * 2));
+  for (int s = 0; s < sc->n_slots; s++)
+    if (exists[UIDX(sc, t, w_src, b, s)])
+      window_add_template(cfg, k_min, nb, &win, u + 8 * UIDX(sc, t, w_src, b, s), -1.0);
+  const double* ipsd = inv_psd + (int64_t)w_res * 2 * nb;
+  double rr = 0;
+  for (int c = 0; c < 2; c++)
+    for (int i = 0; i < win.len; i++) {
+      int64_t k = win.k0 + i;
+      if (k < k_min || k >= k_min + nb) continue;
+      rr += creal(conj(win.r[c][i]) * win.r[c][i]) * ipsd[c * nb + (k - k_min)];
+    }
+  free(win.r[0]);
+  free(win.r[1]);
+  return -0.5 * 4.0 / cfg->T * rr;
+}
+
+/* walker permutation of temperature t in band b (Fisher-Yates) */
+static void pt_permutation(const gblo_sweep_config* sc, int64_t sweep, int b, int t, int* perm) {
+  for (int i = 0; i < sc->n_walkers; i++) perm[i] = i;
+  uint64_t unit = (uint64_t)b * sc->n_temps + t;
+  for (int j = sc->n_walkers - 1; j >= 1; j--) {
+    int r = (int)floor(rng_uniform(sc->seed, sweep, MOVE_PTPERM, unit, (uint64_t)j) * (j + 1));
+    int tmp = perm[j];
+    perm[j] = perm[r];
+    perm[r] = tmp;
+  }
+}
+
+static void swap_sets(const gblo_sweep_config* sc, int t1, int w1, int t2, int w2, int b, double* u, int32_t* ex) {
+  for (int s = 0; s < sc->n_slots; s++) {
+    int64_t i1 = UIDX(sc, t1, w1, b, s), i2 = UIDX(sc, t2, w2, b, s);
+    for (int k = 0; k < 8; k++) {
+      double tmp = u[8 * i1 + k];
+      u[8 * i1 + k] = u[8 * i2 + k];
+      u[8 * i2 + k] = tmp;
+    }
+    int32_t e = ex[i1];
+    ex[i1] = ex[i2];
+    ex[i2] = e;
+  }
+}
+
+/* eq. temp-final: walker i at inverse temperature bI holds parameters n,
+ * walker j at bII holds m; L_xy = likelihood of walker x's data at parameters
+ * y.  Returns ln alpha = bI (ln L_im - ln L_in) + bII (ln L_jn - ln L_jm). */
+static double pt_log_alpha(double bI, double bII, double lnL_im, double lnL_in, double lnL_jn, double lnL_jm) {
+  return bI * (lnL_im - lnL_in) + bII * (lnL_jn - lnL_jm);
+}
+
+double gblo_pt_log_alpha(double bI, double bII, double lnL_im, double lnL_in, double lnL_jn, double lnL_jm) {
+  return pt_log_alpha(bI, bII, lnL_im, lnL_in, lnL_jn, lnL_jm);
+}
+
+/* Alg. gb2 for band b and ensemble index i: swaps from the hottest pair down,
+ * accepted with the residual-aware ratio (eq. temp-final). */
+static void pt_chain(const gblo_config* cfg, const gblo_sweep_config* sc, int64_t sweep, int b, int i, double* u,
+                     int32_t* exists, const double* betas, double* resid, const double* inv_psd, int64_t* stats) {
+  int64_t k_min, nb;
+  gblo_band(cfg, &k_min, &nb);
+  int nt = sc->n_temps;
+  int* wt = (int*)malloc(sizeof(int) * nt);
+  int* perm = (int*)malloc(sizeof(int) * sc->n_walkers);
+  for (int t = 0; t < nt; t++) {
+    pt_permutation(sc, sweep, b, t, perm);
+    wt[t] = perm[i];
+  }
+  double* Lc = (double*)malloc(sizeof(double) * nt);
+  for (int t = 0; t < nt; t++) Lc[t] = band_loglike(cfg, sc, t, wt[t], b, wt[t], u, exists, resid, inv_psd);
+  const double* bt = betas + (int64_t)b * nt;
+  for (int t = nt - 1; t >= 1; t--) {
+    /* L1: sources of (t-1) against walker w_t's residual; L2: sources of t against w_(t-1)'s */
+    double L1 = band_loglike(cfg, sc, t - 1, wt[t - 1], b, wt[t], u, exists, resid, inv_psd);
+    double L2 = band_loglike(cfg, sc, t, wt[t], b, wt[t - 1], u, exists, resid, inv_psd);
+    double la = pt_log_alpha(bt[t], bt[t - 1], L1, Lc[t], L2, Lc[t - 1]);
+    double r = rng_uniform(sc->seed, sweep, MOVE_PT, (uint64_t)b * sc->n_walkers + i, (uint64_t)t);
+    stats[6]++;
+    if (log(r) < la) {
+      stats[7]++;
+      if (t == 1) {
+        /* new cold-chain sources for walker w_0: update its own-parity buffer */
+        window_t dw;
+        dw.k0 = win_start(sc, b);
+        dw.len = 3 * sc->N;
+        dw.r[0] = (cplx*)calloc(dw.len, sizeof(cplx));
+        dw.r[1] = (cplx*)calloc(dw.len, sizeof(cplx));
+        for (int s = 0; s < sc->n_slots; s++) {
+          if (exists[UIDX(sc, 0, wt[0], b, s)])
+            window_add_template(cfg, k_min, nb, &dw, u + 8 * UIDX(sc, 0, wt[0], b, s), 1.0);
+          if (exists[UIDX(sc, 1, wt[1], b, s)])
+            window_add_template(cfg, k_min, nb, &dw, u + 8 * UIDX(sc, 1, wt[1], b, s), -1.0);
+        }
+        window_store_add(k_min, nb, &dw, (cplx*)(resid + ((int64_t)(b & 1) * sc->n_walkers + wt[0]) * 2 * nb * 2));
+        free(dw.r[0]);
+        free(dw.r[1]);
+      }
+      swap_sets(sc, t, wt[t], t - 1, wt[t - 1], b, u, exists);
+      Lc[t] = L1;
+      Lc[t - 1] = L2;
+    }
+  }
+  free(wt);
+  free(perm);
+  free(Lc);
+}
+
+/* One step of the sweep over all bands of one parity:
+ * move 0 in-model, 1 reversible jump (Alg. gb1), 2 tempering (Alg. gb2). */
+int gblo_sweep_step(const gblo_config* cfg, const gblo_sweep_config* sc, int move, int parity, int64_t sweep,
+                    double* u, int32_t* exists, const double* betas, double* resid, const double* inv_psd,
+                    const double* group, const int32_t* group_count, int64_t* stats) {
+  if (sc->n_slots > 64 || sc->n_slots < 1) return -1;
+  for (int b = parity; b < sc->n_bands; b += 2) {
+    if (move == MOVE_PT) {
+      for (int i = 0; i < sc->n_walkers; i++)
+        pt_chain(cfg, sc, sweep, b, i, u, exists, betas, resid, inv_psd, stats);
+    } else {
+      for (int t = 0; t < sc->n_temps; t++)
+        for (int w = 0; w < sc->n_walkers; w++)
+          band_loop(cfg, sc, move, sweep, t, w, b, u, exists, betas, resid, inv_psd, group, group_count, stats);
+    }
+  }
+  return 0;
+}
+
+/* Stationary group per band: the cold-chain (t = 0) sources of every walker,
+ * sorted by f0 (ties by walker, then slot). */
+int gblo_sweep_group(const gblo_sweep_config* sc, const double* u, const int32_t* exists, double* group,
+                     int32_t* group_count) {
+  int S = sc->n_slots;
+  for (int b = 0; b < sc->n_bands; b++) {
+    double* g = group + (int64_t)b * sc->n_walkers * S * 8;
+    int n = 0;
+    for (int w = 0; w < sc->n_walkers; w++)
+      for (int s = 0; s < S; s++)
+        if (exists[UIDX(sc, 0, w, b, s)]) {
+          for (int k = 0; k < 8; k++) g[8 * n + k] = u[8 * UIDX(sc, 0, w, b, s) + k];
+          n++;
+        }
+    /* insertion sort by f0 (stable) */
+    for (int i = 1; i < n; i++) {
+      double tmp[8];
+      for (int k = 0; k < 8; k++) tmp[k] = g[8 * i + k];
+      int j = i - 1;
+      while (j >= 0 && g[8 * j + 1] > tmp[1]) {
+        for (int k = 0; k < 8; k++) g[8 * (j + 1) + k] = g[8 * j + k];
+        j--;
+      }
+      for (int k = 0; k < 8; k++) g[8 * (j + 1) + k] = tmp[k];
+    }
+    group_count[b] = n;
+  }
+  return 0;
+}

@@ -11,6 +11,7 @@
 
 #include "../../include/gbl.h"
 #include "gbl_kernels.hpp"
+#include "gbl_sampler.hpp"
 
 using gbl::cd;
 
@@ -429,4 +430,164 @@ extern "C" int gb_make_noise(gbl_ctx* ctx, const double* S, const double* normal
   hipLaunchKernelGGL(gbl::k_make_noise, dim3((unsigned)blocks), dim3(256), 0, ctx->stream, total,
                      ctx->cfg.T / 4.0, S, (const cd*)normals, (cd*)out);
   return check_launch(ctx, "gb_make_noise");
+}
+
+// ---------------------------------------------------------------------------
+// sampler sweep (Sec. 4; appendix algorithms gb1 and gb2)
+// ---------------------------------------------------------------------------
+static int sweep_check(gbl_ctx* ctx, const gbl_sweep_config* c, const gbl_sweep_state* st) {
+  if (!c || !st) return fail(ctx, GBL_EINVAL, "sweep: null config or state%s");
+  if (c->N != 128 && c->N != 256 && c->N != 512) return fail(ctx, GBL_EUNSUPPORTED, "sweep: N must be 128, 256 or 512%s");
+  if (c->n_temps < 1 || c->n_temps > 256 || c->n_walkers < 1 || c->n_walkers > 256 || c->n_bands < 1 ||
+      c->n_slots < 1 || c->n_slots > gbl::kMaxSlots || c->n_prop < 0 || c->n_friends < 1 || !(c->stretch_a > 1.0))
+    return fail(ctx, GBL_EINVAL, "sweep: configuration out of range%s");
+  if (!st->u || !st->exists || !st->betas || !st->resid || !st->inv_psd || !st->group || !st->group_count ||
+      !st->stats || !st->sweep_counter)
+    return fail(ctx, GBL_EINVAL, "sweep: null state pointer%s");
+  if (ctx->cfg.precision != GBL_FP64) return fail(ctx, GBL_EUNSUPPORTED, "sweep: FP64 contexts only%s");
+  return GBL_OK;
+}
+
+static gbl::SweepArgs sweep_args(const gbl_sweep_config* c, const gbl_sweep_state* st) {
+  gbl::SweepArgs a;
+  a.n_t = c->n_temps;
+  a.n_w = c->n_walkers;
+  a.n_b = c->n_bands;
+  a.n_slot = c->n_slots;
+  a.n_prop = c->n_prop;
+  a.n_friends = c->n_friends;
+  a.k_band0 = c->k_band0;
+  a.stretch_a = c->stretch_a;
+  a.seed = c->seed;
+  for (int i = 0; i < 8; i++) {
+    a.lo[i] = c->prior_lo[i];
+    a.hi[i] = c->prior_hi[i];
+  }
+  a.u = st->u;
+  a.exists = st->exists;
+  a.betas = st->betas;
+  a.resid = (cd*)st->resid;
+  a.inv_psd = st->inv_psd;
+  a.group = st->group;
+  a.group_count = st->group_count;
+  a.stats = (unsigned long long*)st->stats;
+  a.sweep_ctr = st->sweep_counter;
+  return a;
+}
+
+template <int N>
+static void launch_sweep_step(gbl_ctx* ctx, const gbl::SweepArgs& a, int move, int parity) {
+  const int nbp = (a.n_b - parity + 1) / 2;
+  if (nbp <= 0) return;
+  const gbl::WaveTables<double>& tb = tables_for<N, double>(ctx);
+  if (move == GBL_MOVE_PT)
+    hipLaunchKernelGGL((gbl::k_sweep_pt<N>), dim3((unsigned)(nbp * a.n_w)), dim3(gbl::block_threads<N>()), 0,
+                       ctx->stream, ctx->geo, tb, a, parity);
+  else
+    hipLaunchKernelGGL((gbl::k_sweep_band<N>), dim3((unsigned)(nbp * a.n_w * a.n_t)), dim3(gbl::block_threads<N>()),
+                       0, ctx->stream, ctx->geo, tb, a, move, parity);
+}
+
+static void sweep_step(gbl_ctx* ctx, const gbl_sweep_config* c, const gbl::SweepArgs& a, int move, int parity) {
+  switch (c->N) {
+    case 128: launch_sweep_step<128>(ctx, a, move, parity); break;
+    case 256: launch_sweep_step<256>(ctx, a, move, parity); break;
+    case 512: launch_sweep_step<512>(ctx, a, move, parity); break;
+    default: break;
+  }
+}
+
+extern "C" int gb_sweep_step(gbl_ctx* ctx, const gbl_sweep_config* cfg, const gbl_sweep_state* st, int32_t move,
+                             int32_t parity) {
+  if (!ctx) return GBL_EINVAL;
+  int rc = sweep_check(ctx, cfg, st);
+  if (rc) return rc;
+  if (move < GBL_MOVE_INMODEL || move > GBL_MOVE_PT || (parity != 0 && parity != 1))
+    return fail(ctx, GBL_EINVAL, "gb_sweep_step: bad move or parity%s");
+  sweep_step(ctx, cfg, sweep_args(cfg, st), move, parity);
+  return check_launch(ctx, "gb_sweep_step");
+}
+
+extern "C" int gb_sweep_group(gbl_ctx* ctx, const gbl_sweep_config* cfg, const gbl_sweep_state* st) {
+  if (!ctx) return GBL_EINVAL;
+  int rc = sweep_check(ctx, cfg, st);
+  if (rc) return rc;
+  hipLaunchKernelGGL(gbl::k_sweep_group, dim3((unsigned)cfg->n_bands), dim3(256), 0, ctx->stream,
+                     sweep_args(cfg, st), 0);
+  return check_launch(ctx, "gb_sweep_group");
+}
+
+extern "C" int gb_sweep_advance(gbl_ctx* ctx, const gbl_sweep_state* st) {
+  if (!ctx) return GBL_EINVAL;
+  if (!st || !st->sweep_counter) return fail(ctx, GBL_EINVAL, "gb_sweep_advance: null state%s");
+  hipLaunchKernelGGL(gbl::k_sweep_advance, dim3(1), dim3(64), 0, ctx->stream, st->sweep_counter);
+  return check_launch(ctx, "gb_sweep_advance");
+}
+
+extern "C" int gb_sweep_run(gbl_ctx* ctx, const gbl_sweep_config* cfg, const gbl_sweep_state* st,
+                            int32_t n_sweeps) {
+  if (!ctx) return GBL_EINVAL;
+  int rc = sweep_check(ctx, cfg, st);
+  if (rc) return rc;
+  if (n_sweeps < 0) return fail(ctx, GBL_EINVAL, "gb_sweep_run: n_sweeps < 0%s");
+  const gbl::SweepArgs a = sweep_args(cfg, st);
+  for (int i = 0; i < n_sweeps; i++) {
+    if (cfg->group_every > 0)
+      hipLaunchKernelGGL(gbl::k_sweep_group, dim3((unsigned)cfg->n_bands), dim3(256), 0, ctx->stream, a,
+                         cfg->group_every);
+    for (int move = GBL_MOVE_INMODEL; move <= GBL_MOVE_PT; move++)
+      for (int parity = 1; parity >= 0; parity--) sweep_step(ctx, cfg, a, move, parity);
+    hipLaunchKernelGGL(gbl::k_sweep_advance, dim3(1), dim3(64), 0, ctx->stream, st->sweep_counter);
+  }
+  return check_launch(ctx, "gb_sweep_run");
+}
+
+struct gbl_graph {
+  hipGraph_t graph;
+  hipGraphExec_t exec;
+  hipStream_t stream;
+};
+
+extern "C" int gb_sweep_graph_create(gbl_ctx* ctx, const gbl_sweep_config* cfg, const gbl_sweep_state* st,
+                                     int32_t n_sweeps, gbl_graph** out) {
+  if (!ctx || !out) return GBL_EINVAL;
+  *out = nullptr;
+  int rc = sweep_check(ctx, cfg, st);
+  if (rc) return rc;
+  if (n_sweeps < 1) return fail(ctx, GBL_EINVAL, "gb_sweep_graph_create: n_sweeps < 1%s");
+  if (!ctx->stream) return fail(ctx, GBL_EINVAL, "gb_sweep_graph_create: capture needs a non-default stream%s");
+  gbl_graph* gr = new gbl_graph();
+  gr->stream = ctx->stream;
+  if (hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    delete gr;
+    return fail(ctx, GBL_EHIP, "gb_sweep_graph_create: begin capture failed%s");
+  }
+  int rr = gb_sweep_run(ctx, cfg, st, n_sweeps);
+  hipError_t e = hipStreamEndCapture(ctx->stream, &gr->graph);
+  if (rr != GBL_OK || e != hipSuccess) {
+    if (e == hipSuccess) (void)hipGraphDestroy(gr->graph);
+    delete gr;
+    return fail(ctx, GBL_EHIP, "gb_sweep_graph_create: capture failed%s");
+  }
+  if (hipGraphInstantiate(&gr->exec, gr->graph, nullptr, nullptr, 0) != hipSuccess) {
+    (void)hipGraphDestroy(gr->graph);
+    delete gr;
+    return fail(ctx, GBL_EHIP, "gb_sweep_graph_create: instantiate failed%s");
+  }
+  *out = gr;
+  return GBL_OK;
+}
+
+extern "C" int gb_graph_launch(gbl_graph* gr) {
+  if (!gr) return GBL_EINVAL;
+  return hipGraphLaunch(gr->exec, gr->stream) == hipSuccess ? GBL_OK : GBL_EHIP;
+}
+
+extern "C" int gb_graph_destroy(gbl_graph* gr) {
+  if (!gr) return GBL_OK;
+  (void)hipStreamSynchronize(gr->stream);
+  (void)hipGraphExecDestroy(gr->exec);
+  (void)hipGraphDestroy(gr->graph);
+  delete gr;
+  return GBL_OK;
 }

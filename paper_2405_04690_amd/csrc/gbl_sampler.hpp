@@ -1,0 +1,625 @@
+// gbl_sampler.hpp -- the GB sampler sweep on the GPU (Sec. 4; appendix
+// algorithms gb1 "Galaxy sampling" and gb2 "Galaxy tempering").
+//
+// State (caller-owned device arrays):
+//   u       [n_t][n_w][n_b][n_slot][8] sampling coordinates (log10 A, f0, fdot,
+//           phi0, cos iota, psi, lambda, sin beta)
+//   exists  [n_t][n_w][n_b][n_slot]    slot occupancy (reversible jump)
+//   betas   [n_b][n_t]                  inverse temperatures per sub-band
+//   resid   [2][n_w][2][n_bins]         cold-chain buffers: parity p holds the
+//           data minus the cold-chain sources of the sub-bands with b % 2 == p
+//   inv_psd [n_w][2][n_bins]            1/S per walker
+//   group   [n_b][n_w * n_slot][8], group_count [n_b]: stationary groups
+//   stats   [8] proposal / acceptance counters; sweep_ctr: sweep index
+// Sub-band b covers bins [k_band0 + b N, k_band0 + (b+1) N); its analysis
+// window is sub-bands b-1..b+1, read from the opposite-parity buffer, so the
+// neighbours' sources stay fixed while band b's sources move.
+#pragma once
+
+#include "gbl_kernels.hpp"
+
+namespace gbl {
+
+constexpr int kMaxSlots = 64;
+
+// ---------------------------------------------------------------------------
+// Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11) from its definition.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void philox4x64(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3, uint64_t k0,
+                                           uint64_t k1, uint64_t* o) {
+  const uint64_t M0 = 0xD2E7470EE14C6C93ULL, M1 = 0xCA5A826395121157ULL;
+  const uint64_t W0 = 0x9E3779B97F4A7C15ULL, W1 = 0xBB67AE8584CAA73BULL;
+#pragma unroll
+  for (int r = 0; r < 10; r++) {
+    uint64_t hi0 = __umul64hi(M0, c0), lo0 = M0 * c0;
+    uint64_t hi1 = __umul64hi(M1, c2), lo1 = M1 * c2;
+    uint64_t y0 = hi1 ^ c1 ^ k0, y2 = hi0 ^ c3 ^ k1;
+    c0 = y0;
+    c1 = lo1;
+    c2 = y2;
+    c3 = lo0;
+    k0 += W0;
+    k1 += W1;
+  }
+  o[0] = c0;
+  o[1] = c1;
+  o[2] = c2;
+  o[3] = c3;
+}
+
+// uniform in (0, 1): counter (sweep, move << 40 | unit, idx / 4, 0), word idx % 4
+__device__ __forceinline__ double rng_uniform(uint64_t seed, int64_t sweep, int move, uint64_t unit, uint64_t idx) {
+  uint64_t o[4];
+  philox4x64((uint64_t)sweep, ((uint64_t)move << 40) | unit, idx >> 2, 0, seed, 0, o);
+  return ((double)(o[idx & 3] >> 11) + 0.5) * (1.0 / 9007199254740992.0);
+}
+
+enum { kMoveInModel = 0, kMoveRJ = 1, kMovePT = 2, kMovePTPerm = 3 };
+
+struct SweepArgs {
+  int n_t, n_w, n_b, n_slot, n_prop, n_friends;
+  int64_t k_band0;
+  double stretch_a;
+  uint64_t seed;
+  double lo[8], hi[8];
+  double* u;
+  int32_t* exists;
+  const double* betas;
+  cd* resid;
+  const double* inv_psd;
+  double* group;
+  int32_t* group_count;
+  unsigned long long* stats;
+  const int64_t* sweep_ctr;
+};
+
+__device__ __forceinline__ int64_t uidx(const SweepArgs& a, int t, int w, int b, int s) {
+  return (((int64_t)t * a.n_w + w) * a.n_b + b) * a.n_slot + s;
+}
+
+__device__ __forceinline__ double period_of(int i) {
+  return i == 3 ? kTwoPi : i == 5 ? kPi : i == 6 ? kTwoPi : 0.0;
+}
+
+__device__ __forceinline__ double wrap_p(double x, double P) {
+  double y = fmod(x, P);
+  return y < 0 ? y + P : y;
+}
+
+template <int N>
+__device__ __forceinline__ void band_f0_range(const Geo& g, const SweepArgs& a, int b, double& lo, double& hi) {
+  lo = ((double)a.k_band0 + ((double)b - 0.5) * N) / g.T;
+  hi = ((double)a.k_band0 + ((double)b + 1.5) * N) / g.T;
+}
+
+template <int N>
+__device__ __forceinline__ bool in_prior(const Geo& g, const SweepArgs& a, int b, const double* u) {
+  double flo, fhi;
+  band_f0_range<N>(g, a, b, flo, fhi);
+  if (!(u[1] >= flo && u[1] < fhi)) return false;
+#pragma unroll
+  for (int i = 0; i < 8; i++) {
+    if (i == 1 || period_of(i) > 0) continue;
+    if (!(u[i] >= a.lo[i] && u[i] <= a.hi[i])) return false;
+  }
+  return true;
+}
+
+// LDS of one band loop
+template <int N>
+struct BandSmem {
+  cd win[2][3 * N];         // residual window r' (channels A, E)
+  double wts[2][3 * N];     // 1/S over the window (0 outside the analysis band)
+  cd buf[4 * series_pitch<N>()];
+  cd rwin[2 * N];           // spectrum of the template being removed
+  double red[2 * (block_threads<N>() / kWave)];
+  double u_old[8], u_new[8], prm[8];
+  Src src;
+  double su[kMaxSlots][8];  // the band's slot coordinates during the loop
+  int32_t ex[kMaxSlots];
+  int32_t order[kMaxSlots];
+  double bcast;
+};
+
+// Build the template of sampling coordinates u (shared) into the FFT workspace;
+// sm.src holds its decode afterwards.  Block-uniform; contains barriers.
+template <int N>
+__device__ __forceinline__ void band_template(const Geo& g, const WaveTables<double>& tb, const double* u,
+                                              BandSmem<N>& sm) {
+  const int tid = threadIdx.x;
+  if (tid == 0) {
+    sm.prm[0] = exp10(u[0]);
+    sm.prm[1] = u[1];
+    sm.prm[2] = u[2];
+    sm.prm[3] = u[3];
+    sm.prm[4] = acos(u[4]);
+    sm.prm[5] = u[5];
+    sm.prm[6] = u[6];
+    sm.prm[7] = asin(u[7]);
+  }
+  __syncthreads();
+  if (tid < kWave) {
+    Src d = decode_source(sm.prm, g);
+    if (tid == 0) sm.src = d;
+  }
+  __syncthreads();
+  template_transform<N, 4, double>(sm.src, g, tb, sm.buf, tid);
+}
+
+// sum over the block, broadcast to every thread
+template <int NT>
+__device__ __forceinline__ double block_allsum(double v, double* red, double* bc) {
+  double t = block_sum<NT>(v, red);
+  if (threadIdx.x == 0) *bc = t;
+  __syncthreads();
+  double r = *bc;
+  __syncthreads();
+  return r;
+}
+
+// window += s * (template in the FFT workspace), bins inside the window;
+// with `global_buf`, the same change also goes (atomically) to the cold-chain
+// buffer of the band's own parity.
+template <int N>
+__device__ __forceinline__ void band_add_template(const Geo& g, const WaveTables<double>& tb, BandSmem<N>& sm,
+                                                  int64_t k0w, double s, cd* global_buf) {
+  constexpr int NT = block_threads<N>();
+  const int64_t ks = sm.src.q - N / 2;
+  for (int j = threadIdx.x; j < N; j += NT) {
+    int64_t i = ks + j - k0w;
+    if (i < 0 || i >= 3 * N) continue;
+    cd v[2];
+    bin_spectrum<N, 2, double>(sm.src, g, tb, sm.buf, j, v);
+#pragma unroll
+    for (int c = 0; c < 2; c++) {
+      sm.win[c][i] = sm.win[c][i] + cd{s * v[c].re, s * v[c].im};
+      if (global_buf) {
+        int64_t k = k0w + i - g.k_min;
+        if (k >= 0 && k < g.n_bins) {
+          double* dst = reinterpret_cast<double*>(global_buf + c * g.n_bins + k);
+          atomicAdd(dst, s * v[c].re);
+          atomicAdd(dst + 1, s * v[c].im);
+        }
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// same for the spectrum held in sm.rwin (start bin kr)
+template <int N>
+__device__ __forceinline__ void band_add_rwin(const Geo& g, BandSmem<N>& sm, int64_t k0w, int64_t kr, double s,
+                                              cd* global_buf) {
+  constexpr int NT = block_threads<N>();
+  for (int j = threadIdx.x; j < N; j += NT) {
+    int64_t i = kr + j - k0w;
+    if (i < 0 || i >= 3 * N) continue;
+#pragma unroll
+    for (int c = 0; c < 2; c++) {
+      cd v = sm.rwin[c * N + j];
+      sm.win[c][i] = sm.win[c][i] + cd{s * v.re, s * v.im};
+      if (global_buf) {
+        int64_t k = k0w + i - g.k_min;
+        if (k >= 0 && k < g.n_bins) {
+          double* dst = reinterpret_cast<double*>(global_buf + c * g.n_bins + k);
+          atomicAdd(dst, s * v.re);
+          atomicAdd(dst + 1, s * v.im);
+        }
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// dlnL = 4 df [<R|d> - 1/2 <d|d>], d = a - r, R = window; a = template in the
+// FFT workspace (if has_a), r = sm.rwin (if has_r).  Block-uniform result.
+template <int N>
+__device__ __forceinline__ double band_dlogl(const Geo& g, const WaveTables<double>& tb, BandSmem<N>& sm,
+                                             int64_t k0w, bool has_a, int64_t ka, bool has_r, int64_t kr) {
+  constexpr int NT = block_threads<N>();
+  double rd = 0.0, dd = 0.0;
+  auto acc = [&](int64_t i, cd d0, cd d1) {
+    if (i < 0 || i >= 3 * N) return;
+    double w0 = sm.wts[0][i], w1 = sm.wts[1][i];
+    cd R0 = sm.win[0][i], R1 = sm.win[1][i];
+    rd += (R0.re * d0.re + R0.im * d0.im) * w0 + (R1.re * d1.re + R1.im * d1.im) * w1;
+    dd += (d0.re * d0.re + d0.im * d0.im) * w0 + (d1.re * d1.re + d1.im * d1.im) * w1;
+  };
+  if (has_a) {
+    for (int j = threadIdx.x; j < N; j += NT) {
+      cd v[2];
+      bin_spectrum<N, 2, double>(sm.src, g, tb, sm.buf, j, v);
+      int64_t k = ka + j;
+      int64_t jr = k - kr;
+      if (has_r && jr >= 0 && jr < N) {
+        v[0] = v[0] - sm.rwin[jr];
+        v[1] = v[1] - sm.rwin[N + jr];
+      }
+      acc(k - k0w, v[0], v[1]);
+    }
+  }
+  if (has_r) {
+    for (int j = threadIdx.x; j < N; j += NT) {
+      int64_t k = kr + j;
+      if (has_a && k >= ka && k < ka + N) continue;
+      cd r0 = sm.rwin[j], r1 = sm.rwin[N + j];
+      acc(k - k0w, cd{-r0.re, -r0.im}, cd{-r1.re, -r1.im});
+    }
+  }
+  rd = block_allsum<NT>(rd, sm.red, &sm.bcast);
+  dd = block_allsum<NT>(dd, sm.red, &sm.bcast);
+  return g.df4 * rd - 0.5 * g.df4 * dd;
+}
+
+// spectrum of the template in the workspace into sm.rwin
+template <int N>
+__device__ __forceinline__ void band_store_rwin(const Geo& g, const WaveTables<double>& tb, BandSmem<N>& sm) {
+  constexpr int NT = block_threads<N>();
+  for (int j = threadIdx.x; j < N; j += NT) {
+    cd v[2];
+    bin_spectrum<N, 2, double>(sm.src, g, tb, sm.buf, j, v);
+    sm.rwin[j] = v[0];
+    sm.rwin[N + j] = v[1];
+  }
+  __syncthreads();
+}
+
+// load walker w's window from the opposite-parity buffer, and its weights
+template <int N>
+__device__ __forceinline__ void band_load_window(const Geo& g, const SweepArgs& a, int w, int b, int64_t k0w,
+                                                 BandSmem<N>& sm) {
+  constexpr int NT = block_threads<N>();
+  const int par = b & 1;
+  const cd* opp = a.resid + ((int64_t)(1 - par) * a.n_w + w) * 2 * g.n_bins;
+  const double* ip = a.inv_psd + (int64_t)w * 2 * g.n_bins;
+  for (int i = threadIdx.x; i < 3 * N; i += NT) {
+    int64_t k = k0w + i - g.k_min;
+    bool inb = k >= 0 && k < g.n_bins;
+#pragma unroll
+    for (int c = 0; c < 2; c++) {
+      sm.win[c][i] = inb ? opp[c * g.n_bins + k] : cd{0.0, 0.0};
+      sm.wts[c][i] = inb ? ip[c * g.n_bins + k] : 0.0;
+    }
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// Alg. gb1 for every (t, w, b) of one parity: in-model group-stretch moves
+// (move 0) or the reversible-jump pass that flips every slot (move 1).
+// ---------------------------------------------------------------------------
+template <int N>
+__global__ __launch_bounds__(block_threads<N>()) void k_sweep_band(Geo g, WaveTables<double> tb, SweepArgs a,
+                                                                   int move, int parity) {
+  __shared__ BandSmem<N> sm;
+  const int nbp = (a.n_b - parity + 1) / 2;  // bands of this parity
+  const int bi = blockIdx.x % nbp;
+  const int tw = blockIdx.x / nbp;
+  const int w = tw % a.n_w;
+  const int t = tw / a.n_w;
+  const int b = parity + 2 * bi;
+  const int tid = threadIdx.x;
+  const int S = a.n_slot;
+  const int64_t sweep = *a.sweep_ctr;
+  const int64_t k0w = a.k_band0 + (int64_t)(b - 1) * N;
+  const double beta = a.betas[(int64_t)b * a.n_t + t];
+  const uint64_t unit = ((uint64_t)t * a.n_w + w) * a.n_b + b;
+  cd* own = (t == 0) ? a.resid + ((int64_t)(b & 1) * a.n_w + w) * 2 * g.n_bins : nullptr;
+
+  band_load_window<N>(g, a, w, b, k0w, sm);
+  for (int s = tid; s < S; s += block_threads<N>()) {
+    sm.ex[s] = a.exists[uidx(a, t, w, b, s)];
+    for (int k = 0; k < 8; k++) sm.su[s][k] = a.u[8 * uidx(a, t, w, b, s) + k];
+  }
+  __syncthreads();
+  // the band's residual: remove its current sources
+  for (int s = 0; s < S; s++) {
+    if (!sm.ex[s]) continue;
+    band_template<N>(g, tb, sm.su[s], sm);
+    band_add_template<N>(g, tb, sm, k0w, -1.0, nullptr);
+  }
+
+  unsigned long long n_prop = 0, n_acc = 0, n_bprop = 0, n_bacc = 0, n_dprop = 0, n_dacc = 0;
+  if (move == kMoveInModel) {
+    const double* grp = a.group + (int64_t)b * a.n_w * S * 8;
+    const int G = a.group_count[b];
+    for (int p = 0; p < a.n_prop; p++) {
+      const double r_pick = rng_uniform(a.seed, sweep, move, unit, 8 * (uint64_t)p + 0);
+      const double r_friend = rng_uniform(a.seed, sweep, move, unit, 8 * (uint64_t)p + 1);
+      const double r_z = rng_uniform(a.seed, sweep, move, unit, 8 * (uint64_t)p + 2);
+      const double r_acc = rng_uniform(a.seed, sweep, move, unit, 8 * (uint64_t)p + 3);
+      int gcount = 0;
+      for (int s = 0; s < S; s++) gcount += sm.ex[s] != 0;
+      if (gcount == 0) continue;
+      const int pick = (int)floor(r_pick * gcount);
+      int sk = -1;
+      for (int s = 0, c = 0; s < S; s++)
+        if (sm.ex[s]) {
+          if (c == pick) {
+            sk = s;
+            break;
+          }
+          c++;
+        }
+      const double* uk = sm.su[sk];
+      n_prop++;
+      if (G <= 0) continue;
+      // friend: the n_friends sorted group entries around the current f0
+      int lo = 0, hi = G;
+      while (lo < hi) {
+        int mid = (lo + hi) / 2;
+        if (grp[8 * mid + 1] < uk[1])
+          lo = mid + 1;
+        else
+          hi = mid;
+      }
+      const int nf = a.n_friends < G ? a.n_friends : G;
+      int start = lo - nf / 2;
+      if (start < 0) start = 0;
+      if (start > G - nf) start = G - nf;
+      const double* X = grp + 8 * (start + (int)floor(r_friend * nf));
+      const double am = a.stretch_a;
+      const double z = ((am - 1.0) * r_z + 1.0) * ((am - 1.0) * r_z + 1.0) / am;
+      double un[8];
+#pragma unroll
+      for (int i = 0; i < 8; i++) {
+        double diff = uk[i] - X[i];
+        double P = period_of(i);
+        if (P > 0) {
+          diff = wrap_p(diff + 0.5 * P, P) - 0.5 * P;
+          un[i] = wrap_p(X[i] + z * diff, P);
+        } else {
+          un[i] = X[i] + z * diff;
+        }
+      }
+      if (!in_prior<N>(g, a, b, un)) continue;
+      const double lr = 7.0 * log(z);
+      if (tid < 8) {
+        sm.u_old[tid] = uk[tid];
+        sm.u_new[tid] = un[tid];
+      }
+      __syncthreads();
+      band_template<N>(g, tb, sm.u_old, sm);
+      band_store_rwin<N>(g, tb, sm);
+      const int64_t kr = sm.src.q - N / 2;
+      band_template<N>(g, tb, sm.u_new, sm);
+      const int64_t ka = sm.src.q - N / 2;
+      const double dl = band_dlogl<N>(g, tb, sm, k0w, true, ka, true, kr);
+      if (log(r_acc) < beta * dl + lr) {
+        band_add_template<N>(g, tb, sm, k0w, -1.0, own);
+        band_add_rwin<N>(g, sm, k0w, kr, 1.0, own);
+        if (tid < 8) sm.su[sk][tid] = sm.u_new[tid];
+        n_acc++;
+      }
+      __syncthreads();
+    }
+  } else {
+    // flip every slot once in a random order (Fisher-Yates)
+    if (tid == 0) {
+      for (int s = 0; s < S; s++) sm.order[s] = s;
+      for (int j = S - 1; j >= 1; j--) {
+        int r = (int)floor(rng_uniform(a.seed, sweep, move, unit, (uint64_t)j) * (j + 1));
+        int tmp = sm.order[j];
+        sm.order[j] = sm.order[r];
+        sm.order[r] = tmp;
+      }
+    }
+    __syncthreads();
+    double flo, fhi;
+    band_f0_range<N>(g, a, b, flo, fhi);
+    for (int i = 0; i < S; i++) {
+      const int s = sm.order[i];
+      const uint64_t base = 64 + 16 * (uint64_t)i;
+      const double r_acc = rng_uniform(a.seed, sweep, move, unit, base);
+      double* us = sm.su[s];
+      if (sm.ex[s]) {
+        // death: the new template is zero; q = p, so only the likelihood enters
+        n_dprop++;
+        if (tid < 8) sm.u_old[tid] = us[tid];
+        __syncthreads();
+        band_template<N>(g, tb, sm.u_old, sm);
+        band_store_rwin<N>(g, tb, sm);
+        const int64_t kr = sm.src.q - N / 2;
+        const double dl = band_dlogl<N>(g, tb, sm, k0w, false, 0, true, kr);
+        if (log(r_acc) < beta * dl) {
+          band_add_rwin<N>(g, sm, k0w, kr, 1.0, own);
+          if (tid == 0) sm.ex[s] = 0;
+          n_dacc++;
+        }
+      } else {
+        // birth drawn from the prior
+        n_bprop++;
+        if (tid < 8) {
+          const int k = tid;
+          double r = rng_uniform(a.seed, sweep, move, unit, base + 1 + k);
+          double lo = a.lo[k], hi = a.hi[k];
+          if (k == 1) {
+            lo = flo;
+            hi = fhi;
+          } else if (period_of(k) > 0) {
+            lo = 0.0;
+            hi = period_of(k);
+          }
+          sm.u_new[k] = lo + (hi - lo) * r;
+        }
+        __syncthreads();
+        band_template<N>(g, tb, sm.u_new, sm);
+        const int64_t ka = sm.src.q - N / 2;
+        const double dl = band_dlogl<N>(g, tb, sm, k0w, true, ka, false, 0);
+        if (log(r_acc) < beta * dl) {
+          band_add_template<N>(g, tb, sm, k0w, -1.0, own);
+          if (tid < 8) us[tid] = sm.u_new[tid];
+          if (tid == 0) sm.ex[s] = 1;
+          n_bacc++;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int s = tid; s < S; s += block_threads<N>()) {
+    a.exists[uidx(a, t, w, b, s)] = sm.ex[s];
+    for (int k = 0; k < 8; k++) a.u[8 * uidx(a, t, w, b, s) + k] = sm.su[s][k];
+  }
+  if (tid == 0) {
+    if (n_prop) atomicAdd(&a.stats[0], n_prop);
+    if (n_acc) atomicAdd(&a.stats[1], n_acc);
+    if (n_bprop) atomicAdd(&a.stats[2], n_bprop);
+    if (n_bacc) atomicAdd(&a.stats[3], n_bacc);
+    if (n_dprop) atomicAdd(&a.stats[4], n_dprop);
+    if (n_dacc) atomicAdd(&a.stats[5], n_dacc);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Alg. gb2: residual-aware tempering for every band of one parity and every
+// ensemble index i; the walker at temperature t is perm_t[i] with perm_t a
+// random permutation per (band, temperature).  Swaps run from the hottest
+// pair down and are accepted with eq. temp-final.
+// ---------------------------------------------------------------------------
+template <int N>
+__device__ __forceinline__ double band_set_loglike(const Geo& g, const WaveTables<double>& tb, const SweepArgs& a,
+                                                   int t, int w_src, int b, int w_res, int64_t k0w,
+                                                   BandSmem<N>& sm) {
+  constexpr int NT = block_threads<N>();
+  band_load_window<N>(g, a, w_res, b, k0w, sm);
+  for (int s = 0; s < a.n_slot; s++) {
+    if (!a.exists[uidx(a, t, w_src, b, s)]) continue;
+    band_template<N>(g, tb, a.u + 8 * uidx(a, t, w_src, b, s), sm);
+    band_add_template<N>(g, tb, sm, k0w, -1.0, nullptr);
+  }
+  double rr = 0.0;
+  for (int i = threadIdx.x; i < 3 * N; i += NT) {
+    cd r0 = sm.win[0][i], r1 = sm.win[1][i];
+    rr += (r0.re * r0.re + r0.im * r0.im) * sm.wts[0][i] + (r1.re * r1.re + r1.im * r1.im) * sm.wts[1][i];
+  }
+  rr = block_allsum<NT>(rr, sm.red, &sm.bcast);
+  return -0.5 * g.df4 * rr;
+}
+
+template <int N>
+__global__ __launch_bounds__(block_threads<N>()) void k_sweep_pt(Geo g, WaveTables<double> tb, SweepArgs a,
+                                                                 int parity) {
+  __shared__ BandSmem<N> sm;
+  __shared__ int wt[256];
+  __shared__ double Lc[256];
+  __shared__ int perm[256];
+  const int nbp = (a.n_b - parity + 1) / 2;
+  const int bi = blockIdx.x % nbp;
+  const int i = blockIdx.x / nbp;
+  const int b = parity + 2 * bi;
+  const int tid = threadIdx.x;
+  const int nt = a.n_t;
+  const int64_t sweep = *a.sweep_ctr;
+  const int64_t k0w = a.k_band0 + (int64_t)(b - 1) * N;
+  if (tid == 0) {
+    for (int t = 0; t < nt; t++) {
+      for (int j = 0; j < a.n_w; j++) perm[j] = j;
+      const uint64_t unit = (uint64_t)b * nt + t;
+      for (int j = a.n_w - 1; j >= 1; j--) {
+        int r = (int)floor(rng_uniform(a.seed, sweep, kMovePTPerm, unit, (uint64_t)j) * (j + 1));
+        int tmp = perm[j];
+        perm[j] = perm[r];
+        perm[r] = tmp;
+      }
+      wt[t] = perm[i];
+    }
+  }
+  __syncthreads();
+  for (int t = 0; t < nt; t++) {
+    double L = band_set_loglike<N>(g, tb, a, t, wt[t], b, wt[t], k0w, sm);
+    if (tid == 0) Lc[t] = L;
+  }
+  __syncthreads();
+  const double* bt = a.betas + (int64_t)b * nt;
+  unsigned long long n_prop = 0, n_acc = 0;
+  for (int t = nt - 1; t >= 1; t--) {
+    const double L1 = band_set_loglike<N>(g, tb, a, t - 1, wt[t - 1], b, wt[t], k0w, sm);
+    const double L2 = band_set_loglike<N>(g, tb, a, t, wt[t], b, wt[t - 1], k0w, sm);
+    const double la = bt[t] * (L1 - Lc[t]) + bt[t - 1] * (L2 - Lc[t - 1]);
+    const double r = rng_uniform(a.seed, sweep, kMovePT, (uint64_t)b * a.n_w + i, (uint64_t)t);
+    n_prop++;
+    if (log(r) < la) {
+      n_acc++;
+      if (t == 1) {
+        // the cold chain of walker w_0 changes: own-parity buffer += old - new
+        cd* own = a.resid + ((int64_t)(b & 1) * a.n_w + wt[0]) * 2 * g.n_bins;
+        for (int s = 0; s < a.n_slot; s++) {
+          if (a.exists[uidx(a, 0, wt[0], b, s)]) {
+            band_template<N>(g, tb, a.u + 8 * uidx(a, 0, wt[0], b, s), sm);
+            band_add_template<N>(g, tb, sm, k0w, 1.0, own);
+          }
+          if (a.exists[uidx(a, 1, wt[1], b, s)]) {
+            band_template<N>(g, tb, a.u + 8 * uidx(a, 1, wt[1], b, s), sm);
+            band_add_template<N>(g, tb, sm, k0w, -1.0, own);
+          }
+        }
+      }
+      // exchange the source sets of (t, w_t) and (t-1, w_(t-1))
+      for (int s = tid; s < a.n_slot; s += block_threads<N>()) {
+        int64_t i1 = uidx(a, t, wt[t], b, s), i2 = uidx(a, t - 1, wt[t - 1], b, s);
+        for (int k = 0; k < 8; k++) {
+          double tmp = a.u[8 * i1 + k];
+          a.u[8 * i1 + k] = a.u[8 * i2 + k];
+          a.u[8 * i2 + k] = tmp;
+        }
+        int32_t e = a.exists[i1];
+        a.exists[i1] = a.exists[i2];
+        a.exists[i2] = e;
+      }
+      __threadfence_block();
+      __syncthreads();
+      if (tid == 0) {
+        Lc[t] = L1;
+        Lc[t - 1] = L2;
+      }
+      __syncthreads();
+    }
+  }
+  if (tid == 0) {
+    atomicAdd(&a.stats[6], n_prop);
+    if (n_acc) atomicAdd(&a.stats[7], n_acc);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Stationary groups: the cold-chain sources of every walker in each band,
+// sorted by f0 (ties keep walker-major, slot-minor order).
+// ---------------------------------------------------------------------------
+// every > 0: rebuild only on sweeps that are multiples of `every` (the check
+// runs on the device so that captured sweeps stay replayable)
+__global__ void k_sweep_group(SweepArgs a, int every) {
+  if (every > 0 && (*a.sweep_ctr % every) != 0) return;
+  const int b = blockIdx.x;
+  const int S = a.n_slot;
+  const int M = a.n_w * S;
+  double* grp = a.group + (int64_t)b * M * 8;
+  __shared__ int count;
+  if (threadIdx.x == 0) {
+    int n = 0;
+    for (int m = 0; m < M; m++) n += a.exists[uidx(a, 0, m / S, b, m % S)] != 0;
+    count = n;
+    a.group_count[b] = n;
+  }
+  __syncthreads();
+  for (int m = threadIdx.x; m < M; m += blockDim.x) {
+    const int w = m / S, s = m % S;
+    const int64_t ui = uidx(a, 0, w, b, s);
+    if (!a.exists[ui]) continue;
+    const double f = a.u[8 * ui + 1];
+    int rank = 0;
+    for (int m2 = 0; m2 < M; m2++) {
+      const int64_t u2 = uidx(a, 0, m2 / S, b, m2 % S);
+      if (!a.exists[u2]) continue;
+      const double f2 = a.u[8 * u2 + 1];
+      rank += (f2 < f) || (f2 == f && m2 < m);
+    }
+    for (int k = 0; k < 8; k++) grp[8 * rank + k] = a.u[8 * ui + k];
+  }
+  (void)count;
+}
+
+__global__ void k_sweep_advance(int64_t* sweep_ctr) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *sweep_ctr += 1;
+}
+
+}  // namespace gbl

@@ -26,7 +26,10 @@ SUPPORTED_N = (128, 256, 512, 1024)
 
 EXPORTED = ("gbl_create", "gbl_destroy", "gbl_set_stream", "gbl_last_error", "gbl_band", "gb_waveform",
             "gb_waveform_var", "gb_delta_loglike", "gb_delta_loglike_var", "gb_psd_eval", "gb_psd_loglike",
-            "gb_scatter_add", "gb_make_noise")
+            "gb_scatter_add", "gb_make_noise", "gb_sweep_step", "gb_sweep_group", "gb_sweep_advance",
+            "gb_sweep_run", "gb_sweep_graph_create", "gb_graph_launch", "gb_graph_destroy")
+
+GBL_MOVE_INMODEL, GBL_MOVE_RJ, GBL_MOVE_PT = 0, 1, 2
 
 
 class GblError(RuntimeError):
@@ -39,6 +42,21 @@ class Config(ctypes.Structure):
     _fields_ = [("T", ctypes.c_double), ("dt", ctypes.c_double), ("L", ctypes.c_double),
                 ("f_lo", ctypes.c_double), ("f_hi", ctypes.c_double), ("precision", ctypes.c_int32),
                 ("flags", ctypes.c_int32)]
+
+
+class SweepConfig(ctypes.Structure):
+    """gbl_sweep_config"""
+    _fields_ = [("n_temps", ctypes.c_int32), ("n_walkers", ctypes.c_int32), ("n_bands", ctypes.c_int32),
+                ("n_slots", ctypes.c_int32), ("N", ctypes.c_int32), ("n_prop", ctypes.c_int32),
+                ("n_friends", ctypes.c_int32), ("group_every", ctypes.c_int32), ("k_band0", ctypes.c_int64),
+                ("stretch_a", ctypes.c_double), ("seed", ctypes.c_uint64),
+                ("prior_lo", ctypes.c_double * 8), ("prior_hi", ctypes.c_double * 8)]
+
+
+class SweepState(ctypes.Structure):
+    """gbl_sweep_state (device pointers)"""
+    _fields_ = [(n, ctypes.c_void_p) for n in ("u", "exists", "betas", "resid", "inv_psd", "group", "group_count",
+                                              "stats", "sweep_counter")]
 
 
 _lib = None
@@ -66,6 +84,14 @@ def load_library(path: str = LIB_PATH):
         "gb_psd_loglike": [vp, vp, i32, vp, vp, i64, vp],
         "gb_scatter_add": [vp, vp, i64, i32, dbl, vp, i32, vp],
         "gb_make_noise": [vp, vp, vp, i64, vp],
+        "gb_sweep_step": [vp, ctypes.POINTER(SweepConfig), ctypes.POINTER(SweepState), i32, i32],
+        "gb_sweep_group": [vp, ctypes.POINTER(SweepConfig), ctypes.POINTER(SweepState)],
+        "gb_sweep_advance": [vp, ctypes.POINTER(SweepState)],
+        "gb_sweep_run": [vp, ctypes.POINTER(SweepConfig), ctypes.POINTER(SweepState), i32],
+        "gb_sweep_graph_create": [vp, ctypes.POINTER(SweepConfig), ctypes.POINTER(SweepState), i32,
+                                  ctypes.POINTER(vp)],
+        "gb_graph_launch": [vp],
+        "gb_graph_destroy": [vp],
     }
     for name, args in sigs.items():
         fn = getattr(lib, name)

@@ -1,0 +1,104 @@
+"""Binding of the sampler sweep (Sec. 4; appendix algorithms gb1 and gb2).
+
+`Sweep` owns the device tensors of the sampler state in the layouts of
+include/gbl.h and forwards to the C ABI (argument marshalling only).
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from .gbl import GBL_MOVE_INMODEL, GBL_MOVE_PT, GBL_MOVE_RJ, Context, SweepConfig, SweepState, _ptr
+
+__all__ = ["Sweep", "make_config", "GBL_MOVE_INMODEL", "GBL_MOVE_RJ", "GBL_MOVE_PT"]
+
+# default prior box of the sampling coordinates
+# (log10 A, f0 [per band], fdot, phi0, cos iota, psi, lambda, sin beta)
+DEFAULT_PRIOR_LO = (-23.0, 0.0, -1e-16, 0.0, -1.0, 0.0, 0.0, -1.0)
+DEFAULT_PRIOR_HI = (-21.0, 0.0, 1e-15, 0.0, 1.0, 0.0, 0.0, 1.0)
+
+
+def make_config(n_temps, n_walkers, n_bands, n_slots, N, k_band0, n_prop=10, n_friends=8, group_every=30,
+                stretch_a=2.0, seed=1234, prior_lo=DEFAULT_PRIOR_LO, prior_hi=DEFAULT_PRIOR_HI, cls=SweepConfig):
+    c = cls()
+    c.n_temps, c.n_walkers, c.n_bands, c.n_slots = n_temps, n_walkers, n_bands, n_slots
+    c.N, c.n_prop, c.n_friends, c.group_every = N, n_prop, n_friends, group_every
+    c.k_band0, c.stretch_a, c.seed = k_band0, stretch_a, seed
+    for i in range(8):
+        c.prior_lo[i] = prior_lo[i]
+        c.prior_hi[i] = prior_hi[i]
+    return c
+
+
+class Sweep:
+    def __init__(self, ctx: Context, cfg: SweepConfig):
+        self.ctx, self.cfg = ctx, cfg
+        dev = ctx.device
+        nt, nw, nb, ns = cfg.n_temps, cfg.n_walkers, cfg.n_bands, cfg.n_slots
+        f64 = dict(dtype=torch.float64, device=dev)
+        self.u = torch.zeros((nt, nw, nb, ns, 8), **f64)
+        self.exists = torch.zeros((nt, nw, nb, ns), dtype=torch.int32, device=dev)
+        self.betas = torch.ones((nb, nt), **f64)
+        self.resid = torch.zeros((2, nw, 2, ctx.n_bins), dtype=torch.complex128, device=dev)
+        self.inv_psd = torch.zeros((nw, 2, ctx.n_bins), **f64)
+        self.group = torch.zeros((nb, nw * ns, 8), **f64)
+        self.group_count = torch.zeros(nb, dtype=torch.int32, device=dev)
+        self.stats = torch.zeros(8, dtype=torch.int64, device=dev)
+        self.sweep_counter = torch.zeros(1, dtype=torch.int64, device=dev)
+        self._graph = None
+
+    def _state(self):
+        st = SweepState()
+        for n in ("u", "exists", "betas", "resid", "inv_psd", "group", "group_count", "stats", "sweep_counter"):
+            setattr(st, n, getattr(self, n).data_ptr())
+        return st
+
+    def _call(self, name, *args):
+        self.ctx._sync_stream()
+        rc = getattr(self.ctx.lib, name)(self.ctx._h, *args)
+        self.ctx._check(rc, name)
+
+    def step(self, move: int, parity: int):
+        self._call("gb_sweep_step", ctypes.byref(self.cfg), ctypes.byref(self._state()), int(move), int(parity))
+
+    def group_refresh(self):
+        self._call("gb_sweep_group", ctypes.byref(self.cfg), ctypes.byref(self._state()))
+
+    def advance(self):
+        self._call("gb_sweep_advance", ctypes.byref(self._state()))
+
+    def run(self, n_sweeps: int):
+        self._call("gb_sweep_run", ctypes.byref(self.cfg), ctypes.byref(self._state()), int(n_sweeps))
+
+    def capture(self, n_sweeps: int):
+        """Capture n_sweeps full sweeps into a HIP graph (context stream must not be the default one)."""
+        self.release_graph()
+        h = ctypes.c_void_p()
+        self._call("gb_sweep_graph_create", ctypes.byref(self.cfg), ctypes.byref(self._state()), int(n_sweeps),
+                   ctypes.byref(h))
+        self._graph = h
+
+    def replay(self):
+        rc = self.ctx.lib.gb_graph_launch(self._graph)
+        self.ctx._check(rc, "gb_graph_launch")
+
+    def release_graph(self):
+        if self._graph is not None:
+            self.ctx.lib.gb_graph_destroy(self._graph)
+            self._graph = None
+
+    def __del__(self):
+        try:
+            self.release_graph()
+        except Exception:
+            pass
+
+    @staticmethod
+    def geometric_ladder(n_temps: int, ratio: float = 1.2, hottest_zero: bool = True):
+        """Inverse temperatures 1, 1/r, 1/r^2, ... with an infinite-temperature top rung (Sec. 4)."""
+        b = ratio ** -np.arange(n_temps, dtype=np.float64)
+        if hottest_zero and n_temps > 1:
+            b[-1] = 0.0
+        return b
