@@ -59,6 +59,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true", help="skip the secondary measurements")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the sampler-sweep measurement")
+    ap.add_argument("--sweeps", type=int, default=2, help="timed sampler sweeps")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 512 MiB device copy (counter calibration for profiles)")
     return ap.parse_args()
@@ -155,6 +157,108 @@ def secondary(ctx, torch, stream, cfg, R, invS, po, pn, ri, pi):
     return out
 
 
+def _physical(u):
+    """sampling coordinates -> physical parameter vectors (input marshalling)"""
+    import torch
+    p = u.clone()
+    p[:, 0] = torch.pow(10.0, u[:, 0])
+    p[:, 4] = torch.acos(u[:, 4])
+    p[:, 7] = torch.asin(u[:, 7])
+    return p
+
+
+def sweep_bench(torch, dev, stream, n_sweeps, n_temps=36, n_walkers=32, n_prop=30):
+    """Full sampler sweeps (group refresh when due, in-model, RJ, tempering;
+    odd then even sub-bands) over a 12,000-source 1 yr data set, N = 256
+    sub-bands, 36 temperatures x 32 walkers, every walker starting from the
+    injected catalogue (f0 jittered)."""
+    from paper_2405_04690_amd import inputs
+    from paper_2405_04690_amd.gbl import Context
+    from paper_2405_04690_amd.sampler import Sweep, make_config
+    cfg = inputs.PAPER
+    N, T = 256, cfg.T
+    ctx = Context(T=T, dt=cfg.dt, L=cfg.L, f_lo=cfg.f_lo, f_hi=cfg.f_hi, device=dev, stream=stream)
+    src = inputs.draw_sources(35, 12000, (1e-3, 1e-2), (-19.0, -15.0))
+    k_band0 = int(np.floor(1e-3 * T))
+    n_bands = int(np.ceil((1e-2 * T - k_band0) / N))
+    ub, eb, dropped = inputs.band_slots(src, T, k_band0, N, n_bands, 64)
+    n_slot = ub.shape[1]
+    sc = make_config(n_temps, n_walkers, n_bands, n_slot, N, k_band0, n_prop=n_prop, n_friends=40,
+                     group_every=30, seed=37)
+    sw = Sweep(ctx, sc)
+    sw.u.copy_(torch.from_numpy(ub).to(dev).expand(n_temps, n_walkers, -1, -1, -1))
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(38)
+    sw.u[..., 1] += torch.randn(sw.u.shape[:-1], generator=gen, device=dev, dtype=torch.float64) * (0.1 / T)
+    sw.exists.copy_(torch.from_numpy(eb).to(dev).expand(n_temps, n_walkers, -1, -1))
+    sw.betas.copy_(torch.from_numpy(Sweep.geometric_ladder(n_temps)).to(dev).expand(n_bands, -1))
+    noise = torch.tensor([[cfg.sqrt_oms, cfg.sqrt_acc, cfg.sqrt_oms, cfg.sqrt_acc]], dtype=torch.float64,
+                         device=dev)
+    S = ctx.gb_psd_eval(noise)
+    sw.inv_psd.copy_(ctx.gb_psd_eval(noise, inverse=True).expand(n_walkers, -1, -1))
+    d = ctx.gb_make_noise(S, torch.from_numpy(inputs.complex_normals(36, (1, 2, ctx.n_bins))).to(dev))
+    keep = eb.astype(bool)
+    inj = torch.from_numpy(ub[keep]).to(dev)
+    ctx.gb_scatter_add(_physical(inj), N, 1.0, d)
+    band_par = (torch.arange(n_bands, device=dev) % 2).view(1, n_bands, 1).expand(n_walkers, -1, n_slot)
+    walker = torch.arange(n_walkers, device=dev, dtype=torch.int32).view(n_walkers, 1, 1).expand(-1, n_bands, n_slot)
+    for par in (0, 1):
+        sw.resid[par].copy_(d.expand(n_walkers, -1, -1))
+        sel = (sw.exists[0] != 0) & (band_par == par)
+        cold = _physical(sw.u[0][sel].contiguous())
+        ctx.gb_scatter_add(cold, N, -1.0, sw.resid[par], walker[sel].contiguous())
+    torch.cuda.synchronize()
+    # warm-up sweep (builds the groups at sweep 0), then one sweep phase by phase
+    sw.run(1)
+    torch.cuda.synchronize()
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+    phases = [("group", lambda: sw.group_refresh())]
+    for mv, name in ((0, "inmodel"), (1, "rj"), (2, "tempering")):
+        for par in (1, 0):
+            phases.append((f"{name}_{'odd' if par else 'even'}", (lambda m=mv, q=par: sw.step(m, q))))
+    marks = [ev() for _ in range(len(phases) + 1)]
+    marks[0].record(stream)
+    for i, (_, fn) in enumerate(phases):
+        fn()
+        marks[i + 1].record(stream)
+    sw.advance()
+    torch.cuda.synchronize()
+    phase_ms = {name: round(marks[i].elapsed_time(marks[i + 1]), 3) for i, (name, _) in enumerate(phases)}
+    # timed direct sweeps, then the same number replayed from a captured graph
+    st0 = sw.stats.cpu().numpy().copy()
+    a, b = ev(), ev()
+    a.record(stream)
+    sw.run(n_sweeps)
+    b.record(stream)
+    torch.cuda.synchronize()
+    direct_ms = a.elapsed_time(b) / n_sweeps
+    st1 = sw.stats.cpu().numpy().copy()
+    sw.capture(1)
+    a, b = ev(), ev()
+    a.record(stream)
+    for _ in range(n_sweeps):
+        sw.replay()
+    b.record(stream)
+    torch.cuda.synchronize()
+    graph_ms = a.elapsed_time(b) / n_sweeps
+    sw.release_graph()
+    dst = st1 - st0
+    rate = lambda k: round(float(dst[k]) / (direct_ms * n_sweeps / 1e3), 1)
+    acc = lambda p, q: round(float(dst[q]) / max(1.0, float(dst[p])), 4)
+    out = {"workload": f"1 yr, 12000 sources log-uniform in 1-10 mHz ({dropped} beyond slot capacity), "
+                       f"{n_bands} sub-bands of N=256, {n_temps} temps x {n_walkers} walkers x {n_slot} slots, "
+                       f"n_prop={n_prop}, group refresh every 30 sweeps, FP64",
+           "sweeps": n_sweeps, "ms_per_sweep": round(direct_ms, 3), "sweeps_per_s": round(1e3 / direct_ms, 4),
+           "graph_ms_per_sweep": round(graph_ms, 3), "phase_ms": phase_ms,
+           "group_ms_amortised": round(phase_ms["group"] / 30, 3),
+           "inmodel_proposals_per_s": rate(0), "rj_proposals_per_s": rate(2) + rate(4),
+           "swap_proposals_per_s": rate(6),
+           "acceptance": {"inmodel": acc(0, 1), "birth": acc(2, 3), "death": acc(4, 5), "swap": acc(6, 7)}}
+    del sw
+    ctx.close()
+    return out
+
+
 def cpu_baseline(batch, cfg, target_s):
     """The FP64 oracle on a bounded sample of the same swap batch."""
     import oracle
@@ -235,6 +339,11 @@ def main():
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         sec = None if args.no_secondary else secondary(ctx, torch, stream, cfg, R, invS, po, pn, ri, pi)
+        if not args.no_sweep:
+            del R
+            torch.cuda.empty_cache()
+            sec = dict(sec or {})
+            sec["sweep"] = sweep_bench(torch, dev, stream, args.sweeps)
     per_launch_ms = float(np.mean([s.elapsed_time(e) for s, e in ev]))
     total_ms = ev[0][0].elapsed_time(ev[-1][1])
     value = B * args.steps / (total_ms / 1e3)

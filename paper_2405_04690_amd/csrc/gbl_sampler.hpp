@@ -587,35 +587,50 @@ __global__ __launch_bounds__(block_threads<N>()) void k_sweep_pt(Geo g, WaveTabl
 // ---------------------------------------------------------------------------
 // every > 0: rebuild only on sweeps that are multiples of `every` (the check
 // runs on the device so that captured sweeps stay replayable)
-__global__ void k_sweep_group(SweepArgs a, int every) {
+__global__ __launch_bounds__(256) void k_sweep_group(SweepArgs a, int every) {
   if (every > 0 && (*a.sweep_ctr % every) != 0) return;
+  constexpr int kChunk = 4096;
+  __shared__ double fv[kChunk];  // f0 of a chunk of entries, NaN where the slot is empty
+  __shared__ int count;
   const int b = blockIdx.x;
   const int S = a.n_slot;
   const int M = a.n_w * S;
   double* grp = a.group + (int64_t)b * M * 8;
-  __shared__ int count;
-  if (threadIdx.x == 0) {
-    int n = 0;
-    for (int m = 0; m < M; m++) n += a.exists[uidx(a, 0, m / S, b, m % S)] != 0;
-    count = n;
-    a.group_count[b] = n;
+  if (threadIdx.x == 0) count = 0;
+  for (int m0 = 0; m0 < M; m0 += blockDim.x) {
+    const int m = m0 + threadIdx.x;
+    bool mine = false;
+    double f = 0.0;
+    int64_t ui = 0;
+    if (m < M) {
+      ui = uidx(a, 0, m / S, b, m % S);
+      mine = a.exists[ui] != 0;
+      f = a.u[8 * ui + 1];
+    }
+    // rank = number of entries ordered before this one (f0, then entry index)
+    int rank = 0;
+    for (int c0 = 0; c0 < M; c0 += kChunk) {
+      const int n = min(kChunk, M - c0);
+      __syncthreads();
+      for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const int m2 = c0 + i;
+        const int64_t u2 = uidx(a, 0, m2 / S, b, m2 % S);
+        fv[i] = a.exists[u2] ? a.u[8 * u2 + 1] : qnan();
+      }
+      __syncthreads();
+      if (mine)
+        for (int i = 0; i < n; i++) {
+          const double f2 = fv[i];
+          rank += (f2 < f) || (f2 == f && c0 + i < m);
+        }
+    }
+    if (mine) {
+      for (int k = 0; k < 8; k++) grp[8 * rank + k] = a.u[8 * ui + k];
+      atomicAdd(&count, 1);
+    }
   }
   __syncthreads();
-  for (int m = threadIdx.x; m < M; m += blockDim.x) {
-    const int w = m / S, s = m % S;
-    const int64_t ui = uidx(a, 0, w, b, s);
-    if (!a.exists[ui]) continue;
-    const double f = a.u[8 * ui + 1];
-    int rank = 0;
-    for (int m2 = 0; m2 < M; m2++) {
-      const int64_t u2 = uidx(a, 0, m2 / S, b, m2 % S);
-      if (!a.exists[u2]) continue;
-      const double f2 = a.u[8 * u2 + 1];
-      rank += (f2 < f) || (f2 == f && m2 < m);
-    }
-    for (int k = 0; k < 8; k++) grp[8 * rank + k] = a.u[8 * ui + k];
-  }
-  (void)count;
+  if (threadIdx.x == 0) a.group_count[b] = count;
 }
 
 __global__ void k_sweep_advance(int64_t* sweep_ctr) {

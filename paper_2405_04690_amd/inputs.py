@@ -135,3 +135,34 @@ def paper_swap_batch(n_walkers: int = 32, n_temps: int = 24, n_src: int = 130, s
         raise ValueError(mix)
     walker = (np.arange(B) // n_src) % n_walkers
     return SwapBatch(src, old, new, walker.astype(np.int32), n_walkers, n_temps)
+
+
+def band_slots(sources: np.ndarray, T: float, k_band0: int, width: int, n_bands: int, max_slots: int):
+    """Assign sources to sub-bands of `width` bins starting at bin k_band0 by
+    their carrier bin floor(f0 T), and lay them out as per-band slot lists in
+    sampling coordinates (log10 A, f0, fdot, phi0, cos iota, psi, lambda,
+    sin beta).
+
+    Returns (u [n_bands, n_slot, 8], exists [n_bands, n_slot] int32, dropped)
+    with n_slot = min(max_slots, largest band count + 8); sources beyond a
+    band's capacity or outside the band range are dropped (count returned).
+    """
+    q = np.floor(sources[:, 1] * T).astype(np.int64)
+    b = (q - k_band0) // width
+    keep = (b >= 0) & (b < n_bands)
+    counts = np.bincount(b[keep], minlength=n_bands)
+    n_slot = int(min(max_slots, counts.max() + 8))
+    u = np.zeros((n_bands, n_slot, 8))
+    ex = np.zeros((n_bands, n_slot), np.int32)
+    fill = np.zeros(n_bands, np.int64)
+    dropped = int((~keep).sum())
+    for i in np.nonzero(keep)[0]:
+        bb = b[i]
+        if fill[bb] >= n_slot:
+            dropped += 1
+            continue
+        p = sources[i]
+        u[bb, fill[bb]] = [np.log10(p[0]), p[1], p[2], p[3], np.cos(p[4]), p[5], p[6], np.sin(p[7])]
+        ex[bb, fill[bb]] = 1
+        fill[bb] += 1
+    return u, ex, dropped
