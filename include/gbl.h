@@ -255,6 +255,82 @@ int gb_sweep_graph_create(gbl_ctx* ctx, const gbl_sweep_config* cfg, const gbl_s
 int gb_graph_launch(gbl_graph* graph);
 int gb_graph_destroy(gbl_graph* graph);
 
+/* ---------------------------------------------------------------------------
+ * Learned reversible-jump proposal: a conditional affine-coupling flow.
+ *
+ * The paper fits its RJ proposal distributions with Gaussian mixtures and
+ * plans normalizing flows instead (Discussion, "Single source
+ * search-to-parameter estimation information transfer"; appendix "Algorithm
+ * for fitting proposal distributions"; Sec. 4 "Online updating of RJ sampling
+ * distributions" for the online refit).  The flow's form is a reading:
+ *   u = (log10 A, f0, fdot, phi0, cos iota, psi, lambda, sin beta) inside the
+ *   prior box of sub-band b (f0 in [k_band0 + (b - 1/2) width,
+ *   k_band0 + (b + 3/2) width) / T; phi0, lambda in [0, 2 pi); psi in [0, pi);
+ *   the other four from prior_lo / prior_hi) maps to x_i = logit of its
+ *   position in the box; six affine coupling layers (layer l keeps the
+ *   coordinates (0,2,4,6) for even l, (1,3,5,7) for odd l, and moves the rest:
+ *   y = x exp(s) + t, s = 2 tanh(s_hat), (s_hat, t) = MLP([x_kept, E[b]]) with
+ *   MLP 20 -> 128 -> 128 -> 8 and SiLU, E a learned 16-wide embedding of b);
+ *   ln q_u(u) = sum ln N(z_i; 0, 1) + sum of s + sum ln |dx_i/du_i|.
+ * Arithmetic: BF16 MFMA inputs (weights, embeddings, activations; round to
+ * nearest even), FP32 accumulation, FP64 flow state and log-density sums.
+ *
+ * Parameter vector (FP32, caller-owned, n_params = 6 * GBL_FLOW_LAYER_PARAMS
+ * + 16 * n_emb): for each layer W1 [128][20], b1 [128], W2 [128][128],
+ * b2 [128], W3 [8][128], b3 [8] (row-major, output-major), then E [n_emb][16].
+ * `packed` holds the BF16 copy in MFMA fragment order (write it with
+ * gb_flow_pack after changing params; gb_flow_adam repacks by itself).
+ * --------------------------------------------------------------------------- */
+#define GBL_FLOW_LAYER_PARAMS 20232
+
+typedef struct {
+  int32_t n_emb;       /* number of sub-bands (conditioning values b = 0..n_emb-1) */
+  int32_t width;       /* sub-band width in bins */
+  int64_t k_band0;     /* first bin of sub-band 0 */
+  double prior_lo[8];  /* box bounds of log10 A, fdot, cos iota, sin beta (entries 0, 2, 4, 7) */
+  double prior_hi[8];
+} gbl_flow_config;
+
+typedef struct {
+  float* params;     /* [n_params] FP32 master weights */
+  float* adam_m;     /* [n_params] Adam first moment */
+  float* adam_v;     /* [n_params] Adam second moment */
+  float* grad;       /* [n_params] gradient of the last gb_flow_grad */
+  void* packed;      /* packed_bytes: BF16 fragments */
+  void* workspace;   /* workspace_bytes: partial sums of gb_flow_grad */
+  double* loss;      /* [1] mean negative log-density of the last gb_flow_grad */
+} gbl_flow;
+
+/* Sizes of the caller-owned flow buffers (host call; no device work). */
+int gb_flow_sizes(const gbl_flow_config* cfg, int64_t* n_params, int64_t* packed_bytes, int64_t* workspace_bytes);
+
+/* packed <- BF16(params). */
+int gb_flow_pack(gbl_ctx* ctx, const gbl_flow_config* cfg, const gbl_flow* flow);
+
+/* logq[i] = ln q_u(u[i] | band[i]); u [B][8], band [B] int32.  A point not
+ * strictly inside its box or an out-of-range band gives NaN. */
+int gb_flow_log_prob(gbl_ctx* ctx, const gbl_flow_config* cfg, const gbl_flow* flow, const double* u,
+                     const int32_t* band, int64_t B, double* logq);
+
+/* Push standard normals z [B][8] through the inverse flow: u [B][8] inside the
+ * box of band[i] and logq[i] = ln q_u(u[i] | band[i]) (equal to what
+ * gb_flow_log_prob returns at u[i], up to FP64 rounding). */
+int gb_flow_sample(gbl_ctx* ctx, const gbl_flow_config* cfg, const gbl_flow* flow, const double* z,
+                   const int32_t* band, int64_t B, double* u, double* logq);
+
+/* Training gradient: flow->grad = d/dparams of -(1/B) sum_i ln q_x(x(u[i]) | band[i])
+ * and flow->loss = that mean (B >= 1; points outside their box contribute 0). */
+int gb_flow_grad(gbl_ctx* ctx, const gbl_flow_config* cfg, const gbl_flow* flow, const double* u,
+                 const int32_t* band, int64_t B);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias correction with
+ * `step` counted from 1) from flow->grad, then repack. */
+int gb_flow_adam(gbl_ctx* ctx, const gbl_flow_config* cfg, const gbl_flow* flow, int64_t step, float lr);
+
+/* gb_flow_grad followed by gb_flow_adam. */
+int gb_flow_train_step(gbl_ctx* ctx, const gbl_flow_config* cfg, const gbl_flow* flow, const double* u,
+                       const int32_t* band, int64_t B, int64_t step, float lr);
+
 #ifdef __cplusplus
 }
 #endif

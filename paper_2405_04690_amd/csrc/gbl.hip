@@ -12,6 +12,7 @@
 #include "../../include/gbl.h"
 #include "gbl_kernels.hpp"
 #include "gbl_sampler.hpp"
+#include "gbl_flow.hpp"
 
 using gbl::cd;
 
@@ -590,4 +591,138 @@ extern "C" int gb_graph_destroy(gbl_graph* gr) {
   (void)hipGraphDestroy(gr->graph);
   delete gr;
   return GBL_OK;
+}
+
+// ---------------------------------------------------------------------------
+// learned RJ proposal (flow)
+// ---------------------------------------------------------------------------
+static int64_t flow_n_params(const gbl_flow_config* c) {
+  return (int64_t)gbl::flow::kLayers * gbl::flow::kLayerParams + (int64_t)gbl::flow::kEmb * c->n_emb;
+}
+
+static int64_t flow_workspace_bytes() {
+  return (int64_t)gbl::flow::kMaxGroups * gbl::flow::kLayers * gbl::flow::kLayerParams * 4 +
+         (int64_t)gbl::flow::kMaxGroups * 8;
+}
+
+extern "C" int gb_flow_sizes(const gbl_flow_config* cfg, int64_t* n_params, int64_t* packed_bytes,
+                             int64_t* workspace_bytes) {
+  if (!cfg || cfg->n_emb < 1) return GBL_EINVAL;
+  if (n_params) *n_params = flow_n_params(cfg);
+  if (packed_bytes) *packed_bytes = gbl::flow::kPackedBytes;
+  if (workspace_bytes) *workspace_bytes = flow_workspace_bytes();
+  return GBL_OK;
+}
+
+static int flow_check(gbl_ctx* ctx, const gbl_flow_config* c, const gbl_flow* f) {
+  if (!c || !f) return fail(ctx, GBL_EINVAL, "flow: null config or state%s");
+  if (c->n_emb < 1 || c->width < 1) return fail(ctx, GBL_EINVAL, "flow: n_emb and width must be positive%s");
+  const int dims[4] = {0, 2, 4, 7};
+  for (int i : dims)
+    if (!(c->prior_lo[i] < c->prior_hi[i])) return fail(ctx, GBL_EINVAL, "flow: empty prior box%s");
+  if (!f->params || !f->packed) return fail(ctx, GBL_EINVAL, "flow: null params or packed buffer%s");
+  return GBL_OK;
+}
+
+static gbl::flow::FlowArgs flow_args(gbl_ctx* ctx, const gbl_flow_config* c, const gbl_flow* f) {
+  gbl::flow::FlowArgs a;
+  a.params = f->params;
+  a.packed = (const gbl::flow::u32x4_t*)f->packed;
+  a.n_emb = c->n_emb;
+  a.width = c->width;
+  a.k_band0 = c->k_band0;
+  a.T = ctx->cfg.T;
+  for (int i = 0; i < 8; i++) {
+    a.lo[i] = c->prior_lo[i];
+    a.hi[i] = c->prior_hi[i];
+  }
+  return a;
+}
+
+extern "C" int gb_flow_pack(gbl_ctx* ctx, const gbl_flow_config* cfg, const gbl_flow* fl) {
+  if (!ctx) return GBL_EINVAL;
+  int rc = flow_check(ctx, cfg, fl);
+  if (rc) return rc;
+  const int n = gbl::flow::kLayers * gbl::flow::kFragPerLayer * 64;
+  hipLaunchKernelGGL(gbl::flow::k_flow_pack, dim3((n + 255) / 256), dim3(256), 0, ctx->stream, fl->params,
+                     (gbl::flow::u32x4_t*)fl->packed);
+  return check_launch(ctx, "gb_flow_pack");
+}
+
+static unsigned flow_grid(int64_t B) {
+  const int64_t blocks = (B + 63) / 64;
+  return (unsigned)(blocks < 4096 ? blocks : 4096);
+}
+
+extern "C" int gb_flow_log_prob(gbl_ctx* ctx, const gbl_flow_config* cfg, const gbl_flow* fl, const double* u,
+                                const int32_t* band, int64_t B, double* logq) {
+  if (!ctx) return GBL_EINVAL;
+  int rc = flow_check(ctx, cfg, fl);
+  if (rc) return rc;
+  if (B < 0) return fail(ctx, GBL_EINVAL, "gb_flow_log_prob: B < 0%s");
+  if (B == 0) return GBL_OK;
+  if (!u || !band || !logq) return fail(ctx, GBL_EINVAL, "gb_flow_log_prob: null pointer%s");
+  hipLaunchKernelGGL(gbl::flow::k_flow_apply<false>, dim3(flow_grid(B)), dim3(256), 0, ctx->stream,
+                     flow_args(ctx, cfg, fl), u, band, B, (double*)nullptr, logq);
+  return check_launch(ctx, "gb_flow_log_prob");
+}
+
+extern "C" int gb_flow_sample(gbl_ctx* ctx, const gbl_flow_config* cfg, const gbl_flow* fl, const double* z,
+                              const int32_t* band, int64_t B, double* u, double* logq) {
+  if (!ctx) return GBL_EINVAL;
+  int rc = flow_check(ctx, cfg, fl);
+  if (rc) return rc;
+  if (B < 0) return fail(ctx, GBL_EINVAL, "gb_flow_sample: B < 0%s");
+  if (B == 0) return GBL_OK;
+  if (!z || !band || !u || !logq) return fail(ctx, GBL_EINVAL, "gb_flow_sample: null pointer%s");
+  hipLaunchKernelGGL(gbl::flow::k_flow_apply<true>, dim3(flow_grid(B)), dim3(256), 0, ctx->stream,
+                     flow_args(ctx, cfg, fl), z, band, B, u, logq);
+  return check_launch(ctx, "gb_flow_sample");
+}
+
+extern "C" int gb_flow_grad(gbl_ctx* ctx, const gbl_flow_config* cfg, const gbl_flow* fl, const double* u,
+                            const int32_t* band, int64_t B) {
+  if (!ctx) return GBL_EINVAL;
+  int rc = flow_check(ctx, cfg, fl);
+  if (rc) return rc;
+  if (B < 1) return fail(ctx, GBL_EINVAL, "gb_flow_grad: B < 1%s");
+  if (!u || !band || !fl->grad || !fl->workspace || !fl->loss)
+    return fail(ctx, GBL_EINVAL, "gb_flow_grad: null pointer%s");
+  using namespace gbl::flow;
+  const int64_t n_layer = (int64_t)kLayers * kLayerParams;
+  const int64_t n_emb = (int64_t)kEmb * cfg->n_emb;
+  hipLaunchKernelGGL(k_flow_fill, dim3((unsigned)((n_emb + 255) / 256)), dim3(256), 0, ctx->stream,
+                     fl->grad + n_layer, n_emb, 0.0f);
+  const int64_t chunks = (B + kChunk - 1) / kChunk;
+  const int groups = (int)(chunks < kMaxGroups ? chunks : kMaxGroups);
+  float* partial = (float*)fl->workspace;
+  double* loss_part = (double*)((char*)fl->workspace + (int64_t)kMaxGroups * n_layer * 4);
+  hipLaunchKernelGGL(k_flow_grad, dim3(groups), dim3(256), 0, ctx->stream, flow_args(ctx, cfg, fl), u, band, B,
+                     partial, loss_part, fl->grad + n_layer);
+  hipLaunchKernelGGL(k_flow_reduce, dim3((unsigned)((n_layer + 255) / 256)), dim3(256), 0, ctx->stream,
+                     (const float*)partial, groups, (const double*)loss_part, fl->grad, fl->loss);
+  return check_launch(ctx, "gb_flow_grad");
+}
+
+extern "C" int gb_flow_adam(gbl_ctx* ctx, const gbl_flow_config* cfg, const gbl_flow* fl, int64_t step, float lr) {
+  if (!ctx) return GBL_EINVAL;
+  int rc = flow_check(ctx, cfg, fl);
+  if (rc) return rc;
+  if (step < 1 || !(lr >= 0.0f)) return fail(ctx, GBL_EINVAL, "gb_flow_adam: step < 1 or bad learning rate%s");
+  if (!fl->adam_m || !fl->adam_v || !fl->grad) return fail(ctx, GBL_EINVAL, "gb_flow_adam: null pointer%s");
+  const int64_t n = flow_n_params(cfg);
+  const double bc1 = 1.0 - std::pow(0.9, (double)step);
+  const double bc2 = 1.0 - std::pow(0.999, (double)step);
+  hipLaunchKernelGGL(gbl::flow::k_flow_adam, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, ctx->stream,
+                     fl->params, fl->adam_m, fl->adam_v, (const float*)fl->grad, n, bc1, bc2, lr);
+  rc = check_launch(ctx, "gb_flow_adam");
+  if (rc) return rc;
+  return gb_flow_pack(ctx, cfg, fl);
+}
+
+extern "C" int gb_flow_train_step(gbl_ctx* ctx, const gbl_flow_config* cfg, const gbl_flow* fl, const double* u,
+                                  const int32_t* band, int64_t B, int64_t step, float lr) {
+  int rc = gb_flow_grad(ctx, cfg, fl, u, band, B);
+  if (rc) return rc;
+  return gb_flow_adam(ctx, cfg, fl, step, lr);
 }

@@ -27,7 +27,9 @@ SUPPORTED_N = (128, 256, 512, 1024)
 EXPORTED = ("gbl_create", "gbl_destroy", "gbl_set_stream", "gbl_last_error", "gbl_band", "gb_waveform",
             "gb_waveform_var", "gb_delta_loglike", "gb_delta_loglike_var", "gb_psd_eval", "gb_psd_loglike",
             "gb_scatter_add", "gb_make_noise", "gb_sweep_step", "gb_sweep_group", "gb_sweep_advance",
-            "gb_sweep_run", "gb_sweep_graph_create", "gb_graph_launch", "gb_graph_destroy")
+            "gb_sweep_run", "gb_sweep_graph_create", "gb_graph_launch", "gb_graph_destroy", "gb_flow_sizes",
+            "gb_flow_pack", "gb_flow_log_prob", "gb_flow_sample", "gb_flow_grad", "gb_flow_adam",
+            "gb_flow_train_step")
 
 GBL_MOVE_INMODEL, GBL_MOVE_RJ, GBL_MOVE_PT = 0, 1, 2
 
@@ -57,6 +59,17 @@ class SweepState(ctypes.Structure):
     """gbl_sweep_state (device pointers)"""
     _fields_ = [(n, ctypes.c_void_p) for n in ("u", "exists", "betas", "resid", "inv_psd", "group", "group_count",
                                               "stats", "sweep_counter")]
+
+
+class FlowConfig(ctypes.Structure):
+    """gbl_flow_config"""
+    _fields_ = [("n_emb", ctypes.c_int32), ("width", ctypes.c_int32), ("k_band0", ctypes.c_int64),
+                ("prior_lo", ctypes.c_double * 8), ("prior_hi", ctypes.c_double * 8)]
+
+
+class FlowState(ctypes.Structure):
+    """gbl_flow (device pointers)"""
+    _fields_ = [(n, ctypes.c_void_p) for n in ("params", "adam_m", "adam_v", "grad", "packed", "workspace", "loss")]
 
 
 _lib = None
@@ -91,6 +104,14 @@ def load_library(path: str = LIB_PATH):
         "gb_sweep_graph_create": [vp, ctypes.POINTER(SweepConfig), ctypes.POINTER(SweepState), i32,
                                   ctypes.POINTER(vp)],
         "gb_graph_launch": [vp],
+        "gb_flow_sizes": [ctypes.POINTER(FlowConfig), ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64)],
+        "gb_flow_pack": [vp, ctypes.POINTER(FlowConfig), ctypes.POINTER(FlowState)],
+        "gb_flow_log_prob": [vp, ctypes.POINTER(FlowConfig), ctypes.POINTER(FlowState), vp, vp, i64, vp],
+        "gb_flow_sample": [vp, ctypes.POINTER(FlowConfig), ctypes.POINTER(FlowState), vp, vp, i64, vp, vp],
+        "gb_flow_grad": [vp, ctypes.POINTER(FlowConfig), ctypes.POINTER(FlowState), vp, vp, i64],
+        "gb_flow_adam": [vp, ctypes.POINTER(FlowConfig), ctypes.POINTER(FlowState), i64, ctypes.c_float],
+        "gb_flow_train_step": [vp, ctypes.POINTER(FlowConfig), ctypes.POINTER(FlowState), vp, vp, i64, i64,
+                               ctypes.c_float],
         "gb_graph_destroy": [vp],
     }
     for name, args in sigs.items():
