@@ -227,6 +227,11 @@ typedef struct {
   int32_t* group_count;   /* [n_bands] */
   int64_t* stats;         /* [8] in-model proposed/accepted, births, deaths, swaps (proposed/accepted) */
   int64_t* sweep_counter; /* [1] current sweep index */
+  /* Optional (NULL = prior RJ proposal, no log-likelihood trace): */
+  double* prop_u;         /* [n_t][n_w][n_b][n_slot][8] birth candidates (read for empty slots) */
+  double* rj_logq;        /* [n_t][n_w][n_b][n_slot] ln q of the RJ proposal at the candidate
+                             (empty slot) or at the current source (occupied slot) */
+  double* cold_logl;      /* [n_w][n_b] cold chain's band log-likelihood, written by tempering */
 } gbl_sweep_state;
 
 typedef struct gbl_graph gbl_graph;
@@ -253,7 +258,6 @@ int gb_sweep_run(gbl_ctx* ctx, const gbl_sweep_config* cfg, const gbl_sweep_stat
 int gb_sweep_graph_create(gbl_ctx* ctx, const gbl_sweep_config* cfg, const gbl_sweep_state* st, int32_t n_sweeps,
                           gbl_graph** graph);
 int gb_graph_launch(gbl_graph* graph);
-int gb_graph_destroy(gbl_graph* graph);
 
 /* ---------------------------------------------------------------------------
  * Learned reversible-jump proposal: a conditional affine-coupling flow.
@@ -330,6 +334,33 @@ int gb_flow_adam(gbl_ctx* ctx, const gbl_flow_config* cfg, const gbl_flow* flow,
 /* gb_flow_grad followed by gb_flow_adam. */
 int gb_flow_train_step(gbl_ctx* ctx, const gbl_flow_config* cfg, const gbl_flow* flow, const double* u,
                        const int32_t* band, int64_t B, int64_t step, float lr);
+
+/* RJ with a proposal density q instead of the prior (appendix on the RJ
+ * proposal basis: the in-sampler flags and proposal density values are the
+ * RJ pass's inputs).  With st->prop_u and st->rj_logq set, a birth in an
+ * empty slot proposes prop_u and is accepted with
+ *   ln alpha = beta dlnL + ln p(theta) - ln q(theta),
+ * a death of an occupied slot with ln alpha = beta dlnL - ln p(theta) +
+ * ln q(theta) (p = the uniform prior density of the band's box; a candidate
+ * outside the prior, or a NaN ln q, is rejected).
+ *
+ * gb_sweep_rj_prepare fills prop_u and rj_logq for every slot from the flow:
+ * for empty slots it draws 8 standard normals (Box-Muller on the sweep's
+ * Philox stream: unit (t, w, b), move RJ, draws 2048 + 16 s + k) and pushes
+ * them through the flow of sub-band b; for occupied slots it evaluates the
+ * flow density at the current source.  fcfg must describe the sweep's own
+ * box (n_emb = n_bands, width = N, same k_band0 and prior bounds). */
+int gb_sweep_rj_prepare(gbl_ctx* ctx, const gbl_sweep_config* cfg, const gbl_sweep_state* st,
+                        const gbl_flow_config* fcfg, const gbl_flow* flow);
+
+/* gb_sweep_run / gb_sweep_graph_create with the flow as RJ proposal: every
+ * sweep runs gb_sweep_rj_prepare between the in-model and the RJ moves. */
+int gb_sweep_run_flow(gbl_ctx* ctx, const gbl_sweep_config* cfg, const gbl_sweep_state* st,
+                      const gbl_flow_config* fcfg, const gbl_flow* flow, int32_t n_sweeps);
+int gb_sweep_graph_create_flow(gbl_ctx* ctx, const gbl_sweep_config* cfg, const gbl_sweep_state* st,
+                               const gbl_flow_config* fcfg, const gbl_flow* flow, int32_t n_sweeps,
+                               gbl_graph** graph);
+int gb_graph_destroy(gbl_graph* graph);
 
 #ifdef __cplusplus
 }

@@ -87,7 +87,7 @@ def _load():
                                                    ctypes.c_uint64]),
             "gblo_pt_log_alpha": (ctypes.c_double, [ctypes.c_double] * 6),
             "gblo_sweep_step": (ctypes.c_int, [C, ctypes.POINTER(SweepConfig), ctypes.c_int, ctypes.c_int,
-                                               ctypes.c_int64, D, I32, D, D, D, D, I32, I64]),
+                                               ctypes.c_int64, D, I32, D, D, D, D, I32, I64, D, D, D]),
             "gblo_sweep_group": (ctypes.c_int, [ctypes.POINTER(SweepConfig), D, I32, D, I32]),
         }
         for name, (res, args) in sig.items():
@@ -273,10 +273,21 @@ class SweepState:
         self.stats = np.zeros(8, np.int64)
 
 
-def sweep_step(orc: "Oracle", sc: SweepConfig, st: SweepState, move: int, parity: int, sweep: int):
+def sweep_step(orc: "Oracle", sc: SweepConfig, st: SweepState, move: int, parity: int, sweep: int,
+               prop_u=None, rj_logq=None, cold_logl=None):
+    """One move over the bands of one parity.  prop_u [n_t][n_w][n_b][n_slot][8]
+    and rj_logq [n_t][n_w][n_b][n_slot] give an RJ proposal (None: the prior);
+    cold_logl [n_w][n_b] receives the cold chain's band logL after tempering."""
+    pu_a = np.ascontiguousarray(prop_u, np.float64) if prop_u is not None else None
+    lq_a = np.ascontiguousarray(rj_logq, np.float64) if rj_logq is not None else None
+    pu = _d(pu_a) if pu_a is not None else None
+    lq = _d(lq_a) if lq_a is not None else None
+    if cold_logl is not None:
+        assert cold_logl.dtype == np.float64 and cold_logl.flags.c_contiguous
     rc = orc.lib.gblo_sweep_step(ctypes.byref(orc.cfg), ctypes.byref(sc), int(move), int(parity), int(sweep),
                                  _d(st.u), _i32(st.exists), _d(st.betas), _d(st.resid.view(np.float64)),
-                                 _d(st.inv_psd), _d(st.group), _i32(st.group_count), _i64(st.stats))
+                                 _d(st.inv_psd), _d(st.group), _i32(st.group_count), _i64(st.stats), pu, lq,
+                                 _d(cold_logl) if cold_logl is not None else None)
     _check(rc, "sweep_step")
 
 

@@ -756,9 +756,24 @@ static int stretch_propose(const gblo_sweep_config* sc, const double* u, const d
 #define UIDX(sc, t, w, b, s) ((((int64_t)(t) * (sc)->n_walkers + (w)) * (sc)->n_bands + (b)) * (sc)->n_slots + (s))
 
 /* Alg. gb1 for one (t, w, b): in-model (move 0) or RJ (move 1) band loop. */
+/* ln of the prior box volume of band b in sampling coordinates (the uniform
+ * prior density is its inverse) */
+static double log_box_volume(const gblo_config* cfg, const gblo_sweep_config* sc, int b) {
+  double flo, fhi, v = 0.0;
+  band_f0_range(cfg, sc, b, &flo, &fhi);
+  for (int k = 0; k < 8; k++) {
+    double w = sc->prior_hi[k] - sc->prior_lo[k];
+    if (k == 1) w = fhi - flo;
+    else if (PERIOD[k] > 0) w = PERIOD[k];
+    v += log(w);
+  }
+  return v;
+}
+
 static void band_loop(const gblo_config* cfg, const gblo_sweep_config* sc, int move, int64_t sweep, int t, int w,
                       int b, double* u, int32_t* exists, const double* betas, double* resid, const double* inv_psd,
-                      const double* group, const int32_t* group_count, int64_t* stats) {
+                      const double* group, const int32_t* group_count, int64_t* stats, const double* prop_u,
+                      const double* rj_logq) {
   int64_t k_min, nb;
   gblo_band(cfg, &k_min, &nb);
   int par = b & 1;
@@ -834,18 +849,34 @@ static void band_loop(const gblo_config* cfg, const gblo_sweep_config* sc, int m
       int64_t ui = UIDX(sc, t, w, b, s);
       double* us = u + 8 * ui;
       if (exists[ui]) {
-        /* death: new template zero; prior and proposal densities cancel (q = p) */
+        /* death: new template zero; with the prior proposal (q = p) the densities
+         * cancel, otherwise ln alpha gains ln q(theta) - ln p(theta) */
         stats[4]++;
         double dl = window_dlogl(cfg, k_min, nb, &win, ipsd, us, NULL);
-        if (log(r_acc) < beta * dl) {
+        double lpq = rj_logq ? rj_logq[ui] + log_box_volume(cfg, sc, b) : 0.0;
+        if (log(r_acc) < beta * dl + lpq) {
           window_add_template(cfg, k_min, nb, &win, us, 1.0);
           if (t == 0) window_add_template(cfg, k_min, nb, &dsum, us, 1.0);
           exists[ui] = 0;
           stats[5]++;
         }
       } else {
-        /* birth from the prior */
         stats[2]++;
+        if (prop_u) {
+          /* birth from the given proposal: ln alpha gains ln p(theta) - ln q(theta) */
+          for (int k = 0; k < 8; k++) un[k] = prop_u[8 * ui + k];
+          if (!in_prior(cfg, sc, b, un)) continue;
+          double dl = window_dlogl(cfg, k_min, nb, &win, ipsd, NULL, un);
+          if (log(r_acc) < beta * dl - log_box_volume(cfg, sc, b) - rj_logq[ui]) {
+            window_add_template(cfg, k_min, nb, &win, un, -1.0);
+            if (t == 0) window_add_template(cfg, k_min, nb, &dsum, un, -1.0);
+            for (int k = 0; k < 8; k++) us[k] = un[k];
+            exists[ui] = 1;
+            stats[3]++;
+          }
+          continue;
+        }
+        /* birth from the prior */
         for (int k = 0; k < 8; k++) {
           double r = rng_uniform(sc->seed, sweep, move, unit, base + 1 + k);
           double lo = sc->prior_lo[k], hi = sc->prior_hi[k];
@@ -950,7 +981,8 @@ double gblo_pt_log_alpha(double bI, double bII, double lnL_im, double lnL_in, do
 /* Alg. gb2 for band b and ensemble index i: swaps from the hottest pair down,
  * accepted with the residual-aware ratio (eq. temp-final). */
 static void pt_chain(const gblo_config* cfg, const gblo_sweep_config* sc, int64_t sweep, int b, int i, double* u,
-                     int32_t* exists, const double* betas, double* resid, const double* inv_psd, int64_t* stats) {
+                     int32_t* exists, const double* betas, double* resid, const double* inv_psd, int64_t* stats,
+                     double* cold_logl) {
   int64_t k_min, nb;
   gblo_band(cfg, &k_min, &nb);
   int nt = sc->n_temps;
@@ -994,6 +1026,8 @@ static void pt_chain(const gblo_config* cfg, const gblo_sweep_config* sc, int64_
       Lc[t - 1] = L2;
     }
   }
+  /* band log-likelihood of the cold chain of walker w_0 after the swaps */
+  if (cold_logl) cold_logl[(int64_t)wt[0] * sc->n_bands + b] = Lc[0];
   free(wt);
   free(perm);
   free(Lc);
@@ -1001,18 +1035,26 @@ static void pt_chain(const gblo_config* cfg, const gblo_sweep_config* sc, int64_
 
 /* One step of the sweep over all bands of one parity:
  * move 0 in-model, 1 reversible jump (Alg. gb1), 2 tempering (Alg. gb2). */
+/* prop_u / rj_logq (both NULL: prior RJ proposal): per slot, the birth
+ * candidate (read for empty slots) and ln q of the proposal density at the
+ * candidate (empty slot) or at the current source (occupied slot).
+ * cold_logl [n_w][n_b] (may be NULL): tempering writes the cold chain's band
+ * log-likelihood after the swaps. */
 int gblo_sweep_step(const gblo_config* cfg, const gblo_sweep_config* sc, int move, int parity, int64_t sweep,
                     double* u, int32_t* exists, const double* betas, double* resid, const double* inv_psd,
-                    const double* group, const int32_t* group_count, int64_t* stats) {
+                    const double* group, const int32_t* group_count, int64_t* stats, const double* prop_u,
+                    const double* rj_logq, double* cold_logl) {
   if (sc->n_slots > 64 || sc->n_slots < 1) return -1;
+  if ((prop_u == NULL) != (rj_logq == NULL)) return -1;
   for (int b = parity; b < sc->n_bands; b += 2) {
     if (move == MOVE_PT) {
       for (int i = 0; i < sc->n_walkers; i++)
-        pt_chain(cfg, sc, sweep, b, i, u, exists, betas, resid, inv_psd, stats);
+        pt_chain(cfg, sc, sweep, b, i, u, exists, betas, resid, inv_psd, stats, cold_logl);
     } else {
       for (int t = 0; t < sc->n_temps; t++)
         for (int w = 0; w < sc->n_walkers; w++)
-          band_loop(cfg, sc, move, sweep, t, w, b, u, exists, betas, resid, inv_psd, group, group_count, stats);
+          band_loop(cfg, sc, move, sweep, t, w, b, u, exists, betas, resid, inv_psd, group, group_count, stats,
+                    prop_u, rj_logq);
     }
   }
   return 0;

@@ -445,6 +445,8 @@ static int sweep_check(gbl_ctx* ctx, const gbl_sweep_config* c, const gbl_sweep_
   if (!st->u || !st->exists || !st->betas || !st->resid || !st->inv_psd || !st->group || !st->group_count ||
       !st->stats || !st->sweep_counter)
     return fail(ctx, GBL_EINVAL, "sweep: null state pointer%s");
+  if ((st->prop_u == nullptr) != (st->rj_logq == nullptr))
+    return fail(ctx, GBL_EINVAL, "sweep: prop_u and rj_logq must be given together%s");
   if (ctx->cfg.precision != GBL_FP64) return fail(ctx, GBL_EUNSUPPORTED, "sweep: FP64 contexts only%s");
   return GBL_OK;
 }
@@ -473,6 +475,9 @@ static gbl::SweepArgs sweep_args(const gbl_sweep_config* c, const gbl_sweep_stat
   a.group_count = st->group_count;
   a.stats = (unsigned long long*)st->stats;
   a.sweep_ctr = st->sweep_counter;
+  a.prop_u = st->prop_u;
+  a.rj_logq = st->rj_logq;
+  a.cold_logl = st->cold_logl;
   return a;
 }
 
@@ -525,22 +530,35 @@ extern "C" int gb_sweep_advance(gbl_ctx* ctx, const gbl_sweep_state* st) {
   return check_launch(ctx, "gb_sweep_advance");
 }
 
+static int rj_prepare(gbl_ctx* ctx, const gbl_sweep_config* cfg, const gbl_sweep_state* st,
+                      const gbl_flow_config* fcfg, const gbl_flow* fl);
+
+static int sweep_run_impl(gbl_ctx* ctx, const gbl_sweep_config* cfg, const gbl_sweep_state* st,
+                          const gbl_flow_config* fcfg, const gbl_flow* fl, int32_t n_sweeps) {
+  const gbl::SweepArgs a = sweep_args(cfg, st);
+  for (int i = 0; i < n_sweeps; i++) {
+    if (cfg->group_every > 0)
+      hipLaunchKernelGGL(gbl::k_sweep_group, dim3((unsigned)cfg->n_bands), dim3(256), 0, ctx->stream, a,
+                         cfg->group_every);
+    for (int move = GBL_MOVE_INMODEL; move <= GBL_MOVE_PT; move++) {
+      if (move == GBL_MOVE_RJ && fl) {
+        int rc = rj_prepare(ctx, cfg, st, fcfg, fl);
+        if (rc) return rc;
+      }
+      for (int parity = 1; parity >= 0; parity--) sweep_step(ctx, cfg, a, move, parity);
+    }
+    hipLaunchKernelGGL(gbl::k_sweep_advance, dim3(1), dim3(64), 0, ctx->stream, st->sweep_counter);
+  }
+  return check_launch(ctx, "gb_sweep_run");
+}
+
 extern "C" int gb_sweep_run(gbl_ctx* ctx, const gbl_sweep_config* cfg, const gbl_sweep_state* st,
                             int32_t n_sweeps) {
   if (!ctx) return GBL_EINVAL;
   int rc = sweep_check(ctx, cfg, st);
   if (rc) return rc;
   if (n_sweeps < 0) return fail(ctx, GBL_EINVAL, "gb_sweep_run: n_sweeps < 0%s");
-  const gbl::SweepArgs a = sweep_args(cfg, st);
-  for (int i = 0; i < n_sweeps; i++) {
-    if (cfg->group_every > 0)
-      hipLaunchKernelGGL(gbl::k_sweep_group, dim3((unsigned)cfg->n_bands), dim3(256), 0, ctx->stream, a,
-                         cfg->group_every);
-    for (int move = GBL_MOVE_INMODEL; move <= GBL_MOVE_PT; move++)
-      for (int parity = 1; parity >= 0; parity--) sweep_step(ctx, cfg, a, move, parity);
-    hipLaunchKernelGGL(gbl::k_sweep_advance, dim3(1), dim3(64), 0, ctx->stream, st->sweep_counter);
-  }
-  return check_launch(ctx, "gb_sweep_run");
+  return sweep_run_impl(ctx, cfg, st, nullptr, nullptr, n_sweeps);
 }
 
 struct gbl_graph {
@@ -549,8 +567,8 @@ struct gbl_graph {
   hipStream_t stream;
 };
 
-extern "C" int gb_sweep_graph_create(gbl_ctx* ctx, const gbl_sweep_config* cfg, const gbl_sweep_state* st,
-                                     int32_t n_sweeps, gbl_graph** out) {
+static int graph_create_impl(gbl_ctx* ctx, const gbl_sweep_config* cfg, const gbl_sweep_state* st,
+                             const gbl_flow_config* fcfg, const gbl_flow* fl, int32_t n_sweeps, gbl_graph** out) {
   if (!ctx || !out) return GBL_EINVAL;
   *out = nullptr;
   int rc = sweep_check(ctx, cfg, st);
@@ -563,7 +581,7 @@ extern "C" int gb_sweep_graph_create(gbl_ctx* ctx, const gbl_sweep_config* cfg, 
     delete gr;
     return fail(ctx, GBL_EHIP, "gb_sweep_graph_create: begin capture failed%s");
   }
-  int rr = gb_sweep_run(ctx, cfg, st, n_sweeps);
+  int rr = sweep_run_impl(ctx, cfg, st, fcfg, fl, n_sweeps);
   hipError_t e = hipStreamEndCapture(ctx->stream, &gr->graph);
   if (rr != GBL_OK || e != hipSuccess) {
     if (e == hipSuccess) (void)hipGraphDestroy(gr->graph);
@@ -577,6 +595,11 @@ extern "C" int gb_sweep_graph_create(gbl_ctx* ctx, const gbl_sweep_config* cfg, 
   }
   *out = gr;
   return GBL_OK;
+}
+
+extern "C" int gb_sweep_graph_create(gbl_ctx* ctx, const gbl_sweep_config* cfg, const gbl_sweep_state* st,
+                                     int32_t n_sweeps, gbl_graph** out) {
+  return graph_create_impl(ctx, cfg, st, nullptr, nullptr, n_sweeps, out);
 }
 
 extern "C" int gb_graph_launch(gbl_graph* gr) {
@@ -636,6 +659,10 @@ static gbl::flow::FlowArgs flow_args(gbl_ctx* ctx, const gbl_flow_config* c, con
     a.lo[i] = c->prior_lo[i];
     a.hi[i] = c->prior_hi[i];
   }
+  a.band_div = 1;
+  a.band_mod = 1;
+  a.mask_want = 0;
+  a.mask = nullptr;
   return a;
 }
 
@@ -725,4 +752,62 @@ extern "C" int gb_flow_train_step(gbl_ctx* ctx, const gbl_flow_config* cfg, cons
   int rc = gb_flow_grad(ctx, cfg, fl, u, band, B);
   if (rc) return rc;
   return gb_flow_adam(ctx, cfg, fl, step, lr);
+}
+
+// ---------------------------------------------------------------------------
+// flow as the RJ proposal of the sweep
+// ---------------------------------------------------------------------------
+static int rj_prepare(gbl_ctx* ctx, const gbl_sweep_config* cfg, const gbl_sweep_state* st,
+                      const gbl_flow_config* fcfg, const gbl_flow* fl) {
+  int rc = flow_check(ctx, fcfg, fl);
+  if (rc) return rc;
+  if (!st->prop_u || !st->rj_logq) return fail(ctx, GBL_EINVAL, "gb_sweep_rj_prepare: prop_u / rj_logq not set%s");
+  if (fcfg->n_emb != cfg->n_bands || fcfg->width != cfg->N || fcfg->k_band0 != cfg->k_band0)
+    return fail(ctx, GBL_EINVAL, "gb_sweep_rj_prepare: flow box differs from the sweep's sub-bands%s");
+  const int dims[4] = {0, 2, 4, 7};
+  for (int i : dims)
+    if (fcfg->prior_lo[i] != cfg->prior_lo[i] || fcfg->prior_hi[i] != cfg->prior_hi[i])
+      return fail(ctx, GBL_EINVAL, "gb_sweep_rj_prepare: flow box differs from the sweep's prior%s");
+  const gbl::SweepArgs a = sweep_args(cfg, st);
+  const int64_t n = (int64_t)cfg->n_temps * cfg->n_walkers * cfg->n_bands * cfg->n_slots;
+  hipLaunchKernelGGL(gbl::k_rj_normals, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, ctx->stream, a, st->prop_u);
+  gbl::flow::FlowArgs fa = flow_args(ctx, fcfg, fl);
+  fa.band_div = cfg->n_slots;
+  fa.band_mod = cfg->n_bands;
+  fa.mask = st->exists;
+  fa.mask_want = 0;  // empty slots: candidates from the normals, in place
+  hipLaunchKernelGGL(gbl::flow::k_flow_apply<true>, dim3(flow_grid(n)), dim3(256), 0, ctx->stream, fa,
+                     (const double*)st->prop_u, (const int32_t*)nullptr, n, st->prop_u, st->rj_logq);
+  fa.mask_want = 1;  // occupied slots: density at the current source
+  hipLaunchKernelGGL(gbl::flow::k_flow_apply<false>, dim3(flow_grid(n)), dim3(256), 0, ctx->stream, fa,
+                     (const double*)st->u, (const int32_t*)nullptr, n, (double*)nullptr, st->rj_logq);
+  return check_launch(ctx, "gb_sweep_rj_prepare");
+}
+
+extern "C" int gb_sweep_rj_prepare(gbl_ctx* ctx, const gbl_sweep_config* cfg, const gbl_sweep_state* st,
+                                   const gbl_flow_config* fcfg, const gbl_flow* fl) {
+  if (!ctx) return GBL_EINVAL;
+  int rc = sweep_check(ctx, cfg, st);
+  if (rc) return rc;
+  return rj_prepare(ctx, cfg, st, fcfg, fl);
+}
+
+extern "C" int gb_sweep_run_flow(gbl_ctx* ctx, const gbl_sweep_config* cfg, const gbl_sweep_state* st,
+                                 const gbl_flow_config* fcfg, const gbl_flow* fl, int32_t n_sweeps) {
+  if (!ctx) return GBL_EINVAL;
+  int rc = sweep_check(ctx, cfg, st);
+  if (rc) return rc;
+  if (n_sweeps < 0) return fail(ctx, GBL_EINVAL, "gb_sweep_run_flow: n_sweeps < 0%s");
+  rc = flow_check(ctx, fcfg, fl);
+  if (rc) return rc;
+  return sweep_run_impl(ctx, cfg, st, fcfg, fl, n_sweeps);
+}
+
+extern "C" int gb_sweep_graph_create_flow(gbl_ctx* ctx, const gbl_sweep_config* cfg, const gbl_sweep_state* st,
+                                          const gbl_flow_config* fcfg, const gbl_flow* fl, int32_t n_sweeps,
+                                          gbl_graph** out) {
+  if (!ctx || !out) return GBL_EINVAL;
+  int rc = flow_check(ctx, fcfg, fl);
+  if (rc) return rc;
+  return graph_create_impl(ctx, cfg, st, fcfg, fl, n_sweeps, out);
 }

@@ -57,6 +57,12 @@ struct FlowArgs {
   int64_t k_band0;
   double T;
   double lo[8], hi[8];      // prior box (f0 and the periodic angles are set per band)
+  // sample i's band when no band array is given: (i / band_div) % band_mod
+  int64_t band_div;
+  int32_t band_mod;
+  // with a mask, sample i is processed only if (mask[i] != 0) == mask_want
+  int32_t mask_want;
+  const int32_t* mask;
 };
 
 __device__ __forceinline__ uint32_t bf16_bits(float f) {
@@ -229,16 +235,18 @@ __device__ __forceinline__ void kept_of(const double* x, int parity, double* xc)
 // (kSample = true).  One wave per 16 samples; lanes with g = 0 own the state.
 // ---------------------------------------------------------------------------
 template <bool kSample>
-__global__ __launch_bounds__(256) void k_flow_apply(FlowArgs fa, const double* __restrict__ in,
-                                                   const int32_t* __restrict__ band, int64_t B,
-                                                   double* __restrict__ u_out, double* __restrict__ logq) {
+// `in` and `u_out` may be the same buffer (each sample is read, then written,
+// by the same lane).
+__global__ __launch_bounds__(256) void k_flow_apply(FlowArgs fa, const double* in, const int32_t* __restrict__ band,
+                                                   int64_t B, double* u_out, double* __restrict__ logq) {
   const int lane = threadIdx.x & 63;
   const int c = lane & 15, g = lane >> 4;
   const int64_t n_tiles = (B + 15) / 16;
   for (int64_t tile = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); tile < n_tiles; tile += (int64_t)gridDim.x * 4) {
     const int64_t idx = tile * 16 + c;
-    const bool inb = idx < B;
-    int b = inb ? band[idx] : 0;
+    bool inb = idx < B;
+    if (inb && fa.mask && ((fa.mask[idx] != 0) != (fa.mask_want != 0))) inb = false;  // not ours: no output
+    int b = inb ? (band ? band[idx] : (int)((idx / fa.band_div) % fa.band_mod)) : 0;
     bool valid = inb && b >= 0 && b < fa.n_emb;
     if (!valid) b = 0;
     double lo[8], hi[8];

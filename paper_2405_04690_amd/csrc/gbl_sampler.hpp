@@ -71,6 +71,9 @@ struct SweepArgs {
   int32_t* group_count;
   unsigned long long* stats;
   const int64_t* sweep_ctr;
+  const double* prop_u;   // RJ birth candidates (nullptr: prior draws)
+  const double* rj_logq;  // ln q per slot (with prop_u)
+  double* cold_logl;      // [n_w][n_b] cold-chain band logL after tempering (optional)
 };
 
 __device__ __forceinline__ int64_t uidx(const SweepArgs& a, int t, int w, int b, int s) {
@@ -90,6 +93,22 @@ template <int N>
 __device__ __forceinline__ void band_f0_range(const Geo& g, const SweepArgs& a, int b, double& lo, double& hi) {
   lo = ((double)a.k_band0 + ((double)b - 0.5) * N) / g.T;
   hi = ((double)a.k_band0 + ((double)b + 1.5) * N) / g.T;
+}
+
+// ln of the prior box volume of band b in sampling coordinates
+template <int N>
+__device__ __forceinline__ double log_box_volume(const Geo& g, const SweepArgs& a, int b) {
+  double flo, fhi, v = 0.0;
+  band_f0_range<N>(g, a, b, flo, fhi);
+  for (int k = 0; k < 8; k++) {
+    double w = a.hi[k] - a.lo[k];
+    if (k == 1)
+      w = fhi - flo;
+    else if (period_of(k) > 0)
+      w = period_of(k);
+    v += log(w);
+  }
+  return v;
 }
 
 template <int N>
@@ -407,13 +426,16 @@ __global__ __launch_bounds__(block_threads<N>()) void k_sweep_band(Geo g, WaveTa
     __syncthreads();
     double flo, fhi;
     band_f0_range<N>(g, a, b, flo, fhi);
+    const double lvol = a.prop_u ? log_box_volume<N>(g, a, b) : 0.0;
     for (int i = 0; i < S; i++) {
       const int s = sm.order[i];
       const uint64_t base = 64 + 16 * (uint64_t)i;
       const double r_acc = rng_uniform(a.seed, sweep, move, unit, base);
+      const int64_t ui = uidx(a, t, w, b, s);
       double* us = sm.su[s];
       if (sm.ex[s]) {
-        // death: the new template is zero; q = p, so only the likelihood enters
+        // death: the new template is zero; with the prior proposal (q = p) only
+        // the likelihood enters, otherwise ln q - ln p as well
         n_dprop++;
         if (tid < 8) sm.u_old[tid] = us[tid];
         __syncthreads();
@@ -421,10 +443,27 @@ __global__ __launch_bounds__(block_threads<N>()) void k_sweep_band(Geo g, WaveTa
         band_store_rwin<N>(g, tb, sm);
         const int64_t kr = sm.src.q - N / 2;
         const double dl = band_dlogl<N>(g, tb, sm, k0w, false, 0, true, kr);
-        if (log(r_acc) < beta * dl) {
+        const double lpq = a.prop_u ? a.rj_logq[ui] + lvol : 0.0;
+        if (log(r_acc) < beta * dl + lpq) {
           band_add_rwin<N>(g, sm, k0w, kr, 1.0, own);
           if (tid == 0) sm.ex[s] = 0;
           n_dacc++;
+        }
+      } else if (a.prop_u) {
+        // birth from the given proposal: ln p - ln q enters
+        n_bprop++;
+        if (tid < 8) sm.u_new[tid] = a.prop_u[8 * ui + tid];
+        __syncthreads();
+        if (in_prior<N>(g, a, b, sm.u_new)) {
+          band_template<N>(g, tb, sm.u_new, sm);
+          const int64_t ka = sm.src.q - N / 2;
+          const double dl = band_dlogl<N>(g, tb, sm, k0w, true, ka, false, 0);
+          if (log(r_acc) < beta * dl - lvol - a.rj_logq[ui]) {
+            band_add_template<N>(g, tb, sm, k0w, -1.0, own);
+            if (tid < 8) us[tid] = sm.u_new[tid];
+            if (tid == 0) sm.ex[s] = 1;
+            n_bacc++;
+          }
         }
       } else {
         // birth drawn from the prior
@@ -578,6 +617,7 @@ __global__ __launch_bounds__(block_threads<N>()) void k_sweep_pt(Geo g, WaveTabl
   if (tid == 0) {
     atomicAdd(&a.stats[6], n_prop);
     if (n_acc) atomicAdd(&a.stats[7], n_acc);
+    if (a.cold_logl) a.cold_logl[(int64_t)wt[0] * a.n_b + b] = Lc[0];
   }
 }
 
@@ -631,6 +671,27 @@ __global__ __launch_bounds__(256) void k_sweep_group(SweepArgs a, int every) {
   }
   __syncthreads();
   if (threadIdx.x == 0) a.group_count[b] = count;
+}
+
+// standard normals for the flow's birth candidates of the empty slots:
+// Box-Muller on the sweep's stream, unit (t, w, b), move RJ, draws 2048 + 16 s + k
+__global__ void k_rj_normals(SweepArgs a, double* z) {
+  const int64_t n = (int64_t)a.n_t * a.n_w * a.n_b * a.n_slot;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n || a.exists[i]) return;
+  const int s = (int)(i % a.n_slot);
+  const uint64_t unit = (uint64_t)(i / a.n_slot);
+  const int64_t sweep = *a.sweep_ctr;
+  for (int p = 0; p < 4; p++) {
+    const uint64_t d = 2048 + 16 * (uint64_t)s + 2 * p;
+    const double u1 = rng_uniform(a.seed, sweep, kMoveRJ, unit, d);
+    const double u2 = rng_uniform(a.seed, sweep, kMoveRJ, unit, d + 1);
+    const double r = sqrt(-2.0 * log(u1));
+    double sn, cs;
+    sincospi(2.0 * u2, &sn, &cs);
+    z[8 * i + 2 * p] = r * cs;
+    z[8 * i + 2 * p + 1] = r * sn;
+  }
 }
 
 __global__ void k_sweep_advance(int64_t* sweep_ctr) {

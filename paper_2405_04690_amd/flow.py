@@ -9,9 +9,27 @@ import torch
 
 from .gbl import Context, FlowConfig, FlowState, load_library
 
-__all__ = ["Flow", "FlowConfig", "flow_config", "LAYER_PARAMS"]
+__all__ = ["Flow", "FlowConfig", "flow_config", "init_params", "LAYER_PARAMS"]
 
 LAYER_PARAMS = 20232
+N_LAYERS, HIDDEN, EMB, COND_IN, OUT = 6, 128, 16, 20, 8
+
+
+def init_params(seed: int, n_emb: int) -> np.ndarray:
+    """Seeded starting weights in the layout of include/gbl.h: W1, W2 uniform in
+    +-1/sqrt(fan_in), W3 and all biases zero (the flow starts as the identity
+    map, i.e. as a logit-normal proposal), embedding N(0, 1)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(N_LAYERS):
+        out.append(rng.uniform(-1, 1, HIDDEN * COND_IN) / np.sqrt(COND_IN))
+        out.append(np.zeros(HIDDEN))
+        out.append(rng.uniform(-1, 1, HIDDEN * HIDDEN) / np.sqrt(HIDDEN))
+        out.append(np.zeros(HIDDEN))
+        out.append(np.zeros(OUT * HIDDEN))
+        out.append(np.zeros(OUT))
+    out.append(rng.standard_normal(EMB * n_emb))
+    return np.concatenate(out).astype(np.float32)
 
 
 def flow_config(n_emb: int, width: int, k_band0: int, prior_lo, prior_hi) -> FlowConfig:

@@ -29,7 +29,7 @@ EXPORTED = ("gbl_create", "gbl_destroy", "gbl_set_stream", "gbl_last_error", "gb
             "gb_scatter_add", "gb_make_noise", "gb_sweep_step", "gb_sweep_group", "gb_sweep_advance",
             "gb_sweep_run", "gb_sweep_graph_create", "gb_graph_launch", "gb_graph_destroy", "gb_flow_sizes",
             "gb_flow_pack", "gb_flow_log_prob", "gb_flow_sample", "gb_flow_grad", "gb_flow_adam",
-            "gb_flow_train_step")
+            "gb_flow_train_step", "gb_sweep_rj_prepare", "gb_sweep_run_flow", "gb_sweep_graph_create_flow")
 
 GBL_MOVE_INMODEL, GBL_MOVE_RJ, GBL_MOVE_PT = 0, 1, 2
 
@@ -58,7 +58,7 @@ class SweepConfig(ctypes.Structure):
 class SweepState(ctypes.Structure):
     """gbl_sweep_state (device pointers)"""
     _fields_ = [(n, ctypes.c_void_p) for n in ("u", "exists", "betas", "resid", "inv_psd", "group", "group_count",
-                                              "stats", "sweep_counter")]
+                                              "stats", "sweep_counter", "prop_u", "rj_logq", "cold_logl")]
 
 
 class FlowConfig(ctypes.Structure):
@@ -112,6 +112,13 @@ def load_library(path: str = LIB_PATH):
         "gb_flow_adam": [vp, ctypes.POINTER(FlowConfig), ctypes.POINTER(FlowState), i64, ctypes.c_float],
         "gb_flow_train_step": [vp, ctypes.POINTER(FlowConfig), ctypes.POINTER(FlowState), vp, vp, i64, i64,
                                ctypes.c_float],
+        "gb_sweep_rj_prepare": [vp, ctypes.POINTER(SweepConfig), ctypes.POINTER(SweepState),
+                                ctypes.POINTER(FlowConfig), ctypes.POINTER(FlowState)],
+        "gb_sweep_run_flow": [vp, ctypes.POINTER(SweepConfig), ctypes.POINTER(SweepState),
+                              ctypes.POINTER(FlowConfig), ctypes.POINTER(FlowState), i32],
+        "gb_sweep_graph_create_flow": [vp, ctypes.POINTER(SweepConfig), ctypes.POINTER(SweepState),
+                                       ctypes.POINTER(FlowConfig), ctypes.POINTER(FlowState), i32,
+                                       ctypes.POINTER(vp)],
         "gb_graph_destroy": [vp],
     }
     for name, args in sigs.items():

@@ -166,3 +166,19 @@ def band_slots(sources: np.ndarray, T: float, k_band0: int, width: int, n_bands:
         ex[bb, fill[bb]] = 1
         fill[bb] += 1
     return u, ex, dropped
+
+
+def band_sources(seed: int, n_bands: int, per_band: int, T: float, k_band0: int, width: int) -> np.ndarray:
+    """per_band sources in each sub-band b (carrier bin inside [k_band0 + (b + 0.2) W,
+    k_band0 + (b + 0.8) W)), unit amplitude, other parameters as in draw_sources
+    (fdot = 0); rows ordered band-major."""
+    rng = np.random.default_rng(seed)
+    n = n_bands * per_band
+    b = np.repeat(np.arange(n_bands), per_band)
+    f0 = (k_band0 + (b + rng.uniform(0.2, 0.8, n)) * width) / T
+    lam = rng.uniform(0.0, 2 * np.pi, n)
+    sinb = rng.uniform(-1.0, 1.0, n)
+    psi = rng.uniform(0.0, np.pi, n)
+    cosi = rng.uniform(-1.0, 1.0, n)
+    phi0 = rng.uniform(0.0, 2 * np.pi, n)
+    return np.stack([np.ones(n), f0, np.zeros(n), phi0, np.arccos(cosi), psi, lam, np.arcsin(sinb)], axis=1)

@@ -1,0 +1,192 @@
+"""Learned versus prior RJ proposal on one sampler problem: the comparison of
+RJ acceptance and effective samples per second (Sec. 4 "Online updating of RJ
+sampling distributions"; the flow replaces the paper's fitted mixtures).
+
+Problem: sub-bands of width N from bin k_band0, each holding one loud and one
+near-threshold injected source in stationary Gaussian noise; every chain
+starts from the injections.  The sampler first runs with prior RJ draws and
+collects cold-chain samples; the flow is trained on them with the library's
+own training kernels; then, from the same saved state, the same number of
+sweeps runs once with prior RJ draws and once with the flow as the RJ
+proposal, recording per sweep the cold chain's source count and band
+log-likelihood per (walker, band).  Everything runs through the C ABI; only
+the bookkeeping (trace copies, ESS) is host-side.
+"""
+from __future__ import annotations
+
+import time
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import ess as ess_mod
+from . import inputs
+from .flow import Flow, flow_config
+from .gbl import Context
+from .sampler import Sweep, make_config
+
+PRIOR_LO = (-24.0, 0.0, -1e-17, 0.0, -1.0, 0.0, 0.0, -1.0)
+PRIOR_HI = (-20.0, 0.0, 1e-17, 0.0, 1.0, 0.0, 0.0, 1.0)
+
+
+@dataclass
+class Problem:
+    ctx: Context
+    sweep: Sweep
+    fcfg: object
+    sources: np.ndarray
+    snr: np.ndarray
+
+
+def _to_u(p):
+    return np.stack([np.log10(p[:, 0]), p[:, 1], p[:, 2], p[:, 3], np.cos(p[:, 4]), p[:, 5], p[:, 6],
+                     np.sin(p[:, 7])], axis=1)
+
+
+def _physical(u):
+    p = u.clone()
+    p[:, 0] = torch.pow(10.0, u[:, 0])
+    p[:, 4] = torch.acos(u[:, 4])
+    p[:, 7] = torch.asin(u[:, 7])
+    return p
+
+
+def build(cfg=inputs.TINY, N=128, n_temps=4, n_walkers=32, n_bands=8, n_slots=6, snr=(20.0, 7.0), seed=60,
+          f_start=3e-3, stream=None) -> Problem:
+    dev = torch.device("cuda", torch.cuda.current_device())
+    ctx = Context(T=cfg.T, dt=cfg.dt, L=cfg.L, f_lo=cfg.f_lo, f_hi=cfg.f_hi, device=dev, stream=stream)
+    T = cfg.T
+    k_band0 = int(f_start * T)
+    src = inputs.band_sources(seed, n_bands, len(snr), T, k_band0, N)
+    noise = torch.tensor([[cfg.sqrt_oms, cfg.sqrt_acc, cfg.sqrt_oms, cfg.sqrt_acc]], dtype=torch.float64, device=dev)
+    S = ctx.gb_psd_eval(noise)
+    invS = ctx.gb_psd_eval(noise, inverse=True)
+    # amplitude for the target SNR: a birth into noise-free data has dlnL = -SNR^2 / 2
+    zero = torch.zeros((1, 2, ctx.n_bins), dtype=torch.complex128, device=dev)
+    unit = torch.from_numpy(src).to(dev)
+    none = unit.clone()
+    none[:, 0] = 0.0
+    dl = ctx.gb_delta_loglike(zero, invS, none, unit, N, psd_inverse=True)
+    snr_unit = torch.sqrt(-2.0 * dl).cpu().numpy()
+    target = np.tile(np.asarray(snr, dtype=np.float64), n_bands)
+    src[:, 0] = target / snr_unit
+    d = ctx.gb_make_noise(S, torch.from_numpy(inputs.complex_normals(seed + 1, (1, 2, ctx.n_bins))).to(dev))
+    ctx.gb_scatter_add(torch.from_numpy(src).to(dev), N, 1.0, d)
+    sc = make_config(n_temps, n_walkers, n_bands, n_slots, N, k_band0, n_prop=20, n_friends=8, group_every=10,
+                     seed=seed + 2, prior_lo=PRIOR_LO, prior_hi=PRIOR_HI)
+    sw = Sweep(ctx, sc)
+    u0 = np.zeros((n_bands, n_slots, 8))
+    e0 = np.zeros((n_bands, n_slots), np.int32)
+    us = _to_u(src)
+    for b in range(n_bands):
+        for j in range(len(snr)):
+            u0[b, j] = us[b * len(snr) + j]
+            e0[b, j] = 1
+    sw.u.copy_(torch.from_numpy(u0).to(dev).expand(n_temps, n_walkers, -1, -1, -1))
+    sw.exists.copy_(torch.from_numpy(e0).to(dev).expand(n_temps, n_walkers, -1, -1))
+    sw.betas.copy_(torch.from_numpy(np.geomspace(1.0, 0.1, n_temps)).to(dev).expand(n_bands, -1))
+    sw.inv_psd.copy_(invS.expand(n_walkers, -1, -1))
+    band_par = (torch.arange(n_bands, device=dev) % 2).view(1, n_bands, 1).expand(n_walkers, -1, n_slots)
+    walker = torch.arange(n_walkers, device=dev, dtype=torch.int32).view(n_walkers, 1, 1).expand(-1, n_bands, n_slots)
+    for par in (0, 1):
+        sw.resid[par].copy_(d.expand(n_walkers, -1, -1))
+        sel = (sw.exists[0] != 0) & (band_par == par)
+        ctx.gb_scatter_add(_physical(sw.u[0][sel].contiguous()), N, -1.0, sw.resid[par], walker[sel].contiguous())
+    sw.enable_logl_trace()
+    fcfg = flow_config(n_bands, N, k_band0, PRIOR_LO, PRIOR_HI)
+    torch.cuda.synchronize()
+    return Problem(ctx, sw, fcfg, src, target)
+
+
+_STATE = ("u", "exists", "resid", "group", "group_count", "stats", "sweep_counter")
+
+
+def save(sw: Sweep):
+    return {k: getattr(sw, k).clone() for k in _STATE}
+
+
+def restore(sw: Sweep, st):
+    for k in _STATE:
+        getattr(sw, k).copy_(st[k])
+
+
+def collect(sw: Sweep, n_sweeps: int, every: int = 1):
+    """run n_sweeps prior-RJ sweeps; return the cold chain's occupied (u, band) pairs"""
+    c = sw.cfg
+    band_of = torch.arange(c.n_bands, device=sw.u.device, dtype=torch.int32).view(1, c.n_bands, 1).expand(
+        c.n_walkers, -1, c.n_slots)
+    us, bs = [], []
+    for i in range(n_sweeps):
+        sw.run(1)
+        if i % every == 0:
+            m = sw.exists[0] != 0
+            us.append(sw.u[0][m].clone())
+            bs.append(band_of[m].clone())
+    return torch.cat(us), torch.cat(bs).contiguous()
+
+
+def train(flow: Flow, u, band, steps: int, batch: int = 4096, lr: float = 1e-3, seed: int = 0):
+    gen = torch.Generator(device=u.device)
+    gen.manual_seed(seed)
+    losses = []
+    for _ in range(steps):
+        idx = torch.randint(0, u.shape[0], (batch,), generator=gen, device=u.device)
+        losses.append(flow.train_step(u[idx].contiguous(), band[idx].contiguous(), lr))
+    return torch.stack(losses).view(-1).cpu().numpy()
+
+
+def measure(sw: Sweep, n_sweeps: int, flow: Flow | None = None):
+    """n_sweeps sweeps (flow RJ proposal if given, else prior draws); traces and rates"""
+    k_tr, l_tr = [], []
+    st0 = sw.stats.clone()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(n_sweeps):
+        if flow is None:
+            sw.disable_proposals()
+            sw.run(1)
+        else:
+            sw.run_flow(flow, 1)
+        k_tr.append(sw.exists[0].sum(dim=-1))
+        l_tr.append(sw.cold_logl.clone())
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    k = torch.stack(k_tr, dim=-1).double().cpu().numpy()   # [n_w][n_b][n_sweeps]
+    lnl = torch.stack(l_tr, dim=-1).cpu().numpy()
+    dst = (sw.stats - st0).cpu().numpy()
+    ess_k = float(sum(ess_mod.ess(k[:, b, :]) for b in range(k.shape[1])))
+    ess_l = float(sum(ess_mod.ess(lnl[:, b, :]) for b in range(lnl.shape[1])))
+    return {"sweeps": n_sweeps, "wall_s": wall,
+            "birth_acceptance": float(dst[3]) / max(1.0, float(dst[2])),
+            "death_acceptance": float(dst[5]) / max(1.0, float(dst[4])),
+            "rj_accepted_per_s": float(dst[3] + dst[5]) / wall,
+            "ess_k": ess_k, "ess_logl": ess_l, "ess_k_per_s": ess_k / wall, "ess_logl_per_s": ess_l / wall,
+            "mean_k": float(k.mean())}
+
+
+def compare(problem: Problem, burn: int = 100, collect_sweeps: int = 200, train_steps: int = 300,
+            measure_sweeps: int = 400, lr: float = 1e-3, seed: int = 0):
+    """burn-in and sample collection with prior RJ, flow training, then the
+    same number of sweeps from the same state with each proposal"""
+    from .flow import init_params
+    sw = problem.sweep
+    sw.run(burn)
+    u, band = collect(sw, collect_sweeps)
+    flow = Flow(problem.ctx, problem.fcfg, init_params(seed, problem.fcfg.n_emb))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    losses = train(flow, u, band, train_steps, lr=lr, seed=seed)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    state = save(sw)
+    plain = measure(sw, measure_sweeps, None)
+    restore(sw, state)
+    learned = measure(sw, measure_sweeps, flow)
+    return {"training_samples": int(u.shape[0]), "train_steps": train_steps,
+            "train_ms_per_step": 1e3 * t_train / max(1, train_steps),
+            "loss_first": float(np.mean(losses[:10])), "loss_last": float(np.mean(losses[-10:])),
+            "plain": plain, "learned": learned,
+            "gain_ess_k_per_s": learned["ess_k_per_s"] / max(plain["ess_k_per_s"], 1e-300),
+            "gain_ess_logl_per_s": learned["ess_logl_per_s"] / max(plain["ess_logl_per_s"], 1e-300),
+            "gain_birth_acceptance": learned["birth_acceptance"] / max(plain["birth_acceptance"], 1e-300)}, flow

@@ -47,12 +47,34 @@ class Sweep:
         self.group_count = torch.zeros(nb, dtype=torch.int32, device=dev)
         self.stats = torch.zeros(8, dtype=torch.int64, device=dev)
         self.sweep_counter = torch.zeros(1, dtype=torch.int64, device=dev)
+        # optional: RJ proposal arrays (flow proposals) and the cold-chain logL trace
+        self.prop_u = None
+        self.rj_logq = None
+        self.cold_logl = None
         self._graph = None
+
+    def enable_proposals(self):
+        """allocate prop_u / rj_logq (used by the flow RJ proposal, or filled by the caller)"""
+        c = self.cfg
+        dev = self.ctx.device
+        self.prop_u = torch.zeros((c.n_temps, c.n_walkers, c.n_bands, c.n_slots, 8), dtype=torch.float64, device=dev)
+        self.rj_logq = torch.zeros((c.n_temps, c.n_walkers, c.n_bands, c.n_slots), dtype=torch.float64, device=dev)
+
+    def disable_proposals(self):
+        self.prop_u = None
+        self.rj_logq = None
+
+    def enable_logl_trace(self):
+        c = self.cfg
+        self.cold_logl = torch.full((c.n_walkers, c.n_bands), float("nan"), dtype=torch.float64,
+                                    device=self.ctx.device)
 
     def _state(self):
         st = SweepState()
-        for n in ("u", "exists", "betas", "resid", "inv_psd", "group", "group_count", "stats", "sweep_counter"):
-            setattr(st, n, getattr(self, n).data_ptr())
+        for n in ("u", "exists", "betas", "resid", "inv_psd", "group", "group_count", "stats", "sweep_counter",
+                  "prop_u", "rj_logq", "cold_logl"):
+            t = getattr(self, n)
+            setattr(st, n, t.data_ptr() if t is not None else None)
         return st
 
     def _call(self, name, *args):
@@ -71,6 +93,29 @@ class Sweep:
 
     def run(self, n_sweeps: int):
         self._call("gb_sweep_run", ctypes.byref(self.cfg), ctypes.byref(self._state()), int(n_sweeps))
+
+    def rj_prepare(self, flow):
+        """fill prop_u / rj_logq from the flow (births: flow samples; deaths: flow density)"""
+        if self.prop_u is None:
+            self.enable_proposals()
+        self._call("gb_sweep_rj_prepare", ctypes.byref(self.cfg), ctypes.byref(self._state()),
+                   ctypes.byref(flow.cfg), ctypes.byref(flow._state()))
+
+    def run_flow(self, flow, n_sweeps: int):
+        if self.prop_u is None:
+            self.enable_proposals()
+        self._call("gb_sweep_run_flow", ctypes.byref(self.cfg), ctypes.byref(self._state()), ctypes.byref(flow.cfg),
+                   ctypes.byref(flow._state()), int(n_sweeps))
+
+    def capture_flow(self, flow, n_sweeps: int):
+        """capture n_sweeps sweeps with the flow RJ proposal into a HIP graph"""
+        self.release_graph()
+        if self.prop_u is None:
+            self.enable_proposals()
+        h = ctypes.c_void_p()
+        self._call("gb_sweep_graph_create_flow", ctypes.byref(self.cfg), ctypes.byref(self._state()),
+                   ctypes.byref(flow.cfg), ctypes.byref(flow._state()), int(n_sweeps), ctypes.byref(h))
+        self._graph = h
 
     def capture(self, n_sweeps: int):
         """Capture n_sweeps full sweeps into a HIP graph (context stream must not be the default one)."""

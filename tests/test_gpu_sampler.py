@@ -138,3 +138,152 @@ def test_inmodel_moves_keep_the_prior_at_zero_inverse_temperature():
             p = sps.kstest(x, "uniform").pvalue
             assert p > 1e-4, (b, k, p)
     ctx.close()
+
+
+def _given_proposals(sc, T, seed):
+    """seeded RJ proposal arrays (not from any flow): candidates inside the
+    band's prior box (a tenth with f0 outside it) and arbitrary ln q values"""
+    rng = np.random.default_rng(seed)
+    nt, nw, nb, ns = sc.n_temps, sc.n_walkers, sc.n_bands, sc.n_slots
+    lo = np.array(list(sc.prior_lo))
+    hi = np.array(list(sc.prior_hi))
+    prop = np.zeros((nt, nw, nb, ns, 8))
+    for b in range(nb):
+        blo, bhi = lo.copy(), hi.copy()
+        blo[1] = (sc.k_band0 + (b - 0.5) * sc.N) / T
+        bhi[1] = (sc.k_band0 + (b + 1.5) * sc.N) / T
+        for k, P in ((3, 2 * np.pi), (5, np.pi), (6, 2 * np.pi)):
+            blo[k], bhi[k] = 0.0, P
+        prop[:, :, b] = blo + (bhi - blo) * rng.uniform(size=(nt, nw, ns, 8))
+    out = rng.uniform(size=(nt, nw, nb, ns)) < 0.1
+    prop[..., 1] = np.where(out, prop[..., 1] + 2.5 * sc.N / T, prop[..., 1])
+    logq = rng.normal(-5.0, 3.0, (nt, nw, nb, ns))
+    return prop, logq
+
+
+def test_rj_with_given_proposal_densities_and_cold_logl_trace():
+    cfg, orc, sc, st = sampler_setup.problem(seed=21)
+    ctx, sw = _gpu_sweep(cfg, sc, st)
+    prop, logq = _given_proposals(sc, cfg.T, 22)
+    sw.enable_proposals()
+    sw.prop_u.copy_(torch.from_numpy(prop))
+    sw.rj_logq.copy_(torch.from_numpy(logq))
+    sw.enable_logl_trace()
+    s0 = 3
+    sw.sweep_counter.fill_(s0)
+    for parity in (1, 0):
+        oracle.sweep_step(orc, sc, st, 1, parity, s0, prop_u=prop, rj_logq=logq)
+        sw.step(1, parity)
+        _compare(sw, st, f"rj given proposals/{parity}")
+    assert st.stats[3] > 0 and st.stats[5] > 0
+    cl = np.full((sc.n_walkers, sc.n_bands), np.nan)
+    for parity in (1, 0):
+        oracle.sweep_step(orc, sc, st, 2, parity, s0, cold_logl=cl)
+        sw.step(2, parity)
+        _compare(sw, st, f"tempering/{parity}")
+    got = sw.cold_logl.cpu().numpy()
+    assert np.all(np.isfinite(cl))
+    assert np.max(np.abs(got - cl)) <= 1e-10 * np.abs(cl).max()
+    ctx.close()
+
+
+def _flow_for(sc, cfg, s_bias=0.0, seed=31, identity=False):
+    from oracle import flow as oflow
+    from paper_2405_04690_amd.flow import Flow, flow_config
+    fc = flow_config(sc.n_bands, sc.N, sc.k_band0, list(sc.prior_lo), list(sc.prior_hi))
+    th = oflow.init_params(seed, sc.n_bands, out_scale=0.0 if identity else 0.3)
+    layers, _ = oflow.unpack(th, sc.n_bands)
+    for l, L in enumerate(layers):
+        if l % 2 == 0:
+            L["b3"][0] = s_bias   # contracts coordinate 1 (f0) in the even layers
+    return fc, th
+
+
+def test_flow_rj_prepare_identity_flow_is_box_muller_of_the_stream():
+    """identity flow (W3 = b3 = 0): birth candidates are the box images of the
+    stream's normals and ln q is the logit-normal density"""
+    from oracle import flow as oflow
+    from paper_2405_04690_amd.flow import Flow
+    cfg, orc, sc, st = sampler_setup.problem(seed=41)
+    ctx, sw = _gpu_sweep(cfg, sc, st)
+    fc, th = _flow_for(sc, cfg, identity=True)
+    fl = Flow(ctx, fc, th.astype(np.float32))
+    s0 = 9
+    sw.sweep_counter.fill_(s0)
+    sw.rj_prepare(fl)
+    torch.cuda.synchronize()
+    pu = sw.prop_u.cpu().numpy()
+    lq = sw.rj_logq.cpu().numpy()
+    ex = st.exists.astype(bool)
+    nt, nw, nb, ns = ex.shape
+    idx = np.argwhere(~ex)[:200]
+    for (t, w, b, s) in idx:
+        unit = ((t * nw + w) * nb + b)
+        z = np.zeros(8)
+        for p in range(4):
+            d = 2048 + 16 * s + 2 * p
+            u1 = oracle.rng_uniform(sc.seed, s0, 1, unit, d)
+            u2 = oracle.rng_uniform(sc.seed, s0, 1, unit, d + 1)
+            r = np.sqrt(-2 * np.log(u1))
+            z[2 * p], z[2 * p + 1] = r * np.cos(2 * np.pi * u2), r * np.sin(2 * np.pi * u2)
+        lo, hi = oflow.box(np.array([b]), cfg.T, sc.k_band0, sc.N, list(sc.prior_lo), list(sc.prior_hi))
+        u_ref, lj = oflow.from_real(z[None], lo, hi)
+        assert np.allclose(pu[t, w, b, s], u_ref[0], rtol=1e-12, atol=1e-12 * np.abs(hi - lo).max())
+        assert abs(lq[t, w, b, s] - (oflow.log_normal(z[None])[0] + lj[0])) <= 1e-9 * max(1.0, abs(lq[t, w, b, s]))
+    occ = np.argwhere(ex)
+    for (t, w, b, s) in occ[:100]:
+        lo, hi = oflow.box(np.array([b]), cfg.T, sc.k_band0, sc.N, list(sc.prior_lo), list(sc.prior_hi))
+        uu = st.u[t, w, b, s][None]
+        if not np.all((uu > lo) & (uu < hi)):
+            assert np.isnan(lq[t, w, b, s])
+            continue
+        x, lj = oflow.to_real(uu, lo, hi)
+        assert abs(lq[t, w, b, s] - (oflow.log_normal(x)[0] + lj[0])) <= 1e-9 * max(1.0, abs(lq[t, w, b, s]))
+    ctx.close()
+
+
+def test_flow_rj_keeps_the_prior_at_zero_inverse_temperature():
+    """beta = 0 with a flow proposal concentrated in f0: the exact MH ratio
+    keeps each slot occupied with probability 1/2 and the occupied f0
+    uniform over the band's range (without the ln q terms they would follow q)"""
+    from paper_2405_04690_amd.flow import Flow
+    from scipy import stats as sps
+    cfg, orc, sc, st = sampler_setup.problem(n_t=1, n_w=16, n_b=4, n_slots=16, seed=51)
+    rng = np.random.default_rng(52)
+    lo = np.array(list(sc.prior_lo))
+    hi = np.array(list(sc.prior_hi))
+    for b in range(sc.n_bands):
+        blo, bhi = lo.copy(), hi.copy()
+        blo[1] = (sc.k_band0 + (b - 0.5) * sc.N) / cfg.T
+        bhi[1] = (sc.k_band0 + (b + 1.5) * sc.N) / cfg.T
+        for k, P in ((3, 2 * np.pi), (5, np.pi), (6, 2 * np.pi)):
+            blo[k], bhi[k] = 0.0, P
+        st.u[:, :, b] = blo + (bhi - blo) * rng.uniform(size=st.u[:, :, b].shape)
+    st.exists[:] = (rng.uniform(size=st.exists.shape) < 0.5).astype(np.int32)
+    st.betas[:] = 0.0
+    ctx, sw = _gpu_sweep(cfg, sc, st)
+    fc, th = _flow_for(sc, cfg, s_bias=-0.5)
+    fl = Flow(ctx, fc, th.astype(np.float32))
+    f0s, occ = [], []
+    for it in range(400):
+        sw.rj_prepare(fl)
+        sw.step(1, 1)
+        sw.step(1, 0)
+        sw.advance()
+        if it >= 100 and it % 25 == 0:
+            ex = sw.exists.cpu().numpy().astype(bool)
+            u = sw.u.cpu().numpy()
+            occ.append(ex.mean())
+            for b in range(sc.n_bands):
+                flo = (sc.k_band0 + (b - 0.5) * sc.N) / cfg.T
+                fhi = (sc.k_band0 + (b + 1.5) * sc.N) / cfg.T
+                f0s.append((u[:, :, b][ex[:, :, b]][:, 1] - flo) / (fhi - flo))
+    stats = sw.stats.cpu().numpy()
+    assert stats[3] > 0.02 * stats[2] and stats[5] > 0.02 * stats[4]
+    assert abs(np.mean(occ) - 0.5) < 0.05, np.mean(occ)
+    x = np.concatenate(f0s)
+    # the flow's f0 density peaks at the band centre; the occupied f0 must not
+    # (snapshots 25 sweeps apart are correlated: a loose KS threshold)
+    assert sps.kstest(x, "uniform").pvalue > 1e-6
+    assert abs(np.mean(np.abs(x - 0.5) < 0.1) - 0.2) < 0.05
+    ctx.close()
