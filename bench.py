@@ -61,6 +61,7 @@ def parse():
     ap.add_argument("--no-secondary", action="store_true", help="skip the secondary measurements")
     ap.add_argument("--no-sweep", action="store_true", help="skip the sampler-sweep measurement")
     ap.add_argument("--sweeps", type=int, default=2, help="timed sampler sweeps")
+    ap.add_argument("--no-rj", action="store_true", help="skip the learned-vs-prior RJ comparison")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 512 MiB device copy (counter calibration for profiles)")
     return ap.parse_args()
@@ -259,6 +260,39 @@ def sweep_bench(torch, dev, stream, n_sweeps, n_temps=36, n_walkers=32, n_prop=3
     return out
 
 
+def rj_bench(torch, dev, stream):
+    """Learned (flow) versus prior RJ proposal on the same problem: 1 yr,
+    N = 256 sub-bands from 3 mHz, one loud (SNR 20) and one near-threshold
+    (SNR 7) source per sub-band, 8 temperatures x 32 walkers; flow trained on
+    the prior-RJ chain's cold samples with the library's BF16 kernels; then
+    the same number of sweeps from the same state with each proposal."""
+    from paper_2405_04690_amd import inputs, learned_rj
+    with torch.cuda.stream(stream):
+        prob = learned_rj.build(cfg=inputs.PAPER, N=256, n_temps=8, n_walkers=32, n_bands=16, n_slots=6, seed=60,
+                                stream=stream)
+        res, flow = learned_rj.compare(prob, burn=50, collect_sweeps=100, train_steps=300, measure_sweeps=300)
+        # flow throughput inside the RJ preparation (all slots, both directions)
+        sw = prob.sweep
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(5):
+            sw.rj_prepare(flow)
+        b.record(stream)
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / 5
+        n_slots = sw.exists.numel()
+        flops = 2 * n_slots * 6 * 2 * (20 * 128 + 128 * 128 + 128 * 8)  # both passes run over every slot
+        res["flow_rj_prepare_ms"] = round(ms, 4)
+        res["flow_samples_per_s"] = round(2 * n_slots / (ms / 1e3), 1)
+        res["flow_mfma_tflops"] = round(flops / (ms / 1e3) / 1e12, 3)
+        res["flow_mfma_frac_bf16_peak"] = round(flops / (ms / 1e3) / 1e12 / 2500.0, 5)
+        res["workload"] = ("1 yr, 16 sub-bands of N=256 from 3 mHz, SNR 20 + SNR 7 source per sub-band, "
+                           "8 temps x 32 walkers x 6 slots; burn 50, collect 100, train 300 x 4096, "
+                           "measure 300 sweeps per proposal")
+        prob.ctx.close()
+    return res
+
+
 def cpu_baseline(batch, cfg, target_s):
     """The FP64 oracle on a bounded sample of the same swap batch."""
     import oracle
@@ -344,6 +378,9 @@ def main():
             torch.cuda.empty_cache()
             sec = dict(sec or {})
             sec["sweep"] = sweep_bench(torch, dev, stream, args.sweeps)
+        if not args.no_rj:
+            sec = dict(sec or {})
+            sec["learned_rj"] = rj_bench(torch, dev, stream)
     per_launch_ms = float(np.mean([s.elapsed_time(e) for s, e in ev]))
     total_ms = ev[0][0].elapsed_time(ev[-1][1])
     value = B * args.steps / (total_ms / 1e3)

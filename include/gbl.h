@@ -66,6 +66,13 @@ extern "C" {
                        likelihood sums in double; link amplitudes, the TDI
                        response, the FFT and the per-bin factor in float */
 
+/* config flags.  In a GBL_MIXED context gb_delta_loglike(_var) estimates the
+ * FP32 error of every pair (20 * 2^-24 times the largest of <a|a>, <r|r>,
+ * |<R|a>|, |<R|r>|) and re-evaluates the pairs whose estimate exceeds 5e-4 in
+ * FP64 in a second pass, so every result stays within 1e-3 of the FP64 path;
+ * GBL_MIXED_UNROUTED skips that pass (pure FP32 response). */
+#define GBL_MIXED_UNROUTED 1
+
 /* psd flags */
 #define GBL_PSD_INVERSE 1 /* the psd array holds 1/S_n instead of S_n */
 
@@ -78,7 +85,7 @@ typedef struct {
   double f_lo;       /* analysis band [Hz] */
   double f_hi;
   int32_t precision; /* GBL_FP64 or GBL_MIXED */
-  int32_t flags;     /* reserved, must be 0 */
+  int32_t flags;     /* 0, or GBL_MIXED_UNROUTED with GBL_MIXED */
 } gbl_config;
 
 /* Create a context for one configuration on the current HIP device.

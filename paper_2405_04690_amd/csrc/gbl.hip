@@ -44,6 +44,8 @@ struct gbl_ctx {
   double* psd_work;
   int* counts;       // [4 widths] templates per width bucket
   int32_t* perm;     // [4 widths][kBucketCap] template indices per width
+  int* route_counts;      // [4 widths] mixed-precision pairs queued for the FP64 pass
+  int32_t* route_lists;   // [4 widths][kBucketCap]
   std::string err;
 };
 
@@ -73,6 +75,8 @@ static void release(gbl_ctx* ctx) {
   if (ctx->psd_work) (void)hipFree(ctx->psd_work);
   if (ctx->counts) (void)hipFree(ctx->counts);
   if (ctx->perm) (void)hipFree(ctx->perm);
+  if (ctx->route_counts) (void)hipFree(ctx->route_counts);
+  if (ctx->route_lists) (void)hipFree(ctx->route_lists);
 }
 
 extern "C" int gbl_create(gbl_ctx** out, const gbl_config* cfg, void* hip_stream) {
@@ -80,7 +84,8 @@ extern "C" int gbl_create(gbl_ctx** out, const gbl_config* cfg, void* hip_stream
   *out = nullptr;
   if (!cfg) return GBL_EINVAL;
   if (!(cfg->T > 0) || !(cfg->dt > 0) || !(cfg->L > 0) || !(cfg->f_lo > 0) || !(cfg->f_hi > cfg->f_lo) ||
-      cfg->f_hi > 0.5 / cfg->dt || cfg->flags != 0)
+      cfg->f_hi > 0.5 / cfg->dt || (cfg->flags & ~GBL_MIXED_UNROUTED) != 0 ||
+      ((cfg->flags & GBL_MIXED_UNROUTED) && cfg->precision != GBL_MIXED))
     return GBL_EINVAL;
   if (cfg->precision != GBL_FP64 && cfg->precision != GBL_MIXED) return GBL_EUNSUPPORTED;
 
@@ -127,7 +132,9 @@ extern "C" int gbl_create(gbl_ctx** out, const gbl_config* cfg, void* hip_stream
   if (hipMalloc(&ctx->psd_P1, nbb) != hipSuccess || hipMalloc(&ctx->psd_P2, nbb) != hipSuccess ||
       hipMalloc(&ctx->psd_work, sizeof(double) * 2 * gbl::kPsdChunks * kPsdBatch) != hipSuccess ||
       hipMalloc(&ctx->counts, sizeof(int) * kNumWidths) != hipSuccess ||
-      hipMalloc(&ctx->perm, sizeof(int32_t) * (size_t)kNumWidths * kBucketCap) != hipSuccess) {
+      hipMalloc(&ctx->perm, sizeof(int32_t) * (size_t)kNumWidths * kBucketCap) != hipSuccess ||
+      hipMalloc(&ctx->route_counts, sizeof(int) * kNumWidths) != hipSuccess ||
+      hipMalloc(&ctx->route_lists, sizeof(int32_t) * (size_t)kNumWidths * kBucketCap) != hipSuccess) {
     release(ctx);
     delete ctx;
     return GBL_EHIP;
@@ -222,10 +229,40 @@ struct LaunchWaveform {
   }
 };
 
+static bool routed(const gbl_ctx* ctx) {
+  return ctx->cfg.precision == GBL_MIXED && !(ctx->cfg.flags & GBL_MIXED_UNROUTED);
+}
+
+// mixed precision: pairs whose FP32 error estimate exceeds this are re-evaluated in FP64
+constexpr double kRouteTol = 5e-4;
+
+static gbl::DeltaArgs with_route(gbl_ctx* ctx, gbl::DeltaArgs da, int N, int64_t b0) {
+  const int slot = width_slot(N);
+  da.route_list = ctx->route_lists + (int64_t)slot * kBucketCap;
+  da.route_count = ctx->route_counts + slot;
+  da.route_tol = kRouteTol;
+  da.route_b0 = b0;
+  return da;
+}
+
+template <int N>
+static void launch_route_pass(gbl_ctx* ctx, const gbl::DeltaArgs& da, int64_t b0, int64_t nb) {
+  const int slot = width_slot(N);
+  const int64_t grid = nb < 2048 ? nb : 2048;
+  hipLaunchKernelGGL((gbl::k_delta_loglike_list<N>), dim3((unsigned)grid), dim3(gbl::block_threads<N>()), 0,
+                     ctx->stream, ctx->geo, tables_for<N, double>(ctx), da, b0,
+                     (const int*)(ctx->route_counts + slot), (const int32_t*)(ctx->route_lists + (int64_t)slot * kBucketCap));
+}
+
 template <int N>
 struct LaunchDelta {
   static void run(gbl_ctx* ctx, const gbl::DeltaArgs& da, int64_t b0, int64_t nb) {
-    if (ctx->cfg.precision == GBL_MIXED)
+    if (routed(ctx)) {
+      hipLaunchKernelGGL(gbl::k_bucket_reset, dim3(1), dim3(64), 0, ctx->stream, ctx->route_counts, kNumWidths);
+      hipLaunchKernelGGL((gbl::k_delta_loglike<N, float>), dim3((unsigned)nb), dim3(gbl::block_threads<N>()), 0,
+                         ctx->stream, ctx->geo, tables_for<N, float>(ctx), with_route(ctx, da, N, b0), b0);
+      launch_route_pass<N>(ctx, da, b0, nb);
+    } else if (ctx->cfg.precision == GBL_MIXED)
       hipLaunchKernelGGL((gbl::k_delta_loglike<N, float>), dim3((unsigned)nb), dim3(gbl::block_threads<N>()), 0,
                          ctx->stream, ctx->geo, tables_for<N, float>(ctx), da, b0);
     else
@@ -240,7 +277,12 @@ struct LaunchDeltaBucket {
     const int slot = width_slot(N);
     const int* cnt = ctx->counts + slot;
     const int32_t* perm = ctx->perm + (int64_t)slot * kBucketCap;
-    if (ctx->cfg.precision == GBL_MIXED)
+    if (routed(ctx)) {
+      hipLaunchKernelGGL((gbl::k_delta_loglike_bucket<N, float>), dim3((unsigned)nb), dim3(gbl::block_threads<N>()),
+                         0, ctx->stream, ctx->geo, tables_for<N, float>(ctx), with_route(ctx, da, N, b0), b0, cnt,
+                         perm);
+      launch_route_pass<N>(ctx, da, b0, nb);
+    } else if (ctx->cfg.precision == GBL_MIXED)
       hipLaunchKernelGGL((gbl::k_delta_loglike_bucket<N, float>), dim3((unsigned)nb), dim3(gbl::block_threads<N>()),
                          0, ctx->stream, ctx->geo, tables_for<N, float>(ctx), da, b0, cnt, perm);
     else
@@ -325,9 +367,11 @@ extern "C" int gb_delta_loglike(gbl_ctx* ctx, const double* residual, int32_t n_
   if (!residual || !psd || !params_old || !params_new || !res_idx || !psd_idx || !dlogl)
     return fail(ctx, GBL_EINVAL, "gb_delta_loglike: null pointer%s");
   const gbl::DeltaArgs da = {(const cd*)residual, (int)n_res, psd, (int)n_psd,
-                             (psd_flags & GBL_PSD_INVERSE) ? 1 : 0, params_old, params_new, res_idx, psd_idx, dlogl};
-  for (int64_t b0 = 0; b0 < B; b0 += kMaxGrid) {
-    int64_t nb = B - b0 < kMaxGrid ? B - b0 : kMaxGrid;
+                             (psd_flags & GBL_PSD_INVERSE) ? 1 : 0, params_old, params_new, res_idx, psd_idx, dlogl,
+                             nullptr, nullptr, 0.0, 0};
+  const int64_t chunk = routed(ctx) ? kBucketCap : kMaxGrid;
+  for (int64_t b0 = 0; b0 < B; b0 += chunk) {
+    int64_t nb = B - b0 < chunk ? B - b0 : chunk;
     dispatch_width<LaunchDelta>(N, ctx, da, b0, nb);
   }
   return check_launch(ctx, "gb_delta_loglike");
@@ -344,10 +388,13 @@ extern "C" int gb_delta_loglike_var(gbl_ctx* ctx, const double* residual, int32_
   if (!residual || !psd || !params_old || !params_new || !N || !res_idx || !psd_idx || !dlogl)
     return fail(ctx, GBL_EINVAL, "gb_delta_loglike_var: null pointer%s");
   const gbl::DeltaArgs da = {(const cd*)residual, (int)n_res, psd, (int)n_psd,
-                             (psd_flags & GBL_PSD_INVERSE) ? 1 : 0, params_old, params_new, res_idx, psd_idx, dlogl};
+                             (psd_flags & GBL_PSD_INVERSE) ? 1 : 0, params_old, params_new, res_idx, psd_idx, dlogl,
+                             nullptr, nullptr, 0.0, 0};
   for (int64_t b0 = 0; b0 < B; b0 += kBucketCap) {
     int64_t nb = B - b0 < kBucketCap ? B - b0 : kBucketCap;
     bucket_widths(ctx, N, b0, nb, dlogl, nullptr);
+    if (routed(ctx))
+      hipLaunchKernelGGL(gbl::k_bucket_reset, dim3(1), dim3(64), 0, ctx->stream, ctx->route_counts, kNumWidths);
     // widest first, so the long blocks start early and the short ones fill in
     LaunchDeltaBucket<1024>::run(ctx, da, b0, nb);
     LaunchDeltaBucket<512>::run(ctx, da, b0, nb);

@@ -1,6 +1,8 @@
 // gbl_kernels.hpp -- HIP kernels of the GB likelihood library (gfx950).
 #pragma once
 
+#include <type_traits>
+
 #include "gbl_device.hpp"
 
 namespace gbl {
@@ -152,13 +154,19 @@ struct DeltaArgs {
   const int32_t* res_idx;
   const int32_t* psd_idx;
   double* out;
+  // mixed precision: pairs whose FP32 error estimate exceeds route_tol are
+  // queued (index - route_b0) on route_list / route_count for an FP64 pass
+  int32_t* route_list;
+  int* route_count;
+  double route_tol;
+  int64_t route_b0;
 };
 
 template <int N, typename F>
 struct DeltaSmem {
   cx<F> buf[4 * series_pitch<N>()];
   cx<F> rwin[2 * N];
-  double red[2 * (block_threads<N>() / kWave)];
+  double red[6 * (block_threads<N>() / kWave)];
   Src src[2];  // 0: old, 1: new
 };
 
@@ -233,6 +241,22 @@ __device__ __forceinline__ void delta_one(const Geo& g, const WaveTables<F>& tb,
     acc_rd += (R0.re * d0.re + R0.im * d0.im) * w0 + (R1.re * d1.re + R1.im * d1.im) * w1;
     acc_dd += (d0.re * d0.re + d0.im * d0.im) * w0 + (d1.re * d1.re + d1.im * d1.im) * w1;
   };
+  // FP32 templates: magnitudes of the inner-product terms <a|a>, <r|r>,
+  // <R|a>, <R|r> for the error estimate (<a|r> is at most max(<a|a>, <r|r>))
+  constexpr bool kEst = std::is_same<F, float>::value;
+  double m_aa = 0.0, m_rr = 0.0, m_Ra = 0.0, m_Rr = 0.0;
+  // x = a: adds to <a|a>, <R|a>; else to <r|r>, <R|r>
+  auto magnitude = [&](cd R0, cd R1, double w0, double w1, cd x0, cd x1, bool is_a) {
+    const double xx = (x0.re * x0.re + x0.im * x0.im) * w0 + (x1.re * x1.re + x1.im * x1.im) * w1;
+    const double Rx = (R0.re * x0.re + R0.im * x0.im) * w0 + (R1.re * x1.re + R1.im * x1.im) * w1;
+    if (is_a) {
+      m_aa += xx;
+      m_Ra += Rx;
+    } else {
+      m_rr += xx;
+      m_Rr += Rx;
+    }
+  };
 
   if (hn.state == 0) {
     const Src& sn = sm.src[1];
@@ -247,7 +271,16 @@ __device__ __forceinline__ void delta_one(const Geo& g, const WaveTables<F>& tb,
       cd a0 = cvt<double>(v[0]);
       cd a1 = cvt<double>(v[1]);
       int64_t jr = k - kr;
-      if (ho.state == 0 && jr >= 0 && jr < N) {
+      const bool has_r = ho.state == 0 && jr >= 0 && jr < N;
+      if constexpr (kEst) {
+        if (da.route_list) {
+          magnitude(pR0[m], pR1[m], pW0[m], pW1[m], a0, a1, true);
+          if (has_r)
+            magnitude(pR0[m], pR1[m], pW0[m], pW1[m], cvt<double>(sm.rwin[jr]), cvt<double>(sm.rwin[N + jr]),
+                      false);
+        }
+      }
+      if (has_r) {
         a0 = a0 - cvt<double>(sm.rwin[jr]);
         a1 = a1 - cvt<double>(sm.rwin[N + jr]);
       }
@@ -262,12 +295,33 @@ __device__ __forceinline__ void delta_one(const Geo& g, const WaveTables<F>& tb,
       if (k < g.k_min || k >= g.k_min + nb) continue;
       int64_t idx = k - g.k_min;
       cd r0 = cvt<double>(sm.rwin[j]), r1 = cvt<double>(sm.rwin[N + j]);
-      accumulate(RA[idx], RE[idx], weight(SA, idx), weight(SE, idx), cd{-r0.re, -r0.im}, cd{-r1.re, -r1.im});
+      const cd R0 = RA[idx], R1 = RE[idx];
+      const double w0 = weight(SA, idx), w1 = weight(SE, idx);
+      if constexpr (kEst) {
+        if (da.route_list) magnitude(R0, R1, w0, w1, r0, r1, false);
+      }
+      accumulate(R0, R1, w0, w1, cd{-r0.re, -r0.im}, cd{-r1.re, -r1.im});
     }
   }
   acc_rd = block_sum<NT>(acc_rd, sm.red);
   acc_dd = block_sum<NT>(acc_dd, sm.red + NT / kWave);
   if (tid == 0) da.out[b] = g.df4 * acc_rd - 0.5 * g.df4 * acc_dd;
+  if constexpr (kEst) {
+    if (da.route_list) {
+      m_aa = block_sum<NT>(m_aa, sm.red + 2 * (NT / kWave));
+      m_rr = block_sum<NT>(m_rr, sm.red + 3 * (NT / kWave));
+      m_Ra = block_sum<NT>(m_Ra, sm.red + 4 * (NT / kWave));
+      m_Rr = block_sum<NT>(m_Rr, sm.red + 5 * (NT / kWave));
+      if (tid == 0) {
+        // error estimate of the FP32 path: 20 * 2^-24 * the largest term
+        const double M = g.df4 * fmax(fmax(m_aa, m_rr), fmax(fabs(m_Ra), fabs(m_Rr)));
+        if (20.0 * 5.9604644775390625e-8 * M > da.route_tol) {
+          const int pos = atomicAdd(da.route_count, 1);
+          da.route_list[pos] = (int32_t)(b - da.route_b0);
+        }
+      }
+    }
+  }
 }
 
 template <int N, typename F>
@@ -275,6 +329,21 @@ __global__ __launch_bounds__(block_threads<N>()) void k_delta_loglike(Geo g, Wav
                                                                       int64_t b0) {
   __shared__ DeltaSmem<N, F> sm;
   delta_one<N, F>(g, tb, da, b0 + blockIdx.x, sm);
+}
+
+// FP64 pass over a list of pairs (the mixed-precision pairs whose error
+// estimate is too large); a fixed grid walks the list.
+template <int N>
+__global__ __launch_bounds__(block_threads<N>()) void k_delta_loglike_list(Geo g, WaveTables<double> tb,
+                                                                           DeltaArgs da, int64_t b0,
+                                                                           const int* __restrict__ count,
+                                                                           const int32_t* __restrict__ list) {
+  __shared__ DeltaSmem<N, double> sm;
+  const int n = *count;
+  for (int i = blockIdx.x; i < n; i += gridDim.x) {
+    delta_one<N, double>(g, tb, da, b0 + list[i], sm);
+    __syncthreads();
+  }
 }
 
 // ---------------------------------------------------------------------------

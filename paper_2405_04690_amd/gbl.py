@@ -21,6 +21,7 @@ GBL_EHIP = -3
 GBL_FP64 = 0
 GBL_MIXED = 1
 GBL_PSD_INVERSE = 1
+GBL_MIXED_UNROUTED = 1  # config flag
 
 SUPPORTED_N = (128, 256, 512, 1024)
 
@@ -139,10 +140,10 @@ class Context:
     """One library context: a run configuration bound to a device and stream."""
 
     def __init__(self, T: float, dt: float, L: float = 2.5e9, f_lo: float = 1e-4, f_hi: float = 3e-2,
-                 precision: int = GBL_FP64, device=None, stream=None):
+                 precision: int = GBL_FP64, device=None, stream=None, flags: int = 0):
         self.lib = load_library()
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
-        self.cfg = Config(T, dt, L, f_lo, f_hi, precision, 0)
+        self.cfg = Config(T, dt, L, f_lo, f_hi, precision, flags)
         self._h = ctypes.c_void_p()
         with torch.cuda.device(self.device):
             s = stream if stream is not None else torch.cuda.current_stream(self.device)

@@ -9,14 +9,19 @@ of the template's peak.  The likelihood change then errs by up to about
 eps32 times its largest inner-product term (~SNR x mismatch SNR), so
 |dlogL_mixed - dlogL_oracle| <= 1e-3 + 20 eps32 max|terms|: 1e-3 absolute for
 every pair whose terms stay below ~800, and a relative bound for louder ones.
-Integer outputs are exact."""
+Integer outputs are exact.
+
+By default a mixed context re-evaluates in FP64 every pair whose FP32 error
+estimate (20 eps32 times its largest term) exceeds 5e-4, so every ΔlogL is
+within 1e-3 of the FP64 oracle; with GBL_MIXED_UNROUTED the pure FP32
+response must meet the relative bound above."""
 import numpy as np
 import pytest
 import torch
 
 import oracle
 from paper_2405_04690_amd import inputs
-from paper_2405_04690_amd.gbl import GBL_MIXED, Context
+from paper_2405_04690_amd.gbl import GBL_MIXED, GBL_MIXED_UNROUTED, Context
 
 pytestmark = pytest.mark.gpu
 
@@ -38,6 +43,15 @@ def mixed():
     ctx.close()
 
 
+@pytest.fixture(scope="module")
+def unrouted():
+    cfg = inputs.TINY
+    ctx = Context(T=cfg.T, dt=cfg.dt, L=cfg.L, f_lo=cfg.f_lo, f_hi=cfg.f_hi, precision=GBL_MIXED,
+                  flags=GBL_MIXED_UNROUTED)
+    yield ctx
+    ctx.close()
+
+
 @pytest.mark.parametrize("N", [128, 256, 512, 1024])
 def test_mixed_waveform_error(mixed, N):
     cfg, ctx, orc = mixed
@@ -55,8 +69,11 @@ def test_mixed_waveform_error(mixed, N):
 
 
 @pytest.mark.parametrize("N", [128, 256, 1024])
-def test_mixed_delta_loglike_error(mixed, N):
+@pytest.mark.parametrize("routed", [True, False])
+def test_mixed_delta_loglike_error(mixed, unrouted, N, routed):
     cfg, ctx, orc = mixed
+    if not routed:
+        ctx = unrouted
     S = orc.psd_eval(np.array([cfg.sqrt_oms, cfg.sqrt_acc, cfg.sqrt_oms, cfg.sqrt_acc]))
     src = inputs.draw_sources(400, 48, log10_fdot_range=(-19, -15))
     R = np.sqrt(S[0] / (4 * orc.df)) * inputs.complex_normals(401, (2, orc.n_bins))
@@ -82,6 +99,9 @@ def test_mixed_delta_loglike_error(mixed, N):
     assert np.all(err <= DLOGL_ABS_TOL + 20 * EPS32 * scale)
     quiet = scale < 800
     assert np.all(err[quiet] <= DLOGL_ABS_TOL)
+    if routed:
+        assert np.all(err <= DLOGL_ABS_TOL)
+        assert (scale >= 800).any()   # the case has loud pairs that needed the FP64 pass
 
 
 def test_mixed_psd_and_scatter_paths_run(mixed):
@@ -92,3 +112,21 @@ def test_mixed_psd_and_scatter_paths_run(mixed):
     exp = np.zeros((1, 2, orc.n_bins), np.complex128)
     orc.scatter_add(params, 256, 1.0, exp)
     assert np.max(np.abs(res.cpu().numpy() - exp)) <= WAVE_REL_TOL * np.abs(exp).max()
+
+
+def test_mixed_uneven_widths_stay_within_1e_3(mixed):
+    """the bucketed uneven-width call routes its loud pairs to FP64 too"""
+    cfg, ctx, orc = mixed
+    S = orc.psd_eval(np.array([cfg.sqrt_oms, cfg.sqrt_acc, cfg.sqrt_oms, cfg.sqrt_acc]))
+    src = inputs.draw_sources(410, 64, log10_fdot_range=(-19, -15))
+    R = np.sqrt(S[0] / (4 * orc.df)) * inputs.complex_normals(411, (2, orc.n_bins))
+    orc.scatter_add(src, 256, 1.0, R)
+    old = inputs.perturb(412, src, orc.T, "jitter")
+    new = inputs.perturb(413, old, orc.T, "inmodel")
+    widths = np.array([128, 256, 512, 1024] * 16, np.int32)
+    got = ctx.gb_delta_loglike_var(_t(R[None]), _t(S), _t(old), _t(new), _t(widths)).cpu().numpy()
+    ref = np.empty(len(src))
+    for N in (128, 256, 512, 1024):
+        m = widths == N
+        ref[m] = orc.delta_loglike(R[None], S, old[m], new[m], N)
+    assert np.all(np.abs(got - ref) <= DLOGL_ABS_TOL)
