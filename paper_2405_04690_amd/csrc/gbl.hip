@@ -44,6 +44,7 @@ struct gbl_ctx {
   double* psd_work;
   int* counts;       // [4 widths] templates per width bucket
   int32_t* perm;     // [4 widths][kBucketCap] template indices per width
+  gbl_tuning tune;        // launch-shape knobs
   int* route_counts;      // [4 widths] mixed-precision pairs queued for the FP64 pass
   int32_t* route_lists;   // [4 widths][kBucketCap]
   std::string err;
@@ -90,6 +91,7 @@ extern "C" int gbl_create(gbl_ctx** out, const gbl_config* cfg, void* hip_stream
   if (cfg->precision != GBL_FP64 && cfg->precision != GBL_MIXED) return GBL_EUNSUPPORTED;
 
   gbl_ctx* ctx = new gbl_ctx();
+  ctx->tune = gbl_tuning{2048, 4096, kBucketCap, 1};
   ctx->cfg = *cfg;
   ctx->stream = (hipStream_t)hip_stream;
   int64_t k_min = (int64_t)std::ceil(cfg->f_lo * cfg->T);
@@ -248,7 +250,7 @@ static gbl::DeltaArgs with_route(gbl_ctx* ctx, gbl::DeltaArgs da, int N, int64_t
 template <int N>
 static void launch_route_pass(gbl_ctx* ctx, const gbl::DeltaArgs& da, int64_t b0, int64_t nb) {
   const int slot = width_slot(N);
-  const int64_t grid = nb < 2048 ? nb : 2048;
+  const int64_t grid = nb < ctx->tune.route_grid ? nb : ctx->tune.route_grid;
   hipLaunchKernelGGL((gbl::k_delta_loglike_list<N>), dim3((unsigned)grid), dim3(gbl::block_threads<N>()), 0,
                      ctx->stream, ctx->geo, tables_for<N, double>(ctx), da, b0,
                      (const int*)(ctx->route_counts + slot), (const int32_t*)(ctx->route_lists + (int64_t)slot * kBucketCap));
@@ -369,7 +371,7 @@ extern "C" int gb_delta_loglike(gbl_ctx* ctx, const double* residual, int32_t n_
   const gbl::DeltaArgs da = {(const cd*)residual, (int)n_res, psd, (int)n_psd,
                              (psd_flags & GBL_PSD_INVERSE) ? 1 : 0, params_old, params_new, res_idx, psd_idx, dlogl,
                              nullptr, nullptr, 0.0, 0};
-  const int64_t chunk = routed(ctx) ? kBucketCap : kMaxGrid;
+  const int64_t chunk = routed(ctx) ? (int64_t)ctx->tune.bucket_chunk : kMaxGrid;
   for (int64_t b0 = 0; b0 < B; b0 += chunk) {
     int64_t nb = B - b0 < chunk ? B - b0 : chunk;
     dispatch_width<LaunchDelta>(N, ctx, da, b0, nb);
@@ -390,16 +392,24 @@ extern "C" int gb_delta_loglike_var(gbl_ctx* ctx, const double* residual, int32_
   const gbl::DeltaArgs da = {(const cd*)residual, (int)n_res, psd, (int)n_psd,
                              (psd_flags & GBL_PSD_INVERSE) ? 1 : 0, params_old, params_new, res_idx, psd_idx, dlogl,
                              nullptr, nullptr, 0.0, 0};
-  for (int64_t b0 = 0; b0 < B; b0 += kBucketCap) {
-    int64_t nb = B - b0 < kBucketCap ? B - b0 : kBucketCap;
+  const int64_t chunk = ctx->tune.bucket_chunk;
+  for (int64_t b0 = 0; b0 < B; b0 += chunk) {
+    int64_t nb = B - b0 < chunk ? B - b0 : chunk;
     bucket_widths(ctx, N, b0, nb, dlogl, nullptr);
     if (routed(ctx))
       hipLaunchKernelGGL(gbl::k_bucket_reset, dim3(1), dim3(64), 0, ctx->stream, ctx->route_counts, kNumWidths);
-    // widest first, so the long blocks start early and the short ones fill in
-    LaunchDeltaBucket<1024>::run(ctx, da, b0, nb);
-    LaunchDeltaBucket<512>::run(ctx, da, b0, nb);
-    LaunchDeltaBucket<256>::run(ctx, da, b0, nb);
-    LaunchDeltaBucket<128>::run(ctx, da, b0, nb);
+    // widest first (default): the long blocks start early and the short ones fill in
+    if (ctx->tune.widest_first) {
+      LaunchDeltaBucket<1024>::run(ctx, da, b0, nb);
+      LaunchDeltaBucket<512>::run(ctx, da, b0, nb);
+      LaunchDeltaBucket<256>::run(ctx, da, b0, nb);
+      LaunchDeltaBucket<128>::run(ctx, da, b0, nb);
+    } else {
+      LaunchDeltaBucket<128>::run(ctx, da, b0, nb);
+      LaunchDeltaBucket<256>::run(ctx, da, b0, nb);
+      LaunchDeltaBucket<512>::run(ctx, da, b0, nb);
+      LaunchDeltaBucket<1024>::run(ctx, da, b0, nb);
+    }
   }
   return check_launch(ctx, "gb_delta_loglike_var");
 }
@@ -411,8 +421,9 @@ extern "C" int gb_waveform_var(gbl_ctx* ctx, const double* params, const int32_t
   if (B == 0) return GBL_OK;
   if (!params || !N || !out_offset || !A || !E || !start_bin)
     return fail(ctx, GBL_EINVAL, "gb_waveform_var: null pointer%s");
-  for (int64_t b0 = 0; b0 < B; b0 += kBucketCap) {
-    int64_t nb = B - b0 < kBucketCap ? B - b0 : kBucketCap;
+  const int64_t chunk = ctx->tune.bucket_chunk;
+  for (int64_t b0 = 0; b0 < B; b0 += chunk) {
+    int64_t nb = B - b0 < chunk ? B - b0 : chunk;
     bucket_widths(ctx, N, b0, nb, nullptr, start_bin);
     LaunchWaveformBucket<1024>::run(ctx, params, b0, nb, out_offset, (cd*)A, (cd*)E, (cd*)Tch, start_bin);
     LaunchWaveformBucket<512>::run(ctx, params, b0, nb, out_offset, (cd*)A, (cd*)E, (cd*)Tch, start_bin);
@@ -723,9 +734,9 @@ extern "C" int gb_flow_pack(gbl_ctx* ctx, const gbl_flow_config* cfg, const gbl_
   return check_launch(ctx, "gb_flow_pack");
 }
 
-static unsigned flow_grid(int64_t B) {
+static unsigned flow_grid(const gbl_ctx* ctx, int64_t B) {
   const int64_t blocks = (B + 63) / 64;
-  return (unsigned)(blocks < 4096 ? blocks : 4096);
+  return (unsigned)(blocks < ctx->tune.flow_grid ? blocks : ctx->tune.flow_grid);
 }
 
 extern "C" int gb_flow_log_prob(gbl_ctx* ctx, const gbl_flow_config* cfg, const gbl_flow* fl, const double* u,
@@ -736,7 +747,7 @@ extern "C" int gb_flow_log_prob(gbl_ctx* ctx, const gbl_flow_config* cfg, const 
   if (B < 0) return fail(ctx, GBL_EINVAL, "gb_flow_log_prob: B < 0%s");
   if (B == 0) return GBL_OK;
   if (!u || !band || !logq) return fail(ctx, GBL_EINVAL, "gb_flow_log_prob: null pointer%s");
-  hipLaunchKernelGGL(gbl::flow::k_flow_apply<false>, dim3(flow_grid(B)), dim3(256), 0, ctx->stream,
+  hipLaunchKernelGGL(gbl::flow::k_flow_apply<false>, dim3(flow_grid(ctx, B)), dim3(256), 0, ctx->stream,
                      flow_args(ctx, cfg, fl), u, band, B, (double*)nullptr, logq);
   return check_launch(ctx, "gb_flow_log_prob");
 }
@@ -749,7 +760,7 @@ extern "C" int gb_flow_sample(gbl_ctx* ctx, const gbl_flow_config* cfg, const gb
   if (B < 0) return fail(ctx, GBL_EINVAL, "gb_flow_sample: B < 0%s");
   if (B == 0) return GBL_OK;
   if (!z || !band || !u || !logq) return fail(ctx, GBL_EINVAL, "gb_flow_sample: null pointer%s");
-  hipLaunchKernelGGL(gbl::flow::k_flow_apply<true>, dim3(flow_grid(B)), dim3(256), 0, ctx->stream,
+  hipLaunchKernelGGL(gbl::flow::k_flow_apply<true>, dim3(flow_grid(ctx, B)), dim3(256), 0, ctx->stream,
                      flow_args(ctx, cfg, fl), z, band, B, u, logq);
   return check_launch(ctx, "gb_flow_sample");
 }
@@ -823,10 +834,10 @@ static int rj_prepare(gbl_ctx* ctx, const gbl_sweep_config* cfg, const gbl_sweep
   fa.band_mod = cfg->n_bands;
   fa.mask = st->exists;
   fa.mask_want = 0;  // empty slots: candidates from the normals, in place
-  hipLaunchKernelGGL(gbl::flow::k_flow_apply<true>, dim3(flow_grid(n)), dim3(256), 0, ctx->stream, fa,
+  hipLaunchKernelGGL(gbl::flow::k_flow_apply<true>, dim3(flow_grid(ctx, n)), dim3(256), 0, ctx->stream, fa,
                      (const double*)st->prop_u, (const int32_t*)nullptr, n, st->prop_u, st->rj_logq);
   fa.mask_want = 1;  // occupied slots: density at the current source
-  hipLaunchKernelGGL(gbl::flow::k_flow_apply<false>, dim3(flow_grid(n)), dim3(256), 0, ctx->stream, fa,
+  hipLaunchKernelGGL(gbl::flow::k_flow_apply<false>, dim3(flow_grid(ctx, n)), dim3(256), 0, ctx->stream, fa,
                      (const double*)st->u, (const int32_t*)nullptr, n, (double*)nullptr, st->rj_logq);
   return check_launch(ctx, "gb_sweep_rj_prepare");
 }
@@ -857,4 +868,24 @@ extern "C" int gb_sweep_graph_create_flow(gbl_ctx* ctx, const gbl_sweep_config* 
   int rc = flow_check(ctx, fcfg, fl);
   if (rc) return rc;
   return graph_create_impl(ctx, cfg, st, fcfg, fl, n_sweeps, out);
+}
+
+// ---------------------------------------------------------------------------
+// launch-shape knobs
+// ---------------------------------------------------------------------------
+extern "C" int gbl_get_tuning(const gbl_ctx* ctx, gbl_tuning* out) {
+  if (!ctx || !out) return GBL_EINVAL;
+  *out = ctx->tune;
+  return GBL_OK;
+}
+
+extern "C" int gbl_set_tuning(gbl_ctx* ctx, const gbl_tuning* t) {
+  if (!ctx) return GBL_EINVAL;
+  if (!t) return fail(ctx, GBL_EINVAL, "gbl_set_tuning: null tuning%s");
+  const bool pow2 = t->bucket_chunk > 0 && (t->bucket_chunk & (t->bucket_chunk - 1)) == 0;
+  if (t->route_grid < 64 || t->route_grid > 65536 || t->flow_grid < 64 || t->flow_grid > 65536 || !pow2 ||
+      t->bucket_chunk < 4096 || t->bucket_chunk > kBucketCap || (t->widest_first != 0 && t->widest_first != 1))
+    return fail(ctx, GBL_EINVAL, "gbl_set_tuning: knob out of range%s");
+  ctx->tune = *t;
+  return GBL_OK;
 }

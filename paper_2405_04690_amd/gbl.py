@@ -30,7 +30,8 @@ EXPORTED = ("gbl_create", "gbl_destroy", "gbl_set_stream", "gbl_last_error", "gb
             "gb_scatter_add", "gb_make_noise", "gb_sweep_step", "gb_sweep_group", "gb_sweep_advance",
             "gb_sweep_run", "gb_sweep_graph_create", "gb_graph_launch", "gb_graph_destroy", "gb_flow_sizes",
             "gb_flow_pack", "gb_flow_log_prob", "gb_flow_sample", "gb_flow_grad", "gb_flow_adam",
-            "gb_flow_train_step", "gb_sweep_rj_prepare", "gb_sweep_run_flow", "gb_sweep_graph_create_flow")
+            "gb_flow_train_step", "gb_sweep_rj_prepare", "gb_sweep_run_flow", "gb_sweep_graph_create_flow",
+            "gbl_get_tuning", "gbl_set_tuning")
 
 GBL_MOVE_INMODEL, GBL_MOVE_RJ, GBL_MOVE_PT = 0, 1, 2
 
@@ -60,6 +61,15 @@ class SweepState(ctypes.Structure):
     """gbl_sweep_state (device pointers)"""
     _fields_ = [(n, ctypes.c_void_p) for n in ("u", "exists", "betas", "resid", "inv_psd", "group", "group_count",
                                               "stats", "sweep_counter", "prop_u", "rj_logq", "cold_logl")]
+
+
+class Tuning(ctypes.Structure):
+    """gbl_tuning: launch-shape knobs of a context"""
+    _fields_ = [("route_grid", ctypes.c_int32), ("flow_grid", ctypes.c_int32), ("bucket_chunk", ctypes.c_int32),
+                ("widest_first", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class FlowConfig(ctypes.Structure):
@@ -105,6 +115,8 @@ def load_library(path: str = LIB_PATH):
         "gb_sweep_graph_create": [vp, ctypes.POINTER(SweepConfig), ctypes.POINTER(SweepState), i32,
                                   ctypes.POINTER(vp)],
         "gb_graph_launch": [vp],
+        "gbl_get_tuning": [vp, ctypes.POINTER(Tuning)],
+        "gbl_set_tuning": [vp, ctypes.POINTER(Tuning)],
         "gb_flow_sizes": [ctypes.POINTER(FlowConfig), ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64)],
         "gb_flow_pack": [vp, ctypes.POINTER(FlowConfig), ctypes.POINTER(FlowState)],
         "gb_flow_log_prob": [vp, ctypes.POINTER(FlowConfig), ctypes.POINTER(FlowState), vp, vp, i64, vp],
@@ -166,6 +178,20 @@ class Context:
             self.close()
         except Exception:
             pass
+
+    def get_tuning(self) -> Tuning:
+        t = Tuning()
+        self._check(self.lib.gbl_get_tuning(self._h, ctypes.byref(t)), "gbl_get_tuning")
+        return t
+
+    def set_tuning(self, **knobs) -> Tuning:
+        t = self.get_tuning()
+        for k, v in knobs.items():
+            if k not in dict(Tuning._fields_):
+                raise KeyError(k)
+            setattr(t, k, int(v))
+        self._check(self.lib.gbl_set_tuning(self._h, ctypes.byref(t)), "gbl_set_tuning")
+        return t
 
     # -- helpers ---------------------------------------------------------
     def _sync_stream(self):

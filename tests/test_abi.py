@@ -64,3 +64,21 @@ def test_create_rejects_bad_config_on_host(lib):
     cfg = gbl.Config(1e7, 5.0, 2.5e9, 1e-4, 3e-2, 99, 0)    # unknown precision
     assert lib.gbl_create(ctypes.byref(h), ctypes.byref(cfg), None) == gbl.GBL_EUNSUPPORTED
     assert lib.gbl_create(None, ctypes.byref(cfg), None) == gbl.GBL_EINVAL
+
+
+def test_null_context_rejected_by_sampler_flow_and_tuning_calls(lib):
+    null = None
+    assert lib.gbl_get_tuning(null, null) == gbl.GBL_EINVAL
+    assert lib.gbl_set_tuning(null, null) == gbl.GBL_EINVAL
+    assert lib.gb_sweep_step(null, null, null, 0, 0) == gbl.GBL_EINVAL
+    assert lib.gb_sweep_rj_prepare(null, null, null, null, null) == gbl.GBL_EINVAL
+    assert lib.gb_sweep_run_flow(null, null, null, null, null, 1) == gbl.GBL_EINVAL
+    assert lib.gb_flow_pack(null, null, null) == gbl.GBL_EINVAL
+    assert lib.gb_flow_log_prob(null, null, null, null, null, 1, null) == gbl.GBL_EINVAL
+    assert lib.gb_flow_train_step(null, null, null, null, null, 1, 1, 1e-3) == gbl.GBL_EINVAL
+    cfg = gbl.FlowConfig()
+    assert lib.gb_flow_sizes(ctypes.byref(cfg), None, None, None) == gbl.GBL_EINVAL   # n_emb = 0
+    cfg.n_emb = 3
+    n, pb, wb = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    assert lib.gb_flow_sizes(ctypes.byref(cfg), ctypes.byref(n), ctypes.byref(pb), ctypes.byref(wb)) == gbl.GBL_OK
+    assert n.value == 6 * 20232 + 16 * 3 and pb.value == 6 * 92 * 64 * 16
