@@ -258,6 +258,7 @@ typedef struct {
   double* rj_logq;        /* [n_t][n_w][n_b][n_slot] ln q of the RJ proposal at the candidate
                              (empty slot) or at the current source (occupied slot) */
   double* cold_logl;      /* [n_w][n_b] cold chain's band log-likelihood, written by tempering */
+  int32_t* rj_mode;       /* [n_t][n_w][n_b][n_slot] workspace of gb_sweep_rj_prepare */
 } gbl_sweep_state;
 
 typedef struct gbl_graph gbl_graph;
@@ -319,6 +320,7 @@ typedef struct {
   int64_t k_band0;     /* first bin of sub-band 0 */
   double prior_lo[8];  /* box bounds of log10 A, fdot, cos iota, sin beta (entries 0, 2, 4, 7) */
   double prior_hi[8];
+  double prior_weight; /* RJ proposal = (1 - prior_weight) flow + prior_weight prior, in [0, 1] */
 } gbl_flow_config;
 
 typedef struct {
@@ -370,12 +372,16 @@ int gb_flow_train_step(gbl_ctx* ctx, const gbl_flow_config* cfg, const gbl_flow*
  * ln q(theta) (p = the uniform prior density of the band's box; a candidate
  * outside the prior, or a NaN ln q, is rejected).
  *
- * gb_sweep_rj_prepare fills prop_u and rj_logq for every slot from the flow:
- * for empty slots it draws 8 standard normals (Box-Muller on the sweep's
- * Philox stream: unit (t, w, b), move RJ, draws 2048 + 16 s + k) and pushes
- * them through the flow of sub-band b; for occupied slots it evaluates the
- * flow density at the current source.  fcfg must describe the sweep's own
- * box (n_emb = n_bands, width = N, same k_band0 and prior bounds). */
+ * gb_sweep_rj_prepare fills prop_u and rj_logq for every slot with the
+ * mixture proposal q = (1 - w) q_flow + w p, w = fcfg->prior_weight (as the
+ * paper mixes its fitted RJ proposals with prior draws, Sec. 4 "Transition
+ * from search to parameter estimation"): from the sweep's Philox stream
+ * (unit (t, w, b), move RJ, draws 2048 + 16 s + k) an empty slot takes a
+ * prior draw (probability w, uniforms k = 0..7) or 8 Box-Muller normals pushed
+ * through the flow of sub-band b; rj_logq is ln q at the candidate (empty
+ * slot) or at the current source (occupied slot).  st->rj_mode is its
+ * workspace.  fcfg must describe the sweep's own box (n_emb = n_bands,
+ * width = N, same k_band0 and prior bounds). */
 int gb_sweep_rj_prepare(gbl_ctx* ctx, const gbl_sweep_config* cfg, const gbl_sweep_state* st,
                         const gbl_flow_config* fcfg, const gbl_flow* flow);
 

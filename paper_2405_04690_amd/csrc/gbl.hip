@@ -826,19 +826,35 @@ static int rj_prepare(gbl_ctx* ctx, const gbl_sweep_config* cfg, const gbl_sweep
   for (int i : dims)
     if (fcfg->prior_lo[i] != cfg->prior_lo[i] || fcfg->prior_hi[i] != cfg->prior_hi[i])
       return fail(ctx, GBL_EINVAL, "gb_sweep_rj_prepare: flow box differs from the sweep's prior%s");
+  if (!st->rj_mode) return fail(ctx, GBL_EINVAL, "gb_sweep_rj_prepare: rj_mode workspace not set%s");
+  const double w = fcfg->prior_weight;
+  if (!(w >= 0.0 && w <= 1.0)) return fail(ctx, GBL_EINVAL, "gb_sweep_rj_prepare: prior_weight outside [0, 1]%s");
   const gbl::SweepArgs a = sweep_args(cfg, st);
   const int64_t n = (int64_t)cfg->n_temps * cfg->n_walkers * cfg->n_bands * cfg->n_slots;
-  hipLaunchKernelGGL(gbl::k_rj_normals, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, ctx->stream, a, st->prop_u);
+  const dim3 g1((unsigned)((n + 255) / 256)), b1(256);
+  switch (cfg->N) {
+    case 128: hipLaunchKernelGGL(gbl::k_rj_draw<128>, g1, b1, 0, ctx->stream, ctx->geo, a, w, st->prop_u, st->rj_mode); break;
+    case 256: hipLaunchKernelGGL(gbl::k_rj_draw<256>, g1, b1, 0, ctx->stream, ctx->geo, a, w, st->prop_u, st->rj_mode); break;
+    default: hipLaunchKernelGGL(gbl::k_rj_draw<512>, g1, b1, 0, ctx->stream, ctx->geo, a, w, st->prop_u, st->rj_mode); break;
+  }
   gbl::flow::FlowArgs fa = flow_args(ctx, fcfg, fl);
   fa.band_div = cfg->n_slots;
   fa.band_mod = cfg->n_bands;
-  fa.mask = st->exists;
-  fa.mask_want = 0;  // empty slots: candidates from the normals, in place
+  fa.mask = st->rj_mode;
+  fa.mask_want = 1;  // flow candidates: normals -> samples, in place
   hipLaunchKernelGGL(gbl::flow::k_flow_apply<true>, dim3(flow_grid(ctx, n)), dim3(256), 0, ctx->stream, fa,
                      (const double*)st->prop_u, (const int32_t*)nullptr, n, st->prop_u, st->rj_logq);
-  fa.mask_want = 1;  // occupied slots: density at the current source
+  fa.mask_want = 0;  // occupied slots: flow density at the current source
   hipLaunchKernelGGL(gbl::flow::k_flow_apply<false>, dim3(flow_grid(ctx, n)), dim3(256), 0, ctx->stream, fa,
                      (const double*)st->u, (const int32_t*)nullptr, n, (double*)nullptr, st->rj_logq);
+  fa.mask_want = 2;  // prior candidates: flow density at the candidate
+  hipLaunchKernelGGL(gbl::flow::k_flow_apply<false>, dim3(flow_grid(ctx, n)), dim3(256), 0, ctx->stream, fa,
+                     (const double*)st->prop_u, (const int32_t*)nullptr, n, (double*)nullptr, st->rj_logq);
+  switch (cfg->N) {
+    case 128: hipLaunchKernelGGL(gbl::k_rj_mix<128>, g1, b1, 0, ctx->stream, ctx->geo, a, w, st->rj_logq); break;
+    case 256: hipLaunchKernelGGL(gbl::k_rj_mix<256>, g1, b1, 0, ctx->stream, ctx->geo, a, w, st->rj_logq); break;
+    default: hipLaunchKernelGGL(gbl::k_rj_mix<512>, g1, b1, 0, ctx->stream, ctx->geo, a, w, st->rj_logq); break;
+  }
   return check_launch(ctx, "gb_sweep_rj_prepare");
 }
 

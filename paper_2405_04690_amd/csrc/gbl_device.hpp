@@ -530,16 +530,67 @@ __device__ __forceinline__ void dft4(cx<F>* x) {
 
 // ---------------------------------------------------------------------------
 // Block-level in-place decimation-in-frequency FFT over NSER series of length
-// N held in LDS (one padding element per 16 against bank conflicts), with
-// radix-4 passes and a final radix-2 pass when log2 N is odd, so that every
-// pass offers NSER * N / 4 butterflies to the NT threads of the block.
-// Output X[k] sits at the digit-reversed position fft_pos<N>(k).
+// N held in LDS, with radix-4 passes and a final radix-2 pass when log2 N is
+// odd, so that every pass offers NSER * N / 4 butterflies to the NT threads of
+// the block.  Output X[k] sits at the digit-reversed position fft_pos<N>(k).
+//
+// LDS layout of element e of a series (against bank conflicts of the 16-byte
+// accesses): GBL_LDS_LAYOUT 0 pads one element per 16 (e + e/16); layouts 1
+// and 2 swizzle, e ^ X(e >> LB) with X linear over GF(2) (LB = 3 or 4),
+// chosen so that the butterfly reads/writes of every pass, the sample writes
+// and the digit-reversed read-out hit distinct banks within 8-lane (layout 1)
+// or 16-lane (layout 2) groups.  Linearity lets a butterfly address its four
+// elements as lds_pad(base) ^ lds_pad(ST r) with the second term a constant.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int lds_pad(int i) { return i + (i >> 4); }
+#ifndef GBL_LDS_LAYOUT
+#define GBL_LDS_LAYOUT 1
+#endif
+
+template <int N>
+struct LdsSwizzle {
+  static constexpr int LB = GBL_LDS_LAYOUT == 1 ? 3 : 4;
+  static constexpr int NBITS = (N == 128 ? 7 : N == 256 ? 8 : N == 512 ? 9 : 10) - LB;
+  static constexpr int col(int j) {
+    if constexpr (GBL_LDS_LAYOUT == 1) {
+      constexpr int c128[] = {7, 5, 2, 4}, c256[] = {1, 6, 7, 1, 2}, c512[] = {3, 7, 3, 0, 6, 2},
+                    c1024[] = {1, 6, 5, 6, 6, 7, 2};
+      return N == 128 ? c128[j] : N == 256 ? c256[j] : N == 512 ? c512[j] : c1024[j];
+    } else {
+      constexpr int c128[] = {13, 10, 14}, c256[] = {13, 7, 14, 12}, c512[] = {11, 15, 10, 11, 9},
+                    c1024[] = {13, 11, 11, 6, 14, 2};
+      return N == 128 ? c128[j] : N == 256 ? c256[j] : N == 512 ? c512[j] : c1024[j];
+    }
+  }
+};
+
+template <int N>
+__device__ __forceinline__ constexpr int lds_pad(int e) {
+  if constexpr (GBL_LDS_LAYOUT == 0) {
+    return e + (e >> 4);
+  } else {
+    using S = LdsSwizzle<N>;
+    int x = 0;
+#pragma unroll
+    for (int j = 0; j < S::NBITS; j++) x ^= ((e >> (S::LB + j)) & 1) ? S::col(j) : 0;
+    return e ^ x;
+  }
+}
+
+// address of element base + off where off's bits are clear in base (off a constant)
+template <int N>
+__device__ __forceinline__ int lds_pad_add(int base, int base_addr, int off) {
+  if constexpr (GBL_LDS_LAYOUT == 0) {
+    (void)base_addr;
+    return lds_pad<N>(base + off);
+  } else {
+    (void)base;
+    return base_addr ^ lds_pad<N>(off);
+  }
+}
 
 template <int N>
 constexpr int series_pitch() {
-  return N + N / 16;
+  return GBL_LDS_LAYOUT == 0 ? N + N / 16 : N;
 }
 
 // threads per block for template width N: one sample and one bin per thread
@@ -580,9 +631,10 @@ __device__ __forceinline__ void fft_pass(cx<F>* buf, const cx<F>* __restrict__ t
     int grp = beta / ST, i = beta % ST;
     int base = grp * R * ST + i;
     cx<F>* b = buf + sidx * SP;
+    const int base_addr = GBL_LDS_LAYOUT == 0 ? 0 : lds_pad<N>(base);
     cx<F> x[R];
 #pragma unroll
-    for (int r = 0; r < R; r++) x[r] = b[lds_pad(base + ST * r)];
+    for (int r = 0; r < R; r++) x[r] = b[lds_pad_add<N>(base, base_addr, ST * r)];
     if constexpr (R == 4) dft4(x);
     if constexpr (R == 2) dft2(x);
     if constexpr (ST > 1) {
@@ -590,7 +642,7 @@ __device__ __forceinline__ void fft_pass(cx<F>* buf, const cx<F>* __restrict__ t
       for (int r = 1; r < R; r++) x[r] = x[r] * tw[TWS * i * r];
     }
 #pragma unroll
-    for (int r = 0; r < R; r++) b[lds_pad(base + ST * r)] = x[r];
+    for (int r = 0; r < R; r++) b[lds_pad_add<N>(base, base_addr, ST * r)] = x[r];
   }
 }
 
@@ -621,8 +673,9 @@ __device__ __forceinline__ void template_transform(const Src& s, const Geo& g, c
     double t = ((double)n + 0.5) * g.T / (double)N;
     cx<F> v[6];
     slow_sample<NSER, F>(s, g, tb.basis, n, t, v);
+    const int a = lds_pad<N>(n);
 #pragma unroll
-    for (int c = 0; c < NSER; c++) buf[c * SP + lds_pad(n)] = v[c];
+    for (int c = 0; c < NSER; c++) buf[c * SP + a] = v[c];
   }
   __syncthreads();
   fft_stages<N, NT, NSER, N>(buf, tb.fft_tw, tid);
@@ -639,7 +692,7 @@ __device__ __forceinline__ void bin_spectrum(const Src& s, const Geo& g, const W
                                              int j, cx<F>* out) {
   constexpr int SP = series_pitch<N>();
   const int kk = (j + N / 2) & (N - 1);
-  const int pos = lds_pad(fft_pos<N>(kk));
+  const int pos = lds_pad<N>(fft_pos<N>(kk));
   const double cyc = -(double)(s.q + (int64_t)(j - N / 2)) * (g.Lc / g.T);
   cx<F> D;
   expi_cycles_k<1, F>(&cyc, &D);

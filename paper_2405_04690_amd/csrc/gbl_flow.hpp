@@ -60,7 +60,7 @@ struct FlowArgs {
   // sample i's band when no band array is given: (i / band_div) % band_mod
   int64_t band_div;
   int32_t band_mod;
-  // with a mask, sample i is processed only if (mask[i] != 0) == mask_want
+  // with a mask, sample i is processed only if mask[i] == mask_want
   int32_t mask_want;
   const int32_t* mask;
 };
@@ -245,7 +245,7 @@ __global__ __launch_bounds__(256) void k_flow_apply(FlowArgs fa, const double* i
   for (int64_t tile = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); tile < n_tiles; tile += (int64_t)gridDim.x * 4) {
     const int64_t idx = tile * 16 + c;
     bool inb = idx < B;
-    if (inb && fa.mask && ((fa.mask[idx] != 0) != (fa.mask_want != 0))) inb = false;  // not ours: no output
+    if (inb && fa.mask && fa.mask[idx] != fa.mask_want) inb = false;  // not ours: no output
     int b = inb ? (band ? band[idx] : (int)((idx / fa.band_div) % fa.band_mod)) : 0;
     bool valid = inb && b >= 0 && b < fa.n_emb;
     if (!valid) b = 0;

@@ -673,25 +673,75 @@ __global__ __launch_bounds__(256) void k_sweep_group(SweepArgs a, int every) {
   if (threadIdx.x == 0) a.group_count[b] = count;
 }
 
-// standard normals for the flow's birth candidates of the empty slots:
-// Box-Muller on the sweep's stream, unit (t, w, b), move RJ, draws 2048 + 16 s + k
-__global__ void k_rj_normals(SweepArgs a, double* z) {
+// RJ candidates of the flow-and-prior mixture proposal.  Per slot (unit
+// (t, w, b), move RJ, draws 2048 + 16 s + k): an occupied slot gets mode 0
+// (density at its source); an empty slot draws c = U(2048 + 16 s + 8) and,
+// if c < prior_weight, a prior point from the uniforms k = 0..7 (mode 2),
+// else 8 standard normals by Box-Muller from the same uniforms (mode 1), to be
+// pushed through the flow.
+template <int N>
+__global__ void k_rj_draw(Geo g, SweepArgs a, double prior_weight, double* prop, int32_t* mode) {
   const int64_t n = (int64_t)a.n_t * a.n_w * a.n_b * a.n_slot;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n || a.exists[i]) return;
+  if (i >= n) return;
+  if (a.exists[i]) {
+    mode[i] = 0;
+    return;
+  }
   const int s = (int)(i % a.n_slot);
   const uint64_t unit = (uint64_t)(i / a.n_slot);
+  const int b = (int)(unit % a.n_b);
   const int64_t sweep = *a.sweep_ctr;
-  for (int p = 0; p < 4; p++) {
-    const uint64_t d = 2048 + 16 * (uint64_t)s + 2 * p;
-    const double u1 = rng_uniform(a.seed, sweep, kMoveRJ, unit, d);
-    const double u2 = rng_uniform(a.seed, sweep, kMoveRJ, unit, d + 1);
-    const double r = sqrt(-2.0 * log(u1));
-    double sn, cs;
-    sincospi(2.0 * u2, &sn, &cs);
-    z[8 * i + 2 * p] = r * cs;
-    z[8 * i + 2 * p + 1] = r * sn;
+  const uint64_t d0 = 2048 + 16 * (uint64_t)s;
+  double uu[8];
+  for (int k = 0; k < 8; k++) uu[k] = rng_uniform(a.seed, sweep, kMoveRJ, unit, d0 + k);
+  const double c = rng_uniform(a.seed, sweep, kMoveRJ, unit, d0 + 8);
+  if (c < prior_weight) {
+    double flo, fhi;
+    band_f0_range<N>(g, a, b, flo, fhi);
+    for (int k = 0; k < 8; k++) {
+      double lo = a.lo[k], hi = a.hi[k];
+      if (k == 1) {
+        lo = flo;
+        hi = fhi;
+      } else if (period_of(k) > 0) {
+        lo = 0.0;
+        hi = period_of(k);
+      }
+      prop[8 * i + k] = lo + (hi - lo) * uu[k];
+    }
+    mode[i] = 2;
+  } else {
+    for (int p = 0; p < 4; p++) {
+      const double r = sqrt(-2.0 * log(uu[2 * p]));
+      double sn, cs;
+      sincospi(2.0 * uu[2 * p + 1], &sn, &cs);
+      prop[8 * i + 2 * p] = r * cs;
+      prop[8 * i + 2 * p + 1] = r * sn;
+    }
+    mode[i] = 1;
   }
+}
+
+// rj_logq <- ln[(1 - w) q_flow + w p] with rj_logq holding ln q_flow on entry
+// (NaN = outside the flow's support) and p the band's uniform prior density
+template <int N>
+__global__ void k_rj_mix(Geo g, SweepArgs a, double prior_weight, double* rj_logq) {
+  const int64_t n = (int64_t)a.n_t * a.n_w * a.n_b * a.n_slot;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int b = (int)((i / a.n_slot) % a.n_b);
+  const double lp = -log_box_volume<N>(g, a, b);
+  const double lf = rj_logq[i];
+  if (prior_weight <= 0.0) return;  // pure flow: ln q_flow as it is
+  const double x = log(prior_weight) + lp;
+  if (!(lf == lf) || prior_weight >= 1.0) {
+    rj_logq[i] = x;
+    return;
+  }
+  const double y = log1p(-prior_weight) + lf;
+  const double m = fmax(x, y);
+  rj_logq[i] = m + log1p(exp(-fabs(x - y)));
 }
 
 __global__ void k_sweep_advance(int64_t* sweep_ctr) {

@@ -32,9 +32,11 @@ def init_params(seed: int, n_emb: int) -> np.ndarray:
     return np.concatenate(out).astype(np.float32)
 
 
-def flow_config(n_emb: int, width: int, k_band0: int, prior_lo, prior_hi) -> FlowConfig:
+def flow_config(n_emb: int, width: int, k_band0: int, prior_lo, prior_hi, prior_weight: float = 0.2) -> FlowConfig:
+    """prior_weight: share of prior draws in the sampler's RJ proposal mixture"""
     c = FlowConfig()
     c.n_emb, c.width, c.k_band0 = int(n_emb), int(width), int(k_band0)
+    c.prior_weight = float(prior_weight)
     for i in range(8):
         c.prior_lo[i] = float(prior_lo[i])
         c.prior_hi[i] = float(prior_hi[i])

@@ -60,7 +60,8 @@ class SweepConfig(ctypes.Structure):
 class SweepState(ctypes.Structure):
     """gbl_sweep_state (device pointers)"""
     _fields_ = [(n, ctypes.c_void_p) for n in ("u", "exists", "betas", "resid", "inv_psd", "group", "group_count",
-                                              "stats", "sweep_counter", "prop_u", "rj_logq", "cold_logl")]
+                                              "stats", "sweep_counter", "prop_u", "rj_logq", "cold_logl",
+                                              "rj_mode")]
 
 
 class Tuning(ctypes.Structure):
@@ -75,7 +76,7 @@ class Tuning(ctypes.Structure):
 class FlowConfig(ctypes.Structure):
     """gbl_flow_config"""
     _fields_ = [("n_emb", ctypes.c_int32), ("width", ctypes.c_int32), ("k_band0", ctypes.c_int64),
-                ("prior_lo", ctypes.c_double * 8), ("prior_hi", ctypes.c_double * 8)]
+                ("prior_lo", ctypes.c_double * 8), ("prior_hi", ctypes.c_double * 8), ("prior_weight", ctypes.c_double)]
 
 
 class FlowState(ctypes.Structure):
@@ -91,6 +92,7 @@ def load_library(path: str = LIB_PATH):
     global _lib
     if _lib is not None:
         return _lib
+    path = os.environ.get("GBL_LIBRARY", path)   # an alternative build of the same library
     if not os.path.exists(path):
         raise ImportError(f"{path} not found: build the HIP library first (python -m paper_2405_04690_amd.build)")
     lib = ctypes.CDLL(path)

@@ -6,11 +6,14 @@ Problem: sub-bands of width N from bin k_band0, each holding one loud and one
 near-threshold injected source in stationary Gaussian noise; every chain
 starts from the injections.  The sampler first runs with prior RJ draws and
 collects cold-chain samples; the flow is trained on them with the library's
-own training kernels; then, from the same saved state, the same number of
-sweeps runs once with prior RJ draws and once with the flow as the RJ
-proposal, recording per sweep the cold chain's source count and band
-log-likelihood per (walker, band).  Everything runs through the C ABI; only
-the bookkeeping (trace copies, ESS) is host-side.
+own training kernels.  Two measurements follow, each once with prior RJ
+draws and once with the flow mixture (prior share 0.2) as the RJ proposal:
+(1) stationary mixing: from the same saved state, the same number of sweeps,
+recording per sweep the cold chain's source count and band log-likelihood
+per (walker, band) for their ESS per second; (2) discovery: from every slot
+empty, the fraction of (walker, injected source) pairs the cold chain has
+recovered per sweep.  Everything runs through the C ABI; only the
+bookkeeping (trace copies, ESS, recovery fractions) is host-side.
 """
 from __future__ import annotations
 
@@ -26,8 +29,13 @@ from .flow import Flow, flow_config
 from .gbl import Context
 from .sampler import Sweep, make_config
 
-PRIOR_LO = (-24.0, 0.0, -1e-17, 0.0, -1.0, 0.0, 0.0, -1.0)
-PRIOR_HI = (-20.0, 0.0, 1e-17, 0.0, 1.0, 0.0, 0.0, 1.0)
+# amplitude prior: log10 A from the amplitude of an SNR_MIN source at the
+# injections' median sensitivity up to 2.5 decades above (sources too quiet to
+# be resolved are outside the model, as with the paper's final SNR limit of 5
+# in the search-to-PE schedule); fdot in a narrow symmetric range
+SNR_MIN = 5.0
+LOG10A_SPAN = 2.5
+FDOT_MAX = 1e-17
 
 
 @dataclass
@@ -37,6 +45,7 @@ class Problem:
     fcfg: object
     sources: np.ndarray
     snr: np.ndarray
+    data: torch.Tensor
 
 
 def _to_u(p):
@@ -53,7 +62,7 @@ def _physical(u):
 
 
 def build(cfg=inputs.TINY, N=128, n_temps=4, n_walkers=32, n_bands=8, n_slots=6, snr=(20.0, 7.0), seed=60,
-          f_start=3e-3, stream=None) -> Problem:
+          f_start=3e-3, stream=None, snr_min: float = SNR_MIN) -> Problem:
     dev = torch.device("cuda", torch.cuda.current_device())
     ctx = Context(T=cfg.T, dt=cfg.dt, L=cfg.L, f_lo=cfg.f_lo, f_hi=cfg.f_hi, device=dev, stream=stream)
     T = cfg.T
@@ -71,10 +80,13 @@ def build(cfg=inputs.TINY, N=128, n_temps=4, n_walkers=32, n_bands=8, n_slots=6,
     snr_unit = torch.sqrt(-2.0 * dl).cpu().numpy()
     target = np.tile(np.asarray(snr, dtype=np.float64), n_bands)
     src[:, 0] = target / snr_unit
+    lo_a = float(np.log10(snr_min / np.median(snr_unit)))
+    prior_lo = (lo_a, 0.0, -FDOT_MAX, 0.0, -1.0, 0.0, 0.0, -1.0)
+    prior_hi = (lo_a + LOG10A_SPAN, 0.0, FDOT_MAX, 0.0, 1.0, 0.0, 0.0, 1.0)
     d = ctx.gb_make_noise(S, torch.from_numpy(inputs.complex_normals(seed + 1, (1, 2, ctx.n_bins))).to(dev))
     ctx.gb_scatter_add(torch.from_numpy(src).to(dev), N, 1.0, d)
     sc = make_config(n_temps, n_walkers, n_bands, n_slots, N, k_band0, n_prop=20, n_friends=8, group_every=10,
-                     seed=seed + 2, prior_lo=PRIOR_LO, prior_hi=PRIOR_HI)
+                     seed=seed + 2, prior_lo=prior_lo, prior_hi=prior_hi)
     sw = Sweep(ctx, sc)
     u0 = np.zeros((n_bands, n_slots, 8))
     e0 = np.zeros((n_bands, n_slots), np.int32)
@@ -94,9 +106,9 @@ def build(cfg=inputs.TINY, N=128, n_temps=4, n_walkers=32, n_bands=8, n_slots=6,
         sel = (sw.exists[0] != 0) & (band_par == par)
         ctx.gb_scatter_add(_physical(sw.u[0][sel].contiguous()), N, -1.0, sw.resid[par], walker[sel].contiguous())
     sw.enable_logl_trace()
-    fcfg = flow_config(n_bands, N, k_band0, PRIOR_LO, PRIOR_HI)
+    fcfg = flow_config(n_bands, N, k_band0, prior_lo, prior_hi)
     torch.cuda.synchronize()
-    return Problem(ctx, sw, fcfg, src, target)
+    return Problem(ctx, sw, fcfg, src, target, d)
 
 
 _STATE = ("u", "exists", "resid", "group", "group_count", "stats", "sweep_counter")
@@ -132,7 +144,7 @@ def train(flow: Flow, u, band, steps: int, batch: int = 4096, lr: float = 1e-3, 
     losses = []
     for _ in range(steps):
         idx = torch.randint(0, u.shape[0], (batch,), generator=gen, device=u.device)
-        losses.append(flow.train_step(u[idx].contiguous(), band[idx].contiguous(), lr))
+        losses.append(flow.train_step(u[idx].contiguous(), band[idx].contiguous(), lr).clone())
     return torch.stack(losses).view(-1).cpu().numpy()
 
 
@@ -165,6 +177,54 @@ def measure(sw: Sweep, n_sweeps: int, flow: Flow | None = None):
             "mean_k": float(k.mean())}
 
 
+def empty_state(problem: Problem):
+    """every slot empty, both cold-chain buffers = the data"""
+    sw = problem.sweep
+    st = save(sw)
+    st["exists"] = torch.zeros_like(sw.exists)
+    st["resid"] = problem.data.expand(sw.resid.shape[1], -1, -1).unsqueeze(0).expand(2, -1, -1, -1).contiguous()
+    st["stats"] = torch.zeros_like(sw.stats)
+    return st
+
+
+def recovered(problem: Problem, tol_bins: float = 1.0, tol_log10a: float = 0.3):
+    """fraction of (walker, injected source) pairs whose source the cold chain holds:
+    an occupied slot of its sub-band within tol_bins of its f0 and tol_log10a of its log10 A"""
+    sw = problem.sweep
+    c = sw.cfg
+    per_band = len(problem.sources) // c.n_bands
+    u = sw.u[0]                        # [n_w][n_b][n_slot][8]
+    ex = sw.exists[0] != 0
+    src = torch.from_numpy(problem.sources).to(u.device).view(c.n_bands, per_band, 8)
+    f_inj = src[..., 1]
+    a_inj = torch.log10(src[..., 0])
+    df = (u[:, :, None, :, 1] - f_inj[None, :, :, None]).abs() * problem.ctx.T   # [w][b][j][s]
+    da = (u[:, :, None, :, 0] - a_inj[None, :, :, None]).abs()
+    hit = (df < tol_bins) & (da < tol_log10a) & ex[:, :, None, :]
+    return hit.any(dim=-1).double().mean(dim=(0, 1)).cpu().numpy()   # per source rank j
+
+
+def discover(problem: Problem, n_sweeps: int, flow: Flow | None, start):
+    """from `start` (all slots empty), n_sweeps sweeps; recovered fractions per sweep"""
+    sw = problem.sweep
+    restore(sw, start)
+    traj = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(n_sweeps):
+        if flow is None:
+            sw.disable_proposals()
+            sw.run(1)
+        else:
+            sw.run_flow(flow, 1)
+        traj.append(recovered(problem))
+    wall = time.perf_counter() - t0
+    traj = np.array(traj)              # [n_sweeps][per_band]
+    return {"wall_s": wall, "final": traj[-1].tolist(), "mean": traj.mean(axis=0).tolist(),
+            "sweeps_to_half": [int(np.argmax(traj[:, j] >= 0.5)) if np.any(traj[:, j] >= 0.5) else None
+                               for j in range(traj.shape[1])]}
+
+
 def compare(problem: Problem, burn: int = 100, collect_sweeps: int = 200, train_steps: int = 300,
             measure_sweeps: int = 400, lr: float = 1e-3, seed: int = 0):
     """burn-in and sample collection with prior RJ, flow training, then the
@@ -183,10 +243,15 @@ def compare(problem: Problem, burn: int = 100, collect_sweeps: int = 200, train_
     plain = measure(sw, measure_sweeps, None)
     restore(sw, state)
     learned = measure(sw, measure_sweeps, flow)
+    start = empty_state(problem)
+    disc_plain = discover(problem, measure_sweeps, None, start)
+    disc_learned = discover(problem, measure_sweeps, flow, start)
+    restore(sw, state)
     return {"training_samples": int(u.shape[0]), "train_steps": train_steps,
             "train_ms_per_step": 1e3 * t_train / max(1, train_steps),
             "loss_first": float(np.mean(losses[:10])), "loss_last": float(np.mean(losses[-10:])),
             "plain": plain, "learned": learned,
+            "discovery": {"plain": disc_plain, "learned": disc_learned},
             "gain_ess_k_per_s": learned["ess_k_per_s"] / max(plain["ess_k_per_s"], 1e-300),
             "gain_ess_logl_per_s": learned["ess_logl_per_s"] / max(plain["ess_logl_per_s"], 1e-300),
             "gain_birth_acceptance": learned["birth_acceptance"] / max(plain["birth_acceptance"], 1e-300)}, flow

@@ -51,6 +51,7 @@ class Sweep:
         self.prop_u = None
         self.rj_logq = None
         self.cold_logl = None
+        self.rj_mode = None
         self._graph = None
 
     def enable_proposals(self):
@@ -59,10 +60,12 @@ class Sweep:
         dev = self.ctx.device
         self.prop_u = torch.zeros((c.n_temps, c.n_walkers, c.n_bands, c.n_slots, 8), dtype=torch.float64, device=dev)
         self.rj_logq = torch.zeros((c.n_temps, c.n_walkers, c.n_bands, c.n_slots), dtype=torch.float64, device=dev)
+        self.rj_mode = torch.zeros((c.n_temps, c.n_walkers, c.n_bands, c.n_slots), dtype=torch.int32, device=dev)
 
     def disable_proposals(self):
         self.prop_u = None
         self.rj_logq = None
+        self.rj_mode = None
 
     def enable_logl_trace(self):
         c = self.cfg
@@ -72,7 +75,7 @@ class Sweep:
     def _state(self):
         st = SweepState()
         for n in ("u", "exists", "betas", "resid", "inv_psd", "group", "group_count", "stats", "sweep_counter",
-                  "prop_u", "rj_logq", "cold_logl"):
+                  "prop_u", "rj_logq", "cold_logl", "rj_mode"):
             t = getattr(self, n)
             setattr(st, n, t.data_ptr() if t is not None else None)
         return st

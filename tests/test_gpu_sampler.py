@@ -187,10 +187,10 @@ def test_rj_with_given_proposal_densities_and_cold_logl_trace():
     ctx.close()
 
 
-def _flow_for(sc, cfg, s_bias=0.0, seed=31, identity=False):
+def _flow_for(sc, cfg, s_bias=0.0, seed=31, identity=False, prior_weight=0.2):
     from oracle import flow as oflow
-    from paper_2405_04690_amd.flow import Flow, flow_config
-    fc = flow_config(sc.n_bands, sc.N, sc.k_band0, list(sc.prior_lo), list(sc.prior_hi))
+    from paper_2405_04690_amd.flow import flow_config
+    fc = flow_config(sc.n_bands, sc.N, sc.k_band0, list(sc.prior_lo), list(sc.prior_hi), prior_weight)
     th = oflow.init_params(seed, sc.n_bands, out_scale=0.0 if identity else 0.3)
     layers, _ = oflow.unpack(th, sc.n_bands)
     for l, L in enumerate(layers):
@@ -199,14 +199,17 @@ def _flow_for(sc, cfg, s_bias=0.0, seed=31, identity=False):
     return fc, th
 
 
-def test_flow_rj_prepare_identity_flow_is_box_muller_of_the_stream():
-    """identity flow (W3 = b3 = 0): birth candidates are the box images of the
-    stream's normals and ln q is the logit-normal density"""
+def test_rj_prepare_mixture_with_identity_flow():
+    """identity flow (W3 = b3 = 0) in a 3:1 flow/prior mixture: each empty
+    slot's candidate is either the box image of the stream's Box-Muller
+    normals or a prior draw from the same uniforms (choice by the stream), and
+    ln q = ln(3/4 q_flow + 1/4 p) at candidates and current sources alike"""
     from oracle import flow as oflow
     from paper_2405_04690_amd.flow import Flow
     cfg, orc, sc, st = sampler_setup.problem(seed=41)
     ctx, sw = _gpu_sweep(cfg, sc, st)
-    fc, th = _flow_for(sc, cfg, identity=True)
+    w = 0.25
+    fc, th = _flow_for(sc, cfg, identity=True, prior_weight=w)
     fl = Flow(ctx, fc, th.astype(np.float32))
     s0 = 9
     sw.sweep_counter.fill_(s0)
@@ -214,31 +217,47 @@ def test_flow_rj_prepare_identity_flow_is_box_muller_of_the_stream():
     torch.cuda.synchronize()
     pu = sw.prop_u.cpu().numpy()
     lq = sw.rj_logq.cpu().numpy()
+    mode = sw.rj_mode.cpu().numpy()
     ex = st.exists.astype(bool)
     nt, nw, nb, ns = ex.shape
-    idx = np.argwhere(~ex)[:200]
-    for (t, w, b, s) in idx:
-        unit = ((t * nw + w) * nb + b)
-        z = np.zeros(8)
-        for p in range(4):
-            d = 2048 + 16 * s + 2 * p
-            u1 = oracle.rng_uniform(sc.seed, s0, 1, unit, d)
-            u2 = oracle.rng_uniform(sc.seed, s0, 1, unit, d + 1)
-            r = np.sqrt(-2 * np.log(u1))
-            z[2 * p], z[2 * p + 1] = r * np.cos(2 * np.pi * u2), r * np.sin(2 * np.pi * u2)
-        lo, hi = oflow.box(np.array([b]), cfg.T, sc.k_band0, sc.N, list(sc.prior_lo), list(sc.prior_hi))
-        u_ref, lj = oflow.from_real(z[None], lo, hi)
-        assert np.allclose(pu[t, w, b, s], u_ref[0], rtol=1e-12, atol=1e-12 * np.abs(hi - lo).max())
-        assert abs(lq[t, w, b, s] - (oflow.log_normal(z[None])[0] + lj[0])) <= 1e-9 * max(1.0, abs(lq[t, w, b, s]))
-    occ = np.argwhere(ex)
-    for (t, w, b, s) in occ[:100]:
-        lo, hi = oflow.box(np.array([b]), cfg.T, sc.k_band0, sc.N, list(sc.prior_lo), list(sc.prior_hi))
-        uu = st.u[t, w, b, s][None]
-        if not np.all((uu > lo) & (uu < hi)):
-            assert np.isnan(lq[t, w, b, s])
-            continue
-        x, lj = oflow.to_real(uu, lo, hi)
-        assert abs(lq[t, w, b, s] - (oflow.log_normal(x)[0] + lj[0])) <= 1e-9 * max(1.0, abs(lq[t, w, b, s]))
+    lo8 = np.array(list(sc.prior_lo))
+    hi8 = np.array(list(sc.prior_hi))
+
+    def lnq_mix(u, b):
+        lo, hi = oflow.box(np.array([b]), cfg.T, sc.k_band0, sc.N, lo8, hi8)
+        lnV = np.sum(np.log(hi - lo))
+        if np.all((u > lo) & (u < hi)):
+            x, lj = oflow.to_real(u[None], lo, hi)
+            lf = oflow.log_normal(x)[0] + lj[0]
+            return np.logaddexp(np.log1p(-w) + lf, np.log(w) - lnV)
+        return np.log(w) - lnV
+
+    n_prior = 0
+    for (t, wk, b, s) in np.argwhere(~ex)[:300]:
+        unit = (t * nw + wk) * nb + b
+        d0 = 2048 + 16 * s
+        uu = np.array([oracle.rng_uniform(sc.seed, s0, 1, unit, d0 + k) for k in range(8)])
+        c = oracle.rng_uniform(sc.seed, s0, 1, unit, d0 + 8)
+        lo, hi = oflow.box(np.array([b]), cfg.T, sc.k_band0, sc.N, lo8, hi8)
+        if c < w:
+            n_prior += 1
+            assert mode[t, wk, b, s] == 2
+            u_ref = lo[0] + (hi[0] - lo[0]) * uu
+        else:
+            assert mode[t, wk, b, s] == 1
+            z = np.zeros(8)
+            for p in range(4):
+                r = np.sqrt(-2 * np.log(uu[2 * p]))
+                z[2 * p], z[2 * p + 1] = r * np.cos(2 * np.pi * uu[2 * p + 1]), r * np.sin(2 * np.pi * uu[2 * p + 1])
+            u_ref = oflow.from_real(z[None], lo, hi)[0][0]
+        assert np.allclose(pu[t, wk, b, s], u_ref, rtol=1e-12, atol=1e-12 * np.abs(hi - lo).max())
+        ref = lnq_mix(pu[t, wk, b, s], b)
+        assert abs(lq[t, wk, b, s] - ref) <= 1e-9 * max(1.0, abs(ref))
+    assert 0 < n_prior < 300
+    for (t, wk, b, s) in np.argwhere(ex)[:100]:
+        assert mode[t, wk, b, s] == 0
+        ref = lnq_mix(st.u[t, wk, b, s], b)
+        assert abs(lq[t, wk, b, s] - ref) <= 1e-9 * max(1.0, abs(ref))
     ctx.close()
 
 
