@@ -145,6 +145,18 @@ def secondary(ctx, torch, stream, cfg, R, invS, po, pn, ri, pi):
                                    "median_abs_err_vs_fp64": float(err.median()),
                                    "frac_err_le_1e-3": float((err <= 1e-3).double().mean())}
     ctx_m.close()
+    # the same without the FP64 re-evaluation of the loud pairs (pure FP32 response)
+    from paper_2405_04690_amd.gbl import GBL_MIXED_UNROUTED
+    ctx_u = Context(T=cfg.T, dt=cfg.dt, L=cfg.L, f_lo=cfg.f_lo, f_hi=cfg.f_hi, precision=GBL_MIXED, device=dev,
+                    stream=stream, flags=GBL_MIXED_UNROUTED)
+    ms = _time_launches(torch, stream, lambda: ctx_u.gb_delta_loglike(R, invS, po, pn, cfg.N, ri, pi,
+                                                                       psd_inverse=True, out=resm), 10)
+    err = (resm - ref).abs()
+    out["mixed_precision_N256_unrouted"] = {"evals_per_s": round(B / (ms / 1e3), 1), "ms": round(ms, 4),
+                                            "max_abs_err_vs_fp64": float(err.max()),
+                                            "median_abs_err_vs_fp64": float(err.median()),
+                                            "frac_err_le_1e-3": float((err <= 1e-3).double().mean())}
+    ctx_u.close()
     # PSD-parameter log-likelihood: one parameter set per walker residual
     nw = R.shape[0]
     noise = torch.tensor([[cfg.sqrt_oms, cfg.sqrt_acc, cfg.sqrt_oms, cfg.sqrt_acc]], dtype=torch.float64,
