@@ -16,6 +16,8 @@
 //   G = n^T H n,  phi_r = Phi(xi_r) - 2 pi q t/T,  xi_r = t - k.x_r/c.
 #pragma once
 
+#include <type_traits>
+
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -248,7 +250,10 @@ __device__ __forceinline__ void sinc_cos(double u, double& sinc, double& cosu) {
 // register moves besides its FMA).  The float versions (mixed precision) use
 // the shortest truncations whose next term is below 2.5e-10 on the same
 // ranges.
-template <int K>
+// UC = 1: any |u| in band (above, with the library fallback); UC = 0: the
+// caller guarantees |u| <= 0.25 (templates below ~4.7 mHz), where sinc through
+// u^12 and cos through u^14 already leave next terms below 3e-21.
+template <int K, int UC = 1>
 __device__ __forceinline__ void sinc_cos_k(const double* u, double* sinc, double* cosu) {
   constexpr double cs_[10] = {-1.0 / 51090942171709440000.0, 1.0 / 121645100408832000.0,
                               -1.0 / 355687428096000.0,      1.0 / 1307674368000.0,
@@ -262,22 +267,24 @@ __device__ __forceinline__ void sinc_cos_k(const double* u, double* sinc, double
                               1.0 / 40320.0,                    -1.0 / 720.0,
                               1.0 / 24.0,                       -0.5,
                               1.0};
+  constexpr int S0 = UC == 0 ? 4 : 0;  // first sinc coefficient used
+  constexpr int C0 = UC == 0 ? 5 : 0;  // first cos coefficient used
   double v[K], a[K], c[K];
   bool in_range = true;
 #pragma unroll
   for (int i = 0; i < K; i++) {
     v[i] = u[i] * u[i];
     in_range = in_range && (v[i] <= 2.89);
-    a[i] = cs_[0];
-    c[i] = cc_[0];
+    a[i] = cs_[S0];
+    c[i] = cc_[C0];
   }
 #pragma unroll
-  for (int k = 1; k < 10; k++) {
+  for (int k = S0 + 1; k < 10; k++) {
 #pragma unroll
     for (int i = 0; i < K; i++) a[i] = a[i] * v[i] + cs_[k];
   }
 #pragma unroll
-  for (int k = 1; k < 13; k++) {
+  for (int k = C0 + 1; k < 13; k++) {
 #pragma unroll
     for (int i = 0; i < K; i++) c[i] = c[i] * v[i] + cc_[k];
   }
@@ -286,14 +293,14 @@ __device__ __forceinline__ void sinc_cos_k(const double* u, double* sinc, double
     sinc[i] = 1.0 - a[i] * v[i];
     cosu[i] = c[i];
   }
-  if (!in_range) {
+  if (UC != 0 && !in_range) {
     // sources far above the band: exact library evaluation
 #pragma unroll
     for (int i = 0; i < K; i++) sinc_cos(u[i], sinc[i], cosu[i]);
   }
 }
 
-template <int K>
+template <int K, int UC = 1>
 __device__ __forceinline__ void sinc_cos_k(const float* u, float* sinc, float* cosu) {
   // sinc through u^14 (next 1.7^16/17! < 1.4e-11), cos through u^14 (next < 2.3e-10)
   constexpr float cs_[7] = {-1.0f / 1307674368000.0f, 1.0f / 6227020800.0f, -1.0f / 39916800.0f,
@@ -408,7 +415,7 @@ __device__ __forceinline__ void expi_cycles_k(const double* c, cx<F>* out) {
 // The spacecraft positions, k.x/c and the receiver phases are always formed
 // in double; arm projections, link amplitudes and the TDI algebra in F.
 // ---------------------------------------------------------------------------
-template <int NSER, typename F>
+template <int NSER, typename F, int UC = 1>
 __device__ __forceinline__ void slow_sample(const Src& s, const Geo& g, const double* __restrict__ basis, int n,
                                             double t, cx<F>* out) {
   // orientation cosines/sines of the three craft
@@ -482,7 +489,7 @@ __device__ __forceinline__ void slow_sample(const Src& s, const Geo& g, const do
     amp[l] = piLc * fr[l / 2] - dterm * om;
     u[l] = om * amp[l];
   }
-  sinc_cos_k<6>(u, sc, cu);
+  sinc_cos_k<6, UC>(u, sc, cu);
   // s_{snd->rcv} = -i G w exp(-i u) P_rcv,  w = amp sinc(u)
   cx<F> lk[6];
 #pragma unroll
@@ -668,14 +675,42 @@ __device__ __forceinline__ void template_transform(const Src& s, const Geo& g, c
                                                    cx<F>* buf, int tid) {
   constexpr int SP = series_pitch<N>();
   constexpr int NT = block_threads<N>();
+  // link phases u = (1 -+ k.n) (pi f L/c - ...) stay below 2 pi (L/c) f_max plus the
+  // tiny fdot term: block-uniform choice of the short sinc/cos series
+  // (FP64 only; the FP32 series are short already)
+  const double f_max = fabs(s.f0) + fabs(s.fdot) * (g.T + 1100.0);
+  const bool small_u = std::is_same<F, double>::value &&
+                       2.0 * kPi * g.Lc * f_max + 2.0 * kPi * fabs(s.fdot) * g.Lc * g.Lc <= 0.25;
+  if constexpr (!std::is_same<F, double>::value) {
 #pragma unroll 1
-  for (int n = tid; n < N; n += NT) {
-    double t = ((double)n + 0.5) * g.T / (double)N;
-    cx<F> v[6];
-    slow_sample<NSER, F>(s, g, tb.basis, n, t, v);
-    const int a = lds_pad<N>(n);
+    for (int n = tid; n < N; n += NT) {
+      double t = ((double)n + 0.5) * g.T / (double)N;
+      cx<F> v[6];
+      slow_sample<NSER, F, 1>(s, g, tb.basis, n, t, v);
+      const int a = lds_pad<N>(n);
 #pragma unroll
-    for (int c = 0; c < NSER; c++) buf[c * SP + a] = v[c];
+      for (int c = 0; c < NSER; c++) buf[c * SP + a] = v[c];
+    }
+  } else if (small_u) {
+#pragma unroll 1
+    for (int n = tid; n < N; n += NT) {
+      double t = ((double)n + 0.5) * g.T / (double)N;
+      cx<F> v[6];
+      slow_sample<NSER, F, 0>(s, g, tb.basis, n, t, v);
+      const int a = lds_pad<N>(n);
+#pragma unroll
+      for (int c = 0; c < NSER; c++) buf[c * SP + a] = v[c];
+    }
+  } else {
+#pragma unroll 1
+    for (int n = tid; n < N; n += NT) {
+      double t = ((double)n + 0.5) * g.T / (double)N;
+      cx<F> v[6];
+      slow_sample<NSER, F, 1>(s, g, tb.basis, n, t, v);
+      const int a = lds_pad<N>(n);
+#pragma unroll
+      for (int c = 0; c < NSER; c++) buf[c * SP + a] = v[c];
+    }
   }
   __syncthreads();
   fft_stages<N, NT, NSER, N>(buf, tb.fft_tw, tid);

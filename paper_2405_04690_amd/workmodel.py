@@ -13,6 +13,8 @@ kernel evaluates, per template of width N:
     arm terms, 3 arms: direction 15, k.n 5, p.n 3, q.n 5, G 13      -> 41 each
     links, 6: amplitude/phase 6, sinc & cos Taylor (13 + 14 FMA) 54,
       envelope products 17                                           -> 77 each
+      (59 each for templates whose link phases stay below 0.25, about
+      f0 < 4.7 mHz, where the series stop 9 FMA earlier)
     TDI pieces and A/E combinations                                  -> 48
     common phase terms                                               -> 7
   FFT: 5 N log2 N per series (the standard radix-2 count), 4 series
@@ -29,12 +31,22 @@ PARAM_BYTES = 64
 BIN_BYTES = 2 * (16 + 8)  # A and E: complex128 residual + float64 inverse PSD
 
 
-def flops_per_sample() -> int:
-    return 7 + 3 * 71 + 3 * 41 + 6 * 77 + 48
+C_LIGHT = 299792458.0
 
 
-def flops_per_template(N: int, n_series: int = 4) -> int:
-    return N * flops_per_sample() + n_series * 5 * N * int(math.log2(N)) + N * 54
+def flops_per_sample(small_u: bool = False) -> int:
+    return 7 + 3 * 71 + 3 * 41 + 6 * (59 if small_u else 77) + 48
+
+
+def flops_per_template(N: int, n_series: int = 4, small_u: bool = False) -> int:
+    return N * flops_per_sample(small_u) + n_series * 5 * N * int(math.log2(N)) + N * 54
+
+
+def small_link_phase(params: np.ndarray, T: float, L: float = 2.5e9) -> np.ndarray:
+    """templates whose link phases stay below 0.25 (the kernel's rule)"""
+    Lc = L / C_LIGHT
+    f_max = np.abs(params[:, 1]) + np.abs(params[:, 2]) * (T + 1100.0)
+    return 2 * math.pi * Lc * f_max + 2 * math.pi * np.abs(params[:, 2]) * Lc * Lc <= 0.25
 
 
 def union_bins(params_old: np.ndarray, params_new: np.ndarray, T: float, N: int) -> np.ndarray:
@@ -52,8 +64,12 @@ def union_bins(params_old: np.ndarray, params_new: np.ndarray, T: float, N: int)
 def launch_work(params_old: np.ndarray, params_new: np.ndarray, T: float, N: int):
     """(algorithmic bytes, algorithmic FP64 flops) of one batched launch."""
     U = union_bins(params_old, params_new, T, N)
-    n_tmpl = int(np.sum(params_old[:, 0] != 0) + np.sum(params_new[:, 0] != 0))
     B = params_old.shape[0]
     bytes_ = int(B * (2 * PARAM_BYTES + 8) + BIN_BYTES * U.sum())
-    flops = int(n_tmpl * flops_per_template(N) + 20 * U.sum())
+    flops = 20 * int(U.sum())
+    for p in (params_old, params_new):
+        live = p[:, 0] != 0
+        small = small_link_phase(p, T) & live
+        flops += int(small.sum()) * flops_per_template(N, small_u=True)
+        flops += int((live & ~small).sum()) * flops_per_template(N)
     return bytes_, flops
