@@ -111,16 +111,14 @@ const char* gbl_last_error(const gbl_ctx* ctx);
 int gbl_band(const gbl_ctx* ctx, int64_t* k_min, int64_t* n_bins);
 
 /* Launch-shape knobs of a context (set by the autotuner, paper_2405_04690_amd/autotune.py):
- *   route_grid    work-groups of the FP64 re-evaluation pass of mixed-precision
- *                 contexts, in [64, 65536] (default 2048);
  *   flow_grid     maximum work-groups of a flow inference launch, in [64, 65536]
  *                 (default 4096);
- *   bucket_chunk  templates per bucketed (uneven-width / routed) launch group, a
+ *   bucket_chunk  templates per bucketed launch group (uneven widths; the FP64
+ *                 re-evaluation of mixed-precision pairs), a
  *                 power of two in [4096, 1048576] (default 1048576);
  *   widest_first  uneven widths: launch the widest bucket first (1) or last (0).
  * Results do not depend on them (bitwise for the FP64 paths). */
 typedef struct {
-  int32_t route_grid;
   int32_t flow_grid;
   int32_t bucket_chunk;
   int32_t widest_first;

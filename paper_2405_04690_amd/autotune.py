@@ -3,9 +3,9 @@ times each candidate setting on the caller's own workload with HIP events on
 the context's stream and keeps the fastest.  Results can be cached in a JSON
 file keyed by device, precision and a workload tag.
 
-Knobs: the uneven-width bucket group size and launch order (length-bucketed
-scheduling), the grid of the mixed-precision FP64 re-evaluation pass, and the
-grid cap of the flow inference launches."""
+Knobs: the bucket group size (uneven widths and the mixed-precision FP64
+re-evaluation), the launch order of the width buckets, and the grid cap of
+the flow inference launches."""
 from __future__ import annotations
 
 import itertools
@@ -19,7 +19,6 @@ from .gbl import Context
 __all__ = ["time_call", "tune", "tune_delta_var", "tune_flow", "load_cached", "store_cached"]
 
 CHUNKS = (1 << 14, 1 << 16, 1 << 18, 1 << 20)
-ROUTE_GRIDS = (512, 1024, 2048, 4096, 8192)
 FLOW_GRIDS = (512, 1024, 2048, 4096, 8192, 16384)
 
 
@@ -54,14 +53,11 @@ def tune(ctx: Context, fn, space: dict, reps: int = 5):
 
 
 def tune_delta_var(ctx: Context, args: tuple, kwargs: dict | None = None, reps: int = 5):
-    """knobs of gb_delta_loglike_var on the given call (bucket group size,
-    launch order; FP64 re-evaluation grid in mixed contexts)"""
+    """knobs of gb_delta_loglike_var on the given call (bucket group size, launch order)"""
     kwargs = dict(kwargs or {})
     out = torch.empty(args[2].shape[0], dtype=torch.float64, device=ctx.device)
     kwargs["out"] = out
-    space = {"bucket_chunk": [c for c in CHUNKS if c <= max(CHUNKS)], "widest_first": [1, 0]}
-    if ctx.cfg.precision == 1:
-        space["route_grid"] = list(ROUTE_GRIDS)
+    space = {"bucket_chunk": list(CHUNKS), "widest_first": [1, 0]}
     return tune(ctx, lambda: ctx.gb_delta_loglike_var(*args, **kwargs), space, reps)
 
 

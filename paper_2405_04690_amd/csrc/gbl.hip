@@ -91,7 +91,7 @@ extern "C" int gbl_create(gbl_ctx** out, const gbl_config* cfg, void* hip_stream
   if (cfg->precision != GBL_FP64 && cfg->precision != GBL_MIXED) return GBL_EUNSUPPORTED;
 
   gbl_ctx* ctx = new gbl_ctx();
-  ctx->tune = gbl_tuning{2048, 4096, kBucketCap, 1};
+  ctx->tune = gbl_tuning{4096, kBucketCap, 1};
   ctx->cfg = *cfg;
   ctx->stream = (hipStream_t)hip_stream;
   int64_t k_min = (int64_t)std::ceil(cfg->f_lo * cfg->T);
@@ -250,8 +250,7 @@ static gbl::DeltaArgs with_route(gbl_ctx* ctx, gbl::DeltaArgs da, int N, int64_t
 template <int N>
 static void launch_route_pass(gbl_ctx* ctx, const gbl::DeltaArgs& da, int64_t b0, int64_t nb) {
   const int slot = width_slot(N);
-  const int64_t grid = nb < ctx->tune.route_grid ? nb : ctx->tune.route_grid;
-  hipLaunchKernelGGL((gbl::k_delta_loglike_list<N>), dim3((unsigned)grid), dim3(gbl::block_threads<N>()), 0,
+  hipLaunchKernelGGL((gbl::k_delta_loglike_list<N>), dim3((unsigned)nb), dim3(gbl::block_threads<N>()), 0,
                      ctx->stream, ctx->geo, tables_for<N, double>(ctx), da, b0,
                      (const int*)(ctx->route_counts + slot), (const int32_t*)(ctx->route_lists + (int64_t)slot * kBucketCap));
 }
@@ -899,7 +898,7 @@ extern "C" int gbl_set_tuning(gbl_ctx* ctx, const gbl_tuning* t) {
   if (!ctx) return GBL_EINVAL;
   if (!t) return fail(ctx, GBL_EINVAL, "gbl_set_tuning: null tuning%s");
   const bool pow2 = t->bucket_chunk > 0 && (t->bucket_chunk & (t->bucket_chunk - 1)) == 0;
-  if (t->route_grid < 64 || t->route_grid > 65536 || t->flow_grid < 64 || t->flow_grid > 65536 || !pow2 ||
+  if (t->flow_grid < 64 || t->flow_grid > 65536 || !pow2 ||
       t->bucket_chunk < 4096 || t->bucket_chunk > kBucketCap || (t->widest_first != 0 && t->widest_first != 1))
     return fail(ctx, GBL_EINVAL, "gbl_set_tuning: knob out of range%s");
   ctx->tune = *t;

@@ -324,26 +324,30 @@ __device__ __forceinline__ void delta_one(const Geo& g, const WaveTables<F>& tb,
   }
 }
 
+// occupancy target of the fused kernel: four waves per SIMD at N <= 256 (the
+// compiler then keeps 128 VGPRs and spills a few values to scratch, which
+// measures faster than three waves without spills)
+template <int N>
+constexpr int delta_min_waves() {
+  return N <= 256 ? 4 : 1;
+}
+
 template <int N, typename F>
-__global__ __launch_bounds__(block_threads<N>()) void k_delta_loglike(Geo g, WaveTables<F> tb, DeltaArgs da,
-                                                                      int64_t b0) {
+__global__ __launch_bounds__(block_threads<N>(), delta_min_waves<N>()) void k_delta_loglike(Geo g, WaveTables<F> tb,
+                                                                                            DeltaArgs da, int64_t b0) {
   __shared__ DeltaSmem<N, F> sm;
   delta_one<N, F>(g, tb, da, b0 + blockIdx.x, sm);
 }
 
 // FP64 pass over a list of pairs (the mixed-precision pairs whose error
-// estimate is too large); a fixed grid walks the list.
+// estimate is too large): block i takes entry i, blocks past the count exit.
 template <int N>
-__global__ __launch_bounds__(block_threads<N>()) void k_delta_loglike_list(Geo g, WaveTables<double> tb,
-                                                                           DeltaArgs da, int64_t b0,
-                                                                           const int* __restrict__ count,
-                                                                           const int32_t* __restrict__ list) {
+__global__ __launch_bounds__(block_threads<N>(), delta_min_waves<N>()) void k_delta_loglike_list(
+    Geo g, WaveTables<double> tb, DeltaArgs da, int64_t b0, const int* __restrict__ count,
+    const int32_t* __restrict__ list) {
   __shared__ DeltaSmem<N, double> sm;
-  const int n = *count;
-  for (int i = blockIdx.x; i < n; i += gridDim.x) {
-    delta_one<N, double>(g, tb, da, b0 + list[i], sm);
-    __syncthreads();
-  }
+  if ((int)blockIdx.x >= *count) return;
+  delta_one<N, double>(g, tb, da, b0 + list[blockIdx.x], sm);
 }
 
 // ---------------------------------------------------------------------------
@@ -379,7 +383,9 @@ __global__ void k_bucket_by_width(const int32_t* __restrict__ widths, int64_t b0
 }
 
 template <int N, typename F>
-__global__ __launch_bounds__(block_threads<N>()) void k_delta_loglike_bucket(Geo g, WaveTables<F> tb, DeltaArgs da,
+__global__ __launch_bounds__(block_threads<N>(), delta_min_waves<N>()) void k_delta_loglike_bucket(Geo g,
+                                                                                                   WaveTables<F> tb,
+                                                                                                   DeltaArgs da,
                                                                              int64_t b0, const int* __restrict__ count,
                                                                              const int32_t* __restrict__ perm) {
   __shared__ DeltaSmem<N, F> sm;

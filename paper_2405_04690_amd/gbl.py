@@ -66,8 +66,7 @@ class SweepState(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     """gbl_tuning: launch-shape knobs of a context"""
-    _fields_ = [("route_grid", ctypes.c_int32), ("flow_grid", ctypes.c_int32), ("bucket_chunk", ctypes.c_int32),
-                ("widest_first", ctypes.c_int32)]
+    _fields_ = [("flow_grid", ctypes.c_int32), ("bucket_chunk", ctypes.c_int32), ("widest_first", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -32,8 +32,7 @@ def test_results_do_not_depend_on_the_knobs(precision):
     ctx = Context(T=cfg.T, dt=cfg.dt, L=cfg.L, f_lo=cfg.f_lo, f_hi=cfg.f_hi, precision=precision)
     R, S, old, new, w = _problem(ctx)
     ref = ctx.gb_delta_loglike_var(R, S, old, new, w).cpu().numpy()
-    for knobs in ({"bucket_chunk": 4096, "widest_first": 0, "route_grid": 64},
-                  {"bucket_chunk": 1 << 16, "widest_first": 1, "route_grid": 8192}):
+    for knobs in ({"bucket_chunk": 4096, "widest_first": 0}, {"bucket_chunk": 1 << 16, "widest_first": 1}):
         ctx.set_tuning(**knobs)
         got = ctx.gb_delta_loglike_var(R, S, old, new, w).cpu().numpy()
         assert np.array_equal(got, ref, equal_nan=True)
@@ -47,7 +46,7 @@ def test_results_do_not_depend_on_the_knobs(precision):
 def test_out_of_range_knobs_are_rejected():
     cfg = inputs.TINY
     ctx = Context(T=cfg.T, dt=cfg.dt, L=cfg.L, f_lo=cfg.f_lo, f_hi=cfg.f_hi)
-    for bad in ({"bucket_chunk": 5000}, {"bucket_chunk": 1 << 21}, {"route_grid": 1}, {"flow_grid": 10 ** 6},
+    for bad in ({"bucket_chunk": 5000}, {"bucket_chunk": 1 << 21}, {"flow_grid": 1}, {"flow_grid": 10 ** 6},
                 {"widest_first": 2}):
         with pytest.raises(GblError):
             ctx.set_tuning(**bad)
