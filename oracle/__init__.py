@@ -49,6 +49,13 @@ class SweepConfig(ctypes.Structure):
 
 
 MOVE_INMODEL, MOVE_RJ, MOVE_PT = 0, 1, 2
+MOVE_PSD, MOVE_PSDPT = 4, 5
+
+
+class PsdSweepConfig(ctypes.Structure):
+    """Noise-PSD step configuration (field order of gblo_psd_sweep_config)."""
+    _fields_ = [("n_tn", ctypes.c_int32), ("n_walkers", ctypes.c_int32), ("stretch_a", ctypes.c_double),
+                ("seed", ctypes.c_uint64), ("prior_lo", ctypes.c_double * 4), ("prior_hi", ctypes.c_double * 4)]
 
 
 _lib = None
@@ -89,6 +96,8 @@ def _load():
             "gblo_sweep_step": (ctypes.c_int, [C, ctypes.POINTER(SweepConfig), ctypes.c_int, ctypes.c_int,
                                                ctypes.c_int64, D, I32, D, D, D, D, I32, I64, D, D, D]),
             "gblo_sweep_group": (ctypes.c_int, [ctypes.POINTER(SweepConfig), D, I32, D, I32]),
+            "gblo_psd_sweep_step": (ctypes.c_int, [C, ctypes.POINTER(PsdSweepConfig), ctypes.c_int64, D, D, D, D, D,
+                                                   D, I64]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(lib, name)
@@ -304,3 +313,19 @@ def sweep_full(orc: "Oracle", sc: SweepConfig, st: SweepState, sweep: int):
     for move in (MOVE_INMODEL, MOVE_RJ, MOVE_PT):
         for parity in (1, 0):
             sweep_step(orc, sc, st, move, parity, sweep)
+
+
+def psd_sweep_step(orc: "Oracle", pc: PsdSweepConfig, sweep: int, theta, logl, betas, data, resid, inv_psd, stats):
+    """Noise-PSD step (stretch moves with vertical tempering) on host arrays, in place:
+    theta [n_tn][n_w][4], logl [n_tn][n_w], betas [n_tn], data [2][n_bins] complex,
+    resid [2][n_w][2][n_bins] complex (the sweep's cold-chain buffers), inv_psd [n_w][2][n_bins],
+    stats [4]."""
+    data = np.ascontiguousarray(data, np.complex128)
+    resid = np.ascontiguousarray(resid, np.complex128)
+    betas = np.ascontiguousarray(betas, np.float64)
+    for a, dt in ((theta, np.float64), (logl, np.float64), (inv_psd, np.float64), (stats, np.int64)):
+        assert a.dtype == dt and a.flags.c_contiguous
+    rc = orc.lib.gblo_psd_sweep_step(ctypes.byref(orc.cfg), ctypes.byref(pc), int(sweep), _d(theta), _d(logl),
+                                     _d(betas), _d(data.view(np.float64)), _d(resid.view(np.float64)), _d(inv_psd),
+                                     _i64(stats))
+    _check(rc, "psd_sweep_step")

@@ -1089,3 +1089,120 @@ int gblo_sweep_group(const gblo_sweep_config* sc, const double* u, const int32_t
   }
   return 0;
 }
+
+/* ------------------------------------------------------------------------
+ * Noise-PSD step of the sweep (Sec. 3 eq. psd with the likelihood of Sec. 2
+ * eq. like; Sec. 4: the PSD parameters are sampled with ensemble stretch
+ * moves, eq. stretch, and vertical tempering: chain (t, w) always uses walker
+ * w's residual, so a temperature swap is the plain eq. temp-orig).
+ * theta [n_tn][n_w][4] = (sqrt S_oms^A, sqrt S_acc^A, sqrt S_oms^E,
+ * sqrt S_acc^E), uniform prior box; full residual of walker w = the sum of its
+ * two cold-chain buffers minus the data.  Random numbers: stretch unit
+ * t n_w + w, move 4, draws 4 h + (0 partner, 1 z, 2 accept) for half h;
+ * swaps unit w, move 5, draw t.  stats: stretch (proposed, accepted), swaps
+ * (proposed, accepted).
+ * ------------------------------------------------------------------------ */
+#define MOVE_PSD 4
+#define MOVE_PSDPT 5
+
+typedef struct {
+  int32_t n_tn, n_walkers;
+  double stretch_a;
+  uint64_t seed;
+  double prior_lo[4], prior_hi[4];
+} gblo_psd_sweep_config;
+
+int gblo_psd_sweep_step(const gblo_config* cfg, const gblo_psd_sweep_config* pc, int64_t sweep, double* theta,
+                        double* logl, const double* betas, const double* data, const double* resid,
+                        double* inv_psd, int64_t* stats) {
+  int64_t k_min, nb;
+  gblo_band(cfg, &k_min, &nb);
+  const int nt = pc->n_tn, nw = pc->n_walkers;
+  if (nw < 2 || nw % 2) return -1;
+  /* full residual per walker: buffer 0 + buffer 1 - data */
+  double* R = (double*)malloc(sizeof(double) * (size_t)nw * 2 * nb * 2);
+  for (int w = 0; w < nw; w++)
+    for (int64_t i = 0; i < 2 * nb * 2; i++)
+      R[(int64_t)w * 2 * nb * 2 + i] = resid[((int64_t)0 * nw + w) * 2 * nb * 2 + i] +
+                                       resid[((int64_t)1 * nw + w) * 2 * nb * 2 + i] - data[i];
+  int32_t* ridx = (int32_t*)malloc(sizeof(int32_t) * (size_t)nt * nw);
+  for (int t = 0; t < nt; t++)
+    for (int w = 0; w < nw; w++) ridx[t * nw + w] = w;
+  /* current log-likelihoods against the current residuals */
+  gblo_psd_loglike(cfg, R, nw, theta, ridx, (int64_t)nt * nw, logl);
+  double* prop = (double*)malloc(sizeof(double) * (size_t)nt * nw * 4);
+  double* lprop = (double*)malloc(sizeof(double) * (size_t)nt * nw);
+  int* ok = (int*)malloc(sizeof(int) * (size_t)nt * nw);
+  double* lz = (double*)malloc(sizeof(double) * (size_t)nt * nw);
+  const int half = nw / 2;
+  for (int h = 0; h < 2; h++) {
+    /* proposals for the walkers of half h, partners from the other half (eq. stretch) */
+    for (int t = 0; t < nt; t++)
+      for (int w = h; w < nw; w += 2) {
+        uint64_t unit = (uint64_t)t * nw + w;
+        double r_pick = rng_uniform(pc->seed, sweep, MOVE_PSD, unit, 4 * (uint64_t)h + 0);
+        double r_z = rng_uniform(pc->seed, sweep, MOVE_PSD, unit, 4 * (uint64_t)h + 1);
+        int j = 2 * (int)floor(r_pick * half) + (1 - h);
+        double a = pc->stretch_a;
+        double z = ((a - 1.0) * r_z + 1.0) * ((a - 1.0) * r_z + 1.0) / a;
+        const double* X = theta + ((int64_t)t * nw + j) * 4;
+        const double* Y = theta + ((int64_t)t * nw + w) * 4;
+        double* P = prop + ((int64_t)t * nw + w) * 4;
+        int inside = 1;
+        for (int k = 0; k < 4; k++) {
+          P[k] = X[k] + z * (Y[k] - X[k]);
+          if (!(P[k] >= pc->prior_lo[k] && P[k] <= pc->prior_hi[k])) inside = 0;
+        }
+        ok[t * nw + w] = inside;
+        lz[t * nw + w] = 3.0 * log(z); /* z^(d-1), d = 4 */
+      }
+    for (int t = 0; t < nt; t++)
+      for (int w = h; w < nw; w += 2)
+        if (ok[t * nw + w]) gblo_psd_loglike(cfg, R, nw, prop + ((int64_t)t * nw + w) * 4, &w, 1, lprop + t * nw + w);
+    for (int t = 0; t < nt; t++)
+      for (int w = h; w < nw; w += 2) {
+        stats[0]++;
+        if (!ok[t * nw + w]) continue;
+        uint64_t unit = (uint64_t)t * nw + w;
+        double r_acc = rng_uniform(pc->seed, sweep, MOVE_PSD, unit, 4 * (uint64_t)h + 2);
+        double la = betas[t] * (lprop[t * nw + w] - logl[t * nw + w]) + lz[t * nw + w];
+        if (log(r_acc) < la) {
+          for (int k = 0; k < 4; k++) theta[((int64_t)t * nw + w) * 4 + k] = prop[((int64_t)t * nw + w) * 4 + k];
+          logl[t * nw + w] = lprop[t * nw + w];
+          stats[1]++;
+        }
+      }
+  }
+  /* temperature swaps per walker, hottest pair first (eq. temp-orig) */
+  for (int w = 0; w < nw; w++)
+    for (int t = nt - 1; t >= 1; t--) {
+      stats[2]++;
+      double r = rng_uniform(pc->seed, sweep, MOVE_PSDPT, (uint64_t)w, (uint64_t)t);
+      double la = (betas[t - 1] - betas[t]) * (logl[t * nw + w] - logl[(t - 1) * nw + w]);
+      if (log(r) < la) {
+        for (int k = 0; k < 4; k++) {
+          double tmp = theta[((int64_t)t * nw + w) * 4 + k];
+          theta[((int64_t)t * nw + w) * 4 + k] = theta[((int64_t)(t - 1) * nw + w) * 4 + k];
+          theta[((int64_t)(t - 1) * nw + w) * 4 + k] = tmp;
+        }
+        double tl = logl[t * nw + w];
+        logl[t * nw + w] = logl[(t - 1) * nw + w];
+        logl[(t - 1) * nw + w] = tl;
+        stats[3]++;
+      }
+    }
+  /* the cold chain's PSD for the GB likelihood */
+  double* S = (double*)malloc(sizeof(double) * 2 * nb);
+  for (int w = 0; w < nw; w++) {
+    gblo_psd_eval(cfg, theta + (int64_t)w * 4, 1, S);
+    for (int64_t i = 0; i < 2 * nb; i++) inv_psd[(int64_t)w * 2 * nb + i] = 1.0 / S[i];
+  }
+  free(S);
+  free(R);
+  free(ridx);
+  free(prop);
+  free(lprop);
+  free(ok);
+  free(lz);
+  return 0;
+}
