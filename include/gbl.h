@@ -285,6 +285,48 @@ int gb_sweep_graph_create(gbl_ctx* ctx, const gbl_sweep_config* cfg, const gbl_s
 int gb_graph_launch(gbl_graph* graph);
 
 /* ---------------------------------------------------------------------------
+ * Noise-PSD step of the sweep (Sec. 3 eq. psd with Sec. 2 eq. like; Sec. 4:
+ * the PSD parameters are sampled with ensemble stretch moves, eq. stretch,
+ * and vertical tempering -- chain (t, w) always uses walker w's residual, so a
+ * temperature swap is eq. temp-orig).  One call:
+ *   1. full residual of walker w = cold-chain buffer 0 + buffer 1 - data;
+ *   2. logl of every chain refreshed against it;
+ *   3. for half h = 0, 1: every chain (t, w) with w % 2 == h proposes
+ *      theta' = theta_j + z (theta - theta_j), j a walker of the other half at
+ *      the same temperature, z = ((a-1) u + 1)^2 / a; accepted with
+ *      ln alpha = beta_t (L' - L) + 3 ln z inside the uniform prior box;
+ *   4. per walker, swaps from the hottest pair down;
+ *   5. inv_psd[w] = 1/S at the cold chain's parameters.
+ * Random numbers: the Philox stream of the sweep (seed, *sweep_counter):
+ * stretch unit t n_w + w, move 4, draws 4 h + (0 partner, 1 z, 2 accept);
+ * swaps unit w, move 5, draw t.  n_walkers must be even.
+ * --------------------------------------------------------------------------- */
+typedef struct {
+  int32_t n_tn;          /* PSD temperatures */
+  int32_t n_walkers;     /* the sweep's walkers */
+  double stretch_a;
+  uint64_t seed;
+  double prior_lo[4];    /* box of (sqrt S_oms^A, sqrt S_acc^A, sqrt S_oms^E, sqrt S_acc^E) */
+  double prior_hi[4];
+} gbl_psd_sweep_config;
+
+typedef struct {
+  double* theta;             /* [n_tn][n_w][4] */
+  double* logl;              /* [n_tn][n_w] */
+  const double* betas;       /* [n_tn] */
+  const double* data;        /* [2][n_bins] complex: the data d (A, E) */
+  const double* resid;       /* the sweep's cold-chain buffers [2][n_w][2][n_bins] complex */
+  double* full_resid;        /* workspace [n_w][2][n_bins] complex */
+  double* inv_psd;           /* [n_w][2][n_bins], written (the sweep's 1/S) */
+  double* work;              /* workspace, 7 n_tn n_w doubles */
+  int32_t* res_idx;          /* workspace, n_tn n_w */
+  int64_t* stats;            /* [4]: stretch proposed, accepted; swaps proposed, accepted */
+  const int64_t* sweep_counter;
+} gbl_psd_sweep_state;
+
+int gb_psd_sweep_step(gbl_ctx* ctx, const gbl_psd_sweep_config* cfg, const gbl_psd_sweep_state* st);
+
+/* ---------------------------------------------------------------------------
  * Learned reversible-jump proposal: a conditional affine-coupling flow.
  *
  * The paper fits its RJ proposal distributions with Gaussian mixtures and

@@ -904,3 +904,72 @@ extern "C" int gbl_set_tuning(gbl_ctx* ctx, const gbl_tuning* t) {
   ctx->tune = *t;
   return GBL_OK;
 }
+
+// ---------------------------------------------------------------------------
+// noise-PSD step
+// ---------------------------------------------------------------------------
+static void psd_loglike_launch(gbl_ctx* ctx, const cd* residual, int n_res, const double* noise,
+                               const int32_t* res_idx, int64_t P, double* logl) {
+  for (int64_t p0 = 0; p0 < P; p0 += kPsdBatch) {
+    int64_t np = P - p0 < kPsdBatch ? P - p0 : kPsdBatch;
+    hipLaunchKernelGGL(gbl::k_psd_partial, dim3(gbl::kPsdChunks, (unsigned)np), dim3(gbl::kPsdBlock), 0,
+                       ctx->stream, ctx->geo.n_bins, ctx->psd_P1, ctx->psd_P2, residual, n_res, noise, res_idx, p0,
+                       ctx->psd_work);
+    hipLaunchKernelGGL(gbl::k_psd_final, dim3((unsigned)np), dim3(64), 0, ctx->stream, 1.0 / ctx->cfg.T,
+                       ctx->psd_work, p0, logl);
+  }
+}
+
+extern "C" int gb_psd_sweep_step(gbl_ctx* ctx, const gbl_psd_sweep_config* c, const gbl_psd_sweep_state* st) {
+  if (!ctx) return GBL_EINVAL;
+  if (!c || !st) return fail(ctx, GBL_EINVAL, "gb_psd_sweep_step: null config or state%s");
+  if (c->n_tn < 1 || c->n_walkers < 2 || c->n_walkers % 2 || !(c->stretch_a > 1.0))
+    return fail(ctx, GBL_EINVAL, "gb_psd_sweep_step: configuration out of range%s");
+  for (int k = 0; k < 4; k++)
+    if (!(c->prior_lo[k] < c->prior_hi[k])) return fail(ctx, GBL_EINVAL, "gb_psd_sweep_step: empty prior box%s");
+  if (!st->theta || !st->logl || !st->betas || !st->data || !st->resid || !st->full_resid || !st->inv_psd ||
+      !st->work || !st->res_idx || !st->stats || !st->sweep_counter)
+    return fail(ctx, GBL_EINVAL, "gb_psd_sweep_step: null state pointer%s");
+  const int nt = c->n_tn, nw = c->n_walkers, half = nw / 2;
+  const int64_t nb = ctx->geo.n_bins;
+  gbl::PsdArgs p;
+  p.nt = nt;
+  p.nw = nw;
+  p.a = c->stretch_a;
+  p.seed = c->seed;
+  for (int k = 0; k < 4; k++) {
+    p.lo[k] = c->prior_lo[k];
+    p.hi[k] = c->prior_hi[k];
+  }
+  p.theta = st->theta;
+  p.logl = st->logl;
+  p.betas = st->betas;
+  p.sweep_ctr = st->sweep_counter;
+  p.stats = (unsigned long long*)st->stats;
+  cd* full = (cd*)st->full_resid;
+  // 1. full residuals, 2. current log-likelihoods
+  hipLaunchKernelGGL(gbl::k_psd_full_resid, dim3(4096), dim3(256), 0, ctx->stream, nb, nw, (const cd*)st->resid,
+                     (const cd*)st->data, full);
+  const int n_all = nt * nw, n_half = nt * half;
+  hipLaunchKernelGGL(gbl::k_psd_res_idx, dim3((n_all + 255) / 256), dim3(256), 0, ctx->stream, nt, nw, -1,
+                     st->res_idx);
+  psd_loglike_launch(ctx, full, nw, st->theta, st->res_idx, n_all, st->logl);
+  // 3. stretch moves, half by half
+  double* prop = st->work;
+  double* lprop = prop + 4 * (int64_t)n_half;
+  double* lz = lprop + n_half;
+  double* ok = lz + n_half;
+  for (int h = 0; h < 2; h++) {
+    hipLaunchKernelGGL(gbl::k_psd_propose, dim3((n_half + 255) / 256), dim3(256), 0, ctx->stream, p, h, prop, lz, ok);
+    hipLaunchKernelGGL(gbl::k_psd_res_idx, dim3((n_half + 255) / 256), dim3(256), 0, ctx->stream, nt, nw, h,
+                       st->res_idx);
+    psd_loglike_launch(ctx, full, nw, prop, st->res_idx, n_half, lprop);
+    hipLaunchKernelGGL(gbl::k_psd_accept, dim3((n_half + 255) / 256), dim3(256), 0, ctx->stream, p, h,
+                       (const double*)prop, (const double*)lprop, (const double*)lz, (const double*)ok);
+  }
+  // 4. vertical swaps, 5. the cold chain's 1/S
+  hipLaunchKernelGGL(gbl::k_psd_swap, dim3((nw + 63) / 64), dim3(64), 0, ctx->stream, p);
+  hipLaunchKernelGGL(gbl::k_psd_eval, dim3(2048), dim3(256), 0, ctx->stream, nb, ctx->psd_P1, ctx->psd_P2,
+                     (const double*)st->theta, (int64_t)nw, 1, st->inv_psd);
+  return check_launch(ctx, "gb_psd_sweep_step");
+}

@@ -747,6 +747,113 @@ __global__ void k_rj_mix(Geo g, SweepArgs a, double prior_weight, double* rj_log
   rj_logq[i] = m + log1p(exp(-fabs(x - y)));
 }
 
+// ---------------------------------------------------------------------------
+// Noise-PSD step: stretch moves of the four noise parameters with vertical
+// tempering (one chain per temperature and walker, walker w's residual).
+// ---------------------------------------------------------------------------
+enum { kMovePsd = 4, kMovePsdPT = 5 };
+
+struct PsdArgs {
+  int nt, nw;
+  double a;
+  uint64_t seed;
+  double lo[4], hi[4];
+  double* theta;
+  double* logl;
+  const double* betas;
+  const int64_t* sweep_ctr;
+  unsigned long long* stats;
+};
+
+// full residual of walker w: buffer 0 + buffer 1 - data
+__global__ void k_psd_full_resid(int64_t nb, int nw, const cd* __restrict__ resid, const cd* __restrict__ data,
+                                 cd* __restrict__ out) {
+  const int64_t total = (int64_t)nw * 2 * nb;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t ck = i % (2 * nb);
+    out[i] = resid[i] + resid[total + i] - data[ck];
+  }
+}
+
+// res_idx for all chains (h < 0: set t n_w + w -> w) or the chains of half h
+// (set t (n_w/2) + i -> walker 2 i + h)
+__global__ void k_psd_res_idx(int nt, int nw, int h, int32_t* res_idx) {
+  const int n = h < 0 ? nt * nw : nt * (nw / 2);
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  res_idx[s] = h < 0 ? s % nw : 2 * (s % (nw / 2)) + h;
+}
+
+// proposals of half h: prop [nt][nw/2][4], lz = 3 ln z, ok = inside the prior box
+__global__ void k_psd_propose(PsdArgs p, int h, double* prop, double* lz, double* ok) {
+  const int half = p.nw / 2;
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= p.nt * half) return;
+  const int t = s / half, w = 2 * (s % half) + h;
+  const int64_t sweep = *p.sweep_ctr;
+  const uint64_t unit = (uint64_t)t * p.nw + w;
+  const double r_pick = rng_uniform(p.seed, sweep, kMovePsd, unit, 4 * (uint64_t)h + 0);
+  const double r_z = rng_uniform(p.seed, sweep, kMovePsd, unit, 4 * (uint64_t)h + 1);
+  const int j = 2 * (int)floor(r_pick * half) + (1 - h);
+  const double z = ((p.a - 1.0) * r_z + 1.0) * ((p.a - 1.0) * r_z + 1.0) / p.a;
+  const double* X = p.theta + ((int64_t)t * p.nw + j) * 4;
+  const double* Y = p.theta + ((int64_t)t * p.nw + w) * 4;
+  bool inside = true;
+  for (int k = 0; k < 4; k++) {
+    const double v = X[k] + z * (Y[k] - X[k]);
+    prop[4 * s + k] = v;
+    inside = inside && (v >= p.lo[k] && v <= p.hi[k]);
+  }
+  lz[s] = 3.0 * log(z);
+  ok[s] = inside ? 1.0 : 0.0;
+}
+
+__global__ void k_psd_accept(PsdArgs p, int h, const double* prop, const double* lprop, const double* lz,
+                             const double* ok) {
+  const int half = p.nw / 2;
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= p.nt * half) return;
+  const int t = s / half, w = 2 * (s % half) + h;
+  const int64_t c = (int64_t)t * p.nw + w;
+  atomicAdd(&p.stats[0], 1ull);
+  if (ok[s] == 0.0) return;
+  const int64_t sweep = *p.sweep_ctr;
+  const double r = rng_uniform(p.seed, sweep, kMovePsd, (uint64_t)c, 4 * (uint64_t)h + 2);
+  const double la = p.betas[t] * (lprop[s] - p.logl[c]) + lz[s];
+  if (log(r) < la) {
+    for (int k = 0; k < 4; k++) p.theta[4 * c + k] = prop[4 * s + k];
+    p.logl[c] = lprop[s];
+    atomicAdd(&p.stats[1], 1ull);
+  }
+}
+
+// vertical tempering: per walker, swaps from the hottest pair down
+__global__ void k_psd_swap(PsdArgs p) {
+  const int w = blockIdx.x * blockDim.x + threadIdx.x;
+  if (w >= p.nw) return;
+  const int64_t sweep = *p.sweep_ctr;
+  unsigned long long np = 0, na = 0;
+  for (int t = p.nt - 1; t >= 1; t--) {
+    np++;
+    const double r = rng_uniform(p.seed, sweep, kMovePsdPT, (uint64_t)w, (uint64_t)t);
+    const int64_t c1 = (int64_t)t * p.nw + w, c0 = (int64_t)(t - 1) * p.nw + w;
+    const double la = (p.betas[t - 1] - p.betas[t]) * (p.logl[c1] - p.logl[c0]);
+    if (log(r) < la) {
+      for (int k = 0; k < 4; k++) {
+        const double tmp = p.theta[4 * c1 + k];
+        p.theta[4 * c1 + k] = p.theta[4 * c0 + k];
+        p.theta[4 * c0 + k] = tmp;
+      }
+      const double tl = p.logl[c1];
+      p.logl[c1] = p.logl[c0];
+      p.logl[c0] = tl;
+      na++;
+    }
+  }
+  if (np) atomicAdd(&p.stats[2], np);
+  if (na) atomicAdd(&p.stats[3], na);
+}
+
 __global__ void k_sweep_advance(int64_t* sweep_ctr) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *sweep_ctr += 1;
 }

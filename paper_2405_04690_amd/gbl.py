@@ -31,7 +31,7 @@ EXPORTED = ("gbl_create", "gbl_destroy", "gbl_set_stream", "gbl_last_error", "gb
             "gb_sweep_run", "gb_sweep_graph_create", "gb_graph_launch", "gb_graph_destroy", "gb_flow_sizes",
             "gb_flow_pack", "gb_flow_log_prob", "gb_flow_sample", "gb_flow_grad", "gb_flow_adam",
             "gb_flow_train_step", "gb_sweep_rj_prepare", "gb_sweep_run_flow", "gb_sweep_graph_create_flow",
-            "gbl_get_tuning", "gbl_set_tuning")
+            "gbl_get_tuning", "gbl_set_tuning", "gb_psd_sweep_step")
 
 GBL_MOVE_INMODEL, GBL_MOVE_RJ, GBL_MOVE_PT = 0, 1, 2
 
@@ -70,6 +70,18 @@ class Tuning(ctypes.Structure):
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class PsdSweepConfig(ctypes.Structure):
+    """gbl_psd_sweep_config"""
+    _fields_ = [("n_tn", ctypes.c_int32), ("n_walkers", ctypes.c_int32), ("stretch_a", ctypes.c_double),
+                ("seed", ctypes.c_uint64), ("prior_lo", ctypes.c_double * 4), ("prior_hi", ctypes.c_double * 4)]
+
+
+class PsdSweepState(ctypes.Structure):
+    """gbl_psd_sweep_state (device pointers)"""
+    _fields_ = [(n, ctypes.c_void_p) for n in ("theta", "logl", "betas", "data", "resid", "full_resid", "inv_psd",
+                                              "work", "res_idx", "stats", "sweep_counter")]
 
 
 class FlowConfig(ctypes.Structure):
@@ -117,6 +129,7 @@ def load_library(path: str = LIB_PATH):
                                   ctypes.POINTER(vp)],
         "gb_graph_launch": [vp],
         "gbl_get_tuning": [vp, ctypes.POINTER(Tuning)],
+        "gb_psd_sweep_step": [vp, ctypes.POINTER(PsdSweepConfig), ctypes.POINTER(PsdSweepState)],
         "gbl_set_tuning": [vp, ctypes.POINTER(Tuning)],
         "gb_flow_sizes": [ctypes.POINTER(FlowConfig), ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64)],
         "gb_flow_pack": [vp, ctypes.POINTER(FlowConfig), ctypes.POINTER(FlowState)],

@@ -10,9 +10,10 @@ import ctypes
 import numpy as np
 import torch
 
-from .gbl import GBL_MOVE_INMODEL, GBL_MOVE_PT, GBL_MOVE_RJ, Context, SweepConfig, SweepState, _ptr
+from .gbl import (GBL_MOVE_INMODEL, GBL_MOVE_PT, GBL_MOVE_RJ, Context, PsdSweepConfig, PsdSweepState, SweepConfig,
+                  SweepState, _ptr)
 
-__all__ = ["Sweep", "make_config", "GBL_MOVE_INMODEL", "GBL_MOVE_RJ", "GBL_MOVE_PT"]
+__all__ = ["Sweep", "PsdSweep", "make_config", "psd_config", "GBL_MOVE_INMODEL", "GBL_MOVE_RJ", "GBL_MOVE_PT"]
 
 # default prior box of the sampling coordinates
 # (log10 A, f0 [per band], fdot, phi0, cos iota, psi, lambda, sin beta)
@@ -150,3 +151,51 @@ class Sweep:
         if hottest_zero and n_temps > 1:
             b[-1] = 0.0
         return b
+
+
+def psd_config(n_tn: int, n_walkers: int, prior_lo, prior_hi, stretch_a: float = 2.0, seed: int = 4321):
+    c = PsdSweepConfig()
+    c.n_tn, c.n_walkers, c.stretch_a, c.seed = int(n_tn), int(n_walkers), float(stretch_a), int(seed)
+    for k in range(4):
+        c.prior_lo[k], c.prior_hi[k] = float(prior_lo[k]), float(prior_hi[k])
+    return c
+
+
+class PsdSweep:
+    """Noise-PSD step bound to a Sweep: its cold-chain buffers, 1/S and sweep
+    counter; owns the PSD chains (theta, logl, betas) and the workspaces."""
+
+    def __init__(self, sweep: Sweep, cfg: PsdSweepConfig, data):
+        self.sweep, self.cfg = sweep, cfg
+        ctx = sweep.ctx
+        dev = ctx.device
+        nt, nw = cfg.n_tn, cfg.n_walkers
+        if nw != sweep.cfg.n_walkers:
+            raise ValueError("the PSD step needs the sweep's walkers")
+        self.data = ctx._dev(data, torch.complex128, "data")
+        if self.data.shape != (2, ctx.n_bins):
+            raise ValueError("data must have shape [2, n_bins]")
+        f64 = dict(dtype=torch.float64, device=dev)
+        self.theta = torch.zeros((nt, nw, 4), **f64)
+        self.logl = torch.zeros((nt, nw), **f64)
+        self.betas = torch.ones(nt, **f64)
+        self.full_resid = torch.zeros((nw, 2, ctx.n_bins), dtype=torch.complex128, device=dev)
+        self.work = torch.zeros(7 * nt * nw, **f64)
+        self.res_idx = torch.zeros(nt * nw, dtype=torch.int32, device=dev)
+        self.stats = torch.zeros(4, dtype=torch.int64, device=dev)
+
+    def _state(self):
+        st = PsdSweepState()
+        sw = self.sweep
+        for n, t in (("theta", self.theta), ("logl", self.logl), ("betas", self.betas), ("data", self.data),
+                     ("resid", sw.resid), ("full_resid", self.full_resid), ("inv_psd", sw.inv_psd),
+                     ("work", self.work), ("res_idx", self.res_idx), ("stats", self.stats),
+                     ("sweep_counter", sw.sweep_counter)):
+            setattr(st, n, t.data_ptr())
+        return st
+
+    def step(self):
+        ctx = self.sweep.ctx
+        ctx._sync_stream()
+        rc = ctx.lib.gb_psd_sweep_step(ctx._h, ctypes.byref(self.cfg), ctypes.byref(self._state()))
+        ctx._check(rc, "gb_psd_sweep_step")
