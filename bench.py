@@ -255,6 +255,7 @@ def sweep_bench(torch, dev, stream, n_sweeps, n_temps=36, n_walkers=32, n_prop=3
     torch.cuda.synchronize()
     graph_ms = a.elapsed_time(b) / n_sweeps
     sw.release_graph()
+    full = _full_sweep(torch, ctx, sw, stream, d, n_bands, k_band0, N, n_temps, n_walkers)
     dst = st1 - st0
     rate = lambda k: round(float(dst[k]) / (direct_ms * n_sweeps / 1e3), 1)
     acc = lambda p, q: round(float(dst[q]) / max(1.0, float(dst[p])), 4)
@@ -266,7 +267,8 @@ def sweep_bench(torch, dev, stream, n_sweeps, n_temps=36, n_walkers=32, n_prop=3
            "group_ms_amortised": round(phase_ms["group"] / 30, 3),
            "inmodel_proposals_per_s": rate(0), "rj_proposals_per_s": rate(2) + rate(4),
            "swap_proposals_per_s": rate(6),
-           "acceptance": {"inmodel": acc(0, 1), "birth": acc(2, 3), "death": acc(4, 5), "swap": acc(6, 7)}}
+           "acceptance": {"inmodel": acc(0, 1), "birth": acc(2, 3), "death": acc(4, 5), "swap": acc(6, 7)},
+           "full_gb_noise_sweep": full}
     del sw
     ctx.close()
     return out
@@ -311,6 +313,70 @@ def rj_bench(torch, dev, stream):
                            "300 from empty slots (discovery); RJ proposal = 0.8 flow + 0.2 prior")
         prob.ctx.close()
     return res
+
+
+def _full_sweep(torch, ctx, sw, stream, d, n_bands, k_band0, N, n_temps, n_walkers):
+    """The full GB + noise sweep: the sweep with the flow mixture as RJ
+    proposal (flow trained for 200 steps on the chain's current cold samples)
+    followed by the noise-PSD step (stretch moves over the four noise
+    parameters of 36 x 32 vertically tempered chains); timed directly and as
+    one captured graph."""
+    from paper_2405_04690_amd.flow import Flow, flow_config, init_params
+    from paper_2405_04690_amd.learned_rj import train
+    from paper_2405_04690_amd.sampler import DEFAULT_PRIOR_HI, DEFAULT_PRIOR_LO, PsdSweep, psd_config
+    from paper_2405_04690_amd import inputs
+    cfg = inputs.PAPER
+    fl = Flow(ctx, flow_config(n_bands, N, k_band0, DEFAULT_PRIOR_LO, DEFAULT_PRIOR_HI, 0.2), init_params(0, n_bands))
+    c = sw.cfg
+    band_of = torch.arange(n_bands, device=sw.u.device, dtype=torch.int32).view(1, n_bands, 1).expand(
+        n_walkers, -1, c.n_slots)
+    m = sw.exists[0] != 0
+    t0 = time.perf_counter()
+    losses = train(fl, sw.u[0][m].contiguous(), band_of[m].contiguous(), 200)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    nominal = np.array([cfg.sqrt_oms, cfg.sqrt_acc, cfg.sqrt_oms, cfg.sqrt_acc])
+    lo, hi = 0.5 * nominal, 2.0 * nominal
+    ps = PsdSweep(sw, psd_config(n_temps, n_walkers, lo, hi, seed=39), d[0])
+    gen = torch.Generator(device=ctx.device)
+    gen.manual_seed(40)
+    jit = 1.0 + 0.01 * torch.randn((n_temps, n_walkers, 4), generator=gen, device=ctx.device, dtype=torch.float64)
+    ps.theta.copy_(torch.from_numpy(nominal).to(ctx.device) * jit)
+    ps.betas.copy_(torch.from_numpy(sw.geometric_ladder(n_temps)).to(ctx.device))
+    sw.enable_proposals()
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+    a, b, c2 = ev(), ev(), ev()
+    a.record(stream)
+    sw.run_flow(fl, 1)
+    b.record(stream)
+    ps.step()
+    c2.record(stream)
+    torch.cuda.synchronize()
+    gb_ms, psd_ms = a.elapsed_time(b), b.elapsed_time(c2)
+    ctx.graph_begin()
+    sw.run_flow(fl, 1)
+    ps.step()
+    g = ctx.graph_end()
+    a, b = ev(), ev()
+    a.record(stream)
+    g.launch()
+    b.record(stream)
+    torch.cuda.synchronize()
+    graph_ms = a.elapsed_time(b)
+    g.destroy()
+    st = sw.stats.cpu().numpy()
+    pst = ps.stats.cpu().numpy()
+    sets = n_temps * n_walkers * 2   # refresh of every chain + one proposal per chain
+    psd_bytes = sets * ctx.n_bins * 2 * (16 + 16) + 3 * n_walkers * 2 * ctx.n_bins * 16
+    return {"flow_train_s": round(train_s, 3), "flow_loss_first_last": [round(float(losses[0]), 3),
+                                                                       round(float(losses[-1]), 3)],
+            "gb_sweep_with_flow_ms": round(gb_ms, 3), "psd_step_ms": round(psd_ms, 3),
+            "ms_per_sweep": round(gb_ms + psd_ms, 3), "graph_ms_per_sweep": round(graph_ms, 3),
+            "sweeps_per_s": round(1e3 / (gb_ms + psd_ms), 4),
+            "psd_step_algorithmic_gbs": round(psd_bytes / (psd_ms / 1e3) / 1e9, 1),
+            "psd_acceptance": round(float(pst[1]) / max(1.0, float(pst[0])), 4),
+            "psd_swap_acceptance": round(float(pst[3]) / max(1.0, float(pst[2])), 4),
+            "birth_acceptance_total": round(float(st[3]) / max(1.0, float(st[2])), 4)}
 
 
 def cpu_baseline(batch, cfg, target_s):

@@ -283,6 +283,14 @@ int gb_sweep_run(gbl_ctx* ctx, const gbl_sweep_config* cfg, const gbl_sweep_stat
 int gb_sweep_graph_create(gbl_ctx* ctx, const gbl_sweep_config* cfg, const gbl_sweep_state* st, int32_t n_sweeps,
                           gbl_graph** graph);
 int gb_graph_launch(gbl_graph* graph);
+int gb_graph_destroy(gbl_graph* graph);
+
+/* General capture: every library call enqueued on the context's stream
+ * (non-default) between gb_graph_begin and gb_graph_end is recorded into one
+ * graph, e.g. a sweep with the flow proposal followed by the noise-PSD step.
+ * No call in between may synchronise the stream. */
+int gb_graph_begin(gbl_ctx* ctx);
+int gb_graph_end(gbl_ctx* ctx, gbl_graph** graph);
 
 /* ---------------------------------------------------------------------------
  * Noise-PSD step of the sweep (Sec. 3 eq. psd with Sec. 2 eq. like; Sec. 4:
@@ -432,7 +440,6 @@ int gb_sweep_run_flow(gbl_ctx* ctx, const gbl_sweep_config* cfg, const gbl_sweep
 int gb_sweep_graph_create_flow(gbl_ctx* ctx, const gbl_sweep_config* cfg, const gbl_sweep_state* st,
                                const gbl_flow_config* fcfg, const gbl_flow* flow, int32_t n_sweeps,
                                gbl_graph** graph);
-int gb_graph_destroy(gbl_graph* graph);
 
 #ifdef __cplusplus
 }

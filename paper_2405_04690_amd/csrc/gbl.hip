@@ -973,3 +973,32 @@ extern "C" int gb_psd_sweep_step(gbl_ctx* ctx, const gbl_psd_sweep_config* c, co
                      (const double*)st->theta, (int64_t)nw, 1, st->inv_psd);
   return check_launch(ctx, "gb_psd_sweep_step");
 }
+
+// ---------------------------------------------------------------------------
+// general capture of the context's stream
+// ---------------------------------------------------------------------------
+extern "C" int gb_graph_begin(gbl_ctx* ctx) {
+  if (!ctx) return GBL_EINVAL;
+  if (!ctx->stream) return fail(ctx, GBL_EINVAL, "gb_graph_begin: capture needs a non-default stream%s");
+  if (hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+    return fail(ctx, GBL_EHIP, "gb_graph_begin: begin capture failed%s");
+  return GBL_OK;
+}
+
+extern "C" int gb_graph_end(gbl_ctx* ctx, gbl_graph** out) {
+  if (!ctx || !out) return GBL_EINVAL;
+  *out = nullptr;
+  gbl_graph* gr = new gbl_graph();
+  gr->stream = ctx->stream;
+  if (hipStreamEndCapture(ctx->stream, &gr->graph) != hipSuccess) {
+    delete gr;
+    return fail(ctx, GBL_EHIP, "gb_graph_end: end capture failed%s");
+  }
+  if (hipGraphInstantiate(&gr->exec, gr->graph, nullptr, nullptr, 0) != hipSuccess) {
+    (void)hipGraphDestroy(gr->graph);
+    delete gr;
+    return fail(ctx, GBL_EHIP, "gb_graph_end: instantiate failed%s");
+  }
+  *out = gr;
+  return GBL_OK;
+}

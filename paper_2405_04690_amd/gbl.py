@@ -31,7 +31,7 @@ EXPORTED = ("gbl_create", "gbl_destroy", "gbl_set_stream", "gbl_last_error", "gb
             "gb_sweep_run", "gb_sweep_graph_create", "gb_graph_launch", "gb_graph_destroy", "gb_flow_sizes",
             "gb_flow_pack", "gb_flow_log_prob", "gb_flow_sample", "gb_flow_grad", "gb_flow_adam",
             "gb_flow_train_step", "gb_sweep_rj_prepare", "gb_sweep_run_flow", "gb_sweep_graph_create_flow",
-            "gbl_get_tuning", "gbl_set_tuning", "gb_psd_sweep_step")
+            "gbl_get_tuning", "gbl_set_tuning", "gb_psd_sweep_step", "gb_graph_begin", "gb_graph_end")
 
 GBL_MOVE_INMODEL, GBL_MOVE_RJ, GBL_MOVE_PT = 0, 1, 2
 
@@ -129,6 +129,8 @@ def load_library(path: str = LIB_PATH):
                                   ctypes.POINTER(vp)],
         "gb_graph_launch": [vp],
         "gbl_get_tuning": [vp, ctypes.POINTER(Tuning)],
+        "gb_graph_begin": [vp],
+        "gb_graph_end": [vp, ctypes.POINTER(vp)],
         "gb_psd_sweep_step": [vp, ctypes.POINTER(PsdSweepConfig), ctypes.POINTER(PsdSweepState)],
         "gbl_set_tuning": [vp, ctypes.POINTER(Tuning)],
         "gb_flow_sizes": [ctypes.POINTER(FlowConfig), ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64)],
@@ -206,6 +208,16 @@ class Context:
             setattr(t, k, int(v))
         self._check(self.lib.gbl_set_tuning(self._h, ctypes.byref(t)), "gbl_set_tuning")
         return t
+
+    def graph_begin(self):
+        """start recording every library call on this context's stream (non-default stream)"""
+        self._sync_stream()
+        self._check(self.lib.gb_graph_begin(self._h), "gb_graph_begin")
+
+    def graph_end(self) -> "Graph":
+        h = ctypes.c_void_p()
+        self._check(self.lib.gb_graph_end(self._h, ctypes.byref(h)), "gb_graph_end")
+        return Graph(self.lib, h)
 
     # -- helpers ---------------------------------------------------------
     def _sync_stream(self):
@@ -388,3 +400,26 @@ class Context:
         rc = self.lib.gb_make_noise(self._h, _ptr(S), _ptr(normals), S.shape[0], _ptr(out))
         self._check(rc, "gb_make_noise")
         return out
+
+
+class Graph:
+    """an instantiated HIP graph of library calls (gb_graph_end)"""
+
+    def __init__(self, lib, handle):
+        self.lib, self.h = lib, handle
+
+    def launch(self):
+        rc = self.lib.gb_graph_launch(self.h)
+        if rc != GBL_OK:
+            raise GblError(rc, "gb_graph_launch")
+
+    def destroy(self):
+        if self.h:
+            self.lib.gb_graph_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass

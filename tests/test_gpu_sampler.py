@@ -306,3 +306,53 @@ def test_flow_rj_keeps_the_prior_at_zero_inverse_temperature():
     assert sps.kstest(x, "uniform").pvalue > 1e-6
     assert abs(np.mean(np.abs(x - 0.5) < 0.1) - 0.2) < 0.05
     ctx.close()
+
+
+def test_general_capture_of_flow_sweep_and_psd_step():
+    """one graph holding a sweep with the flow RJ proposal and the noise-PSD
+    step: two replays give what two direct calls give"""
+    from paper_2405_04690_amd.flow import Flow
+    from paper_2405_04690_amd.sampler import PsdSweep, psd_config
+    cfg, orc, sc, st = sampler_setup.problem(n_t=2, n_w=4, n_b=4, n_slots=4, seed=61)
+    lo, hi = (10e-12, 2e-15, 10e-12, 2e-15), (20e-12, 4e-15, 20e-12, 4e-15)
+    rng = np.random.default_rng(62)
+    theta = np.array(lo) + (np.array(hi) - np.array(lo)) * rng.uniform(size=(2, sc.n_walkers, 4))
+    stream = torch.cuda.Stream()
+    runs = []
+    with torch.cuda.stream(stream):
+        for captured in (False, True):
+            ctx, sw = _gpu_sweep(cfg, sc, st, stream=stream)
+            fc, th = _flow_for(sc, cfg, s_bias=-0.3)
+            fl = Flow(ctx, fc, th.astype(np.float32))
+            data = sw.resid[0][0].clone()
+            ps = PsdSweep(sw, psd_config(2, sc.n_walkers, lo, hi, seed=63), data)
+            ps.theta.copy_(torch.from_numpy(theta))
+            ps.betas.copy_(torch.tensor([1.0, 0.5], dtype=torch.float64))
+            sw.enable_proposals()
+            sw.sweep_counter.fill_(7)
+            if captured:
+                ctx.graph_begin()
+                sw.run_flow(fl, 1)
+                ps.step()
+                g = ctx.graph_end()
+                g.launch()
+                g.launch()
+            else:
+                for _ in range(2):
+                    sw.run_flow(fl, 1)
+                    ps.step()
+            stream.synchronize()
+            runs.append({k: getattr(sw, k).cpu().numpy().copy() for k in ("u", "exists", "resid", "stats",
+                                                                          "sweep_counter", "inv_psd")} |
+                        {k: getattr(ps, k).cpu().numpy().copy() for k in ("theta", "logl")} |
+                        {"psd_stats": ps.stats.cpu().numpy().copy()})
+            if captured:
+                g.destroy()
+            ctx.close()
+    a, b = runs
+    assert int(a["sweep_counter"][0]) == 9 and int(b["sweep_counter"][0]) == 9
+    for k in ("exists", "stats", "psd_stats"):
+        assert np.array_equal(a[k], b[k]), k
+    for k in ("u", "theta", "logl", "inv_psd"):
+        assert np.allclose(a[k], b[k], rtol=1e-12, atol=0), k
+    assert np.max(np.abs(a["resid"] - b["resid"])) <= 1e-10 * np.abs(a["resid"]).max()
