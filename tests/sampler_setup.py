@@ -14,7 +14,7 @@ from paper_2405_04690_amd import inputs
 N = 128
 
 
-def problem(n_t=3, n_w=4, n_b=6, n_slots=4, n_prop=6, n_friends=4, group_every=1, seed=77, beta_top=0.3):
+def problem(n_t=3, n_w=4, n_b=6, n_slots=4, n_prop=6, n_friends=4, group_every=1, seed=77, beta_top=0.3, N=N):
     cfg = inputs.TINY
     orc = oracle.Oracle(T=cfg.T, dt=cfg.dt, L=cfg.L, f_lo=cfg.f_lo, f_hi=cfg.f_hi)
     k_band0 = int(3e-3 * cfg.T)

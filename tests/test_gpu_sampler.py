@@ -41,16 +41,16 @@ def _compare(sw, st, what):
     u = sw.u.cpu().numpy()
     occ = st.exists.astype(bool)
     # per-coordinate scale: log10 A, f0 (one band), fdot, phi0, cos iota, psi, lambda, sin beta
-    width = np.array([2.5, sampler_setup.N / sampler_setup.inputs.TINY.T, 1e-15, 2 * np.pi, 2.0, np.pi,
-                      2 * np.pi, 2.0])
+    width = np.array([2.5, 512 / sampler_setup.inputs.TINY.T, 1e-15, 2 * np.pi, 2.0, np.pi, 2 * np.pi, 2.0])
     scale = np.maximum(np.abs(st.u[occ]), width)
     assert np.max(np.abs(u[occ] - st.u[occ]) / scale) <= 1e-10, f"{what}: coordinates differ"
     r = sw.resid.cpu().numpy()
     assert np.max(np.abs(r - st.resid)) <= 1e-10 * np.abs(st.resid).max(), f"{what}: residual buffers differ"
 
 
-def test_sweep_parity_each_move():
-    cfg, orc, sc, st = sampler_setup.problem()
+@pytest.mark.parametrize("N", [128, 256, 512])
+def test_sweep_parity_each_move(N):
+    cfg, orc, sc, st = sampler_setup.problem(N=N, n_b=6 if N == 128 else 4)
     ctx, sw = _gpu_sweep(cfg, sc, st)
     s0 = 11
     sw.sweep_counter.fill_(s0)
