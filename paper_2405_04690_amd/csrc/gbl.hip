@@ -504,6 +504,8 @@ static int sweep_check(gbl_ctx* ctx, const gbl_sweep_config* c, const gbl_sweep_
     return fail(ctx, GBL_EINVAL, "sweep: null state pointer%s");
   if ((st->prop_u == nullptr) != (st->rj_logq == nullptr))
     return fail(ctx, GBL_EINVAL, "sweep: prop_u and rj_logq must be given together%s");
+  if (st->spec_pool && (!st->pool_flags || st->pool_size < 1))
+    return fail(ctx, GBL_EINVAL, "sweep: spectrum pool without flags or size%s");
   if (ctx->cfg.precision != GBL_FP64) return fail(ctx, GBL_EUNSUPPORTED, "sweep: FP64 contexts only%s");
   return GBL_OK;
 }
@@ -535,6 +537,9 @@ static gbl::SweepArgs sweep_args(const gbl_sweep_config* c, const gbl_sweep_stat
   a.prop_u = st->prop_u;
   a.rj_logq = st->rj_logq;
   a.cold_logl = st->cold_logl;
+  a.spec_pool = (cd*)st->spec_pool;
+  a.pool_flags = st->pool_flags;
+  a.pool_size = st->pool_size;
   return a;
 }
 

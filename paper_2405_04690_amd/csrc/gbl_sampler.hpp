@@ -74,6 +74,9 @@ struct SweepArgs {
   const double* prop_u;   // RJ birth candidates (nullptr: prior draws)
   const double* rj_logq;  // ln q per slot (with prop_u)
   double* cold_logl;      // [n_w][n_b] cold-chain band logL after tempering (optional)
+  cd* spec_pool;          // optional pool of per-slot spectra, pool_size entries of n_slot x 2N
+  int32_t* pool_flags;    // [pool_size], 0 = free
+  int pool_size;
 };
 
 __device__ __forceinline__ int64_t uidx(const SweepArgs& a, int t, int w, int b, int s) {
@@ -137,6 +140,8 @@ struct BandSmem {
   double su[kMaxSlots][8];  // the band's slot coordinates during the loop
   int32_t ex[kMaxSlots];
   int32_t order[kMaxSlots];
+  int64_t sq[kMaxSlots];    // carrier bin of each slot's cached spectrum
+  int entry;                // spectrum pool entry held by the block (-1: none)
   double bcast;
 };
 
@@ -182,16 +187,23 @@ __device__ __forceinline__ double block_allsum(double v, double* red, double* bc
 // window += s * (template in the FFT workspace), bins inside the window;
 // with `global_buf`, the same change also goes (atomically) to the cold-chain
 // buffer of the band's own parity.
+// With `store`, the template's spectrum (all N bins, A then E) is also kept
+// there for later reuse.
 template <int N>
 __device__ __forceinline__ void band_add_template(const Geo& g, const WaveTables<double>& tb, BandSmem<N>& sm,
-                                                  int64_t k0w, double s, cd* global_buf) {
+                                                  int64_t k0w, double s, cd* global_buf, cd* store = nullptr) {
   constexpr int NT = block_threads<N>();
   const int64_t ks = sm.src.q - N / 2;
   for (int j = threadIdx.x; j < N; j += NT) {
     int64_t i = ks + j - k0w;
-    if (i < 0 || i >= 3 * N) continue;
+    if (!store && (i < 0 || i >= 3 * N)) continue;
     cd v[2];
     bin_spectrum<N, 2, double>(sm.src, g, tb, sm.buf, j, v);
+    if (store) {
+      store[j] = v[0];
+      store[N + j] = v[1];
+      if (i < 0 || i >= 3 * N) continue;
+    }
 #pragma unroll
     for (int c = 0; c < 2; c++) {
       sm.win[c][i] = sm.win[c][i] + cd{s * v[c].re, s * v[c].im};
@@ -286,6 +298,14 @@ __device__ __forceinline__ void band_store_rwin(const Geo& g, const WaveTables<d
   __syncthreads();
 }
 
+// a cached spectrum into sm.rwin
+template <int N>
+__device__ __forceinline__ void band_load_rwin(BandSmem<N>& sm, const cd* spec) {
+  constexpr int NT = block_threads<N>();
+  for (int j = threadIdx.x; j < 2 * N; j += NT) sm.rwin[j] = spec[j];
+  __syncthreads();
+}
+
 // load walker w's window from the opposite-parity buffer, and its weights
 template <int N>
 __device__ __forceinline__ void band_load_window(const Geo& g, const SweepArgs& a, int w, int b, int64_t k0w,
@@ -333,13 +353,29 @@ __global__ __launch_bounds__(block_threads<N>()) void k_sweep_band(Geo g, WaveTa
     sm.ex[s] = a.exists[uidx(a, t, w, b, s)];
     for (int k = 0; k < 8; k++) sm.su[s][k] = a.u[8 * uidx(a, t, w, b, s) + k];
   }
+  // a pool entry for the slots' spectra (a bounded scan; without one the
+  // spectra are recomputed)
+  if (tid == 0) {
+    sm.entry = -1;
+    if (a.spec_pool) {
+      const int P = a.pool_size;
+      const int start = (int)(((uint64_t)blockIdx.x * 2654435761ull) % (uint64_t)P);
+      for (int k = 0; k < P && sm.entry < 0; k++) {
+        const int e = (start + k) % P;
+        if (atomicCAS(&a.pool_flags[e], 0, 1) == 0) sm.entry = e;
+      }
+    }
+  }
   __syncthreads();
-  // the band's residual: remove its current sources
+  cd* const spec = sm.entry >= 0 ? a.spec_pool + (int64_t)sm.entry * S * 2 * N : nullptr;
+  // the band's residual: remove its current sources (keeping their spectra)
   for (int s = 0; s < S; s++) {
     if (!sm.ex[s]) continue;
     band_template<N>(g, tb, sm.su[s], sm);
-    band_add_template<N>(g, tb, sm, k0w, -1.0, nullptr);
+    band_add_template<N>(g, tb, sm, k0w, -1.0, nullptr, spec ? spec + (int64_t)s * 2 * N : nullptr);
+    if (tid == 0) sm.sq[s] = sm.src.q;
   }
+  __syncthreads();
 
   unsigned long long n_prop = 0, n_acc = 0, n_bprop = 0, n_bacc = 0, n_dprop = 0, n_dacc = 0;
   if (move == kMoveInModel) {
@@ -401,16 +437,23 @@ __global__ __launch_bounds__(block_threads<N>()) void k_sweep_band(Geo g, WaveTa
         sm.u_new[tid] = un[tid];
       }
       __syncthreads();
-      band_template<N>(g, tb, sm.u_old, sm);
-      band_store_rwin<N>(g, tb, sm);
-      const int64_t kr = sm.src.q - N / 2;
+      int64_t kr;
+      if (spec) {
+        band_load_rwin<N>(sm, spec + (int64_t)sk * 2 * N);
+        kr = sm.sq[sk] - N / 2;
+      } else {
+        band_template<N>(g, tb, sm.u_old, sm);
+        band_store_rwin<N>(g, tb, sm);
+        kr = sm.src.q - N / 2;
+      }
       band_template<N>(g, tb, sm.u_new, sm);
       const int64_t ka = sm.src.q - N / 2;
       const double dl = band_dlogl<N>(g, tb, sm, k0w, true, ka, true, kr);
       if (log(r_acc) < beta * dl + lr) {
-        band_add_template<N>(g, tb, sm, k0w, -1.0, own);
+        band_add_template<N>(g, tb, sm, k0w, -1.0, own, spec ? spec + (int64_t)sk * 2 * N : nullptr);
         band_add_rwin<N>(g, sm, k0w, kr, 1.0, own);
         if (tid < 8) sm.su[sk][tid] = sm.u_new[tid];
+        if (tid == 0) sm.sq[sk] = sm.src.q;
         n_acc++;
       }
       __syncthreads();
@@ -440,11 +483,17 @@ __global__ __launch_bounds__(block_threads<N>()) void k_sweep_band(Geo g, WaveTa
         // death: the new template is zero; with the prior proposal (q = p) only
         // the likelihood enters, otherwise ln q - ln p as well
         n_dprop++;
-        if (tid < 8) sm.u_old[tid] = us[tid];
-        __syncthreads();
-        band_template<N>(g, tb, sm.u_old, sm);
-        band_store_rwin<N>(g, tb, sm);
-        const int64_t kr = sm.src.q - N / 2;
+        int64_t kr;
+        if (spec) {
+          band_load_rwin<N>(sm, spec + (int64_t)s * 2 * N);
+          kr = sm.sq[s] - N / 2;
+        } else {
+          if (tid < 8) sm.u_old[tid] = us[tid];
+          __syncthreads();
+          band_template<N>(g, tb, sm.u_old, sm);
+          band_store_rwin<N>(g, tb, sm);
+          kr = sm.src.q - N / 2;
+        }
         const double dl = band_dlogl<N>(g, tb, sm, k0w, false, 0, true, kr);
         const double lpq = a.prop_u ? a.rj_logq[ui] + lvol : 0.0;
         if (log(r_acc) < beta * dl + lpq) {
@@ -462,9 +511,12 @@ __global__ __launch_bounds__(block_threads<N>()) void k_sweep_band(Geo g, WaveTa
           const int64_t ka = sm.src.q - N / 2;
           const double dl = band_dlogl<N>(g, tb, sm, k0w, true, ka, false, 0);
           if (log(r_acc) < beta * dl - lvol - a.rj_logq[ui]) {
-            band_add_template<N>(g, tb, sm, k0w, -1.0, own);
+            band_add_template<N>(g, tb, sm, k0w, -1.0, own, spec ? spec + (int64_t)s * 2 * N : nullptr);
             if (tid < 8) us[tid] = sm.u_new[tid];
-            if (tid == 0) sm.ex[s] = 1;
+            if (tid == 0) {
+              sm.ex[s] = 1;
+              sm.sq[s] = sm.src.q;
+            }
             n_bacc++;
           }
         }
@@ -489,9 +541,12 @@ __global__ __launch_bounds__(block_threads<N>()) void k_sweep_band(Geo g, WaveTa
         const int64_t ka = sm.src.q - N / 2;
         const double dl = band_dlogl<N>(g, tb, sm, k0w, true, ka, false, 0);
         if (log(r_acc) < beta * dl) {
-          band_add_template<N>(g, tb, sm, k0w, -1.0, own);
+          band_add_template<N>(g, tb, sm, k0w, -1.0, own, spec ? spec + (int64_t)s * 2 * N : nullptr);
           if (tid < 8) us[tid] = sm.u_new[tid];
-          if (tid == 0) sm.ex[s] = 1;
+          if (tid == 0) {
+            sm.ex[s] = 1;
+            sm.sq[s] = sm.src.q;
+          }
           n_bacc++;
         }
       }
@@ -502,6 +557,7 @@ __global__ __launch_bounds__(block_threads<N>()) void k_sweep_band(Geo g, WaveTa
     a.exists[uidx(a, t, w, b, s)] = sm.ex[s];
     for (int k = 0; k < 8; k++) a.u[8 * uidx(a, t, w, b, s) + k] = sm.su[s][k];
   }
+  if (tid == 0 && sm.entry >= 0) atomicExch(&a.pool_flags[sm.entry], 0);
   if (tid == 0) {
     if (n_prop) atomicAdd(&a.stats[0], n_prop);
     if (n_acc) atomicAdd(&a.stats[1], n_acc);

@@ -61,7 +61,7 @@ class SweepState(ctypes.Structure):
     """gbl_sweep_state (device pointers)"""
     _fields_ = [(n, ctypes.c_void_p) for n in ("u", "exists", "betas", "resid", "inv_psd", "group", "group_count",
                                               "stats", "sweep_counter", "prop_u", "rj_logq", "cold_logl",
-                                              "rj_mode")]
+                                              "rj_mode", "spec_pool", "pool_flags")] + [("pool_size", ctypes.c_int32)]
 
 
 class Tuning(ctypes.Structure):

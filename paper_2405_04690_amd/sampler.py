@@ -34,7 +34,7 @@ def make_config(n_temps, n_walkers, n_bands, n_slots, N, k_band0, n_prop=10, n_f
 
 
 class Sweep:
-    def __init__(self, ctx: Context, cfg: SweepConfig):
+    def __init__(self, ctx: Context, cfg: SweepConfig, spectrum_pool: int = 1024):
         self.ctx, self.cfg = ctx, cfg
         dev = ctx.device
         nt, nw, nb, ns = cfg.n_temps, cfg.n_walkers, cfg.n_bands, cfg.n_slots
@@ -53,6 +53,12 @@ class Sweep:
         self.rj_logq = None
         self.cold_logl = None
         self.rj_mode = None
+        # per-slot spectrum cache of the band loops (spectrum_pool entries)
+        self.spec_pool = None
+        self.pool_flags = None
+        if spectrum_pool > 0:
+            self.spec_pool = torch.zeros((spectrum_pool, ns, 2, cfg.N), dtype=torch.complex128, device=dev)
+            self.pool_flags = torch.zeros(spectrum_pool, dtype=torch.int32, device=dev)
         self._graph = None
 
     def enable_proposals(self):
@@ -76,9 +82,10 @@ class Sweep:
     def _state(self):
         st = SweepState()
         for n in ("u", "exists", "betas", "resid", "inv_psd", "group", "group_count", "stats", "sweep_counter",
-                  "prop_u", "rj_logq", "cold_logl", "rj_mode"):
+                  "prop_u", "rj_logq", "cold_logl", "rj_mode", "spec_pool", "pool_flags"):
             t = getattr(self, n)
             setattr(st, n, t.data_ptr() if t is not None else None)
+        st.pool_size = self.spec_pool.shape[0] if self.spec_pool is not None else 0
         return st
 
     def _call(self, name, *args):

@@ -17,7 +17,7 @@ from paper_2405_04690_amd.sampler import Sweep
 pytestmark = pytest.mark.gpu
 
 
-def _gpu_sweep(cfg, sc, st, stream=None):
+def _gpu_sweep(cfg, sc, st, stream=None, pool=1024):
     ctx = Context(T=cfg.T, dt=cfg.dt, L=cfg.L, f_lo=cfg.f_lo, f_hi=cfg.f_hi, stream=stream)
     gc = SweepConfig()
     for name, _ in oracle.SweepConfig._fields_:
@@ -27,7 +27,7 @@ def _gpu_sweep(cfg, sc, st, stream=None):
                 getattr(gc, name)[i] = v[i]
         else:
             setattr(gc, name, v)
-    sw = Sweep(ctx, gc)
+    sw = Sweep(ctx, gc, spectrum_pool=pool)
     for name in ("u", "exists", "betas", "resid", "inv_psd", "group", "group_count", "stats"):
         getattr(sw, name).copy_(torch.from_numpy(np.ascontiguousarray(getattr(st, name))))
     return ctx, sw
@@ -48,10 +48,12 @@ def _compare(sw, st, what):
     assert np.max(np.abs(r - st.resid)) <= 1e-10 * np.abs(st.resid).max(), f"{what}: residual buffers differ"
 
 
-@pytest.mark.parametrize("N", [128, 256, 512])
-def test_sweep_parity_each_move(N):
+@pytest.mark.parametrize("N,pool", [(128, 1024), (256, 1024), (512, 1024), (128, 0), (256, 2)])
+def test_sweep_parity_each_move(N, pool):
+    """pool: the per-slot spectrum cache (0: recomputed spectra; 2: most band
+    loops find no free entry and recompute, the others use the cache)"""
     cfg, orc, sc, st = sampler_setup.problem(N=N, n_b=6 if N == 128 else 4)
-    ctx, sw = _gpu_sweep(cfg, sc, st)
+    ctx, sw = _gpu_sweep(cfg, sc, st, pool=pool)
     s0 = 11
     sw.sweep_counter.fill_(s0)
     oracle.sweep_group(sc, st)
