@@ -257,11 +257,13 @@ typedef struct {
                              (empty slot) or at the current source (occupied slot) */
   double* cold_logl;      /* [n_w][n_b] cold chain's band log-likelihood, written by tempering */
   int32_t* rj_mode;       /* [n_t][n_w][n_b][n_slot] workspace of gb_sweep_rj_prepare */
-  /* Optional per-slot spectrum cache of the band loops (NULL: spectra are
-   * recomputed): pool_size entries of n_slot x 2 x N complex doubles, and
-   * pool_size flags that must be zero before the first call.  A band loop
-   * takes a free entry for its lifetime; pool_size >= 1024 covers the blocks
-   * one launch keeps resident.  Results do not depend on it. */
+  /* Optional cache (NULL: everything is recomputed): pool_size entries of
+   * max(n_slot x 2N, n_temps x 6N) complex doubles -- the band loops keep the
+   * spectra of their slots, the tempering kernel the window sums of its
+   * source sets -- and pool_size flags that must be zero before the first
+   * call.  A block takes a free entry for its lifetime (bounded scan; without
+   * one it recomputes); pool_size >= 1024 covers the blocks one launch keeps
+   * resident.  Results do not depend on it beyond FP64 rounding order. */
   double* spec_pool;
   int32_t* pool_flags;
   int32_t pool_size;

@@ -326,6 +326,25 @@ __device__ __forceinline__ void band_load_window(const Geo& g, const SweepArgs& 
   __syncthreads();
 }
 
+// entry size of the spectrum pool (complex values): the band loops keep n_slot
+// spectra of 2N bins, the tempering kernel n_t window sums of 2 x 3N bins
+__host__ __device__ __forceinline__ int64_t pool_entry(int n_slot, int n_t, int N) {
+  const int64_t e1 = (int64_t)n_slot * 2 * N, e2 = (int64_t)n_t * 6 * N;
+  return e1 > e2 ? e1 : e2;
+}
+
+// a free pool entry for the block (bounded scan), or -1
+__device__ __forceinline__ int pool_acquire(const SweepArgs& a) {
+  if (!a.spec_pool) return -1;
+  const int P = a.pool_size;
+  const int start = (int)(((uint64_t)blockIdx.x * 2654435761ull) % (uint64_t)P);
+  for (int k = 0; k < P; k++) {
+    const int e = (start + k) % P;
+    if (atomicCAS(&a.pool_flags[e], 0, 1) == 0) return e;
+  }
+  return -1;
+}
+
 // ---------------------------------------------------------------------------
 // Alg. gb1 for every (t, w, b) of one parity: in-model group-stretch moves
 // (move 0) or the reversible-jump pass that flips every slot (move 1).
@@ -355,19 +374,9 @@ __global__ __launch_bounds__(block_threads<N>()) void k_sweep_band(Geo g, WaveTa
   }
   // a pool entry for the slots' spectra (a bounded scan; without one the
   // spectra are recomputed)
-  if (tid == 0) {
-    sm.entry = -1;
-    if (a.spec_pool) {
-      const int P = a.pool_size;
-      const int start = (int)(((uint64_t)blockIdx.x * 2654435761ull) % (uint64_t)P);
-      for (int k = 0; k < P && sm.entry < 0; k++) {
-        const int e = (start + k) % P;
-        if (atomicCAS(&a.pool_flags[e], 0, 1) == 0) sm.entry = e;
-      }
-    }
-  }
+  if (tid == 0) sm.entry = pool_acquire(a);
   __syncthreads();
-  cd* const spec = sm.entry >= 0 ? a.spec_pool + (int64_t)sm.entry * S * 2 * N : nullptr;
+  cd* const spec = sm.entry >= 0 ? a.spec_pool + (int64_t)sm.entry * pool_entry(S, a.n_t, N) : nullptr;
   // the band's residual: remove its current sources (keeping their spectra)
   for (int s = 0; s < S; s++) {
     if (!sm.ex[s]) continue;
@@ -594,6 +603,52 @@ __device__ __forceinline__ double band_set_loglike(const Geo& g, const WaveTable
   return -0.5 * g.df4 * rr;
 }
 
+// H [2][3N] = sum of the templates of source set (t, w_src) over band b's
+// window (the templates of band b lie inside it); block-exclusive memory
+template <int N>
+__device__ __forceinline__ void band_set_sum(const Geo& g, const WaveTables<double>& tb, const SweepArgs& a, int t,
+                                             int w_src, int b, int64_t k0w, BandSmem<N>& sm, cd* H) {
+  constexpr int NT = block_threads<N>();
+  for (int i = threadIdx.x; i < 6 * N; i += NT) H[i] = cd{0.0, 0.0};
+  __syncthreads();
+  for (int s = 0; s < a.n_slot; s++) {
+    if (!a.exists[uidx(a, t, w_src, b, s)]) continue;
+    band_template<N>(g, tb, a.u + 8 * uidx(a, t, w_src, b, s), sm);
+    const int64_t ks = sm.src.q - N / 2;
+    for (int j = threadIdx.x; j < N; j += NT) {
+      const int64_t i = ks + j - k0w;
+      if (i < 0 || i >= 3 * N) continue;
+      cd v[2];
+      bin_spectrum<N, 2, double>(sm.src, g, tb, sm.buf, j, v);
+      H[i] = H[i] + v[0];
+      H[3 * N + i] = H[3 * N + i] + v[1];
+    }
+    __syncthreads();
+  }
+}
+
+// band log-likelihood -1/2 <R - H | R - H> over band b's window, R = walker
+// w_res's opposite-parity buffer, weights 1/S of w_res
+template <int N>
+__device__ __forceinline__ double band_set_loglike_h(const Geo& g, const SweepArgs& a, int b, int w_res, int64_t k0w,
+                                                     const cd* H, BandSmem<N>& sm) {
+  constexpr int NT = block_threads<N>();
+  const cd* opp = a.resid + ((int64_t)(1 - (b & 1)) * a.n_w + w_res) * 2 * g.n_bins;
+  const double* ip = a.inv_psd + (int64_t)w_res * 2 * g.n_bins;
+  double rr = 0.0;
+  for (int i = threadIdx.x; i < 3 * N; i += NT) {
+    const int64_t k = k0w + i - g.k_min;
+    if (k < 0 || k >= g.n_bins) continue;
+#pragma unroll
+    for (int c = 0; c < 2; c++) {
+      const cd r = opp[c * g.n_bins + k] - H[c * 3 * N + i];
+      rr += (r.re * r.re + r.im * r.im) * ip[c * g.n_bins + k];
+    }
+  }
+  rr = block_allsum<NT>(rr, sm.red, &sm.bcast);
+  return -0.5 * g.df4 * rr;
+}
+
 template <int N>
 __global__ __launch_bounds__(block_threads<N>()) void k_sweep_pt(Geo g, WaveTables<double> tb, SweepArgs a,
                                                                  int parity) {
@@ -601,6 +656,7 @@ __global__ __launch_bounds__(block_threads<N>()) void k_sweep_pt(Geo g, WaveTabl
   __shared__ int wt[256];
   __shared__ double Lc[256];
   __shared__ int perm[256];
+  __shared__ int hidx[256];  // window sum of the set at temperature t: entry slot hidx[t]
   const int nbp = (a.n_b - parity + 1) / 2;
   const int bi = blockIdx.x % nbp;
   const int i = blockIdx.x / nbp;
@@ -622,23 +678,52 @@ __global__ __launch_bounds__(block_threads<N>()) void k_sweep_pt(Geo g, WaveTabl
       wt[t] = perm[i];
     }
   }
+  if (tid == 0) sm.entry = pool_acquire(a);
+  for (int t = tid; t < nt; t += block_threads<N>()) hidx[t] = t;
   __syncthreads();
+  cd* const Hs = sm.entry >= 0 ? a.spec_pool + (int64_t)sm.entry * pool_entry(a.n_slot, nt, N) : nullptr;
+  auto Hof = [&](int t) { return Hs + (int64_t)hidx[t] * 6 * N; };
   for (int t = 0; t < nt; t++) {
-    double L = band_set_loglike<N>(g, tb, a, t, wt[t], b, wt[t], k0w, sm);
+    double L;
+    if (Hs) {
+      band_set_sum<N>(g, tb, a, t, wt[t], b, k0w, sm, Hof(t));
+      L = band_set_loglike_h<N>(g, a, b, wt[t], k0w, Hof(t), sm);
+    } else {
+      L = band_set_loglike<N>(g, tb, a, t, wt[t], b, wt[t], k0w, sm);
+    }
     if (tid == 0) Lc[t] = L;
   }
   __syncthreads();
   const double* bt = a.betas + (int64_t)b * nt;
   unsigned long long n_prop = 0, n_acc = 0;
   for (int t = nt - 1; t >= 1; t--) {
-    const double L1 = band_set_loglike<N>(g, tb, a, t - 1, wt[t - 1], b, wt[t], k0w, sm);
-    const double L2 = band_set_loglike<N>(g, tb, a, t, wt[t], b, wt[t - 1], k0w, sm);
+    const double L1 = Hs ? band_set_loglike_h<N>(g, a, b, wt[t], k0w, Hof(t - 1), sm)
+                         : band_set_loglike<N>(g, tb, a, t - 1, wt[t - 1], b, wt[t], k0w, sm);
+    const double L2 = Hs ? band_set_loglike_h<N>(g, a, b, wt[t - 1], k0w, Hof(t), sm)
+                         : band_set_loglike<N>(g, tb, a, t, wt[t], b, wt[t - 1], k0w, sm);
     const double la = bt[t] * (L1 - Lc[t]) + bt[t - 1] * (L2 - Lc[t - 1]);
     const double r = rng_uniform(a.seed, sweep, kMovePT, (uint64_t)b * a.n_w + i, (uint64_t)t);
     n_prop++;
     if (log(r) < la) {
       n_acc++;
-      if (t == 1) {
+      if (t == 1 && Hs) {
+        // the cold chain of walker w_0 changes: own-parity buffer += old - new
+        cd* own = a.resid + ((int64_t)(b & 1) * a.n_w + wt[0]) * 2 * g.n_bins;
+        const cd* H0 = Hof(0);
+        const cd* H1 = Hof(1);
+        for (int i2 = tid; i2 < 3 * N; i2 += block_threads<N>()) {
+          const int64_t k = k0w + i2 - g.k_min;
+          if (k < 0 || k >= g.n_bins) continue;
+#pragma unroll
+          for (int c = 0; c < 2; c++) {
+            const cd d = H0[c * 3 * N + i2] - H1[c * 3 * N + i2];
+            double* dst = reinterpret_cast<double*>(own + c * g.n_bins + k);
+            atomicAdd(dst, d.re);
+            atomicAdd(dst + 1, d.im);
+          }
+        }
+        __syncthreads();
+      } else if (t == 1) {
         // the cold chain of walker w_0 changes: own-parity buffer += old - new
         cd* own = a.resid + ((int64_t)(b & 1) * a.n_w + wt[0]) * 2 * g.n_bins;
         for (int s = 0; s < a.n_slot; s++) {
@@ -669,10 +754,14 @@ __global__ __launch_bounds__(block_threads<N>()) void k_sweep_pt(Geo g, WaveTabl
       if (tid == 0) {
         Lc[t] = L1;
         Lc[t - 1] = L2;
+        const int h = hidx[t];
+        hidx[t] = hidx[t - 1];
+        hidx[t - 1] = h;
       }
       __syncthreads();
     }
   }
+  if (tid == 0 && sm.entry >= 0) atomicExch(&a.pool_flags[sm.entry], 0);
   if (tid == 0) {
     atomicAdd(&a.stats[6], n_prop);
     if (n_acc) atomicAdd(&a.stats[7], n_acc);

@@ -57,7 +57,8 @@ class Sweep:
         self.spec_pool = None
         self.pool_flags = None
         if spectrum_pool > 0:
-            self.spec_pool = torch.zeros((spectrum_pool, ns, 2, cfg.N), dtype=torch.complex128, device=dev)
+            entry = max(ns * 2 * cfg.N, nt * 6 * cfg.N)
+            self.spec_pool = torch.zeros((spectrum_pool, entry), dtype=torch.complex128, device=dev)
             self.pool_flags = torch.zeros(spectrum_pool, dtype=torch.int32, device=dev)
         self._graph = None
 
