@@ -358,3 +358,36 @@ def test_general_capture_of_flow_sweep_and_psd_step():
     for k in ("u", "theta", "logl", "inv_psd"):
         assert np.allclose(a[k], b[k], rtol=1e-12, atol=0), k
     assert np.max(np.abs(a["resid"] - b["resid"])) <= 1e-10 * np.abs(a["resid"]).max()
+
+
+def test_sweep_parity_at_the_slot_limit():
+    """64 slots per band (the kernel's limit), every slot occupied at the start"""
+    cfg, orc, sc, st = sampler_setup.problem(n_t=2, n_w=2, n_b=3, n_slots=64, n_prop=8, seed=71)
+    rng = np.random.default_rng(72)
+    for b in range(sc.n_bands):
+        flo = (sc.k_band0 + (b + 0.05) * sc.N) / cfg.T
+        fhi = (sc.k_band0 + (b + 0.95) * sc.N) / cfg.T
+        occ = ~st.exists.astype(bool)[:, :, b]
+        n = int(occ.sum())
+        st.u[:, :, b][occ] = np.stack([rng.uniform(-23, -22, n), rng.uniform(flo, fhi, n), np.zeros(n),
+                                       rng.uniform(0, 6.28, n), rng.uniform(-1, 1, n), rng.uniform(0, 3.14, n),
+                                       rng.uniform(0, 6.28, n), rng.uniform(-1, 1, n)], axis=1)
+    st.exists[:] = 1
+    # rebuild the cold-chain buffers for the new slot contents
+    data = st.resid[0, 0].copy()   # buffer 0 = data minus the even bands' original sources: any fixed data will do
+    for par in (0, 1):
+        for w in range(sc.n_walkers):
+            st.resid[par, w] = data
+            for b in range(par, sc.n_bands, 2):
+                phys = np.array([sampler_setup._phys(st.u[0, w, b, s]) for s in range(sc.n_slots)])
+                orc.scatter_add(phys, sc.N, -1.0, st.resid[par, w])
+    ctx, sw = _gpu_sweep(cfg, sc, st)
+    sw.sweep_counter.fill_(2)
+    oracle.sweep_group(sc, st)
+    sw.group_refresh()
+    for move in (0, 1, 2):
+        for parity in (1, 0):
+            oracle.sweep_step(orc, sc, st, move, parity, 2)
+            sw.step(move, parity)
+            _compare(sw, st, f"slot limit {move}/{parity}")
+    ctx.close()
