@@ -446,14 +446,6 @@ __device__ __forceinline__ void slow_sample(const Src& s, const Geo& g, const do
   kn[2] = -(kn[0] + kn[1]);
   pn[2] = -(pn[0] + pn[1]);
   qn[2] = -(qn[0] + qn[1]);
-  cx<F> G[3];
-  const cx<F> cp = cvt<F>(s.cp), cxx = cvt<F>(s.cx);
-#pragma unroll
-  for (int m = 0; m < 3; m++) {
-    F ep = pn[m] * pn[m] - qn[m] * qn[m];
-    F ex = (F)2 * pn[m] * qn[m];
-    G[m] = {cp.re * ep + cxx.re * ex, cp.im * ep + cxx.im * ex};
-  }
 
   // phases in cycles: phi_r / (2 pi) = phi0/(2 pi) + dfq t + fdot t^2/2
   //                                    - (f0 + fdot t) k.x_r/c + fdot (k.x_r/c)^2 / 2
@@ -472,9 +464,6 @@ __device__ __forceinline__ void slow_sample(const Src& s, const Geo& g, const do
     cyc[r] = base - fwd * kx + 0.5 * s.fdot * kx * kx;
     fr[r] = (F)(s.f0 + s.fdot * (t - kx));
   }
-  cx<F> P[3];
-  expi_cycles_k<3, F>(cyc, P);
-
   // the six links, ordered by receiver: (arm, direction, receiver)
   //   l21 = (0,-1,0)  l31 = (2,+1,0)  l12 = (0,+1,1)  l32 = (1,-1,1)
   //   l23 = (1,+1,2)  l13 = (2,-1,2)
@@ -490,6 +479,20 @@ __device__ __forceinline__ void slow_sample(const Src& s, const Geo& g, const do
     u[l] = om * amp[l];
   }
   sinc_cos_k<6, UC>(u, sc, cu);
+  // arm factors G = n^T H n and receiver phase factors P, formed only now so
+  // that they do not occupy registers across the series above
+  cx<F> G[3];
+  {
+    const cx<F> cp = cvt<F>(s.cp), cxx = cvt<F>(s.cx);
+#pragma unroll
+    for (int m = 0; m < 3; m++) {
+      F ep = pn[m] * pn[m] - qn[m] * qn[m];
+      F ex = (F)2 * pn[m] * qn[m];
+      G[m] = {cp.re * ep + cxx.re * ex, cp.im * ep + cxx.im * ex};
+    }
+  }
+  cx<F> P[3];
+  expi_cycles_k<3, F>(cyc, P);
   // s_{snd->rcv} = -i G w exp(-i u) P_rcv,  w = amp sinc(u)
   cx<F> lk[6];
 #pragma unroll

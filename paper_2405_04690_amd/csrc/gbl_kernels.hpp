@@ -204,23 +204,6 @@ __device__ __forceinline__ void delta_one(const Geo& g, const WaveTables<F>& tb,
     if ((tid & (kWave - 1)) == 0) sm.src[which] = d;
   }
 
-  // prefetch residual and weights over a's window
-  cd pR0[BPT], pR1[BPT];
-  double pW0[BPT], pW1[BPT];
-  if (hn.state == 0) {
-#pragma unroll
-    for (int m = 0; m < BPT; m++) {
-      int64_t k = ka + tid + NT * m;
-      if (k >= g.k_min && k < g.k_min + nb) {
-        int64_t idx = k - g.k_min;
-        pR0[m] = RA[idx];
-        pR1[m] = RE[idx];
-        pW0[m] = weight(SA, idx);
-        pW1[m] = weight(SE, idx);
-      }
-    }
-  }
-
   __syncthreads();
 
   // old template into the LDS window
@@ -261,6 +244,22 @@ __device__ __forceinline__ void delta_one(const Geo& g, const WaveTables<F>& tb,
   if (hn.state == 0) {
     const Src& sn = sm.src[1];
     template_transform<N, 4, F>(sn, g, tb, sm.buf, tid);
+    // residual and weights over a's window (loaded here, not earlier: at four
+    // waves per SIMD the other waves hide the latency, and no registers stay
+    // occupied across the two template builds)
+    cd pR0[BPT], pR1[BPT];
+    double pW0[BPT], pW1[BPT];
+#pragma unroll
+    for (int m = 0; m < BPT; m++) {
+      int64_t k = ka + tid + NT * m;
+      if (k >= g.k_min && k < g.k_min + nb) {
+        int64_t idx = k - g.k_min;
+        pR0[m] = RA[idx];
+        pR1[m] = RE[idx];
+        pW0[m] = weight(SA, idx);
+        pW1[m] = weight(SE, idx);
+      }
+    }
 #pragma unroll
     for (int m = 0; m < BPT; m++) {
       const int j = tid + NT * m;
