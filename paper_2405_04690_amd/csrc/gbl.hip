@@ -114,7 +114,7 @@ extern "C" int gbl_create(gbl_ctx** out, const gbl_config* cfg, void* hip_stream
 
   for (int i = 0; i < kNumWidths; i++) {
     int N = kWidths[i];
-    size_t bytes = sizeof(double) * 4 * N + sizeof(cd) * 2 * N + sizeof(gbl::cf) * 2 * N;
+    size_t bytes = sizeof(double) * 4 * N + sizeof(cd) * 3 * N + sizeof(gbl::cf) * 3 * N;
     if (hipMalloc(&ctx->table_mem[i], bytes) != hipSuccess) {
       release(ctx);
       delete ctx;
@@ -123,12 +123,14 @@ extern "C" int gbl_create(gbl_ctx** out, const gbl_config* cfg, void* hip_stream
     double* basis = (double*)ctx->table_mem[i];
     cd* tw = (cd*)(basis + 4 * N);
     cd* bF = tw + N;
-    gbl::cf* tw32 = (gbl::cf*)(bF + N);
+    cd* bW = bF + N;
+    gbl::cf* tw32 = (gbl::cf*)(bW + N);
     gbl::cf* bF32 = tw32 + N;
-    ctx->tables[i] = {basis, tw, bF};
-    ctx->tables32[i] = {basis, tw32, bF32};
-    hipLaunchKernelGGL(gbl::k_init_wave_tables, dim3((N + 255) / 256), dim3(256), 0, ctx->stream, N, g.T, basis,
-                       tw, bF, tw32, bF32);
+    gbl::cf* bW32 = bF32 + N;
+    ctx->tables[i] = {basis, tw, bF, bW};
+    ctx->tables32[i] = {basis, tw32, bF32, bW32};
+    hipLaunchKernelGGL(gbl::k_init_wave_tables, dim3((N + 255) / 256), dim3(256), 0, ctx->stream, N, g.T, g.Lc,
+                       basis, tw, bF, bW, tw32, bF32, bW32);
   }
   size_t nbb = sizeof(double) * (size_t)g.n_bins;
   if (hipMalloc(&ctx->psd_P1, nbb) != hipSuccess || hipMalloc(&ctx->psd_P2, nbb) != hipSuccess ||

@@ -23,6 +23,7 @@
 
 namespace gbl {
 
+constexpr int kWave = 64;                // wavefront width of CDNA
 constexpr double kC = 299792458.0;        // speed of light [m/s]
 constexpr double kAU = 1.495978707e11;    // astronomical unit [m]
 constexpr double kYear = 31557600.0;      // Julian year [s]: orbital period
@@ -91,6 +92,7 @@ struct WaveTables {
   const double* basis;  // [N][4] cos a, sin a, cos 2a, sin 2a at t_n = (n+1/2) T/N, a = 2 pi t/yr
   const cx<F>* fft_tw;  // [N]    exp(-2 pi i m / N)
   const cx<F>* bin_F;   // [N]    (1/2)(T/N) exp(-i pi k / N),   k = j - N/2
+  const cx<F>* bin_W;   // [N]    exp(-2 pi i k L/(c T)):  the bin's TDI delay factor over the carrier's
 };
 
 // ---------------------------------------------------------------------------
@@ -135,10 +137,15 @@ __device__ __forceinline__ cd expi_cycles(double c) {
 struct Src {
   double f0, fdot, phi0_cyc, dfq;  // phi0 / (2 pi); dfq = f0 - q/T
   int64_t q;                   // carrier bin floor(f0 T)
-  double kc[3];                // khat / c
-  double kh[3];                // khat = -(sky direction)
-  double pv[3], qv[3];         // polarisation basis vectors
-  cd cp, cx;                   // n^T H n = cp (p.n^2 - q.n^2) + cx 2 (p.n)(q.n)
+  // The orbit enters through the four basis values b = (cos a, sin a, cos 2a,
+  // sin 2a) of the orientation angle a, and every projection the response
+  // needs is an affine function of b whose coefficients depend on the source
+  // alone: v = c[0] cos a + c[1] sin a + c[2] cos 2a + c[3] sin 2a + c[4].
+  double xr[3][5];             // k.x_r / c of receivers (craft) r = 0, 1, 2 [s]
+  double kn[2][5], qn[2][5];   // k.n_m and q.n_m of arms m = 0, 1
+  double pn[2][3];             // p.n_m (cos 2a, sin 2a, 1: p has no z component)
+  cd cp, cx2;                  // n^T H n = cp (p.n^2 - q.n^2) + cx2 (p.n)(q.n)
+  cd dq;                       // exp(-2 pi i q L/(c T)): the carrier's TDI delay factor
   int state;                   // 0 regular, 1 exactly zero amplitude, 2 non-finite parameters
 };
 
@@ -180,23 +187,50 @@ __device__ __forceinline__ Src decode_source(const double* __restrict__ prm, con
   double sl, cl, sb, cb;
   sincos(lam, &sl, &cl);
   sincos(beta, &sb, &cb);
-  s.kh[0] = -cb * cl;
-  s.kh[1] = -cb * sl;
-  s.kh[2] = -sb;
-  for (int i = 0; i < 3; i++) s.kc[i] = s.kh[i] / kC;
-  s.pv[0] = sl;
-  s.pv[1] = -cl;
-  s.pv[2] = 0.0;
-  s.qv[0] = -sb * cl;
-  s.qv[1] = -sb * sl;
-  s.qv[2] = cb;
+  // propagation direction k = -(sky direction) and polarisation basis p, q
+  const double kh[3] = {-cb * cl, -cb * sl, -sb};
+  const double pv[2] = {sl, -cl};
+  const double qv[3] = {-sb * cl, -sb * sl, cb};
+  const double kc[3] = {kh[0] / kC, kh[1] / kC, kh[2] / kC};
+  // craft r at orientation 2 pi r/3 (cos/sin br):
+  //   x_r = AU (cos a, sin a, 0) + eh (cos 2a cbr + sin 2a sbr - 3 cbr,
+  //         sin 2a cbr - cos 2a sbr - 3 sbr, 0) - ez (0, 0, cos a cbr + sin a sbr)
+  constexpr double cbs[3] = {1.0, -0.5, -0.5};
+  constexpr double sbs[3] = {0.0, 0.86602540378443864676, -0.86602540378443864676};
+  for (int r = 0; r < 3; r++) {
+    s.xr[r][0] = kc[0] * kAU - kc[2] * g.ez * cbs[r];
+    s.xr[r][1] = kc[1] * kAU - kc[2] * g.ez * sbs[r];
+    s.xr[r][2] = g.eh * (kc[0] * cbs[r] - kc[1] * sbs[r]);
+    s.xr[r][3] = g.eh * (kc[0] * sbs[r] + kc[1] * cbs[r]);
+    s.xr[r][4] = -3.0 * g.eh * (kc[0] * cbs[r] + kc[1] * sbs[r]);
+  }
+  // arm m = craft m -> m+1: n_m = (x_{m+1} - x_m) / L
+  const double sh = g.inv_L * g.eh, sz = g.inv_L * g.ez;
+  for (int m = 0; m < 2; m++) {
+    const double dcb = cbs[m + 1] - cbs[m], dsb = sbs[m + 1] - sbs[m];
+    auto proj = [&](double v0, double v1, double v2, double* c) {
+      c[0] = -sz * v2 * dcb;
+      c[1] = -sz * v2 * dsb;
+      c[2] = sh * (v0 * dcb - v1 * dsb);
+      c[3] = sh * (v0 * dsb + v1 * dcb);
+      c[4] = -3.0 * sh * (v0 * dcb + v1 * dsb);
+    };
+    proj(kh[0], kh[1], kh[2], s.kn[m]);
+    proj(qv[0], qv[1], qv[2], s.qn[m]);
+    double c[5];
+    proj(pv[0], pv[1], 0.0, c);
+    s.pn[m][0] = c[2];
+    s.pn[m][1] = c[3];
+    s.pn[m][2] = c[4];
+  }
   double ci = cos(iota);
   double s2p, c2p;
   sincos(2.0 * psi, &s2p, &c2p);
   double ap = A * (1.0 + ci * ci);
   double ax = 2.0 * A * ci;
   s.cp = {ap * c2p, -ax * s2p};
-  s.cx = {ap * s2p, ax * c2p};
+  s.cx2 = {2.0 * ap * s2p, 2.0 * ax * c2p};
+  s.dq = expi_cycles(-(double)s.q * (g.Lc / g.T));
   return s;
 }
 
@@ -252,7 +286,7 @@ __device__ __forceinline__ void sinc_cos(double u, double& sinc, double& cosu) {
 // ranges.
 // UC = 1: any |u| in band (above, with the library fallback); UC = 0: the
 // caller guarantees |u| <= 0.25 (templates below ~4.7 mHz), where sinc through
-// u^12 and cos through u^14 already leave next terms below 3e-21.
+// u^10 and cos through u^12 leave next terms below 1e-17 (u^12/13!, u^14/14!).
 template <int K, int UC = 1>
 __device__ __forceinline__ void sinc_cos_k(const double* u, double* sinc, double* cosu) {
   constexpr double cs_[10] = {-1.0 / 51090942171709440000.0, 1.0 / 121645100408832000.0,
@@ -267,8 +301,8 @@ __device__ __forceinline__ void sinc_cos_k(const double* u, double* sinc, double
                               1.0 / 40320.0,                    -1.0 / 720.0,
                               1.0 / 24.0,                       -0.5,
                               1.0};
-  constexpr int S0 = UC == 0 ? 4 : 0;  // first sinc coefficient used
-  constexpr int C0 = UC == 0 ? 5 : 0;  // first cos coefficient used
+  constexpr int S0 = UC == 0 ? 5 : 0;  // first sinc coefficient used
+  constexpr int C0 = UC == 0 ? 6 : 0;  // first cos coefficient used
   double v[K], a[K], c[K];
   bool in_range = true;
 #pragma unroll
@@ -418,34 +452,20 @@ __device__ __forceinline__ void expi_cycles_k(const double* c, cx<F>* out) {
 template <int NSER, typename F, int UC = 1>
 __device__ __forceinline__ void slow_sample(const Src& s, const Geo& g, const double* __restrict__ basis, int n,
                                             double t, cx<F>* out) {
-  // orientation cosines/sines of the three craft
-  constexpr double cbs[3] = {1.0, -0.5, -0.5};
-  constexpr double sbs[3] = {0.0, 0.86602540378443864676, -0.86602540378443864676};
   const double ca = basis[4 * n + 0], sa = basis[4 * n + 1];
   const double c2a = basis[4 * n + 2], s2a = basis[4 * n + 3];
+  auto affine = [&](const double* c) { return c[4] + c[0] * ca + c[1] * sa + c[2] * c2a + c[3] * s2a; };
 
-  // arm projections first: k.n and G = n^T H n for arm m (craft m -> m+1)
-  // (the arms close the triangle, n_0 + n_1 + n_2 = 0, so the third arm's
-  //  projections are minus the sum of the first two)
-  F kn[3], pn[3], qn[3];
-  {
-    const F fca = (F)ca, fsa = (F)sa, fc2a = (F)c2a, fs2a = (F)s2a;
-    const F sh = (F)(g.inv_L * g.eh), sz = (F)(g.inv_L * g.ez);
-#pragma unroll
-    for (int m = 0; m < 2; m++) {
-      const int j = m + 1;
-      const F dcb = (F)(cbs[j] - cbs[m]), dsb = (F)(sbs[j] - sbs[m]);
-      F nx = sh * (fc2a * dcb + fs2a * dsb - (F)3 * dcb);
-      F ny = sh * (fs2a * dcb - fc2a * dsb - (F)3 * dsb);
-      F nz = -sz * (fca * dcb + fsa * dsb);
-      kn[m] = (F)s.kh[0] * nx + (F)s.kh[1] * ny + (F)s.kh[2] * nz;
-      pn[m] = (F)s.pv[0] * nx + (F)s.pv[1] * ny;  // p has no z component
-      qn[m] = (F)s.qv[0] * nx + (F)s.qv[1] * ny + (F)s.qv[2] * nz;
-    }
-  }
+  const F fca = (F)ca, fsa = (F)sa, fc2a = (F)c2a, fs2a = (F)s2a;
+  auto affine_f = [&](const double* c) {
+    return (F)c[4] + (F)c[0] * fca + (F)c[1] * fsa + (F)c[2] * fc2a + (F)c[3] * fs2a;
+  };
+  // arm projections k.n (the arms close the triangle, n_0 + n_1 + n_2 = 0,
+  // so the third arm's projections are minus the sum of the first two)
+  F kn[3];
+  kn[0] = affine_f(s.kn[0]);
+  kn[1] = affine_f(s.kn[1]);
   kn[2] = -(kn[0] + kn[1]);
-  pn[2] = -(pn[0] + pn[1]);
-  qn[2] = -(qn[0] + qn[1]);
 
   // phases in cycles: phi_r / (2 pi) = phi0/(2 pi) + dfq t + fdot t^2/2
   //                                    - (f0 + fdot t) k.x_r/c + fdot (k.x_r/c)^2 / 2
@@ -457,12 +477,9 @@ __device__ __forceinline__ void slow_sample(const Src& s, const Geo& g, const do
   F fr[3];
 #pragma unroll
   for (int r = 0; r < 3; r++) {
-    double x = kAU * ca + g.eh * (c2a * cbs[r] + s2a * sbs[r] - 3.0 * cbs[r]);
-    double y = kAU * sa + g.eh * (s2a * cbs[r] - c2a * sbs[r] - 3.0 * sbs[r]);
-    double z = -g.ez * (ca * cbs[r] + sa * sbs[r]);
-    double kx = s.kc[0] * x + s.kc[1] * y + s.kc[2] * z;  // k.x_r / c
+    const double kx = affine(s.xr[r]);
     cyc[r] = base - fwd * kx + 0.5 * s.fdot * kx * kx;
-    fr[r] = (F)(s.f0 + s.fdot * (t - kx));
+    fr[r] = (F)(fwd - s.fdot * kx);
   }
   // the six links, ordered by receiver: (arm, direction, receiver)
   //   l21 = (0,-1,0)  l31 = (2,+1,0)  l12 = (0,+1,1)  l32 = (1,-1,1)
@@ -479,42 +496,67 @@ __device__ __forceinline__ void slow_sample(const Src& s, const Geo& g, const do
     u[l] = om * amp[l];
   }
   sinc_cos_k<6, UC>(u, sc, cu);
+  // w exp(-i u) with w = amp sinc(u)
+  cx<F> wz[6];
+#pragma unroll
+  for (int l = 0; l < 6; l++) {
+    const F w = amp[l] * sc[l];
+    wz[l] = {w * cu[l], -(w * u[l]) * sc[l]};
+  }
   // arm factors G = n^T H n and receiver phase factors P, formed only now so
-  // that they do not occupy registers across the series above
+  // that neither they nor their inputs occupy registers across the series
   cx<F> G[3];
   {
-    const cx<F> cp = cvt<F>(s.cp), cxx = cvt<F>(s.cx);
+    F pn[3], qn[3];
+#pragma unroll
+    for (int m = 0; m < 2; m++) {
+      qn[m] = affine_f(s.qn[m]);
+      pn[m] = (F)s.pn[m][2] + (F)s.pn[m][0] * fc2a + (F)s.pn[m][1] * fs2a;
+    }
+    pn[2] = -(pn[0] + pn[1]);
+    qn[2] = -(qn[0] + qn[1]);
+    const cx<F> cp = cvt<F>(s.cp), cx2 = cvt<F>(s.cx2);
 #pragma unroll
     for (int m = 0; m < 3; m++) {
       F ep = pn[m] * pn[m] - qn[m] * qn[m];
-      F ex = (F)2 * pn[m] * qn[m];
-      G[m] = {cp.re * ep + cxx.re * ex, cp.im * ep + cxx.im * ex};
+      F ex = pn[m] * qn[m];
+      G[m] = {cp.re * ep + cx2.re * ex, cp.im * ep + cx2.im * ex};
     }
   }
   cx<F> P[3];
-  expi_cycles_k<3, F>(cyc, P);
-  // s_{snd->rcv} = -i G w exp(-i u) P_rcv,  w = amp sinc(u)
+  if constexpr (UC == 0) {
+    // FP64 with every phase small: P_1, P_2 follow from P_0 through the
+    // offsets x_r = 2 pi (cyc_r - cyc_0), which the caller's bound keeps
+    // within |x| <= 0.25 like the link phases, so they take the same short
+    // series: exp(i x) = cos x + i x sinc x
+    expi_cycles_k<1, F>(cyc, P);
+    F x[2], sx[2], cxr[2];
+    x[0] = (F)(kTwoPi * (cyc[1] - cyc[0]));
+    x[1] = (F)(kTwoPi * (cyc[2] - cyc[0]));
+    sinc_cos_k<2, 0>(x, sx, cxr);
+#pragma unroll
+    for (int r = 1; r < 3; r++) P[r] = P[0] * cx<F>{cxr[r - 1], x[r - 1] * sx[r - 1]};
+  } else {
+    expi_cycles_k<3, F>(cyc, P);
+  }
+  // s_{snd->rcv} = -i G w exp(-i u) P_rcv
   cx<F> lk[6];
 #pragma unroll
-  for (int l = 0; l < 6; l++) {
-    F w = amp[l] * sc[l];
-    cx<F> z = {cu[l], -u[l] * sc[l]};
-    cx<F> t1 = z * P[l / 2];
-    cx<F> t2 = G[arm_[l]] * t1;
-    lk[l] = mul_negi(w * t2);
-  }
+  for (int l = 0; l < 6; l++) lk[l] = mul_negi(G[arm_[l]] * (P[l / 2] * wz[l]));
   // TDI pieces: U_X = s21 - s31, V_X = s12 - s13, U_Y = s32 - s12,
   //             V_Y = s23 - s21, U_Z = s13 - s23, V_Z = s31 - s32
+  // and the A, E (T) combinations without their normalisations 1/sqrt 2,
+  // 1/sqrt 6 (1/sqrt 3), which bin_spectrum applies per bin
   const cx<F> UX = lk[0] - lk[1], VX = lk[2] - lk[5];
   const cx<F> UY = lk[3] - lk[2], VY = lk[4] - lk[0];
   const cx<F> UZ = lk[5] - lk[4], VZ = lk[1] - lk[3];
-  out[0] = (F)kInvSqrt2 * (UZ - UX);
-  out[1] = (F)kInvSqrt2 * (VZ - VX);
-  out[2] = (F)kInvSqrt6 * (UX - (F)2 * UY + UZ);
-  out[3] = (F)kInvSqrt6 * (VX - (F)2 * VY + VZ);
+  out[0] = UZ - UX;
+  out[1] = VZ - VX;
+  out[2] = UX - (F)2 * UY + UZ;
+  out[3] = VX - (F)2 * VY + VZ;
   if constexpr (NSER == 6) {
-    out[4] = (F)kInvSqrt3 * (UX + UY + UZ);
-    out[5] = (F)kInvSqrt3 * (VX + VY + VZ);
+    out[4] = UX + UY + UZ;
+    out[5] = VX + VY + VZ;
   }
 }
 
@@ -630,42 +672,68 @@ __device__ __forceinline__ int fft_pos(int k) {
   return pos;
 }
 
+// Each wave owns whole series when the series divide evenly over the waves of
+// the block (4 series on 1, 2 or 4 waves): a pass then only reads what the
+// same wave wrote in the pass before, and the passes are ordered by a
+// wavefront-scope fence instead of a block barrier.
+template <int NSER, int NT>
+constexpr bool fft_wave_local() {
+  return NSER % (NT / kWave) == 0;
+}
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int N, int R, int ST, typename F>
+__device__ __forceinline__ void fft_butterfly(cx<F>* b, const cx<F>* __restrict__ tw, int beta) {
+  constexpr int TWS = N / (R * ST);
+  int grp = beta / ST, i = beta % ST;
+  int base = grp * R * ST + i;
+  const int base_addr = GBL_LDS_LAYOUT == 0 ? 0 : lds_pad<N>(base);
+  cx<F> x[R];
+#pragma unroll
+  for (int r = 0; r < R; r++) x[r] = b[lds_pad_add<N>(base, base_addr, ST * r)];
+  if constexpr (R == 4) dft4(x);
+  if constexpr (R == 2) dft2(x);
+  if constexpr (ST > 1) {
+#pragma unroll
+    for (int r = 1; r < R; r++) x[r] = x[r] * tw[TWS * i * r];
+  }
+#pragma unroll
+  for (int r = 0; r < R; r++) b[lds_pad_add<N>(base, base_addr, ST * r)] = x[r];
+}
+
 template <int N, int R, int ST, int NSER, int NT, typename F>
 __device__ __forceinline__ void fft_pass(cx<F>* buf, const cx<F>* __restrict__ tw, int tid) {
   constexpr int NB = N / R;  // butterflies per series
   constexpr int SP = series_pitch<N>();
-  constexpr int TWS = N / (R * ST);
+  if constexpr (fft_wave_local<NSER, NT>()) {
+    constexpr int SPW = NSER / (NT / kWave);  // series per wave
+    const int w = tid / kWave, lane = tid % kWave;
 #pragma unroll 1
-  for (int item = tid; item < NSER * NB; item += NT) {
-    int sidx = item / NB, beta = item % NB;
-    int grp = beta / ST, i = beta % ST;
-    int base = grp * R * ST + i;
-    cx<F>* b = buf + sidx * SP;
-    const int base_addr = GBL_LDS_LAYOUT == 0 ? 0 : lds_pad<N>(base);
-    cx<F> x[R];
-#pragma unroll
-    for (int r = 0; r < R; r++) x[r] = b[lds_pad_add<N>(base, base_addr, ST * r)];
-    if constexpr (R == 4) dft4(x);
-    if constexpr (R == 2) dft2(x);
-    if constexpr (ST > 1) {
-#pragma unroll
-      for (int r = 1; r < R; r++) x[r] = x[r] * tw[TWS * i * r];
-    }
-#pragma unroll
-    for (int r = 0; r < R; r++) b[lds_pad_add<N>(base, base_addr, ST * r)] = x[r];
+    for (int item = lane; item < SPW * NB; item += kWave)
+      fft_butterfly<N, R, ST>(buf + (w * SPW + item / NB) * SP, tw, item % NB);
+    wave_sync();
+  } else {
+#pragma unroll 1
+    for (int item = tid; item < NSER * NB; item += NT) fft_butterfly<N, R, ST>(buf + (item / NB) * SP, tw, item % NB);
+    __syncthreads();
   }
 }
 
+// all passes; ends with a block barrier, so every thread may read every series
 template <int N, int NT, int NSER, int M, typename F>
 __device__ __forceinline__ void fft_stages(cx<F>* buf, const cx<F>* __restrict__ tw, int tid) {
   if constexpr (M >= 4) {
     fft_pass<N, 4, M / 4, NSER, NT>(buf, tw, tid);
-    __syncthreads();
     fft_stages<N, NT, NSER, M / 4>(buf, tw, tid);
   } else if constexpr (M == 2) {
     fft_pass<N, 2, 1, NSER, NT>(buf, tw, tid);
-    __syncthreads();
   }
+  if constexpr (M == N && fft_wave_local<NSER, NT>()) __syncthreads();
 }
 
 // ---------------------------------------------------------------------------
@@ -678,12 +746,14 @@ __device__ __forceinline__ void template_transform(const Src& s, const Geo& g, c
                                                    cx<F>* buf, int tid) {
   constexpr int SP = series_pitch<N>();
   constexpr int NT = block_threads<N>();
-  // link phases u = (1 -+ k.n) (pi f L/c - ...) stay below 2 pi (L/c) f_max plus the
-  // tiny fdot term: block-uniform choice of the short sinc/cos series
-  // (FP64 only; the FP32 series are short already)
+  // link phases u = (1 -+ k.n) (pi f L/c - ...) stay below 2 pi (L/c) f_max plus
+  // a tiny fdot term, and so do the receiver phase offsets
+  // 2 pi (cyc_r - cyc_0) = 2 pi (k.x_r - k.x_0)/c (-f + fdot (k.x_r + k.x_0)/(2c))
+  // with |k.x_r - k.x_0| <= L and |k.x_r| <= AU + 2L: block-uniform choice of
+  // the short series for both (FP64 only; the FP32 series are short already)
   const double f_max = fabs(s.f0) + fabs(s.fdot) * (g.T + 1100.0);
   const bool small_u = std::is_same<F, double>::value &&
-                       2.0 * kPi * g.Lc * f_max + 2.0 * kPi * fabs(s.fdot) * g.Lc * g.Lc <= 0.25;
+                       2.0 * kPi * g.Lc * (f_max + fabs(s.fdot) * (kAU / kC + 2.0 * g.Lc)) <= 0.25;
   if constexpr (!std::is_same<F, double>::value) {
 #pragma unroll 1
     for (int n = tid; n < N; n += NT) {
@@ -720,25 +790,29 @@ __device__ __forceinline__ void template_transform(const Src& s, const Geo& g, c
 }
 
 // Spectra of channels 0..NCH-1 (A, E[, T]) at window bin j, from the
-// transformed U/V series in LDS: C = (1 - D^2) F (U + D V) with D = exp(-i x),
-// x = 2 pi (q + k) L/(c T), F = (1/2)(T/N) exp(-i pi k/N), k = j - N/2.
-// D comes from the bin's phase in cycles through the exact reduction, and
-// 1 - D^2 = 2 sin x (sin x, cos x) is formed without cancellation (at 0.1 mHz
-// x ~ 5e-3, where 1 - cos 2x would lose three digits in single precision).
+// transformed U/V series in LDS: C = c_A,E,T (1 - D^2) F (U + D V) with
+// D = exp(-i x), x = 2 pi (q + k) L/(c T), F = (1/2)(T/N) exp(-i pi k/N),
+// k = j - N/2, and the channel normalisations c = 1/sqrt 2, 1/sqrt 6, 1/sqrt 3.
+// D is the carrier's factor exp(-2 pi i q L/(c T)) times the bin's table
+// entry (the relative error of sin x stays within a few ulp wherever
+// q + k >= N/2, since |k| <= N/2); 1 - D^2 = 2 sin x (sin x, cos x) is formed
+// without cancellation (at 0.1 mHz x ~ 5e-3, where 1 - cos 2x would lose
+// three digits in single precision).
 template <int N, int NCH, typename F>
 __device__ __forceinline__ void bin_spectrum(const Src& s, const Geo& g, const WaveTables<F>& tb, const cx<F>* buf,
                                              int j, cx<F>* out) {
   constexpr int SP = series_pitch<N>();
+  constexpr double norm[3] = {kInvSqrt2, kInvSqrt6, kInvSqrt3};
   const int kk = (j + N / 2) & (N - 1);
   const int pos = lds_pad<N>(fft_pos<N>(kk));
-  const double cyc = -(double)(s.q + (int64_t)(j - N / 2)) * (g.Lc / g.T);
-  cx<F> D;
-  expi_cycles_k<1, F>(&cyc, &D);
+  const cx<F> D = cvt<F>(s.dq) * tb.bin_W[j];
   // D = (cos x, -sin x):  1 - D^2 = (2 sin^2 x, 2 sin x cos x)
-  const cx<F> one_m = {(F)2 * D.im * D.im, (F)(-2) * D.im * D.re};
+  const F two_s = (F)2 * D.im;
   const cx<F> Fj = tb.bin_F[j];
 #pragma unroll
   for (int c = 0; c < NCH; c++) {
+    const F h = (F)norm[c] * two_s;
+    const cx<F> one_m = {h * D.im, -h * D.re};
     cx<F> U = buf[(2 * c) * SP + pos];
     cx<F> V = buf[(2 * c + 1) * SP + pos];
     out[c] = one_m * (Fj * (U + D * V));

@@ -7,8 +7,6 @@
 
 namespace gbl {
 
-constexpr int kWave = 64;
-
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -20,8 +18,8 @@ __device__ __forceinline__ double qnan() { return __builtin_nan(""); }
 // ---------------------------------------------------------------------------
 // Table construction (once per context)
 // ---------------------------------------------------------------------------
-__global__ void k_init_wave_tables(int N, double T, double* basis, cd* fft_tw, cd* bin_F, cf* fft_tw32,
-                                   cf* bin_F32) {
+__global__ void k_init_wave_tables(int N, double T, double Lc, double* basis, cd* fft_tw, cd* bin_F, cd* bin_W,
+                                   cf* fft_tw32, cf* bin_F32, cf* bin_W32) {
   int n = blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= N) return;
   double t = ((double)n + 0.5) * T / (double)N;
@@ -40,8 +38,10 @@ __global__ void k_init_wave_tables(int N, double T, double* basis, cd* fft_tw, c
   sincospi(-(double)k / (double)N, &s, &c);
   double h = 0.5 * T / (double)N;
   bin_F[n] = {h * c, h * s};
+  bin_W[n] = expi_cycles(-(double)k * (Lc / T));
   fft_tw32[n] = cvt<float>(fft_tw[n]);
   bin_F32[n] = cvt<float>(bin_F[n]);
+  bin_W32[n] = cvt<float>(bin_W[n]);
 }
 
 // PSD basis of eq. psd, linear in (S_oms, S_acc):  S_n = S_oms P1 + S_acc P2,
@@ -176,8 +176,8 @@ __device__ __forceinline__ void delta_one(const Geo& g, const WaveTables<F>& tb,
   constexpr int NT = block_threads<N>();
   constexpr int BPT = N / NT;  // window bins per thread
   const int tid = threadIdx.x;
-  // validity and carrier bins first; each source is fully decoded by one
-  // wave into LDS, which keeps the decoded sources out of the registers
+  // validity and carrier bins first; the full decode goes to LDS, which
+  // keeps the decoded sources out of the registers
   const SrcHead ho = source_head(da.p_old + 8 * b, g);
   const SrcHead hn = source_head(da.p_new + 8 * b, g);
   const int ri = da.res_idx[b];
@@ -197,12 +197,9 @@ __device__ __forceinline__ void delta_one(const Geo& g, const WaveTables<F>& tb,
 
   auto weight = [&](const double* Sc, int64_t idx) { return psd_inv ? Sc[idx] : 1.0 / Sc[idx]; };
 
-  // wave 0 decodes the old source, wave 1 the new one; the block shares them
-  if (tid < 2 * kWave) {
-    const int which = tid / kWave;
-    Src d = decode_source((which ? da.p_new : da.p_old) + 8 * b, g);
-    if ((tid & (kWave - 1)) == 0) sm.src[which] = d;
-  }
+  // lanes 0 and 1 of wave 0 decode the old and the new source side by side
+  // (one pass of the decode's instruction stream per pair); the block shares them
+  if (tid < 2) sm.src[tid] = decode_source((tid ? da.p_new : da.p_old) + 8 * b, g);
 
   __syncthreads();
 

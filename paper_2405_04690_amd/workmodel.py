@@ -6,19 +6,23 @@ channels A and E over the union U of the two template windows, and the 8-byte
 result.  The templates themselves never leave the chip.
 
 FP64 flops (an FMA counts 2): counted by hand from the formulation the
-kernel evaluates, per template of width N:
-  slow part, per midpoint sample
-    receiver terms, 3 craft: position 15, k.x/c 5, phase 8, sin/cos
-      (octant reduction in cycles + degree-15/16 Taylor) 40, f_r 3  -> 71 each
-    arm terms, 3 arms: direction 15, k.n 5, p.n 3, q.n 5, G 13      -> 41 each
-    links, 6: amplitude/phase 6, sinc & cos Taylor (13 + 14 FMA) 54,
-      envelope products 17                                           -> 77 each
-      (59 each for templates whose link phases stay below 0.25, about
-      f0 < 4.7 mHz, where the series stop 9 FMA earlier)
-    TDI pieces and A/E combinations                                  -> 48
-    common phase terms                                               -> 7
+kernel evaluates, per template of width N (the per-template decode, done once
+per source, is left out):
+  slow part, per midpoint sample; every projection on the orbit is an affine
+  function of (cos a, sin a, cos 2a, sin 2a) with per-source coefficients
+    receiver terms, 3 craft: k.x/c 8, phase 5, f_r 2               -> 15 each
+      phase factor: octant reduction in cycles + degree-15/16 Taylor  40 each
+      (templates whose link phases stay below 0.25, about f0 < 4.7 mHz:
+      40 for craft 0, and for craft 1, 2 the offset from craft 0 through
+      the short link series and one complex product: 32 each)
+    arm terms: k.n 8, q.n 8, p.n 4 for two arms, the third by closure 3,
+      G 10 for each of the three arms                               -> 73
+    links, 6: amplitude/phase 5, sinc & cos Taylor 45 (short series 23),
+      envelope products 16                                   -> 66 (44) each
+    TDI pieces and A/E combinations                                 -> 28
+    common phase terms                                              -> 9
   FFT: 5 N log2 N per series (the standard radix-2 count), 4 series
-  per bin: delay factors 14, per channel 20 (x2)                     -> 54
+  per bin: delay factor 6, 1 - D^2 1, per channel 23 (x2)          -> 53
 inner products: 20 flops per union bin.
 """
 from __future__ import annotations
@@ -35,18 +39,24 @@ C_LIGHT = 299792458.0
 
 
 def flops_per_sample(small_u: bool = False) -> int:
-    return 7 + 3 * 71 + 3 * 41 + 6 * (59 if small_u else 77) + 48
+    receivers = 3 * 15 + (40 + 2 * 32 if small_u else 3 * 40)
+    return 9 + receivers + 73 + 6 * (44 if small_u else 66) + 28
 
 
 def flops_per_template(N: int, n_series: int = 4, small_u: bool = False) -> int:
-    return N * flops_per_sample(small_u) + n_series * 5 * N * int(math.log2(N)) + N * 54
+    return N * flops_per_sample(small_u) + n_series * 5 * N * int(math.log2(N)) + N * 53
+
+
+AU = 1.495978707e11
 
 
 def small_link_phase(params: np.ndarray, T: float, L: float = 2.5e9) -> np.ndarray:
-    """templates whose link phases stay below 0.25 (the kernel's rule)"""
+    """templates whose link phases and receiver phase offsets stay below 0.25
+    (the kernel's rule)"""
     Lc = L / C_LIGHT
-    f_max = np.abs(params[:, 1]) + np.abs(params[:, 2]) * (T + 1100.0)
-    return 2 * math.pi * Lc * f_max + 2 * math.pi * np.abs(params[:, 2]) * Lc * Lc <= 0.25
+    fd = np.abs(params[:, 2])
+    f_max = np.abs(params[:, 1]) + fd * (T + 1100.0)
+    return 2 * math.pi * Lc * (f_max + fd * (AU / C_LIGHT + 2 * Lc)) <= 0.25
 
 
 def union_bins(params_old: np.ndarray, params_new: np.ndarray, T: float, N: int) -> np.ndarray:
