@@ -168,70 +168,97 @@ __device__ __forceinline__ SrcHead source_head(const double* __restrict__ prm, c
   return h;
 }
 
-__device__ __forceinline__ Src decode_source(const double* __restrict__ prm, const Geo& g) {
-  Src s;
-  double A = prm[0], f0 = prm[1], fdot = prm[2], phi0 = prm[3];
-  double iota = prm[4], psi = prm[5], lam = prm[6], beta = prm[7];
-  bool finite = isfinite(A) && isfinite(f0) && isfinite(fdot) && isfinite(phi0) && isfinite(iota) &&
-                isfinite(psi) && isfinite(lam) && isfinite(beta) && fabs(f0 * g.T) < 4503599627370496.0;
-  s.state = finite ? (A == 0.0 ? 1 : 0) : 2;
-  if (!finite) {
-    f0 = 0.0;  // keep the arithmetic below well defined
+// Full decode of NSRC (1 or 2) sources by one whole wave (every lane must
+// take part) into LDS, spread over the lanes so that the wave issues about one
+// trigonometric evaluation and one group of coefficients instead of all of
+// them.  Lanes 32 t + a of source t:
+//   a = 0..3  sin/cos of lambda, beta, iota, 2 psi (then shared by shuffles)
+//   a = 0..2  k.x_r/c coefficients of receiver r = a
+//   a = 3..8  arm m = (a-3)/3 projection coefficients of k, q or p
+//   a = 9     carrier bin, phases, polarisation amplitudes, delay factor, state
+template <int NSRC>
+__device__ __forceinline__ void decode_sources(const double* __restrict__ p0, const double* __restrict__ p1,
+                                               const Geo& g, Src* out) {
+  const int lane = (int)(threadIdx.x & (kWave - 1));
+  const int t = (lane >> 5) < NSRC ? (lane >> 5) : 0;
+  const int role = lane & 31;
+  const bool writer = (lane >> 5) < NSRC;
+  const double* prm = t ? p1 : p0;
+  double sv = 0.0, cv = 1.0;
+  {
+    const int a = role & 3;
+    const double ang = a == 0 ? prm[6] : a == 1 ? prm[7] : a == 2 ? prm[4] : 2.0 * prm[5];
+    if (role < 4) sincos(ang, &sv, &cv);
   }
-  s.f0 = f0;
-  s.fdot = fdot;
-  s.phi0_cyc = phi0 / kTwoPi;
-  double qd = floor(f0 * g.T);
-  s.q = (int64_t)qd;
-  s.dfq = f0 - qd / g.T;
-  double sl, cl, sb, cb;
-  sincos(lam, &sl, &cl);
-  sincos(beta, &sb, &cb);
+  const int l0 = t << 5;
+  const double sl = __shfl(sv, l0 + 0), cl = __shfl(cv, l0 + 0);
+  const double sb = __shfl(sv, l0 + 1), cb = __shfl(cv, l0 + 1);
+  const double ci = __shfl(cv, l0 + 2);
+  const double s2p = __shfl(sv, l0 + 3), c2p = __shfl(cv, l0 + 3);
+  if (!writer) return;
+  Src& s = out[t];
   // propagation direction k = -(sky direction) and polarisation basis p, q
   const double kh[3] = {-cb * cl, -cb * sl, -sb};
   const double pv[2] = {sl, -cl};
   const double qv[3] = {-sb * cl, -sb * sl, cb};
-  const double kc[3] = {kh[0] / kC, kh[1] / kC, kh[2] / kC};
-  // craft r at orientation 2 pi r/3 (cos/sin br):
-  //   x_r = AU (cos a, sin a, 0) + eh (cos 2a cbr + sin 2a sbr - 3 cbr,
-  //         sin 2a cbr - cos 2a sbr - 3 sbr, 0) - ez (0, 0, cos a cbr + sin a sbr)
   constexpr double cbs[3] = {1.0, -0.5, -0.5};
   constexpr double sbs[3] = {0.0, 0.86602540378443864676, -0.86602540378443864676};
-  for (int r = 0; r < 3; r++) {
-    s.xr[r][0] = kc[0] * kAU - kc[2] * g.ez * cbs[r];
-    s.xr[r][1] = kc[1] * kAU - kc[2] * g.ez * sbs[r];
-    s.xr[r][2] = g.eh * (kc[0] * cbs[r] - kc[1] * sbs[r]);
-    s.xr[r][3] = g.eh * (kc[0] * sbs[r] + kc[1] * cbs[r]);
-    s.xr[r][4] = -3.0 * g.eh * (kc[0] * cbs[r] + kc[1] * sbs[r]);
-  }
-  // arm m = craft m -> m+1: n_m = (x_{m+1} - x_m) / L
-  const double sh = g.inv_L * g.eh, sz = g.inv_L * g.ez;
-  for (int m = 0; m < 2; m++) {
-    const double dcb = cbs[m + 1] - cbs[m], dsb = sbs[m + 1] - sbs[m];
-    auto proj = [&](double v0, double v1, double v2, double* c) {
+  if (role < 3) {
+    // craft r at orientation 2 pi r/3 (cos/sin br):
+    //   x_r = AU (cos a, sin a, 0) + eh (cos 2a cbr + sin 2a sbr - 3 cbr,
+    //         sin 2a cbr - cos 2a sbr - 3 sbr, 0) - ez (0, 0, cos a cbr + sin a sbr)
+    const int r = role;
+    const double cbr = r == 0 ? cbs[0] : r == 1 ? cbs[1] : cbs[2];
+    const double sbr = r == 0 ? sbs[0] : r == 1 ? sbs[1] : sbs[2];
+    const double kc[3] = {kh[0] / kC, kh[1] / kC, kh[2] / kC};
+    double* c = s.xr[r];
+    c[0] = kc[0] * kAU - kc[2] * g.ez * cbr;
+    c[1] = kc[1] * kAU - kc[2] * g.ez * sbr;
+    c[2] = g.eh * (kc[0] * cbr - kc[1] * sbr);
+    c[3] = g.eh * (kc[0] * sbr + kc[1] * cbr);
+    c[4] = -3.0 * g.eh * (kc[0] * cbr + kc[1] * sbr);
+  } else if (role < 9) {
+    // arm m = craft m -> m+1: n_m = (x_{m+1} - x_m) / L; projection of v = k, q or p
+    const int m = (role - 3) / 3, w = (role - 3) % 3;
+    const double dcb = m == 0 ? cbs[1] - cbs[0] : cbs[2] - cbs[1];
+    const double dsb = m == 0 ? sbs[1] - sbs[0] : sbs[2] - sbs[1];
+    const double v0 = w == 0 ? kh[0] : w == 1 ? qv[0] : pv[0];
+    const double v1 = w == 0 ? kh[1] : w == 1 ? qv[1] : pv[1];
+    const double v2 = w == 0 ? kh[2] : w == 1 ? qv[2] : 0.0;
+    const double sh = g.inv_L * g.eh, sz = g.inv_L * g.ez;
+    const double c2 = sh * (v0 * dcb - v1 * dsb);
+    const double c3 = sh * (v0 * dsb + v1 * dcb);
+    const double c4 = -3.0 * sh * (v0 * dcb + v1 * dsb);
+    if (w == 2) {
+      s.pn[m][0] = c2;
+      s.pn[m][1] = c3;
+      s.pn[m][2] = c4;
+    } else {
+      double* c = w == 0 ? s.kn[m] : s.qn[m];
       c[0] = -sz * v2 * dcb;
       c[1] = -sz * v2 * dsb;
-      c[2] = sh * (v0 * dcb - v1 * dsb);
-      c[3] = sh * (v0 * dsb + v1 * dcb);
-      c[4] = -3.0 * sh * (v0 * dcb + v1 * dsb);
-    };
-    proj(kh[0], kh[1], kh[2], s.kn[m]);
-    proj(qv[0], qv[1], qv[2], s.qn[m]);
-    double c[5];
-    proj(pv[0], pv[1], 0.0, c);
-    s.pn[m][0] = c[2];
-    s.pn[m][1] = c[3];
-    s.pn[m][2] = c[4];
+      c[2] = c2;
+      c[3] = c3;
+      c[4] = c4;
+    }
+  } else if (role == 9) {
+    double A = prm[0], f0 = prm[1], fdot = prm[2], phi0 = prm[3];
+    bool finite = isfinite(A) && isfinite(f0) && isfinite(fdot) && isfinite(phi0) && isfinite(prm[4]) &&
+                  isfinite(prm[5]) && isfinite(prm[6]) && isfinite(prm[7]) && fabs(f0 * g.T) < 4503599627370496.0;
+    s.state = finite ? (A == 0.0 ? 1 : 0) : 2;
+    if (!finite) f0 = 0.0;  // keep the arithmetic below well defined
+    s.f0 = f0;
+    s.fdot = fdot;
+    s.phi0_cyc = phi0 / kTwoPi;
+    const double qd = floor(f0 * g.T);
+    s.q = (int64_t)qd;
+    s.dfq = f0 - qd / g.T;
+    const double ap = A * (1.0 + ci * ci);
+    const double ax = 2.0 * A * ci;
+    s.cp = {ap * c2p, -ax * s2p};
+    s.cx2 = {2.0 * ap * s2p, 2.0 * ax * c2p};
+    s.dq = expi_cycles(-(double)s.q * (g.Lc / g.T));
   }
-  double ci = cos(iota);
-  double s2p, c2p;
-  sincos(2.0 * psi, &s2p, &c2p);
-  double ap = A * (1.0 + ci * ci);
-  double ax = 2.0 * A * ci;
-  s.cp = {ap * c2p, -ax * s2p};
-  s.cx2 = {2.0 * ap * s2p, 2.0 * ax * c2p};
-  s.dq = expi_cycles(-(double)s.q * (g.Lc / g.T));
-  return s;
 }
 
 // ---------------------------------------------------------------------------

@@ -97,10 +97,7 @@ __device__ __forceinline__ void waveform_one(const Geo& g, const WaveTables<F>& 
                                              WaveSmem<N, NSER, F>& sm) {
   constexpr int NT = block_threads<N>();
   const int tid = threadIdx.x;
-  if (tid < kWave) {  // one wave decodes, the block shares the result
-    Src d = decode_source(prm, g);
-    if (tid == 0) sm.src = d;
-  }
+  if (tid < kWave) decode_sources<1>(prm, prm, g, &sm.src);  // one wave decodes, the block shares it
   __syncthreads();
   const Src& s = sm.src;
   if (s.state == 0) template_transform<N, NSER, F>(s, g, tb, sm.buf, tid);
@@ -197,9 +194,8 @@ __device__ __forceinline__ void delta_one(const Geo& g, const WaveTables<F>& tb,
 
   auto weight = [&](const double* Sc, int64_t idx) { return psd_inv ? Sc[idx] : 1.0 / Sc[idx]; };
 
-  // lanes 0 and 1 of wave 0 decode the old and the new source side by side
-  // (one pass of the decode's instruction stream per pair); the block shares them
-  if (tid < 2) sm.src[tid] = decode_source((tid ? da.p_new : da.p_old) + 8 * b, g);
+  // wave 0 decodes the old and the new source side by side; the block shares them
+  if (tid < kWave) decode_sources<2>(da.p_old + 8 * b, da.p_new + 8 * b, g, sm.src);
 
   __syncthreads();
 
@@ -418,10 +414,7 @@ __global__ __launch_bounds__(block_threads<N>()) void k_scatter_add(Geo g, WaveT
   const SrcHead h = source_head(params + 8 * b, g);
   const int ri = res_idx[b];
   if (h.state != 0 || ri < 0 || ri >= n_res) return;  // zero or invalid templates add nothing
-  if (tid < kWave) {
-    Src d = decode_source(params + 8 * b, g);
-    if (tid == 0) s_sh = d;
-  }
+  if (tid < kWave) decode_sources<1>(params + 8 * b, params + 8 * b, g, &s_sh);
   __syncthreads();
   const Src& s = s_sh;
   template_transform<N, 4, F>(s, g, tb, buf, tid);

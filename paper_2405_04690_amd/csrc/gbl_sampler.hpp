@@ -165,10 +165,7 @@ __device__ __noinline__ void band_template(const Geo& g, const WaveTables<double
     sm.prm[7] = asin(u[7]);
   }
   __syncthreads();
-  if (tid < kWave) {
-    Src d = decode_source(sm.prm, g);
-    if (tid == 0) sm.src = d;
-  }
+  if (tid < kWave) decode_sources<1>(sm.prm, sm.prm, g, &sm.src);
   __syncthreads();
   template_transform<N, 4, double>(sm.src, g, tb, sm.buf, tid);
 }
