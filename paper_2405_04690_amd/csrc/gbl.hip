@@ -18,7 +18,7 @@ using gbl::cd;
 
 namespace {
 
-constexpr int kNumWidths = 4;
+constexpr int kNumWidths = gbl::kBucketWidths;
 constexpr int kWidths[kNumWidths] = {128, 256, 512, 1024};
 constexpr int64_t kMaxGrid = (int64_t)1 << 30;  // blocks per launch (grid.x limit is 2^31 - 1)
 constexpr int64_t kPsdBatch = 4096;             // parameter sets per PSD-likelihood launch pair
@@ -252,7 +252,7 @@ static gbl::DeltaArgs with_route(gbl_ctx* ctx, gbl::DeltaArgs da, int N, int64_t
 template <int N>
 static void launch_route_pass(gbl_ctx* ctx, const gbl::DeltaArgs& da, int64_t b0, int64_t nb) {
   const int slot = width_slot(N);
-  hipLaunchKernelGGL((gbl::k_delta_loglike_list<N>), dim3((unsigned)nb), dim3(gbl::block_threads<N>()), 0,
+  hipLaunchKernelGGL((gbl::k_delta_loglike_list<N>), dim3((unsigned)nb), dim3(gbl::delta_threads<N>()), 0,
                      ctx->stream, ctx->geo, tables_for<N, double>(ctx), da, b0,
                      (const int*)(ctx->route_counts + slot), (const int32_t*)(ctx->route_lists + (int64_t)slot * kBucketCap));
 }
@@ -262,14 +262,14 @@ struct LaunchDelta {
   static void run(gbl_ctx* ctx, const gbl::DeltaArgs& da, int64_t b0, int64_t nb) {
     if (routed(ctx)) {
       hipLaunchKernelGGL(gbl::k_bucket_reset, dim3(1), dim3(64), 0, ctx->stream, ctx->route_counts, kNumWidths);
-      hipLaunchKernelGGL((gbl::k_delta_loglike<N, float>), dim3((unsigned)nb), dim3(gbl::block_threads<N>()), 0,
+      hipLaunchKernelGGL((gbl::k_delta_loglike<N, float>), dim3((unsigned)nb), dim3(gbl::delta_threads<N>()), 0,
                          ctx->stream, ctx->geo, tables_for<N, float>(ctx), with_route(ctx, da, N, b0), b0);
       launch_route_pass<N>(ctx, da, b0, nb);
     } else if (ctx->cfg.precision == GBL_MIXED)
-      hipLaunchKernelGGL((gbl::k_delta_loglike<N, float>), dim3((unsigned)nb), dim3(gbl::block_threads<N>()), 0,
+      hipLaunchKernelGGL((gbl::k_delta_loglike<N, float>), dim3((unsigned)nb), dim3(gbl::delta_threads<N>()), 0,
                          ctx->stream, ctx->geo, tables_for<N, float>(ctx), da, b0);
     else
-      hipLaunchKernelGGL((gbl::k_delta_loglike<N, double>), dim3((unsigned)nb), dim3(gbl::block_threads<N>()), 0,
+      hipLaunchKernelGGL((gbl::k_delta_loglike<N, double>), dim3((unsigned)nb), dim3(gbl::delta_threads<N>()), 0,
                          ctx->stream, ctx->geo, tables_for<N, double>(ctx), da, b0);
   }
 };
@@ -281,15 +281,15 @@ struct LaunchDeltaBucket {
     const int* cnt = ctx->counts + slot;
     const int32_t* perm = ctx->perm + (int64_t)slot * kBucketCap;
     if (routed(ctx)) {
-      hipLaunchKernelGGL((gbl::k_delta_loglike_bucket<N, float>), dim3((unsigned)nb), dim3(gbl::block_threads<N>()),
+      hipLaunchKernelGGL((gbl::k_delta_loglike_bucket<N, float>), dim3((unsigned)nb), dim3(gbl::delta_threads<N>()),
                          0, ctx->stream, ctx->geo, tables_for<N, float>(ctx), with_route(ctx, da, N, b0), b0, cnt,
                          perm);
       launch_route_pass<N>(ctx, da, b0, nb);
     } else if (ctx->cfg.precision == GBL_MIXED)
-      hipLaunchKernelGGL((gbl::k_delta_loglike_bucket<N, float>), dim3((unsigned)nb), dim3(gbl::block_threads<N>()),
+      hipLaunchKernelGGL((gbl::k_delta_loglike_bucket<N, float>), dim3((unsigned)nb), dim3(gbl::delta_threads<N>()),
                          0, ctx->stream, ctx->geo, tables_for<N, float>(ctx), da, b0, cnt, perm);
     else
-      hipLaunchKernelGGL((gbl::k_delta_loglike_bucket<N, double>), dim3((unsigned)nb), dim3(gbl::block_threads<N>()),
+      hipLaunchKernelGGL((gbl::k_delta_loglike_bucket<N, double>), dim3((unsigned)nb), dim3(gbl::delta_threads<N>()),
                          0, ctx->stream, ctx->geo, tables_for<N, double>(ctx), da, b0, cnt, perm);
   }
 };

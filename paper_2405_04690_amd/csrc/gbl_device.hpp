@@ -768,11 +768,10 @@ __device__ __forceinline__ void fft_stages(cx<F>* buf, const cx<F>* __restrict__
 // spectrum at any window bin j from the transformed U/V series in LDS.
 // Ends with a barrier, so the caller may read the workspace immediately.
 // ---------------------------------------------------------------------------
-template <int N, int NSER, typename F>
+template <int N, int NSER, typename F, int NT = block_threads<N>()>
 __device__ __forceinline__ void template_transform(const Src& s, const Geo& g, const WaveTables<F>& tb,
                                                    cx<F>* buf, int tid) {
   constexpr int SP = series_pitch<N>();
-  constexpr int NT = block_threads<N>();
   // link phases u = (1 -+ k.n) (pi f L/c - ...) stay below 2 pi (L/c) f_max plus
   // a tiny fdot term, and so do the receiver phase offsets
   // 2 pi (cyc_r - cyc_0) = 2 pi (k.x_r - k.x_0)/c (-f + fdot (k.x_r + k.x_0)/(2c))

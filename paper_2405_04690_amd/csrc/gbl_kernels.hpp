@@ -159,18 +159,27 @@ struct DeltaArgs {
   int64_t route_b0;
 };
 
+// threads per block of the fused likelihood kernels: one per sample and bin
+// at every width.  The LDS a block needs grows with N (96 KB at N = 1024), so
+// wide templates fit one or a few blocks per CU; a block of N threads keeps
+// four waves on every SIMD all the same.
+template <int N>
+constexpr int delta_threads() {
+  return N;
+}
+
 template <int N, typename F>
 struct DeltaSmem {
   cx<F> buf[4 * series_pitch<N>()];
   cx<F> rwin[2 * N];
-  double red[6 * (block_threads<N>() / kWave)];
+  double red[6 * (delta_threads<N>() / kWave)];
   Src src[2];  // 0: old, 1: new
 };
 
 template <int N, typename F>
 __device__ __forceinline__ void delta_one(const Geo& g, const WaveTables<F>& tb, const DeltaArgs& da, int64_t b,
                                           DeltaSmem<N, F>& sm) {
-  constexpr int NT = block_threads<N>();
+  constexpr int NT = delta_threads<N>();
   constexpr int BPT = N / NT;  // window bins per thread
   const int tid = threadIdx.x;
   // validity and carrier bins first; the full decode goes to LDS, which
@@ -202,7 +211,7 @@ __device__ __forceinline__ void delta_one(const Geo& g, const WaveTables<F>& tb,
   // old template into the LDS window
   if (ho.state == 0) {
     const Src& so = sm.src[0];
-    template_transform<N, 4, F>(so, g, tb, sm.buf, tid);
+    template_transform<N, 4, F, NT>(so, g, tb, sm.buf, tid);
     for (int j = tid; j < N; j += NT) {
       cx<F> v[2];
       bin_spectrum<N, 2, F>(so, g, tb, sm.buf, j, v);
@@ -236,28 +245,19 @@ __device__ __forceinline__ void delta_one(const Geo& g, const WaveTables<F>& tb,
 
   if (hn.state == 0) {
     const Src& sn = sm.src[1];
-    template_transform<N, 4, F>(sn, g, tb, sm.buf, tid);
-    // residual and weights over a's window (loaded here, not earlier: at four
-    // waves per SIMD the other waves hide the latency, and no registers stay
-    // occupied across the two template builds)
-    cd pR0[BPT], pR1[BPT];
-    double pW0[BPT], pW1[BPT];
-#pragma unroll
-    for (int m = 0; m < BPT; m++) {
-      int64_t k = ka + tid + NT * m;
-      if (k >= g.k_min && k < g.k_min + nb) {
-        int64_t idx = k - g.k_min;
-        pR0[m] = RA[idx];
-        pR1[m] = RE[idx];
-        pW0[m] = weight(SA, idx);
-        pW1[m] = weight(SE, idx);
-      }
-    }
-#pragma unroll
+    template_transform<N, 4, F, NT>(sn, g, tb, sm.buf, tid);
+    // a's window, one bin per iteration: residual and weights are loaded at
+    // the top of the iteration (not earlier: at four waves per SIMD the other
+    // waves hide the latency, and no registers stay occupied across the
+    // template builds or across the bins of the wider templates)
+#pragma unroll 1
     for (int m = 0; m < BPT; m++) {
       const int j = tid + NT * m;
       int64_t k = ka + j;
       if (k < g.k_min || k >= g.k_min + nb) continue;
+      const int64_t idx = k - g.k_min;
+      const cd R0 = RA[idx], R1 = RE[idx];
+      const double W0 = weight(SA, idx), W1 = weight(SE, idx);
       cx<F> v[2];
       bin_spectrum<N, 2, F>(sn, g, tb, sm.buf, j, v);
       cd a0 = cvt<double>(v[0]);
@@ -266,17 +266,16 @@ __device__ __forceinline__ void delta_one(const Geo& g, const WaveTables<F>& tb,
       const bool has_r = ho.state == 0 && jr >= 0 && jr < N;
       if constexpr (kEst) {
         if (da.route_list) {
-          magnitude(pR0[m], pR1[m], pW0[m], pW1[m], a0, a1, true);
+          magnitude(R0, R1, W0, W1, a0, a1, true);
           if (has_r)
-            magnitude(pR0[m], pR1[m], pW0[m], pW1[m], cvt<double>(sm.rwin[jr]), cvt<double>(sm.rwin[N + jr]),
-                      false);
+            magnitude(R0, R1, W0, W1, cvt<double>(sm.rwin[jr]), cvt<double>(sm.rwin[N + jr]), false);
         }
       }
       if (has_r) {
         a0 = a0 - cvt<double>(sm.rwin[jr]);
         a1 = a1 - cvt<double>(sm.rwin[N + jr]);
       }
-      accumulate(pR0[m], pR1[m], pW0[m], pW1[m], a0, a1);
+      accumulate(R0, R1, W0, W1, a0, a1);
     }
   }
   if (ho.state == 0) {
@@ -316,16 +315,15 @@ __device__ __forceinline__ void delta_one(const Geo& g, const WaveTables<F>& tb,
   }
 }
 
-// occupancy target of the fused kernel: four waves per SIMD at N <= 256 (the
-// compiler then keeps 128 VGPRs and spills a few values to scratch, which
-// measures faster than three waves without spills)
+// occupancy target of the fused kernel: four waves per SIMD at every width
+// (at most 128 VGPRs; the kernels fit in 112 without spills)
 template <int N>
 constexpr int delta_min_waves() {
-  return N <= 256 ? 4 : 1;
+  return 4;
 }
 
 template <int N, typename F>
-__global__ __launch_bounds__(block_threads<N>(), delta_min_waves<N>()) void k_delta_loglike(Geo g, WaveTables<F> tb,
+__global__ __launch_bounds__(delta_threads<N>(), delta_min_waves<N>()) void k_delta_loglike(Geo g, WaveTables<F> tb,
                                                                                             DeltaArgs da, int64_t b0) {
   __shared__ DeltaSmem<N, F> sm;
   delta_one<N, F>(g, tb, da, b0 + blockIdx.x, sm);
@@ -334,7 +332,7 @@ __global__ __launch_bounds__(block_threads<N>(), delta_min_waves<N>()) void k_de
 // FP64 pass over a list of pairs (the mixed-precision pairs whose error
 // estimate is too large): block i takes entry i, blocks past the count exit.
 template <int N>
-__global__ __launch_bounds__(block_threads<N>(), delta_min_waves<N>()) void k_delta_loglike_list(
+__global__ __launch_bounds__(delta_threads<N>(), delta_min_waves<N>()) void k_delta_loglike_list(
     Geo g, WaveTables<double> tb, DeltaArgs da, int64_t b0, const int* __restrict__ count,
     const int32_t* __restrict__ list) {
   __shared__ DeltaSmem<N, double> sm;
@@ -359,23 +357,40 @@ __global__ void k_bucket_reset(int* counts, int n) {
 
 // Templates whose width is not supported are not queued; they get a NaN
 // output (bad_out) or the start-bin sentinel INT64_MIN (bad_start).
-__global__ void k_bucket_by_width(const int32_t* __restrict__ widths, int64_t b0, int64_t nb, int cap,
-                                  int* __restrict__ counts, int32_t* __restrict__ perm, double* __restrict__ bad_out,
-                                  int64_t* __restrict__ bad_start) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nb) return;
-  int slot = width_bucket(widths[b0 + i]);
-  if (slot < 0) {
-    if (bad_out) bad_out[b0 + i] = qnan();
-    if (bad_start) bad_start[b0 + i] = INT64_MIN;
-    return;
+// Positions are taken per block: LDS atomics give each pair its place among
+// the block's pairs of the same width, and one global atomic per width and
+// block reserves the block's run in the bucket (a global atomic per pair
+// would serialise on the four counters).  The order inside a bucket follows
+// the order in which blocks reserve; every pair is queued exactly once.
+constexpr int kBucketWidths = 4;
+
+__global__ __launch_bounds__(256) void k_bucket_by_width(const int32_t* __restrict__ widths, int64_t b0, int64_t nb,
+                                                         int cap, int* __restrict__ counts,
+                                                         int32_t* __restrict__ perm, double* __restrict__ bad_out,
+                                                         int64_t* __restrict__ bad_start) {
+  __shared__ int local_count[kBucketWidths], block_base[kBucketWidths];
+  const int tid = threadIdx.x;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + tid;
+  if (tid < kBucketWidths) local_count[tid] = 0;
+  __syncthreads();
+  int slot = -1, local = 0;
+  if (i < nb) {
+    slot = width_bucket(widths[b0 + i]);
+    if (slot < 0) {
+      if (bad_out) bad_out[b0 + i] = qnan();
+      if (bad_start) bad_start[b0 + i] = INT64_MIN;
+    } else {
+      local = atomicAdd(&local_count[slot], 1);
+    }
   }
-  int pos = atomicAdd(&counts[slot], 1);
-  perm[(int64_t)slot * cap + pos] = (int32_t)i;
+  __syncthreads();
+  if (tid < kBucketWidths && local_count[tid] > 0) block_base[tid] = atomicAdd(&counts[tid], local_count[tid]);
+  __syncthreads();
+  if (slot >= 0) perm[(int64_t)slot * cap + block_base[slot] + local] = (int32_t)i;
 }
 
 template <int N, typename F>
-__global__ __launch_bounds__(block_threads<N>(), delta_min_waves<N>()) void k_delta_loglike_bucket(Geo g,
+__global__ __launch_bounds__(delta_threads<N>(), delta_min_waves<N>()) void k_delta_loglike_bucket(Geo g,
                                                                                                    WaveTables<F> tb,
                                                                                                    DeltaArgs da,
                                                                              int64_t b0, const int* __restrict__ count,
