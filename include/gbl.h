@@ -20,7 +20,11 @@
  *              PSD basis, reduction workspace) and frees it in gbl_destroy.
  *   Streams    Compute calls only enqueue work on the context's stream and
  *              return; outputs are valid once the caller synchronises that
- *              stream.  Compute calls never allocate, synchronise or print.
+ *              stream.  Compute calls never allocate or print, and they do not
+ *              synchronise, with one exception that the exact_grids knob
+ *              (gbl_tuning) controls: the width-bucketed calls and the FP64
+ *              re-evaluation pass of GBL_MIXED read device-side list lengths
+ *              back to size their launches, outside stream capture only.
  *   Errors     Calls return GBL_OK (0) or a negative status.  Argument errors
  *              are detected on the host before anything is launched;
  *              gbl_last_error() returns a message for the last failure.
@@ -116,12 +120,22 @@ int gbl_band(const gbl_ctx* ctx, int64_t* k_min, int64_t* n_bins);
  *   bucket_chunk  templates per bucketed launch group (uneven widths; the FP64
  *                 re-evaluation of mixed-precision pairs), a
  *                 power of two in [4096, 1048576] (default 1048576);
- *   widest_first  uneven widths: launch the widest bucket first (1) or last (0).
+ *   widest_first  uneven widths: launch the widest bucket first (1) or last (0);
+ *   exact_grids   1 (default): when the context's stream is not being captured,
+ *                 gb_waveform_var, gb_delta_loglike_var and the FP64
+ *                 re-evaluation pass of GBL_MIXED copy the device-side bucket
+ *                 sizes (and routed-pair counts) to pinned host memory, one
+ *                 stream synchronisation each, and launch exactly that many
+ *                 work-groups; 0: never synchronise, launch the upper bound
+ *                 (the batch size) and let the surplus work-groups exit (at
+ *                 N = 1024 those hold 96 KB of LDS each and cost up to a third
+ *                 of the launch).  Under capture the upper bound is always used.
  * Results do not depend on them (bitwise for the FP64 paths). */
 typedef struct {
   int32_t flow_grid;
   int32_t bucket_chunk;
   int32_t widest_first;
+  int32_t exact_grids;
 } gbl_tuning;
 
 int gbl_get_tuning(const gbl_ctx* ctx, gbl_tuning* out);
@@ -162,7 +176,7 @@ int gb_delta_loglike(gbl_ctx* ctx, const double* residual, int32_t n_res, const 
  * array) and its slices start at element out_offset[b] (device array, in
  * complex elements) of A, E and Tch.  Templates are bucketed by width on the
  * device (atomic position counters) and each width runs as one launch over
- * its bucket; nothing is synchronised on the host.  A template whose N[b] is not
+ * its bucket, sized as the exact_grids knob says.  A template whose N[b] is not
  * supported is skipped and gets start_bin[b] = INT64_MIN.  The caller owns the
  * layout: slices of different templates must not overlap.
  * Errors: GBL_EINVAL (null pointers, B < 0). */

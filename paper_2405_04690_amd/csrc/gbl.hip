@@ -47,8 +47,31 @@ struct gbl_ctx {
   gbl_tuning tune;        // launch-shape knobs
   int* route_counts;      // [4 widths] mixed-precision pairs queued for the FP64 pass
   int32_t* route_lists;   // [4 widths][kBucketCap]
+  int* host_counts;       // pinned [8]: device-side counts read back for exact grids
   std::string err;
 };
+
+// Device-side list lengths (width buckets, routed pairs) copied to the host
+// when the stream is not being captured, at the price of one stream
+// synchronisation, so that the launches that walk the lists get exact grids.
+// Under capture (or if the copy fails) the grids stay at their upper bound and
+// the surplus blocks exit at once; at N = 1024, whose blocks hold 96 KB of LDS,
+// those empty blocks cost as much as a third of the launch.
+static bool host_counts(gbl_ctx* ctx, const int* dev, int n, int* out) {
+  if (!ctx->tune.exact_grids) return false;
+  hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(ctx->stream, &st) != hipSuccess || st != hipStreamCaptureStatusNone) {
+    (void)hipGetLastError();
+    return false;
+  }
+  if (hipMemcpyAsync(ctx->host_counts, dev, sizeof(int) * n, hipMemcpyDeviceToHost, ctx->stream) != hipSuccess ||
+      hipStreamSynchronize(ctx->stream) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  for (int i = 0; i < n; i++) out[i] = ctx->host_counts[i];
+  return true;
+}
 
 static int fail(gbl_ctx* ctx, int code, const char* fmt, const char* detail = "") {
   if (ctx) {
@@ -78,6 +101,7 @@ static void release(gbl_ctx* ctx) {
   if (ctx->perm) (void)hipFree(ctx->perm);
   if (ctx->route_counts) (void)hipFree(ctx->route_counts);
   if (ctx->route_lists) (void)hipFree(ctx->route_lists);
+  if (ctx->host_counts) (void)hipHostFree(ctx->host_counts);
 }
 
 extern "C" int gbl_create(gbl_ctx** out, const gbl_config* cfg, void* hip_stream) {
@@ -91,7 +115,7 @@ extern "C" int gbl_create(gbl_ctx** out, const gbl_config* cfg, void* hip_stream
   if (cfg->precision != GBL_FP64 && cfg->precision != GBL_MIXED) return GBL_EUNSUPPORTED;
 
   gbl_ctx* ctx = new gbl_ctx();
-  ctx->tune = gbl_tuning{4096, kBucketCap, 1};
+  ctx->tune = gbl_tuning{4096, kBucketCap, 1, 1};
   ctx->cfg = *cfg;
   ctx->stream = (hipStream_t)hip_stream;
   int64_t k_min = (int64_t)std::ceil(cfg->f_lo * cfg->T);
@@ -138,7 +162,8 @@ extern "C" int gbl_create(gbl_ctx** out, const gbl_config* cfg, void* hip_stream
       hipMalloc(&ctx->counts, sizeof(int) * kNumWidths) != hipSuccess ||
       hipMalloc(&ctx->perm, sizeof(int32_t) * (size_t)kNumWidths * kBucketCap) != hipSuccess ||
       hipMalloc(&ctx->route_counts, sizeof(int) * kNumWidths) != hipSuccess ||
-      hipMalloc(&ctx->route_lists, sizeof(int32_t) * (size_t)kNumWidths * kBucketCap) != hipSuccess) {
+      hipMalloc(&ctx->route_lists, sizeof(int32_t) * (size_t)kNumWidths * kBucketCap) != hipSuccess ||
+      hipHostMalloc((void**)&ctx->host_counts, sizeof(int) * 8, hipHostMallocDefault) != hipSuccess) {
     release(ctx);
     delete ctx;
     return GBL_EHIP;
@@ -249,13 +274,26 @@ static gbl::DeltaArgs with_route(gbl_ctx* ctx, gbl::DeltaArgs da, int N, int64_t
   return da;
 }
 
+// FP64 re-evaluation of the routed pairs of width N; grid = the routed count
+// when known on the host, else its upper bound nb
 template <int N>
-static void launch_route_pass(gbl_ctx* ctx, const gbl::DeltaArgs& da, int64_t b0, int64_t nb) {
+static void launch_route_pass(gbl_ctx* ctx, const gbl::DeltaArgs& da, int64_t b0, int64_t grid) {
+  if (grid <= 0) return;
   const int slot = width_slot(N);
-  hipLaunchKernelGGL((gbl::k_delta_loglike_list<N>), dim3((unsigned)nb), dim3(gbl::delta_threads<N>()), 0,
+  hipLaunchKernelGGL((gbl::k_delta_loglike_list<N>), dim3((unsigned)grid), dim3(gbl::delta_threads<N>()), 0,
                      ctx->stream, ctx->geo, tables_for<N, double>(ctx), da, b0,
-                     (const int*)(ctx->route_counts + slot), (const int32_t*)(ctx->route_lists + (int64_t)slot * kBucketCap));
+                     (const int*)(ctx->route_counts + slot),
+                     (const int32_t*)(ctx->route_lists + (int64_t)slot * kBucketCap));
 }
+
+template <int N>
+struct LaunchRoutePass {
+  static void run(gbl_ctx* ctx, const gbl::DeltaArgs& da, int64_t b0, int64_t nb) {
+    int rc[kNumWidths];
+    const int slot = width_slot(N);
+    launch_route_pass<N>(ctx, da, b0, host_counts(ctx, ctx->route_counts, kNumWidths, rc) ? rc[slot] : nb);
+  }
+};
 
 template <int N>
 struct LaunchDelta {
@@ -264,7 +302,7 @@ struct LaunchDelta {
       hipLaunchKernelGGL(gbl::k_bucket_reset, dim3(1), dim3(64), 0, ctx->stream, ctx->route_counts, kNumWidths);
       hipLaunchKernelGGL((gbl::k_delta_loglike<N, float>), dim3((unsigned)nb), dim3(gbl::delta_threads<N>()), 0,
                          ctx->stream, ctx->geo, tables_for<N, float>(ctx), with_route(ctx, da, N, b0), b0);
-      launch_route_pass<N>(ctx, da, b0, nb);
+      LaunchRoutePass<N>::run(ctx, da, b0, nb);
     } else if (ctx->cfg.precision == GBL_MIXED)
       hipLaunchKernelGGL((gbl::k_delta_loglike<N, float>), dim3((unsigned)nb), dim3(gbl::delta_threads<N>()), 0,
                          ctx->stream, ctx->geo, tables_for<N, float>(ctx), da, b0);
@@ -274,29 +312,34 @@ struct LaunchDelta {
   }
 };
 
+// one width's bucket; grid = the bucket's size when known on the host, else
+// its upper bound (the routed pairs are re-evaluated after all widths)
 template <int N>
 struct LaunchDeltaBucket {
-  static void run(gbl_ctx* ctx, const gbl::DeltaArgs& da, int64_t b0, int64_t nb) {
+  static void run(gbl_ctx* ctx, const gbl::DeltaArgs& da, int64_t b0, int64_t grid) {
+    if (grid <= 0) return;
     const int slot = width_slot(N);
     const int* cnt = ctx->counts + slot;
     const int32_t* perm = ctx->perm + (int64_t)slot * kBucketCap;
-    if (routed(ctx)) {
-      hipLaunchKernelGGL((gbl::k_delta_loglike_bucket<N, float>), dim3((unsigned)nb), dim3(gbl::delta_threads<N>()),
-                         0, ctx->stream, ctx->geo, tables_for<N, float>(ctx), with_route(ctx, da, N, b0), b0, cnt,
-                         perm);
-      launch_route_pass<N>(ctx, da, b0, nb);
-    } else if (ctx->cfg.precision == GBL_MIXED)
-      hipLaunchKernelGGL((gbl::k_delta_loglike_bucket<N, float>), dim3((unsigned)nb), dim3(gbl::delta_threads<N>()),
-                         0, ctx->stream, ctx->geo, tables_for<N, float>(ctx), da, b0, cnt, perm);
+    if (routed(ctx))
+      hipLaunchKernelGGL((gbl::k_delta_loglike_bucket<N, float>), dim3((unsigned)grid),
+                         dim3(gbl::delta_threads<N>()), 0, ctx->stream, ctx->geo, tables_for<N, float>(ctx),
+                         with_route(ctx, da, N, b0), b0, cnt, perm);
+    else if (ctx->cfg.precision == GBL_MIXED)
+      hipLaunchKernelGGL((gbl::k_delta_loglike_bucket<N, float>), dim3((unsigned)grid),
+                         dim3(gbl::delta_threads<N>()), 0, ctx->stream, ctx->geo, tables_for<N, float>(ctx), da, b0,
+                         cnt, perm);
     else
-      hipLaunchKernelGGL((gbl::k_delta_loglike_bucket<N, double>), dim3((unsigned)nb), dim3(gbl::delta_threads<N>()),
-                         0, ctx->stream, ctx->geo, tables_for<N, double>(ctx), da, b0, cnt, perm);
+      hipLaunchKernelGGL((gbl::k_delta_loglike_bucket<N, double>), dim3((unsigned)grid),
+                         dim3(gbl::delta_threads<N>()), 0, ctx->stream, ctx->geo, tables_for<N, double>(ctx), da,
+                         b0, cnt, perm);
   }
 };
 
 template <int N, typename F>
 static void launch_waveform_bucket(gbl_ctx* ctx, const double* params, int64_t b0, int64_t nb, const int64_t* off,
                                    cd* A, cd* E, cd* Tc, int64_t* sb) {
+  if (nb <= 0) return;
   const int slot = width_slot(N);
   const int* cnt = ctx->counts + slot;
   const int32_t* perm = ctx->perm + (int64_t)slot * kBucketCap;
@@ -397,19 +440,30 @@ extern "C" int gb_delta_loglike_var(gbl_ctx* ctx, const double* residual, int32_
   for (int64_t b0 = 0; b0 < B; b0 += chunk) {
     int64_t nb = B - b0 < chunk ? B - b0 : chunk;
     bucket_widths(ctx, N, b0, nb, dlogl, nullptr);
+    int cnt[kNumWidths];
+    if (!host_counts(ctx, ctx->counts, kNumWidths, cnt))
+      for (int w = 0; w < kNumWidths; w++) cnt[w] = (int)nb;
     if (routed(ctx))
       hipLaunchKernelGGL(gbl::k_bucket_reset, dim3(1), dim3(64), 0, ctx->stream, ctx->route_counts, kNumWidths);
     // widest first (default): the long blocks start early and the short ones fill in
     if (ctx->tune.widest_first) {
-      LaunchDeltaBucket<1024>::run(ctx, da, b0, nb);
-      LaunchDeltaBucket<512>::run(ctx, da, b0, nb);
-      LaunchDeltaBucket<256>::run(ctx, da, b0, nb);
-      LaunchDeltaBucket<128>::run(ctx, da, b0, nb);
+      LaunchDeltaBucket<1024>::run(ctx, da, b0, cnt[3]);
+      LaunchDeltaBucket<512>::run(ctx, da, b0, cnt[2]);
+      LaunchDeltaBucket<256>::run(ctx, da, b0, cnt[1]);
+      LaunchDeltaBucket<128>::run(ctx, da, b0, cnt[0]);
     } else {
-      LaunchDeltaBucket<128>::run(ctx, da, b0, nb);
-      LaunchDeltaBucket<256>::run(ctx, da, b0, nb);
-      LaunchDeltaBucket<512>::run(ctx, da, b0, nb);
-      LaunchDeltaBucket<1024>::run(ctx, da, b0, nb);
+      LaunchDeltaBucket<128>::run(ctx, da, b0, cnt[0]);
+      LaunchDeltaBucket<256>::run(ctx, da, b0, cnt[1]);
+      LaunchDeltaBucket<512>::run(ctx, da, b0, cnt[2]);
+      LaunchDeltaBucket<1024>::run(ctx, da, b0, cnt[3]);
+    }
+    if (routed(ctx)) {
+      int rc[kNumWidths];
+      const bool exact = host_counts(ctx, ctx->route_counts, kNumWidths, rc);
+      launch_route_pass<1024>(ctx, da, b0, exact ? rc[3] : cnt[3]);
+      launch_route_pass<512>(ctx, da, b0, exact ? rc[2] : cnt[2]);
+      launch_route_pass<256>(ctx, da, b0, exact ? rc[1] : cnt[1]);
+      launch_route_pass<128>(ctx, da, b0, exact ? rc[0] : cnt[0]);
     }
   }
   return check_launch(ctx, "gb_delta_loglike_var");
@@ -426,10 +480,13 @@ extern "C" int gb_waveform_var(gbl_ctx* ctx, const double* params, const int32_t
   for (int64_t b0 = 0; b0 < B; b0 += chunk) {
     int64_t nb = B - b0 < chunk ? B - b0 : chunk;
     bucket_widths(ctx, N, b0, nb, nullptr, start_bin);
-    LaunchWaveformBucket<1024>::run(ctx, params, b0, nb, out_offset, (cd*)A, (cd*)E, (cd*)Tch, start_bin);
-    LaunchWaveformBucket<512>::run(ctx, params, b0, nb, out_offset, (cd*)A, (cd*)E, (cd*)Tch, start_bin);
-    LaunchWaveformBucket<256>::run(ctx, params, b0, nb, out_offset, (cd*)A, (cd*)E, (cd*)Tch, start_bin);
-    LaunchWaveformBucket<128>::run(ctx, params, b0, nb, out_offset, (cd*)A, (cd*)E, (cd*)Tch, start_bin);
+    int cnt[kNumWidths];
+    if (!host_counts(ctx, ctx->counts, kNumWidths, cnt))
+      for (int w = 0; w < kNumWidths; w++) cnt[w] = (int)nb;
+    LaunchWaveformBucket<1024>::run(ctx, params, b0, cnt[3], out_offset, (cd*)A, (cd*)E, (cd*)Tch, start_bin);
+    LaunchWaveformBucket<512>::run(ctx, params, b0, cnt[2], out_offset, (cd*)A, (cd*)E, (cd*)Tch, start_bin);
+    LaunchWaveformBucket<256>::run(ctx, params, b0, cnt[1], out_offset, (cd*)A, (cd*)E, (cd*)Tch, start_bin);
+    LaunchWaveformBucket<128>::run(ctx, params, b0, cnt[0], out_offset, (cd*)A, (cd*)E, (cd*)Tch, start_bin);
   }
   return check_launch(ctx, "gb_waveform_var");
 }
@@ -906,7 +963,8 @@ extern "C" int gbl_set_tuning(gbl_ctx* ctx, const gbl_tuning* t) {
   if (!t) return fail(ctx, GBL_EINVAL, "gbl_set_tuning: null tuning%s");
   const bool pow2 = t->bucket_chunk > 0 && (t->bucket_chunk & (t->bucket_chunk - 1)) == 0;
   if (t->flow_grid < 64 || t->flow_grid > 65536 || !pow2 ||
-      t->bucket_chunk < 4096 || t->bucket_chunk > kBucketCap || (t->widest_first != 0 && t->widest_first != 1))
+      t->bucket_chunk < 4096 || t->bucket_chunk > kBucketCap || (t->widest_first != 0 && t->widest_first != 1) ||
+      (t->exact_grids != 0 && t->exact_grids != 1))
     return fail(ctx, GBL_EINVAL, "gbl_set_tuning: knob out of range%s");
   ctx->tune = *t;
   return GBL_OK;

@@ -159,19 +159,27 @@ struct DeltaArgs {
   int64_t route_b0;
 };
 
+// Wide templates (N >= 512) keep the old template's spectrum in registers
+// and hand it over through the FFT buffer once the new template's bins are
+// taken, instead of holding it in an LDS array of its own: 64 instead of
+// 96 KB at N = 1024, so that two blocks share a CU and one block's barriers
+// are filled by the other's work.
+template <int N>
+constexpr bool delta_rwin_in_buf() {
+  return N >= 512;
+}
+
 // threads per block of the fused likelihood kernels: one per sample and bin
-// at every width.  The LDS a block needs grows with N (96 KB at N = 1024), so
-// wide templates fit one or a few blocks per CU; a block of N threads keeps
-// four waves on every SIMD all the same.
+// up to N = 256, two per thread above (8 waves at N = 1024, two blocks per CU)
 template <int N>
 constexpr int delta_threads() {
-  return N;
+  return N <= 256 ? N : N / 2;
 }
 
 template <int N, typename F>
 struct DeltaSmem {
   cx<F> buf[4 * series_pitch<N>()];
-  cx<F> rwin[2 * N];
+  cx<F> rwin[delta_rwin_in_buf<N>() ? 1 : 2 * N];
   double red[6 * (delta_threads<N>() / kWave)];
   Src src[2];  // 0: old, 1: new
 };
@@ -208,18 +216,44 @@ __device__ __forceinline__ void delta_one(const Geo& g, const WaveTables<F>& tb,
 
   __syncthreads();
 
-  // old template into the LDS window
+  // old template r: its spectrum over its window, in LDS (rw) or, for the
+  // wide templates, in registers until the new template's bins are taken
+  constexpr bool kRegR = delta_rwin_in_buf<N>();
+  cx<F> rr[BPT][2];
+  cx<F> aa[BPT][2];
+  cx<F>* rw = kRegR ? sm.buf : sm.rwin;
   if (ho.state == 0) {
     const Src& so = sm.src[0];
     template_transform<N, 4, F, NT>(so, g, tb, sm.buf, tid);
-    for (int j = tid; j < N; j += NT) {
-      cx<F> v[2];
-      bin_spectrum<N, 2, F>(so, g, tb, sm.buf, j, v);
-      sm.rwin[j] = v[0];
-      sm.rwin[N + j] = v[1];
+#pragma unroll
+    for (int m = 0; m < BPT; m++) {
+      const int j = tid + NT * m;
+      bin_spectrum<N, 2, F>(so, g, tb, sm.buf, j, rr[m]);
+      if constexpr (!kRegR) {
+        sm.rwin[j] = rr[m][0];
+        sm.rwin[N + j] = rr[m][1];
+      }
     }
   }
   __syncthreads();
+  if constexpr (kRegR) {
+    // new template a: bins into registers, then r's spectrum into the buffer
+    if (hn.state == 0) {
+      const Src& sn = sm.src[1];
+      template_transform<N, 4, F, NT>(sn, g, tb, sm.buf, tid);
+#pragma unroll
+      for (int m = 0; m < BPT; m++) bin_spectrum<N, 2, F>(sn, g, tb, sm.buf, tid + NT * m, aa[m]);
+    }
+    __syncthreads();
+    if (ho.state == 0) {
+#pragma unroll
+      for (int m = 0; m < BPT; m++) {
+        rw[tid + NT * m] = rr[m][0];
+        rw[N + tid + NT * m] = rr[m][1];
+      }
+    }
+    __syncthreads();
+  }
 
   double acc_rd = 0.0, acc_dd = 0.0;
   auto accumulate = [&](cd R0, cd R1, double w0, double w1, cd d0, cd d1) {
@@ -245,12 +279,12 @@ __device__ __forceinline__ void delta_one(const Geo& g, const WaveTables<F>& tb,
 
   if (hn.state == 0) {
     const Src& sn = sm.src[1];
-    template_transform<N, 4, F, NT>(sn, g, tb, sm.buf, tid);
+    if constexpr (!kRegR) template_transform<N, 4, F, NT>(sn, g, tb, sm.buf, tid);
     // a's window, one bin per iteration: residual and weights are loaded at
     // the top of the iteration (not earlier: at four waves per SIMD the other
     // waves hide the latency, and no registers stay occupied across the
     // template builds or across the bins of the wider templates)
-#pragma unroll 1
+#pragma unroll
     for (int m = 0; m < BPT; m++) {
       const int j = tid + NT * m;
       int64_t k = ka + j;
@@ -259,7 +293,12 @@ __device__ __forceinline__ void delta_one(const Geo& g, const WaveTables<F>& tb,
       const cd R0 = RA[idx], R1 = RE[idx];
       const double W0 = weight(SA, idx), W1 = weight(SE, idx);
       cx<F> v[2];
-      bin_spectrum<N, 2, F>(sn, g, tb, sm.buf, j, v);
+      if constexpr (kRegR) {
+        v[0] = aa[m][0];
+        v[1] = aa[m][1];
+      } else {
+        bin_spectrum<N, 2, F>(sn, g, tb, sm.buf, j, v);
+      }
       cd a0 = cvt<double>(v[0]);
       cd a1 = cvt<double>(v[1]);
       int64_t jr = k - kr;
@@ -267,25 +306,26 @@ __device__ __forceinline__ void delta_one(const Geo& g, const WaveTables<F>& tb,
       if constexpr (kEst) {
         if (da.route_list) {
           magnitude(R0, R1, W0, W1, a0, a1, true);
-          if (has_r)
-            magnitude(R0, R1, W0, W1, cvt<double>(sm.rwin[jr]), cvt<double>(sm.rwin[N + jr]), false);
+          if (has_r) magnitude(R0, R1, W0, W1, cvt<double>(rw[jr]), cvt<double>(rw[N + jr]), false);
         }
       }
       if (has_r) {
-        a0 = a0 - cvt<double>(sm.rwin[jr]);
-        a1 = a1 - cvt<double>(sm.rwin[N + jr]);
+        a0 = a0 - cvt<double>(rw[jr]);
+        a1 = a1 - cvt<double>(rw[N + jr]);
       }
       accumulate(R0, R1, W0, W1, a0, a1);
     }
   }
   if (ho.state == 0) {
     // bins of r's window not already covered by a's window
-    for (int j = tid; j < N; j += NT) {
+#pragma unroll
+    for (int m = 0; m < BPT; m++) {
+      const int j = tid + NT * m;
       int64_t k = kr + j;
       if (hn.state == 0 && k >= ka && k < ka + N) continue;
       if (k < g.k_min || k >= g.k_min + nb) continue;
       int64_t idx = k - g.k_min;
-      cd r0 = cvt<double>(sm.rwin[j]), r1 = cvt<double>(sm.rwin[N + j]);
+      cd r0 = cvt<double>(kRegR ? rr[m][0] : sm.rwin[j]), r1 = cvt<double>(kRegR ? rr[m][1] : sm.rwin[N + j]);
       const cd R0 = RA[idx], R1 = RE[idx];
       const double w0 = weight(SA, idx), w1 = weight(SE, idx);
       if constexpr (kEst) {

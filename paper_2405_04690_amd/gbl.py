@@ -66,7 +66,8 @@ class SweepState(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     """gbl_tuning: launch-shape knobs of a context"""
-    _fields_ = [("flow_grid", ctypes.c_int32), ("bucket_chunk", ctypes.c_int32), ("widest_first", ctypes.c_int32)]
+    _fields_ = [("flow_grid", ctypes.c_int32), ("bucket_chunk", ctypes.c_int32), ("widest_first", ctypes.c_int32),
+                ("exact_grids", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

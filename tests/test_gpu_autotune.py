@@ -32,7 +32,8 @@ def test_results_do_not_depend_on_the_knobs(precision):
     ctx = Context(T=cfg.T, dt=cfg.dt, L=cfg.L, f_lo=cfg.f_lo, f_hi=cfg.f_hi, precision=precision)
     R, S, old, new, w = _problem(ctx)
     ref = ctx.gb_delta_loglike_var(R, S, old, new, w).cpu().numpy()
-    for knobs in ({"bucket_chunk": 4096, "widest_first": 0}, {"bucket_chunk": 1 << 16, "widest_first": 1}):
+    for knobs in ({"bucket_chunk": 4096, "widest_first": 0}, {"bucket_chunk": 1 << 16, "widest_first": 1},
+                  {"exact_grids": 0}, {"exact_grids": 1, "bucket_chunk": 1 << 20}):
         ctx.set_tuning(**knobs)
         got = ctx.gb_delta_loglike_var(R, S, old, new, w).cpu().numpy()
         assert np.array_equal(got, ref, equal_nan=True)
@@ -47,7 +48,32 @@ def test_out_of_range_knobs_are_rejected():
     cfg = inputs.TINY
     ctx = Context(T=cfg.T, dt=cfg.dt, L=cfg.L, f_lo=cfg.f_lo, f_hi=cfg.f_hi)
     for bad in ({"bucket_chunk": 5000}, {"bucket_chunk": 1 << 21}, {"flow_grid": 1}, {"flow_grid": 10 ** 6},
-                {"widest_first": 2}):
+                {"widest_first": 2}, {"exact_grids": 2}):
         with pytest.raises(GblError):
             ctx.set_tuning(**bad)
     ctx.close()
+
+
+@pytest.mark.parametrize("precision", [0, GBL_MIXED])
+def test_uneven_widths_under_capture_match_eager(precision):
+    """Captured, the bucketed call cannot read its bucket sizes back and runs
+    upper-bound grids; three replays (with eager work in between) give the
+    eager, exactly-sized result bit for bit."""
+    cfg = inputs.TINY
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        ctx = Context(T=cfg.T, dt=cfg.dt, L=cfg.L, f_lo=cfg.f_lo, f_hi=cfg.f_hi, precision=precision,
+                      stream=stream)
+        R, S, old, new, w = _problem(ctx, seed=710)
+        ref = ctx.gb_delta_loglike_var(R, S, old, new, w).clone()
+        out = torch.full_like(ref, 7.0)
+        ctx.graph_begin()
+        ctx.gb_delta_loglike_var(R, S, old, new, w, out=out)
+        g = ctx.graph_end()
+        for _ in range(3):
+            out.fill_(7.0)
+            g.launch()
+            stream.synchronize()
+            assert torch.equal(torch.nan_to_num(out, nan=-1.0), torch.nan_to_num(ref, nan=-1.0))
+        g.destroy()
+        ctx.close()
