@@ -474,7 +474,7 @@ def main():
     achieved = flops_l / (per_launch_ms / 1e3) / 1e12
     roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
             "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": measured_traffic(),
-            "kernel": "k_delta_loglike<256>", "avg_launch_ms": round(per_launch_ms, 4),
+            "kernel": "k_decode_pairs + k_delta_loglike<256>", "avg_launch_ms": round(per_launch_ms, 4),
             "algorithmic_gbs": round(bytes_l / (per_launch_ms / 1e3) / 1e9, 1),
             "algorithmic_hbm_frac": round(bytes_l / (per_launch_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
     cpu = None

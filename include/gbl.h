@@ -17,7 +17,9 @@
  *   Pointers   All array arguments are DEVICE pointers owned by the caller
  *              (e.g. PyTorch allocations on the same GPU).  The library
  *              allocates device memory only inside gbl_create (constant tables,
- *              PSD basis, reduction workspace) and frees it in gbl_destroy.
+ *              PSD basis, reduction workspace, and a 111 MB workspace for the
+ *              decoded sources of up to 2^17 likelihood pairs, through which
+ *              longer batches pass in chunks) and frees it in gbl_destroy.
  *   Streams    Compute calls only enqueue work on the context's stream and
  *              return; outputs are valid once the caller synchronises that
  *              stream.  Compute calls never allocate or print, and they do not
@@ -119,7 +121,8 @@ int gbl_band(const gbl_ctx* ctx, int64_t* k_min, int64_t* n_bins);
  *                 (default 4096);
  *   bucket_chunk  templates per bucketed launch group (uneven widths; the FP64
  *                 re-evaluation of mixed-precision pairs), a
- *                 power of two in [4096, 1048576] (default 1048576);
+ *                 power of two in [4096, 1048576] (default 1048576); likelihood
+ *                 calls use at most 2^17 pairs per group (the decode workspace);
  *   widest_first  uneven widths: launch the widest bucket first (1) or last (0);
  *   exact_grids   1 (default): when the context's stream is not being captured,
  *                 gb_waveform_var, gb_delta_loglike_var and the FP64

@@ -21,6 +21,7 @@ namespace {
 constexpr int kNumWidths = gbl::kBucketWidths;
 constexpr int kWidths[kNumWidths] = {128, 256, 512, 1024};
 constexpr int64_t kMaxGrid = (int64_t)1 << 30;  // blocks per launch (grid.x limit is 2^31 - 1)
+constexpr int64_t kDecodeChunk = (int64_t)1 << 17; // pairs per decode pass (workspace 2^18 decoded sources, 111 MB)
 constexpr int64_t kPsdBatch = 4096;             // parameter sets per PSD-likelihood launch pair
 constexpr int kBucketCap = 1 << 20;             // templates per bucketed (uneven-width) launch group
 
@@ -48,6 +49,7 @@ struct gbl_ctx {
   int* route_counts;      // [4 widths] mixed-precision pairs queued for the FP64 pass
   int32_t* route_lists;   // [4 widths][kBucketCap]
   int* host_counts;       // pinned [8]: device-side counts read back for exact grids
+  gbl::Src* src_ws;       // [2 kDecodeChunk] decoded sources of one chunk of pairs
   std::string err;
 };
 
@@ -102,6 +104,7 @@ static void release(gbl_ctx* ctx) {
   if (ctx->route_counts) (void)hipFree(ctx->route_counts);
   if (ctx->route_lists) (void)hipFree(ctx->route_lists);
   if (ctx->host_counts) (void)hipHostFree(ctx->host_counts);
+  if (ctx->src_ws) (void)hipFree(ctx->src_ws);
 }
 
 extern "C" int gbl_create(gbl_ctx** out, const gbl_config* cfg, void* hip_stream) {
@@ -163,7 +166,8 @@ extern "C" int gbl_create(gbl_ctx** out, const gbl_config* cfg, void* hip_stream
       hipMalloc(&ctx->perm, sizeof(int32_t) * (size_t)kNumWidths * kBucketCap) != hipSuccess ||
       hipMalloc(&ctx->route_counts, sizeof(int) * kNumWidths) != hipSuccess ||
       hipMalloc(&ctx->route_lists, sizeof(int32_t) * (size_t)kNumWidths * kBucketCap) != hipSuccess ||
-      hipHostMalloc((void**)&ctx->host_counts, sizeof(int) * 8, hipHostMallocDefault) != hipSuccess) {
+      hipHostMalloc((void**)&ctx->host_counts, sizeof(int) * 8, hipHostMallocDefault) != hipSuccess ||
+      hipMalloc(&ctx->src_ws, sizeof(gbl::Src) * 2 * kDecodeChunk) != hipSuccess) {
     release(ctx);
     delete ctx;
     return GBL_EHIP;
@@ -402,6 +406,16 @@ extern "C" int gb_waveform(gbl_ctx* ctx, const double* params, int64_t B, int32_
   return check_launch(ctx, "gb_waveform");
 }
 
+// decode pass of pairs [b0, b0 + nb) (nb <= kDecodeChunk) into the context's
+// workspace; returns the arguments that point the fused kernels at it
+static gbl::DeltaArgs decode_pairs(gbl_ctx* ctx, gbl::DeltaArgs da, int64_t b0, int64_t nb) {
+  hipLaunchKernelGGL(gbl::k_decode_pairs, dim3((unsigned)((2 * nb + 255) / 256)), dim3(256), 0, ctx->stream,
+                     ctx->geo, da.p_old, da.p_new, b0, nb, ctx->src_ws);
+  da.srcs = ctx->src_ws;
+  da.src_b0 = b0;
+  return da;
+}
+
 extern "C" int gb_delta_loglike(gbl_ctx* ctx, const double* residual, int32_t n_res, const double* psd,
                                 int32_t n_psd, int32_t psd_flags, const double* params_old, const double* params_new,
                                 int32_t N, const int32_t* res_idx, const int32_t* psd_idx, int64_t B, double* dlogl) {
@@ -414,11 +428,11 @@ extern "C" int gb_delta_loglike(gbl_ctx* ctx, const double* residual, int32_t n_
     return fail(ctx, GBL_EINVAL, "gb_delta_loglike: null pointer%s");
   const gbl::DeltaArgs da = {(const cd*)residual, (int)n_res, psd, (int)n_psd,
                              (psd_flags & GBL_PSD_INVERSE) ? 1 : 0, params_old, params_new, res_idx, psd_idx, dlogl,
-                             nullptr, nullptr, 0.0, 0};
-  const int64_t chunk = routed(ctx) ? (int64_t)ctx->tune.bucket_chunk : kMaxGrid;
+                             nullptr, nullptr, 0.0, 0, nullptr, 0};
+  const int64_t chunk = std::min<int64_t>(routed(ctx) ? (int64_t)ctx->tune.bucket_chunk : kMaxGrid, kDecodeChunk);
   for (int64_t b0 = 0; b0 < B; b0 += chunk) {
     int64_t nb = B - b0 < chunk ? B - b0 : chunk;
-    dispatch_width<LaunchDelta>(N, ctx, da, b0, nb);
+    dispatch_width<LaunchDelta>(N, ctx, decode_pairs(ctx, da, b0, nb), b0, nb);
   }
   return check_launch(ctx, "gb_delta_loglike");
 }
@@ -433,12 +447,13 @@ extern "C" int gb_delta_loglike_var(gbl_ctx* ctx, const double* residual, int32_
   if (B == 0) return GBL_OK;
   if (!residual || !psd || !params_old || !params_new || !N || !res_idx || !psd_idx || !dlogl)
     return fail(ctx, GBL_EINVAL, "gb_delta_loglike_var: null pointer%s");
-  const gbl::DeltaArgs da = {(const cd*)residual, (int)n_res, psd, (int)n_psd,
+  const gbl::DeltaArgs da_all = {(const cd*)residual, (int)n_res, psd, (int)n_psd,
                              (psd_flags & GBL_PSD_INVERSE) ? 1 : 0, params_old, params_new, res_idx, psd_idx, dlogl,
-                             nullptr, nullptr, 0.0, 0};
-  const int64_t chunk = ctx->tune.bucket_chunk;
+                             nullptr, nullptr, 0.0, 0, nullptr, 0};
+  const int64_t chunk = std::min<int64_t>(ctx->tune.bucket_chunk, kDecodeChunk);
   for (int64_t b0 = 0; b0 < B; b0 += chunk) {
     int64_t nb = B - b0 < chunk ? B - b0 : chunk;
+    const gbl::DeltaArgs dc = decode_pairs(ctx, da_all, b0, nb);
     bucket_widths(ctx, N, b0, nb, dlogl, nullptr);
     int cnt[kNumWidths];
     if (!host_counts(ctx, ctx->counts, kNumWidths, cnt))
@@ -447,23 +462,23 @@ extern "C" int gb_delta_loglike_var(gbl_ctx* ctx, const double* residual, int32_
       hipLaunchKernelGGL(gbl::k_bucket_reset, dim3(1), dim3(64), 0, ctx->stream, ctx->route_counts, kNumWidths);
     // widest first (default): the long blocks start early and the short ones fill in
     if (ctx->tune.widest_first) {
-      LaunchDeltaBucket<1024>::run(ctx, da, b0, cnt[3]);
-      LaunchDeltaBucket<512>::run(ctx, da, b0, cnt[2]);
-      LaunchDeltaBucket<256>::run(ctx, da, b0, cnt[1]);
-      LaunchDeltaBucket<128>::run(ctx, da, b0, cnt[0]);
+      LaunchDeltaBucket<1024>::run(ctx, dc, b0, cnt[3]);
+      LaunchDeltaBucket<512>::run(ctx, dc, b0, cnt[2]);
+      LaunchDeltaBucket<256>::run(ctx, dc, b0, cnt[1]);
+      LaunchDeltaBucket<128>::run(ctx, dc, b0, cnt[0]);
     } else {
-      LaunchDeltaBucket<128>::run(ctx, da, b0, cnt[0]);
-      LaunchDeltaBucket<256>::run(ctx, da, b0, cnt[1]);
-      LaunchDeltaBucket<512>::run(ctx, da, b0, cnt[2]);
-      LaunchDeltaBucket<1024>::run(ctx, da, b0, cnt[3]);
+      LaunchDeltaBucket<128>::run(ctx, dc, b0, cnt[0]);
+      LaunchDeltaBucket<256>::run(ctx, dc, b0, cnt[1]);
+      LaunchDeltaBucket<512>::run(ctx, dc, b0, cnt[2]);
+      LaunchDeltaBucket<1024>::run(ctx, dc, b0, cnt[3]);
     }
     if (routed(ctx)) {
       int rc[kNumWidths];
       const bool exact = host_counts(ctx, ctx->route_counts, kNumWidths, rc);
-      launch_route_pass<1024>(ctx, da, b0, exact ? rc[3] : cnt[3]);
-      launch_route_pass<512>(ctx, da, b0, exact ? rc[2] : cnt[2]);
-      launch_route_pass<256>(ctx, da, b0, exact ? rc[1] : cnt[1]);
-      launch_route_pass<128>(ctx, da, b0, exact ? rc[0] : cnt[0]);
+      launch_route_pass<1024>(ctx, dc, b0, exact ? rc[3] : cnt[3]);
+      launch_route_pass<512>(ctx, dc, b0, exact ? rc[2] : cnt[2]);
+      launch_route_pass<256>(ctx, dc, b0, exact ? rc[1] : cnt[1]);
+      launch_route_pass<128>(ctx, dc, b0, exact ? rc[0] : cnt[0]);
     }
   }
   return check_launch(ctx, "gb_delta_loglike_var");

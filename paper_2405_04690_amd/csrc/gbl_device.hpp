@@ -71,6 +71,12 @@ template <typename F, typename G>
 __device__ __forceinline__ cx<F> cvt(cx<G> a) {
   return {(F)a.re, (F)a.im};
 }
+// a complex value of a decoded source read field by field (the source may sit
+// in the constant address space, which the copy constructor cannot bind)
+template <typename F, typename C>
+__device__ __forceinline__ cx<F> load_cx(const C& c) {
+  return {(F)c.re, (F)c.im};
+}
 
 // Configuration-wide constants handed to every kernel by value.
 struct Geo {
@@ -168,46 +174,28 @@ __device__ __forceinline__ SrcHead source_head(const double* __restrict__ prm, c
   return h;
 }
 
-// Full decode of NSRC (1 or 2) sources by one whole wave (every lane must
-// take part) into LDS, spread over the lanes so that the wave issues about one
-// trigonometric evaluation and one group of coefficients instead of all of
-// them.  Lanes 32 t + a of source t:
-//   a = 0..3  sin/cos of lambda, beta, iota, 2 psi (then shared by shuffles)
-//   a = 0..2  k.x_r/c coefficients of receiver r = a
-//   a = 3..8  arm m = (a-3)/3 projection coefficients of k, q or p
-//   a = 9     carrier bin, phases, polarisation amplitudes, delay factor, state
-template <int NSRC>
-__device__ __forceinline__ void decode_sources(const double* __restrict__ p0, const double* __restrict__ p1,
-                                               const Geo& g, Src* out) {
-  const int lane = (int)(threadIdx.x & (kWave - 1));
-  const int t = (lane >> 5) < NSRC ? (lane >> 5) : 0;
-  const int role = lane & 31;
-  const bool writer = (lane >> 5) < NSRC;
-  const double* prm = t ? p1 : p0;
-  double sv = 0.0, cv = 1.0;
-  {
-    const int a = role & 3;
-    const double ang = a == 0 ? prm[6] : a == 1 ? prm[7] : a == 2 ? prm[4] : 2.0 * prm[5];
-    if (role < 4) sincos(ang, &sv, &cv);
-  }
-  const int l0 = t << 5;
-  const double sl = __shfl(sv, l0 + 0), cl = __shfl(cv, l0 + 0);
-  const double sb = __shfl(sv, l0 + 1), cb = __shfl(cv, l0 + 1);
-  const double ci = __shfl(cv, l0 + 2);
-  const double s2p = __shfl(sv, l0 + 3), c2p = __shfl(cv, l0 + 3);
-  if (!writer) return;
-  Src& s = out[t];
+// Source decode from the parameters (A, f0, fdot, phi0, iota, psi, lambda,
+// beta) and the sines and cosines of lambda, beta, iota and 2 psi, in three
+// groups of outputs: a = 0..2 the k.x_r/c coefficients of receiver r = a,
+// a = 3..8 the arm m = (a-3)/3 projection coefficients of k, q or p, a = 9
+// carrier bin, phases, polarisation amplitudes, delay factor and state.
+struct SrcTrig {
+  double sl, cl, sb, cb, ci, s2p, c2p;
+};
+
+__device__ __forceinline__ void decode_group(int a, const double* __restrict__ prm, const SrcTrig& tr,
+                                             const Geo& g, Src& s) {
   // propagation direction k = -(sky direction) and polarisation basis p, q
-  const double kh[3] = {-cb * cl, -cb * sl, -sb};
-  const double pv[2] = {sl, -cl};
-  const double qv[3] = {-sb * cl, -sb * sl, cb};
+  const double kh[3] = {-tr.cb * tr.cl, -tr.cb * tr.sl, -tr.sb};
+  const double pv[2] = {tr.sl, -tr.cl};
+  const double qv[3] = {-tr.sb * tr.cl, -tr.sb * tr.sl, tr.cb};
   constexpr double cbs[3] = {1.0, -0.5, -0.5};
   constexpr double sbs[3] = {0.0, 0.86602540378443864676, -0.86602540378443864676};
-  if (role < 3) {
+  if (a < 3) {
     // craft r at orientation 2 pi r/3 (cos/sin br):
     //   x_r = AU (cos a, sin a, 0) + eh (cos 2a cbr + sin 2a sbr - 3 cbr,
     //         sin 2a cbr - cos 2a sbr - 3 sbr, 0) - ez (0, 0, cos a cbr + sin a sbr)
-    const int r = role;
+    const int r = a;
     const double cbr = r == 0 ? cbs[0] : r == 1 ? cbs[1] : cbs[2];
     const double sbr = r == 0 ? sbs[0] : r == 1 ? sbs[1] : sbs[2];
     const double kc[3] = {kh[0] / kC, kh[1] / kC, kh[2] / kC};
@@ -217,9 +205,9 @@ __device__ __forceinline__ void decode_sources(const double* __restrict__ p0, co
     c[2] = g.eh * (kc[0] * cbr - kc[1] * sbr);
     c[3] = g.eh * (kc[0] * sbr + kc[1] * cbr);
     c[4] = -3.0 * g.eh * (kc[0] * cbr + kc[1] * sbr);
-  } else if (role < 9) {
+  } else if (a < 9) {
     // arm m = craft m -> m+1: n_m = (x_{m+1} - x_m) / L; projection of v = k, q or p
-    const int m = (role - 3) / 3, w = (role - 3) % 3;
+    const int m = (a - 3) / 3, w = (a - 3) % 3;
     const double dcb = m == 0 ? cbs[1] - cbs[0] : cbs[2] - cbs[1];
     const double dsb = m == 0 ? sbs[1] - sbs[0] : sbs[2] - sbs[1];
     const double v0 = w == 0 ? kh[0] : w == 1 ? qv[0] : pv[0];
@@ -241,7 +229,7 @@ __device__ __forceinline__ void decode_sources(const double* __restrict__ p0, co
       c[3] = c3;
       c[4] = c4;
     }
-  } else if (role == 9) {
+  } else if (a == 9) {
     double A = prm[0], f0 = prm[1], fdot = prm[2], phi0 = prm[3];
     bool finite = isfinite(A) && isfinite(f0) && isfinite(fdot) && isfinite(phi0) && isfinite(prm[4]) &&
                   isfinite(prm[5]) && isfinite(prm[6]) && isfinite(prm[7]) && fabs(f0 * g.T) < 4503599627370496.0;
@@ -253,12 +241,56 @@ __device__ __forceinline__ void decode_sources(const double* __restrict__ p0, co
     const double qd = floor(f0 * g.T);
     s.q = (int64_t)qd;
     s.dfq = f0 - qd / g.T;
-    const double ap = A * (1.0 + ci * ci);
-    const double ax = 2.0 * A * ci;
-    s.cp = {ap * c2p, -ax * s2p};
-    s.cx2 = {2.0 * ap * s2p, 2.0 * ax * c2p};
+    const double ap = A * (1.0 + tr.ci * tr.ci);
+    const double ax = 2.0 * A * tr.ci;
+    s.cp = {ap * tr.c2p, -ax * tr.s2p};
+    s.cx2 = {2.0 * ap * tr.s2p, 2.0 * ax * tr.c2p};
     s.dq = expi_cycles(-(double)s.q * (g.Lc / g.T));
   }
+}
+
+// the angle whose sine and cosine slot a = 0..3 of SrcTrig needs
+__device__ __forceinline__ double decode_angle(int a, const double* __restrict__ prm) {
+  return a == 0 ? prm[6] : a == 1 ? prm[7] : a == 2 ? prm[4] : 2.0 * prm[5];
+}
+
+// Full decode of NSRC (1 or 2) sources by one whole wave (every lane must
+// take part) into LDS, spread over the lanes so that the wave issues about one
+// trigonometric evaluation and one group of outputs instead of all of them:
+// lanes 32 t + a of source t evaluate the sine and cosine of angle a = 0..3
+// (then shared by shuffles) and write output group a = 0..9.
+template <int NSRC>
+__device__ __forceinline__ void decode_sources(const double* __restrict__ p0, const double* __restrict__ p1,
+                                               const Geo& g, Src* out) {
+  const int lane = (int)(threadIdx.x & (kWave - 1));
+  const int t = (lane >> 5) < NSRC ? (lane >> 5) : 0;
+  const int role = lane & 31;
+  const bool writer = (lane >> 5) < NSRC;
+  const double* prm = t ? p1 : p0;
+  double sv = 0.0, cv = 1.0;
+  if (role < 4) sincos(decode_angle(role, prm), &sv, &cv);
+  const int l0 = t << 5;
+  SrcTrig tr;
+  tr.sl = __shfl(sv, l0 + 0);
+  tr.cl = __shfl(cv, l0 + 0);
+  tr.sb = __shfl(sv, l0 + 1);
+  tr.cb = __shfl(cv, l0 + 1);
+  tr.ci = __shfl(cv, l0 + 2);
+  tr.s2p = __shfl(sv, l0 + 3);
+  tr.c2p = __shfl(cv, l0 + 3);
+  if (writer && role < 10) decode_group(role, prm, tr, g, out[t]);
+}
+
+// The same decode by one thread (all groups in turn), for the decode pass
+// that runs one thread per template.
+__device__ __forceinline__ void decode_source(const double* __restrict__ prm, const Geo& g, Src& out) {
+  SrcTrig tr;
+  sincos(decode_angle(0, prm), &tr.sl, &tr.cl);
+  sincos(decode_angle(1, prm), &tr.sb, &tr.cb);
+  double si;
+  sincos(decode_angle(2, prm), &si, &tr.ci);
+  sincos(decode_angle(3, prm), &tr.s2p, &tr.c2p);
+  for (int a = 0; a < 10; a++) decode_group(a, prm, tr, g, out);
 }
 
 // ---------------------------------------------------------------------------
@@ -476,15 +508,17 @@ __device__ __forceinline__ void expi_cycles_k(const double* c, cx<F>* out) {
 // The spacecraft positions, k.x/c and the receiver phases are always formed
 // in double; arm projections, link amplitudes and the TDI algebra in F.
 // ---------------------------------------------------------------------------
-template <int NSER, typename F, int UC = 1>
-__device__ __forceinline__ void slow_sample(const Src& s, const Geo& g, const double* __restrict__ basis, int n,
+// S is Src, or Src in the constant address space (decoded sources read
+// through the scalar cache)
+template <int NSER, typename F, int UC = 1, typename S = Src>
+__device__ __forceinline__ void slow_sample(const S& s, const Geo& g, const double* __restrict__ basis, int n,
                                             double t, cx<F>* out) {
   const double ca = basis[4 * n + 0], sa = basis[4 * n + 1];
   const double c2a = basis[4 * n + 2], s2a = basis[4 * n + 3];
-  auto affine = [&](const double* c) { return c[4] + c[0] * ca + c[1] * sa + c[2] * c2a + c[3] * s2a; };
+  auto affine = [&](const auto* c) { return c[4] + c[0] * ca + c[1] * sa + c[2] * c2a + c[3] * s2a; };
 
   const F fca = (F)ca, fsa = (F)sa, fc2a = (F)c2a, fs2a = (F)s2a;
-  auto affine_f = [&](const double* c) {
+  auto affine_f = [&](const auto* c) {
     return (F)c[4] + (F)c[0] * fca + (F)c[1] * fsa + (F)c[2] * fc2a + (F)c[3] * fs2a;
   };
   // arm projections k.n (the arms close the triangle, n_0 + n_1 + n_2 = 0,
@@ -542,7 +576,7 @@ __device__ __forceinline__ void slow_sample(const Src& s, const Geo& g, const do
     }
     pn[2] = -(pn[0] + pn[1]);
     qn[2] = -(qn[0] + qn[1]);
-    const cx<F> cp = cvt<F>(s.cp), cx2 = cvt<F>(s.cx2);
+    const cx<F> cp = load_cx<F>(s.cp), cx2 = load_cx<F>(s.cx2);
 #pragma unroll
     for (int m = 0; m < 3; m++) {
       F ep = pn[m] * pn[m] - qn[m] * qn[m];
@@ -768,8 +802,8 @@ __device__ __forceinline__ void fft_stages(cx<F>* buf, const cx<F>* __restrict__
 // spectrum at any window bin j from the transformed U/V series in LDS.
 // Ends with a barrier, so the caller may read the workspace immediately.
 // ---------------------------------------------------------------------------
-template <int N, int NSER, typename F, int NT = block_threads<N>()>
-__device__ __forceinline__ void template_transform(const Src& s, const Geo& g, const WaveTables<F>& tb,
+template <int N, int NSER, typename F, int NT = block_threads<N>(), typename S = Src>
+__device__ __forceinline__ void template_transform(const S& s, const Geo& g, const WaveTables<F>& tb,
                                                    cx<F>* buf, int tid) {
   constexpr int SP = series_pitch<N>();
   // link phases u = (1 -+ k.n) (pi f L/c - ...) stay below 2 pi (L/c) f_max plus
@@ -785,7 +819,7 @@ __device__ __forceinline__ void template_transform(const Src& s, const Geo& g, c
     for (int n = tid; n < N; n += NT) {
       double t = ((double)n + 0.5) * g.T / (double)N;
       cx<F> v[6];
-      slow_sample<NSER, F, 1>(s, g, tb.basis, n, t, v);
+      slow_sample<NSER, F, 1, S>(s, g, tb.basis, n, t, v);
       const int a = lds_pad<N>(n);
 #pragma unroll
       for (int c = 0; c < NSER; c++) buf[c * SP + a] = v[c];
@@ -795,7 +829,7 @@ __device__ __forceinline__ void template_transform(const Src& s, const Geo& g, c
     for (int n = tid; n < N; n += NT) {
       double t = ((double)n + 0.5) * g.T / (double)N;
       cx<F> v[6];
-      slow_sample<NSER, F, 0>(s, g, tb.basis, n, t, v);
+      slow_sample<NSER, F, 0, S>(s, g, tb.basis, n, t, v);
       const int a = lds_pad<N>(n);
 #pragma unroll
       for (int c = 0; c < NSER; c++) buf[c * SP + a] = v[c];
@@ -805,7 +839,7 @@ __device__ __forceinline__ void template_transform(const Src& s, const Geo& g, c
     for (int n = tid; n < N; n += NT) {
       double t = ((double)n + 0.5) * g.T / (double)N;
       cx<F> v[6];
-      slow_sample<NSER, F, 1>(s, g, tb.basis, n, t, v);
+      slow_sample<NSER, F, 1, S>(s, g, tb.basis, n, t, v);
       const int a = lds_pad<N>(n);
 #pragma unroll
       for (int c = 0; c < NSER; c++) buf[c * SP + a] = v[c];
@@ -824,14 +858,14 @@ __device__ __forceinline__ void template_transform(const Src& s, const Geo& g, c
 // q + k >= N/2, since |k| <= N/2); 1 - D^2 = 2 sin x (sin x, cos x) is formed
 // without cancellation (at 0.1 mHz x ~ 5e-3, where 1 - cos 2x would lose
 // three digits in single precision).
-template <int N, int NCH, typename F>
-__device__ __forceinline__ void bin_spectrum(const Src& s, const Geo& g, const WaveTables<F>& tb, const cx<F>* buf,
+template <int N, int NCH, typename F, typename S = Src>
+__device__ __forceinline__ void bin_spectrum(const S& s, const Geo& g, const WaveTables<F>& tb, const cx<F>* buf,
                                              int j, cx<F>* out) {
   constexpr int SP = series_pitch<N>();
   constexpr double norm[3] = {kInvSqrt2, kInvSqrt6, kInvSqrt3};
   const int kk = (j + N / 2) & (N - 1);
   const int pos = lds_pad<N>(fft_pos<N>(kk));
-  const cx<F> D = cvt<F>(s.dq) * tb.bin_W[j];
+  const cx<F> D = load_cx<F>(s.dq) * tb.bin_W[j];
   // D = (cos x, -sin x):  1 - D^2 = (2 sin^2 x, 2 sin x cos x)
   const F two_s = (F)2 * D.im;
   const cx<F> Fj = tb.bin_F[j];

@@ -157,7 +157,28 @@ struct DeltaArgs {
   int* route_count;
   double route_tol;
   int64_t route_b0;
+  // decoded sources of pairs [src_b0, src_b0 + chunk): old at 2 (b - src_b0),
+  // new at 2 (b - src_b0) + 1 (k_decode_pairs)
+  const Src* srcs;
+  int64_t src_b0;
 };
+
+// Decode pass: one thread per template of pairs [b0, b0 + nb) into out
+// (old, new interleaved).  The fused kernels then read the decoded sources
+// through the scalar cache: per template a wave loads each coefficient once
+// into scalar registers instead of every lane reading it from LDS, and no
+// wave of the fused kernel spends time on the decode.
+__global__ __launch_bounds__(256) void k_decode_pairs(Geo g, const double* __restrict__ p_old,
+                                                      const double* __restrict__ p_new, int64_t b0, int64_t nb,
+                                                      Src* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= 2 * nb) return;
+  decode_source(((i & 1) ? p_new : p_old) + 8 * (b0 + (i >> 1)), g, out[i]);
+}
+
+// a decoded source in the constant address space: loads of its fields are
+// scalar loads
+using ConstSrc = const __attribute__((address_space(4))) Src;
 
 // Wide templates (N >= 512) keep the old template's spectrum in registers
 // and hand it over through the FFT buffer once the new template's bins are
@@ -181,7 +202,6 @@ struct DeltaSmem {
   cx<F> buf[4 * series_pitch<N>()];
   cx<F> rwin[delta_rwin_in_buf<N>() ? 1 : 2 * N];
   double red[6 * (delta_threads<N>() / kWave)];
-  Src src[2];  // 0: old, 1: new
 };
 
 template <int N, typename F>
@@ -190,8 +210,8 @@ __device__ __forceinline__ void delta_one(const Geo& g, const WaveTables<F>& tb,
   constexpr int NT = delta_threads<N>();
   constexpr int BPT = N / NT;  // window bins per thread
   const int tid = threadIdx.x;
-  // validity and carrier bins first; the full decode goes to LDS, which
-  // keeps the decoded sources out of the registers
+  // validity and carrier bins first; the decoded sources come from the
+  // decode pass
   const SrcHead ho = source_head(da.p_old + 8 * b, g);
   const SrcHead hn = source_head(da.p_new + 8 * b, g);
   const int ri = da.res_idx[b];
@@ -211,10 +231,7 @@ __device__ __forceinline__ void delta_one(const Geo& g, const WaveTables<F>& tb,
 
   auto weight = [&](const double* Sc, int64_t idx) { return psd_inv ? Sc[idx] : 1.0 / Sc[idx]; };
 
-  // wave 0 decodes the old and the new source side by side; the block shares them
-  if (tid < kWave) decode_sources<2>(da.p_old + 8 * b, da.p_new + 8 * b, g, sm.src);
-
-  __syncthreads();
+  ConstSrc* const cs = (ConstSrc*)da.srcs + 2 * (b - da.src_b0);
 
   // old template r: its spectrum over its window, in LDS (rw) or, for the
   // wide templates, in registers until the new template's bins are taken
@@ -223,7 +240,7 @@ __device__ __forceinline__ void delta_one(const Geo& g, const WaveTables<F>& tb,
   cx<F> aa[BPT][2];
   cx<F>* rw = kRegR ? sm.buf : sm.rwin;
   if (ho.state == 0) {
-    const Src& so = sm.src[0];
+    ConstSrc& so = cs[0];
     template_transform<N, 4, F, NT>(so, g, tb, sm.buf, tid);
 #pragma unroll
     for (int m = 0; m < BPT; m++) {
@@ -239,7 +256,7 @@ __device__ __forceinline__ void delta_one(const Geo& g, const WaveTables<F>& tb,
   if constexpr (kRegR) {
     // new template a: bins into registers, then r's spectrum into the buffer
     if (hn.state == 0) {
-      const Src& sn = sm.src[1];
+      ConstSrc& sn = cs[1];
       template_transform<N, 4, F, NT>(sn, g, tb, sm.buf, tid);
 #pragma unroll
       for (int m = 0; m < BPT; m++) bin_spectrum<N, 2, F>(sn, g, tb, sm.buf, tid + NT * m, aa[m]);
@@ -278,7 +295,7 @@ __device__ __forceinline__ void delta_one(const Geo& g, const WaveTables<F>& tb,
   };
 
   if (hn.state == 0) {
-    const Src& sn = sm.src[1];
+    ConstSrc& sn = cs[1];
     if constexpr (!kRegR) template_transform<N, 4, F, NT>(sn, g, tb, sm.buf, tid);
     // a's window, one bin per iteration: residual and weights are loaded at
     // the top of the iteration (not earlier: at four waves per SIMD the other
