@@ -303,3 +303,34 @@ def test_full_scale_sampled_parity():
     scale = np.maximum(1.0, np.abs(terms[:, :5]).max(axis=1))
     assert np.max(np.abs(got[idx] - ref) / scale) <= TOL
     ctx.close()
+
+
+def test_batches_beyond_one_decode_chunk(tiny, tiny_likelihood_data):
+    """A call of more than 2^17 pairs passes through the decode workspace in
+    chunks: every pair's result equals, bit for bit, its result in a small
+    call (fixed and uneven widths), and sampled pairs of both chunks match
+    the oracle."""
+    cfg, ctx, orc = tiny
+    S, R, src = tiny_likelihood_data
+    old, new = _pairs(orc, src, 1300)
+    n = len(old)
+    B = (1 << 17) + 300
+    rep = np.arange(B) % n
+    rng = np.random.default_rng(1301)
+    ri_s = rng.integers(0, 3, n).astype(np.int32)
+    pi_s = rng.integers(0, 2, n).astype(np.int32)
+    print(f"decode chunks: B={B} (2^17 + 300), N=128 and uneven", flush=True)
+    small = ctx.gb_delta_loglike(_t(R), _t(S), _t(old), _t(new), 128, _t(ri_s), _t(pi_s)).cpu().numpy()
+    big = ctx.gb_delta_loglike(_t(R), _t(S), _t(old[rep]), _t(new[rep]), 128, _t(ri_s[rep]),
+                               _t(pi_s[rep])).cpu().numpy()
+    assert np.array_equal(big, small[rep])
+    N = _width_rule(old[:, 1])
+    small_v = ctx.gb_delta_loglike_var(_t(R), _t(S), _t(old), _t(new), _t(N), _t(ri_s), _t(pi_s)).cpu().numpy()
+    big_v = ctx.gb_delta_loglike_var(_t(R), _t(S), _t(old[rep]), _t(new[rep]), _t(N[rep]), _t(ri_s[rep]),
+                                     _t(pi_s[rep])).cpu().numpy()
+    assert np.array_equal(big_v, small_v[rep])
+    idx = np.concatenate([rng.choice(B, 40, replace=False), [0, (1 << 17) - 1, 1 << 17, B - 1]])
+    ref, terms = orc.delta_loglike(R, S, old[rep[idx]], new[rep[idx]], 128, ri_s[rep[idx]], pi_s[rep[idx]],
+                                   return_terms=True)
+    scale = np.maximum(1.0, np.abs(terms[:, :5]).max(axis=1))
+    assert np.max(np.abs(big[idx] - ref) / scale) <= TOL
