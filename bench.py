@@ -122,6 +122,12 @@ def secondary(ctx, torch, stream, cfg, R, invS, po, pn, ri, pi):
                                                                          psd_inverse=True, out=res), 5)
     counts = {int(w): int((widths == w).sum()) for w in (128, 256, 512, 1024)}
     out["uneven_width"] = {"evals_per_s": round(B / (ms / 1e3), 1), "ms": round(ms, 4), "widths": counts}
+    # the same with exact grids (bucket sizes read back: one synchronisation per call)
+    ctx.set_tuning(exact_grids=1)
+    ms = _time_launches(torch, stream, lambda: ctx.gb_delta_loglike_var(R, invS, po, pn, Nt, ri, pi,
+                                                                         psd_inverse=True, out=res), 5)
+    ctx.set_tuning(exact_grids=0)
+    out["uneven_width_exact_grids"] = {"evals_per_s": round(B / (ms / 1e3), 1), "ms": round(ms, 4)}
     # the full proposal mix: 10% births, 10% deaths
     fb = inputs.paper_swap_batch(mix="full")
     fo = torch.from_numpy(fb.params_old).to(dev)
@@ -144,6 +150,10 @@ def secondary(ctx, torch, stream, cfg, R, invS, po, pn, ri, pi):
                                    "max_abs_err_vs_fp64": float(err.max()),
                                    "median_abs_err_vs_fp64": float(err.median()),
                                    "frac_err_le_1e-3": float((err <= 1e-3).double().mean())}
+    ctx_m.set_tuning(exact_grids=1)
+    ms = _time_launches(torch, stream, lambda: ctx_m.gb_delta_loglike(R, invS, po, pn, cfg.N, ri, pi,
+                                                                       psd_inverse=True, out=resm), 10)
+    out["mixed_precision_N256_exact_grids"] = {"evals_per_s": round(B / (ms / 1e3), 1), "ms": round(ms, 4)}
     ctx_m.close()
     # the same without the FP64 re-evaluation of the loud pairs (pure FP32 response)
     from paper_2405_04690_amd.gbl import GBL_MIXED_UNROUTED

@@ -22,11 +22,12 @@
  *              longer batches pass in chunks) and frees it in gbl_destroy.
  *   Streams    Compute calls only enqueue work on the context's stream and
  *              return; outputs are valid once the caller synchronises that
- *              stream.  Compute calls never allocate or print, and they do not
- *              synchronise, with one exception that the exact_grids knob
- *              (gbl_tuning) controls: the width-bucketed calls and the FP64
- *              re-evaluation pass of GBL_MIXED read device-side list lengths
- *              back to size their launches, outside stream capture only.
+ *              stream.  Compute calls never allocate, synchronise or print
+ *              (so they can be captured into graphs), unless the caller opts
+ *              into the exact_grids knob (gbl_tuning): then the
+ *              width-bucketed calls and the FP64 re-evaluation pass of
+ *              GBL_MIXED read device-side list lengths back to size their
+ *              launches, outside stream capture only.
  *   Errors     Calls return GBL_OK (0) or a negative status.  Argument errors
  *              are detected on the host before anything is launched;
  *              gbl_last_error() returns a message for the last failure.
@@ -124,15 +125,15 @@ int gbl_band(const gbl_ctx* ctx, int64_t* k_min, int64_t* n_bins);
  *                 power of two in [4096, 1048576] (default 1048576); likelihood
  *                 calls use at most 2^17 pairs per group (the decode workspace);
  *   widest_first  uneven widths: launch the widest bucket first (1) or last (0);
- *   exact_grids   1 (default): when the context's stream is not being captured,
- *                 gb_waveform_var, gb_delta_loglike_var and the FP64
- *                 re-evaluation pass of GBL_MIXED copy the device-side bucket
- *                 sizes (and routed-pair counts) to pinned host memory, one
- *                 stream synchronisation each, and launch exactly that many
- *                 work-groups; 0: never synchronise, launch the upper bound
- *                 (the batch size) and let the surplus work-groups exit (at
- *                 N = 1024 those hold 96 KB of LDS each and cost up to a third
- *                 of the launch).  Under capture the upper bound is always used.
+ *   exact_grids   0 (default): never synchronise; the bucketed launches and
+ *                 the FP64 re-evaluation pass of GBL_MIXED use the upper bound
+ *                 (the batch size) as grid and the surplus work-groups exit;
+ *                 1: when the context's stream is not being captured,
+ *                 gb_waveform_var, gb_delta_loglike_var and that pass copy the
+ *                 device-side bucket sizes (and routed-pair counts) to pinned
+ *                 host memory, one stream synchronisation each, and launch
+ *                 exactly that many work-groups.  Under capture the upper
+ *                 bound is always used.
  * Results do not depend on them (bitwise for the FP64 paths). */
 typedef struct {
   int32_t flow_grid;

@@ -4,8 +4,9 @@ the context's stream and keeps the fastest.  Results can be cached in a JSON
 file keyed by device, precision and a workload tag.
 
 Knobs: the bucket group size (uneven widths and the mixed-precision FP64
-re-evaluation), the launch order of the width buckets, and the grid cap of
-the flow inference launches."""
+re-evaluation), the launch order of the width buckets, exact grids from
+host-read bucket sizes (a stream synchronisation per call), and the grid cap
+of the flow inference launches."""
 from __future__ import annotations
 
 import itertools
@@ -57,7 +58,7 @@ def tune_delta_var(ctx: Context, args: tuple, kwargs: dict | None = None, reps: 
     kwargs = dict(kwargs or {})
     out = torch.empty(args[2].shape[0], dtype=torch.float64, device=ctx.device)
     kwargs["out"] = out
-    space = {"bucket_chunk": list(CHUNKS), "widest_first": [1, 0]}
+    space = {"bucket_chunk": list(CHUNKS), "widest_first": [1, 0], "exact_grids": [0, 1]}
     return tune(ctx, lambda: ctx.gb_delta_loglike_var(*args, **kwargs), space, reps)
 
 

@@ -54,11 +54,11 @@ struct gbl_ctx {
 };
 
 // Device-side list lengths (width buckets, routed pairs) copied to the host
-// when the stream is not being captured, at the price of one stream
-// synchronisation, so that the launches that walk the lists get exact grids.
-// Under capture (or if the copy fails) the grids stay at their upper bound and
-// the surplus blocks exit at once; at N = 1024, whose blocks hold 96 KB of LDS,
-// those empty blocks cost as much as a third of the launch.
+// when the caller opted in (exact_grids) and the stream is not being captured,
+// at the price of one stream synchronisation, so that the launches that walk
+// the lists get exact grids.  Otherwise the grids stay at their upper bound
+// and the surplus blocks exit at once; for the wide templates, whose blocks
+// hold 64 KB of LDS, those empty blocks cost as much as a third of the launch.
 static bool host_counts(gbl_ctx* ctx, const int* dev, int n, int* out) {
   if (!ctx->tune.exact_grids) return false;
   hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
@@ -118,7 +118,7 @@ extern "C" int gbl_create(gbl_ctx** out, const gbl_config* cfg, void* hip_stream
   if (cfg->precision != GBL_FP64 && cfg->precision != GBL_MIXED) return GBL_EUNSUPPORTED;
 
   gbl_ctx* ctx = new gbl_ctx();
-  ctx->tune = gbl_tuning{4096, kBucketCap, 1, 1};
+  ctx->tune = gbl_tuning{4096, kBucketCap, 1, 0};
   ctx->cfg = *cfg;
   ctx->stream = (hipStream_t)hip_stream;
   int64_t k_min = (int64_t)std::ceil(cfg->f_lo * cfg->T);
