@@ -409,8 +409,8 @@ extern "C" int gb_waveform(gbl_ctx* ctx, const double* params, int64_t B, int32_
 // decode pass of pairs [b0, b0 + nb) (nb <= kDecodeChunk) into the context's
 // workspace; returns the arguments that point the fused kernels at it
 static gbl::DeltaArgs decode_pairs(gbl_ctx* ctx, gbl::DeltaArgs da, int64_t b0, int64_t nb) {
-  hipLaunchKernelGGL(gbl::k_decode_pairs, dim3((unsigned)((2 * nb + 255) / 256)), dim3(256), 0, ctx->stream,
-                     ctx->geo, da.p_old, da.p_new, b0, nb, ctx->src_ws);
+  hipLaunchKernelGGL(gbl::k_decode_pairs, dim3((unsigned)((2 * nb + gbl::kDecodeBlock - 1) / gbl::kDecodeBlock)),
+                     dim3(gbl::kDecodeBlock), 0, ctx->stream, ctx->geo, da.p_old, da.p_new, b0, nb, ctx->src_ws);
   da.srcs = ctx->src_ws;
   da.src_b0 = b0;
   return da;

@@ -140,7 +140,7 @@ __device__ __forceinline__ cd expi_cycles(double c) {
 // ---------------------------------------------------------------------------
 // Source decode (uniform across the wave)
 // ---------------------------------------------------------------------------
-struct Src {
+struct alignas(16) Src {
   double f0, fdot, phi0_cyc, dfq;  // phi0 / (2 pi); dfq = f0 - q/T
   int64_t q;                   // carrier bin floor(f0 T)
   // The orbit enters through the four basis values b = (cos a, sin a, cos 2a,

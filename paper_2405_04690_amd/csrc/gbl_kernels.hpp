@@ -168,12 +168,24 @@ struct DeltaArgs {
 // through the scalar cache: per template a wave loads each coefficient once
 // into scalar registers instead of every lane reading it from LDS, and no
 // wave of the fused kernel spends time on the decode.
-__global__ __launch_bounds__(256) void k_decode_pairs(Geo g, const double* __restrict__ p_old,
-                                                      const double* __restrict__ p_new, int64_t b0, int64_t nb,
-                                                      Src* __restrict__ out) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= 2 * nb) return;
-  decode_source(((i & 1) ? p_new : p_old) + 8 * (b0 + (i >> 1)), g, out[i]);
+// (decoded into LDS first, then copied out in 16-byte pieces by consecutive
+// lanes, so that the stores to the workspace are contiguous)
+constexpr int kDecodeBlock = 64;
+
+__global__ __launch_bounds__(kDecodeBlock) void k_decode_pairs(Geo g, const double* __restrict__ p_old,
+                                                               const double* __restrict__ p_new, int64_t b0,
+                                                               int64_t nb, Src* __restrict__ out) {
+  static_assert(sizeof(Src) % 16 == 0, "decoded sources are copied in 16-byte pieces");
+  __shared__ Src stage[kDecodeBlock];
+  const int64_t first = (int64_t)blockIdx.x * kDecodeBlock;
+  const int64_t i = first + threadIdx.x;
+  if (i < 2 * nb) decode_source(((i & 1) ? p_new : p_old) + 8 * (b0 + (i >> 1)), g, stage[threadIdx.x]);
+  __syncthreads();
+  const int64_t count = (2 * nb - first) < kDecodeBlock ? (2 * nb - first) : kDecodeBlock;
+  const int pieces = (int)(count * (int64_t)(sizeof(Src) / 16));
+  const uint4* src = reinterpret_cast<const uint4*>(stage);
+  uint4* dst = reinterpret_cast<uint4*>(out + first);
+  for (int k = threadIdx.x; k < pieces; k += kDecodeBlock) dst[k] = src[k];
 }
 
 // a decoded source in the constant address space: loads of its fields are
