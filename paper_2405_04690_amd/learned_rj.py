@@ -138,12 +138,32 @@ def collect(sw: Sweep, n_sweeps: int, every: int = 1):
     return torch.cat(us), torch.cat(bs).contiguous()
 
 
-def train(flow: Flow, u, band, steps: int, batch: int = 4096, lr: float = 1e-3, seed: int = 0):
+def source_weights(u, band, T: float, n_states: int, min_presence: float = 0.1, cell_bins: float = 4.0):
+    """Per-sample training weights that give every recurring source the same
+    total weight, the way the paper's refit proposal fits the sources that
+    appear regularly and combines their mixtures with equal probability
+    (Sec. 4, "refit RJ proposal"): samples are grouped into sources by
+    sub-band and carrier-frequency cell (cell_bins frequency bins wide); a
+    group present in at least min_presence of the n_states collected chain
+    states shares weight 1, a rarer one gets none."""
+    cell = torch.floor(u[:, 1].double() * T / cell_bins).to(torch.int64)
+    key = band.to(torch.int64) * (1 << 40) + cell
+    _, inv, counts = torch.unique(key, return_inverse=True, return_counts=True)
+    c = counts[inv].double()
+    return torch.where(c >= min_presence * n_states, 1.0 / c, torch.zeros_like(c))
+
+
+def train(flow: Flow, u, band, steps: int, batch: int = 4096, lr: float = 1e-3, seed: int = 0, weights=None):
+    """Adam steps on batches drawn from (u, band), uniformly or with the given
+    per-sample weights"""
     gen = torch.Generator(device=u.device)
     gen.manual_seed(seed)
     losses = []
     for _ in range(steps):
-        idx = torch.randint(0, u.shape[0], (batch,), generator=gen, device=u.device)
+        if weights is None:
+            idx = torch.randint(0, u.shape[0], (batch,), generator=gen, device=u.device)
+        else:
+            idx = torch.multinomial(weights, batch, replacement=True, generator=gen)
         losses.append(flow.train_step(u[idx].contiguous(), band[idx].contiguous(), lr).clone())
     return torch.stack(losses).view(-1).cpu().numpy()
 
@@ -226,17 +246,20 @@ def discover(problem: Problem, n_sweeps: int, flow: Flow | None, start):
 
 
 def compare(problem: Problem, burn: int = 100, collect_sweeps: int = 200, train_steps: int = 300,
-            measure_sweeps: int = 400, lr: float = 1e-3, seed: int = 0):
-    """burn-in and sample collection with prior RJ, flow training, then the
-    same number of sweeps from the same state with each proposal"""
+            measure_sweeps: int = 400, lr: float = 1e-3, seed: int = 0, balance: bool = False):
+    """burn-in and sample collection with prior RJ, flow training (samples
+    weighted per source if balance), then the same number of sweeps from the
+    same state with each proposal"""
     from .flow import init_params
     sw = problem.sweep
     sw.run(burn)
     u, band = collect(sw, collect_sweeps)
     flow = Flow(problem.ctx, problem.fcfg, init_params(seed, problem.fcfg.n_emb))
+    n_states = sw.cfg.n_walkers * collect_sweeps
+    weights = source_weights(u, band, problem.ctx.cfg.T, n_states) if balance else None
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    losses = train(flow, u, band, train_steps, lr=lr, seed=seed)
+    losses = train(flow, u, band, train_steps, lr=lr, seed=seed, weights=weights)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     state = save(sw)
