@@ -173,8 +173,9 @@ def secondary(ctx, torch, stream, cfg, R, invS, po, pn, ri, pi):
                          device=dev).repeat(nw, 1)
     ridx = torch.arange(nw, dtype=torch.int32, device=dev)
     ms = _time_launches(torch, stream, lambda: ctx.gb_psd_loglike(R, noise, ridx), 10)
-    # algorithmic bytes per set: residual A+E (32 B/bin) + PSD basis P1, P2 (16 B/bin)
-    gbs = nw * ctx.n_bins * 48 / (ms / 1e3) / 1e9
+    # algorithmic bytes: residual A+E of each set (32 B/bin) + the PSD basis P1, P2
+    # (16 B/bin), which every set of the launch shares
+    gbs = (nw * 32 + 16) * ctx.n_bins / (ms / 1e3) / 1e9
     out["psd_loglike"] = {"sets": nw, "ms": round(ms, 4), "sets_per_s": round(nw / (ms / 1e3), 1),
                           "algorithmic_gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
     return out
@@ -414,7 +415,10 @@ def _full_sweep(torch, ctx, sw, stream, d, n_bands, k_band0, N, n_temps, n_walke
     st = sw.stats.cpu().numpy()
     pst = ps.stats.cpu().numpy()
     sets = n_temps * n_walkers * 2   # refresh of every chain + one proposal per chain
-    psd_bytes = sets * ctx.n_bins * 2 * (16 + 16) + 3 * n_walkers * 2 * ctx.n_bins * 16
+    # residual A+E per set evaluation (32 B/bin) and the shared PSD basis per pass
+    # (16 B/bin, three passes); the full-residual build (two buffers read and one
+    # written per walker, the data once: 32 B/bin each); the cold chains' 1/S (16 B/bin)
+    psd_bytes = (sets * 32 + 3 * 16 + (3 * n_walkers + 1) * 32 + n_walkers * 16) * ctx.n_bins
     return {"flow_train_s": round(train_s, 3), "flow_loss_first_last": [round(float(losses[0]), 3),
                                                                        round(float(losses[-1]), 3)],
             "gb_sweep_with_flow_ms": round(gb_ms, 3), "psd_step_ms": round(psd_ms, 3),

@@ -520,20 +520,33 @@ extern "C" int gb_psd_eval(gbl_ctx* ctx, const double* noise, int64_t P, int32_t
   return check_launch(ctx, "gb_psd_eval");
 }
 
+// PSD likelihood of P parameter sets: partial sums in groups of kPsdSets sets (the
+// remainder one set per block), then the fixed-order final sum per set.
+static void psd_loglike_launch(gbl_ctx* ctx, const cd* residual, int n_res, const double* noise,
+                               const int32_t* res_idx, int64_t P, double* logl) {
+  for (int64_t p0 = 0; p0 < P; p0 += kPsdBatch) {
+    const int64_t np = P - p0 < kPsdBatch ? P - p0 : kPsdBatch;
+    const int64_t ng = np / gbl::kPsdSets, rest = np - ng * gbl::kPsdSets;
+    if (ng > 0)
+      hipLaunchKernelGGL(gbl::k_psd_partial<gbl::kPsdSets>, dim3(gbl::kPsdChunks, (unsigned)ng),
+                         dim3(gbl::kPsdBlock), 0, ctx->stream, ctx->geo.n_bins, ctx->psd_P1, ctx->psd_P2, residual,
+                         n_res, noise, res_idx, p0, p0, ctx->psd_work);
+    if (rest > 0)
+      hipLaunchKernelGGL(gbl::k_psd_partial<1>, dim3(gbl::kPsdChunks, (unsigned)rest), dim3(gbl::kPsdBlock), 0,
+                         ctx->stream, ctx->geo.n_bins, ctx->psd_P1, ctx->psd_P2, residual, n_res, noise, res_idx,
+                         p0, p0 + ng * gbl::kPsdSets, ctx->psd_work);
+    hipLaunchKernelGGL(gbl::k_psd_final, dim3((unsigned)np), dim3(64), 0, ctx->stream, 1.0 / ctx->cfg.T,
+                       ctx->psd_work, p0, logl);
+  }
+}
+
 extern "C" int gb_psd_loglike(gbl_ctx* ctx, const double* residual, int32_t n_res, const double* noise,
                               const int32_t* res_idx, int64_t P, double* logl) {
   if (!ctx) return GBL_EINVAL;
   if (P < 0 || n_res < 1) return fail(ctx, GBL_EINVAL, "gb_psd_loglike: bad sizes%s");
   if (P == 0) return GBL_OK;
   if (!residual || !noise || !res_idx || !logl) return fail(ctx, GBL_EINVAL, "gb_psd_loglike: null pointer%s");
-  for (int64_t p0 = 0; p0 < P; p0 += kPsdBatch) {
-    int64_t np = P - p0 < kPsdBatch ? P - p0 : kPsdBatch;
-    hipLaunchKernelGGL(gbl::k_psd_partial, dim3(gbl::kPsdChunks, (unsigned)np), dim3(gbl::kPsdBlock), 0,
-                       ctx->stream, ctx->geo.n_bins, ctx->psd_P1, ctx->psd_P2, (const cd*)residual, (int)n_res, noise,
-                       res_idx, p0, ctx->psd_work);
-    hipLaunchKernelGGL(gbl::k_psd_final, dim3((unsigned)np), dim3(64), 0, ctx->stream, 1.0 / ctx->cfg.T,
-                       ctx->psd_work, p0, logl);
-  }
+  psd_loglike_launch(ctx, (const cd*)residual, (int)n_res, noise, res_idx, P, logl);
   return check_launch(ctx, "gb_psd_loglike");
 }
 
@@ -988,18 +1001,6 @@ extern "C" int gbl_set_tuning(gbl_ctx* ctx, const gbl_tuning* t) {
 // ---------------------------------------------------------------------------
 // noise-PSD step
 // ---------------------------------------------------------------------------
-static void psd_loglike_launch(gbl_ctx* ctx, const cd* residual, int n_res, const double* noise,
-                               const int32_t* res_idx, int64_t P, double* logl) {
-  for (int64_t p0 = 0; p0 < P; p0 += kPsdBatch) {
-    int64_t np = P - p0 < kPsdBatch ? P - p0 : kPsdBatch;
-    hipLaunchKernelGGL(gbl::k_psd_partial, dim3(gbl::kPsdChunks, (unsigned)np), dim3(gbl::kPsdBlock), 0,
-                       ctx->stream, ctx->geo.n_bins, ctx->psd_P1, ctx->psd_P2, residual, n_res, noise, res_idx, p0,
-                       ctx->psd_work);
-    hipLaunchKernelGGL(gbl::k_psd_final, dim3((unsigned)np), dim3(64), 0, ctx->stream, 1.0 / ctx->cfg.T,
-                       ctx->psd_work, p0, logl);
-  }
-}
-
 extern "C" int gb_psd_sweep_step(gbl_ctx* ctx, const gbl_psd_sweep_config* c, const gbl_psd_sweep_state* st) {
   if (!ctx) return GBL_EINVAL;
   if (!c || !st) return fail(ctx, GBL_EINVAL, "gb_psd_sweep_step: null config or state%s");

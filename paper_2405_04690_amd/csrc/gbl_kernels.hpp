@@ -537,54 +537,83 @@ __global__ void k_psd_eval(int64_t nb, const double* __restrict__ P1, const doub
 
 constexpr int kPsdChunks = 256;
 constexpr int kPsdBlock = 256;
+constexpr int kPsdSets = 4;  // parameter sets per block of the PSD likelihood
+constexpr double kLn2 = 0.69314718055994530942;
 
-// partial sums over one chunk of bins for one parameter set:
-// work[p][chunk] = (sum |R|^2/S, sum ln S) over both channels
+// partial sums over one chunk of bins for G parameter sets
+// (sets p = p1st + blockIdx.y * G + s, s < G; p0 = first set of the workspace):
+// work[p - p0][chunk] = (sum |R|^2/S, sum ln S) over both channels.  The sets of a
+// block share each bin's PSD basis load; every set's sums run in the same order
+// whatever G is, so the result does not depend on the grouping.
+// Each S is split as m 2^e (m in [1/2, 1)): a bin's two quadratic terms take one
+// division of m_A m_E, and a thread's ln S terms are one logarithm of the running
+// mantissa product (renormalised every bin) plus ln 2 times the exponent sum.
+template <int G>
 __global__ __launch_bounds__(kPsdBlock) void k_psd_partial(int64_t nb, const double* __restrict__ P1,
                                                            const double* __restrict__ P2,
                                                            const cd* __restrict__ residual, int n_res,
                                                            const double* __restrict__ noise,
                                                            const int32_t* __restrict__ res_idx, int64_t p0,
-                                                           double* __restrict__ work) {
-  const int64_t p = p0 + blockIdx.y;
+                                                           int64_t p1st, double* __restrict__ work) {
+  const int64_t pg = p1st + (int64_t)blockIdx.y * G;
   const int chunk = blockIdx.x;
   const int64_t cs = (nb + kPsdChunks - 1) / kPsdChunks;
   const int64_t lo = chunk * cs;
   const int64_t hi = lo + cs < nb ? lo + cs : nb;
-  const int ri = res_idx[p];
-  double quad = 0.0, lg = 0.0;
-  if (ri >= 0 && ri < n_res) {
-    const cd* R = residual + (int64_t)ri * 2 * nb;
-    const double oA = noise[4 * p] * noise[4 * p], aA = noise[4 * p + 1] * noise[4 * p + 1];
-    const double oE = noise[4 * p + 2] * noise[4 * p + 2], aE = noise[4 * p + 3] * noise[4 * p + 3];
-    for (int64_t k = lo + threadIdx.x; k < hi; k += kPsdBlock) {
-      double p1 = P1[k], p2 = P2[k];
-      double SAv = oA * p1 + aA * p2;
-      double SEv = oE * p1 + aE * p2;
-      cd r0 = R[k], r1 = R[nb + k];
-      quad += (r0.re * r0.re + r0.im * r0.im) / SAv + (r1.re * r1.re + r1.im * r1.im) / SEv;
-      lg += log(SAv) + log(SEv);
-    }
-  } else {
-    quad = qnan();
+  const cd* R[G];
+  double oA[G], aA[G], oE[G], aE[G], quad[G], lm[G];
+  int le[G];
+#pragma unroll
+  for (int s = 0; s < G; s++) {
+    const int64_t p = pg + s;
+    const int ri = res_idx[p];
+    R[s] = residual + (int64_t)(ri >= 0 && ri < n_res ? ri : 0) * 2 * nb;  // a bad index reports NaN below
+    oA[s] = noise[4 * p] * noise[4 * p];
+    aA[s] = noise[4 * p + 1] * noise[4 * p + 1];
+    oE[s] = noise[4 * p + 2] * noise[4 * p + 2];
+    aE[s] = noise[4 * p + 3] * noise[4 * p + 3];
+    quad[s] = 0.0;
+    lm[s] = 1.0;
+    le[s] = 0;
   }
-  __shared__ double sq[kPsdBlock / kWave], sl[kPsdBlock / kWave];
-  quad = wave_sum(quad);
-  lg = wave_sum(lg);
+  for (int64_t k = lo + threadIdx.x; k < hi; k += kPsdBlock) {
+    const double p1 = P1[k], p2 = P2[k];
+#pragma unroll
+    for (int s = 0; s < G; s++) {
+      // explicit fma: the same rounding in every instance of G
+      const double SAv = fma(oA[s], p1, aA[s] * p2);
+      const double SEv = fma(oE[s], p1, aE[s] * p2);
+      const cd r0 = R[s][k], r1 = R[s][nb + k];
+      const double qa = fma(r0.re, r0.re, r0.im * r0.im), qe = fma(r1.re, r1.re, r1.im * r1.im);
+      int eA, eE, eM;
+      const double mA = frexp(SAv, &eA), mE = frexp(SEv, &eE);
+      const double m = mA * mE;  // in [1/4, 1)
+      quad[s] += fma(ldexp(qa, -eA), mE, ldexp(qe, -eE) * mA) / m;
+      lm[s] = frexp(lm[s] * m, &eM);
+      le[s] += eA + eE + eM;
+    }
+  }
+  __shared__ double sq[G][kPsdBlock / kWave], sl[G][kPsdBlock / kWave];
   const int w = threadIdx.x / kWave;
-  if ((threadIdx.x & (kWave - 1)) == 0) {
-    sq[w] = quad;
-    sl[w] = lg;
+#pragma unroll
+  for (int s = 0; s < G; s++) {
+    const double q = wave_sum(quad[s]), l = wave_sum(fma((double)le[s], kLn2, log(lm[s])));
+    if ((threadIdx.x & (kWave - 1)) == 0) {
+      sq[s][w] = q;
+      sl[s][w] = l;
+    }
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
+  if (threadIdx.x < G) {
+    const int s = threadIdx.x;
+    const int ri = res_idx[pg + s];
     double a = 0.0, c = 0.0;
     for (int i = 0; i < kPsdBlock / kWave; i++) {
-      a += sq[i];
-      c += sl[i];
+      a += sq[s][i];
+      c += sl[s][i];
     }
-    double* dst = work + 2 * ((p - p0) * kPsdChunks + chunk);
-    dst[0] = a;
+    double* dst = work + 2 * ((pg + s - p0) * kPsdChunks + chunk);
+    dst[0] = ri >= 0 && ri < n_res ? a : qnan();
     dst[1] = c;
   }
 }

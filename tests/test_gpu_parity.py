@@ -244,6 +244,15 @@ def test_psd_eval_and_loglike_parity(tiny, tiny_likelihood_data):
     g1 = ctx.gb_psd_loglike(_t(R), _t(noise), _t(ri)).cpu().numpy()
     g2 = ctx.gb_psd_loglike(_t(R), _t(noise), _t(ri)).cpu().numpy()
     assert np.array_equal(g1, g2)  # fixed-order reduction: bitwise reproducible
+    # sets run in blocks of several sets, the remainder one set per block: a
+    # set's result does not depend on which way it ran
+    one = np.concatenate([ctx.gb_psd_loglike(_t(R), _t(noise[i:i + 1]), _t(ri[i:i + 1])).cpu().numpy()
+                          for i in range(P)])
+    assert np.array_equal(one, g1)
+    # PSD values near 1e-200, where S_A S_E is below the double range
+    tiny_g = ctx.gb_psd_loglike(_t(R * 1e-80), _t(noise * 1e-80), _t(ri)).cpu().numpy()
+    tiny_ref = orc.psd_loglike(R * 1e-80, noise * 1e-80, ri)
+    assert np.max(np.abs(tiny_g - tiny_ref) / np.abs(tiny_ref)) <= 1e-12
     ref = orc.psd_loglike(R, noise, ri)
     assert np.max(np.abs(g1 - ref) / np.abs(ref)) <= 1e-12
     # differences between parameter sets (what a sampler uses): bounded by the
