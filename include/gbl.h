@@ -204,7 +204,8 @@ int gb_psd_eval(gbl_ctx* ctx, const double* noise, int64_t P, int32_t psd_flags,
 /* Noise-parameter log-likelihood (Sec. 2 eq. like with Sec. 3 eq. psd):
  *   logl[p] = sum_{c in A,E} [ -2 df sum_k |R_c,k|^2 / S_c,k - sum_k ln S_c,k ]
  * with R = residual[res_idx[p]] and S from noise[p].  The sum over bins is a
- * fixed-order two-pass reduction, so results are bitwise reproducible.
+ * fixed-order two-pass reduction, so results are bitwise reproducible, and a
+ * set's result does not depend on P or on the other sets of the call.
  * Errors: GBL_EINVAL.  Out-of-range res_idx gives NaN for that set. */
 int gb_psd_loglike(gbl_ctx* ctx, const double* residual, int32_t n_res, const double* noise,
                    const int32_t* res_idx, int64_t P, double* logl);
