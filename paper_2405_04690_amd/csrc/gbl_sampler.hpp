@@ -652,7 +652,6 @@ __global__ __launch_bounds__(block_threads<N>()) void k_sweep_pt(Geo g, WaveTabl
   __shared__ BandSmem<N> sm;
   __shared__ int wt[256];
   __shared__ double Lc[256];
-  __shared__ int perm[256];
   __shared__ int hidx[256];  // window sum of the set at temperature t: entry slot hidx[t]
   const int nbp = (a.n_b - parity + 1) / 2;
   const int bi = blockIdx.x % nbp;
@@ -662,18 +661,21 @@ __global__ __launch_bounds__(block_threads<N>()) void k_sweep_pt(Geo g, WaveTabl
   const int nt = a.n_t;
   const int64_t sweep = *a.sweep_ctr;
   const int64_t k0w = a.k_band0 + (int64_t)(b - 1) * N;
-  if (tid == 0) {
-    for (int t = 0; t < nt; t++) {
-      for (int j = 0; j < a.n_w; j++) perm[j] = j;
-      const uint64_t unit = (uint64_t)b * nt + t;
-      for (int j = a.n_w - 1; j >= 1; j--) {
-        int r = (int)floor(rng_uniform(a.seed, sweep, kMovePTPerm, unit, (uint64_t)j) * (j + 1));
-        int tmp = perm[j];
-        perm[j] = perm[r];
-        perm[r] = tmp;
-      }
-      wt[t] = perm[i];
+  // walker of pairing i at temperature t: entry i of a uniform permutation of
+  // the walkers (Fisher-Yates from the top: position j swaps with r_j <= j).
+  // Each temperature's thread follows position i back through the swaps
+  // (j = 1, 2, ...) instead of building the whole permutation.
+  for (int t = tid; t < nt; t += block_threads<N>()) {
+    const uint64_t unit = (uint64_t)b * nt + t;
+    int p = i;
+    for (int j = 1; j < a.n_w; j++) {
+      const int r = (int)floor(rng_uniform(a.seed, sweep, kMovePTPerm, unit, (uint64_t)j) * (j + 1));
+      if (p == j)
+        p = r;
+      else if (p == r)
+        p = j;
     }
+    wt[t] = p;
   }
   if (tid == 0) sm.entry = pool_acquire(a);
   for (int t = tid; t < nt; t += block_threads<N>()) hidx[t] = t;
