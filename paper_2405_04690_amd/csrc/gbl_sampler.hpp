@@ -140,6 +140,7 @@ struct BandSmem {
   double su[kMaxSlots][8];  // the band's slot coordinates during the loop
   int32_t ex[kMaxSlots];
   int32_t order[kMaxSlots];
+  int32_t draw[kMaxSlots];  // the slot-order draws of the reversible-jump pass
   int64_t sq[kMaxSlots];    // carrier bin of each slot's cached spectrum
   int entry;                // spectrum pool entry held by the block (-1: none)
   double bcast;
@@ -465,12 +466,17 @@ __global__ __launch_bounds__(block_threads<N>()) void k_sweep_band(Geo g, WaveTa
       __syncthreads();
     }
   } else {
-    // flip every slot once in a random order (Fisher-Yates)
+    // flip every slot once in a random order (Fisher-Yates from the top:
+    // position j swaps with r_j <= j); the draws in parallel, the swaps on one
+    // thread
+    for (int j = tid; j < S; j += block_threads<N>())
+      sm.draw[j] = j ? (int)floor(rng_uniform(a.seed, sweep, move, unit, (uint64_t)j) * (j + 1)) : 0;
+    __syncthreads();
     if (tid == 0) {
       for (int s = 0; s < S; s++) sm.order[s] = s;
       for (int j = S - 1; j >= 1; j--) {
-        int r = (int)floor(rng_uniform(a.seed, sweep, move, unit, (uint64_t)j) * (j + 1));
-        int tmp = sm.order[j];
+        const int r = sm.draw[j];
+        const int tmp = sm.order[j];
         sm.order[j] = sm.order[r];
         sm.order[r] = tmp;
       }
