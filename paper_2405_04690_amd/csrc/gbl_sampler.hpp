@@ -155,15 +155,25 @@ template <int N>
 __device__ __noinline__ void band_template(const Geo& g, const WaveTables<double>& tb, const double* u,
                                            BandSmem<N>& sm) {
   const int tid = threadIdx.x;
-  if (tid == 0) {
-    sm.prm[0] = exp10(u[0]);
-    sm.prm[1] = u[1];
-    sm.prm[2] = u[2];
-    sm.prm[3] = u[3];
-    sm.prm[4] = acos(u[4]);
-    sm.prm[5] = u[5];
-    sm.prm[6] = u[6];
-    sm.prm[7] = asin(u[7]);
+  // sampling -> physical coordinates: the three transcendental maps on lane 0
+  // of different waves, so that they run side by side
+  static_assert(block_threads<N>() >= kWave, "band loops use whole waves");
+  if ((tid & (kWave - 1)) == 0) {
+    for (int r = tid / kWave; r < 4; r += block_threads<N>() / kWave) {
+      if (r == 0) {
+        sm.prm[0] = exp10(u[0]);
+      } else if (r == 1) {
+        sm.prm[4] = acos(u[4]);
+      } else if (r == 2) {
+        sm.prm[7] = asin(u[7]);
+      } else {
+        sm.prm[1] = u[1];
+        sm.prm[2] = u[2];
+        sm.prm[3] = u[3];
+        sm.prm[5] = u[5];
+        sm.prm[6] = u[6];
+      }
+    }
   }
   __syncthreads();
   if (tid < kWave) decode_sources<1>(sm.prm, sm.prm, g, &sm.src);
