@@ -143,7 +143,6 @@ struct BandSmem {
   int32_t draw[kMaxSlots];  // the slot-order draws of the reversible-jump pass
   int64_t sq[kMaxSlots];    // carrier bin of each slot's cached spectrum
   int entry;                // spectrum pool entry held by the block (-1: none)
-  double bcast;
 };
 
 // Build the template of sampling coordinates u (shared) into the FFT workspace;
@@ -181,15 +180,28 @@ __device__ __noinline__ void band_template(const Geo& g, const WaveTables<double
   template_transform<N, 4, double>(sm.src, g, tb, sm.buf, tid);
 }
 
-// sum over the block, broadcast to every thread
-template <int NT>
-__device__ __forceinline__ double block_allsum(double v, double* red, double* bc) {
-  double t = block_sum<NT>(v, red);
-  if (threadIdx.x == 0) *bc = t;
+// sums over the block of K values per thread, returned to every thread: wave
+// sums, then every thread adds the per-wave partials in wave order (red holds
+// K x NT/64 values; the closing barrier frees it for the next reduction)
+template <int NT, int K>
+__device__ __forceinline__ void block_allsum(double (&v)[K], double* red) {
+  constexpr int NW = NT / kWave;
+#pragma unroll
+  for (int k = 0; k < K; k++) v[k] = wave_sum(v[k]);
+  const int w = threadIdx.x / kWave;
+  if ((threadIdx.x & (kWave - 1)) == 0) {
+#pragma unroll
+    for (int k = 0; k < K; k++) red[k * NW + w] = v[k];
+  }
   __syncthreads();
-  double r = *bc;
+#pragma unroll
+  for (int k = 0; k < K; k++) {
+    double t = 0.0;
+#pragma unroll
+    for (int i = 0; i < NW; i++) t += red[k * NW + i];
+    v[k] = t;
+  }
   __syncthreads();
-  return r;
 }
 
 // window += s * (template in the FFT workspace), bins inside the window;
@@ -288,8 +300,10 @@ __device__ __forceinline__ double band_dlogl(const Geo& g, const WaveTables<doub
       acc(k - k0w, cd{-r0.re, -r0.im}, cd{-r1.re, -r1.im});
     }
   }
-  rd = block_allsum<NT>(rd, sm.red, &sm.bcast);
-  dd = block_allsum<NT>(dd, sm.red, &sm.bcast);
+  double sums[2] = {rd, dd};
+  block_allsum<NT>(sums, sm.red);
+  rd = sums[0];
+  dd = sums[1];
   return g.df4 * rd - 0.5 * g.df4 * dd;
 }
 
@@ -612,7 +626,9 @@ __device__ __forceinline__ double band_set_loglike(const Geo& g, const WaveTable
     cd r0 = sm.win[0][i], r1 = sm.win[1][i];
     rr += (r0.re * r0.re + r0.im * r0.im) * sm.wts[0][i] + (r1.re * r1.re + r1.im * r1.im) * sm.wts[1][i];
   }
-  rr = block_allsum<NT>(rr, sm.red, &sm.bcast);
+  double sums[1] = {rr};
+  block_allsum<NT>(sums, sm.red);
+  rr = sums[0];
   return -0.5 * g.df4 * rr;
 }
 
@@ -658,7 +674,9 @@ __device__ __forceinline__ double band_set_loglike_h(const Geo& g, const SweepAr
       rr += (r.re * r.re + r.im * r.im) * ip[c * g.n_bins + k];
     }
   }
-  rr = block_allsum<NT>(rr, sm.red, &sm.bcast);
+  double sums[1] = {rr};
+  block_allsum<NT>(sums, sm.red);
+  rr = sums[0];
   return -0.5 * g.df4 * rr;
 }
 
