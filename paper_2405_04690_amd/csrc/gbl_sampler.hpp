@@ -433,14 +433,27 @@ __global__ __launch_bounds__(block_threads<N>()) void k_sweep_band(Geo g, WaveTa
       const double* uk = sm.su[sk];
       n_prop++;
       if (G <= 0) continue;
-      // friend: the n_friends sorted group entries around the current f0
+      // friend: the n_friends sorted group entries around the current f0.
+      // Lower bound of f0 among the group keys by a 64-way search of each
+      // wave: lane l tests the key at lo + l n / 64, and the ballot (a prefix,
+      // the keys being sorted) narrows [lo, hi] 64-fold per step.
       int lo = 0, hi = G;
-      while (lo < hi) {
-        int mid = (lo + hi) / 2;
-        if (grp[8 * mid + 1] < uk[1])
-          lo = mid + 1;
-        else
-          hi = mid;
+      {
+        const int lane = tid & (kWave - 1);
+        while (lo < hi) {
+          const int n = hi - lo;
+          const int pl = n >= kWave ? lo + (int)(((int64_t)lane * n) / kWave) : lo + lane;
+          const bool less = (n >= kWave || lane < n) && grp[8 * (int64_t)pl + 1] < uk[1];
+          const int c = __popcll(__ballot(less));
+          if (n < kWave) {
+            lo += c;
+            break;
+          }
+          if (c == 0) break;  // key[lo] >= f0
+          const int lo2 = lo + (int)(((int64_t)(c - 1) * n) / kWave) + 1;
+          hi = c < kWave ? lo + (int)(((int64_t)c * n) / kWave) : hi;
+          lo = lo2;
+        }
       }
       const int nf = a.n_friends < G ? a.n_friends : G;
       int start = lo - nf / 2;
