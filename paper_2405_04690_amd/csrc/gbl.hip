@@ -512,11 +512,8 @@ extern "C" int gb_psd_eval(gbl_ctx* ctx, const double* noise, int64_t P, int32_t
   if (psd_flags & ~GBL_PSD_INVERSE) return fail(ctx, GBL_EINVAL, "gb_psd_eval: unknown psd flag%s");
   if (P == 0) return GBL_OK;
   if (!noise || !S) return fail(ctx, GBL_EINVAL, "gb_psd_eval: null pointer%s");
-  int64_t total = P * 2 * ctx->geo.n_bins;
-  int64_t blocks = (total + 255) / 256;
-  if (blocks > 65536) blocks = 65536;
-  hipLaunchKernelGGL(gbl::k_psd_eval, dim3((unsigned)blocks), dim3(256), 0, ctx->stream, ctx->geo.n_bins,
-                     ctx->psd_P1, ctx->psd_P2, noise, P, (psd_flags & GBL_PSD_INVERSE) ? 1 : 0, S);
+  hipLaunchKernelGGL(gbl::k_psd_eval, gbl::row_grid(ctx->geo.n_bins, 2 * P), dim3(256), 0, ctx->stream,
+                     ctx->geo.n_bins, ctx->psd_P1, ctx->psd_P2, noise, P, (psd_flags & GBL_PSD_INVERSE) ? 1 : 0, S);
   return check_launch(ctx, "gb_psd_eval");
 }
 
@@ -1029,8 +1026,8 @@ extern "C" int gb_psd_sweep_step(gbl_ctx* ctx, const gbl_psd_sweep_config* c, co
   p.stats = (unsigned long long*)st->stats;
   cd* full = (cd*)st->full_resid;
   // 1. full residuals, 2. current log-likelihoods
-  hipLaunchKernelGGL(gbl::k_psd_full_resid, dim3(4096), dim3(256), 0, ctx->stream, nb, nw, (const cd*)st->resid,
-                     (const cd*)st->data, full);
+  hipLaunchKernelGGL(gbl::k_psd_full_resid, gbl::row_grid(nb, 2 * (int64_t)nw), dim3(256), 0, ctx->stream, nb, nw,
+                     (const cd*)st->resid, (const cd*)st->data, full);
   const int n_all = nt * nw, n_half = nt * half;
   hipLaunchKernelGGL(gbl::k_psd_res_idx, dim3((n_all + 255) / 256), dim3(256), 0, ctx->stream, nt, nw, -1,
                      st->res_idx);
@@ -1050,8 +1047,8 @@ extern "C" int gb_psd_sweep_step(gbl_ctx* ctx, const gbl_psd_sweep_config* c, co
   }
   // 4. vertical swaps, 5. the cold chain's 1/S
   hipLaunchKernelGGL(gbl::k_psd_swap, dim3((nw + 63) / 64), dim3(64), 0, ctx->stream, p);
-  hipLaunchKernelGGL(gbl::k_psd_eval, dim3(2048), dim3(256), 0, ctx->stream, nb, ctx->psd_P1, ctx->psd_P2,
-                     (const double*)st->theta, (int64_t)nw, 1, st->inv_psd);
+  hipLaunchKernelGGL(gbl::k_psd_eval, gbl::row_grid(nb, 2 * (int64_t)nw), dim3(256), 0, ctx->stream, nb,
+                     ctx->psd_P1, ctx->psd_P2, (const double*)st->theta, (int64_t)nw, 1, st->inv_psd);
   return check_launch(ctx, "gb_psd_sweep_step");
 }
 

@@ -523,16 +523,23 @@ __global__ __launch_bounds__(block_threads<N>()) void k_scatter_add(Geo g, WaveT
 // ---------------------------------------------------------------------------
 // PSD evaluation and the noise-parameter log-likelihood
 // ---------------------------------------------------------------------------
+// rows pc = p * 2 + c over blockIdx.y, bins over blockIdx.x (both grid-stride)
 __global__ void k_psd_eval(int64_t nb, const double* __restrict__ P1, const double* __restrict__ P2,
                            const double* __restrict__ noise, int64_t P, int inverse, double* __restrict__ S) {
-  int64_t total = P * 2 * nb;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
-    int64_t k = i % nb;
-    int64_t pc = i / nb;  // p * 2 + c
-    double so = noise[2 * pc], sa = noise[2 * pc + 1];
-    double v = so * so * P1[k] + sa * sa * P2[k];
-    S[i] = inverse ? 1.0 / v : v;
+  for (int64_t pc = blockIdx.y; pc < 2 * P; pc += gridDim.y) {
+    const double so = noise[2 * pc], sa = noise[2 * pc + 1];
+    double* Sr = S + pc * nb;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < nb; k += (int64_t)gridDim.x * blockDim.x) {
+      const double v = so * so * P1[k] + sa * sa * P2[k];
+      Sr[k] = inverse ? 1.0 / v : v;
+    }
   }
+}
+
+// grid of the row kernels: bins of a row over x, rows over y
+__host__ inline dim3 row_grid(int64_t n, int64_t rows) {
+  const int64_t bx = (n + 255) / 256, cap = 1024;
+  return dim3((unsigned)(bx < cap ? (bx > 0 ? bx : 1) : cap), (unsigned)(rows < cap ? (rows > 0 ? rows : 1) : cap));
 }
 
 constexpr int kPsdChunks = 256;

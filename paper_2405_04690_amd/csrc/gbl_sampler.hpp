@@ -956,13 +956,17 @@ struct PsdArgs {
   unsigned long long* stats;
 };
 
-// full residual of walker w: buffer 0 + buffer 1 - data
+// full residual of walker w: buffer 0 + buffer 1 - data; rows r = w * 2 + c
+// over blockIdx.y, bins over blockIdx.x (both grid-stride)
 __global__ void k_psd_full_resid(int64_t nb, int nw, const cd* __restrict__ resid, const cd* __restrict__ data,
                                  cd* __restrict__ out) {
   const int64_t total = (int64_t)nw * 2 * nb;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t ck = i % (2 * nb);
-    out[i] = resid[i] + resid[total + i] - data[ck];
+  for (int64_t r = blockIdx.y; r < 2 * (int64_t)nw; r += gridDim.y) {
+    const cd* dr = data + (r & 1) * nb;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < nb; k += (int64_t)gridDim.x * blockDim.x) {
+      const int64_t i = r * nb + k;
+      out[i] = resid[i] + resid[total + i] - dr[k];
+    }
   }
 }
 
