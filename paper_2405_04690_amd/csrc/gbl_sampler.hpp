@@ -139,8 +139,9 @@ struct BandSmem {
   Src src;
   double su[kMaxSlots][8];  // the band's slot coordinates during the loop
   int32_t ex[kMaxSlots];
-  int32_t order[kMaxSlots];
-  int32_t draw[kMaxSlots];  // the slot-order draws of the reversible-jump pass
+  int32_t order[kMaxSlots];  // RJ: the slots' flip order; in-model: the occupied slots
+  int32_t draw[kMaxSlots];   // the slot-order draws of the reversible-jump pass
+  int n_occ;                 // in-model: number of occupied slots
   int64_t sq[kMaxSlots];    // carrier bin of each slot's cached spectrum
   int entry;                // spectrum pool entry held by the block (-1: none)
 };
@@ -412,24 +413,22 @@ __global__ __launch_bounds__(block_threads<N>()) void k_sweep_band(Geo g, WaveTa
   if (move == kMoveInModel) {
     const double* grp = a.group + (int64_t)b * a.n_w * S * 8;
     const int G = a.group_count[b];
+    // the occupied slots in slot order (in-model moves keep the occupancy)
+    if (tid == 0) {
+      int c = 0;
+      for (int s = 0; s < S; s++)
+        if (sm.ex[s]) sm.order[c++] = s;
+      sm.n_occ = c;
+    }
+    __syncthreads();
+    const int gcount = sm.n_occ;
     for (int p = 0; p < a.n_prop; p++) {
       const double r_pick = rng_uniform(a.seed, sweep, move, unit, 8 * (uint64_t)p + 0);
       const double r_friend = rng_uniform(a.seed, sweep, move, unit, 8 * (uint64_t)p + 1);
       const double r_z = rng_uniform(a.seed, sweep, move, unit, 8 * (uint64_t)p + 2);
       const double r_acc = rng_uniform(a.seed, sweep, move, unit, 8 * (uint64_t)p + 3);
-      int gcount = 0;
-      for (int s = 0; s < S; s++) gcount += sm.ex[s] != 0;
       if (gcount == 0) continue;
-      const int pick = (int)floor(r_pick * gcount);
-      int sk = -1;
-      for (int s = 0, c = 0; s < S; s++)
-        if (sm.ex[s]) {
-          if (c == pick) {
-            sk = s;
-            break;
-          }
-          c++;
-        }
+      const int sk = sm.order[(int)floor(r_pick * gcount)];
       const double* uk = sm.su[sk];
       n_prop++;
       if (G <= 0) continue;
