@@ -627,9 +627,12 @@ __device__ __forceinline__ double band_set_loglike(const Geo& g, const WaveTable
                                                    int t, int w_src, int b, int w_res, int64_t k0w,
                                                    BandSmem<N>& sm) {
   constexpr int NT = block_threads<N>();
+  // the set's occupancy flags into LDS in parallel (the window load's barrier
+  // covers them)
+  for (int s = threadIdx.x; s < a.n_slot; s += NT) sm.ex[s] = a.exists[uidx(a, t, w_src, b, s)];
   band_load_window<N>(g, a, w_res, b, k0w, sm);
   for (int s = 0; s < a.n_slot; s++) {
-    if (!a.exists[uidx(a, t, w_src, b, s)]) continue;
+    if (!sm.ex[s]) continue;
     band_template<N>(g, tb, a.u + 8 * uidx(a, t, w_src, b, s), sm);
     band_add_template<N>(g, tb, sm, k0w, -1.0, nullptr);
   }
@@ -651,9 +654,10 @@ __device__ __forceinline__ void band_set_sum(const Geo& g, const WaveTables<doub
                                              int w_src, int b, int64_t k0w, BandSmem<N>& sm, cd* H) {
   constexpr int NT = block_threads<N>();
   for (int i = threadIdx.x; i < 6 * N; i += NT) H[i] = cd{0.0, 0.0};
+  for (int s = threadIdx.x; s < a.n_slot; s += NT) sm.ex[s] = a.exists[uidx(a, t, w_src, b, s)];
   __syncthreads();
   for (int s = 0; s < a.n_slot; s++) {
-    if (!a.exists[uidx(a, t, w_src, b, s)]) continue;
+    if (!sm.ex[s]) continue;
     band_template<N>(g, tb, a.u + 8 * uidx(a, t, w_src, b, s), sm);
     const int64_t ks = sm.src.q - N / 2;
     for (int j = threadIdx.x; j < N; j += NT) {
