@@ -141,6 +141,7 @@ struct BandSmem {
   int32_t ex[kMaxSlots];
   int32_t order[kMaxSlots];  // RJ: the slots' flip order; in-model: the occupied slots
   int32_t draw[kMaxSlots];   // the slot-order draws of the reversible-jump pass
+  double rdraw[kMaxSlots][9];  // RJ, per flip: acceptance draw, prior birth's coordinates
   int n_occ;                 // in-model: number of occupied slots
   int64_t sq[kMaxSlots];    // carrier bin of each slot's cached spectrum
   int entry;                // spectrum pool entry held by the block (-1: none)
@@ -517,14 +518,19 @@ __global__ __launch_bounds__(block_threads<N>()) void k_sweep_band(Geo g, WaveTa
         sm.order[r] = tmp;
       }
     }
+    // every flip's uniform draws (words 64 + 16 i + k: k = 0 acceptance,
+    // k = 1..8 a prior birth's coordinates) one per thread ahead of the loop
+    for (int q = tid; q < S * 9; q += block_threads<N>()) {
+      const int i = q / 9, k = q - 9 * (q / 9);
+      sm.rdraw[i][k] = rng_uniform(a.seed, sweep, move, unit, 64 + 16 * (uint64_t)i + k);
+    }
     __syncthreads();
     double flo, fhi;
     band_f0_range<N>(g, a, b, flo, fhi);
     const double lvol = a.prop_u ? log_box_volume<N>(g, a, b) : 0.0;
     for (int i = 0; i < S; i++) {
       const int s = sm.order[i];
-      const uint64_t base = 64 + 16 * (uint64_t)i;
-      const double r_acc = rng_uniform(a.seed, sweep, move, unit, base);
+      const double r_acc = sm.rdraw[i][0];
       const int64_t ui = uidx(a, t, w, b, s);
       double* us = sm.su[s];
       if (sm.ex[s]) {
@@ -573,7 +579,7 @@ __global__ __launch_bounds__(block_threads<N>()) void k_sweep_band(Geo g, WaveTa
         n_bprop++;
         if (tid < 8) {
           const int k = tid;
-          double r = rng_uniform(a.seed, sweep, move, unit, base + 1 + k);
+          const double r = sm.rdraw[i][1 + k];
           double lo = a.lo[k], hi = a.hi[k];
           if (k == 1) {
             lo = flo;
