@@ -21,6 +21,7 @@
 namespace gbl {
 
 constexpr int kMaxSlots = 64;
+static_assert((kMaxSlots & (kMaxSlots - 1)) == 0, "slot and draw rows are indexed with a mask");
 
 // ---------------------------------------------------------------------------
 // Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11) from its definition.
@@ -141,7 +142,8 @@ struct BandSmem {
   int32_t ex[kMaxSlots];
   int32_t order[kMaxSlots];  // RJ: the slots' flip order; in-model: the occupied slots
   int32_t draw[kMaxSlots];   // the slot-order draws of the reversible-jump pass
-  double rdraw[kMaxSlots][9];  // RJ, per flip: acceptance draw, prior birth's coordinates
+  double rdraw[kMaxSlots][9];  // RJ, per flip: acceptance draw, prior birth's coordinates;
+                               // in-model, per proposal: its four draws
   int n_occ;                 // in-model: number of occupied slots
   int64_t sq[kMaxSlots];    // carrier bin of each slot's cached spectrum
   int entry;                // spectrum pool entry held by the block (-1: none)
@@ -424,10 +426,17 @@ __global__ __launch_bounds__(block_threads<N>()) void k_sweep_band(Geo g, WaveTa
     __syncthreads();
     const int gcount = sm.n_occ;
     for (int p = 0; p < a.n_prop; p++) {
-      const double r_pick = rng_uniform(a.seed, sweep, move, unit, 8 * (uint64_t)p + 0);
-      const double r_friend = rng_uniform(a.seed, sweep, move, unit, 8 * (uint64_t)p + 1);
-      const double r_z = rng_uniform(a.seed, sweep, move, unit, 8 * (uint64_t)p + 2);
-      const double r_acc = rng_uniform(a.seed, sweep, move, unit, 8 * (uint64_t)p + 3);
+      if ((p & (kMaxSlots - 1)) == 0) {
+        // the next kMaxSlots proposals' four draws (words 8 p + k), one per
+        // thread, into the RJ draw rows (free during in-model moves)
+        const int pe = a.n_prop - p < kMaxSlots ? a.n_prop - p : kMaxSlots;
+        __syncthreads();
+        for (int q = tid; q < 4 * pe; q += block_threads<N>())
+          sm.rdraw[q >> 2][q & 3] = rng_uniform(a.seed, sweep, move, unit, 8 * (uint64_t)(p + (q >> 2)) + (q & 3));
+        __syncthreads();
+      }
+      const double* rp = sm.rdraw[p & (kMaxSlots - 1)];
+      const double r_pick = rp[0], r_friend = rp[1], r_z = rp[2], r_acc = rp[3];
       if (gcount == 0) continue;
       const int sk = sm.order[(int)floor(r_pick * gcount)];
       const double* uk = sm.su[sk];
