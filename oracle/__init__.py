@@ -96,6 +96,11 @@ def _load():
             "gblo_sweep_step": (ctypes.c_int, [C, ctypes.POINTER(SweepConfig), ctypes.c_int, ctypes.c_int,
                                                ctypes.c_int64, D, I32, D, D, D, D, I32, I64, D, D, D]),
             "gblo_sweep_group": (ctypes.c_int, [ctypes.POINTER(SweepConfig), D, I32, D, I32]),
+            "gblo_stretch_propose": (ctypes.c_int, [ctypes.POINTER(SweepConfig), D, D, ctypes.c_int, ctypes.c_double,
+                                                    ctypes.c_double, D, D]),
+            "gblo_in_prior": (ctypes.c_int, [C, ctypes.POINTER(SweepConfig), ctypes.c_int, D]),
+            "gblo_band_loglike": (ctypes.c_double, [C, ctypes.POINTER(SweepConfig), ctypes.c_int, ctypes.c_int,
+                                                    ctypes.c_int, ctypes.c_int, D, I32, D, D]),
             "gblo_psd_sweep_step": (ctypes.c_int, [C, ctypes.POINTER(PsdSweepConfig), ctypes.c_int64, D, D, D, D, D,
                                                    D, I64]),
         }
@@ -303,6 +308,31 @@ def sweep_step(orc: "Oracle", sc: SweepConfig, st: SweepState, move: int, parity
 def sweep_group(sc: SweepConfig, st: SweepState):
     rc = _load().gblo_sweep_group(ctypes.byref(sc), _d(st.u), _i32(st.exists), _d(st.group), _i32(st.group_count))
     _check(rc, "sweep_group")
+
+
+def stretch_propose(sc: SweepConfig, u, group, uf: float, uz: float):
+    """Group-stretch proposal from u with friend uniform uf and stretch uniform uz
+    against the sorted group [G][8]: (ok, u_new, ln proposal factor)."""
+    u = _f64(u)
+    group = _f64(group).reshape(-1, 8)
+    un = np.zeros(8)
+    lr = np.zeros(1)
+    ok = _load().gblo_stretch_propose(ctypes.byref(sc), _d(u), _d(group), group.shape[0], float(uf), float(uz),
+                                      _d(un), _d(lr))
+    return bool(ok), un, float(lr[0])
+
+
+def in_prior(orc: "Oracle", sc: SweepConfig, b: int, u) -> bool:
+    u = _f64(u)
+    return bool(orc.lib.gblo_in_prior(ctypes.byref(orc.cfg), ctypes.byref(sc), int(b), _d(u)))
+
+
+def band_loglike(orc: "Oracle", sc: SweepConfig, st: SweepState, t: int, w_src: int, b: int, w_res: int) -> float:
+    """-1/2 <r'|r'> over the window of band b: r' = walker w_res's opposite-parity
+    cold-chain buffer minus the sources of (t, w_src, b) (Alg. gb2)."""
+    return float(orc.lib.gblo_band_loglike(ctypes.byref(orc.cfg), ctypes.byref(sc), int(t), int(w_src), int(b),
+                                           int(w_res), _d(st.u), _i32(st.exists), _d(st.resid.view(np.float64)),
+                                           _d(st.inv_psd)))
 
 
 def sweep_full(orc: "Oracle", sc: SweepConfig, st: SweepState, sweep: int):

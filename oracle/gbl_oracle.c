@@ -587,7 +587,9 @@ double gblo_rng_uniform(uint64_t seed, int64_t sweep, int move, uint64_t unit, u
  *    the friend X drawn uniformly from the n_friends entries of the band's
  *    stationary group (cold-chain sources of all walkers, sorted by f0) that
  *    surround the current f0; proposal factor z^(d-1), d = 8; periodic
- *    differences are taken on the circle and the result wrapped;
+ *    differences are taken on the circle and the result wrapped, and a
+ *    proposal whose stretched periodic difference reaches half a period is
+ *    rejected (beyond it the reverse move would not return);
  *  - reversible jump: every slot is flipped once per RJ step, in random order
  *    (birth from the prior: q = p, so the prior/proposal ratio is 1);
  *  - only the likelihood is tempered: accept iff ln u < beta dlnL + ln(prior
@@ -734,17 +736,32 @@ static int stretch_propose(const gblo_sweep_config* sc, const double* u, const d
   const double* X = group + 8 * j;
   double a = sc->stretch_a;
   double z = ((a - 1.0) * uz + 1.0) * ((a - 1.0) * uz + 1.0) / a;
+  int reversible = 1;
   for (int i = 0; i < 8; i++) {
     double diff = u[i] - X[i];
     if (PERIOD[i] > 0) {
+      /* shortest signed difference on the circle, in (-P/2, P/2]; the move
+       * is reversible (same friend, 1/z) only while z * diff stays inside
+       * (-P/2, P/2), so a proposal beyond that is rejected */
       diff = wrap(diff + 0.5 * PERIOD[i], PERIOD[i]) - 0.5 * PERIOD[i];
+      if (!(fabs(z * diff) < 0.5 * PERIOD[i])) reversible = 0;
       u_new[i] = wrap(X[i] + z * diff, PERIOD[i]);
     } else {
       u_new[i] = X[i] + z * diff;
     }
   }
   *log_ratio = 7.0 * log(z);
-  return 1;
+  return reversible;
+}
+
+/* the stretch proposal and the prior box on their own (for the tests) */
+int gblo_stretch_propose(const gblo_sweep_config* sc, const double* u, const double* group, int G, double uf,
+                         double uz, double* u_new, double* log_ratio) {
+  return stretch_propose(sc, u, group, G, uf, uz, u_new, log_ratio);
+}
+
+int gblo_in_prior(const gblo_config* cfg, const gblo_sweep_config* sc, int b, const double* u) {
+  return in_prior(cfg, sc, b, u);
 }
 
 /* state layout: u [n_t][n_w][n_b][n_slot][8], exists [n_t][n_w][n_b][n_slot],
@@ -939,6 +956,11 @@ static double band_loglike(const gblo_config* cfg, const gblo_sweep_config* sc, 
   free(win.r[0]);
   free(win.r[1]);
   return -0.5 * 4.0 / cfg->T * rr;
+}
+
+double gblo_band_loglike(const gblo_config* cfg, const gblo_sweep_config* sc, int t, int w_src, int b, int w_res,
+                         const double* u, const int32_t* exists, const double* resid, const double* inv_psd) {
+  return band_loglike(cfg, sc, t, w_src, b, w_res, u, exists, resid, inv_psd);
 }
 
 /* walker permutation of temperature t in band b (Fisher-Yates) */

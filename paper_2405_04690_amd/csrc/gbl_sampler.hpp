@@ -471,19 +471,27 @@ __global__ __launch_bounds__(block_threads<N>()) void k_sweep_band(Geo g, WaveTa
       const double* X = grp + 8 * (start + (int)floor(r_friend * nf));
       const double am = a.stretch_a;
       const double z = ((am - 1.0) * r_z + 1.0) * ((am - 1.0) * r_z + 1.0) / am;
+      // periodic angles move on the circle: the difference to the friend is
+      // taken in (-P/2, P/2] and the stretched difference must stay inside
+      // (-P/2, P/2), so that the reverse move (same friend, 1/z) returns to
+      // the start; otherwise the proposal is rejected (the pair of moves is
+      // then an exact involution with Jacobian z^8)
       double un[8];
+      bool reversible = true;
 #pragma unroll
       for (int i = 0; i < 8; i++) {
         double diff = uk[i] - X[i];
         double P = period_of(i);
         if (P > 0) {
           diff = wrap_p(diff + 0.5 * P, P) - 0.5 * P;
-          un[i] = wrap_p(X[i] + z * diff, P);
+          const double zd = z * diff;
+          if (!(fabs(zd) < 0.5 * P)) reversible = false;
+          un[i] = wrap_p(X[i] + zd, P);
         } else {
           un[i] = X[i] + z * diff;
         }
       }
-      if (!in_prior<N>(g, a, b, un)) continue;
+      if (!reversible || !in_prior<N>(g, a, b, un)) continue;
       const double lr = 7.0 * log(z);
       if (tid < 8) {
         sm.u_old[tid] = uk[tid];

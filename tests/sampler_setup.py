@@ -59,7 +59,19 @@ def problem(n_t=3, n_w=4, n_b=6, n_slots=4, n_prop=6, n_friends=4, group_every=1
                         orc.scatter_add(_phys(st.u[0, w, b, s])[None], N, -1.0, st.resid[par, w])
     ladder = np.geomspace(1.0, beta_top, n_t) if n_t > 1 else np.ones(1)
     st.betas[:] = ladder[None, :]
+    st.data = data
     return cfg, orc, sc, st
+
+
+def rebuild_buffer(orc, sc, st, par, w):
+    """parity-par cold-chain buffer of walker w from scratch: the data minus
+    every cold-chain (t = 0) source of the bands with b % 2 == par"""
+    buf = st.data.copy()
+    for b in range(par, sc.n_bands, 2):
+        for s in range(sc.n_slots):
+            if st.exists[0, w, b, s]:
+                orc.scatter_add(_phys(st.u[0, w, b, s])[None], sc.N, -1.0, buf)
+    return buf
 
 
 def _phys(u):

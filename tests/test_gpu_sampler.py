@@ -100,45 +100,42 @@ def test_sweep_run_and_graph_replay():
 
 def test_inmodel_moves_keep_the_prior_at_zero_inverse_temperature():
     """beta = 0: the group-stretch chain must leave the uniform prior of the
-    occupied slots invariant (marginals stay uniform over the prior box).
-    Periodic angles are left out: the wrapped stretch is only approximately
-    reversible on a circle."""
-    cfg, orc, sc, st = sampler_setup.problem(n_t=1, n_w=16, n_b=4, n_slots=4, n_prop=8, n_friends=8, seed=9)
+    occupied slots invariant on all eight coordinates, the periodic angles
+    included.  3072 independent slot chains, a fixed group no larger than
+    n_friends (so that the friend window does not depend on the current f0),
+    one final snapshot after 40 sweeps."""
+    from scipy import stats as sps
+    cfg, orc, sc, st = sampler_setup.problem(n_t=64, n_w=4, n_b=4, n_slots=3, n_prop=6, n_friends=16, seed=9)
     rng = np.random.default_rng(2)
     lo = np.array(list(sc.prior_lo))
     hi = np.array(list(sc.prior_hi))
+    boxes = []
     for b in range(sc.n_bands):
-        flo = (sc.k_band0 + (b - 0.5) * sc.N) / cfg.T
-        fhi = (sc.k_band0 + (b + 1.5) * sc.N) / cfg.T
-        n = st.u[:, :, b].shape[:-1]
-        draw = rng.uniform(size=n + (8,))
-        box_lo = lo.copy(); box_hi = hi.copy()
-        box_lo[1], box_hi[1] = flo, fhi
+        box_lo, box_hi = lo.copy(), hi.copy()
+        box_lo[1] = (sc.k_band0 + (b - 0.5) * sc.N) / cfg.T
+        box_hi[1] = (sc.k_band0 + (b + 1.5) * sc.N) / cfg.T
         for k, P in ((3, 2 * np.pi), (5, np.pi), (6, 2 * np.pi)):
             box_lo[k], box_hi[k] = 0.0, P
-        st.u[:, :, b] = box_lo + (box_hi - box_lo) * draw
+        boxes.append((box_lo, box_hi))
+        st.u[:, :, b] = box_lo + (box_hi - box_lo) * rng.uniform(size=st.u[:, :, b].shape)
     st.exists[:] = 1
     st.betas[:] = 0.0
     ctx, sw = _gpu_sweep(cfg, sc, st)
     sw.group_refresh()
-    for it in range(60):
+    for it in range(40):
         sw.step(0, 1)
         sw.step(0, 0)
         sw.advance()
-        if it % 5 == 4:
-            sw.group_refresh()
     torch.cuda.synchronize()
-    u = sw.u.cpu().numpy()[0]
+    assert int(sw.group_count.max().item()) <= sc.n_friends
+    u = sw.u.cpu().numpy()
     stats = sw.stats.cpu().numpy()
-    assert stats[1] > 0.2 * stats[0]
-    from scipy import stats as sps
-    for b in range(sc.n_bands):
-        flo = (sc.k_band0 + (b - 0.5) * sc.N) / cfg.T
-        fhi = (sc.k_band0 + (b + 1.5) * sc.N) / cfg.T
-        for k, (a0, a1) in ((0, (lo[0], hi[0])), (1, (flo, fhi)), (4, (-1, 1)), (7, (-1, 1))):
-            x = (u[:, b, :, k].ravel() - a0) / (a1 - a0)
-            p = sps.kstest(x, "uniform").pvalue
-            assert p > 1e-4, (b, k, p)
+    assert stats[1] > 0.1 * stats[0]
+    x = np.concatenate([(u[:, :, b].reshape(-1, 8) - boxes[b][0]) / (boxes[b][1] - boxes[b][0])
+                        for b in range(sc.n_bands)])
+    for k in range(8):
+        p = sps.kstest(x[:, k], "uniform").pvalue
+        assert p > 1e-3, (k, p)
     ctx.close()
 
 
