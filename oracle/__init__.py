@@ -53,9 +53,11 @@ MOVE_PSD, MOVE_PSDPT = 4, 5
 
 
 class PsdSweepConfig(ctypes.Structure):
-    """Noise-PSD step configuration (field order of gblo_psd_sweep_config)."""
-    _fields_ = [("n_tn", ctypes.c_int32), ("n_walkers", ctypes.c_int32), ("stretch_a", ctypes.c_double),
-                ("seed", ctypes.c_uint64), ("prior_lo", ctypes.c_double * 4), ("prior_hi", ctypes.c_double * 4)]
+    """Noise-PSD step configuration (field order of gblo_psd_sweep_config);
+    n_par = 4 (instrument noise) or 9 (with the Galactic foreground)."""
+    _fields_ = [("n_tn", ctypes.c_int32), ("n_walkers", ctypes.c_int32), ("n_par", ctypes.c_int32),
+                ("stretch_a", ctypes.c_double), ("seed", ctypes.c_uint64), ("prior_lo", ctypes.c_double * 9),
+                ("prior_hi", ctypes.c_double * 9)]
 
 
 _lib = None
@@ -82,6 +84,13 @@ def _load():
             "gblo_waveform": (ctypes.c_int, [C, D, ctypes.c_int64, ctypes.c_int, D, D, D, I64]),
             "gblo_psd_value": (ctypes.c_double, [C, ctypes.c_double, ctypes.c_double, ctypes.c_double]),
             "gblo_psd_eval": (ctypes.c_int, [C, D, ctypes.c_int64, D]),
+            "gblo_psd_eval_n": (ctypes.c_int, [C, D, ctypes.c_int32, ctypes.c_int64, D]),
+            "gblo_foreground_value": (ctypes.c_double, [C, ctypes.c_double, D]),
+            "gblo_psd_loglike_n": (ctypes.c_int, [C, D, ctypes.c_int32, D, ctypes.c_int32, I32, ctypes.c_int64, D]),
+            "gblo_inner": (ctypes.c_int, [C, D, D, I64, ctypes.c_int32, D, ctypes.c_int32, D, ctypes.c_int32,
+                                          ctypes.c_int32, I32, I32, ctypes.c_int64, D]),
+            "gblo_snr": (ctypes.c_int, [C, D, ctypes.c_int64, ctypes.c_int32, D, ctypes.c_int32, ctypes.c_int32, I32,
+                                        D, ctypes.c_int32, I32, D, D]),
             "gblo_loglike": (ctypes.c_double, [C, D, D]),
             "gblo_psd_loglike": (ctypes.c_int, [C, D, ctypes.c_int32, D, I32, ctypes.c_int64, D]),
             "gblo_delta_loglike": (ctypes.c_int, [C, D, ctypes.c_int32, D, ctypes.c_int32, ctypes.c_int32, D, D,
@@ -201,6 +210,65 @@ class Oracle:
         S = np.zeros((P, 2, self.n_bins))
         _check(self.lib.gblo_psd_eval(ctypes.byref(self.cfg), _d(noise), P, _d(S)), "psd_eval")
         return S
+
+    def foreground_value(self, f: float, fg) -> float:
+        fg = _f64(fg)
+        return float(self.lib.gblo_foreground_value(ctypes.byref(self.cfg), float(f), _d(fg)))
+
+    def psd_eval_n(self, noise, n_par: int) -> np.ndarray:
+        """S [P][2][n_bins] for noise sets of 4 or 9 (with the foreground) parameters"""
+        noise = _f64(noise).reshape(-1, n_par)
+        P = noise.shape[0]
+        S = np.zeros((P, 2, self.n_bins))
+        _check(self.lib.gblo_psd_eval_n(ctypes.byref(self.cfg), _d(noise), int(n_par), P, _d(S)), "psd_eval_n")
+        return S
+
+    def psd_loglike_n(self, residual, noise, n_par: int, res_idx) -> np.ndarray:
+        residual = np.ascontiguousarray(residual, dtype=np.complex128).reshape(-1, 2, self.n_bins)
+        noise = _f64(noise).reshape(-1, n_par)
+        res_idx = np.ascontiguousarray(res_idx, dtype=np.int32)
+        out = np.zeros(noise.shape[0])
+        rc = self.lib.gblo_psd_loglike_n(ctypes.byref(self.cfg), _d(residual.view(np.float64)), residual.shape[0],
+                                         _d(noise), int(n_par), _i32(res_idx), noise.shape[0], _d(out))
+        _check(rc, "psd_loglike_n")
+        return out
+
+    def inner(self, A, E, start_bin, residual, psd, res_idx=None, psd_idx=None, psd_is_inverse=False):
+        """[B][2] = (<h|h>, <R|h>) of stored slices A, E [B][N] starting at start_bin [B]"""
+        A = np.ascontiguousarray(A, np.complex128)
+        E = np.ascontiguousarray(E, np.complex128)
+        B, N = A.shape
+        sb = np.ascontiguousarray(start_bin, np.int64)
+        residual = np.ascontiguousarray(residual, dtype=np.complex128).reshape(-1, 2, self.n_bins)
+        psd = _f64(psd).reshape(-1, 2, self.n_bins)
+        res_idx = np.zeros(B, np.int32) if res_idx is None else np.ascontiguousarray(res_idx, np.int32)
+        psd_idx = np.zeros(B, np.int32) if psd_idx is None else np.ascontiguousarray(psd_idx, np.int32)
+        out = np.zeros((B, 2))
+        rc = self.lib.gblo_inner(ctypes.byref(self.cfg), _d(A.view(np.float64)), _d(E.view(np.float64)), _i64(sb),
+                                 int(N), _d(residual.view(np.float64)), residual.shape[0], _d(psd), psd.shape[0],
+                                 int(bool(psd_is_inverse)), _i32(res_idx), _i32(psd_idx), B, _d(out))
+        _check(rc, "inner")
+        return out
+
+    def snr(self, params, N: int, psd, psd_idx=None, data=None, data_idx=None, psd_is_inverse=False):
+        """(optimal SNR [B], observed SNR [B] or None)"""
+        params = _f64(params).reshape(-1, 8)
+        B = params.shape[0]
+        psd = _f64(psd).reshape(-1, 2, self.n_bins)
+        psd_idx = np.zeros(B, np.int32) if psd_idx is None else np.ascontiguousarray(psd_idx, np.int32)
+        opt = np.zeros(B)
+        obs = np.zeros(B) if data is not None else None
+        if data is not None:
+            data = np.ascontiguousarray(data, dtype=np.complex128).reshape(-1, 2, self.n_bins)
+            data_idx = np.zeros(B, np.int32) if data_idx is None else np.ascontiguousarray(data_idx, np.int32)
+        rc = self.lib.gblo_snr(ctypes.byref(self.cfg), _d(params), B, int(N), _d(psd), psd.shape[0],
+                               int(bool(psd_is_inverse)), _i32(psd_idx),
+                               _d(data.view(np.float64)) if data is not None else None,
+                               data.shape[0] if data is not None else 0,
+                               _i32(data_idx) if data is not None else None, _d(opt),
+                               _d(obs) if obs is not None else None)
+        _check(rc, "snr")
+        return opt, obs
 
     def loglike(self, R, S) -> float:
         R = np.ascontiguousarray(R, dtype=np.complex128).reshape(2, self.n_bins)
@@ -347,7 +415,7 @@ def sweep_full(orc: "Oracle", sc: SweepConfig, st: SweepState, sweep: int):
 
 def psd_sweep_step(orc: "Oracle", pc: PsdSweepConfig, sweep: int, theta, logl, betas, data, resid, inv_psd, stats):
     """Noise-PSD step (stretch moves with vertical tempering) on host arrays, in place:
-    theta [n_tn][n_w][4], logl [n_tn][n_w], betas [n_tn], data [2][n_bins] complex,
+    theta [n_tn][n_w][n_par], logl [n_tn][n_w], betas [n_tn], data [2][n_bins] complex,
     resid [2][n_w][2][n_bins] complex (the sweep's cold-chain buffers), inv_psd [n_w][2][n_bins],
     stats [4]."""
     data = np.ascontiguousarray(data, np.complex128)

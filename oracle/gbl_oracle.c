@@ -382,6 +382,42 @@ int gblo_psd_eval(const gblo_config* cfg, const double* noise, int64_t P, double
 }
 
 /* ------------------------------------------------------------------------ */
+/* Galactic foreground (Sec. 3, "Galactic foreground noise                  */
+/* parameterization"): the confusion-noise strain sensitivity               */
+/*   h_fg(f) = 1/2 A_fg f^(-7/3) exp(-s1 f^alpha) [1 + tanh(-s2 (f - f_k))]  */
+/* enters the A and E PSD as S_fg = 6 x^2 sin^2 x h_fg(f), x = 2 pi f L / c, */
+/* added to S_n of both channels (one foreground shared by A and E).        */
+/* fg[5] = (A_fg, alpha, f_k [Hz], s1, s2).                                 */
+/* Noise sets with the foreground are noise[9] = the four instrument        */
+/* parameters followed by fg[5].                                            */
+/* ------------------------------------------------------------------------ */
+
+double gblo_foreground_value(const gblo_config* cfg, double f, const double* fg) {
+  double x = 2.0 * ORC_PI * f * cfg->L / ORC_C;
+  double h = 0.5 * fg[0] * pow(f, -7.0 / 3.0) * exp(-fg[3] * pow(f, fg[1])) * (1.0 + tanh(-fg[4] * (f - fg[2])));
+  return 6.0 * x * x * sin(x) * sin(x) * h;
+}
+
+/* S[P][2][n_bins] for noise sets of n_par = 4 (instrument only) or 9
+ * (instrument + foreground) parameters */
+int gblo_psd_eval_n(const gblo_config* cfg, const double* noise, int32_t n_par, int64_t P, double* S) {
+  int64_t k_min, nb;
+  gblo_band(cfg, &k_min, &nb);
+  if (n_par != 4 && n_par != 9) return -1;
+#pragma omp parallel for
+  for (int64_t pi = 0; pi < P; pi++)
+    for (int c = 0; c < 2; c++)
+      for (int64_t i = 0; i < nb; i++) {
+        double f = (double)(k_min + i) / cfg->T;
+        const double* th = noise + n_par * pi;
+        double v = gblo_psd_value(cfg, f, th[2 * c], th[2 * c + 1]);
+        if (n_par == 9) v += gblo_foreground_value(cfg, f, th + 4);
+        S[(pi * 2 + c) * nb + i] = v;
+      }
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Log-likelihoods.                                                         */
 /* Base (eq. like):  lnL = -1/2 <R|R> - sum_ch sum_k ln S_ch,k,              */
 /* <b|c> = 4 Delta f Re sum_ch sum_k conj(b) c / S  (eq. inner, A and E).     */
@@ -402,21 +438,28 @@ double gblo_loglike(const gblo_config* cfg, const double* R /*[2][n_bins][2]*/, 
 }
 
 /* PSD-parameter log-likelihood: the base likelihood with S built from the
- * four noise parameters of each set; noise [P][4], res_idx [P]. */
-int gblo_psd_loglike(const gblo_config* cfg, const double* residual, int32_t n_res, const double* noise,
-                     const int32_t* res_idx, int64_t P, double* logl) {
+ * n_par (4, or 9 with the foreground) noise parameters of each set;
+ * noise [P][n_par], res_idx [P]. */
+int gblo_psd_loglike_n(const gblo_config* cfg, const double* residual, int32_t n_res, const double* noise,
+                       int32_t n_par, const int32_t* res_idx, int64_t P, double* logl) {
   int64_t k_min, nb;
   gblo_band(cfg, &k_min, &nb);
+  if (n_par != 4 && n_par != 9) return -1;
   for (int64_t pi = 0; pi < P; pi++)
     if (res_idx[pi] < 0 || res_idx[pi] >= n_res) return -1;
 #pragma omp parallel for
   for (int64_t pi = 0; pi < P; pi++) {
     double* S = (double*)malloc(sizeof(double) * 2 * nb);
-    gblo_psd_eval(cfg, noise + 4 * pi, 1, S);
+    gblo_psd_eval_n(cfg, noise + n_par * pi, n_par, 1, S);
     logl[pi] = gblo_loglike(cfg, residual + (int64_t)res_idx[pi] * 2 * nb * 2, S);
     free(S);
   }
   return 0;
+}
+
+int gblo_psd_loglike(const gblo_config* cfg, const double* residual, int32_t n_res, const double* noise,
+                     const int32_t* res_idx, int64_t P, double* logl) {
+  return gblo_psd_loglike_n(cfg, residual, n_res, noise, 4, res_idx, P, logl);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -496,6 +539,81 @@ int gblo_delta_loglike(const gblo_config* cfg, const double* residual, int32_t n
     free(r);
   }
   return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Inner products of stored band slices (eq. inner, channels A and E): for   */
+/* template b with slices A[b], E[b] of width N starting at global bin       */
+/* start_bin[b],                                                            */
+/*   out[b][0] = <h|h>,  out[b][1] = <R|h>,  R = residual[res_idx[b]],       */
+/* over the slice's bins inside the analysis band.                          */
+/* ------------------------------------------------------------------------ */
+
+int gblo_inner(const gblo_config* cfg, const double* A, const double* E, const int64_t* start_bin, int32_t N,
+               const double* residual, int32_t n_res, const double* psd, int32_t n_psd, int32_t psd_is_inverse,
+               const int32_t* res_idx, const int32_t* psd_idx, int64_t B, double* out) {
+  int64_t k_min, nb;
+  gblo_band(cfg, &k_min, &nb);
+  for (int64_t b = 0; b < B; b++) {
+    if (res_idx[b] < 0 || res_idx[b] >= n_res) return -1;
+    if (psd_idx[b] < 0 || psd_idx[b] >= n_psd) return -1;
+  }
+  double f4 = 4.0 / cfg->T;
+  for (int64_t b = 0; b < B; b++) {
+    const cplx* h[2] = {(const cplx*)(A + 2 * b * N), (const cplx*)(E + 2 * b * N)};
+    const cplx* R = (const cplx*)(residual + (int64_t)res_idx[b] * 2 * nb * 2);
+    const double* S = psd + (int64_t)psd_idx[b] * 2 * nb;
+    double hh = 0.0, Rh = 0.0;
+    for (int c = 0; c < 2; c++)
+      for (int j = 0; j < N; j++) {
+        int64_t k = start_bin[b] + j;
+        if (k < k_min || k >= k_min + nb) continue;
+        double w = psd_is_inverse ? S[c * nb + (k - k_min)] : 1.0 / S[c * nb + (k - k_min)];
+        hh += creal(conj(h[c][j]) * h[c][j]) * w;
+        Rh += creal(conj(R[c * nb + (k - k_min)]) * h[c][j]) * w;
+      }
+    out[2 * b] = f4 * hh;
+    out[2 * b + 1] = f4 * Rh;
+  }
+  return 0;
+}
+
+/* Optimal SNR sqrt(<h|h>) and observed SNR <d|h> / sqrt(<h|h>) (Sec. 2,
+ * after eq. like) of the width-N templates of params; data may be NULL (then
+ * snr_obs is not written). */
+int gblo_snr(const gblo_config* cfg, const double* params, int64_t B, int32_t N, const double* psd, int32_t n_psd,
+             int32_t psd_is_inverse, const int32_t* psd_idx, const double* data, int32_t n_data,
+             const int32_t* data_idx, double* snr_opt, double* snr_obs) {
+  int64_t k_min, nb;
+  gblo_band(cfg, &k_min, &nb);
+  if (N < 2 || (N & (N - 1))) return -2;
+  double* A = (double*)malloc(sizeof(double) * 2 * N);
+  double* E = (double*)malloc(sizeof(double) * 2 * N);
+  int rc = 0;
+  for (int64_t b = 0; b < B && rc == 0; b++) {
+    int64_t sb;
+    double o[2];
+    if (!params_finite(cfg, params + 8 * b)) {
+      snr_opt[b] = NAN;
+      if (data) snr_obs[b] = NAN;
+      continue;
+    }
+    waveform_one(cfg, params + 8 * b, N, (cplx*)A, (cplx*)E, NULL, &sb);
+    int32_t ri = data ? data_idx[b] : 0;
+    if (data) {
+      rc = gblo_inner(cfg, A, E, &sb, N, data, n_data, psd, n_psd, psd_is_inverse, &ri, psd_idx + b, 1, o);
+    } else {
+      /* no data: <h|h> only, against a residual of zeros */
+      double* z = (double*)calloc((size_t)4 * nb, sizeof(double));
+      rc = gblo_inner(cfg, A, E, &sb, N, z, 1, psd, n_psd, psd_is_inverse, &ri, psd_idx + b, 1, o);
+      free(z);
+    }
+    snr_opt[b] = sqrt(o[0]);
+    if (data) snr_obs[b] = o[1] / sqrt(o[0]);
+  }
+  free(A);
+  free(E);
+  return rc;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -1117,8 +1235,9 @@ int gblo_sweep_group(const gblo_sweep_config* sc, const double* u, const int32_t
  * eq. like; Sec. 4: the PSD parameters are sampled with ensemble stretch
  * moves, eq. stretch, and vertical tempering: chain (t, w) always uses walker
  * w's residual, so a temperature swap is the plain eq. temp-orig).
- * theta [n_tn][n_w][4] = (sqrt S_oms^A, sqrt S_acc^A, sqrt S_oms^E,
- * sqrt S_acc^E), uniform prior box; full residual of walker w = the sum of its
+ * theta [n_tn][n_w][n_par] = (sqrt S_oms^A, sqrt S_acc^A, sqrt S_oms^E,
+ * sqrt S_acc^E) and, with n_par = 9, the foreground (A_fg, alpha, f_k, s1,
+ * s2); uniform prior box; full residual of walker w = the sum of its
  * two cold-chain buffers minus the data.  Random numbers: stretch unit
  * t n_w + w, move 4, draws 4 h + (0 partner, 1 z, 2 accept) for half h;
  * swaps unit w, move 5, draw t.  stats: stretch (proposed, accepted), swaps
@@ -1129,9 +1248,10 @@ int gblo_sweep_group(const gblo_sweep_config* sc, const double* u, const int32_t
 
 typedef struct {
   int32_t n_tn, n_walkers;
+  int32_t n_par; /* 4: instrument noise only; 9: with the Galactic foreground (Sec. 3) */
   double stretch_a;
   uint64_t seed;
-  double prior_lo[4], prior_hi[4];
+  double prior_lo[9], prior_hi[9];
 } gblo_psd_sweep_config;
 
 int gblo_psd_sweep_step(const gblo_config* cfg, const gblo_psd_sweep_config* pc, int64_t sweep, double* theta,
@@ -1139,8 +1259,9 @@ int gblo_psd_sweep_step(const gblo_config* cfg, const gblo_psd_sweep_config* pc,
                         double* inv_psd, int64_t* stats) {
   int64_t k_min, nb;
   gblo_band(cfg, &k_min, &nb);
-  const int nt = pc->n_tn, nw = pc->n_walkers;
+  const int nt = pc->n_tn, nw = pc->n_walkers, np_ = pc->n_par;
   if (nw < 2 || nw % 2) return -1;
+  if (np_ != 4 && np_ != 9) return -1;
   /* full residual per walker: buffer 0 + buffer 1 - data */
   double* R = (double*)malloc(sizeof(double) * (size_t)nw * 2 * nb * 2);
   for (int w = 0; w < nw; w++)
@@ -1151,8 +1272,8 @@ int gblo_psd_sweep_step(const gblo_config* cfg, const gblo_psd_sweep_config* pc,
   for (int t = 0; t < nt; t++)
     for (int w = 0; w < nw; w++) ridx[t * nw + w] = w;
   /* current log-likelihoods against the current residuals */
-  gblo_psd_loglike(cfg, R, nw, theta, ridx, (int64_t)nt * nw, logl);
-  double* prop = (double*)malloc(sizeof(double) * (size_t)nt * nw * 4);
+  gblo_psd_loglike_n(cfg, R, nw, theta, np_, ridx, (int64_t)nt * nw, logl);
+  double* prop = (double*)malloc(sizeof(double) * (size_t)nt * nw * np_);
   double* lprop = (double*)malloc(sizeof(double) * (size_t)nt * nw);
   int* ok = (int*)malloc(sizeof(int) * (size_t)nt * nw);
   double* lz = (double*)malloc(sizeof(double) * (size_t)nt * nw);
@@ -1167,20 +1288,21 @@ int gblo_psd_sweep_step(const gblo_config* cfg, const gblo_psd_sweep_config* pc,
         int j = 2 * (int)floor(r_pick * half) + (1 - h);
         double a = pc->stretch_a;
         double z = ((a - 1.0) * r_z + 1.0) * ((a - 1.0) * r_z + 1.0) / a;
-        const double* X = theta + ((int64_t)t * nw + j) * 4;
-        const double* Y = theta + ((int64_t)t * nw + w) * 4;
-        double* P = prop + ((int64_t)t * nw + w) * 4;
+        const double* X = theta + ((int64_t)t * nw + j) * np_;
+        const double* Y = theta + ((int64_t)t * nw + w) * np_;
+        double* P = prop + ((int64_t)t * nw + w) * np_;
         int inside = 1;
-        for (int k = 0; k < 4; k++) {
+        for (int k = 0; k < np_; k++) {
           P[k] = X[k] + z * (Y[k] - X[k]);
           if (!(P[k] >= pc->prior_lo[k] && P[k] <= pc->prior_hi[k])) inside = 0;
         }
         ok[t * nw + w] = inside;
-        lz[t * nw + w] = 3.0 * log(z); /* z^(d-1), d = 4 */
+        lz[t * nw + w] = (double)(np_ - 1) * log(z); /* z^(d-1), d = n_par */
       }
     for (int t = 0; t < nt; t++)
       for (int w = h; w < nw; w += 2)
-        if (ok[t * nw + w]) gblo_psd_loglike(cfg, R, nw, prop + ((int64_t)t * nw + w) * 4, &w, 1, lprop + t * nw + w);
+        if (ok[t * nw + w])
+          gblo_psd_loglike_n(cfg, R, nw, prop + ((int64_t)t * nw + w) * np_, np_, &w, 1, lprop + t * nw + w);
     for (int t = 0; t < nt; t++)
       for (int w = h; w < nw; w += 2) {
         stats[0]++;
@@ -1189,7 +1311,7 @@ int gblo_psd_sweep_step(const gblo_config* cfg, const gblo_psd_sweep_config* pc,
         double r_acc = rng_uniform(pc->seed, sweep, MOVE_PSD, unit, 4 * (uint64_t)h + 2);
         double la = betas[t] * (lprop[t * nw + w] - logl[t * nw + w]) + lz[t * nw + w];
         if (log(r_acc) < la) {
-          for (int k = 0; k < 4; k++) theta[((int64_t)t * nw + w) * 4 + k] = prop[((int64_t)t * nw + w) * 4 + k];
+          for (int k = 0; k < np_; k++) theta[((int64_t)t * nw + w) * np_ + k] = prop[((int64_t)t * nw + w) * np_ + k];
           logl[t * nw + w] = lprop[t * nw + w];
           stats[1]++;
         }
@@ -1202,10 +1324,10 @@ int gblo_psd_sweep_step(const gblo_config* cfg, const gblo_psd_sweep_config* pc,
       double r = rng_uniform(pc->seed, sweep, MOVE_PSDPT, (uint64_t)w, (uint64_t)t);
       double la = (betas[t - 1] - betas[t]) * (logl[t * nw + w] - logl[(t - 1) * nw + w]);
       if (log(r) < la) {
-        for (int k = 0; k < 4; k++) {
-          double tmp = theta[((int64_t)t * nw + w) * 4 + k];
-          theta[((int64_t)t * nw + w) * 4 + k] = theta[((int64_t)(t - 1) * nw + w) * 4 + k];
-          theta[((int64_t)(t - 1) * nw + w) * 4 + k] = tmp;
+        for (int k = 0; k < np_; k++) {
+          double tmp = theta[((int64_t)t * nw + w) * np_ + k];
+          theta[((int64_t)t * nw + w) * np_ + k] = theta[((int64_t)(t - 1) * nw + w) * np_ + k];
+          theta[((int64_t)(t - 1) * nw + w) * np_ + k] = tmp;
         }
         double tl = logl[t * nw + w];
         logl[t * nw + w] = logl[(t - 1) * nw + w];
@@ -1216,7 +1338,7 @@ int gblo_psd_sweep_step(const gblo_config* cfg, const gblo_psd_sweep_config* pc,
   /* the cold chain's PSD for the GB likelihood */
   double* S = (double*)malloc(sizeof(double) * 2 * nb);
   for (int w = 0; w < nw; w++) {
-    gblo_psd_eval(cfg, theta + (int64_t)w * 4, 1, S);
+    gblo_psd_eval_n(cfg, theta + (int64_t)w * np_, np_, 1, S);
     for (int64_t i = 0; i < 2 * nb; i++) inv_psd[(int64_t)w * 2 * nb + i] = 1.0 / S[i];
   }
   free(S);

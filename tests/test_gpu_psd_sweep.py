@@ -29,7 +29,7 @@ def test_psd_step_matches_oracle():
     theta = np.array(LO) + (np.array(HI) - np.array(LO)) * rng.uniform(size=(nt, nw, 4))
     betas = np.array([1.0, 0.5, 0.2])
     pco = oracle.PsdSweepConfig()
-    pco.n_tn, pco.n_walkers, pco.stretch_a, pco.seed = nt, nw, 2.0, 805
+    pco.n_tn, pco.n_walkers, pco.n_par, pco.stretch_a, pco.seed = nt, nw, 4, 2.0, 805
     for k in range(4):
         pco.prior_lo[k], pco.prior_hi[k] = LO[k], HI[k]
 
