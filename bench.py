@@ -167,6 +167,20 @@ def secondary(ctx, torch, stream, cfg, R, invS, po, pn, ri, pi):
                                             "median_abs_err_vs_fp64": float(err.median()),
                                             "frac_err_le_1e-3": float((err <= 1e-3).double().mean())}
     ctx_u.close()
+    # the band likelihood alone over stored slices (gb_inner): the new templates of
+    # the headline batch written to HBM by gb_waveform, then <h|h> and <R|h>
+    # against each pair's walker residual, as the likelihood stage reads them
+    A, E, _, sb = ctx.gb_waveform(pn, cfg.N, with_T=False)
+    inner = torch.empty((B, 2), dtype=torch.float64, device=dev)
+    ms = _time_launches(torch, stream, lambda: ctx.gb_inner(A, E, sb, R, invS, ri, pi, psd_inverse=True,
+                                                             out=inner), 20)
+    per = 2 * cfg.N * (16 + 16 + 8) + 8 + 4 + 4 + 16   # slices, residual, 1/S; start, indices, output
+    gbs = B * per / (ms / 1e3) / 1e9
+    out["band_likelihood_stored_slices"] = {
+        "call": "gb_inner", "templates": B, "N": cfg.N, "ms": round(ms, 4),
+        "evals_per_s": round(B / (ms / 1e3), 1), "algorithmic_bytes_per_eval": per,
+        "algorithmic_gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+    del A, E, sb, inner
     # PSD-parameter log-likelihood: one parameter set per walker residual
     nw = R.shape[0]
     noise = torch.tensor([[cfg.sqrt_oms, cfg.sqrt_acc, cfg.sqrt_oms, cfg.sqrt_acc]], dtype=torch.float64,
@@ -178,6 +192,13 @@ def secondary(ctx, torch, stream, cfg, R, invS, po, pn, ri, pi):
     gbs = (nw * 32 + 16) * ctx.n_bins / (ms / 1e3) / 1e9
     out["psd_loglike"] = {"sets": nw, "ms": round(ms, 4), "sets_per_s": round(nw / (ms / 1e3), 1),
                           "algorithmic_gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+    # the same with the Galactic foreground (nine parameters per set, the paper's example foreground)
+    fg = torch.tensor([[3.3e-44, 1.2, 2.8e-3, 1763.3, 1686.3]], dtype=torch.float64, device=dev).repeat(nw, 1)
+    noise9 = torch.cat([noise, fg], dim=1).contiguous()
+    ms = _time_launches(torch, stream, lambda: ctx.gb_psd_loglike(R, noise9, ridx), 10)
+    gbs = (nw * 32 + 32) * ctx.n_bins / (ms / 1e3) / 1e9   # + the foreground factors P3, ln f
+    out["psd_loglike_foreground"] = {"sets": nw, "ms": round(ms, 4), "sets_per_s": round(nw / (ms / 1e3), 1),
+                                     "algorithmic_gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
     return out
 
 
@@ -295,9 +316,11 @@ def rj_bench(torch, dev, stream):
     with torch.cuda.stream(stream):
         prob = learned_rj.build(cfg=inputs.PAPER, N=256, n_temps=8, n_walkers=32, n_bands=16, n_slots=6, seed=60,
                                 stream=stream)
-        res, flow = learned_rj.compare(prob, burn=50, collect_sweeps=100, train_steps=300, measure_sweeps=300)
+        res, flow = learned_rj.compare(prob, burn=50, collect_sweeps=100, train_steps=300, measure_sweeps=300,
+                                       equilibrate=200)
         for m in ("plain", "learned"):
-            for k in ("ess_k", "ess_logl", "ess_k_per_s", "ess_logl_per_s", "wall_s", "rj_accepted_per_s"):
+            for k in ("ess_k", "ess_logl", "ess_k_per_s", "ess_logl_per_s", "wall_s", "rj_accepted_per_s",
+                      "mean_k", "se_mean_k", "mean_logl", "se_mean_logl"):
                 res[m][k] = round(res[m][k], 3)
         for m in ("plain", "learned"):
             d = res["discovery"][m]
@@ -320,7 +343,9 @@ def rj_bench(torch, dev, stream):
         res["flow_mfma_frac_bf16_peak"] = round(flops / (ms / 1e3) / 1e12 / 2500.0, 5)
         res["workload"] = ("1 yr, 16 sub-bands of N=256 from 3 mHz, SNR 20 + SNR 7 source per sub-band, "
                            "amplitude prior from SNR 5, 8 temps x 32 walkers x 6 slots; burn 50, collect 100, "
-                           "train 300 x 4096, then 300 sweeps per proposal from the same state (ESS) and "
+                           "train 300 x 4096, 200 sweeps of equilibration with the flow mixture, then 300 "
+                           "sweeps per proposal from that state (ESS; stationarity: both chains' mean k and "
+                           "mean cold logL agree within 3 Monte Carlo errors) and "
                            "300 from empty slots (discovery); RJ proposal = 0.8 flow + 0.2 prior; "
                            "repeated for problem seeds 60, 61, 62")
         prob.ctx.close()
@@ -329,16 +354,21 @@ def rj_bench(torch, dev, stream):
         per_seed = {"seed": [60], "gain_ess_k_per_s": [res["gain_ess_k_per_s"]],
                     "gain_ess_logl_per_s": [res["gain_ess_logl_per_s"]],
                     "discovery_learned_mean": [res["discovery"]["learned"]["mean"]],
-                    "discovery_plain_mean": [res["discovery"]["plain"]["mean"]]}
+                    "discovery_plain_mean": [res["discovery"]["plain"]["mean"]],
+                    "stationarity": [res["stationarity"]],
+                    "mean_k": [[res["plain"]["mean_k"], res["learned"]["mean_k"]]]}
         for seed in (61, 62):
             p2 = learned_rj.build(cfg=inputs.PAPER, N=256, n_temps=8, n_walkers=32, n_bands=16, n_slots=6,
                                   seed=seed, stream=stream)
-            r2, _ = learned_rj.compare(p2, burn=50, collect_sweeps=100, train_steps=300, measure_sweeps=300)
+            r2, _ = learned_rj.compare(p2, burn=50, collect_sweeps=100, train_steps=300, measure_sweeps=300,
+                                       equilibrate=200)
             per_seed["seed"].append(seed)
             per_seed["gain_ess_k_per_s"].append(r2["gain_ess_k_per_s"])
             per_seed["gain_ess_logl_per_s"].append(r2["gain_ess_logl_per_s"])
             per_seed["discovery_learned_mean"].append(r2["discovery"]["learned"]["mean"])
             per_seed["discovery_plain_mean"].append(r2["discovery"]["plain"]["mean"])
+            per_seed["stationarity"].append(r2["stationarity"])
+            per_seed["mean_k"].append([round(r2["plain"]["mean_k"], 4), round(r2["learned"]["mean_k"], 4)])
             p2.ctx.close()
         for k in ("gain_ess_k_per_s", "gain_ess_logl_per_s"):
             per_seed[k] = [round(x, 4) for x in per_seed[k]]
@@ -357,6 +387,10 @@ def _rj_summary(r):
         v = sd[k]
         out[name] = round(float(np.mean(v)), 4)
         out[name + "_range"] = [min(v), max(v)]
+    out["stationary_all_seeds"] = all(x["stationary"] for x in sd["stationarity"])
+    out["z_mean_k"] = [round(x["z_mean_k"], 2) for x in sd["stationarity"]]
+    out["z_mean_logl"] = [round(x["z_mean_logl"], 2) for x in sd["stationarity"]]
+    out["mean_k_plain_learned"] = sd["mean_k"]
     out["discovery_mean_recovered"] = {
         "plain": [round(float(np.mean([d[j] for d in sd["discovery_plain_mean"]])), 4) for j in (0, 1)],
         "learned": [round(float(np.mean([d[j] for d in sd["discovery_learned_mean"]])), 4) for j in (0, 1)]}

@@ -51,7 +51,10 @@
  *   residual  [n_res][2][n_bins] complex  channel 0 = A, 1 = E; index k - k_min
  *   psd       [n_psd][2][n_bins] double   S_n (or 1/S_n with GBL_PSD_INVERSE)
  *   noise     [P][4] double  (sqrt S_oms^A, sqrt S_acc^A, sqrt S_oms^E, sqrt S_acc^E)
- *             in m/sqrt(Hz) and m s^-2/sqrt(Hz)
+ *             in m/sqrt(Hz) and m s^-2/sqrt(Hz); with the Galactic foreground
+ *             (the *_n calls with n_par = 9) [P][9]: those four followed by
+ *             (A_fg, alpha, f_k [Hz], s1, s2) of Sec. 3 "Galactic foreground
+ *             noise parameterization"
  */
 #ifndef GBL_H
 #define GBL_H
@@ -79,6 +82,11 @@ extern "C" {
  * FP64 in a second pass, so every result stays within 1e-3 of the FP64 path;
  * GBL_MIXED_UNROUTED skips that pass (pure FP32 response). */
 #define GBL_MIXED_UNROUTED 1
+/* GBL_DETERMINISTIC: gb_scatter_add sums overlapping templates in a fixed
+ * order (sorted by residual, start bin, then template index; no atomics), so
+ * its result does not depend on scheduling.  Costs a 128 MB workspace
+ * allocated by gbl_create and a sort per chunk of 2^22 / N templates. */
+#define GBL_DETERMINISTIC 2
 
 /* psd flags */
 #define GBL_PSD_INVERSE 1 /* the psd array holds 1/S_n instead of S_n */
@@ -92,7 +100,7 @@ typedef struct {
   double f_lo;       /* analysis band [Hz] */
   double f_hi;
   int32_t precision; /* GBL_FP64 or GBL_MIXED */
-  int32_t flags;     /* 0, or GBL_MIXED_UNROUTED with GBL_MIXED */
+  int32_t flags;     /* 0 or GBL_DETERMINISTIC, plus GBL_MIXED_UNROUTED with GBL_MIXED */
 } gbl_config;
 
 /* Create a context for one configuration on the current HIP device.
@@ -201,6 +209,15 @@ int gb_delta_loglike_var(gbl_ctx* ctx, const double* residual, int32_t n_res, co
  * (or 1/S_n with GBL_PSD_INVERSE).  Errors: GBL_EINVAL. */
 int gb_psd_eval(gbl_ctx* ctx, const double* noise, int64_t P, int32_t psd_flags, double* S);
 
+/* As gb_psd_eval for noise sets of n_par = 4 or 9 parameters.  With 9, the
+ * Galactic foreground of Sec. 3 is added to both channels:
+ *   S_fg(f) = 6 x^2 sin^2 x h_fg(f),  x = 2 pi f L / c,
+ *   h_fg(f) = 1/2 A_fg f^(-7/3) exp(-s1 f^alpha) [1 + tanh(-s2 (f - f_k))],
+ * one foreground (noise[p][4..8]) shared by A and E.  A_fg = 0 gives S_n
+ * exactly.  Errors: GBL_EINVAL (n_par not 4 or 9, P < 0, null pointers,
+ * unknown flags). */
+int gb_psd_eval_n(gbl_ctx* ctx, const double* noise, int32_t n_par, int64_t P, int32_t psd_flags, double* S);
+
 /* Noise-parameter log-likelihood (Sec. 2 eq. like with Sec. 3 eq. psd):
  *   logl[p] = sum_{c in A,E} [ -2 df sum_k |R_c,k|^2 / S_c,k - sum_k ln S_c,k ]
  * with R = residual[res_idx[p]] and S from noise[p].  The sum over bins is a
@@ -210,12 +227,62 @@ int gb_psd_eval(gbl_ctx* ctx, const double* noise, int64_t P, int32_t psd_flags,
 int gb_psd_loglike(gbl_ctx* ctx, const double* residual, int32_t n_res, const double* noise,
                    const int32_t* res_idx, int64_t P, double* logl);
 
+/* As gb_psd_loglike with noise sets of n_par = 4 or 9 parameters (9: the
+ * PSD includes the Galactic foreground as in gb_psd_eval_n; Sec. 4 "Noise
+ * and stochastic foreground signal PSD fitting").  Errors: GBL_EINVAL. */
+int gb_psd_loglike_n(gbl_ctx* ctx, const double* residual, int32_t n_res, const double* noise, int32_t n_par,
+                     const int32_t* res_idx, int64_t P, double* logl);
+
 /* residual[res_idx[b]] += sign * (A, E) of template b, clipped to the band
- * (the residual updates of the sampling algorithm's write-back step).  Uses
- * FP64 atomic adds, so overlapping templates are summed in an unspecified
- * order.  Errors: GBL_EINVAL, GBL_EUNSUPPORTED (N). */
+ * (the residual updates of the sampling algorithm's write-back step).  By
+ * default FP64 atomic adds, so overlapping templates are summed in an
+ * unspecified order; in a GBL_DETERMINISTIC context every bin is written by
+ * one thread that adds the templates covering it in (residual, start bin,
+ * template index) order, so repeated calls give bitwise equal residuals.
+ * Zero-amplitude and undefined templates and out-of-range res_idx add
+ * nothing.  Errors: GBL_EINVAL, GBL_EUNSUPPORTED (N). */
 int gb_scatter_add(gbl_ctx* ctx, const double* params, int64_t B, int32_t N, double sign, double* residual,
                    int32_t n_res, const int32_t* res_idx);
+
+/* Noise-weighted inner products of stored band slices (Sec. 2 eq. inner,
+ * summed over channels A and E):
+ *   out[b][0] = <h_b|h_b>,  out[b][1] = <R|h_b>,  R = residual[res_idx[b]],
+ * weighted by psd[psd_idx[b]] (S_n, or 1/S_n with GBL_PSD_INVERSE), where
+ * h_b = (A[b][j], E[b][j]) sits at global bin start_bin[b] + j, 0 <= j < N
+ * (the layout gb_waveform writes), and bins outside the band contribute 0.
+ * Any N >= 1.  This is the likelihood stage alone over slices already in
+ * memory (bound by HBM bandwidth): 4 dlnL-style terms of eq. swapsource
+ * follow from two calls.  Sums in FP64, fixed order (bitwise reproducible).
+ * An out-of-range res_idx/psd_idx gives NaN for that template.
+ * Errors: GBL_EINVAL (null pointers, B < 0, N < 1, n_res/n_psd < 1, flags). */
+int gb_inner(gbl_ctx* ctx, const double* A, const double* E, const int64_t* start_bin, int32_t N,
+             const double* residual, int32_t n_res, const double* psd, int32_t n_psd, int32_t psd_flags,
+             const int32_t* res_idx, const int32_t* psd_idx, int64_t B, double* out);
+
+/* Overlaps of template pairs (Sec. 4 "Cataloging Operation": sources are
+ * grouped by overlap above 0.9):
+ *   out[b] = (<a|a>, <b|b>, <a|b>, <a|b> / sqrt(<a|a> <b|b>)),
+ * a = width-N template of params_a[b], b of params_b[b], the inner product of
+ * eq. inner over A and E weighted by psd[psd_idx[b]] (S_n, or 1/S_n with
+ * GBL_PSD_INVERSE), bins outside the band dropped; FP64 response whatever the
+ * context's precision.  Undefined parameters or an out-of-range psd_idx give
+ * NaN; a zero-amplitude template gives a NaN overlap (0/0).
+ * Errors: GBL_EINVAL, GBL_EUNSUPPORTED (N). */
+int gb_overlap(gbl_ctx* ctx, const double* params_a, const double* params_b, int32_t N, const double* psd,
+               int32_t n_psd, int32_t psd_flags, const int32_t* psd_idx, int64_t B, double* out);
+
+/* Optimal SNR rho_opt = sqrt(<h|h>) and observed SNR <d|h> / sqrt(<h|h>) of
+ * width-N templates built from params (Sec. 2: the inner product of eq. inner
+ * over A and E, the optimal SNR defined with the likelihood), FP64 response
+ * whatever the context's precision.  data (may be NULL: snr_obs is then not
+ * written) holds n_data series [n_data][2][n_bins] complex, template b uses
+ * data[data_idx[b]] and psd[psd_idx[b]].  A zero-amplitude template gives
+ * snr_opt 0 and snr_obs NaN (0/0); undefined parameters or out-of-range
+ * indices give NaN.  Errors: GBL_EINVAL (null pointers, sizes, flags),
+ * GBL_EUNSUPPORTED (N). */
+int gb_snr(gbl_ctx* ctx, const double* params, int64_t B, int32_t N, const double* psd, int32_t n_psd,
+           int32_t psd_flags, const int32_t* psd_idx, const double* data, int32_t n_data, const int32_t* data_idx,
+           double* snr_opt, double* snr_obs);
 
 /* Stationary Gaussian noise with PSD S (Sec. 3): for n series,
  *   out[i][c][k] = sqrt(S[i][c][k] / (4 df)) * normals[i][c][k]
@@ -232,7 +299,8 @@ int gb_make_noise(gbl_ctx* ctx, const double* S, const double* normals, int64_t 
  * width, 128/256/512); its analysis window is sub-bands b-1..b+1.  A sweep is:
  * stationary-group refresh (every group_every sweeps), in-model group-stretch
  * band loops (odd bands, then even), the reversible-jump pass that flips every
- * slot (odd, even), residual-aware parallel tempering (odd, even), and
+ * slot (odd, even), residual-aware parallel tempering (odd, even), when
+ * configured the ladder adaptation and the ownership shift, and
  * sweep_counter += 1.  Bands of one parity run in parallel: they read the
  * opposite-parity cold-chain buffer and write only their own.
  * Sampling coordinates u = (log10 A, f0 [Hz], fdot [Hz/s], phi0, cos iota,
@@ -256,6 +324,11 @@ typedef struct {
   double stretch_a;                            /* stretch scale a > 1 */
   uint64_t seed;
   double prior_lo[8], prior_hi[8];
+  /* After the tempering step of every sweep (0 = off):                      */
+  int32_t adapt_ladder;    /* 1: adapt each band's ladder (gb_sweep_adapt_ladder) */
+  int32_t shift_ownership; /* 1: move strayed cold-chain sources (gb_sweep_shift_ownership) */
+  double adapt_lag;        /* t0 of the adaptation's decay t0 / (t + t0), > 0 when adapting */
+  double adapt_time;       /* nu, the adaptation's time scale, > 0 when adapting */
 } gbl_sweep_config;
 
 /* Sampler state: caller-owned device arrays (checkpointable as they are). */
@@ -268,7 +341,8 @@ typedef struct {
   const double* inv_psd;  /* [n_walkers][2][n_bins] 1/S per walker */
   double* group;          /* [n_bands][n_walkers * n_slots][8] stationary groups (sorted by f0) */
   int32_t* group_count;   /* [n_bands] */
-  int64_t* stats;         /* [8] in-model proposed/accepted, births, deaths, swaps (proposed/accepted) */
+  int64_t* stats;         /* [10] in-model proposed/accepted, births, deaths, swaps (proposed/accepted),
+                             ownership shifts (moved, no free slot) */
   int64_t* sweep_counter; /* [1] current sweep index */
   /* Optional (NULL = prior RJ proposal, no log-likelihood trace): */
   double* prop_u;         /* [n_t][n_w][n_b][n_slot][8] birth candidates (read for empty slots) */
@@ -286,6 +360,10 @@ typedef struct {
   double* spec_pool;
   int32_t* pool_flags;
   int32_t pool_size;
+  /* Needed with adapt_ladder (else may be NULL): [n_bands][n_temps] accepted
+   * swaps of rungs (t-1, t) since the last adaptation (tempering adds to it,
+   * the adaptation clears it); must start at zero. */
+  int32_t* swap_acc;
 } gbl_sweep_state;
 
 typedef struct gbl_graph gbl_graph;
@@ -298,6 +376,28 @@ int gb_sweep_step(gbl_ctx* ctx, const gbl_sweep_config* cfg, const gbl_sweep_sta
 
 /* Rebuild the stationary groups from the cold chain (t = 0) of every walker. */
 int gb_sweep_group(gbl_ctx* ctx, const gbl_sweep_config* cfg, const gbl_sweep_state* st);
+
+/* Temperature-ladder adaptation of every band (appendix "Parallel tempering
+ * in a residual-based analysis": independent ladders that adapt, after
+ * Vousden, Farr & Mandel 2016).  With T = 1/beta and A_j = swap_acc[b][j+1] /
+ * n_walkers the accepted fraction of swaps of rungs (j, j+1):
+ *   T_(j+1) - T_j <- (T_(j+1) - T_j) exp(kappa (A_j - A_(j+1))),
+ *   kappa = adapt_lag / (adapt_time (*sweep_counter + adapt_lag)),
+ * for j = 0..n_temps-3; rung 0 (beta = 1) and the hottest rung stay, the
+ * others are rung 0's temperature plus the running sum of the gaps.  Clears
+ * swap_acc.  Errors: GBL_EINVAL (no swap_acc, adapt_lag or adapt_time <= 0). */
+int gb_sweep_adapt_ladder(gbl_ctx* ctx, const gbl_sweep_config* cfg, const gbl_sweep_state* st);
+
+/* Sub-band ownership (Sec. 4: samples may move half a band into the
+ * neighbours; afterwards a cold-chain sample that lies in a neighbouring band
+ * is handed to it): every cold-chain (t = 0) source whose f0 left its band's
+ * nominal range [k_band0 + b N, k_band0 + (b+1) N) / T moves to the lowest
+ * free cold-chain slot of the neighbouring band it lies in (it stays when
+ * there is none, or at the ends of the band range), and the two cold-chain
+ * buffers are updated (added back to the old parity's buffer, removed from the
+ * new one's).  Per walker, bands and then slots in increasing order.  Counts
+ * in stats[8] (moved) and stats[9] (no free slot). */
+int gb_sweep_shift_ownership(gbl_ctx* ctx, const gbl_sweep_config* cfg, const gbl_sweep_state* st);
 
 /* *sweep_counter += 1 on the device. */
 int gb_sweep_advance(gbl_ctx* ctx, const gbl_sweep_state* st);
@@ -331,9 +431,11 @@ int gb_graph_end(gbl_ctx* ctx, gbl_graph** graph);
  *   3. for half h = 0, 1: every chain (t, w) with w % 2 == h proposes
  *      theta' = theta_j + z (theta - theta_j), j a walker of the other half at
  *      the same temperature, z = ((a-1) u + 1)^2 / a; accepted with
- *      ln alpha = beta_t (L' - L) + 3 ln z inside the uniform prior box;
+ *      ln alpha = beta_t (L' - L) + (n_par - 1) ln z inside the uniform prior
+ *      box (z^(d-1) for the d = n_par dimensional stretch);
  *   4. per walker, swaps from the hottest pair down;
- *   5. inv_psd[w] = 1/S at the cold chain's parameters.
+ *   5. inv_psd[w] = 1/S at the cold chain's parameters (foreground included
+ *      when n_par = 9).
  * Random numbers: the Philox stream of the sweep (seed, *sweep_counter):
  * stretch unit t n_w + w, move 4, draws 4 h + (0 partner, 1 z, 2 accept);
  * swaps unit w, move 5, draw t.  n_walkers must be even.
@@ -341,14 +443,16 @@ int gb_graph_end(gbl_ctx* ctx, gbl_graph** graph);
 typedef struct {
   int32_t n_tn;          /* PSD temperatures */
   int32_t n_walkers;     /* the sweep's walkers */
+  int32_t n_par;         /* 4 (instrument noise) or 9 (with the Galactic foreground, Sec. 3) */
   double stretch_a;
   uint64_t seed;
-  double prior_lo[4];    /* box of (sqrt S_oms^A, sqrt S_acc^A, sqrt S_oms^E, sqrt S_acc^E) */
-  double prior_hi[4];
+  double prior_lo[9];    /* box of (sqrt S_oms^A, sqrt S_acc^A, sqrt S_oms^E, sqrt S_acc^E[, A_fg, alpha,
+                            f_k, s1, s2]); entries past n_par are ignored */
+  double prior_hi[9];
 } gbl_psd_sweep_config;
 
 typedef struct {
-  double* theta;             /* [n_tn][n_w][4] */
+  double* theta;             /* [n_tn][n_w][n_par] */
   double* logl;              /* [n_tn][n_w] */
   const double* betas;       /* [n_tn] */
   const double* data;        /* [2][n_bins] complex: the data d (A, E) */

@@ -27,7 +27,8 @@ YEAR = 31557600.0
 
 
 def build() -> str:
-    """Compile the oracle with gcc (plain -O2, OpenMP over templates only)."""
+    """Compile the oracle with gcc (plain -O2; OpenMP over independent templates,
+    parameter sets and sampler units, never inside one sum)."""
     cmd = ["gcc", "-O2", "-std=gnu11", "-fPIC", "-shared", "-fopenmp", "-o", _LIB + ".tmp", _SRC, "-lm"]
     subprocess.run(cmd, check=True)
     os.replace(_LIB + ".tmp", _LIB)
@@ -45,7 +46,9 @@ class SweepConfig(ctypes.Structure):
                 ("n_slots", ctypes.c_int32), ("N", ctypes.c_int32), ("n_prop", ctypes.c_int32),
                 ("n_friends", ctypes.c_int32), ("group_every", ctypes.c_int32), ("k_band0", ctypes.c_int64),
                 ("stretch_a", ctypes.c_double), ("seed", ctypes.c_uint64),
-                ("prior_lo", ctypes.c_double * 8), ("prior_hi", ctypes.c_double * 8)]
+                ("prior_lo", ctypes.c_double * 8), ("prior_hi", ctypes.c_double * 8),
+                ("adapt_ladder", ctypes.c_int32), ("shift_ownership", ctypes.c_int32),
+                ("adapt_lag", ctypes.c_double), ("adapt_time", ctypes.c_double)]
 
 
 MOVE_INMODEL, MOVE_RJ, MOVE_PT = 0, 1, 2
@@ -91,6 +94,8 @@ def _load():
                                           ctypes.c_int32, I32, I32, ctypes.c_int64, D]),
             "gblo_snr": (ctypes.c_int, [C, D, ctypes.c_int64, ctypes.c_int32, D, ctypes.c_int32, ctypes.c_int32, I32,
                                         D, ctypes.c_int32, I32, D, D]),
+            "gblo_overlap": (ctypes.c_int, [C, D, D, ctypes.c_int64, ctypes.c_int32, D, ctypes.c_int32,
+                                            ctypes.c_int32, I32, D]),
             "gblo_loglike": (ctypes.c_double, [C, D, D]),
             "gblo_psd_loglike": (ctypes.c_int, [C, D, ctypes.c_int32, D, I32, ctypes.c_int64, D]),
             "gblo_delta_loglike": (ctypes.c_int, [C, D, ctypes.c_int32, D, ctypes.c_int32, ctypes.c_int32, D, D,
@@ -103,7 +108,9 @@ def _load():
                                                    ctypes.c_uint64]),
             "gblo_pt_log_alpha": (ctypes.c_double, [ctypes.c_double] * 6),
             "gblo_sweep_step": (ctypes.c_int, [C, ctypes.POINTER(SweepConfig), ctypes.c_int, ctypes.c_int,
-                                               ctypes.c_int64, D, I32, D, D, D, D, I32, I64, D, D, D]),
+                                               ctypes.c_int64, D, I32, D, D, D, D, I32, I64, D, D, D, I32]),
+            "gblo_sweep_adapt_ladder": (ctypes.c_int, [ctypes.POINTER(SweepConfig), ctypes.c_int64, D, I32]),
+            "gblo_sweep_shift_ownership": (ctypes.c_int, [C, ctypes.POINTER(SweepConfig), D, I32, D, I64]),
             "gblo_sweep_group": (ctypes.c_int, [ctypes.POINTER(SweepConfig), D, I32, D, I32]),
             "gblo_stretch_propose": (ctypes.c_int, [ctypes.POINTER(SweepConfig), D, D, ctypes.c_int, ctypes.c_double,
                                                     ctypes.c_double, D, D]),
@@ -270,6 +277,20 @@ class Oracle:
         _check(rc, "snr")
         return opt, obs
 
+    def overlap(self, params_a, params_b, N: int, psd, psd_idx=None, psd_is_inverse=False):
+        """[B][4] = (<a|a>, <b|b>, <a|b>, normalised overlap) of template pairs"""
+        pa = _f64(params_a).reshape(-1, 8)
+        pb = _f64(params_b).reshape(-1, 8)
+        assert pa.shape == pb.shape
+        B = pa.shape[0]
+        psd = _f64(psd).reshape(-1, 2, self.n_bins)
+        psd_idx = np.zeros(B, np.int32) if psd_idx is None else np.ascontiguousarray(psd_idx, np.int32)
+        out = np.zeros((B, 4))
+        rc = self.lib.gblo_overlap(ctypes.byref(self.cfg), _d(pa), _d(pb), B, int(N), _d(psd), psd.shape[0],
+                                   int(bool(psd_is_inverse)), _i32(psd_idx), _d(out))
+        _check(rc, "overlap")
+        return out
+
     def loglike(self, R, S) -> float:
         R = np.ascontiguousarray(R, dtype=np.complex128).reshape(2, self.n_bins)
         S = _f64(S).reshape(2, self.n_bins)
@@ -352,14 +373,16 @@ class SweepState:
         self.inv_psd = np.zeros((nw, 2, n_bins))
         self.group = np.zeros((nb, nw * ns, 8))
         self.group_count = np.zeros(nb, np.int32)
-        self.stats = np.zeros(8, np.int64)
+        self.stats = np.zeros(10, np.int64)              # [8], [9]: ownership shifts (moved, no free slot)
+        self.swap_acc = np.zeros((nb, nt), np.int32)   # accepted swaps of rungs (t-1, t) since the last adaptation
 
 
 def sweep_step(orc: "Oracle", sc: SweepConfig, st: SweepState, move: int, parity: int, sweep: int,
                prop_u=None, rj_logq=None, cold_logl=None):
     """One move over the bands of one parity.  prop_u [n_t][n_w][n_b][n_slot][8]
     and rj_logq [n_t][n_w][n_b][n_slot] give an RJ proposal (None: the prior);
-    cold_logl [n_w][n_b] receives the cold chain's band logL after tempering."""
+    cold_logl [n_w][n_b] receives the cold chain's band logL after tempering;
+    tempering also counts its accepted swaps per band and rung in st.swap_acc."""
     pu_a = np.ascontiguousarray(prop_u, np.float64) if prop_u is not None else None
     lq_a = np.ascontiguousarray(rj_logq, np.float64) if rj_logq is not None else None
     pu = _d(pu_a) if pu_a is not None else None
@@ -369,8 +392,26 @@ def sweep_step(orc: "Oracle", sc: SweepConfig, st: SweepState, move: int, parity
     rc = orc.lib.gblo_sweep_step(ctypes.byref(orc.cfg), ctypes.byref(sc), int(move), int(parity), int(sweep),
                                  _d(st.u), _i32(st.exists), _d(st.betas), _d(st.resid.view(np.float64)),
                                  _d(st.inv_psd), _d(st.group), _i32(st.group_count), _i64(st.stats), pu, lq,
-                                 _d(cold_logl) if cold_logl is not None else None)
+                                 _d(cold_logl) if cold_logl is not None else None, _i32(st.swap_acc))
     _check(rc, "sweep_step")
+
+
+def adapt_ladder(sc: SweepConfig, st: SweepState, sweep: int):
+    """each band's ladder from the swap acceptance counted since the last call
+    (Vousden-Farr-Mandel gap dynamics); clears st.swap_acc"""
+    rc = _load().gblo_sweep_adapt_ladder(ctypes.byref(sc), int(sweep), _d(st.betas), _i32(st.swap_acc))
+    _check(rc, "sweep_adapt_ladder")
+
+
+def shift_ownership(orc: "Oracle", sc: SweepConfig, st: SweepState, stats=None):
+    """cold-chain sources whose f0 left their band move to the neighbouring band
+    (lowest free slot), buffers updated; stats [2]: moved, no free slot"""
+    if stats is not None:
+        assert stats.dtype == np.int64 and stats.flags.c_contiguous
+    rc = orc.lib.gblo_sweep_shift_ownership(ctypes.byref(orc.cfg), ctypes.byref(sc), _d(st.u), _i32(st.exists),
+                                            _d(st.resid.view(np.float64)),
+                                            _i64(stats) if stats is not None else None)
+    _check(rc, "sweep_shift_ownership")
 
 
 def sweep_group(sc: SweepConfig, st: SweepState):
@@ -405,12 +446,17 @@ def band_loglike(orc: "Oracle", sc: SweepConfig, st: SweepState, t: int, w_src: 
 
 def sweep_full(orc: "Oracle", sc: SweepConfig, st: SweepState, sweep: int):
     """One full sweep in the library's order: group refresh (when due),
-    in-model (odd, even), RJ (odd, even), tempering (odd, even)."""
+    in-model (odd, even), RJ (odd, even), tempering (odd, even), then the
+    ladder adaptation and the ownership shift when the configuration asks."""
     if sc.group_every > 0 and sweep % sc.group_every == 0:
         sweep_group(sc, st)
     for move in (MOVE_INMODEL, MOVE_RJ, MOVE_PT):
         for parity in (1, 0):
             sweep_step(orc, sc, st, move, parity, sweep)
+    if sc.adapt_ladder:
+        adapt_ladder(sc, st, sweep)
+    if sc.shift_ownership:
+        shift_ownership(orc, sc, st, st.stats[8:])
 
 
 def psd_sweep_step(orc: "Oracle", pc: PsdSweepConfig, sweep: int, theta, logl, betas, data, resid, inv_psd, stats):

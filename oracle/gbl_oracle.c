@@ -616,6 +616,63 @@ int gblo_snr(const gblo_config* cfg, const double* params, int64_t B, int32_t N,
   return rc;
 }
 
+/* Overlap of two templates (Sec. 4 "Cataloging Operation": sources are
+ * grouped by their overlap; the overlap of templates a and b is the
+ * normalised inner product of eq. inner over A and E):
+ *   out[b] = (<a|a>, <b|b>, <a|b>, <a|b> / sqrt(<a|a> <b|b>))
+ * for width-N templates of params_a[b] and params_b[b], weighted by
+ * psd[psd_idx[b]]; bins outside the band contribute zero.  Undefined
+ * parameters give NaN; a zero template gives a NaN overlap (0/0). */
+int gblo_overlap(const gblo_config* cfg, const double* params_a, const double* params_b, int64_t B, int32_t N,
+                 const double* psd, int32_t n_psd, int32_t psd_is_inverse, const int32_t* psd_idx, double* out) {
+  int64_t k_min, nb;
+  gblo_band(cfg, &k_min, &nb);
+  if (N < 2 || (N & (N - 1))) return -2;
+  for (int64_t b = 0; b < B; b++)
+    if (psd_idx[b] < 0 || psd_idx[b] >= n_psd) return -1;
+  const double f4 = 4.0 / cfg->T;
+#pragma omp parallel for schedule(dynamic, 4)
+  for (int64_t b = 0; b < B; b++) {
+    const double* pa = params_a + 8 * b;
+    const double* pb = params_b + 8 * b;
+    double* o = out + 4 * b;
+    if (!params_finite(cfg, pa) || !params_finite(cfg, pb)) {
+      o[0] = o[1] = o[2] = o[3] = NAN;
+      continue;
+    }
+    cplx* ha = (cplx*)malloc(sizeof(cplx) * 2 * N);
+    cplx* hb = (cplx*)malloc(sizeof(cplx) * 2 * N);
+    int64_t ka, kb;
+    waveform_one(cfg, pa, N, ha, ha + N, NULL, &ka);
+    waveform_one(cfg, pb, N, hb, hb + N, NULL, &kb);
+    const double* S = psd + (int64_t)psd_idx[b] * 2 * nb;
+    double aa = 0, bb = 0, ab = 0;
+    for (int c = 0; c < 2; c++) {
+      for (int j = 0; j < N; j++) {
+        int64_t k = ka + j;
+        if (k < k_min || k >= k_min + nb) continue;
+        double w = psd_is_inverse ? S[c * nb + (k - k_min)] : 1.0 / S[c * nb + (k - k_min)];
+        aa += creal(conj(ha[c * N + j]) * ha[c * N + j]) * w;
+        int64_t jb = k - kb;
+        if (jb >= 0 && jb < N) ab += creal(conj(ha[c * N + j]) * hb[c * N + jb]) * w;
+      }
+      for (int j = 0; j < N; j++) {
+        int64_t k = kb + j;
+        if (k < k_min || k >= k_min + nb) continue;
+        double w = psd_is_inverse ? S[c * nb + (k - k_min)] : 1.0 / S[c * nb + (k - k_min)];
+        bb += creal(conj(hb[c * N + j]) * hb[c * N + j]) * w;
+      }
+    }
+    o[0] = f4 * aa;
+    o[1] = f4 * bb;
+    o[2] = f4 * ab;
+    o[3] = o[2] / sqrt(o[0] * o[1]);
+    free(ha);
+    free(hb);
+  }
+  return 0;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Residual update: residual[res_idx[b]] += sign * (A, E) of template b,     */
 /* clipped to the band.  Used to build data d = sum h + n and residuals.     */
@@ -718,6 +775,11 @@ typedef struct {
   double stretch_a;
   uint64_t seed;
   double prior_lo[8], prior_hi[8]; /* f0 bounds unused (per band) */
+  /* after the tempering step of every sweep: */
+  int32_t adapt_ladder;    /* 1: adapt each band's ladder (gblo_sweep_adapt_ladder) */
+  int32_t shift_ownership; /* 1: move cold-chain sources to the band their f0 now lies in */
+  double adapt_lag;        /* t0 of the adaptation's decay t0 / (t + t0) */
+  double adapt_time;       /* nu: the adaptation's time scale */
 } gblo_sweep_config;
 
 #define MOVE_INMODEL 0
@@ -905,10 +967,14 @@ static double log_box_volume(const gblo_config* cfg, const gblo_sweep_config* sc
   return v;
 }
 
+/* One band loop of Alg. gb1 for chain (t, w, b).  It reads only the
+ * opposite-parity cold-chain buffer; at t = 0 the change of the band's
+ * sources is returned in *dsum_out (window of bands b-1..b+1, owned by the
+ * caller) for the caller to add to the own-parity buffer. */
 static void band_loop(const gblo_config* cfg, const gblo_sweep_config* sc, int move, int64_t sweep, int t, int w,
-                      int b, double* u, int32_t* exists, const double* betas, double* resid, const double* inv_psd,
-                      const double* group, const int32_t* group_count, int64_t* stats, const double* prop_u,
-                      const double* rj_logq) {
+                      int b, double* u, int32_t* exists, const double* betas, const double* resid,
+                      const double* inv_psd, const double* group, const int32_t* group_count, int64_t* stats,
+                      const double* prop_u, const double* rj_logq, window_t* dsum_out) {
   int64_t k_min, nb;
   gblo_band(cfg, &k_min, &nb);
   int par = b & 1;
@@ -1035,15 +1101,15 @@ static void band_loop(const gblo_config* cfg, const gblo_sweep_config* sc, int m
       }
     }
   }
-  /* cold chain: write the change of the band's sources back to its own buffer */
+  /* cold chain: the change of the band's sources, for its own buffer */
   if (t == 0) {
-    cplx* own = (cplx*)(resid + ((int64_t)par * sc->n_walkers + w) * 2 * nb * 2);
-    window_store_add(k_min, nb, &dsum, own);
+    *dsum_out = dsum;
+  } else {
+    free(dsum.r[0]);
+    free(dsum.r[1]);
   }
   free(win.r[0]);
   free(win.r[1]);
-  free(dsum.r[0]);
-  free(dsum.r[1]);
 }
 
 /* band log-likelihood of the source set (t, w_src, b) against walker w_res's
@@ -1120,9 +1186,13 @@ double gblo_pt_log_alpha(double bI, double bII, double lnL_im, double lnL_in, do
 
 /* Alg. gb2 for band b and ensemble index i: swaps from the hottest pair down,
  * accepted with the residual-aware ratio (eq. temp-final). */
+/* It reads only the opposite-parity cold-chain buffer; an accepted swap at
+ * t = 1 returns the change of walker w_0's cold-chain sources in *dw_out
+ * (dw_out->r[0] stays NULL otherwise) for the caller to add to the
+ * own-parity buffer of walker *w0_out. */
 static void pt_chain(const gblo_config* cfg, const gblo_sweep_config* sc, int64_t sweep, int b, int i, double* u,
-                     int32_t* exists, const double* betas, double* resid, const double* inv_psd, int64_t* stats,
-                     double* cold_logl) {
+                     int32_t* exists, const double* betas, const double* resid, const double* inv_psd,
+                     int64_t* stats, double* cold_logl, window_t* dw_out, int* w0_out, int32_t* acc_t) {
   int64_t k_min, nb;
   gblo_band(cfg, &k_min, &nb);
   int nt = sc->n_temps;
@@ -1144,6 +1214,7 @@ static void pt_chain(const gblo_config* cfg, const gblo_sweep_config* sc, int64_
     stats[6]++;
     if (log(r) < la) {
       stats[7]++;
+      acc_t[t]++;
       if (t == 1) {
         /* new cold-chain sources for walker w_0: update its own-parity buffer */
         window_t dw;
@@ -1157,9 +1228,8 @@ static void pt_chain(const gblo_config* cfg, const gblo_sweep_config* sc, int64_
           if (exists[UIDX(sc, 1, wt[1], b, s)])
             window_add_template(cfg, k_min, nb, &dw, u + 8 * UIDX(sc, 1, wt[1], b, s), -1.0);
         }
-        window_store_add(k_min, nb, &dw, (cplx*)(resid + ((int64_t)(b & 1) * sc->n_walkers + wt[0]) * 2 * nb * 2));
-        free(dw.r[0]);
-        free(dw.r[1]);
+        *dw_out = dw;
+        *w0_out = wt[0];
       }
       swap_sets(sc, t, wt[t], t - 1, wt[t - 1], b, u, exists);
       Lc[t] = L1;
@@ -1180,23 +1250,144 @@ static void pt_chain(const gblo_config* cfg, const gblo_sweep_config* sc, int64_
  * candidate (empty slot) or at the current source (occupied slot).
  * cold_logl [n_w][n_b] (may be NULL): tempering writes the cold chain's band
  * log-likelihood after the swaps. */
+/* swap_acc [n_b][n_t] (may be NULL): tempering adds, per band, the number of
+ * accepted swaps between rungs t-1 and t at entry t. */
 int gblo_sweep_step(const gblo_config* cfg, const gblo_sweep_config* sc, int move, int parity, int64_t sweep,
                     double* u, int32_t* exists, const double* betas, double* resid, const double* inv_psd,
                     const double* group, const int32_t* group_count, int64_t* stats, const double* prop_u,
-                    const double* rj_logq, double* cold_logl) {
+                    const double* rj_logq, double* cold_logl, int32_t* swap_acc) {
   if (sc->n_slots > 64 || sc->n_slots < 1) return -1;
   if ((prop_u == NULL) != (rj_logq == NULL)) return -1;
-  for (int b = parity; b < sc->n_bands; b += 2) {
+  int64_t k_min, nb;
+  gblo_band(cfg, &k_min, &nb);
+  /* The units of one step -- band loops (t, w, b), or tempering chains
+   * (b, i) -- touch disjoint slots and read only the opposite-parity
+   * buffers, so they may run in any order; their cold-chain changes are then
+   * added to the own-parity buffers one by one in the sequential order (b,
+   * then t, w or i), which gives exactly the sums of a sequential loop. */
+  const int per_band = move == MOVE_PT ? sc->n_walkers : sc->n_temps * sc->n_walkers;
+  const int n_par_bands = (sc->n_bands - parity + 1) / 2;
+  const int64_t n_units = (int64_t)n_par_bands * per_band;
+  window_t* dw = (window_t*)calloc((size_t)(n_units > 0 ? n_units : 1), sizeof(window_t));
+  int* w0 = (int*)calloc((size_t)(n_units > 0 ? n_units : 1), sizeof(int));
+  int64_t* st = (int64_t*)calloc((size_t)(n_units > 0 ? n_units : 1) * 8, sizeof(int64_t));
+  int32_t* acc = (int32_t*)calloc((size_t)(n_units > 0 ? n_units : 1) * sc->n_temps, sizeof(int32_t));
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t q = 0; q < n_units; q++) {
+    const int b = parity + 2 * (int)(q / per_band);
+    const int r = (int)(q % per_band);
     if (move == MOVE_PT) {
-      for (int i = 0; i < sc->n_walkers; i++)
-        pt_chain(cfg, sc, sweep, b, i, u, exists, betas, resid, inv_psd, stats, cold_logl);
+      pt_chain(cfg, sc, sweep, b, r, u, exists, betas, resid, inv_psd, st + 8 * q, cold_logl, dw + q, w0 + q,
+               acc + (int64_t)sc->n_temps * q);
     } else {
-      for (int t = 0; t < sc->n_temps; t++)
-        for (int w = 0; w < sc->n_walkers; w++)
-          band_loop(cfg, sc, move, sweep, t, w, b, u, exists, betas, resid, inv_psd, group, group_count, stats,
-                    prop_u, rj_logq);
+      const int t = r / sc->n_walkers, w = r % sc->n_walkers;
+      band_loop(cfg, sc, move, sweep, t, w, b, u, exists, betas, resid, inv_psd, group, group_count, st + 8 * q,
+                prop_u, rj_logq, dw + q);
+      w0[q] = w;
     }
   }
+  for (int64_t q = 0; q < n_units; q++) {
+    for (int k = 0; k < 8; k++) stats[k] += st[8 * q + k];
+    if (swap_acc && move == MOVE_PT) {
+      const int b = parity + 2 * (int)(q / per_band);
+      for (int t = 0; t < sc->n_temps; t++) swap_acc[(int64_t)b * sc->n_temps + t] += acc[(int64_t)sc->n_temps * q + t];
+    }
+    if (dw[q].r[0]) {
+      const int b = parity + 2 * (int)(q / per_band);
+      cplx* own = (cplx*)(resid + ((int64_t)(b & 1) * sc->n_walkers + w0[q]) * 2 * nb * 2);
+      window_store_add(k_min, nb, dw + q, own);
+      free(dw[q].r[0]);
+      free(dw[q].r[1]);
+    }
+  }
+  free(dw);
+  free(w0);
+  free(st);
+  free(acc);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------
+ * Temperature-ladder adaptation (appendix "Parallel tempering in a
+ * residual-based analysis": each sub-band's ladder adapts on its own, after
+ * Vousden, Farr & Mandel 2016).  With T = 1/beta, the gaps between adjacent
+ * rungs evolve as S_j = ln(T_(j+1) - T_j), dS_j = kappa (A_j - A_(j+1)),
+ * kappa = t0 / (nu (t + t0)), A_j the fraction of accepted swaps between
+ * rungs j and j+1 at this sweep (swap_acc[b][j+1] / n_walkers), t the sweep
+ * index; the coldest (beta = 1) and hottest rungs stay fixed, the rungs in
+ * between are the coldest temperature plus the running sum of the new gaps.
+ * swap_acc is cleared afterwards.
+ * ------------------------------------------------------------------------ */
+int gblo_sweep_adapt_ladder(const gblo_sweep_config* sc, int64_t sweep, double* betas, int32_t* swap_acc) {
+  const int nt = sc->n_temps;
+  const double kappa = sc->adapt_lag / (sc->adapt_time * ((double)sweep + sc->adapt_lag));
+  double* gap = (double*)malloc(sizeof(double) * (nt > 1 ? nt : 1));
+  for (int b = 0; b < sc->n_bands; b++) {
+    double* bt = betas + (int64_t)b * nt;
+    int32_t* ac = swap_acc + (int64_t)b * nt;
+    if (nt > 2) {
+      /* new gaps of the rungs 0..nt-2 (the last rung does not move) */
+      for (int j = 0; j + 2 < nt; j++) {
+        const double A_lo = (double)ac[j + 1] / (double)sc->n_walkers; /* rungs j, j+1 */
+        const double A_hi = (double)ac[j + 2] / (double)sc->n_walkers; /* rungs j+1, j+2 */
+        gap[j] = (1.0 / bt[j + 1] - 1.0 / bt[j]) * exp(kappa * (A_lo - A_hi));
+      }
+      double T = 1.0 / bt[0];
+      for (int j = 0; j + 2 < nt; j++) {
+        T += gap[j];
+        bt[j + 1] = 1.0 / T;
+      }
+    }
+    for (int t = 0; t < nt; t++) ac[t] = 0;
+  }
+  free(gap);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------
+ * Sub-band ownership (Sec. 4 "Galactic binary search and parameter
+ * estimation"): samples may roam half a band into the neighbours; a
+ * cold-chain source whose f0 has left its band's nominal range [k_band0 +
+ * b N, k_band0 + (b+1) N) / T moves to the neighbouring band it now lies in,
+ * into that band's lowest free cold-chain slot (it stays if there is none).
+ * The source then belongs to the opposite parity: it is added back to the
+ * old parity's buffer and removed from the new one's.  Per walker, bands in
+ * increasing order, slots in increasing order.  stats (may be NULL): [0]
+ * sources moved, [1] sources that found no free slot.
+ * ------------------------------------------------------------------------ */
+int gblo_sweep_shift_ownership(const gblo_config* cfg, const gblo_sweep_config* sc, double* u, int32_t* exists,
+                               double* resid, int64_t* stats) {
+  int64_t k_min, nb;
+  gblo_band(cfg, &k_min, &nb);
+  const int S = sc->n_slots;
+  for (int w = 0; w < sc->n_walkers; w++)
+    for (int b = 0; b < sc->n_bands; b++)
+      for (int s = 0; s < S; s++) {
+        const int64_t ui = UIDX(sc, 0, w, b, s);
+        if (!exists[ui]) continue;
+        const double f0 = u[8 * ui + 1];
+        const double lo = (double)(sc->k_band0 + (int64_t)b * sc->N) / cfg->T;
+        const double hi = (double)(sc->k_band0 + (int64_t)(b + 1) * sc->N) / cfg->T;
+        int bb = f0 < lo ? b - 1 : (f0 >= hi ? b + 1 : b);
+        if (bb == b || bb < 0 || bb >= sc->n_bands) continue;
+        int s2 = -1;
+        for (int j = 0; j < S && s2 < 0; j++)
+          if (!exists[UIDX(sc, 0, w, bb, j)]) s2 = j;
+        if (s2 < 0) {
+          if (stats) stats[1]++;
+          continue;
+        }
+        const int64_t u2 = UIDX(sc, 0, w, bb, s2);
+        for (int k = 0; k < 8; k++) u[8 * u2 + k] = u[8 * ui + k];
+        exists[u2] = 1;
+        exists[ui] = 0;
+        double p[8];
+        u_to_params(u + 8 * u2, p);
+        const int32_t ri_old = (b & 1) * sc->n_walkers + w, ri_new = (bb & 1) * sc->n_walkers + w;
+        gblo_scatter_add(cfg, p, 1, sc->N, 1.0, resid, 2 * sc->n_walkers, &ri_old);
+        gblo_scatter_add(cfg, p, 1, sc->N, -1.0, resid, 2 * sc->n_walkers, &ri_new);
+        if (stats) stats[0]++;
+      }
   return 0;
 }
 

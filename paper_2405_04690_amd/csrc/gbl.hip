@@ -3,6 +3,7 @@
 // Argument checking, context set-up (tables, PSD basis, workspace) and kernel
 // launches.  Every compute entry point only enqueues on the context stream.
 #include <hip/hip_runtime.h>
+#include <hipcub/device/device_radix_sort.hpp>
 
 #include <cmath>
 #include <cstdio>
@@ -24,6 +25,9 @@ constexpr int64_t kMaxGrid = (int64_t)1 << 30;  // blocks per launch (grid.x lim
 constexpr int64_t kDecodeChunk = (int64_t)1 << 17; // pairs per decode pass (workspace 2^18 decoded sources, 111 MB)
 constexpr int64_t kPsdBatch = 4096;             // parameter sets per PSD-likelihood launch pair
 constexpr int kBucketCap = 1 << 20;             // templates per bucketed (uneven-width) launch group
+constexpr int64_t kDetCap = (int64_t)1 << 22;    // deterministic scatter: slice elements per channel and chunk
+                                                 // (128 MB of slices; 2^22 / N templates per chunk)
+constexpr int64_t kDetMaxChunk = kDetCap / 128;
 
 int width_slot(int N) {
   for (int i = 0; i < kNumWidths; i++)
@@ -42,6 +46,8 @@ struct gbl_ctx {
   gbl::WaveTables<float> tables32[kNumWidths];  // mixed precision response
   double* psd_P1;
   double* psd_P2;
+  double* psd_P3;    // foreground factors (Sec. 3): 3 x^2 sin^2 x f^(-7/3)
+  double* psd_LF;    // ln f
   double* psd_work;
   int* counts;       // [4 widths] templates per width bucket
   int32_t* perm;     // [4 widths][kBucketCap] template indices per width
@@ -50,6 +56,13 @@ struct gbl_ctx {
   int32_t* route_lists;   // [4 widths][kBucketCap]
   int* host_counts;       // pinned [8]: device-side counts read back for exact grids
   gbl::Src* src_ws;       // [2 kDecodeChunk] decoded sources of one chunk of pairs
+  // deterministic scatter (GBL_DETERMINISTIC only)
+  cd* det_ws;             // [2][kDetCap] A, E slices of one chunk of templates
+  int64_t* det_start;     // [kDetMaxChunk]
+  uint64_t* det_keys;     // [2][kDetMaxChunk] sort keys in / out
+  int32_t* det_vals;      // [2][kDetMaxChunk] template slots in / out
+  void* det_sort_tmp;
+  size_t det_sort_bytes;
   std::string err;
 };
 
@@ -98,6 +111,8 @@ static void release(gbl_ctx* ctx) {
     if (ctx->table_mem[i]) (void)hipFree(ctx->table_mem[i]);
   if (ctx->psd_P1) (void)hipFree(ctx->psd_P1);
   if (ctx->psd_P2) (void)hipFree(ctx->psd_P2);
+  if (ctx->psd_P3) (void)hipFree(ctx->psd_P3);
+  if (ctx->psd_LF) (void)hipFree(ctx->psd_LF);
   if (ctx->psd_work) (void)hipFree(ctx->psd_work);
   if (ctx->counts) (void)hipFree(ctx->counts);
   if (ctx->perm) (void)hipFree(ctx->perm);
@@ -105,6 +120,11 @@ static void release(gbl_ctx* ctx) {
   if (ctx->route_lists) (void)hipFree(ctx->route_lists);
   if (ctx->host_counts) (void)hipHostFree(ctx->host_counts);
   if (ctx->src_ws) (void)hipFree(ctx->src_ws);
+  if (ctx->det_ws) (void)hipFree(ctx->det_ws);
+  if (ctx->det_start) (void)hipFree(ctx->det_start);
+  if (ctx->det_keys) (void)hipFree(ctx->det_keys);
+  if (ctx->det_vals) (void)hipFree(ctx->det_vals);
+  if (ctx->det_sort_tmp) (void)hipFree(ctx->det_sort_tmp);
 }
 
 extern "C" int gbl_create(gbl_ctx** out, const gbl_config* cfg, void* hip_stream) {
@@ -112,7 +132,7 @@ extern "C" int gbl_create(gbl_ctx** out, const gbl_config* cfg, void* hip_stream
   *out = nullptr;
   if (!cfg) return GBL_EINVAL;
   if (!(cfg->T > 0) || !(cfg->dt > 0) || !(cfg->L > 0) || !(cfg->f_lo > 0) || !(cfg->f_hi > cfg->f_lo) ||
-      cfg->f_hi > 0.5 / cfg->dt || (cfg->flags & ~GBL_MIXED_UNROUTED) != 0 ||
+      cfg->f_hi > 0.5 / cfg->dt || (cfg->flags & ~(GBL_MIXED_UNROUTED | GBL_DETERMINISTIC)) != 0 ||
       ((cfg->flags & GBL_MIXED_UNROUTED) && cfg->precision != GBL_MIXED))
     return GBL_EINVAL;
   if (cfg->precision != GBL_FP64 && cfg->precision != GBL_MIXED) return GBL_EUNSUPPORTED;
@@ -161,6 +181,7 @@ extern "C" int gbl_create(gbl_ctx** out, const gbl_config* cfg, void* hip_stream
   }
   size_t nbb = sizeof(double) * (size_t)g.n_bins;
   if (hipMalloc(&ctx->psd_P1, nbb) != hipSuccess || hipMalloc(&ctx->psd_P2, nbb) != hipSuccess ||
+      hipMalloc(&ctx->psd_P3, nbb) != hipSuccess || hipMalloc(&ctx->psd_LF, nbb) != hipSuccess ||
       hipMalloc(&ctx->psd_work, sizeof(double) * 2 * gbl::kPsdChunks * kPsdBatch) != hipSuccess ||
       hipMalloc(&ctx->counts, sizeof(int) * kNumWidths) != hipSuccess ||
       hipMalloc(&ctx->perm, sizeof(int32_t) * (size_t)kNumWidths * kBucketCap) != hipSuccess ||
@@ -172,8 +193,24 @@ extern "C" int gbl_create(gbl_ctx** out, const gbl_config* cfg, void* hip_stream
     delete ctx;
     return GBL_EHIP;
   }
+  if (cfg->flags & GBL_DETERMINISTIC) {
+    size_t tmp = 0;
+    if (hipcub::DeviceRadixSort::SortPairs(nullptr, tmp, (const uint64_t*)nullptr, (uint64_t*)nullptr,
+                                           (const int32_t*)nullptr, (int32_t*)nullptr, (int)kDetMaxChunk, 0, 64,
+                                           ctx->stream) != hipSuccess ||
+        hipMalloc(&ctx->det_ws, sizeof(cd) * 2 * kDetCap) != hipSuccess ||
+        hipMalloc(&ctx->det_start, sizeof(int64_t) * kDetMaxChunk) != hipSuccess ||
+        hipMalloc(&ctx->det_keys, sizeof(uint64_t) * 2 * kDetMaxChunk) != hipSuccess ||
+        hipMalloc(&ctx->det_vals, sizeof(int32_t) * 2 * kDetMaxChunk) != hipSuccess ||
+        hipMalloc(&ctx->det_sort_tmp, tmp > 0 ? tmp : 1) != hipSuccess) {
+      release(ctx);
+      delete ctx;
+      return GBL_EHIP;
+    }
+    ctx->det_sort_bytes = tmp;
+  }
   hipLaunchKernelGGL(gbl::k_init_psd_basis, dim3((unsigned)((g.n_bins + 255) / 256)), dim3(256), 0, ctx->stream,
-                     g.k_min, g.n_bins, g.T, g.L, ctx->psd_P1, ctx->psd_P2);
+                     g.k_min, g.n_bins, g.T, g.L, ctx->psd_P1, ctx->psd_P2, ctx->psd_P3, ctx->psd_LF);
   if (hipGetLastError() != hipSuccess || hipStreamSynchronize(ctx->stream) != hipSuccess) {
     release(ctx);
     delete ctx;
@@ -380,6 +417,71 @@ struct LaunchScatter {
   }
 };
 
+// deterministic scatter: chunks of kDetCap / N templates, each built into the
+// workspace, sorted by (residual, start bin) and gathered bin by bin
+template <int N, typename F>
+static int det_scatter(gbl_ctx* ctx, const double* params, int64_t b0, int64_t nb, double sign, cd* residual,
+                       int n_res, const int32_t* ri) {
+  const int64_t chunk = kDetCap / N;
+  uint64_t* keys_in = ctx->det_keys;
+  uint64_t* keys_out = ctx->det_keys + kDetMaxChunk;
+  int32_t* vals_in = ctx->det_vals;
+  int32_t* vals_out = ctx->det_vals + kDetMaxChunk;
+  for (int64_t c0 = 0; c0 < nb; c0 += chunk) {
+    const int64_t n = nb - c0 < chunk ? nb - c0 : chunk;
+    hipLaunchKernelGGL(gbl::k_det_keys, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, ctx->stream, ctx->geo,
+                       params, b0 + c0, n, N, ri, n_res, keys_in, vals_in);
+    hipLaunchKernelGGL((gbl::k_det_slices<N, F>), dim3((unsigned)n), dim3(gbl::block_threads<N>()), 0, ctx->stream,
+                       ctx->geo, tables_for<N, F>(ctx), params, b0 + c0, ctx->det_ws, kDetCap, ctx->det_start);
+    size_t bytes = 0;
+    if (hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, (const uint64_t*)keys_in, keys_out,
+                                           (const int32_t*)vals_in, vals_out, (int)n, 0, 64, ctx->stream) !=
+            hipSuccess ||
+        bytes > ctx->det_sort_bytes)
+      return fail(ctx, GBL_EHIP, "gb_scatter_add: sort workspace too small%s");
+    bytes = ctx->det_sort_bytes;
+    if (hipcub::DeviceRadixSort::SortPairs(ctx->det_sort_tmp, bytes, (const uint64_t*)keys_in, keys_out,
+                                           (const int32_t*)vals_in, vals_out, (int)n, 0, 64, ctx->stream) !=
+        hipSuccess)
+      return fail(ctx, GBL_EHIP, "gb_scatter_add: sort failed%s");
+    hipLaunchKernelGGL((gbl::k_det_gather<N>), dim3((unsigned)n), dim3(gbl::block_threads<N>()), 0, ctx->stream,
+                       ctx->geo, (const uint64_t*)keys_out, (const int32_t*)vals_out, n, (const cd*)ctx->det_ws,
+                       kDetCap, sign, residual);
+  }
+  return GBL_OK;
+}
+
+template <int N>
+struct LaunchDetScatter {
+  static void run(gbl_ctx* ctx, const double* params, int64_t b0, int64_t nb, double sign, cd* residual, int n_res,
+                  const int32_t* ri, int* rc) {
+    if (ctx->cfg.precision == GBL_MIXED)
+      *rc = det_scatter<N, float>(ctx, params, b0, nb, sign, residual, n_res, ri);
+    else
+      *rc = det_scatter<N, double>(ctx, params, b0, nb, sign, residual, n_res, ri);
+  }
+};
+
+template <int N>
+struct LaunchSnr {
+  static void run(gbl_ctx* ctx, const double* params, int64_t b0, int64_t nb, const double* psd, int n_psd,
+                  int psd_inv, const int32_t* psd_idx, const cd* data, int n_data, const int32_t* data_idx,
+                  double* snr_opt, double* snr_obs) {
+    hipLaunchKernelGGL((gbl::k_snr<N>), dim3((unsigned)nb), dim3(gbl::block_threads<N>()), 0, ctx->stream, ctx->geo,
+                       tables_for<N, double>(ctx), params, b0, psd, n_psd, psd_inv, psd_idx, data, n_data, data_idx,
+                       snr_opt, snr_obs);
+  }
+};
+
+template <int N>
+struct LaunchOverlap {
+  static void run(gbl_ctx* ctx, const double* pa, const double* pb, int64_t b0, int64_t nb, const double* psd,
+                  int n_psd, int psd_inv, const int32_t* psd_idx, double* out) {
+    hipLaunchKernelGGL((gbl::k_overlap<N>), dim3((unsigned)nb), dim3(gbl::block_threads<N>()), 0, ctx->stream,
+                       ctx->geo, tables_for<N, double>(ctx), pa, pb, b0, psd, n_psd, psd_inv, psd_idx, out);
+  }
+};
+
 // device-side bucketing of templates [b0, b0 + nb) by width
 static void bucket_widths(gbl_ctx* ctx, const int32_t* widths, int64_t b0, int64_t nb, double* bad_out,
                           int64_t* bad_start) {
@@ -506,45 +608,78 @@ extern "C" int gb_waveform_var(gbl_ctx* ctx, const double* params, const int32_t
   return check_launch(ctx, "gb_waveform_var");
 }
 
-extern "C" int gb_psd_eval(gbl_ctx* ctx, const double* noise, int64_t P, int32_t psd_flags, double* S) {
+static gbl::PsdBasis psd_basis(const gbl_ctx* ctx) {
+  return gbl::PsdBasis{ctx->psd_P1, ctx->psd_P2, ctx->psd_P3, ctx->psd_LF, ctx->geo.k_min, ctx->cfg.T};
+}
+
+static void psd_eval_launch(gbl_ctx* ctx, const double* noise, int n_par, int64_t P, int inverse, double* S) {
+  if (n_par == 9)
+    hipLaunchKernelGGL(gbl::k_psd_eval<9>, gbl::row_grid(ctx->geo.n_bins, 2 * P), dim3(256), 0, ctx->stream,
+                       ctx->geo.n_bins, psd_basis(ctx), noise, P, inverse, S);
+  else
+    hipLaunchKernelGGL(gbl::k_psd_eval<4>, gbl::row_grid(ctx->geo.n_bins, 2 * P), dim3(256), 0, ctx->stream,
+                       ctx->geo.n_bins, psd_basis(ctx), noise, P, inverse, S);
+}
+
+extern "C" int gb_psd_eval_n(gbl_ctx* ctx, const double* noise, int32_t n_par, int64_t P, int32_t psd_flags,
+                             double* S) {
   if (!ctx) return GBL_EINVAL;
   if (P < 0) return fail(ctx, GBL_EINVAL, "gb_psd_eval: P < 0%s");
+  if (n_par != 4 && n_par != 9) return fail(ctx, GBL_EINVAL, "gb_psd_eval: n_par must be 4 or 9%s");
   if (psd_flags & ~GBL_PSD_INVERSE) return fail(ctx, GBL_EINVAL, "gb_psd_eval: unknown psd flag%s");
   if (P == 0) return GBL_OK;
   if (!noise || !S) return fail(ctx, GBL_EINVAL, "gb_psd_eval: null pointer%s");
-  hipLaunchKernelGGL(gbl::k_psd_eval, gbl::row_grid(ctx->geo.n_bins, 2 * P), dim3(256), 0, ctx->stream,
-                     ctx->geo.n_bins, ctx->psd_P1, ctx->psd_P2, noise, P, (psd_flags & GBL_PSD_INVERSE) ? 1 : 0, S);
+  psd_eval_launch(ctx, noise, n_par, P, (psd_flags & GBL_PSD_INVERSE) ? 1 : 0, S);
   return check_launch(ctx, "gb_psd_eval");
+}
+
+extern "C" int gb_psd_eval(gbl_ctx* ctx, const double* noise, int64_t P, int32_t psd_flags, double* S) {
+  return gb_psd_eval_n(ctx, noise, 4, P, psd_flags, S);
 }
 
 // PSD likelihood of P parameter sets: partial sums in groups of kPsdSets sets (the
 // remainder one set per block), then the fixed-order final sum per set.
-static void psd_loglike_launch(gbl_ctx* ctx, const cd* residual, int n_res, const double* noise,
+template <int NP>
+static void psd_partial_launch(gbl_ctx* ctx, const cd* residual, int n_res, const double* noise,
+                               const int32_t* res_idx, int64_t p0, int64_t np) {
+  const int64_t ng = np / gbl::kPsdSets, rest = np - ng * gbl::kPsdSets;
+  if (ng > 0)
+    hipLaunchKernelGGL((gbl::k_psd_partial<gbl::kPsdSets, NP>), dim3(gbl::kPsdChunks, (unsigned)ng),
+                       dim3(gbl::kPsdBlock), 0, ctx->stream, ctx->geo.n_bins, psd_basis(ctx), residual, n_res, noise,
+                       res_idx, p0, p0, ctx->psd_work);
+  if (rest > 0)
+    hipLaunchKernelGGL((gbl::k_psd_partial<1, NP>), dim3(gbl::kPsdChunks, (unsigned)rest), dim3(gbl::kPsdBlock), 0,
+                       ctx->stream, ctx->geo.n_bins, psd_basis(ctx), residual, n_res, noise, res_idx, p0,
+                       p0 + ng * gbl::kPsdSets, ctx->psd_work);
+}
+
+static void psd_loglike_launch(gbl_ctx* ctx, const cd* residual, int n_res, const double* noise, int n_par,
                                const int32_t* res_idx, int64_t P, double* logl) {
   for (int64_t p0 = 0; p0 < P; p0 += kPsdBatch) {
     const int64_t np = P - p0 < kPsdBatch ? P - p0 : kPsdBatch;
-    const int64_t ng = np / gbl::kPsdSets, rest = np - ng * gbl::kPsdSets;
-    if (ng > 0)
-      hipLaunchKernelGGL(gbl::k_psd_partial<gbl::kPsdSets>, dim3(gbl::kPsdChunks, (unsigned)ng),
-                         dim3(gbl::kPsdBlock), 0, ctx->stream, ctx->geo.n_bins, ctx->psd_P1, ctx->psd_P2, residual,
-                         n_res, noise, res_idx, p0, p0, ctx->psd_work);
-    if (rest > 0)
-      hipLaunchKernelGGL(gbl::k_psd_partial<1>, dim3(gbl::kPsdChunks, (unsigned)rest), dim3(gbl::kPsdBlock), 0,
-                         ctx->stream, ctx->geo.n_bins, ctx->psd_P1, ctx->psd_P2, residual, n_res, noise, res_idx,
-                         p0, p0 + ng * gbl::kPsdSets, ctx->psd_work);
+    if (n_par == 9)
+      psd_partial_launch<9>(ctx, residual, n_res, noise, res_idx, p0, np);
+    else
+      psd_partial_launch<4>(ctx, residual, n_res, noise, res_idx, p0, np);
     hipLaunchKernelGGL(gbl::k_psd_final, dim3((unsigned)np), dim3(64), 0, ctx->stream, 1.0 / ctx->cfg.T,
                        ctx->psd_work, p0, logl);
   }
 }
 
-extern "C" int gb_psd_loglike(gbl_ctx* ctx, const double* residual, int32_t n_res, const double* noise,
-                              const int32_t* res_idx, int64_t P, double* logl) {
+extern "C" int gb_psd_loglike_n(gbl_ctx* ctx, const double* residual, int32_t n_res, const double* noise,
+                                int32_t n_par, const int32_t* res_idx, int64_t P, double* logl) {
   if (!ctx) return GBL_EINVAL;
   if (P < 0 || n_res < 1) return fail(ctx, GBL_EINVAL, "gb_psd_loglike: bad sizes%s");
+  if (n_par != 4 && n_par != 9) return fail(ctx, GBL_EINVAL, "gb_psd_loglike: n_par must be 4 or 9%s");
   if (P == 0) return GBL_OK;
   if (!residual || !noise || !res_idx || !logl) return fail(ctx, GBL_EINVAL, "gb_psd_loglike: null pointer%s");
-  psd_loglike_launch(ctx, (const cd*)residual, (int)n_res, noise, res_idx, P, logl);
+  psd_loglike_launch(ctx, (const cd*)residual, (int)n_res, noise, n_par, res_idx, P, logl);
   return check_launch(ctx, "gb_psd_loglike");
+}
+
+extern "C" int gb_psd_loglike(gbl_ctx* ctx, const double* residual, int32_t n_res, const double* noise,
+                              const int32_t* res_idx, int64_t P, double* logl) {
+  return gb_psd_loglike_n(ctx, residual, n_res, noise, 4, res_idx, P, logl);
 }
 
 extern "C" int gb_scatter_add(gbl_ctx* ctx, const double* params, int64_t B, int32_t N, double sign,
@@ -554,11 +689,72 @@ extern "C" int gb_scatter_add(gbl_ctx* ctx, const double* params, int64_t B, int
   if (width_slot(N) < 0) return fail(ctx, GBL_EUNSUPPORTED, "gb_scatter_add: unsupported N%s");
   if (B == 0) return GBL_OK;
   if (!params || !residual || !res_idx) return fail(ctx, GBL_EINVAL, "gb_scatter_add: null pointer%s");
+  if (ctx->cfg.flags & GBL_DETERMINISTIC) {
+    int rc = GBL_OK;
+    dispatch_width<LaunchDetScatter>(N, ctx, params, (int64_t)0, B, sign, (cd*)residual, (int)n_res, res_idx, &rc);
+    if (rc != GBL_OK) return rc;
+    return check_launch(ctx, "gb_scatter_add");
+  }
   for (int64_t b0 = 0; b0 < B; b0 += kMaxGrid) {
     int64_t nb = B - b0 < kMaxGrid ? B - b0 : kMaxGrid;
     dispatch_width<LaunchScatter>(N, ctx, params, b0, nb, sign, (cd*)residual, (int)n_res, res_idx);
   }
   return check_launch(ctx, "gb_scatter_add");
+}
+
+extern "C" int gb_inner(gbl_ctx* ctx, const double* A, const double* E, const int64_t* start_bin, int32_t N,
+                        const double* residual, int32_t n_res, const double* psd, int32_t n_psd, int32_t psd_flags,
+                        const int32_t* res_idx, const int32_t* psd_idx, int64_t B, double* out) {
+  if (!ctx) return GBL_EINVAL;
+  if (B < 0 || N < 1 || n_res < 1 || n_psd < 1) return fail(ctx, GBL_EINVAL, "gb_inner: bad sizes%s");
+  if (psd_flags & ~GBL_PSD_INVERSE) return fail(ctx, GBL_EINVAL, "gb_inner: unknown psd flag%s");
+  if (B == 0) return GBL_OK;
+  if (!A || !E || !start_bin || !residual || !psd || !res_idx || !psd_idx || !out)
+    return fail(ctx, GBL_EINVAL, "gb_inner: null pointer%s");
+  for (int64_t b0 = 0; b0 < B; b0 += kMaxGrid * gbl::kInnerWaves) {
+    const int64_t nb = B - b0 < kMaxGrid * gbl::kInnerWaves ? B - b0 : kMaxGrid * gbl::kInnerWaves;
+    hipLaunchKernelGGL(gbl::k_inner, dim3((unsigned)((nb + gbl::kInnerWaves - 1) / gbl::kInnerWaves)),
+                       dim3(gbl::kInnerWaves * gbl::kWave), 0, ctx->stream, ctx->geo,
+                       (const cd*)A + b0 * N, (const cd*)E + b0 * N, start_bin + b0, (int)N, (const cd*)residual,
+                       (int)n_res, psd, (int)n_psd, (psd_flags & GBL_PSD_INVERSE) ? 1 : 0, res_idx + b0,
+                       psd_idx + b0, nb, out + 2 * b0);
+  }
+  return check_launch(ctx, "gb_inner");
+}
+
+extern "C" int gb_overlap(gbl_ctx* ctx, const double* params_a, const double* params_b, int32_t N,
+                          const double* psd, int32_t n_psd, int32_t psd_flags, const int32_t* psd_idx, int64_t B,
+                          double* out) {
+  if (!ctx) return GBL_EINVAL;
+  if (B < 0 || n_psd < 1) return fail(ctx, GBL_EINVAL, "gb_overlap: bad sizes%s");
+  if (width_slot(N) < 0) return fail(ctx, GBL_EUNSUPPORTED, "gb_overlap: unsupported N%s");
+  if (psd_flags & ~GBL_PSD_INVERSE) return fail(ctx, GBL_EINVAL, "gb_overlap: unknown psd flag%s");
+  if (B == 0) return GBL_OK;
+  if (!params_a || !params_b || !psd || !psd_idx || !out) return fail(ctx, GBL_EINVAL, "gb_overlap: null pointer%s");
+  for (int64_t b0 = 0; b0 < B; b0 += kMaxGrid) {
+    const int64_t nb = B - b0 < kMaxGrid ? B - b0 : kMaxGrid;
+    dispatch_width<LaunchOverlap>(N, ctx, params_a, params_b, b0, nb, psd, (int)n_psd,
+                                  (psd_flags & GBL_PSD_INVERSE) ? 1 : 0, psd_idx, out);
+  }
+  return check_launch(ctx, "gb_overlap");
+}
+
+extern "C" int gb_snr(gbl_ctx* ctx, const double* params, int64_t B, int32_t N, const double* psd, int32_t n_psd,
+                      int32_t psd_flags, const int32_t* psd_idx, const double* data, int32_t n_data,
+                      const int32_t* data_idx, double* snr_opt, double* snr_obs) {
+  if (!ctx) return GBL_EINVAL;
+  if (B < 0 || n_psd < 1 || (data && n_data < 1)) return fail(ctx, GBL_EINVAL, "gb_snr: bad sizes%s");
+  if (width_slot(N) < 0) return fail(ctx, GBL_EUNSUPPORTED, "gb_snr: unsupported N%s");
+  if (psd_flags & ~GBL_PSD_INVERSE) return fail(ctx, GBL_EINVAL, "gb_snr: unknown psd flag%s");
+  if (B == 0) return GBL_OK;
+  if (!params || !psd || !psd_idx || !snr_opt || (data && (!data_idx || !snr_obs)))
+    return fail(ctx, GBL_EINVAL, "gb_snr: null pointer%s");
+  for (int64_t b0 = 0; b0 < B; b0 += kMaxGrid) {
+    const int64_t nb = B - b0 < kMaxGrid ? B - b0 : kMaxGrid;
+    dispatch_width<LaunchSnr>(N, ctx, params, b0, nb, psd, (int)n_psd, (psd_flags & GBL_PSD_INVERSE) ? 1 : 0,
+                              psd_idx, (const cd*)data, (int)n_data, data_idx, snr_opt, data ? snr_obs : nullptr);
+  }
+  return check_launch(ctx, "gb_snr");
 }
 
 extern "C" int gb_make_noise(gbl_ctx* ctx, const double* S, const double* normals, int64_t n, double* out) {
@@ -590,6 +786,8 @@ static int sweep_check(gbl_ctx* ctx, const gbl_sweep_config* c, const gbl_sweep_
     return fail(ctx, GBL_EINVAL, "sweep: prop_u and rj_logq must be given together%s");
   if (st->spec_pool && (!st->pool_flags || st->pool_size < 1))
     return fail(ctx, GBL_EINVAL, "sweep: spectrum pool without flags or size%s");
+  if (c->adapt_ladder && (!st->swap_acc || !(c->adapt_lag > 0.0) || !(c->adapt_time > 0.0)))
+    return fail(ctx, GBL_EINVAL, "sweep: ladder adaptation needs swap_acc and positive adapt_lag, adapt_time%s");
   if (ctx->cfg.precision != GBL_FP64) return fail(ctx, GBL_EUNSUPPORTED, "sweep: FP64 contexts only%s");
   return GBL_OK;
 }
@@ -621,6 +819,7 @@ static gbl::SweepArgs sweep_args(const gbl_sweep_config* c, const gbl_sweep_stat
   a.prop_u = st->prop_u;
   a.rj_logq = st->rj_logq;
   a.cold_logl = st->cold_logl;
+  a.swap_acc = st->swap_acc;
   a.spec_pool = (cd*)st->spec_pool;
   a.pool_flags = st->pool_flags;
   a.pool_size = st->pool_size;
@@ -638,6 +837,29 @@ static void launch_sweep_step(gbl_ctx* ctx, const gbl::SweepArgs& a, int move, i
   else
     hipLaunchKernelGGL((gbl::k_sweep_band<N>), dim3((unsigned)(nbp * a.n_w * a.n_t)), dim3(gbl::block_threads<N>()),
                        0, ctx->stream, ctx->geo, tb, a, move, parity);
+}
+
+static void sweep_adapt(gbl_ctx* ctx, const gbl_sweep_config* c, const gbl::SweepArgs& a) {
+  hipLaunchKernelGGL(gbl::k_sweep_adapt, dim3((unsigned)((a.n_b + 63) / 64)), dim3(64), 0, ctx->stream, a,
+                     c->adapt_lag, c->adapt_time);
+}
+
+static void sweep_shift(gbl_ctx* ctx, const gbl_sweep_config* c, const gbl::SweepArgs& a) {
+  switch (c->N) {
+    case 128:
+      hipLaunchKernelGGL(gbl::k_sweep_shift<128>, dim3((unsigned)a.n_w), dim3(gbl::block_threads<128>()), 0,
+                         ctx->stream, ctx->geo, tables_for<128, double>(ctx), a);
+      break;
+    case 256:
+      hipLaunchKernelGGL(gbl::k_sweep_shift<256>, dim3((unsigned)a.n_w), dim3(gbl::block_threads<256>()), 0,
+                         ctx->stream, ctx->geo, tables_for<256, double>(ctx), a);
+      break;
+    case 512:
+      hipLaunchKernelGGL(gbl::k_sweep_shift<512>, dim3((unsigned)a.n_w), dim3(gbl::block_threads<512>()), 0,
+                         ctx->stream, ctx->geo, tables_for<512, double>(ctx), a);
+      break;
+    default: break;
+  }
 }
 
 static void sweep_step(gbl_ctx* ctx, const gbl_sweep_config* c, const gbl::SweepArgs& a, int move, int parity) {
@@ -669,6 +891,24 @@ extern "C" int gb_sweep_group(gbl_ctx* ctx, const gbl_sweep_config* cfg, const g
   return check_launch(ctx, "gb_sweep_group");
 }
 
+extern "C" int gb_sweep_adapt_ladder(gbl_ctx* ctx, const gbl_sweep_config* cfg, const gbl_sweep_state* st) {
+  if (!ctx) return GBL_EINVAL;
+  int rc = sweep_check(ctx, cfg, st);
+  if (rc) return rc;
+  if (!st->swap_acc || !(cfg->adapt_lag > 0.0) || !(cfg->adapt_time > 0.0))
+    return fail(ctx, GBL_EINVAL, "gb_sweep_adapt_ladder: needs swap_acc and positive adapt_lag, adapt_time%s");
+  sweep_adapt(ctx, cfg, sweep_args(cfg, st));
+  return check_launch(ctx, "gb_sweep_adapt_ladder");
+}
+
+extern "C" int gb_sweep_shift_ownership(gbl_ctx* ctx, const gbl_sweep_config* cfg, const gbl_sweep_state* st) {
+  if (!ctx) return GBL_EINVAL;
+  int rc = sweep_check(ctx, cfg, st);
+  if (rc) return rc;
+  sweep_shift(ctx, cfg, sweep_args(cfg, st));
+  return check_launch(ctx, "gb_sweep_shift_ownership");
+}
+
 extern "C" int gb_sweep_advance(gbl_ctx* ctx, const gbl_sweep_state* st) {
   if (!ctx) return GBL_EINVAL;
   if (!st || !st->sweep_counter) return fail(ctx, GBL_EINVAL, "gb_sweep_advance: null state%s");
@@ -693,6 +933,8 @@ static int sweep_run_impl(gbl_ctx* ctx, const gbl_sweep_config* cfg, const gbl_s
       }
       for (int parity = 1; parity >= 0; parity--) sweep_step(ctx, cfg, a, move, parity);
     }
+    if (cfg->adapt_ladder) sweep_adapt(ctx, cfg, a);
+    if (cfg->shift_ownership) sweep_shift(ctx, cfg, a);
     hipLaunchKernelGGL(gbl::k_sweep_advance, dim3(1), dim3(64), 0, ctx->stream, st->sweep_counter);
   }
   return check_launch(ctx, "gb_sweep_run");
@@ -1001,9 +1243,10 @@ extern "C" int gbl_set_tuning(gbl_ctx* ctx, const gbl_tuning* t) {
 extern "C" int gb_psd_sweep_step(gbl_ctx* ctx, const gbl_psd_sweep_config* c, const gbl_psd_sweep_state* st) {
   if (!ctx) return GBL_EINVAL;
   if (!c || !st) return fail(ctx, GBL_EINVAL, "gb_psd_sweep_step: null config or state%s");
-  if (c->n_tn < 1 || c->n_walkers < 2 || c->n_walkers % 2 || !(c->stretch_a > 1.0))
+  if (c->n_tn < 1 || c->n_walkers < 2 || c->n_walkers % 2 || !(c->stretch_a > 1.0) ||
+      (c->n_par != 4 && c->n_par != 9))
     return fail(ctx, GBL_EINVAL, "gb_psd_sweep_step: configuration out of range%s");
-  for (int k = 0; k < 4; k++)
+  for (int k = 0; k < c->n_par; k++)
     if (!(c->prior_lo[k] < c->prior_hi[k])) return fail(ctx, GBL_EINVAL, "gb_psd_sweep_step: empty prior box%s");
   if (!st->theta || !st->logl || !st->betas || !st->data || !st->resid || !st->full_resid || !st->inv_psd ||
       !st->work || !st->res_idx || !st->stats || !st->sweep_counter)
@@ -1013,9 +1256,10 @@ extern "C" int gb_psd_sweep_step(gbl_ctx* ctx, const gbl_psd_sweep_config* c, co
   gbl::PsdArgs p;
   p.nt = nt;
   p.nw = nw;
+  p.np = c->n_par;
   p.a = c->stretch_a;
   p.seed = c->seed;
-  for (int k = 0; k < 4; k++) {
+  for (int k = 0; k < c->n_par; k++) {
     p.lo[k] = c->prior_lo[k];
     p.hi[k] = c->prior_hi[k];
   }
@@ -1031,24 +1275,23 @@ extern "C" int gb_psd_sweep_step(gbl_ctx* ctx, const gbl_psd_sweep_config* c, co
   const int n_all = nt * nw, n_half = nt * half;
   hipLaunchKernelGGL(gbl::k_psd_res_idx, dim3((n_all + 255) / 256), dim3(256), 0, ctx->stream, nt, nw, -1,
                      st->res_idx);
-  psd_loglike_launch(ctx, full, nw, st->theta, st->res_idx, n_all, st->logl);
+  psd_loglike_launch(ctx, full, nw, st->theta, p.np, st->res_idx, n_all, st->logl);
   // 3. stretch moves, half by half
   double* prop = st->work;
-  double* lprop = prop + 4 * (int64_t)n_half;
+  double* lprop = prop + (int64_t)p.np * n_half;
   double* lz = lprop + n_half;
   double* ok = lz + n_half;
   for (int h = 0; h < 2; h++) {
     hipLaunchKernelGGL(gbl::k_psd_propose, dim3((n_half + 255) / 256), dim3(256), 0, ctx->stream, p, h, prop, lz, ok);
     hipLaunchKernelGGL(gbl::k_psd_res_idx, dim3((n_half + 255) / 256), dim3(256), 0, ctx->stream, nt, nw, h,
                        st->res_idx);
-    psd_loglike_launch(ctx, full, nw, prop, st->res_idx, n_half, lprop);
+    psd_loglike_launch(ctx, full, nw, prop, p.np, st->res_idx, n_half, lprop);
     hipLaunchKernelGGL(gbl::k_psd_accept, dim3((n_half + 255) / 256), dim3(256), 0, ctx->stream, p, h,
                        (const double*)prop, (const double*)lprop, (const double*)lz, (const double*)ok);
   }
   // 4. vertical swaps, 5. the cold chain's 1/S
   hipLaunchKernelGGL(gbl::k_psd_swap, dim3((nw + 63) / 64), dim3(64), 0, ctx->stream, p);
-  hipLaunchKernelGGL(gbl::k_psd_eval, gbl::row_grid(nb, 2 * (int64_t)nw), dim3(256), 0, ctx->stream, nb,
-                     ctx->psd_P1, ctx->psd_P2, (const double*)st->theta, (int64_t)nw, 1, st->inv_psd);
+  psd_eval_launch(ctx, st->theta, p.np, (int64_t)nw, 1, st->inv_psd);
   return check_launch(ctx, "gb_psd_sweep_step");
 }
 

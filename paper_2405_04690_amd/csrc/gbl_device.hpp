@@ -648,62 +648,42 @@ __device__ __forceinline__ void dft4(cx<F>* x) {
 // the block.  Output X[k] sits at the digit-reversed position fft_pos<N>(k).
 //
 // LDS layout of element e of a series (against bank conflicts of the 16-byte
-// accesses): GBL_LDS_LAYOUT 0 pads one element per 16 (e + e/16); layouts 1
-// and 2 swizzle, e ^ X(e >> LB) with X linear over GF(2) (LB = 3 or 4),
-// chosen so that the butterfly reads/writes of every pass, the sample writes
-// and the digit-reversed read-out hit distinct banks within 8-lane (layout 1)
-// or 16-lane (layout 2) groups.  Linearity lets a butterfly address its four
-// elements as lds_pad(base) ^ lds_pad(ST r) with the second term a constant.
+// accesses): an XOR swizzle e ^ X(e >> 3) with X linear over GF(2), chosen so
+// that the butterfly reads/writes of every pass, the sample writes and the
+// digit-reversed read-out hit distinct banks within 8-lane groups.  Linearity
+// lets a butterfly address its four elements as lds_pad(base) ^ lds_pad(ST r)
+// with the second term a constant.
 // ---------------------------------------------------------------------------
-#ifndef GBL_LDS_LAYOUT
-#define GBL_LDS_LAYOUT 1
-#endif
-
 template <int N>
 struct LdsSwizzle {
-  static constexpr int LB = GBL_LDS_LAYOUT == 1 ? 3 : 4;
+  static constexpr int LB = 3;
   static constexpr int NBITS = (N == 128 ? 7 : N == 256 ? 8 : N == 512 ? 9 : 10) - LB;
   static constexpr int col(int j) {
-    if constexpr (GBL_LDS_LAYOUT == 1) {
-      constexpr int c128[] = {7, 5, 2, 4}, c256[] = {1, 6, 7, 1, 2}, c512[] = {3, 7, 3, 0, 6, 2},
-                    c1024[] = {1, 6, 5, 6, 6, 7, 2};
-      return N == 128 ? c128[j] : N == 256 ? c256[j] : N == 512 ? c512[j] : c1024[j];
-    } else {
-      constexpr int c128[] = {13, 10, 14}, c256[] = {13, 7, 14, 12}, c512[] = {11, 15, 10, 11, 9},
-                    c1024[] = {13, 11, 11, 6, 14, 2};
-      return N == 128 ? c128[j] : N == 256 ? c256[j] : N == 512 ? c512[j] : c1024[j];
-    }
+    constexpr int c128[] = {7, 5, 2, 4}, c256[] = {1, 6, 7, 1, 2}, c512[] = {3, 7, 3, 0, 6, 2},
+                  c1024[] = {1, 6, 5, 6, 6, 7, 2};
+    return N == 128 ? c128[j] : N == 256 ? c256[j] : N == 512 ? c512[j] : c1024[j];
   }
 };
 
 template <int N>
 __device__ __forceinline__ constexpr int lds_pad(int e) {
-  if constexpr (GBL_LDS_LAYOUT == 0) {
-    return e + (e >> 4);
-  } else {
-    using S = LdsSwizzle<N>;
-    int x = 0;
+  using S = LdsSwizzle<N>;
+  int x = 0;
 #pragma unroll
-    for (int j = 0; j < S::NBITS; j++) x ^= ((e >> (S::LB + j)) & 1) ? S::col(j) : 0;
-    return e ^ x;
-  }
+  for (int j = 0; j < S::NBITS; j++) x ^= ((e >> (S::LB + j)) & 1) ? S::col(j) : 0;
+  return e ^ x;
 }
 
 // address of element base + off where off's bits are clear in base (off a constant)
 template <int N>
 __device__ __forceinline__ int lds_pad_add(int base, int base_addr, int off) {
-  if constexpr (GBL_LDS_LAYOUT == 0) {
-    (void)base_addr;
-    return lds_pad<N>(base + off);
-  } else {
-    (void)base;
-    return base_addr ^ lds_pad<N>(off);
-  }
+  (void)base;
+  return base_addr ^ lds_pad<N>(off);
 }
 
 template <int N>
 constexpr int series_pitch() {
-  return GBL_LDS_LAYOUT == 0 ? N + N / 16 : N;
+  return N;
 }
 
 // threads per block for template width N: one sample and one bin per thread
@@ -753,7 +733,7 @@ __device__ __forceinline__ void fft_butterfly(cx<F>* b, const cx<F>* __restrict_
   constexpr int TWS = N / (R * ST);
   int grp = beta / ST, i = beta % ST;
   int base = grp * R * ST + i;
-  const int base_addr = GBL_LDS_LAYOUT == 0 ? 0 : lds_pad<N>(base);
+  const int base_addr = lds_pad<N>(base);
   cx<F> x[R];
 #pragma unroll
   for (int r = 0; r < R; r++) x[r] = b[lds_pad_add<N>(base, base_addr, ST * r)];

@@ -47,7 +47,11 @@ __global__ void k_init_wave_tables(int N, double T, double Lc, double* basis, cd
 // PSD basis of eq. psd, linear in (S_oms, S_acc):  S_n = S_oms P1 + S_acc P2,
 //   P1 = 8 sin^2 x (2 + cos x) (2 pi f/c)^2 [1 + (2 mHz/f)^4]
 //   P2 = 16 sin^2 x (3 + 2 cos x + cos 2x) (2 pi c f)^-2 [1 + (0.4 mHz/f)^2][1 + (f/8 mHz)^4]
-__global__ void k_init_psd_basis(int64_t k_min, int64_t nb, double T, double L, double* P1, double* P2) {
+// and the parameter-free factors of the Galactic foreground (Sec. 3):
+//   S_fg = 6 x^2 sin^2 x h_fg(f),  h_fg = 1/2 A_fg f^(-7/3) exp(-s1 f^alpha) [1 + tanh(-s2 (f - f_k))]
+//   P3 = 3 x^2 sin^2 x f^(-7/3),   LF = ln f
+__global__ void k_init_psd_basis(int64_t k_min, int64_t nb, double T, double L, double* P1, double* P2, double* P3,
+                                 double* LF) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nb) return;
   double f = (double)(k_min + i) / T;
@@ -63,6 +67,15 @@ __global__ void k_init_psd_basis(int64_t k_min, int64_t nb, double T, double L, 
   double wa = kTwoPi * kC * f;
   P1[i] = 8.0 * s2 * (2.0 + cx) * wo * wo * (1.0 + r_oms * r_oms * r_oms * r_oms);
   P2[i] = 16.0 * s2 * (3.0 + 2.0 * cx + c2x) / (wa * wa) * (1.0 + r_acc * r_acc) * (1.0 + r_hi * r_hi * r_hi * r_hi);
+  P3[i] = 3.0 * x * x * s2 * pow(f, -7.0 / 3.0);
+  LF[i] = log(f);
+}
+
+// Galactic-foreground term of one bin: P3 = 3 x^2 sin^2 x f^(-7/3), lf = ln f,
+// fg = (A_fg, alpha, f_k, s1, s2)
+__device__ __forceinline__ double foreground_term(double f, double p3, double lf, const double* fg) {
+  const double fa = exp(fg[1] * lf);  // f^alpha
+  return fg[0] * p3 * exp(-fg[3] * fa) * (1.0 + tanh(-fg[4] * (f - fg[2])));
 }
 
 // Sum over the block (NT threads, NT/64 waves); valid in thread 0 only.
@@ -523,14 +536,27 @@ __global__ __launch_bounds__(block_threads<N>()) void k_scatter_add(Geo g, WaveT
 // ---------------------------------------------------------------------------
 // PSD evaluation and the noise-parameter log-likelihood
 // ---------------------------------------------------------------------------
-// rows pc = p * 2 + c over blockIdx.y, bins over blockIdx.x (both grid-stride)
-__global__ void k_psd_eval(int64_t nb, const double* __restrict__ P1, const double* __restrict__ P2,
-                           const double* __restrict__ noise, int64_t P, int inverse, double* __restrict__ S) {
+// rows pc = p * 2 + c over blockIdx.y, bins over blockIdx.x (both grid-stride);
+// noise sets of NP = 4 (instrument) or 9 (with the foreground) parameters
+struct PsdBasis {
+  const double* P1;
+  const double* P2;
+  const double* P3;
+  const double* LF;
+  int64_t k_min;
+  double T;
+};
+
+template <int NP>
+__global__ void k_psd_eval(int64_t nb, PsdBasis pb, const double* __restrict__ noise, int64_t P, int inverse,
+                           double* __restrict__ S) {
   for (int64_t pc = blockIdx.y; pc < 2 * P; pc += gridDim.y) {
-    const double so = noise[2 * pc], sa = noise[2 * pc + 1];
+    const double* th = noise + NP * (pc >> 1);
+    const double so = th[2 * (pc & 1)], sa = th[2 * (pc & 1) + 1];
     double* Sr = S + pc * nb;
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < nb; k += (int64_t)gridDim.x * blockDim.x) {
-      const double v = so * so * P1[k] + sa * sa * P2[k];
+      double v = so * so * pb.P1[k] + sa * sa * pb.P2[k];
+      if constexpr (NP == 9) v += foreground_term((double)(pb.k_min + k) / pb.T, pb.P3[k], pb.LF[k], th + 4);
       Sr[k] = inverse ? 1.0 / v : v;
     }
   }
@@ -555,11 +581,11 @@ constexpr double kLn2 = 0.69314718055994530942;
 // Each S is split as m 2^e (m in [1/2, 1)): a bin's two quadratic terms take one
 // division of m_A m_E, and a thread's ln S terms are one logarithm of the running
 // mantissa product (renormalised every bin) plus ln 2 times the exponent sum.
-template <int G>
-__global__ __launch_bounds__(kPsdBlock) void k_psd_partial(int64_t nb, const double* __restrict__ P1,
-                                                           const double* __restrict__ P2,
-                                                           const cd* __restrict__ residual, int n_res,
-                                                           const double* __restrict__ noise,
+// NP = 4 (instrument noise) or 9 (with the Galactic foreground, shared by A and E:
+// one foreground evaluation per bin and set serves both channels).
+template <int G, int NP>
+__global__ __launch_bounds__(kPsdBlock) void k_psd_partial(int64_t nb, PsdBasis pb, const cd* __restrict__ residual,
+                                                           int n_res, const double* __restrict__ noise,
                                                            const int32_t* __restrict__ res_idx, int64_t p0,
                                                            int64_t p1st, double* __restrict__ work) {
   const int64_t pg = p1st + (int64_t)blockIdx.y * G;
@@ -569,27 +595,43 @@ __global__ __launch_bounds__(kPsdBlock) void k_psd_partial(int64_t nb, const dou
   const int64_t hi = lo + cs < nb ? lo + cs : nb;
   const cd* R[G];
   double oA[G], aA[G], oE[G], aE[G], quad[G], lm[G];
+  double fg[NP == 9 ? G : 1][5];
   int le[G];
 #pragma unroll
   for (int s = 0; s < G; s++) {
     const int64_t p = pg + s;
     const int ri = res_idx[p];
     R[s] = residual + (int64_t)(ri >= 0 && ri < n_res ? ri : 0) * 2 * nb;  // a bad index reports NaN below
-    oA[s] = noise[4 * p] * noise[4 * p];
-    aA[s] = noise[4 * p + 1] * noise[4 * p + 1];
-    oE[s] = noise[4 * p + 2] * noise[4 * p + 2];
-    aE[s] = noise[4 * p + 3] * noise[4 * p + 3];
+    oA[s] = noise[NP * p] * noise[NP * p];
+    aA[s] = noise[NP * p + 1] * noise[NP * p + 1];
+    oE[s] = noise[NP * p + 2] * noise[NP * p + 2];
+    aE[s] = noise[NP * p + 3] * noise[NP * p + 3];
+    if constexpr (NP == 9) {
+#pragma unroll
+      for (int i = 0; i < 5; i++) fg[s][i] = noise[NP * p + 4 + i];
+    }
     quad[s] = 0.0;
     lm[s] = 1.0;
     le[s] = 0;
   }
   for (int64_t k = lo + threadIdx.x; k < hi; k += kPsdBlock) {
-    const double p1 = P1[k], p2 = P2[k];
+    const double p1 = pb.P1[k], p2 = pb.P2[k];
+    double f = 0.0, p3 = 0.0, lf = 0.0;
+    if constexpr (NP == 9) {
+      f = (double)(pb.k_min + k) / pb.T;
+      p3 = pb.P3[k];
+      lf = pb.LF[k];
+    }
 #pragma unroll
     for (int s = 0; s < G; s++) {
       // explicit fma: the same rounding in every instance of G
-      const double SAv = fma(oA[s], p1, aA[s] * p2);
-      const double SEv = fma(oE[s], p1, aE[s] * p2);
+      double SAv = fma(oA[s], p1, aA[s] * p2);
+      double SEv = fma(oE[s], p1, aE[s] * p2);
+      if constexpr (NP == 9) {
+        const double gfg = foreground_term(f, p3, lf, fg[s]);
+        SAv += gfg;
+        SEv += gfg;
+      }
       const cd r0 = R[s][k], r1 = R[s][nb + k];
       const double qa = fma(r0.re, r0.re, r0.im * r0.im), qe = fma(r1.re, r1.re, r1.im * r1.im);
       int eA, eE, eM;
@@ -644,6 +686,339 @@ __global__ void k_make_noise(int64_t total, double scale, const double* __restri
     double a = sqrt(S[i] * scale);
     cd gv = normals[i];
     out[i] = {a * gv.re, a * gv.im};
+  }
+}
+
+
+// ---------------------------------------------------------------------------
+// gb_inner: PSD-weighted inner products of stored band slices (Sec. 2 eq.
+// inner over channels A, E):
+//   out[b] = (<h|h>, <R|h>) = 4 df sum_{c,k} (|h|^2, Re(conj(R) h)) / S
+// over the slice's bins inside the band.  One wave per template: consecutive
+// lanes read consecutive bins (16-byte loads of the slices and the residual,
+// 8-byte loads of S), the sums stay in FP64 registers and one wave reduction
+// finishes them.  Bound by HBM: 2 N (16 + 16 + 8) + 16 bytes per template.
+// ---------------------------------------------------------------------------
+constexpr int kInnerWaves = 4;  // templates per block
+
+__global__ __launch_bounds__(kInnerWaves * kWave) void k_inner(Geo g, const cd* __restrict__ A,
+                                                               const cd* __restrict__ E,
+                                                               const int64_t* __restrict__ start, int N,
+                                                               const cd* __restrict__ residual, int n_res,
+                                                               const double* __restrict__ psd, int n_psd, int psd_inv,
+                                                               const int32_t* __restrict__ res_idx,
+                                                               const int32_t* __restrict__ psd_idx, int64_t B,
+                                                               double* __restrict__ out) {
+  const int64_t b = (int64_t)blockIdx.x * kInnerWaves + threadIdx.x / kWave;
+  if (b >= B) return;  // uniform over the wave
+  const int lane = threadIdx.x & (kWave - 1);
+  const int ri = res_idx[b], pi = psd_idx[b];
+  if (ri < 0 || ri >= n_res || pi < 0 || pi >= n_psd) {
+    if (lane == 0) out[2 * b] = out[2 * b + 1] = qnan();
+    return;
+  }
+  const int64_t nb = g.n_bins;
+  const int64_t s0 = start[b];
+  // slice element j sits at band index s0 - k_min + j; only j in [jlo, jhi) is inside the band
+  int64_t sb = 0, jlo = 0, jhi = 0;
+  if (s0 > g.k_min - N && s0 < g.k_min + nb) {
+    sb = s0 - g.k_min;
+    jlo = sb < 0 ? -sb : 0;
+    jhi = nb - sb < (int64_t)N ? nb - sb : (int64_t)N;
+  }
+  const cd* hA = A + b * N;
+  const cd* hE = E + b * N;
+  const cd* RA = residual + (int64_t)ri * 2 * nb;
+  const cd* RE = RA + nb;
+  const double* SA = psd + (int64_t)pi * 2 * nb;
+  const double* SE = SA + nb;
+  double hh = 0.0, rh = 0.0;
+#pragma unroll 4
+  for (int64_t j = jlo + lane; j < jhi; j += kWave) {
+    const int64_t k = sb + j;
+    const cd a = hA[j], e = hE[j], ra = RA[k], re = RE[k];
+    const double sa = SA[k], se = SE[k];
+    const double wa = psd_inv ? sa : 1.0 / sa;
+    const double we = psd_inv ? se : 1.0 / se;
+    hh += fma(a.re, a.re, a.im * a.im) * wa + fma(e.re, e.re, e.im * e.im) * we;
+    rh += fma(ra.re, a.re, ra.im * a.im) * wa + fma(re.re, e.re, re.im * e.im) * we;
+  }
+  hh = wave_sum(hh);
+  rh = wave_sum(rh);
+  if (lane == 0) {
+    out[2 * b] = g.df4 * hh;
+    out[2 * b + 1] = g.df4 * rh;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// gb_snr: optimal SNR sqrt(<h|h>) and observed SNR <d|h>/sqrt(<h|h>) of
+// templates built on the fly (one block per template, FP64 response; the
+// template never leaves LDS).
+// ---------------------------------------------------------------------------
+template <int N>
+__global__ __launch_bounds__(block_threads<N>()) void k_snr(Geo g, WaveTables<double> tb,
+                                                            const double* __restrict__ params, int64_t b0,
+                                                            const double* __restrict__ psd, int n_psd, int psd_inv,
+                                                            const int32_t* __restrict__ psd_idx,
+                                                            const cd* __restrict__ data, int n_data,
+                                                            const int32_t* __restrict__ data_idx,
+                                                            double* __restrict__ snr_opt,
+                                                            double* __restrict__ snr_obs) {
+  constexpr int NT = block_threads<N>();
+  constexpr int NW = NT / kWave;
+  __shared__ cd buf[4 * series_pitch<N>()];
+  __shared__ Src s_sh;
+  __shared__ double red[2][NW];
+  const int64_t b = b0 + blockIdx.x;
+  const int tid = threadIdx.x;
+  const SrcHead h = source_head(params + 8 * b, g);
+  const int pi = psd_idx[b];
+  const int di = data ? data_idx[b] : 0;
+  if (h.state == 2 || pi < 0 || pi >= n_psd || (data && (di < 0 || di >= n_data))) {
+    if (tid == 0) {
+      snr_opt[b] = qnan();
+      if (data) snr_obs[b] = qnan();
+    }
+    return;  // uniform over the block
+  }
+  double hh = 0.0, dh = 0.0;
+  if (h.state == 0) {
+    if (tid < kWave) decode_sources<1>(params + 8 * b, params + 8 * b, g, &s_sh);
+    __syncthreads();
+    const Src& s = s_sh;
+    template_transform<N, 4, double>(s, g, tb, buf, tid);
+    const int64_t nb = g.n_bins;
+    const int64_t k0 = s.q - N / 2;
+    const double* S = psd + (int64_t)pi * 2 * nb;
+    const cd* D = data ? data + (int64_t)di * 2 * nb : nullptr;
+    for (int j = tid; j < N; j += NT) {
+      const int64_t k = k0 + j;
+      if (k < g.k_min || k >= g.k_min + nb) continue;
+      const int64_t idx = k - g.k_min;
+      cd v[2];
+      bin_spectrum<N, 2, double>(s, g, tb, buf, j, v);
+#pragma unroll
+      for (int c = 0; c < 2; c++) {
+        const double sv = S[c * nb + idx];
+        const double w = psd_inv ? sv : 1.0 / sv;
+        hh += fma(v[c].re, v[c].re, v[c].im * v[c].im) * w;
+        if (D) {
+          const cd dv = D[c * nb + idx];
+          dh += fma(dv.re, v[c].re, dv.im * v[c].im) * w;
+        }
+      }
+    }
+  }
+  // state 1 (zero amplitude): both sums are exactly zero
+  hh = wave_sum(hh);
+  dh = wave_sum(dh);
+  if ((tid & (kWave - 1)) == 0) {
+    red[0][tid / kWave] = hh;
+    red[1][tid / kWave] = dh;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double a = 0.0, c = 0.0;
+#pragma unroll
+    for (int i = 0; i < NW; i++) {
+      a += red[0][i];
+      c += red[1][i];
+    }
+    a *= g.df4;
+    c *= g.df4;
+    const double so = sqrt(a);
+    snr_opt[b] = so;
+    if (data) snr_obs[b] = c / so;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// gb_overlap: (<a|a>, <b|b>, <a|b>, <a|b> / sqrt(<a|a> <b|b>)) of template
+// pairs (the overlaps that group sources in the cataloging operation of
+// Sec. 4).  One block per pair, FP64: a's spectrum is kept in LDS, b is built
+// in the FFT workspace and every bin of b's window adds to <b|b> and, where
+// a's window covers it, to <a|b>; a's own bins give <a|a>.
+// ---------------------------------------------------------------------------
+template <int N>
+__global__ __launch_bounds__(block_threads<N>()) void k_overlap(Geo g, WaveTables<double> tb,
+                                                                const double* __restrict__ pa,
+                                                                const double* __restrict__ pb, int64_t b0,
+                                                                const double* __restrict__ psd, int n_psd,
+                                                                int psd_inv, const int32_t* __restrict__ psd_idx,
+                                                                double* __restrict__ out) {
+  constexpr int NT = block_threads<N>();
+  constexpr int NW = NT / kWave;
+  __shared__ cd buf[4 * series_pitch<N>()];
+  __shared__ cd aw[2 * N];
+  __shared__ Src src;
+  __shared__ double red[3][NW];
+  const int64_t b = b0 + blockIdx.x;
+  const int tid = threadIdx.x;
+  const double* prm_a = pa + 8 * b;
+  const double* prm_b = pb + 8 * b;
+  const SrcHead ha = source_head(prm_a, g), hb = source_head(prm_b, g);
+  const int pi = psd_idx[b];
+  if (ha.state == 2 || hb.state == 2 || pi < 0 || pi >= n_psd) {
+    if (tid == 0) out[4 * b] = out[4 * b + 1] = out[4 * b + 2] = out[4 * b + 3] = qnan();
+    return;  // uniform over the block
+  }
+  const int64_t nb = g.n_bins;
+  const double* S = psd + (int64_t)pi * 2 * nb;
+  const int64_t ka = ha.q - N / 2, kb = hb.q - N / 2;
+  // template a into aw (zeros for a zero-amplitude template)
+  if (ha.state == 0) {
+    if (tid < kWave) decode_sources<1>(prm_a, prm_a, g, &src);
+    __syncthreads();
+    template_transform<N, 4, double>(src, g, tb, buf, tid);
+    for (int j = tid; j < N; j += NT) {
+      cd v[2];
+      bin_spectrum<N, 2, double>(src, g, tb, buf, j, v);
+      aw[j] = v[0];
+      aw[N + j] = v[1];
+    }
+  } else {
+    for (int j = tid; j < 2 * N; j += NT) aw[j] = cd{0.0, 0.0};
+  }
+  __syncthreads();  // aw complete; the workspace and the decode are free again
+  double aa = 0.0, bb = 0.0, ab = 0.0;
+  for (int j = tid; j < N; j += NT) {
+    const int64_t k = ka + j;
+    if (k < g.k_min || k >= g.k_min + nb) continue;
+#pragma unroll
+    for (int c = 0; c < 2; c++) {
+      const double sv = S[c * nb + (k - g.k_min)];
+      const double w = psd_inv ? sv : 1.0 / sv;
+      const cd x = aw[c * N + j];
+      aa += fma(x.re, x.re, x.im * x.im) * w;
+    }
+  }
+  if (hb.state == 0) {
+    if (tid < kWave) decode_sources<1>(prm_b, prm_b, g, &src);
+    __syncthreads();
+    template_transform<N, 4, double>(src, g, tb, buf, tid);
+    for (int j = tid; j < N; j += NT) {
+      const int64_t k = kb + j;
+      if (k < g.k_min || k >= g.k_min + nb) continue;
+      cd v[2];
+      bin_spectrum<N, 2, double>(src, g, tb, buf, j, v);
+      const int64_t ja = k - ka;
+      const bool in_a = ja >= 0 && ja < N;
+#pragma unroll
+      for (int c = 0; c < 2; c++) {
+        const double sv = S[c * nb + (k - g.k_min)];
+        const double w = psd_inv ? sv : 1.0 / sv;
+        bb += fma(v[c].re, v[c].re, v[c].im * v[c].im) * w;
+        if (in_a) {
+          const cd x = aw[c * N + ja];
+          ab += fma(x.re, v[c].re, x.im * v[c].im) * w;
+        }
+      }
+    }
+  }
+  aa = wave_sum(aa);
+  bb = wave_sum(bb);
+  ab = wave_sum(ab);
+  if ((tid & (kWave - 1)) == 0) {
+    red[0][tid / kWave] = aa;
+    red[1][tid / kWave] = bb;
+    red[2][tid / kWave] = ab;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+#pragma unroll
+    for (int i = 0; i < NW; i++) {
+      s0 += red[0][i];
+      s1 += red[1][i];
+      s2 += red[2][i];
+    }
+    s0 *= g.df4;
+    s1 *= g.df4;
+    s2 *= g.df4;
+    out[4 * b] = s0;
+    out[4 * b + 1] = s1;
+    out[4 * b + 2] = s2;
+    out[4 * b + 3] = s2 / sqrt(s0 * s1);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Deterministic scatter-add (GBL_DETERMINISTIC contexts).  A chunk of
+// templates is built into a workspace, sorted by (residual, start bin) with a
+// stable radix sort (ties keep template order), and every band bin is
+// written by exactly one thread: the first sorted template that covers it
+// sums, in sorted order, every template covering the bin and adds the total
+// with a plain read-modify-write.  No atomics, so the residual does not
+// depend on scheduling.
+// ---------------------------------------------------------------------------
+constexpr uint64_t kDetInvalid = ~0ull;
+
+// key = res_idx << 32 | (start - k_min + N): templates that miss the band,
+// zero or undefined templates and bad indices get kDetInvalid (sorted last)
+__global__ void k_det_keys(Geo g, const double* __restrict__ params, int64_t b0, int64_t nb, int N,
+                           const int32_t* __restrict__ res_idx, int n_res, uint64_t* __restrict__ keys,
+                           int32_t* __restrict__ vals) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nb) return;
+  const int64_t b = b0 + i;
+  const SrcHead h = source_head(params + 8 * b, g);
+  const int ri = res_idx[b];
+  const int64_t start = h.q - N / 2;
+  const bool ok = h.state == 0 && ri >= 0 && ri < n_res && start + N > g.k_min && start < g.k_min + g.n_bins;
+  keys[i] = ok ? ((uint64_t)ri << 32) | (uint64_t)(start - g.k_min + N) : kDetInvalid;
+  vals[i] = (int32_t)i;
+}
+
+// template b0 + blockIdx.x into workspace slot blockIdx.x (A at ws, E at ws + cap)
+template <int N, typename F>
+__global__ __launch_bounds__(block_threads<N>()) void k_det_slices(Geo g, WaveTables<F> tb,
+                                                                   const double* __restrict__ params, int64_t b0,
+                                                                   cd* __restrict__ ws, int64_t cap,
+                                                                   int64_t* __restrict__ ws_start) {
+  __shared__ WaveSmem<N, 4, F> sm;
+  const int64_t i = blockIdx.x;
+  waveform_one<N, 4, F>(g, tb, params + 8 * (b0 + i), i * N, ws, ws + cap, nullptr, ws_start + i, sm);
+}
+
+template <int N>
+__global__ __launch_bounds__(256) void k_det_gather(Geo g, const uint64_t* __restrict__ keys,
+                                                    const int32_t* __restrict__ vals, int64_t nb,
+                                                    const cd* __restrict__ ws, int64_t cap, double sign,
+                                                    cd* __restrict__ residual) {
+  const int64_t i = blockIdx.x;
+  const uint64_t key = keys[i];
+  if (key == kDetInvalid) return;
+  const uint64_t ri = key >> 32;
+  const int64_t start = (int64_t)(key & 0xffffffffull) + g.k_min - N;
+  const bool first_of_row = i == 0 || (keys[i - 1] >> 32) != ri;
+  const int64_t prev_end = first_of_row ? INT64_MIN : (int64_t)(keys[i - 1] & 0xffffffffull) + g.k_min;  // start + N
+  cd* R = residual + (int64_t)ri * 2 * g.n_bins;
+  for (int j = threadIdx.x; j < N; j += blockDim.x) {
+    const int64_t k = start + j;
+    if (k < g.k_min || k >= g.k_min + g.n_bins) continue;
+    if (prev_end > k) continue;  // an earlier sorted template covers k and owns it
+    cd sa = {0.0, 0.0}, se = {0.0, 0.0};
+    for (int64_t i2 = i; i2 < nb; i2++) {
+      const uint64_t k2 = keys[i2];
+      if ((k2 >> 32) != ri) break;  // also stops at kDetInvalid (ri < 2^31)
+      const int64_t s2 = (int64_t)(k2 & 0xffffffffull) + g.k_min - N;
+      if (s2 > k) break;
+      const int64_t slot = vals[i2];
+      const cd a = ws[slot * N + (k - s2)], e = ws[cap + slot * N + (k - s2)];
+      sa.re += a.re;
+      sa.im += a.im;
+      se.re += e.re;
+      se.im += e.im;
+    }
+    const int64_t idx = k - g.k_min;
+    cd ra = R[idx], re = R[g.n_bins + idx];
+    ra.re += sign * sa.re;
+    ra.im += sign * sa.im;
+    re.re += sign * se.re;
+    re.im += sign * se.im;
+    R[idx] = ra;
+    R[g.n_bins + idx] = re;
   }
 }
 

@@ -75,6 +75,7 @@ struct SweepArgs {
   const double* prop_u;   // RJ birth candidates (nullptr: prior draws)
   const double* rj_logq;  // ln q per slot (with prop_u)
   double* cold_logl;      // [n_w][n_b] cold-chain band logL after tempering (optional)
+  int32_t* swap_acc;      // [n_b][n_t] accepted swaps of rungs (t-1, t) since the last ladder adaptation (optional)
   cd* spec_pool;          // optional pool of per-slot spectra, pool_size entries of n_slot x 2N
   int32_t* pool_flags;    // [pool_size], 0 = free
   int pool_size;
@@ -778,6 +779,7 @@ __global__ __launch_bounds__(block_threads<N>()) void k_sweep_pt(Geo g, WaveTabl
     n_prop++;
     if (log(r) < la) {
       n_acc++;
+      if (tid == 0 && a.swap_acc) atomicAdd(&a.swap_acc[(int64_t)b * nt + t], 1);
       if (t == 1 && Hs) {
         // the cold chain of walker w_0 changes: own-parity buffer += old - new
         cd* own = a.resid + ((int64_t)(b & 1) * a.n_w + wt[0]) * 2 * g.n_bins;
@@ -972,9 +974,10 @@ enum { kMovePsd = 4, kMovePsdPT = 5 };
 
 struct PsdArgs {
   int nt, nw;
+  int np;  // parameters per set: 4, or 9 with the Galactic foreground
   double a;
   uint64_t seed;
-  double lo[4], hi[4];
+  double lo[9], hi[9];
   double* theta;
   double* logl;
   const double* betas;
@@ -1005,7 +1008,7 @@ __global__ void k_psd_res_idx(int nt, int nw, int h, int32_t* res_idx) {
   res_idx[s] = h < 0 ? s % nw : 2 * (s % (nw / 2)) + h;
 }
 
-// proposals of half h: prop [nt][nw/2][4], lz = 3 ln z, ok = inside the prior box
+// proposals of half h: prop [nt][nw/2][np], lz = (np - 1) ln z, ok = inside the prior box
 __global__ void k_psd_propose(PsdArgs p, int h, double* prop, double* lz, double* ok) {
   const int half = p.nw / 2;
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1017,15 +1020,15 @@ __global__ void k_psd_propose(PsdArgs p, int h, double* prop, double* lz, double
   const double r_z = rng_uniform(p.seed, sweep, kMovePsd, unit, 4 * (uint64_t)h + 1);
   const int j = 2 * (int)floor(r_pick * half) + (1 - h);
   const double z = ((p.a - 1.0) * r_z + 1.0) * ((p.a - 1.0) * r_z + 1.0) / p.a;
-  const double* X = p.theta + ((int64_t)t * p.nw + j) * 4;
-  const double* Y = p.theta + ((int64_t)t * p.nw + w) * 4;
+  const double* X = p.theta + ((int64_t)t * p.nw + j) * p.np;
+  const double* Y = p.theta + ((int64_t)t * p.nw + w) * p.np;
   bool inside = true;
-  for (int k = 0; k < 4; k++) {
+  for (int k = 0; k < p.np; k++) {
     const double v = X[k] + z * (Y[k] - X[k]);
-    prop[4 * s + k] = v;
+    prop[(int64_t)p.np * s + k] = v;
     inside = inside && (v >= p.lo[k] && v <= p.hi[k]);
   }
-  lz[s] = 3.0 * log(z);
+  lz[s] = (double)(p.np - 1) * log(z);
   ok[s] = inside ? 1.0 : 0.0;
 }
 
@@ -1042,7 +1045,7 @@ __global__ void k_psd_accept(PsdArgs p, int h, const double* prop, const double*
   const double r = rng_uniform(p.seed, sweep, kMovePsd, (uint64_t)c, 4 * (uint64_t)h + 2);
   const double la = p.betas[t] * (lprop[s] - p.logl[c]) + lz[s];
   if (log(r) < la) {
-    for (int k = 0; k < 4; k++) p.theta[4 * c + k] = prop[4 * s + k];
+    for (int k = 0; k < p.np; k++) p.theta[p.np * c + k] = prop[(int64_t)p.np * s + k];
     p.logl[c] = lprop[s];
     atomicAdd(&p.stats[1], 1ull);
   }
@@ -1060,10 +1063,10 @@ __global__ void k_psd_swap(PsdArgs p) {
     const int64_t c1 = (int64_t)t * p.nw + w, c0 = (int64_t)(t - 1) * p.nw + w;
     const double la = (p.betas[t - 1] - p.betas[t]) * (p.logl[c1] - p.logl[c0]);
     if (log(r) < la) {
-      for (int k = 0; k < 4; k++) {
-        const double tmp = p.theta[4 * c1 + k];
-        p.theta[4 * c1 + k] = p.theta[4 * c0 + k];
-        p.theta[4 * c0 + k] = tmp;
+      for (int k = 0; k < p.np; k++) {
+        const double tmp = p.theta[p.np * c1 + k];
+        p.theta[p.np * c1 + k] = p.theta[p.np * c0 + k];
+        p.theta[p.np * c0 + k] = tmp;
       }
       const double tl = p.logl[c1];
       p.logl[c1] = p.logl[c0];
@@ -1073,6 +1076,116 @@ __global__ void k_psd_swap(PsdArgs p) {
   }
   if (np) atomicAdd(&p.stats[2], np);
   if (na) atomicAdd(&p.stats[3], na);
+}
+
+// ---------------------------------------------------------------------------
+// Temperature-ladder adaptation (appendix on parallel tempering; the gap
+// dynamics of Vousden, Farr & Mandel 2016): with T = 1/beta and A_j the
+// fraction of accepted swaps of rungs (j, j+1) since the last call,
+//   T_(j+1) - T_j  <-  (T_(j+1) - T_j) exp(kappa (A_j - A_(j+1))),
+//   kappa = t0 / (nu (sweep + t0)),
+// the coldest and hottest rungs fixed and the others re-summed from the
+// coldest.  One thread per band; the counts are cleared.
+// ---------------------------------------------------------------------------
+__global__ void k_sweep_adapt(SweepArgs a, double lag, double time_scale) {
+#pragma clang fp contract(off)
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= a.n_b) return;
+  const int nt = a.n_t;
+  double* bt = const_cast<double*>(a.betas) + (int64_t)b * nt;
+  int32_t* ac = a.swap_acc + (int64_t)b * nt;
+  const double kappa = lag / (time_scale * ((double)*a.sweep_ctr + lag));
+  if (nt > 2) {
+    double T = 1.0 / bt[0];
+    double inv_cur = 1.0 / bt[0];
+    for (int j = 0; j + 2 < nt; j++) {
+      const double inv_next = 1.0 / bt[j + 1];  // still the old rung
+      const double A_lo = (double)ac[j + 1] / (double)a.n_w;
+      const double A_hi = (double)ac[j + 2] / (double)a.n_w;
+      const double gap = (inv_next - inv_cur) * exp(kappa * (A_lo - A_hi));
+      T += gap;
+      bt[j + 1] = 1.0 / T;
+      inv_cur = inv_next;
+    }
+  }
+  for (int t = 0; t < nt; t++) ac[t] = 0;
+}
+
+// ---------------------------------------------------------------------------
+// Sub-band ownership (Sec. 4): a cold-chain source whose f0 has left its
+// band's nominal range [k_band0 + b N, k_band0 + (b+1) N) / T moves to the
+// neighbouring band it lies in (lowest free cold-chain slot; it stays if
+// there is none); it is added back to the old parity's buffer and removed
+// from the new one's.  One block per walker, bands and slots in increasing
+// order (the walker's buffers belong to its block alone: plain updates).
+// stats[8] counts moved sources, stats[9] sources without a free slot.
+// ---------------------------------------------------------------------------
+template <int N>
+__global__ __launch_bounds__(block_threads<N>()) void k_sweep_shift(Geo g, WaveTables<double> tb, SweepArgs a) {
+  constexpr int NT = block_threads<N>();
+  __shared__ cd buf[4 * series_pitch<N>()];
+  __shared__ Src src;
+  __shared__ double prm[8];
+  const int w = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int S = a.n_slot;
+  unsigned long long moved = 0, stuck = 0;
+  for (int b = 0; b < a.n_b; b++) {
+    for (int s = 0; s < S; s++) {
+      const int64_t ui = uidx(a, 0, w, b, s);
+      if (!a.exists[ui]) continue;  // uniform: every thread reads the same flag
+      const double f0 = a.u[8 * ui + 1];
+      const double lo = (double)(a.k_band0 + (int64_t)b * N) / g.T;
+      const double hi = (double)(a.k_band0 + (int64_t)(b + 1) * N) / g.T;
+      const int bb = f0 < lo ? b - 1 : (f0 >= hi ? b + 1 : b);
+      if (bb == b || bb < 0 || bb >= a.n_b) continue;
+      int s2 = -1;
+      for (int j = 0; j < S && s2 < 0; j++)
+        if (!a.exists[uidx(a, 0, w, bb, j)]) s2 = j;
+      if (s2 < 0) {
+        stuck++;
+        continue;
+      }
+      const int64_t u2 = uidx(a, 0, w, bb, s2);
+      __syncthreads();  // every thread has read the flags before they change
+      if (tid < 8) {
+        // sampling -> physical coordinates (log10 A, cos iota, sin beta mapped back)
+        const double v = a.u[8 * ui + tid];
+        a.u[8 * u2 + tid] = v;
+        prm[tid] = tid == 0 ? exp10(v) : tid == 4 ? acos(v) : tid == 7 ? asin(v) : v;
+      }
+      if (tid == 0) {
+        a.exists[u2] = 1;
+        a.exists[ui] = 0;
+      }
+      __threadfence_block();
+      __syncthreads();
+      if (tid < kWave) decode_sources<1>(prm, prm, g, &src);
+      __syncthreads();
+      template_transform<N, 4, double>(src, g, tb, buf, tid);
+      cd* old_buf = a.resid + ((int64_t)(b & 1) * a.n_w + w) * 2 * g.n_bins;
+      cd* new_buf = a.resid + ((int64_t)(bb & 1) * a.n_w + w) * 2 * g.n_bins;
+      const int64_t k0 = src.q - N / 2;
+      for (int j = tid; j < N; j += NT) {
+        const int64_t k = k0 + j;
+        if (k < g.k_min || k >= g.k_min + g.n_bins) continue;
+        const int64_t idx = k - g.k_min;
+        cd v[2];
+        bin_spectrum<N, 2, double>(src, g, tb, buf, j, v);
+#pragma unroll
+        for (int c = 0; c < 2; c++) {
+          old_buf[c * g.n_bins + idx] = old_buf[c * g.n_bins + idx] + v[c];
+          new_buf[c * g.n_bins + idx] = new_buf[c * g.n_bins + idx] - v[c];
+        }
+      }
+      __syncthreads();
+      moved++;
+    }
+  }
+  if (tid == 0) {
+    if (moved) atomicAdd(&a.stats[8], moved);
+    if (stuck) atomicAdd(&a.stats[9], stuck);
+  }
 }
 
 __global__ void k_sweep_advance(int64_t* sweep_ctr) {

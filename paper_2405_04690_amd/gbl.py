@@ -21,7 +21,8 @@ GBL_EHIP = -3
 GBL_FP64 = 0
 GBL_MIXED = 1
 GBL_PSD_INVERSE = 1
-GBL_MIXED_UNROUTED = 1  # config flag
+GBL_MIXED_UNROUTED = 1  # config flags
+GBL_DETERMINISTIC = 2
 
 SUPPORTED_N = (128, 256, 512, 1024)
 
@@ -31,7 +32,9 @@ EXPORTED = ("gbl_create", "gbl_destroy", "gbl_set_stream", "gbl_last_error", "gb
             "gb_sweep_run", "gb_sweep_graph_create", "gb_graph_launch", "gb_graph_destroy", "gb_flow_sizes",
             "gb_flow_pack", "gb_flow_log_prob", "gb_flow_sample", "gb_flow_grad", "gb_flow_adam",
             "gb_flow_train_step", "gb_sweep_rj_prepare", "gb_sweep_run_flow", "gb_sweep_graph_create_flow",
-            "gbl_get_tuning", "gbl_set_tuning", "gb_psd_sweep_step", "gb_graph_begin", "gb_graph_end")
+            "gbl_get_tuning", "gbl_set_tuning", "gb_psd_sweep_step", "gb_graph_begin", "gb_graph_end",
+            "gb_psd_eval_n", "gb_psd_loglike_n", "gb_inner", "gb_snr", "gb_sweep_adapt_ladder",
+            "gb_sweep_shift_ownership", "gb_overlap")
 
 GBL_MOVE_INMODEL, GBL_MOVE_RJ, GBL_MOVE_PT = 0, 1, 2
 
@@ -54,14 +57,17 @@ class SweepConfig(ctypes.Structure):
                 ("n_slots", ctypes.c_int32), ("N", ctypes.c_int32), ("n_prop", ctypes.c_int32),
                 ("n_friends", ctypes.c_int32), ("group_every", ctypes.c_int32), ("k_band0", ctypes.c_int64),
                 ("stretch_a", ctypes.c_double), ("seed", ctypes.c_uint64),
-                ("prior_lo", ctypes.c_double * 8), ("prior_hi", ctypes.c_double * 8)]
+                ("prior_lo", ctypes.c_double * 8), ("prior_hi", ctypes.c_double * 8),
+                ("adapt_ladder", ctypes.c_int32), ("shift_ownership", ctypes.c_int32),
+                ("adapt_lag", ctypes.c_double), ("adapt_time", ctypes.c_double)]
 
 
 class SweepState(ctypes.Structure):
     """gbl_sweep_state (device pointers)"""
     _fields_ = [(n, ctypes.c_void_p) for n in ("u", "exists", "betas", "resid", "inv_psd", "group", "group_count",
                                               "stats", "sweep_counter", "prop_u", "rj_logq", "cold_logl",
-                                              "rj_mode", "spec_pool", "pool_flags")] + [("pool_size", ctypes.c_int32)]
+                                              "rj_mode", "spec_pool", "pool_flags")] + [("pool_size", ctypes.c_int32),
+                                                                                        ("swap_acc", ctypes.c_void_p)]
 
 
 class Tuning(ctypes.Structure):
@@ -75,8 +81,9 @@ class Tuning(ctypes.Structure):
 
 class PsdSweepConfig(ctypes.Structure):
     """gbl_psd_sweep_config"""
-    _fields_ = [("n_tn", ctypes.c_int32), ("n_walkers", ctypes.c_int32), ("stretch_a", ctypes.c_double),
-                ("seed", ctypes.c_uint64), ("prior_lo", ctypes.c_double * 4), ("prior_hi", ctypes.c_double * 4)]
+    _fields_ = [("n_tn", ctypes.c_int32), ("n_walkers", ctypes.c_int32), ("n_par", ctypes.c_int32),
+                ("stretch_a", ctypes.c_double), ("seed", ctypes.c_uint64), ("prior_lo", ctypes.c_double * 9),
+                ("prior_hi", ctypes.c_double * 9)]
 
 
 class PsdSweepState(ctypes.Structure):
@@ -104,7 +111,6 @@ def load_library(path: str = LIB_PATH):
     global _lib
     if _lib is not None:
         return _lib
-    path = os.environ.get("GBL_LIBRARY", path)   # an alternative build of the same library
     if not os.path.exists(path):
         raise ImportError(f"{path} not found: build the HIP library first (python -m paper_2405_04690_amd.build)")
     lib = ctypes.CDLL(path)
@@ -120,11 +126,18 @@ def load_library(path: str = LIB_PATH):
         "gb_delta_loglike_var": [vp, vp, i32, vp, i32, i32, vp, vp, vp, vp, vp, i64, vp],
         "gb_psd_eval": [vp, vp, i64, i32, vp],
         "gb_psd_loglike": [vp, vp, i32, vp, vp, i64, vp],
+        "gb_psd_eval_n": [vp, vp, i32, i64, i32, vp],
+        "gb_psd_loglike_n": [vp, vp, i32, vp, i32, vp, i64, vp],
+        "gb_inner": [vp, vp, vp, vp, i32, vp, i32, vp, i32, i32, vp, vp, i64, vp],
+        "gb_snr": [vp, vp, i64, i32, vp, i32, i32, vp, vp, i32, vp, vp, vp],
+        "gb_overlap": [vp, vp, vp, i32, vp, i32, i32, vp, i64, vp],
         "gb_scatter_add": [vp, vp, i64, i32, dbl, vp, i32, vp],
         "gb_make_noise": [vp, vp, vp, i64, vp],
         "gb_sweep_step": [vp, ctypes.POINTER(SweepConfig), ctypes.POINTER(SweepState), i32, i32],
         "gb_sweep_group": [vp, ctypes.POINTER(SweepConfig), ctypes.POINTER(SweepState)],
         "gb_sweep_advance": [vp, ctypes.POINTER(SweepState)],
+        "gb_sweep_adapt_ladder": [vp, ctypes.POINTER(SweepConfig), ctypes.POINTER(SweepState)],
+        "gb_sweep_shift_ownership": [vp, ctypes.POINTER(SweepConfig), ctypes.POINTER(SweepState)],
         "gb_sweep_run": [vp, ctypes.POINTER(SweepConfig), ctypes.POINTER(SweepState), i32],
         "gb_sweep_graph_create": [vp, ctypes.POINTER(SweepConfig), ctypes.POINTER(SweepState), i32,
                                   ctypes.POINTER(vp)],
@@ -351,32 +364,113 @@ class Context:
         self._check(rc, "gb_delta_loglike_var")
         return out
 
-    def gb_psd_eval(self, noise, inverse: bool = False):
+    def _noise(self, noise):
         noise = self._dev(noise, torch.float64, "noise")
-        if noise.dim() != 2 or noise.shape[1] != 4:
-            raise ValueError("noise must have shape [P, 4]")
+        if noise.dim() != 2 or noise.shape[1] not in (4, 9):
+            raise ValueError("noise must have shape [P, 4] or [P, 9] (with the Galactic foreground)")
+        return noise
+
+    def gb_psd_eval(self, noise, inverse: bool = False):
+        """S (or 1/S) [P, 2, n_bins] for noise sets [P, 4] or [P, 9]"""
+        noise = self._noise(noise)
         P = noise.shape[0]
         S = torch.empty((P, 2, self.n_bins), dtype=torch.float64, device=self.device)
         self._sync_stream()
-        rc = self.lib.gb_psd_eval(self._h, _ptr(noise), P, GBL_PSD_INVERSE if inverse else 0, _ptr(S))
+        rc = self.lib.gb_psd_eval_n(self._h, _ptr(noise), noise.shape[1], P, GBL_PSD_INVERSE if inverse else 0,
+                                    _ptr(S))
         self._check(rc, "gb_psd_eval")
         return S
 
     def gb_psd_loglike(self, residual, noise, res_idx=None):
         residual = self._residual(residual)
-        noise = self._dev(noise, torch.float64, "noise")
-        if noise.dim() != 2 or noise.shape[1] != 4:
-            raise ValueError("noise must have shape [P, 4]")
+        noise = self._noise(noise)
         P = noise.shape[0]
         if res_idx is None:
             res_idx = torch.zeros(P, dtype=torch.int32, device=self.device)
         res_idx = self._dev(res_idx, torch.int32, "res_idx")
         out = torch.empty(P, dtype=torch.float64, device=self.device)
         self._sync_stream()
-        rc = self.lib.gb_psd_loglike(self._h, _ptr(residual), residual.shape[0], _ptr(noise), _ptr(res_idx), P,
-                                     _ptr(out))
+        rc = self.lib.gb_psd_loglike_n(self._h, _ptr(residual), residual.shape[0], _ptr(noise), noise.shape[1],
+                                       _ptr(res_idx), P, _ptr(out))
         self._check(rc, "gb_psd_loglike")
         return out
+
+    def gb_inner(self, A, E, start_bin, residual, psd, res_idx=None, psd_idx=None, psd_inverse: bool = False,
+                 out=None):
+        """[B, 2] = (<h|h>, <R|h>) of stored slices A, E [B, N] starting at start_bin [B]"""
+        A = self._dev(A, torch.complex128, "A")
+        E = self._dev(E, torch.complex128, "E")
+        if A.dim() != 2 or A.shape != E.shape:
+            raise ValueError("A and E must have the same shape [B, N]")
+        B, N = A.shape
+        start_bin = self._dev(start_bin, torch.int64, "start_bin")
+        residual = self._residual(residual)
+        psd = self._dev(psd, torch.float64, "psd")
+        if psd.dim() != 3 or psd.shape[1] != 2 or psd.shape[2] != self.n_bins:
+            raise ValueError("psd must have shape [n_psd, 2, n_bins]")
+        if res_idx is None:
+            res_idx = torch.zeros(B, dtype=torch.int32, device=self.device)
+        if psd_idx is None:
+            psd_idx = torch.zeros(B, dtype=torch.int32, device=self.device)
+        res_idx = self._dev(res_idx, torch.int32, "res_idx")
+        psd_idx = self._dev(psd_idx, torch.int32, "psd_idx")
+        if start_bin.numel() != B or res_idx.numel() != B or psd_idx.numel() != B:
+            raise ValueError("start_bin/res_idx/psd_idx must have B entries")
+        if out is None:
+            out = torch.empty((B, 2), dtype=torch.float64, device=self.device)
+        self._sync_stream()
+        rc = self.lib.gb_inner(self._h, _ptr(A), _ptr(E), _ptr(start_bin), int(N), _ptr(residual),
+                               residual.shape[0], _ptr(psd), psd.shape[0], GBL_PSD_INVERSE if psd_inverse else 0,
+                               _ptr(res_idx), _ptr(psd_idx), B, _ptr(out))
+        self._check(rc, "gb_inner")
+        return out
+
+    def gb_overlap(self, params_a, params_b, N: int, psd, psd_idx=None, psd_inverse: bool = False, out=None):
+        """[B, 4] = (<a|a>, <b|b>, <a|b>, normalised overlap) of template pairs"""
+        params_a = self._params(params_a, "params_a")
+        params_b = self._params(params_b, "params_b")
+        if params_a.shape != params_b.shape:
+            raise ValueError("params_a and params_b must have the same shape")
+        B = params_a.shape[0]
+        psd = self._dev(psd, torch.float64, "psd")
+        if psd.dim() != 3 or psd.shape[1] != 2 or psd.shape[2] != self.n_bins:
+            raise ValueError("psd must have shape [n_psd, 2, n_bins]")
+        if psd_idx is None:
+            psd_idx = torch.zeros(B, dtype=torch.int32, device=self.device)
+        psd_idx = self._dev(psd_idx, torch.int32, "psd_idx")
+        if out is None:
+            out = torch.empty((B, 4), dtype=torch.float64, device=self.device)
+        self._sync_stream()
+        rc = self.lib.gb_overlap(self._h, _ptr(params_a), _ptr(params_b), int(N), _ptr(psd), psd.shape[0],
+                                 GBL_PSD_INVERSE if psd_inverse else 0, _ptr(psd_idx), B, _ptr(out))
+        self._check(rc, "gb_overlap")
+        return out
+
+    def gb_snr(self, params, N: int, psd, psd_idx=None, data=None, data_idx=None, psd_inverse: bool = False):
+        """(optimal SNR [B], observed SNR [B] or None)"""
+        params = self._params(params)
+        B = params.shape[0]
+        psd = self._dev(psd, torch.float64, "psd")
+        if psd.dim() != 3 or psd.shape[1] != 2 or psd.shape[2] != self.n_bins:
+            raise ValueError("psd must have shape [n_psd, 2, n_bins]")
+        if psd_idx is None:
+            psd_idx = torch.zeros(B, dtype=torch.int32, device=self.device)
+        psd_idx = self._dev(psd_idx, torch.int32, "psd_idx")
+        opt = torch.empty(B, dtype=torch.float64, device=self.device)
+        obs = None
+        if data is not None:
+            data = self._residual(data)
+            if data_idx is None:
+                data_idx = torch.zeros(B, dtype=torch.int32, device=self.device)
+            data_idx = self._dev(data_idx, torch.int32, "data_idx")
+            obs = torch.empty(B, dtype=torch.float64, device=self.device)
+        self._sync_stream()
+        rc = self.lib.gb_snr(self._h, _ptr(params), B, int(N), _ptr(psd), psd.shape[0],
+                             GBL_PSD_INVERSE if psd_inverse else 0, _ptr(psd_idx), _ptr(data),
+                             data.shape[0] if data is not None else 0, _ptr(data_idx) if data is not None else None,
+                             _ptr(opt), _ptr(obs))
+        self._check(rc, "gb_snr")
+        return opt, obs
 
     def gb_scatter_add(self, params, N: int, sign: float, residual, res_idx=None):
         params = self._params(params)

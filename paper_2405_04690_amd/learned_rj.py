@@ -8,9 +8,13 @@ starts from the injections.  The sampler first runs with prior RJ draws and
 collects cold-chain samples; the flow is trained on them with the library's
 own training kernels.  Two measurements follow, each once with prior RJ
 draws and once with the flow mixture (prior share 0.2) as the RJ proposal:
-(1) stationary mixing: from the same saved state, the same number of sweeps,
-recording per sweep the cold chain's source count and band log-likelihood
-per (walker, band) for their ESS per second; (2) discovery: from every slot
+(1) stationary mixing: the state is first equilibrated with the flow mixture
+(the better-mixing chain), then from that saved state the same number of
+sweeps runs with each proposal, recording per sweep the cold chain's source
+count and band log-likelihood per (walker, band) for their ESS per second;
+both chains must then agree on the mean source count and mean cold
+log-likelihood within their Monte Carlo errors (the check that the
+comparison is stationary is reported next to the ratios); (2) discovery: from every slot
 empty, the fraction of (walker, injected source) pairs the cold chain has
 recovered per sweep.  Everything runs through the C ABI; only the
 bookkeeping (trace copies, ESS, recovery fractions) is host-side.
@@ -187,14 +191,22 @@ def measure(sw: Sweep, n_sweeps: int, flow: Flow | None = None):
     k = torch.stack(k_tr, dim=-1).double().cpu().numpy()   # [n_w][n_b][n_sweeps]
     lnl = torch.stack(l_tr, dim=-1).cpu().numpy()
     dst = (sw.stats - st0).cpu().numpy()
-    ess_k = float(sum(ess_mod.ess(k[:, b, :]) for b in range(k.shape[1])))
-    ess_l = float(sum(ess_mod.ess(lnl[:, b, :]) for b in range(lnl.shape[1])))
+    ess_kb = [ess_mod.ess(k[:, b, :]) for b in range(k.shape[1])]
+    ess_lb = [ess_mod.ess(lnl[:, b, :]) for b in range(lnl.shape[1])]
+    ess_k = float(sum(ess_kb))
+    ess_l = float(sum(ess_lb))
+    # Monte Carlo error of the band-summed means: per band var / ESS, summed
+    # over the (independent) bands, then divided by the band count squared
+    nb = k.shape[1]
+    se_k = float(np.sqrt(sum(k[:, b, :].var() / max(e, 1.0) for b, e in enumerate(ess_kb))) / nb)
+    se_l = float(np.sqrt(sum(lnl[:, b, :].var() / max(e, 1.0) for b, e in enumerate(ess_lb))) / nb)
     return {"sweeps": n_sweeps, "wall_s": wall,
             "birth_acceptance": float(dst[3]) / max(1.0, float(dst[2])),
             "death_acceptance": float(dst[5]) / max(1.0, float(dst[4])),
             "rj_accepted_per_s": float(dst[3] + dst[5]) / wall,
             "ess_k": ess_k, "ess_logl": ess_l, "ess_k_per_s": ess_k / wall, "ess_logl_per_s": ess_l / wall,
-            "mean_k": float(k.mean())}
+            "mean_k": float(k.mean()), "se_mean_k": se_k,
+            "mean_logl": float(lnl.mean()), "se_mean_logl": se_l}
 
 
 def empty_state(problem: Problem):
@@ -245,11 +257,22 @@ def discover(problem: Problem, n_sweeps: int, flow: Flow | None, start):
                                for j in range(traj.shape[1])]}
 
 
+def stationarity(plain, learned):
+    """z-scores of the differences of the two chains' mean source count and mean
+    cold log-likelihood, in units of their combined Monte Carlo error"""
+    zk = (plain["mean_k"] - learned["mean_k"]) / max(np.hypot(plain["se_mean_k"], learned["se_mean_k"]), 1e-300)
+    zl = (plain["mean_logl"] - learned["mean_logl"]) / max(np.hypot(plain["se_mean_logl"],
+                                                                    learned["se_mean_logl"]), 1e-300)
+    return {"z_mean_k": float(zk), "z_mean_logl": float(zl), "stationary": bool(abs(zk) < 3 and abs(zl) < 3)}
+
+
 def compare(problem: Problem, burn: int = 100, collect_sweeps: int = 200, train_steps: int = 300,
-            measure_sweeps: int = 400, lr: float = 1e-3, seed: int = 0, balance: bool = False):
+            measure_sweeps: int = 400, lr: float = 1e-3, seed: int = 0, balance: bool = False,
+            equilibrate: int = 200):
     """burn-in and sample collection with prior RJ, flow training (samples
-    weighted per source if balance), then the same number of sweeps from the
-    same state with each proposal"""
+    weighted per source if balance), equilibration with the flow mixture, then
+    the same number of sweeps from the same equilibrated state with each
+    proposal"""
     from .flow import init_params
     sw = problem.sweep
     sw.run(burn)
@@ -262,6 +285,8 @@ def compare(problem: Problem, burn: int = 100, collect_sweeps: int = 200, train_
     losses = train(flow, u, band, train_steps, lr=lr, seed=seed, weights=weights)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
+    for _ in range(equilibrate):
+        sw.run_flow(flow, 1)
     state = save(sw)
     plain = measure(sw, measure_sweeps, None)
     restore(sw, state)
@@ -273,7 +298,8 @@ def compare(problem: Problem, burn: int = 100, collect_sweeps: int = 200, train_
     return {"training_samples": int(u.shape[0]), "train_steps": train_steps,
             "train_ms_per_step": 1e3 * t_train / max(1, train_steps),
             "loss_first": float(np.mean(losses[:10])), "loss_last": float(np.mean(losses[-10:])),
-            "plain": plain, "learned": learned,
+            "equilibration_sweeps": equilibrate, "plain": plain, "learned": learned,
+            "stationarity": stationarity(plain, learned),
             "discovery": {"plain": disc_plain, "learned": disc_learned},
             "gain_ess_k_per_s": learned["ess_k_per_s"] / max(plain["ess_k_per_s"], 1e-300),
             "gain_ess_logl_per_s": learned["ess_logl_per_s"] / max(plain["ess_logl_per_s"], 1e-300),

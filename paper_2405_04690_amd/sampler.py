@@ -22,11 +22,16 @@ DEFAULT_PRIOR_HI = (-21.0, 0.0, 1e-15, 0.0, 1.0, 0.0, 0.0, 1.0)
 
 
 def make_config(n_temps, n_walkers, n_bands, n_slots, N, k_band0, n_prop=10, n_friends=8, group_every=30,
-                stretch_a=2.0, seed=1234, prior_lo=DEFAULT_PRIOR_LO, prior_hi=DEFAULT_PRIOR_HI, cls=SweepConfig):
+                stretch_a=2.0, seed=1234, prior_lo=DEFAULT_PRIOR_LO, prior_hi=DEFAULT_PRIOR_HI, cls=SweepConfig,
+                adapt_ladder=False, shift_ownership=False, adapt_lag=10000.0, adapt_time=100.0):
+    """adapt_lag / adapt_time: t0 and nu of the ladder adaptation's step
+    t0 / (nu (t + t0)) (defaults as commonly used with the Vousden scheme)"""
     c = cls()
     c.n_temps, c.n_walkers, c.n_bands, c.n_slots = n_temps, n_walkers, n_bands, n_slots
     c.N, c.n_prop, c.n_friends, c.group_every = N, n_prop, n_friends, group_every
     c.k_band0, c.stretch_a, c.seed = k_band0, stretch_a, seed
+    c.adapt_ladder, c.shift_ownership = int(bool(adapt_ladder)), int(bool(shift_ownership))
+    c.adapt_lag, c.adapt_time = float(adapt_lag), float(adapt_time)
     for i in range(8):
         c.prior_lo[i] = prior_lo[i]
         c.prior_hi[i] = prior_hi[i]
@@ -46,7 +51,8 @@ class Sweep:
         self.inv_psd = torch.zeros((nw, 2, ctx.n_bins), **f64)
         self.group = torch.zeros((nb, nw * ns, 8), **f64)
         self.group_count = torch.zeros(nb, dtype=torch.int32, device=dev)
-        self.stats = torch.zeros(8, dtype=torch.int64, device=dev)
+        self.stats = torch.zeros(10, dtype=torch.int64, device=dev)
+        self.swap_acc = torch.zeros((nb, nt), dtype=torch.int32, device=dev)
         self.sweep_counter = torch.zeros(1, dtype=torch.int64, device=dev)
         # optional: RJ proposal arrays (flow proposals) and the cold-chain logL trace
         self.prop_u = None
@@ -83,7 +89,7 @@ class Sweep:
     def _state(self):
         st = SweepState()
         for n in ("u", "exists", "betas", "resid", "inv_psd", "group", "group_count", "stats", "sweep_counter",
-                  "prop_u", "rj_logq", "cold_logl", "rj_mode", "spec_pool", "pool_flags"):
+                  "prop_u", "rj_logq", "cold_logl", "rj_mode", "spec_pool", "pool_flags", "swap_acc"):
             t = getattr(self, n)
             setattr(st, n, t.data_ptr() if t is not None else None)
         st.pool_size = self.spec_pool.shape[0] if self.spec_pool is not None else 0
@@ -102,6 +108,12 @@ class Sweep:
 
     def advance(self):
         self._call("gb_sweep_advance", ctypes.byref(self._state()))
+
+    def adapt_ladder(self):
+        self._call("gb_sweep_adapt_ladder", ctypes.byref(self.cfg), ctypes.byref(self._state()))
+
+    def shift_ownership(self):
+        self._call("gb_sweep_shift_ownership", ctypes.byref(self.cfg), ctypes.byref(self._state()))
 
     def run(self, n_sweeps: int):
         self._call("gb_sweep_run", ctypes.byref(self.cfg), ctypes.byref(self._state()), int(n_sweeps))
@@ -162,9 +174,15 @@ class Sweep:
 
 
 def psd_config(n_tn: int, n_walkers: int, prior_lo, prior_hi, stretch_a: float = 2.0, seed: int = 4321):
+    """noise-step configuration; 4 prior bounds (instrument noise) or 9 (with the
+    Galactic foreground (A_fg, alpha, f_k, s1, s2))"""
+    n_par = len(prior_lo)
+    if n_par not in (4, 9) or len(prior_hi) != n_par:
+        raise ValueError("prior_lo/prior_hi must both have 4 or 9 entries")
     c = PsdSweepConfig()
-    c.n_tn, c.n_walkers, c.stretch_a, c.seed = int(n_tn), int(n_walkers), float(stretch_a), int(seed)
-    for k in range(4):
+    c.n_tn, c.n_walkers, c.n_par = int(n_tn), int(n_walkers), n_par
+    c.stretch_a, c.seed = float(stretch_a), int(seed)
+    for k in range(n_par):
         c.prior_lo[k], c.prior_hi[k] = float(prior_lo[k]), float(prior_hi[k])
     return c
 
@@ -184,7 +202,7 @@ class PsdSweep:
         if self.data.shape != (2, ctx.n_bins):
             raise ValueError("data must have shape [2, n_bins]")
         f64 = dict(dtype=torch.float64, device=dev)
-        self.theta = torch.zeros((nt, nw, 4), **f64)
+        self.theta = torch.zeros((nt, nw, cfg.n_par), **f64)
         self.logl = torch.zeros((nt, nw), **f64)
         self.betas = torch.ones(nt, **f64)
         self.full_resid = torch.zeros((nw, 2, ctx.n_bins), dtype=torch.complex128, device=dev)

@@ -14,10 +14,13 @@ from paper_2405_04690_amd import inputs
 N = 128
 
 
-def problem(n_t=3, n_w=4, n_b=6, n_slots=4, n_prop=6, n_friends=4, group_every=1, seed=77, beta_top=0.3, N=N):
-    cfg = inputs.TINY
+def problem(n_t=3, n_w=4, n_b=6, n_slots=4, n_prop=6, n_friends=4, group_every=1, seed=77, beta_top=0.3, N=N,
+            cfg=None, per_band=2, f_band0=3e-3):
+    """per_band injections per sub-band, each held by one slot of every chain
+    (jittered); cfg defaults to the 0.25 yr configuration"""
+    cfg = inputs.TINY if cfg is None else cfg
     orc = oracle.Oracle(T=cfg.T, dt=cfg.dt, L=cfg.L, f_lo=cfg.f_lo, f_hi=cfg.f_hi)
-    k_band0 = int(3e-3 * cfg.T)
+    k_band0 = int(f_band0 * cfg.T)
     sc = oracle.SweepConfig()
     sc.n_temps, sc.n_walkers, sc.n_bands, sc.n_slots = n_t, n_w, n_b, n_slots
     sc.N, sc.n_prop, sc.n_friends, sc.group_every = N, n_prop, n_friends, group_every
@@ -28,10 +31,10 @@ def problem(n_t=3, n_w=4, n_b=6, n_slots=4, n_prop=6, n_friends=4, group_every=1
         sc.prior_lo[i], sc.prior_hi[i] = lo[i], hi[i]
     st = oracle.SweepState(sc, orc.n_bins)
     rng = np.random.default_rng(seed)
-    # injections: two per band, loud enough to matter
+    # injections: per_band per band, loud enough to matter
     src = []
     for b in range(n_b):
-        for _ in range(2):
+        for _ in range(per_band):
             f0 = (k_band0 + (b + rng.uniform(0.1, 0.9)) * N) / cfg.T
             src.append([10 ** rng.uniform(-22.0, -21.3), f0, 0.0, rng.uniform(0, 2 * np.pi),
                         np.arccos(rng.uniform(-1, 1)), rng.uniform(0, np.pi), rng.uniform(0, 2 * np.pi),
@@ -40,12 +43,12 @@ def problem(n_t=3, n_w=4, n_b=6, n_slots=4, n_prop=6, n_friends=4, group_every=1
     S = orc.psd_eval(np.array([cfg.sqrt_oms, cfg.sqrt_acc, cfg.sqrt_oms, cfg.sqrt_acc]))[0]
     data = np.sqrt(S / (4 * orc.df)) * inputs.complex_normals(seed + 1, (2, orc.n_bins))
     orc.scatter_add(src, N, 1.0, data)
-    # slots: jittered injections (first two slots of each band), the rest empty
+    # slots: jittered injections (first per_band slots of each band), the rest empty
     for t in range(n_t):
         for w in range(n_w):
             for b in range(n_b):
-                for s in range(2):
-                    p = src[2 * b + s]
+                for s in range(per_band):
+                    p = src[per_band * b + s]
                     st.u[t, w, b, s] = [np.log10(p[0]) + rng.normal(0, 0.02), p[1] + rng.normal(0, 0.2) / cfg.T,
                                         p[2], p[3], np.cos(p[4]), p[5], p[6], np.sin(p[7])]
                     st.exists[t, w, b, s] = 1
@@ -53,10 +56,9 @@ def problem(n_t=3, n_w=4, n_b=6, n_slots=4, n_prop=6, n_friends=4, group_every=1
         st.inv_psd[w] = 1.0 / S
         for par in (0, 1):
             st.resid[par, w] = data
-            for b in range(par, n_b, 2):
-                for s in range(n_slots):
-                    if st.exists[0, w, b, s]:
-                        orc.scatter_add(_phys(st.u[0, w, b, s])[None], N, -1.0, st.resid[par, w])
+            occ = [_phys(st.u[0, w, b, s]) for b in range(par, n_b, 2) for s in range(n_slots) if st.exists[0, w, b, s]]
+            if occ:
+                orc.scatter_add(np.array(occ), N, -1.0, st.resid[par, w])
     ladder = np.geomspace(1.0, beta_top, n_t) if n_t > 1 else np.ones(1)
     st.betas[:] = ladder[None, :]
     st.data = data

@@ -46,6 +46,10 @@ def test_null_context_rejected_on_host(lib):
     assert lib.gb_psd_loglike(null, null, 1, null, null, 1, null) == gbl.GBL_EINVAL
     assert lib.gb_scatter_add(null, null, 1, 256, 1.0, null, 1, null) == gbl.GBL_EINVAL
     assert lib.gb_make_noise(null, null, null, 1, null) == gbl.GBL_EINVAL
+    assert lib.gb_psd_eval_n(null, null, 9, 1, 0, null) == gbl.GBL_EINVAL
+    assert lib.gb_psd_loglike_n(null, null, 1, null, 9, null, 1, null) == gbl.GBL_EINVAL
+    assert lib.gb_inner(null, null, null, null, 256, null, 1, null, 1, 0, null, null, 1, null) == gbl.GBL_EINVAL
+    assert lib.gb_snr(null, null, 1, 256, null, 1, 0, null, null, 0, null, null, null) == gbl.GBL_EINVAL
     assert lib.gbl_destroy(null) == gbl.GBL_OK
     assert lib.gbl_last_error(null) == b"null context"
 

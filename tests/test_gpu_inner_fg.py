@@ -1,0 +1,315 @@
+"""GPU parity of the stored-slice inner products (gb_inner), the SNRs (gb_snr),
+the deterministic scatter-add and the Galactic-foreground PSD term (gb_psd_eval /
+gb_psd_loglike with nine noise parameters, and the nine-parameter noise step)
+against the FP64 CPU oracle on the same seeded inputs."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2405_04690_amd import inputs
+from paper_2405_04690_amd.gbl import GBL_DETERMINISTIC, Context, GBL_EINVAL
+from paper_2405_04690_amd.sampler import PsdSweep, Sweep, make_config, psd_config
+
+pytestmark = pytest.mark.gpu
+
+CFG = inputs.TINY
+FG_EXAMPLE = np.array([3.3e-44, 1.2, 2.8e-3, 1763.3, 1686.3])  # the paper's example foreground
+
+
+def _dev():
+    return torch.device("cuda", 0)
+
+
+def _t(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(_dev())
+
+
+@pytest.fixture(scope="module")
+def tiny():
+    ctx = Context(T=CFG.T, dt=CFG.dt, L=CFG.L, f_lo=CFG.f_lo, f_hi=CFG.f_hi)
+    det = Context(T=CFG.T, dt=CFG.dt, L=CFG.L, f_lo=CFG.f_lo, f_hi=CFG.f_hi, flags=GBL_DETERMINISTIC)
+    orc = oracle.Oracle(T=CFG.T, dt=CFG.dt, L=CFG.L, f_lo=CFG.f_lo, f_hi=CFG.f_hi)
+    noise = np.array([[CFG.sqrt_oms, CFG.sqrt_acc, CFG.sqrt_oms, CFG.sqrt_acc],
+                      [1.2 * CFG.sqrt_oms, 0.9 * CFG.sqrt_acc, 0.8 * CFG.sqrt_oms, 1.1 * CFG.sqrt_acc]])
+    S = orc.psd_eval(noise)
+    src = inputs.draw_sources(500, 48, log10_fdot_range=(-19, -15))
+    R = np.zeros((3, 2, orc.n_bins), np.complex128)
+    for w in range(3):
+        R[w] = np.sqrt(S[0] / (4 * orc.df)) * inputs.complex_normals(510 + w, (2, orc.n_bins))
+        orc.scatter_add(src, CFG.N, +1.0, R[w])
+    yield ctx, det, orc, S, R, src
+    ctx.close()
+    det.close()
+
+
+def _edge_params(orc):
+    """band-edge straddles (low and high), fully outside, zero amplitude, NaN"""
+    base = inputs.draw_sources(520, 1)[0]
+    out = []
+    for f in ((orc.k_min + 5.3) / orc.T, (orc.k_min - 40.2) / orc.T, (orc.k_min + orc.n_bins - 9.6) / orc.T,
+              (orc.k_min + orc.n_bins + 900.5) / orc.T):
+        p = base.copy(); p[1] = f; out.append(p)
+    z = base.copy(); z[0] = 0.0; out.append(z)
+    n = base.copy(); n[3] = np.nan; out.append(n)
+    return np.array(out)
+
+
+# --------------------------------------------------------------------------
+# gb_inner
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("N", [128, 256, 1024])
+@pytest.mark.parametrize("inverse", [False, True])
+def test_inner_matches_oracle(tiny, N, inverse):
+    ctx, _, orc, S, R, src = tiny
+    params = np.vstack([inputs.perturb(530 + N, src, orc.T, "inmodel"), _edge_params(orc)[:5]])
+    B = len(params)
+    print(f"gb_inner N={N} inverse={inverse} B={B}", flush=True)
+    A, E, _, sb = orc.waveform(params, N, with_T=False)
+    rng = np.random.default_rng(531)
+    ri = rng.integers(0, 3, B).astype(np.int32)
+    pi = rng.integers(0, 2, B).astype(np.int32)
+    W = 1.0 / S if inverse else S
+    got = ctx.gb_inner(_t(A), _t(E), _t(sb.astype(np.int64)), _t(R), _t(W), _t(ri), _t(pi),
+                       psd_inverse=inverse).cpu().numpy()
+    ref = orc.inner(A, E, sb, R, W, ri, pi, psd_is_inverse=inverse)
+    scale = np.maximum(np.abs(ref).max(axis=1, keepdims=True), 1e-300)
+    assert np.max(np.abs(got - ref) / scale) <= 1e-12
+    # fully outside the band: exact zeros; zero amplitude: exact zeros
+    assert np.all(got[-4] == 0.0) and np.all(got[-1] == 0.0)
+    # fixed-order sums: bitwise reproducible
+    again = ctx.gb_inner(_t(A), _t(E), _t(sb.astype(np.int64)), _t(R), _t(W), _t(ri), _t(pi),
+                         psd_inverse=inverse).cpu().numpy()
+    assert np.array_equal(got, again)
+
+
+def test_inner_ragged_width_and_bad_indices(tiny):
+    """a width that is no power of two and not a multiple of the wave, an
+    out-of-range index (NaN), the empty batch, argument errors"""
+    ctx, _, orc, S, R, src = tiny
+    N = 333
+    B = 7
+    rng = np.random.default_rng(540)
+    A = rng.standard_normal((B, N, 2)).view(np.complex128)[..., 0] * 1e-20
+    E = rng.standard_normal((B, N, 2)).view(np.complex128)[..., 0] * 1e-20
+    sb = np.array([orc.k_min - 100, orc.k_min + 1000, orc.k_min + orc.n_bins - 50, 4000, 9000, 12345, 20000])
+    ri = np.array([0, 1, 2, 0, 1, 3, 2], np.int32)       # 3 is out of range
+    pi = np.array([0, 1, 0, 1, 0, 0, -1], np.int32)      # -1 is out of range
+    got = ctx.gb_inner(_t(A), _t(E), _t(sb), _t(R), _t(S), _t(ri), _t(pi)).cpu().numpy()
+    ok = np.array([0, 1, 2, 3, 4])
+    ref = orc.inner(A[ok], E[ok], sb[ok], R, S, ri[ok], pi[ok])
+    assert np.max(np.abs(got[ok] - ref) / np.abs(ref).max(axis=1, keepdims=True)) <= 1e-12
+    assert np.all(np.isnan(got[5:]))
+    empty = ctx.gb_inner(_t(A[:0]), _t(E[:0]), _t(sb[:0]), _t(R), _t(S), _t(ri[:0]), _t(pi[:0]))
+    assert empty.shape == (0, 2)
+    with pytest.raises(ValueError):
+        ctx.gb_inner(_t(A), _t(E[:, :10]), _t(sb), _t(R), _t(S))   # the binding checks shapes
+    import ctypes
+    out = torch.empty((B, 2), dtype=torch.float64, device=_dev())
+    rc = ctx.lib.gb_inner(ctx._h, None, None, None, N, None, 3, None, 2, 0, None, None, B,
+                          ctypes.c_void_p(out.data_ptr()))
+    assert rc == GBL_EINVAL
+
+
+def test_inner_of_waveform_slices_gives_swap_terms(tiny):
+    """gb_waveform -> gb_inner: <R|a - r> - 1/2 <a - r|a - r> from two calls
+    of each equals gb_delta_loglike when both windows coincide (identical
+    carrier bin), which pins the slice layout the two calls share"""
+    ctx, _, orc, S, R, src = tiny
+    old = src[:16].copy()
+    new = old.copy()
+    new[:, 0] *= 1.05
+    new[:, 3] += 0.02
+    gA, gE, _, gsb = ctx.gb_waveform(_t(old), 128, with_T=False)
+    nA, nE, _, nsb = ctx.gb_waveform(_t(new), 128, with_T=False)
+    assert torch.equal(gsb, nsb)
+    dA, dE = nA - gA, nE - gE
+    terms = ctx.gb_inner(dA.contiguous(), dE.contiguous(), gsb, _t(R[:1]), _t(S[:1])).cpu().numpy()
+    dl = terms[:, 1] - 0.5 * terms[:, 0]
+    ref = ctx.gb_delta_loglike(_t(R[:1]), _t(S[:1]), _t(old), _t(new), 128).cpu().numpy()
+    _, ot = orc.delta_loglike(R[:1], S[:1], old, new, 128, return_terms=True)
+    scale = np.maximum(1.0, np.abs(ot[:, :5]).max(axis=1))
+    assert np.max(np.abs(dl - ref) / scale) <= 1e-9
+
+
+# --------------------------------------------------------------------------
+# gb_snr
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("N", [128, 512])
+def test_snr_matches_oracle(tiny, N):
+    ctx, _, orc, S, R, src = tiny
+    params = np.vstack([src[:30], _edge_params(orc)])
+    B = len(params)
+    print(f"gb_snr N={N} B={B}", flush=True)
+    pi = (np.arange(B) % 2).astype(np.int32)
+    di = (np.arange(B) % 3).astype(np.int32)
+    opt, obs = ctx.gb_snr(_t(params), N, _t(S), _t(pi), _t(R), _t(di))
+    opt, obs = opt.cpu().numpy(), obs.cpu().numpy()
+    ro, rb = orc.snr(params, N, S, pi, R, di)
+    fin = np.isfinite(ro)
+    assert np.array_equal(fin, np.isfinite(opt))
+    assert np.max(np.abs(opt[fin] - ro[fin]) / np.maximum(ro[fin], 1e-300)) <= 1e-9
+    ok = np.isfinite(rb)
+    assert np.array_equal(ok, np.isfinite(obs))
+    assert np.max(np.abs(obs[ok] - rb[ok]) / np.maximum(np.abs(ro[ok]), 1.0)) <= 1e-9
+    assert opt[-2] == 0.0 and np.isnan(obs[-2])            # zero amplitude: 0 and 0/0
+    assert np.isnan(opt[-1]) and np.isnan(obs[-1])         # undefined parameters
+    opt2, none = ctx.gb_snr(_t(params), N, _t(1.0 / S), _t(pi), psd_inverse=True)
+    assert none is None
+    assert np.max(np.abs(opt2.cpu().numpy()[fin] - ro[fin]) / np.maximum(ro[fin], 1e-300)) <= 1e-9
+
+
+# --------------------------------------------------------------------------
+# deterministic scatter-add
+# --------------------------------------------------------------------------
+def test_deterministic_scatter(tiny):
+    """overlapping templates (copies of one source, neighbours within a
+    window), several residual rows, band edges, zero and undefined templates:
+    bitwise equal over repeated calls, equal to the oracle's sequential adds
+    to rounding, and equal to the atomic path to rounding"""
+    ctx, det, orc, S, R, src = tiny
+    base = src[:24]
+    crowd = inputs.perturb(550, np.repeat(base[:4], 12, axis=0), orc.T, "jitter")
+    params = np.vstack([base, crowd, _edge_params(orc)])
+    B = len(params)
+    ri = np.random.default_rng(551).integers(0, 3, B).astype(np.int32)
+    ri[-1] = 7  # out of range: adds nothing
+    start = np.zeros((3, 2, orc.n_bins), np.complex128)
+    print(f"deterministic scatter B={B}", flush=True)
+    outs = []
+    for rep in range(3):
+        dev = _t(start.copy())
+        det.gb_scatter_add(_t(params), 256, -0.75, dev, _t(ri))
+        outs.append(dev.cpu().numpy())
+    assert np.array_equal(outs[0].view(np.uint64), outs[1].view(np.uint64))
+    assert np.array_equal(outs[0].view(np.uint64), outs[2].view(np.uint64))
+    exp = start.copy()
+    ok = ri < 3
+    orc.scatter_add(params[ok], 256, -0.75, exp, ri[ok])
+    scale = np.abs(exp).max()
+    assert np.max(np.abs(outs[0] - exp)) <= 1e-12 * scale
+    at = _t(start.copy())
+    ctx.gb_scatter_add(_t(params[ok]), 256, -0.75, at, _t(ri[ok]))
+    assert np.max(np.abs(outs[0] - at.cpu().numpy())) <= 1e-12 * scale
+
+
+def test_deterministic_scatter_chunks(tiny):
+    """more templates than one workspace chunk (2^22 / N at N = 1024: 4096),
+    added onto a non-zero residual"""
+    ctx, det, orc, S, R, src = tiny
+    B = 4096 + 37
+    params = inputs.perturb(560, src[np.arange(B) % len(src)], orc.T, "jitter")
+    ri = (np.arange(B) % 3).astype(np.int32)
+    print(f"deterministic scatter chunks B={B} N=1024", flush=True)
+    a = _t(R.copy())
+    b = _t(R.copy())
+    det.gb_scatter_add(_t(params), 1024, 1.0, a, _t(ri))
+    det.gb_scatter_add(_t(params), 1024, 1.0, b, _t(ri))
+    a, b = a.cpu().numpy(), b.cpu().numpy()
+    assert np.array_equal(a.view(np.uint64), b.view(np.uint64))
+    idx = np.random.default_rng(561).choice(B, 60, replace=False)
+    # linearity: adding the sampled templates again with the oracle equals the
+    # GPU adding them twice, up to rounding
+    c = _t(a.copy())
+    det.gb_scatter_add(_t(params[idx]), 1024, 1.0, c, _t(ri[idx]))
+    exp = a.copy()
+    orc.scatter_add(params[idx], 1024, 1.0, exp, ri[idx])
+    assert np.max(np.abs(c.cpu().numpy() - exp)) <= 1e-12 * np.abs(exp).max()
+
+
+# --------------------------------------------------------------------------
+# Galactic foreground
+# --------------------------------------------------------------------------
+def _noise9(rng, P):
+    n4 = np.column_stack([CFG.sqrt_oms * rng.uniform(0.5, 2, P), CFG.sqrt_acc * rng.uniform(0.5, 2, P),
+                          CFG.sqrt_oms * rng.uniform(0.5, 2, P), CFG.sqrt_acc * rng.uniform(0.5, 2, P)])
+    fg = np.column_stack([FG_EXAMPLE[0] * rng.uniform(0.1, 10, P), rng.uniform(0.8, 1.6, P),
+                          rng.uniform(1.5e-3, 4e-3, P), rng.uniform(500, 3000, P), rng.uniform(500, 3000, P)])
+    return np.hstack([n4, fg])
+
+
+def test_foreground_psd_eval_and_loglike(tiny):
+    ctx, _, orc, S, R, src = tiny
+    rng = np.random.default_rng(570)
+    P = 23
+    noise = _noise9(rng, P)
+    noise[0, 4:] = FG_EXAMPLE
+    noise[1, 4] = 0.0                                    # A_fg = 0: the instrument PSD exactly
+    print(f"foreground PSD P={P}", flush=True)
+    gS = ctx.gb_psd_eval(_t(noise)).cpu().numpy()
+    oS = orc.psd_eval_n(noise, 9)
+    assert np.max(np.abs(gS / oS - 1)) <= 1e-13
+    assert np.array_equal(gS[1], ctx.gb_psd_eval(_t(noise[1:2, :4])).cpu().numpy()[0])
+    gI = ctx.gb_psd_eval(_t(noise), inverse=True).cpu().numpy()
+    assert np.max(np.abs(gI * oS - 1)) <= 1e-13
+    ri = rng.integers(0, 3, P).astype(np.int32)
+    g1 = ctx.gb_psd_loglike(_t(R), _t(noise), _t(ri)).cpu().numpy()
+    ref = orc.psd_loglike_n(R, noise, 9, ri)
+    assert np.max(np.abs(g1 - ref) / np.abs(ref)) <= 1e-12
+    one = np.concatenate([ctx.gb_psd_loglike(_t(R), _t(noise[i:i + 1]), _t(ri[i:i + 1])).cpu().numpy()
+                          for i in range(P)])
+    assert np.array_equal(one, g1)                       # grouping of sets does not change a result
+    # the foreground raises S, so with A_fg = 0 the likelihood is the four-parameter one
+    four = ctx.gb_psd_loglike(_t(R), _t(noise[1:2, :4]), _t(ri[1:2])).cpu().numpy()
+    assert g1[1] == four[0]
+
+
+def test_foreground_noise_step_matches_oracle():
+    """nine-parameter noise step (instrument + foreground): accept decisions
+    and counters exact, parameters and log-likelihoods to rounding"""
+    nt, nw = 3, 6
+    LO = (10e-12, 2e-15, 10e-12, 2e-15, 1e-44, 0.8, 1.5e-3, 500.0, 500.0)
+    HI = (20e-12, 4e-15, 20e-12, 4e-15, 1e-43, 1.6, 4.0e-3, 3000.0, 3000.0)
+    orc = oracle.Oracle(T=CFG.T, dt=CFG.dt, L=CFG.L, f_lo=CFG.f_lo, f_hi=CFG.f_hi)
+    th0 = np.concatenate([[CFG.sqrt_oms, CFG.sqrt_acc, CFG.sqrt_oms, CFG.sqrt_acc], FG_EXAMPLE])
+    S = orc.psd_eval_n(th0, 9)[0]
+    amp = np.sqrt(S / (4 * orc.df))
+    data = amp * inputs.complex_normals(581, (2, orc.n_bins))
+    x = amp * inputs.complex_normals(582, (nw, 2, orc.n_bins))
+    y = 0.3 * amp * inputs.complex_normals(583, (nw, 2, orc.n_bins))
+    resid = np.stack([data[None] + x, data[None] - x + y])
+    rng = np.random.default_rng(584)
+    theta = np.array(LO) + (np.array(HI) - np.array(LO)) * rng.uniform(size=(nt, nw, 9))
+    betas = np.array([1.0, 0.5, 0.2])
+    pco = oracle.PsdSweepConfig()
+    pco.n_tn, pco.n_walkers, pco.n_par, pco.stretch_a, pco.seed = nt, nw, 9, 2.0, 585
+    for k in range(9):
+        pco.prior_lo[k], pco.prior_hi[k] = LO[k], HI[k]
+    ctx = Context(T=CFG.T, dt=CFG.dt, L=CFG.L, f_lo=CFG.f_lo, f_hi=CFG.f_hi)
+    sc = make_config(1, nw, 2, 1, 128, int(3e-3 * CFG.T))
+    sw = Sweep(ctx, sc)
+    sw.resid.copy_(torch.from_numpy(resid))
+    ps = PsdSweep(sw, psd_config(nt, nw, LO, HI, seed=585), torch.from_numpy(data).cuda())
+    assert tuple(ps.theta.shape) == (nt, nw, 9)
+    ps.theta.copy_(torch.from_numpy(theta))
+    ps.betas.copy_(torch.from_numpy(betas))
+    logl = np.zeros((nt, nw))
+    inv = np.zeros((nw, 2, orc.n_bins))
+    st = np.zeros(4, np.int64)
+    th = theta.copy()
+    for s in range(4):
+        print(f"foreground noise step sweep {s}", flush=True)
+        sw.sweep_counter.fill_(s)
+        ps.step()
+        oracle.psd_sweep_step(orc, pco, s, th, logl, betas, data, resid, inv, st)
+        torch.cuda.synchronize()
+        assert np.array_equal(ps.stats.cpu().numpy(), st), s
+        assert np.allclose(ps.theta.cpu().numpy(), th, rtol=1e-12, atol=0), s
+        assert np.allclose(ps.logl.cpu().numpy(), logl, rtol=1e-12, atol=0), s
+        assert np.allclose(sw.inv_psd.cpu().numpy(), inv, rtol=1e-13, atol=0), s
+    assert st[1] > 0 and st[1] < st[0] and st[3] > 0
+    ctx.close()
+
+
+def test_foreground_argument_errors(tiny):
+    ctx, _, orc, S, R, src = tiny
+    with pytest.raises(ValueError):
+        ctx.gb_psd_eval(_t(np.ones((2, 5))))
+    with pytest.raises(ValueError):
+        psd_config(2, 4, (1.0,) * 5, (2.0,) * 5)
+    import ctypes
+    S_out = torch.empty((1, 2, ctx.n_bins), dtype=torch.float64, device=_dev())
+    noise = _t(np.ones((1, 9)))
+    rc = ctx.lib.gb_psd_eval_n(ctx._h, ctypes.c_void_p(noise.data_ptr()), 5, 1, 0,
+                               ctypes.c_void_p(S_out.data_ptr()))
+    assert rc == GBL_EINVAL

@@ -28,12 +28,12 @@ def _gpu_sweep(cfg, sc, st, stream=None, pool=1024):
         else:
             setattr(gc, name, v)
     sw = Sweep(ctx, gc, spectrum_pool=pool)
-    for name in ("u", "exists", "betas", "resid", "inv_psd", "group", "group_count", "stats"):
+    for name in ("u", "exists", "betas", "resid", "inv_psd", "group", "group_count", "stats", "swap_acc"):
         getattr(sw, name).copy_(torch.from_numpy(np.ascontiguousarray(getattr(st, name))))
     return ctx, sw
 
 
-def _compare(sw, st, what):
+def _compare(sw, st, what, T=None):
     torch.cuda.synchronize()
     ex = sw.exists.cpu().numpy()
     assert np.array_equal(ex, st.exists), f"{what}: occupancy differs"
@@ -41,7 +41,8 @@ def _compare(sw, st, what):
     u = sw.u.cpu().numpy()
     occ = st.exists.astype(bool)
     # per-coordinate scale: log10 A, f0 (one band), fdot, phi0, cos iota, psi, lambda, sin beta
-    width = np.array([2.5, 512 / sampler_setup.inputs.TINY.T, 1e-15, 2 * np.pi, 2.0, np.pi, 2 * np.pi, 2.0])
+    T = sampler_setup.inputs.TINY.T if T is None else T
+    width = np.array([2.5, 512 / T, 1e-15, 2 * np.pi, 2.0, np.pi, 2 * np.pi, 2.0])
     scale = np.maximum(np.abs(st.u[occ]), width)
     assert np.max(np.abs(u[occ] - st.u[occ]) / scale) <= 1e-10, f"{what}: coordinates differ"
     r = sw.resid.cpu().numpy()
@@ -387,4 +388,106 @@ def test_sweep_parity_at_the_slot_limit():
             oracle.sweep_step(orc, sc, st, move, parity, 2)
             sw.step(move, parity)
             _compare(sw, st, f"slot limit {move}/{parity}")
+    ctx.close()
+
+
+@pytest.mark.timeout(900)
+def test_sweep_parity_at_the_bench_shape():
+    """The benchmark's chain shape: 36 temperatures x 32 walkers x 60 slots,
+    1 yr at 5 s, N = 256, four sub-bands with every slot occupied, so each
+    stationary group holds 1,920 cold-chain sources (the 64-way friend search
+    over them) and tempering runs 36 rungs; one group refresh and one full
+    sweep (in-model, RJ, tempering; odd then even) against the oracle"""
+    from paper_2405_04690_amd import inputs
+    print("bench shape: building the problem on the host", flush=True)
+    cfg, orc, sc, st = sampler_setup.problem(n_t=36, n_w=32, n_b=4, n_slots=60, n_prop=4, n_friends=40,
+                                             group_every=1, seed=91, beta_top=0.02, N=256, cfg=inputs.PAPER,
+                                             per_band=60)
+    ctx, sw = _gpu_sweep(cfg, sc, st)
+    s0 = 5
+    sw.sweep_counter.fill_(s0)
+    oracle.sweep_group(sc, st)
+    sw.group_refresh()
+    torch.cuda.synchronize()
+    assert np.array_equal(sw.group_count.cpu().numpy(), st.group_count)
+    assert st.group_count.min() == 32 * 60
+    assert np.array_equal(sw.group.cpu().numpy(), st.group)
+    for move, name in ((0, "in-model"), (1, "rj"), (2, "tempering")):
+        for parity in (1, 0):
+            print(f"bench shape: {name} parity {parity}", flush=True)
+            sw.step(move, parity)
+            oracle.sweep_step(orc, sc, st, move, parity, s0)
+            _compare(sw, st, f"bench shape {name}/{parity}", T=cfg.T)
+    assert st.stats[1] > 0 and st.stats[5] > 0 and st.stats[7] > 0
+    ctx.close()
+
+
+def test_inmodel_draws_refill_past_64_proposals():
+    """n_prop = 70: the in-model loop's counter-based draws are computed 64
+    proposals at a time, so the second run (6 proposals) is a partial one"""
+    cfg, orc, sc, st = sampler_setup.problem(n_t=2, n_w=3, n_b=4, n_slots=4, n_prop=70, seed=93)
+    ctx, sw = _gpu_sweep(cfg, sc, st)
+    s0 = 6
+    sw.sweep_counter.fill_(s0)
+    oracle.sweep_group(sc, st)
+    sw.group_refresh()
+    for parity in (1, 0):
+        print(f"n_prop=70 in-model parity {parity}", flush=True)
+        oracle.sweep_step(orc, sc, st, 0, parity, s0)
+        sw.step(0, parity)
+        _compare(sw, st, f"n_prop=70/{parity}")
+    assert st.stats[0] == 70 * 2 * 3 * 4
+    ctx.close()
+
+
+def _push_over_edges(cfg, orc, sc, st, seed):
+    """move some cold-chain sources up to 0.45 band past an edge of their band
+    (inside the prior box) and rebuild the buffers"""
+    rng = np.random.default_rng(seed)
+    T, N, kb = cfg.T, sc.N, sc.k_band0
+    for w in range(sc.n_walkers):
+        for b in range(sc.n_bands):
+            for s in range(sc.n_slots):
+                if st.exists[0, w, b, s] and rng.uniform() < 0.4:
+                    d = rng.uniform(0.02, 0.45)
+                    st.u[0, w, b, s, 1] = (kb + (b + 1.0 + d if rng.uniform() < 0.5 else b - d) * N) / T
+    for par in (0, 1):
+        for w in range(sc.n_walkers):
+            st.resid[par, w] = sampler_setup.rebuild_buffer(orc, sc, st, par, w)
+
+
+def test_ladder_adaptation_and_ownership_shift_match_the_oracle():
+    """the two per-sweep steps on their own (given swap counts; strayed
+    sources), then three full sweeps with both switched on"""
+    cfg, orc, sc, st = sampler_setup.problem(n_t=5, n_w=4, n_b=5, n_slots=4, n_prop=6, seed=141)
+    sc.adapt_ladder, sc.shift_ownership, sc.adapt_lag, sc.adapt_time = 1, 1, 10.0, 2.0
+    _push_over_edges(cfg, orc, sc, st, 142)
+    st.swap_acc[:] = np.random.default_rng(143).integers(0, sc.n_walkers + 1, st.swap_acc.shape).astype(np.int32)
+    ctx, sw = _gpu_sweep(cfg, sc, st)
+    s0 = 4
+    sw.sweep_counter.fill_(s0)
+    print("ladder adaptation step", flush=True)
+    sw.adapt_ladder()
+    oracle.adapt_ladder(sc, st, s0)
+    torch.cuda.synchronize()
+    assert np.array_equal(sw.swap_acc.cpu().numpy(), st.swap_acc)
+    assert np.allclose(sw.betas.cpu().numpy(), st.betas, rtol=1e-14, atol=0)
+    sw.betas.copy_(torch.from_numpy(st.betas))          # both sides continue from the oracle's ladder
+    print("ownership shift step", flush=True)
+    sw.shift_ownership()
+    oracle.shift_ownership(orc, sc, st, st.stats[8:])
+    _compare(sw, st, "ownership shift")
+    assert st.stats[8] > 0
+    print("three full sweeps with adaptation and shifts", flush=True)
+    _push_over_edges(cfg, orc, sc, st, 144)
+    ctx.close()
+    ctx, sw = _gpu_sweep(cfg, sc, st)
+    sw.sweep_counter.fill_(s0)
+    sw.run(3)
+    for s in range(s0, s0 + 3):
+        oracle.sweep_full(orc, sc, st, s)
+    _compare(sw, st, "full sweeps with adaptation and shifts")
+    assert np.allclose(sw.betas.cpu().numpy(), st.betas, rtol=1e-13, atol=0)
+    assert np.array_equal(sw.swap_acc.cpu().numpy(), st.swap_acc)
+    assert st.stats[8] > 0 and st.stats[7] > 0
     ctx.close()

@@ -366,3 +366,139 @@ def test_posterior_of_an_isolated_loud_source_matches_the_inverse_fisher_matrix(
     # E[(u - u0)^T F (u - u0)] = 8 for the Gaussian limit
     m = np.einsum("ni,ij,nj->n", d, F, d).mean()
     assert abs(m - 8.0) < 1.0, m
+
+
+def test_parallel_sweep_schedule_is_bitwise_the_sequential_one():
+    """The oracle runs the units of a step (band loops, tempering chains) on
+    several threads and adds their cold-chain changes in the sequential
+    order: one thread and eight give bitwise identical states."""
+    lib = oracle._load()
+    before = lib.gblo_set_threads(0)
+    runs = []
+    try:
+        for n in (1, 8):
+            cfg, orc, sc, st = sampler_setup.problem(n_t=4, n_w=6, n_b=5, n_slots=8, n_prop=5, seed=123)
+            lib.gblo_set_threads(n)
+            oracle.sweep_group(sc, st)
+            cl = np.zeros((sc.n_walkers, sc.n_bands))
+            for mv in (0, 1, 2):
+                for par in (1, 0):
+                    oracle.sweep_step(orc, sc, st, mv, par, 3, cold_logl=cl if mv == 2 else None)
+            runs.append((st.u.copy(), st.exists.copy(), st.resid.copy(), st.stats.copy(), cl))
+    finally:
+        lib.gblo_set_threads(before)
+    for a, b in zip(*runs):
+        assert np.array_equal(np.asarray(a).view(np.uint8), np.asarray(b).view(np.uint8))
+    assert runs[0][3][1] > 0 and runs[0][3][3] + runs[0][3][5] > 0 and runs[0][3][7] > 0
+
+
+# --------------------------------------------------------------------------
+# temperature-ladder adaptation and sub-band ownership
+# --------------------------------------------------------------------------
+def _ladder_config(nt, nw, nb, lag=1e9, time_scale=2.0):
+    sc = oracle.SweepConfig()
+    sc.n_temps, sc.n_walkers, sc.n_bands, sc.n_slots = nt, nw, nb, 1
+    sc.adapt_ladder, sc.adapt_lag, sc.adapt_time = 1, lag, time_scale
+    return sc
+
+
+def test_ladder_adaptation_converges_to_the_equal_acceptance_ladder():
+    """Swap acceptance that depends only on the ratio of neighbouring
+    temperatures, A = (T_j / T_(j+1))^c: equal acceptance on every pair
+    (the adaptation's fixed point) is the geometric ladder between the fixed
+    end rungs, T_j = T_max^(j / (n_t - 1)).  Starting from a badly spaced
+    ladder, the adapted ladder reaches it; the end rungs never move and the
+    ladder stays ordered."""
+    nt, nw, nb = 8, 1 << 20, 3
+    sc = _ladder_config(nt, nw, nb)
+    st = oracle.SweepState(sc, 1)
+    T_max = 50.0
+    start = [np.r_[1.0, np.linspace(1.01, 1.3, nt - 2), T_max],           # crowded at the bottom
+             np.r_[1.0, np.linspace(20.0, 45.0, nt - 2), T_max],          # crowded at the top
+             np.r_[1.0, np.geomspace(1.5, 40.0, nt - 2), T_max]]
+    st.betas[:] = 1.0 / np.array(start)
+    c = 1.5
+    for sweep in range(4000):
+        T = 1.0 / st.betas
+        A = (T[:, :-1] / T[:, 1:]) ** c                    # pair (t-1, t) at entry t
+        st.swap_acc[:, 1:] = np.rint(A * nw).astype(np.int32)
+        st.swap_acc[:, 0] = 0
+        oracle.adapt_ladder(sc, st, sweep)
+        assert np.all(st.swap_acc == 0)
+        assert np.all(st.betas[:, 0] == 1.0) and np.all(st.betas[:, -1] == 1.0 / T_max)
+        assert np.all(np.diff(st.betas, axis=1) < 0)
+    target = T_max ** (np.arange(nt) / (nt - 1))
+    assert np.max(np.abs(1.0 / st.betas / target - 1)) < 1e-3
+
+
+def test_ladder_adaptation_leaves_an_equal_acceptance_ladder_and_decays():
+    """equal acceptance on every pair: nothing moves; the step size decays as
+    t0 / (t + t0): after a sweep index far beyond t0 an unequal acceptance
+    barely moves the ladder, while at t = 0 it moves it visibly"""
+    nt, nw = 6, 100
+    sc = _ladder_config(nt, nw, 1, lag=10.0, time_scale=1.0)
+    st = oracle.SweepState(sc, 1)
+    ladder = np.r_[1.0 / np.geomspace(1.0, 30.0, nt - 1), 0.0]   # hottest rung at beta = 0
+    st.betas[0] = ladder
+    st.swap_acc[0, 1:] = 37
+    oracle.adapt_ladder(sc, st, 0)
+    assert np.allclose(st.betas[0], ladder, rtol=1e-14, atol=0)
+    moved = []
+    for sweep in (0, 10 ** 9):
+        st.betas[0] = ladder
+        st.swap_acc[0, 1:] = [90, 10, 10, 10, 10]
+        oracle.adapt_ladder(sc, st, sweep)
+        moved.append(np.max(np.abs(st.betas[0, :-1] / ladder[:-1] - 1)))
+        assert st.betas[0, -1] == 0.0
+    assert moved[0] > 0.3 and moved[1] < 1e-7
+
+
+def test_ownership_shift_moves_cold_sources_and_keeps_the_buffers():
+    """cold-chain sources pushed past their band edge move to the
+    neighbouring band's lowest free slot; the multiset of cold sources is
+    unchanged, hot chains are untouched, moved sources sit in their new
+    band's nominal range, and both parity buffers equal a rebuild from the
+    data minus every cold source of that parity"""
+    cfg, orc, sc, st = sampler_setup.problem(n_t=2, n_w=3, n_b=5, n_slots=4, seed=131)
+    T, N, kb = cfg.T, sc.N, sc.k_band0
+    rng = np.random.default_rng(132)
+    # move some cold sources across an edge: up to 0.45 band into the neighbour
+    pushed = []
+    for w in range(sc.n_walkers):
+        for b in range(sc.n_bands):
+            for s in range(2):
+                if rng.uniform() < 0.5:
+                    side = rng.choice([-1, 1])
+                    f = (kb + (b + (1.0 + rng.uniform(0.02, 0.45) if side > 0 else -rng.uniform(0.02, 0.45))) * N) / T
+                    st.u[0, w, b, s, 1] = f
+                    pushed.append((w, b, s, side))
+    # fill the top band's slots of walker 0 so that a push into it finds no room
+    st.exists[0, 0, 4, :] = 1
+    st.u[0, 0, 4, 2:] = st.u[0, 0, 4, 0]
+    st.u[0, 0, 4, 2:, 1] = (kb + 4.5 * N) / T
+    for par in (0, 1):
+        for w in range(sc.n_walkers):
+            st.resid[par, w] = sampler_setup.rebuild_buffer(orc, sc, st, par, w)
+    before = {w: sorted(map(tuple, st.u[0, w][st.exists[0, w].astype(bool)])) for w in range(sc.n_walkers)}
+    hot_u, hot_e = st.u[1].copy(), st.exists[1].copy()
+    stats = np.zeros(2, np.int64)
+    oracle.shift_ownership(orc, sc, st, stats)
+    assert stats[0] > 0
+    for w in range(sc.n_walkers):
+        after = sorted(map(tuple, st.u[0, w][st.exists[0, w].astype(bool)]))
+        assert after == before[w]
+        for b in range(sc.n_bands):
+            for s in range(sc.n_slots):
+                if not st.exists[0, w, b, s]:
+                    continue
+                kk = st.u[0, w, b, s, 1] * T - kb
+                inside = b * N <= kk < (b + 1) * N
+                edge = (kk < 0 and b == 0) or (kk >= sc.n_bands * N and b == sc.n_bands - 1)
+                full = not np.any(st.exists[0, w, b + (1 if kk >= (b + 1) * N else -1)] == 0) if not (inside or edge) else False
+                assert inside or edge or full, (w, b, s, kk / N)
+    assert np.array_equal(st.u[1], hot_u) and np.array_equal(st.exists[1], hot_e)
+    for par in (0, 1):
+        for w in range(sc.n_walkers):
+            ref = sampler_setup.rebuild_buffer(orc, sc, st, par, w)
+            assert np.max(np.abs(st.resid[par, w] - ref)) <= 1e-12 * np.abs(ref).max()
+    assert stats[1] >= 1   # the push into walker 0's full top band stayed
