@@ -51,6 +51,14 @@ class SweepConfig(ctypes.Structure):
                 ("adapt_lag", ctypes.c_double), ("adapt_time", ctypes.c_double)]
 
 
+class SearchConfig(ctypes.Structure):
+    """Per-sub-band search configuration (field order of gblo_search_config)."""
+    _fields_ = [("n_bands", ctypes.c_int32), ("n_temps", ctypes.c_int32), ("n_walkers", ctypes.c_int32),
+                ("N", ctypes.c_int32), ("width", ctypes.c_int32), ("n_stall", ctypes.c_int32),
+                ("k_band0", ctypes.c_int64), ("stretch_a", ctypes.c_double), ("seed", ctypes.c_uint64),
+                ("prior_lo", ctypes.c_double * 8), ("prior_hi", ctypes.c_double * 8)]
+
+
 MOVE_INMODEL, MOVE_RJ, MOVE_PT = 0, 1, 2
 MOVE_PSD, MOVE_PSDPT = 4, 5
 
@@ -112,6 +120,11 @@ def _load():
             "gblo_sweep_adapt_ladder": (ctypes.c_int, [ctypes.POINTER(SweepConfig), ctypes.c_int64, D, I32]),
             "gblo_sweep_shift_ownership": (ctypes.c_int, [C, ctypes.POINTER(SweepConfig), D, I32, D, I64]),
             "gblo_sweep_group": (ctypes.c_int, [ctypes.POINTER(SweepConfig), D, I32, D, I32]),
+            "gblo_search_eval": (ctypes.c_int, [C, ctypes.POINTER(SearchConfig), D, D, D, D]),
+            "gblo_search_step": (ctypes.c_int, [C, ctypes.POINTER(SearchConfig), ctypes.c_int64, D, D, D, D, D,
+                                                D, D, I32, I64]),
+            "gblo_search_ball": (ctypes.c_int, [C, ctypes.POINTER(SearchConfig), ctypes.c_int64, D, D, D, D, D,
+                                                D, I32]),
             "gblo_stretch_propose": (ctypes.c_int, [ctypes.POINTER(SweepConfig), D, D, ctypes.c_int, ctypes.c_double,
                                                     ctypes.c_double, D, D]),
             "gblo_in_prior": (ctypes.c_int, [C, ctypes.POINTER(SweepConfig), ctypes.c_int, D]),
@@ -473,3 +486,44 @@ def psd_sweep_step(orc: "Oracle", pc: PsdSweepConfig, sweep: int, theta, logl, b
                                      _d(betas), _d(data.view(np.float64)), _d(resid.view(np.float64)), _d(inv_psd),
                                      _i64(stats))
     _check(rc, "psd_sweep_step")
+
+
+class SearchState:
+    """Host arrays of the per-sub-band search (layouts of gblo_search_step)."""
+
+    def __init__(self, sc: SearchConfig):
+        nb, nt, nw = sc.n_bands, sc.n_temps, sc.n_walkers
+        self.u = np.zeros((nb, nt, nw, 8))
+        self.logl = np.zeros((nb, nt, nw))
+        self.betas = np.ones(nt)
+        self.best_u = np.zeros((nb, 8))
+        self.best_logl = np.full(nb, -np.inf)
+        self.stall = np.zeros(nb, np.int32)
+        self.stats = np.zeros(4, np.int64)
+
+
+def search_eval(orc: "Oracle", sc: SearchConfig, st: SearchState, residual, psd):
+    """logl of every chain at its current point (residual [2][n_bins], psd [2][n_bins] = S_n)"""
+    residual = np.ascontiguousarray(residual, np.complex128).reshape(2, orc.n_bins)
+    psd = _f64(psd).reshape(2, orc.n_bins)
+    _check(orc.lib.gblo_search_eval(ctypes.byref(orc.cfg), ctypes.byref(sc), _d(residual.view(np.float64)), _d(psd),
+                                    _d(st.u), _d(st.logl)), "search_eval")
+
+
+def search_step(orc: "Oracle", sc: SearchConfig, st: SearchState, it: int, residual, psd):
+    residual = np.ascontiguousarray(residual, np.complex128).reshape(2, orc.n_bins)
+    psd = _f64(psd).reshape(2, orc.n_bins)
+    rc = orc.lib.gblo_search_step(ctypes.byref(orc.cfg), ctypes.byref(sc), int(it), _d(residual.view(np.float64)),
+                                  _d(psd), _d(st.u), _d(st.logl), _d(st.betas), _d(st.best_u), _d(st.best_logl),
+                                  _i32(st.stall), _i64(st.stats))
+    _check(rc, "search_step")
+
+
+def search_ball(orc: "Oracle", sc: SearchConfig, st: SearchState, it: int, sigma, residual, psd):
+    residual = np.ascontiguousarray(residual, np.complex128).reshape(2, orc.n_bins)
+    psd = _f64(psd).reshape(2, orc.n_bins)
+    sigma = _f64(sigma)
+    rc = orc.lib.gblo_search_ball(ctypes.byref(orc.cfg), ctypes.byref(sc), int(it), _d(sigma),
+                                  _d(residual.view(np.float64)), _d(psd), _d(st.u), _d(st.logl), _d(st.best_u),
+                                  _i32(st.stall))
+    _check(rc, "search_ball")

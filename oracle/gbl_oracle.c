@@ -1541,3 +1541,251 @@ int gblo_psd_sweep_step(const gblo_config* cfg, const gblo_psd_sweep_config* pc,
   free(lz);
   return 0;
 }
+
+/* ------------------------------------------------------------------------
+ * Search for the loudest remaining source per sub-band (appendix
+ * "Algorithm for fitting proposal distributions"; Sec. 4 "Online updating of
+ * RJ sampling distributions", the search RJ proposal): independent,
+ * fixed-dimensional (one source, d = 8), parallel-tempered ensemble samplers,
+ * one per sub-band, with the stretch proposal of eq. stretch; the prior
+ * confines f0 to the sub-band (no roaming across its edges); the target is
+ * the likelihood gain of adding the source to the residual,
+ *   l(u) = <R|h(u)> - 1/2 <h(u)|h(u)>   (eq. addsource),
+ * tempered as beta_t l.  A sub-band has converged when its best cold-chain
+ * l has not improved for n_stall consecutive iterations; converged bands
+ * stop moving.
+ *   u [n_b][n_t][n_w][8] sampling coordinates (log10 A, f0, fdot, phi0,
+ *   cos iota, psi, lambda, sin beta), logl [n_b][n_t][n_w], betas [n_t],
+ *   best_u [n_b][8], best_logl [n_b], stall [n_b].
+ * One iteration: for half h = 0, 1 every chain (b, t, w) with w % 2 == h
+ * proposes Y = X_j + z (X_w - X_j), j = 2 floor(U0 n_w/2) + 1 - h of the same
+ * (b, t), z = ((a-1) U1 + 1)^2 / a (periodic coordinates on the circle, with
+ * the group stretch's reversibility rule), accepted iff ln U2 < beta_t (l' - l)
+ * + 7 ln z inside the prior box; then per (b, w) swaps from the hottest pair
+ * down with eq. temp-orig; then the best-point bookkeeping (first maximum
+ * over the cold walkers).  Random numbers: stretch unit (b n_t + t) n_w + w,
+ * move 6, draws 4 (iteration-local) h + k; swaps unit b n_w + w, move 7,
+ * draw t.  stats: [0] proposed, [1] accepted, [2] swaps proposed, [3]
+ * accepted.
+ * ------------------------------------------------------------------------ */
+#define MOVE_SEARCH 6
+#define MOVE_SEARCH_PT 7
+
+typedef struct {
+  int32_t n_bands, n_temps, n_walkers; /* n_walkers even */
+  int32_t N;                           /* template width */
+  int32_t width;                       /* sub-band width in bins */
+  int32_t n_stall;                     /* convergence: iterations without improvement */
+  int64_t k_band0;                     /* first bin of sub-band 0 */
+  double stretch_a;
+  uint64_t seed;
+  double prior_lo[8], prior_hi[8];     /* f0 and the periodic coordinates are set per band / by period */
+} gblo_search_config;
+
+static const double SEARCH_PERIOD[8] = {0, 0, 0, 2.0 * ORC_PI, 0, ORC_PI, 2.0 * ORC_PI, 0};
+
+static void search_box(const gblo_config* cfg, const gblo_search_config* sc, int b, double* lo, double* hi) {
+  for (int k = 0; k < 8; k++) {
+    lo[k] = sc->prior_lo[k];
+    hi[k] = sc->prior_hi[k];
+    if (SEARCH_PERIOD[k] > 0) {
+      lo[k] = 0.0;
+      hi[k] = SEARCH_PERIOD[k];
+    }
+  }
+  lo[1] = (double)(sc->k_band0 + (int64_t)b * sc->width) / cfg->T;
+  hi[1] = (double)(sc->k_band0 + (int64_t)(b + 1) * sc->width) / cfg->T;
+}
+
+static int search_in_prior(const gblo_config* cfg, const gblo_search_config* sc, int b, const double* u) {
+  double lo[8], hi[8];
+  search_box(cfg, sc, b, lo, hi);
+  if (!(u[1] >= lo[1] && u[1] < hi[1])) return 0;
+  for (int k = 0; k < 8; k++) {
+    if (k == 1 || SEARCH_PERIOD[k] > 0) continue;
+    if (!(u[k] >= lo[k] && u[k] <= hi[k])) return 0;
+  }
+  return 1;
+}
+
+/* l(u) for a list of sampling points: the birth likelihood change */
+static void search_logl(const gblo_config* cfg, const gblo_search_config* sc, const double* residual,
+                        const double* psd, int64_t n, const double* u, double* out) {
+  double* pn = (double*)malloc(sizeof(double) * 8 * (size_t)(n > 0 ? n : 1));
+  double* po = (double*)calloc(8 * (size_t)(n > 0 ? n : 1), sizeof(double));
+  int32_t* idx = (int32_t*)calloc((size_t)(n > 0 ? n : 1), sizeof(int32_t));
+  for (int64_t i = 0; i < n; i++) {
+    u_to_params(u + 8 * i, pn + 8 * i);
+    for (int k = 1; k < 8; k++) po[8 * i + k] = pn[8 * i + k]; /* zero amplitude: a birth */
+  }
+  gblo_delta_loglike(cfg, residual, 1, psd, 1, 0, po, pn, sc->N, idx, idx, n, out, NULL);
+  free(pn);
+  free(po);
+  free(idx);
+}
+
+/* logl of every chain at its current point */
+int gblo_search_eval(const gblo_config* cfg, const gblo_search_config* sc, const double* residual,
+                     const double* psd, const double* u, double* logl) {
+  search_logl(cfg, sc, residual, psd, (int64_t)sc->n_bands * sc->n_temps * sc->n_walkers, u, logl);
+  return 0;
+}
+
+int gblo_search_step(const gblo_config* cfg, const gblo_search_config* sc, int64_t iter, const double* residual,
+                     const double* psd, double* u, double* logl, const double* betas, double* best_u,
+                     double* best_logl, int32_t* stall, int64_t* stats) {
+  const int nb = sc->n_bands, nt = sc->n_temps, nw = sc->n_walkers, half = nw / 2;
+  if (nw < 2 || nw % 2) return -1;
+  const int64_t n_half = (int64_t)nb * nt * half;
+  double* prop = (double*)malloc(sizeof(double) * 8 * (size_t)n_half);
+  double* lprop = (double*)malloc(sizeof(double) * (size_t)n_half);
+  double* lz = (double*)malloc(sizeof(double) * (size_t)n_half);
+  int* ok = (int*)malloc(sizeof(int) * (size_t)n_half);
+  const double a = sc->stretch_a;
+  for (int h = 0; h < 2; h++) {
+    for (int b = 0; b < nb; b++)
+      for (int t = 0; t < nt; t++)
+        for (int i = 0; i < half; i++) {
+          const int w = 2 * i + h;
+          const int64_t s = ((int64_t)b * nt + t) * half + i;
+          ok[s] = 0;
+          if (stall[b] >= sc->n_stall) continue; /* converged band */
+          const uint64_t unit = ((uint64_t)b * nt + t) * nw + w;
+          const double r_pick = rng_uniform(sc->seed, iter, MOVE_SEARCH, unit, 4 * (uint64_t)h + 0);
+          const double r_z = rng_uniform(sc->seed, iter, MOVE_SEARCH, unit, 4 * (uint64_t)h + 1);
+          const int j = 2 * (int)floor(r_pick * half) + (1 - h);
+          const double z = ((a - 1.0) * r_z + 1.0) * ((a - 1.0) * r_z + 1.0) / a;
+          const double* X = u + 8 * (((int64_t)b * nt + t) * nw + j);
+          const double* Y = u + 8 * (((int64_t)b * nt + t) * nw + w);
+          double* P = prop + 8 * s;
+          int rev = 1;
+          for (int k = 0; k < 8; k++) {
+            double diff = Y[k] - X[k];
+            if (SEARCH_PERIOD[k] > 0) {
+              diff = wrap(diff + 0.5 * SEARCH_PERIOD[k], SEARCH_PERIOD[k]) - 0.5 * SEARCH_PERIOD[k];
+              if (!(fabs(z * diff) < 0.5 * SEARCH_PERIOD[k])) rev = 0;
+              P[k] = wrap(X[k] + z * diff, SEARCH_PERIOD[k]);
+            } else {
+              P[k] = X[k] + z * diff;
+            }
+          }
+          ok[s] = rev && search_in_prior(cfg, sc, b, P);
+          lz[s] = 7.0 * log(z);
+        }
+    /* likelihood of the proposals inside the prior */
+    int64_t n_ok = 0;
+    for (int64_t s = 0; s < n_half; s++) n_ok += ok[s];
+    double* pu = (double*)malloc(sizeof(double) * 8 * (size_t)(n_ok > 0 ? n_ok : 1));
+    double* pl = (double*)malloc(sizeof(double) * (size_t)(n_ok > 0 ? n_ok : 1));
+    for (int64_t s = 0, c = 0; s < n_half; s++)
+      if (ok[s]) {
+        for (int k = 0; k < 8; k++) pu[8 * c + k] = prop[8 * s + k];
+        c++;
+      }
+    search_logl(cfg, sc, residual, psd, n_ok, pu, pl);
+    for (int64_t s = 0, c = 0; s < n_half; s++)
+      if (ok[s]) lprop[s] = pl[c++];
+    free(pu);
+    free(pl);
+    for (int b = 0; b < nb; b++)
+      for (int t = 0; t < nt; t++)
+        for (int i = 0; i < half; i++) {
+          const int w = 2 * i + h;
+          const int64_t s = ((int64_t)b * nt + t) * half + i;
+          if (stall[b] >= sc->n_stall) continue;
+          stats[0]++;
+          if (!ok[s]) continue;
+          const int64_t c = ((int64_t)b * nt + t) * nw + w;
+          const uint64_t unit = ((uint64_t)b * nt + t) * nw + w;
+          const double r_acc = rng_uniform(sc->seed, iter, MOVE_SEARCH, unit, 4 * (uint64_t)h + 2);
+          if (log(r_acc) < betas[t] * (lprop[s] - logl[c]) + lz[s]) {
+            for (int k = 0; k < 8; k++) u[8 * c + k] = prop[8 * s + k];
+            logl[c] = lprop[s];
+            stats[1]++;
+          }
+        }
+  }
+  /* temperature swaps per (band, walker), hottest pair first (eq. temp-orig) */
+  for (int b = 0; b < nb; b++) {
+    if (stall[b] >= sc->n_stall) continue;
+    for (int w = 0; w < nw; w++)
+      for (int t = nt - 1; t >= 1; t--) {
+        stats[2]++;
+        const double r = rng_uniform(sc->seed, iter, MOVE_SEARCH_PT, (uint64_t)b * nw + w, (uint64_t)t);
+        const int64_t c1 = ((int64_t)b * nt + t) * nw + w, c0 = ((int64_t)b * nt + t - 1) * nw + w;
+        if (log(r) < (betas[t - 1] - betas[t]) * (logl[c1] - logl[c0])) {
+          for (int k = 0; k < 8; k++) {
+            const double tmp = u[8 * c1 + k];
+            u[8 * c1 + k] = u[8 * c0 + k];
+            u[8 * c0 + k] = tmp;
+          }
+          const double tl = logl[c1];
+          logl[c1] = logl[c0];
+          logl[c0] = tl;
+          stats[3]++;
+        }
+      }
+  }
+  /* best cold-chain point per band */
+  for (int b = 0; b < nb; b++) {
+    if (stall[b] >= sc->n_stall) continue;
+    int wb = 0;
+    for (int w = 1; w < nw; w++)
+      if (logl[(int64_t)b * nt * nw + w] > logl[(int64_t)b * nt * nw + wb]) wb = w;
+    const double m = logl[(int64_t)b * nt * nw + wb];
+    if (m > best_logl[b]) {
+      best_logl[b] = m;
+      for (int k = 0; k < 8; k++) best_u[8 * b + k] = u[8 * ((int64_t)b * nt * nw + wb) + k];
+      stall[b] = 0;
+    } else {
+      stall[b]++;
+    }
+  }
+  free(prop);
+  free(lprop);
+  free(lz);
+  free(ok);
+  return 0;
+}
+
+/* Restart around the best points: every chain of band b moves to
+ * best_u[b] + sigma * n (n standard normals by Box-Muller from the uniforms
+ * of unit (b n_t + t) n_w + w, move 8, draws 0..7; coordinate k gets
+ * sigma[k]; periodic coordinates wrapped, the others clamped into the box),
+ * its logl is re-evaluated and the band's stall counter cleared (the best
+ * point stays). */
+#define MOVE_SEARCH_BALL 8
+int gblo_search_ball(const gblo_config* cfg, const gblo_search_config* sc, int64_t iter, const double* sigma,
+                     const double* residual, const double* psd, double* u, double* logl, const double* best_u,
+                     int32_t* stall) {
+  const int nb = sc->n_bands, nt = sc->n_temps, nw = sc->n_walkers;
+  for (int b = 0; b < nb; b++) {
+    double lo[8], hi[8];
+    search_box(cfg, sc, b, lo, hi);
+    for (int t = 0; t < nt; t++)
+      for (int w = 0; w < nw; w++) {
+        const uint64_t unit = ((uint64_t)b * nt + t) * nw + w;
+        double* x = u + 8 * (((int64_t)b * nt + t) * nw + w);
+        for (int p = 0; p < 4; p++) {
+          const double u1 = rng_uniform(sc->seed, iter, MOVE_SEARCH_BALL, unit, 2 * (uint64_t)p);
+          const double u2 = rng_uniform(sc->seed, iter, MOVE_SEARCH_BALL, unit, 2 * (uint64_t)p + 1);
+          const double r = sqrt(-2.0 * log(u1));
+          const double n0 = r * cos(2.0 * ORC_PI * u2), n1 = r * sin(2.0 * ORC_PI * u2);
+          for (int q = 0; q < 2; q++) {
+            const int k = 2 * p + q;
+            double v = best_u[8 * b + k] + sigma[k] * (q ? n1 : n0);
+            if (SEARCH_PERIOD[k] > 0) {
+              v = wrap(v, SEARCH_PERIOD[k]);
+            } else {
+              /* f0 stays strictly inside [lo, hi) */
+              const double top = k == 1 ? nextafter(hi[k], lo[k]) : hi[k];
+              v = v < lo[k] ? lo[k] : (v > top ? top : v);
+            }
+            x[k] = v;
+          }
+        }
+      }
+    stall[b] = 0;
+  }
+  return gblo_search_eval(cfg, sc, residual, psd, u, logl);
+}
