@@ -574,6 +574,73 @@ int gb_sweep_graph_create_flow(gbl_ctx* ctx, const gbl_sweep_config* cfg, const 
                                const gbl_flow_config* fcfg, const gbl_flow* flow, int32_t n_sweeps,
                                gbl_graph** graph);
 
+/* ---------------------------------------------------------------------------
+ * Search for the loudest remaining source in every sub-band (appendix
+ * "Algorithm for fitting proposal distributions"; the search RJ proposal of
+ * Sec. 4 "Online updating of RJ sampling distributions").  Independent,
+ * fixed-dimensional (one source, d = 8), parallel-tempered ensembles, one per
+ * sub-band b = [k_band0 + b width, k_band0 + (b+1) width) (f0 confined to it),
+ * with the stretch move of eq. stretch and the target
+ *   l(u) = <R|h(u)> - 1/2 <h(u)|h(u)>   (eq. addsource; births of the batched
+ * likelihood kernels), tempered as beta_t l.  One gb_search_step:
+ *   for half h = 0, 1: every chain (b, t, w), w % 2 == h, of a band still
+ *     running proposes Y = X_j + z (X_w - X_j), j = 2 floor(U0 n_w/2) + 1 - h
+ *     of the same (b, t), z = ((a-1) U1 + 1)^2 / a (periodic phi0, psi,
+ *     lambda on their circles; a stretched periodic difference of half a
+ *     period or more is rejected), accepted iff ln U2 < beta_t (l' - l) +
+ *     7 ln z inside the band's prior box;
+ *   swaps per (b, w) from the hottest pair down (eq. temp-orig);
+ *   the best cold-chain point: best_logl[b], best_u[b] take the first maximum
+ *     over the cold walkers when it improves, else stall[b] += 1; a band whose
+ *     stall reaches n_stall has converged and no longer moves.
+ * Random numbers: stretch unit (b n_t + t) n_w + w, move 6, draws 4 h + k;
+ * swaps unit b n_w + w, move 7, draw t; the restart ball move 8.  The
+ * iteration index `iter` is the Philox stream's first counter word.
+ * --------------------------------------------------------------------------- */
+typedef struct {
+  int32_t n_bands, n_temps, n_walkers; /* n_walkers even */
+  int32_t N;                           /* template width */
+  int32_t width;                       /* sub-band width in bins */
+  int32_t n_stall;                     /* converged after this many iterations without improvement */
+  int64_t k_band0;                     /* first bin of sub-band 0 */
+  double stretch_a;
+  uint64_t seed;
+  double prior_lo[8], prior_hi[8];     /* box of log10 A, fdot, cos iota, sin beta (entries 0, 2, 4, 7) */
+} gbl_search_config;
+
+typedef struct {
+  double* u;            /* [n_b][n_t][n_w][8] sampling coordinates */
+  double* logl;         /* [n_b][n_t][n_w] */
+  const double* betas;  /* [n_t], betas[0] = 1 */
+  double* best_u;       /* [n_b][8] */
+  double* best_logl;    /* [n_b], start at -inf */
+  int32_t* stall;       /* [n_b], start at 0 */
+  int64_t* stats;       /* [4]: proposed, accepted, swaps proposed, accepted */
+  void* workspace;      /* gb_search_workspace bytes */
+} gbl_search_state;
+
+/* Bytes of the search workspace (host call). */
+int gb_search_workspace(const gbl_search_config* cfg, int64_t* bytes);
+
+/* logl of every chain at its current point.  residual [2][n_bins] complex
+ * (one series), psd [2][n_bins] S_n. */
+int gb_search_eval(gbl_ctx* ctx, const gbl_search_config* cfg, const gbl_search_state* st, const double* residual,
+                   const double* psd);
+
+/* One iteration (see above).  Errors: GBL_EINVAL, GBL_EUNSUPPORTED (N, or a
+ * mixed-precision context). */
+int gb_search_step(gbl_ctx* ctx, const gbl_search_config* cfg, const gbl_search_state* st, int64_t iter,
+                   const double* residual, const double* psd);
+
+/* Restart ball: every chain of band b moves to best_u[b] + sigma n (n
+ * standard normals by Box-Muller from the uniforms of unit (b n_t + t) n_w +
+ * w, move 8, draws 2p and 2p+1 for coordinates 2p, 2p+1), periodic
+ * coordinates wrapped, the others clamped into the box (f0 strictly below the
+ * band's top); logl re-evaluated, stall cleared, the best points kept.
+ * sigma: HOST array [8]. */
+int gb_search_ball(gbl_ctx* ctx, const gbl_search_config* cfg, const gbl_search_state* st, int64_t iter,
+                   const double* sigma, const double* residual, const double* psd);
+
 #ifdef __cplusplus
 }
 #endif

@@ -14,6 +14,7 @@
 #include "gbl_kernels.hpp"
 #include "gbl_sampler.hpp"
 #include "gbl_flow.hpp"
+#include "gbl_search.hpp"
 
 using gbl::cd;
 
@@ -1322,4 +1323,115 @@ extern "C" int gb_graph_end(gbl_ctx* ctx, gbl_graph** out) {
   }
   *out = gr;
   return GBL_OK;
+}
+
+// ---------------------------------------------------------------------------
+// per-sub-band source search (appendix on fitting proposal distributions)
+// ---------------------------------------------------------------------------
+static int64_t search_chains(const gbl_search_config* c) {
+  return (int64_t)c->n_bands * c->n_temps * c->n_walkers;
+}
+
+extern "C" int gb_search_workspace(const gbl_search_config* c, int64_t* bytes) {
+  if (!c || !bytes) return GBL_EINVAL;
+  *bytes = search_chains(c) * (26 * (int64_t)sizeof(double) + 2 * (int64_t)sizeof(int32_t));
+  return GBL_OK;
+}
+
+static int search_check(gbl_ctx* ctx, const gbl_search_config* c, const gbl_search_state* st, const double* residual,
+                        const double* psd) {
+  if (!c || !st) return fail(ctx, GBL_EINVAL, "search: null config or state%s");
+  if (c->n_bands < 1 || c->n_temps < 1 || c->n_walkers < 2 || c->n_walkers % 2 || c->width < 1 ||
+      c->n_stall < 1 || !(c->stretch_a > 1.0))
+    return fail(ctx, GBL_EINVAL, "search: configuration out of range%s");
+  if (width_slot(c->N) < 0) return fail(ctx, GBL_EUNSUPPORTED, "search: unsupported N%s");
+  if (!st->u || !st->logl || !st->betas || !st->best_u || !st->best_logl || !st->stall || !st->stats ||
+      !st->workspace || !residual || !psd)
+    return fail(ctx, GBL_EINVAL, "search: null pointer%s");
+  if (ctx->cfg.precision != GBL_FP64) return fail(ctx, GBL_EUNSUPPORTED, "search: FP64 contexts only%s");
+  return GBL_OK;
+}
+
+static gbl::SearchArgs search_args(const gbl_search_config* c, const gbl_search_state* st) {
+  gbl::SearchArgs a;
+  a.n_b = c->n_bands;
+  a.n_t = c->n_temps;
+  a.n_w = c->n_walkers;
+  a.width = c->width;
+  a.n_stall = c->n_stall;
+  a.k_band0 = c->k_band0;
+  a.stretch_a = c->stretch_a;
+  a.seed = c->seed;
+  for (int k = 0; k < 8; k++) {
+    a.lo[k] = c->prior_lo[k];
+    a.hi[k] = c->prior_hi[k];
+  }
+  a.u = st->u;
+  a.logl = st->logl;
+  a.betas = st->betas;
+  a.best_u = st->best_u;
+  a.best_logl = st->best_logl;
+  a.stall = st->stall;
+  a.stats = (unsigned long long*)st->stats;
+  const int64_t n = search_chains(c);
+  double* w = (double*)st->workspace;
+  a.wu = w;
+  a.wpn = w + 8 * n;
+  a.wpo = w + 16 * n;
+  a.wl = w + 24 * n;
+  a.wlz = w + 25 * n;
+  a.wok = (int32_t*)(w + 26 * n);
+  a.widx = a.wok + n;
+  return a;
+}
+
+static unsigned grid_of(int64_t n, int block) { return (unsigned)((n + block - 1) / block); }
+
+extern "C" int gb_search_eval(gbl_ctx* ctx, const gbl_search_config* cfg, const gbl_search_state* st,
+                              const double* residual, const double* psd) {
+  if (!ctx) return GBL_EINVAL;
+  int rc = search_check(ctx, cfg, st, residual, psd);
+  if (rc) return rc;
+  const gbl::SearchArgs a = search_args(cfg, st);
+  const int64_t n = search_chains(cfg);
+  hipLaunchKernelGGL(gbl::k_search_params, dim3(grid_of(n, 256)), dim3(256), 0, ctx->stream, a);
+  rc = gb_delta_loglike(ctx, residual, 1, psd, 1, 0, a.wpo, a.wpn, cfg->N, a.widx, a.widx, n, st->logl);
+  if (rc) return rc;
+  return check_launch(ctx, "gb_search_eval");
+}
+
+extern "C" int gb_search_step(gbl_ctx* ctx, const gbl_search_config* cfg, const gbl_search_state* st, int64_t iter,
+                              const double* residual, const double* psd) {
+  if (!ctx) return GBL_EINVAL;
+  int rc = search_check(ctx, cfg, st, residual, psd);
+  if (rc) return rc;
+  const gbl::SearchArgs a = search_args(cfg, st);
+  const int64_t n_half = (int64_t)cfg->n_bands * cfg->n_temps * (cfg->n_walkers / 2);
+  for (int h = 0; h < 2; h++) {
+    hipLaunchKernelGGL(gbl::k_search_propose, dim3(grid_of(n_half, 256)), dim3(256), 0, ctx->stream, ctx->geo, a,
+                       iter, h);
+    rc = gb_delta_loglike(ctx, residual, 1, psd, 1, 0, a.wpo, a.wpn, cfg->N, a.widx, a.widx, n_half, a.wl);
+    if (rc) return rc;
+    hipLaunchKernelGGL(gbl::k_search_accept, dim3(grid_of(n_half, 256)), dim3(256), 0, ctx->stream, a, iter, h);
+  }
+  hipLaunchKernelGGL(gbl::k_search_swap, dim3(grid_of((int64_t)cfg->n_bands * cfg->n_walkers, 256)), dim3(256), 0,
+                     ctx->stream, a, iter);
+  hipLaunchKernelGGL(gbl::k_search_best, dim3(grid_of(cfg->n_bands, 64)), dim3(64), 0, ctx->stream, a);
+  return check_launch(ctx, "gb_search_step");
+}
+
+extern "C" int gb_search_ball(gbl_ctx* ctx, const gbl_search_config* cfg, const gbl_search_state* st, int64_t iter,
+                              const double* sigma, const double* residual, const double* psd) {
+  if (!ctx) return GBL_EINVAL;
+  int rc = search_check(ctx, cfg, st, residual, psd);
+  if (rc) return rc;
+  if (!sigma) return fail(ctx, GBL_EINVAL, "gb_search_ball: null sigma%s");
+  gbl::Sigma8 sg;
+  for (int k = 0; k < 8; k++) sg.v[k] = sigma[k];
+  const gbl::SearchArgs a = search_args(cfg, st);
+  const int64_t n = search_chains(cfg);
+  hipLaunchKernelGGL(gbl::k_search_ball, dim3(grid_of(n, 256)), dim3(256), 0, ctx->stream, ctx->geo, a, iter, sg);
+  rc = gb_delta_loglike(ctx, residual, 1, psd, 1, 0, a.wpo, a.wpn, cfg->N, a.widx, a.widx, n, st->logl);
+  if (rc) return rc;
+  return check_launch(ctx, "gb_search_ball");
 }

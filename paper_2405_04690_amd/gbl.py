@@ -34,7 +34,8 @@ EXPORTED = ("gbl_create", "gbl_destroy", "gbl_set_stream", "gbl_last_error", "gb
             "gb_flow_train_step", "gb_sweep_rj_prepare", "gb_sweep_run_flow", "gb_sweep_graph_create_flow",
             "gbl_get_tuning", "gbl_set_tuning", "gb_psd_sweep_step", "gb_graph_begin", "gb_graph_end",
             "gb_psd_eval_n", "gb_psd_loglike_n", "gb_inner", "gb_snr", "gb_sweep_adapt_ladder",
-            "gb_sweep_shift_ownership", "gb_overlap")
+            "gb_sweep_shift_ownership", "gb_overlap", "gb_search_workspace", "gb_search_eval",
+            "gb_search_step", "gb_search_ball")
 
 GBL_MOVE_INMODEL, GBL_MOVE_RJ, GBL_MOVE_PT = 0, 1, 2
 
@@ -92,6 +93,20 @@ class PsdSweepState(ctypes.Structure):
                                               "work", "res_idx", "stats", "sweep_counter")]
 
 
+class SearchConfig(ctypes.Structure):
+    """gbl_search_config"""
+    _fields_ = [("n_bands", ctypes.c_int32), ("n_temps", ctypes.c_int32), ("n_walkers", ctypes.c_int32),
+                ("N", ctypes.c_int32), ("width", ctypes.c_int32), ("n_stall", ctypes.c_int32),
+                ("k_band0", ctypes.c_int64), ("stretch_a", ctypes.c_double), ("seed", ctypes.c_uint64),
+                ("prior_lo", ctypes.c_double * 8), ("prior_hi", ctypes.c_double * 8)]
+
+
+class SearchState(ctypes.Structure):
+    """gbl_search_state (device pointers)"""
+    _fields_ = [(n, ctypes.c_void_p) for n in ("u", "logl", "betas", "best_u", "best_logl", "stall", "stats",
+                                              "workspace")]
+
+
 class FlowConfig(ctypes.Structure):
     """gbl_flow_config"""
     _fields_ = [("n_emb", ctypes.c_int32), ("width", ctypes.c_int32), ("k_band0", ctypes.c_int64),
@@ -131,6 +146,11 @@ def load_library(path: str = LIB_PATH):
         "gb_inner": [vp, vp, vp, vp, i32, vp, i32, vp, i32, i32, vp, vp, i64, vp],
         "gb_snr": [vp, vp, i64, i32, vp, i32, i32, vp, vp, i32, vp, vp, vp],
         "gb_overlap": [vp, vp, vp, i32, vp, i32, i32, vp, i64, vp],
+        "gb_search_workspace": [ctypes.POINTER(SearchConfig), ctypes.POINTER(i64)],
+        "gb_search_eval": [vp, ctypes.POINTER(SearchConfig), ctypes.POINTER(SearchState), vp, vp],
+        "gb_search_step": [vp, ctypes.POINTER(SearchConfig), ctypes.POINTER(SearchState), i64, vp, vp],
+        "gb_search_ball": [vp, ctypes.POINTER(SearchConfig), ctypes.POINTER(SearchState), i64,
+                           ctypes.POINTER(dbl), vp, vp],
         "gb_scatter_add": [vp, vp, i64, i32, dbl, vp, i32, vp],
         "gb_make_noise": [vp, vp, vp, i64, vp],
         "gb_sweep_step": [vp, ctypes.POINTER(SweepConfig), ctypes.POINTER(SweepState), i32, i32],
