@@ -105,6 +105,11 @@ def _load():
             "gblo_overlap": (ctypes.c_int, [C, D, D, ctypes.c_int64, ctypes.c_int32, D, ctypes.c_int32,
                                             ctypes.c_int32, I32, D]),
             "gblo_loglike": (ctypes.c_double, [C, D, D]),
+            "gblo_noise_matrix_value": (None, [C, ctypes.c_double, D, D]),
+            "gblo_noise_matrix": (ctypes.c_int, [C, D, ctypes.c_int64, D]),
+            "gblo_loglike_matrix": (ctypes.c_double, [C, D, D]),
+            "gblo_delta_loglike_matrix": (ctypes.c_int, [C, D, ctypes.c_int32, D, ctypes.c_int32, D, D,
+                                                         ctypes.c_int32, I32, I32, ctypes.c_int64, D]),
             "gblo_psd_loglike": (ctypes.c_int, [C, D, ctypes.c_int32, D, I32, ctypes.c_int64, D]),
             "gblo_delta_loglike": (ctypes.c_int, [C, D, ctypes.c_int32, D, ctypes.c_int32, ctypes.c_int32, D, D,
                                                   ctypes.c_int32, I32, I32, ctypes.c_int64, D, D]),
@@ -302,6 +307,41 @@ class Oracle:
         rc = self.lib.gblo_overlap(ctypes.byref(self.cfg), _d(pa), _d(pb), B, int(N), _d(psd), psd.shape[0],
                                    int(bool(psd_is_inverse)), _i32(psd_idx), _d(out))
         _check(rc, "overlap")
+        return out
+
+    def noise_matrix_value(self, f: float, levels) -> np.ndarray:
+        """(K_AA, K_EE, Re K_AE, Im K_AE, ln det C) at frequency f for 12 link noise levels"""
+        levels = _f64(levels)
+        out = np.zeros(5)
+        self.lib.gblo_noise_matrix_value(ctypes.byref(self.cfg), float(f), _d(levels), _d(out))
+        return out
+
+    def noise_matrix(self, levels) -> np.ndarray:
+        """[P][5][n_bins] inverse channel covariance and ln det for level sets [P][12]"""
+        levels = _f64(levels).reshape(-1, 12)
+        out = np.zeros((levels.shape[0], 5, self.n_bins))
+        _check(self.lib.gblo_noise_matrix(ctypes.byref(self.cfg), _d(levels), levels.shape[0], _d(out)),
+               "noise_matrix")
+        return out
+
+    def loglike_matrix(self, R, K) -> float:
+        R = np.ascontiguousarray(R, dtype=np.complex128).reshape(2, self.n_bins)
+        K = _f64(K).reshape(5, self.n_bins)
+        return float(self.lib.gblo_loglike_matrix(ctypes.byref(self.cfg), _d(R.view(np.float64)), _d(K)))
+
+    def delta_loglike_matrix(self, residual, K, params_old, params_new, N: int, res_idx=None, k_idx=None):
+        residual = np.ascontiguousarray(residual, dtype=np.complex128).reshape(-1, 2, self.n_bins)
+        K = _f64(K).reshape(-1, 5, self.n_bins)
+        po = _f64(params_old).reshape(-1, 8)
+        pn = _f64(params_new).reshape(-1, 8)
+        B = po.shape[0]
+        res_idx = np.zeros(B, np.int32) if res_idx is None else np.ascontiguousarray(res_idx, np.int32)
+        k_idx = np.zeros(B, np.int32) if k_idx is None else np.ascontiguousarray(k_idx, np.int32)
+        out = np.zeros(B)
+        rc = self.lib.gblo_delta_loglike_matrix(ctypes.byref(self.cfg), _d(residual.view(np.float64)),
+                                                residual.shape[0], _d(K), K.shape[0], _d(po), _d(pn), int(N),
+                                                _i32(res_idx), _i32(k_idx), B, _d(out))
+        _check(rc, "delta_loglike_matrix")
         return out
 
     def loglike(self, R, S) -> float:

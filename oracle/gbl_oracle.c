@@ -1789,3 +1789,157 @@ int gblo_search_ball(const gblo_config* cfg, const gblo_search_config* sc, int64
   }
   return gblo_search_eval(cfg, sc, residual, psd, u, logl);
 }
+
+/* ------------------------------------------------------------------------
+ * Correlated A/E noise (Sec. 2: with unequal noise in the links the A and E
+ * channels are no longer uncorrelated, and the likelihood needs the noise
+ * matrix across channels).  Noise model: every link y_{s->r} carries its own
+ * optical-metrology noise o_{sr} and the Doppler noises of the two test
+ * masses it bounces off, delta_{rs} + D delta_{sr} (delta_{ab}: the test
+ * mass on craft a facing craft b, D the one-arm delay exp(-i x),
+ * x = 2 pi f L / c); the twelve noises are independent with the spectral
+ * shapes of eq. psd: S_op = s_o^2 (2 pi f / c)^2 [1 + (2 mHz/f)^4] per link,
+ * S_pm = s_a^2 (2 pi c f)^-2 [1 + (0.4 mHz/f)^2][1 + (f/8 mHz)^4] per test
+ * mass.  The channels are the first-generation Michelson combinations
+ * X = (1 - D^2)[(y_{1->0} + D y_{0->1}) - (y_{2->0} + D y_{0->2})] (and
+ * cyclic), A = (Z - X)/sqrt 2, E = (X - 2Y + Z)/sqrt 6, so their noise
+ * covariance is C = T diag(S_j) T^H with T the coefficients of the twelve
+ * noises in (A, E).
+ * levels[12]: s_o of the links 0->1, 0->2, 1->0, 1->2, 2->0, 2->1, then s_a
+ * of the test masses (0,1), (0,2), (1,0), (1,2), (2,0), (2,1).
+ * Output per bin: K = C^-1 as (K_AA, K_EE, Re K_AE, Im K_AE) and ln det C.
+ * ------------------------------------------------------------------------ */
+static int link_index(int s, int r) { /* (s -> r) in the order above */
+  static const int tab[3][3] = {{-1, 0, 1}, {2, -1, 3}, {4, 5, -1}};
+  return tab[s][r];
+}
+
+/* coefficients of the 12 noises in y_{s->r} */
+static void link_noise(int s, int r, cplx D, cplx* coef /*[12]*/) {
+  for (int j = 0; j < 12; j++) coef[j] = 0;
+  coef[link_index(s, r)] += 1.0;           /* o_{sr} */
+  coef[6 + link_index(r, s)] += 1.0;       /* delta_{rs} */
+  coef[6 + link_index(s, r)] += D;         /* D delta_{sr} */
+}
+
+/* coefficients of the 12 noises in the Michelson combination at vertex v
+ * with arms to b1 and b2 */
+static void michelson_noise(int v, int b1, int b2, cplx D, cplx* coef) {
+  cplx t1[12], t2[12], t3[12], t4[12];
+  link_noise(b1, v, D, t1); /* y_{b1->v} */
+  link_noise(v, b1, D, t2); /* y_{v->b1} */
+  link_noise(b2, v, D, t3);
+  link_noise(v, b2, D, t4);
+  const cplx f = 1.0 - D * D;
+  for (int j = 0; j < 12; j++) coef[j] = f * ((t1[j] + D * t2[j]) - (t3[j] + D * t4[j]));
+}
+
+void gblo_noise_matrix_value(const gblo_config* cfg, double f, const double* levels, double out[5]) {
+  const double x = 2.0 * ORC_PI * f * cfg->L / ORC_C;
+  const cplx D = cexp(-I * x);
+  cplx X[12], Y[12], Z[12];
+  michelson_noise(0, 1, 2, D, X);
+  michelson_noise(1, 2, 0, D, Y);
+  michelson_noise(2, 0, 1, D, Z);
+  double S[12];
+  for (int j = 0; j < 6; j++)
+    S[j] = levels[j] * levels[j] * pow(2.0 * ORC_PI * f / ORC_C, 2.0) * (1.0 + pow(2e-3 / f, 4.0));
+  for (int j = 6; j < 12; j++)
+    S[j] = levels[j] * levels[j] * pow(2.0 * ORC_PI * ORC_C * f, -2.0) * (1.0 + pow(0.4e-3 / f, 2.0)) *
+           (1.0 + pow(f / 8e-3, 4.0));
+  double caa = 0, cee = 0;
+  cplx cae = 0;
+  for (int j = 0; j < 12; j++) {
+    const cplx a = (Z[j] - X[j]) / sqrt(2.0);
+    const cplx e = (X[j] - 2.0 * Y[j] + Z[j]) / sqrt(6.0);
+    caa += creal(a * conj(a)) * S[j];
+    cee += creal(e * conj(e)) * S[j];
+    cae += a * conj(e) * S[j];
+  }
+  /* C = [[caa, cae], [conj(cae), cee]];  K = C^-1 = [[cee, -cae], [-conj(cae), caa]] / det */
+  const double det = caa * cee - creal(cae * conj(cae));
+  out[0] = cee / det;
+  out[1] = caa / det;
+  out[2] = -creal(cae) / det;
+  out[3] = -cimag(cae) / det;
+  out[4] = log(det);
+}
+
+int gblo_noise_matrix(const gblo_config* cfg, const double* levels, int64_t P, double* out /*[P][5][n_bins]*/) {
+  int64_t k_min, nb;
+  gblo_band(cfg, &k_min, &nb);
+#pragma omp parallel for
+  for (int64_t pi = 0; pi < P; pi++)
+    for (int64_t i = 0; i < nb; i++) {
+      double v[5];
+      gblo_noise_matrix_value(cfg, (double)(k_min + i) / cfg->T, levels + 12 * pi, v);
+      for (int c = 0; c < 5; c++) out[(pi * 5 + c) * nb + i] = v[c];
+    }
+  return 0;
+}
+
+/* 4 df Re sum_k a_k^H K_k b_k over the band for full-band series a, b [2][nb] */
+static double matrix_inner(const gblo_config* cfg, int64_t nb, const cplx* a, const cplx* b, const double* K) {
+  double s = 0;
+  for (int64_t k = 0; k < nb; k++) {
+    const cplx kae = K[2 * nb + k] + I * K[3 * nb + k];
+    const cplx Kb0 = K[k] * b[k] + kae * b[nb + k];
+    const cplx Kb1 = conj(kae) * b[k] + K[nb + k] * b[nb + k];
+    s += creal(conj(a[k]) * Kb0 + conj(a[nb + k]) * Kb1);
+  }
+  return 4.0 / cfg->T * s;
+}
+
+/* eq. like with the channel matrix: -1/2 <R|R>_K - sum_k ln det C_k */
+double gblo_loglike_matrix(const gblo_config* cfg, const double* R /*[2][nb][2]*/, const double* K /*[5][nb]*/) {
+  int64_t k_min, nb;
+  gblo_band(cfg, &k_min, &nb);
+  double ld = 0;
+  for (int64_t k = 0; k < nb; k++) ld += K[4 * nb + k];
+  return -0.5 * matrix_inner(cfg, nb, (const cplx*)R, (const cplx*)R, K) - ld;
+}
+
+/* eq. swapsource with the channel matrix:
+ *   dlogl[b] = <R|a - r>_K - 1/2 <a - r|a - r>_K
+ * with R = residual[res_idx[b]], K = Kmat[k_idx[b]] ([n_K][5][n_bins] as
+ * gblo_noise_matrix writes it); templates clipped to the band. */
+int gblo_delta_loglike_matrix(const gblo_config* cfg, const double* residual, int32_t n_res, const double* Kmat,
+                              int32_t n_K, const double* params_old, const double* params_new, int32_t N,
+                              const int32_t* res_idx, const int32_t* k_idx, int64_t B, double* dlogl) {
+  int64_t k_min, nb;
+  gblo_band(cfg, &k_min, &nb);
+  if (N < 2 || (N & (N - 1))) return -2;
+  for (int64_t b = 0; b < B; b++)
+    if (res_idx[b] < 0 || res_idx[b] >= n_res || k_idx[b] < 0 || k_idx[b] >= n_K) return -1;
+#pragma omp parallel for schedule(dynamic, 4)
+  for (int64_t b = 0; b < B; b++) {
+    const double* po = params_old + 8 * b;
+    const double* pn = params_new + 8 * b;
+    if (!params_finite(cfg, po) || !params_finite(cfg, pn)) {
+      dlogl[b] = NAN;
+      continue;
+    }
+    /* d = a - r on the full band (plain, slow) */
+    cplx* d = (cplx*)calloc((size_t)(2 * nb), sizeof(cplx));
+    cplx* h = (cplx*)malloc(sizeof(cplx) * 2 * N);
+    int64_t k0;
+    waveform_one(cfg, pn, N, h, h + N, NULL, &k0);
+    for (int c = 0; c < 2; c++)
+      for (int j = 0; j < N; j++) {
+        int64_t k = k0 + j;
+        if (k >= k_min && k < k_min + nb) d[c * nb + (k - k_min)] += h[c * N + j];
+      }
+    waveform_one(cfg, po, N, h, h + N, NULL, &k0);
+    for (int c = 0; c < 2; c++)
+      for (int j = 0; j < N; j++) {
+        int64_t k = k0 + j;
+        if (k >= k_min && k < k_min + nb) d[c * nb + (k - k_min)] -= h[c * N + j];
+      }
+    const cplx* R = (const cplx*)(residual + (int64_t)res_idx[b] * 2 * nb * 2);
+    const double* K = Kmat + (int64_t)k_idx[b] * 5 * nb;
+    dlogl[b] = matrix_inner(cfg, nb, R, d, K) - 0.5 * matrix_inner(cfg, nb, d, d, K);
+    free(d);
+    free(h);
+  }
+  return 0;
+}
