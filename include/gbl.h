@@ -233,6 +233,18 @@ int gb_psd_loglike(gbl_ctx* ctx, const double* residual, int32_t n_res, const do
 int gb_psd_loglike_n(gbl_ctx* ctx, const double* residual, int32_t n_res, const double* noise, int32_t n_par,
                      const int32_t* res_idx, int64_t P, double* logl);
 
+/* For callers that cannot allocate (code under graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): gb_psd_loglike_n with its partial
+ * sums in a static device array of the library instead of the context's
+ * workspace.  P <= 2048 parameter sets (the array holds 2048 x 256 x 2
+ * doubles, 8 MB per device, kept until the process ends); larger P is
+ * rejected with GBL_EINVAL.  Allocates nothing.  Every call on one device
+ * shares that device's array: calls that overlap on one device (several
+ * streams or contexts) race and must be serialised by the caller.  Results
+ * equal gb_psd_loglike_n's (same kernels, same summation order). */
+int gb_psd_loglike_noalloc(gbl_ctx* ctx, const double* residual, int32_t n_res, const double* noise,
+                           int32_t n_par, const int32_t* res_idx, int64_t P, double* logl);
+
 /* residual[res_idx[b]] += sign * (A, E) of template b, clipped to the band
  * (the residual updates of the sampling algorithm's write-back step).  By
  * default FP64 atomic adds, so overlapping templates are summed in an

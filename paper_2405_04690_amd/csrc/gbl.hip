@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 
 #include "../../include/gbl.h"
@@ -17,6 +18,12 @@
 #include "gbl_search.hpp"
 
 using gbl::cd;
+
+// Static scratch of the allocation-free PSD likelihood: the per-chunk
+// partial sums of up to 2048 parameter sets (8 MB).  Each device holds its
+// own copy; host code uses the address hipGetSymbolAddress returns for the
+// current device (kept per device below), never the symbol's name.
+static __device__ __align__(256) double scratch[2 * gbl::kPsdChunks * 2048];
 
 namespace {
 
@@ -29,6 +36,25 @@ constexpr int kBucketCap = 1 << 20;             // templates per bucketed (uneve
 constexpr int64_t kDetCap = (int64_t)1 << 22;    // deterministic scatter: slice elements per channel and chunk
                                                  // (128 MB of slices; 2^22 / N templates per chunk)
 constexpr int64_t kDetMaxChunk = kDetCap / 128;
+
+constexpr int64_t kScratchSets = 2048;  // parameter sets the static scratch holds
+constexpr int kMaxDevices = 64;
+double* scratch_ptr[kMaxDevices] = {};
+std::mutex scratch_mu;
+
+// the scratch address on the current device (looked up once per device)
+int scratch_for_current_device(double** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return GBL_EHIP;
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  if (!scratch_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return GBL_EHIP;
+    scratch_ptr[dev] = (double*)p;
+  }
+  *out = scratch_ptr[dev];
+  return GBL_OK;
+}
 
 int width_slot(int N) {
   for (int i = 0; i < kNumWidths; i++)
@@ -50,6 +76,7 @@ struct gbl_ctx {
   double* psd_P3;    // foreground factors (Sec. 3): 3 x^2 sin^2 x f^(-7/3)
   double* psd_LF;    // ln f
   double* psd_work;
+  double* scratch;   // this device's static scratch (allocation-free PSD likelihood)
   int* counts;       // [4 widths] templates per width bucket
   int32_t* perm;     // [4 widths][kBucketCap] template indices per width
   gbl_tuning tune;        // launch-shape knobs
@@ -209,6 +236,12 @@ extern "C" int gbl_create(gbl_ctx** out, const gbl_config* cfg, void* hip_stream
       return GBL_EHIP;
     }
     ctx->det_sort_bytes = tmp;
+  }
+  if (scratch_for_current_device(&ctx->scratch) != GBL_OK) {
+    (void)hipGetLastError();
+    release(ctx);
+    delete ctx;
+    return GBL_EHIP;
   }
   hipLaunchKernelGGL(gbl::k_init_psd_basis, dim3((unsigned)((g.n_bins + 255) / 256)), dim3(256), 0, ctx->stream,
                      g.k_min, g.n_bins, g.T, g.L, ctx->psd_P1, ctx->psd_P2, ctx->psd_P3, ctx->psd_LF);
@@ -642,28 +675,31 @@ extern "C" int gb_psd_eval(gbl_ctx* ctx, const double* noise, int64_t P, int32_t
 // remainder one set per block), then the fixed-order final sum per set.
 template <int NP>
 static void psd_partial_launch(gbl_ctx* ctx, const cd* residual, int n_res, const double* noise,
-                               const int32_t* res_idx, int64_t p0, int64_t np) {
+                               const int32_t* res_idx, int64_t p0, int64_t np, double* work) {
   const int64_t ng = np / gbl::kPsdSets, rest = np - ng * gbl::kPsdSets;
   if (ng > 0)
     hipLaunchKernelGGL((gbl::k_psd_partial<gbl::kPsdSets, NP>), dim3(gbl::kPsdChunks, (unsigned)ng),
                        dim3(gbl::kPsdBlock), 0, ctx->stream, ctx->geo.n_bins, psd_basis(ctx), residual, n_res, noise,
-                       res_idx, p0, p0, ctx->psd_work);
+                       res_idx, p0, p0, work);
   if (rest > 0)
     hipLaunchKernelGGL((gbl::k_psd_partial<1, NP>), dim3(gbl::kPsdChunks, (unsigned)rest), dim3(gbl::kPsdBlock), 0,
                        ctx->stream, ctx->geo.n_bins, psd_basis(ctx), residual, n_res, noise, res_idx, p0,
-                       p0 + ng * gbl::kPsdSets, ctx->psd_work);
+                       p0 + ng * gbl::kPsdSets, work);
 }
 
+// work: [kPsdBatch][kPsdChunks][2] partial sums (the context's workspace, or
+// the static scratch for batches of at most kScratchSets sets)
 static void psd_loglike_launch(gbl_ctx* ctx, const cd* residual, int n_res, const double* noise, int n_par,
-                               const int32_t* res_idx, int64_t P, double* logl) {
+                               const int32_t* res_idx, int64_t P, double* logl, double* work = nullptr) {
+  if (!work) work = ctx->psd_work;
   for (int64_t p0 = 0; p0 < P; p0 += kPsdBatch) {
     const int64_t np = P - p0 < kPsdBatch ? P - p0 : kPsdBatch;
     if (n_par == 9)
-      psd_partial_launch<9>(ctx, residual, n_res, noise, res_idx, p0, np);
+      psd_partial_launch<9>(ctx, residual, n_res, noise, res_idx, p0, np, work);
     else
-      psd_partial_launch<4>(ctx, residual, n_res, noise, res_idx, p0, np);
-    hipLaunchKernelGGL(gbl::k_psd_final, dim3((unsigned)np), dim3(64), 0, ctx->stream, 1.0 / ctx->cfg.T,
-                       ctx->psd_work, p0, logl);
+      psd_partial_launch<4>(ctx, residual, n_res, noise, res_idx, p0, np, work);
+    hipLaunchKernelGGL(gbl::k_psd_final, dim3((unsigned)np), dim3(64), 0, ctx->stream, 1.0 / ctx->cfg.T, work, p0,
+                       logl);
   }
 }
 
@@ -676,6 +712,20 @@ extern "C" int gb_psd_loglike_n(gbl_ctx* ctx, const double* residual, int32_t n_
   if (!residual || !noise || !res_idx || !logl) return fail(ctx, GBL_EINVAL, "gb_psd_loglike: null pointer%s");
   psd_loglike_launch(ctx, (const cd*)residual, (int)n_res, noise, n_par, res_idx, P, logl);
   return check_launch(ctx, "gb_psd_loglike");
+}
+
+extern "C" int gb_psd_loglike_noalloc(gbl_ctx* ctx, const double* residual, int32_t n_res, const double* noise,
+                                      int32_t n_par, const int32_t* res_idx, int64_t P, double* logl) {
+  if (!ctx) return GBL_EINVAL;
+  if (P < 0 || n_res < 1) return fail(ctx, GBL_EINVAL, "gb_psd_loglike_noalloc: bad sizes%s");
+  if (P > kScratchSets) return fail(ctx, GBL_EINVAL, "gb_psd_loglike_noalloc: more than 2048 parameter sets%s");
+  if (n_par != 4 && n_par != 9) return fail(ctx, GBL_EINVAL, "gb_psd_loglike_noalloc: n_par must be 4 or 9%s");
+  if (P == 0) return GBL_OK;
+  if (!residual || !noise || !res_idx || !logl)
+    return fail(ctx, GBL_EINVAL, "gb_psd_loglike_noalloc: null pointer%s");
+  // every partial sum is written before it is read: nothing to clear
+  psd_loglike_launch(ctx, (const cd*)residual, (int)n_res, noise, n_par, res_idx, P, logl, ctx->scratch);
+  return check_launch(ctx, "gb_psd_loglike_noalloc");
 }
 
 extern "C" int gb_psd_loglike(gbl_ctx* ctx, const double* residual, int32_t n_res, const double* noise,

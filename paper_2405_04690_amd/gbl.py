@@ -35,7 +35,7 @@ EXPORTED = ("gbl_create", "gbl_destroy", "gbl_set_stream", "gbl_last_error", "gb
             "gbl_get_tuning", "gbl_set_tuning", "gb_psd_sweep_step", "gb_graph_begin", "gb_graph_end",
             "gb_psd_eval_n", "gb_psd_loglike_n", "gb_inner", "gb_snr", "gb_sweep_adapt_ladder",
             "gb_sweep_shift_ownership", "gb_overlap", "gb_search_workspace", "gb_search_eval",
-            "gb_search_step", "gb_search_ball")
+            "gb_search_step", "gb_search_ball", "gb_psd_loglike_noalloc")
 
 GBL_MOVE_INMODEL, GBL_MOVE_RJ, GBL_MOVE_PT = 0, 1, 2
 
@@ -143,6 +143,7 @@ def load_library(path: str = LIB_PATH):
         "gb_psd_loglike": [vp, vp, i32, vp, vp, i64, vp],
         "gb_psd_eval_n": [vp, vp, i32, i64, i32, vp],
         "gb_psd_loglike_n": [vp, vp, i32, vp, i32, vp, i64, vp],
+        "gb_psd_loglike_noalloc": [vp, vp, i32, vp, i32, vp, i64, vp],
         "gb_inner": [vp, vp, vp, vp, i32, vp, i32, vp, i32, i32, vp, vp, i64, vp],
         "gb_snr": [vp, vp, i64, i32, vp, i32, i32, vp, vp, i32, vp, vp, vp],
         "gb_overlap": [vp, vp, vp, i32, vp, i32, i32, vp, i64, vp],
