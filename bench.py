@@ -383,6 +383,20 @@ def sweep_bench(torch, dev, stream, n_sweeps, n_temps=36, n_walkers=32, n_prop=3
     torch.cuda.synchronize()
     graph_ms = a.elapsed_time(b) / n_sweeps
     sw.release_graph()
+    # same-parity overlap: cold-chain templates of bands b and b + 2 whose
+    # windows intersect (carrier bins less than N apart); their cross term is
+    # absent while both bands update in parallel (odd/even scheme)
+    ex0 = sw.exists[0].cpu().numpy().astype(bool)
+    q0 = np.floor(sw.u[0, ..., 1].cpu().numpy() * T).astype(np.int64)
+    n_pairs = n_cold = 0
+    for w in range(n_walkers):
+        for b in range(n_bands - 2):
+            qa = q0[w, b][ex0[w, b]]
+            qb = q0[w, b + 2][ex0[w, b + 2]]
+            n_cold += len(qa)
+            if len(qa) and len(qb):
+                n_pairs += int((np.abs(qa[:, None] - qb[None, :]) < N).sum())
+    overlap = {"cold_sources": int(ex0.sum()), "pairs_b_b2_overlapping": n_pairs}
     full = _full_sweep(torch, ctx, sw, stream, d, n_bands, k_band0, N, n_temps, n_walkers)
     dst = st1 - st0
     rate = lambda k: round(float(dst[k]) / (direct_ms * n_sweeps / 1e3), 1)
@@ -396,6 +410,7 @@ def sweep_bench(torch, dev, stream, n_sweeps, n_temps=36, n_walkers=32, n_prop=3
            "inmodel_proposals_per_s": rate(0), "rj_proposals_per_s": rate(2) + rate(4),
            "swap_proposals_per_s": rate(6),
            "acceptance": {"inmodel": acc(0, 1), "birth": acc(2, 3), "death": acc(4, 5), "swap": acc(6, 7)},
+           "same_parity_overlap": overlap,
            "full_gb_noise_sweep": full}
     del sw
     ctx.close()

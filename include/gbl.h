@@ -653,6 +653,40 @@ int gb_search_step(gbl_ctx* ctx, const gbl_search_config* cfg, const gbl_search_
 int gb_search_ball(gbl_ctx* ctx, const gbl_search_config* cfg, const gbl_search_state* st, int64_t iter,
                    const double* sigma, const double* residual, const double* psd);
 
+/* ---------------------------------------------------------------------------
+ * Correlated A/E channels (Sec. 2: the A, E, T variables are uncorrelated only
+ * under idealised assumptions; with unequal noise a likelihood matrix across
+ * channels is needed).  Noise model: twelve independent noises -- the
+ * metrology noise of each link and the Doppler noise of each test mass --
+ * with the spectral shapes of eq. psd; a link y_{s->r} carries o_{sr} +
+ * delta_{rs} + D delta_{sr}, D = exp(-2 pi i f L / c); the first-generation
+ * Michelson combinations and A = (Z - X)/sqrt 2, E = (X - 2Y + Z)/sqrt 6 give
+ * the 2 x 2 noise matrix C per bin.  Equal levels reproduce eq. psd with no
+ * cross term.  The inner product becomes <a|b>_K = 4 df Re sum_k a_k^H K_k
+ * b_k with K = C^-1.
+ * levels [P][12]: sqrt S_oms of the links 0->1, 0->2, 1->0, 1->2, 2->0, 2->1,
+ * then sqrt S_acc of the test masses (0,1), (0,2), (1,0), (1,2), (2,0), (2,1)
+ * (mass (a, b): on craft a, facing craft b).
+ * Matrix arrays K [n_K][5][n_bins]: K_AA, K_EE, Re K_AE, Im K_AE, ln det C.
+ * --------------------------------------------------------------------------- */
+int gb_noise_matrix(gbl_ctx* ctx, const double* levels, int64_t P, double* out);
+
+/* eq. swapsource with the channel matrix:
+ *   dlogl[b] = <R|a - r>_K - 1/2 <a - r|a - r>_K,  R = residual[res_idx[b]],
+ * K = K[k_idx[b]], a/r the width-N templates of params_new/params_old (FP64),
+ * the sum over the union of their windows clipped to the band.  Undefined
+ * parameters or out-of-range indices give NaN.
+ * Errors: GBL_EINVAL, GBL_EUNSUPPORTED (N). */
+int gb_delta_loglike_matrix(gbl_ctx* ctx, const double* residual, int32_t n_res, const double* K, int32_t n_K,
+                            const double* params_old, const double* params_new, int32_t N, const int32_t* res_idx,
+                            const int32_t* k_idx, int64_t B, double* dlogl);
+
+/* eq. like with the channel matrix: logl[p] = -1/2 <R|R>_K - sum_k ln det C_k,
+ * R = residual[res_idx[p]], K = K[k_idx[p]]; fixed-order reduction.  An
+ * out-of-range index gives NaN.  Errors: GBL_EINVAL. */
+int gb_loglike_matrix(gbl_ctx* ctx, const double* residual, int32_t n_res, const double* K, int32_t n_K,
+                      const int32_t* res_idx, const int32_t* k_idx, int64_t P, double* logl);
+
 #ifdef __cplusplus
 }
 #endif

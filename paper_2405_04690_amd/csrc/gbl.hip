@@ -16,6 +16,7 @@
 #include "gbl_sampler.hpp"
 #include "gbl_flow.hpp"
 #include "gbl_search.hpp"
+#include "gbl_matrix.hpp"
 
 using gbl::cd;
 
@@ -1484,4 +1485,62 @@ extern "C" int gb_search_ball(gbl_ctx* ctx, const gbl_search_config* cfg, const 
   rc = gb_delta_loglike(ctx, residual, 1, psd, 1, 0, a.wpo, a.wpn, cfg->N, a.widx, a.widx, n, st->logl);
   if (rc) return rc;
   return check_launch(ctx, "gb_search_ball");
+}
+
+// ---------------------------------------------------------------------------
+// correlated A/E channels (Sec. 2): noise matrix and matrix-weighted likelihoods
+// ---------------------------------------------------------------------------
+extern "C" int gb_noise_matrix(gbl_ctx* ctx, const double* levels, int64_t P, double* out) {
+  if (!ctx) return GBL_EINVAL;
+  if (P < 0) return fail(ctx, GBL_EINVAL, "gb_noise_matrix: P < 0%s");
+  if (P == 0) return GBL_OK;
+  if (!levels || !out) return fail(ctx, GBL_EINVAL, "gb_noise_matrix: null pointer%s");
+  hipLaunchKernelGGL(gbl::k_noise_matrix, gbl::row_grid(ctx->geo.n_bins, P), dim3(256), 0, ctx->stream,
+                     ctx->geo.n_bins, ctx->geo.k_min, ctx->cfg.T, ctx->cfg.L, (const gbl::NoiseLevels*)levels, P,
+                     out);
+  return check_launch(ctx, "gb_noise_matrix");
+}
+
+template <int N>
+struct LaunchDeltaMat {
+  static void run(gbl_ctx* ctx, const cd* residual, int n_res, const double* K, int n_K, const double* po,
+                  const double* pn, const int32_t* ri, const int32_t* ki, int64_t b0, int64_t nb, double* out) {
+    hipLaunchKernelGGL((gbl::k_delta_loglike_mat<N>), dim3((unsigned)nb), dim3(gbl::block_threads<N>()), 0,
+                       ctx->stream, ctx->geo, tables_for<N, double>(ctx), residual, n_res, K, n_K, po, pn, ri, ki,
+                       b0, out);
+  }
+};
+
+extern "C" int gb_delta_loglike_matrix(gbl_ctx* ctx, const double* residual, int32_t n_res, const double* K,
+                                       int32_t n_K, const double* params_old, const double* params_new, int32_t N,
+                                       const int32_t* res_idx, const int32_t* k_idx, int64_t B, double* dlogl) {
+  if (!ctx) return GBL_EINVAL;
+  if (B < 0 || n_res < 1 || n_K < 1) return fail(ctx, GBL_EINVAL, "gb_delta_loglike_matrix: bad sizes%s");
+  if (width_slot(N) < 0) return fail(ctx, GBL_EUNSUPPORTED, "gb_delta_loglike_matrix: unsupported N%s");
+  if (B == 0) return GBL_OK;
+  if (!residual || !K || !params_old || !params_new || !res_idx || !k_idx || !dlogl)
+    return fail(ctx, GBL_EINVAL, "gb_delta_loglike_matrix: null pointer%s");
+  for (int64_t b0 = 0; b0 < B; b0 += kMaxGrid) {
+    const int64_t nb = B - b0 < kMaxGrid ? B - b0 : kMaxGrid;
+    dispatch_width<LaunchDeltaMat>(N, ctx, (const cd*)residual, (int)n_res, K, (int)n_K, params_old, params_new,
+                                   res_idx, k_idx, b0, nb, dlogl);
+  }
+  return check_launch(ctx, "gb_delta_loglike_matrix");
+}
+
+extern "C" int gb_loglike_matrix(gbl_ctx* ctx, const double* residual, int32_t n_res, const double* K, int32_t n_K,
+                                 const int32_t* res_idx, const int32_t* k_idx, int64_t P, double* logl) {
+  if (!ctx) return GBL_EINVAL;
+  if (P < 0 || n_res < 1 || n_K < 1) return fail(ctx, GBL_EINVAL, "gb_loglike_matrix: bad sizes%s");
+  if (P == 0) return GBL_OK;
+  if (!residual || !K || !res_idx || !k_idx || !logl) return fail(ctx, GBL_EINVAL, "gb_loglike_matrix: null pointer%s");
+  for (int64_t p0 = 0; p0 < P; p0 += kPsdBatch) {
+    const int64_t np = P - p0 < kPsdBatch ? P - p0 : kPsdBatch;
+    hipLaunchKernelGGL(gbl::k_loglike_mat_partial, dim3(gbl::kPsdChunks, (unsigned)np), dim3(gbl::kPsdBlock), 0,
+                       ctx->stream, ctx->geo.n_bins, (const cd*)residual, (int)n_res, K, (int)n_K, res_idx, k_idx, p0,
+                       ctx->psd_work);
+    hipLaunchKernelGGL(gbl::k_psd_final, dim3((unsigned)np), dim3(64), 0, ctx->stream, 1.0 / ctx->cfg.T,
+                       ctx->psd_work, p0, logl);
+  }
+  return check_launch(ctx, "gb_loglike_matrix");
 }

@@ -35,7 +35,8 @@ EXPORTED = ("gbl_create", "gbl_destroy", "gbl_set_stream", "gbl_last_error", "gb
             "gbl_get_tuning", "gbl_set_tuning", "gb_psd_sweep_step", "gb_graph_begin", "gb_graph_end",
             "gb_psd_eval_n", "gb_psd_loglike_n", "gb_inner", "gb_snr", "gb_sweep_adapt_ladder",
             "gb_sweep_shift_ownership", "gb_overlap", "gb_search_workspace", "gb_search_eval",
-            "gb_search_step", "gb_search_ball", "gb_psd_loglike_noalloc")
+            "gb_search_step", "gb_search_ball", "gb_psd_loglike_noalloc", "gb_noise_matrix",
+            "gb_delta_loglike_matrix", "gb_loglike_matrix")
 
 GBL_MOVE_INMODEL, GBL_MOVE_RJ, GBL_MOVE_PT = 0, 1, 2
 
@@ -144,6 +145,9 @@ def load_library(path: str = LIB_PATH):
         "gb_psd_eval_n": [vp, vp, i32, i64, i32, vp],
         "gb_psd_loglike_n": [vp, vp, i32, vp, i32, vp, i64, vp],
         "gb_psd_loglike_noalloc": [vp, vp, i32, vp, i32, vp, i64, vp],
+        "gb_noise_matrix": [vp, vp, i64, vp],
+        "gb_delta_loglike_matrix": [vp, vp, i32, vp, i32, vp, vp, i32, vp, vp, i64, vp],
+        "gb_loglike_matrix": [vp, vp, i32, vp, i32, vp, vp, i64, vp],
         "gb_inner": [vp, vp, vp, vp, i32, vp, i32, vp, i32, i32, vp, vp, i64, vp],
         "gb_snr": [vp, vp, i64, i32, vp, i32, i32, vp, vp, i32, vp, vp, vp],
         "gb_overlap": [vp, vp, vp, i32, vp, i32, i32, vp, i64, vp],
@@ -465,6 +469,58 @@ class Context:
         rc = self.lib.gb_overlap(self._h, _ptr(params_a), _ptr(params_b), int(N), _ptr(psd), psd.shape[0],
                                  GBL_PSD_INVERSE if psd_inverse else 0, _ptr(psd_idx), B, _ptr(out))
         self._check(rc, "gb_overlap")
+        return out
+
+    def gb_noise_matrix(self, levels):
+        """[P, 5, n_bins]: K_AA, K_EE, Re K_AE, Im K_AE, ln det C for link noise levels [P, 12]"""
+        levels = self._dev(levels, torch.float64, "levels")
+        if levels.dim() != 2 or levels.shape[1] != 12:
+            raise ValueError("levels must have shape [P, 12]")
+        P = levels.shape[0]
+        out = torch.empty((P, 5, self.n_bins), dtype=torch.float64, device=self.device)
+        self._sync_stream()
+        self._check(self.lib.gb_noise_matrix(self._h, _ptr(levels), P, _ptr(out)), "gb_noise_matrix")
+        return out
+
+    def _kmat(self, K):
+        K = self._dev(K, torch.float64, "K")
+        if K.dim() != 3 or K.shape[1] != 5 or K.shape[2] != self.n_bins:
+            raise ValueError("K must have shape [n_K, 5, n_bins]")
+        return K
+
+    def gb_delta_loglike_matrix(self, residual, K, params_old, params_new, N: int, res_idx=None, k_idx=None):
+        residual = self._residual(residual)
+        K = self._kmat(K)
+        po = self._params(params_old, "params_old")
+        pn = self._params(params_new, "params_new")
+        B = po.shape[0]
+        if pn.shape[0] != B:
+            raise ValueError("params_old and params_new must have the same length")
+        res_idx = torch.zeros(B, dtype=torch.int32, device=self.device) if res_idx is None else res_idx
+        k_idx = torch.zeros(B, dtype=torch.int32, device=self.device) if k_idx is None else k_idx
+        res_idx = self._dev(res_idx, torch.int32, "res_idx")
+        k_idx = self._dev(k_idx, torch.int32, "k_idx")
+        out = torch.empty(B, dtype=torch.float64, device=self.device)
+        self._sync_stream()
+        rc = self.lib.gb_delta_loglike_matrix(self._h, _ptr(residual), residual.shape[0], _ptr(K), K.shape[0],
+                                              _ptr(po), _ptr(pn), int(N), _ptr(res_idx), _ptr(k_idx), B, _ptr(out))
+        self._check(rc, "gb_delta_loglike_matrix")
+        return out
+
+    def gb_loglike_matrix(self, residual, K, res_idx=None, k_idx=None, P=None):
+        residual = self._residual(residual)
+        K = self._kmat(K)
+        if P is None:
+            P = res_idx.numel() if res_idx is not None else K.shape[0]
+        res_idx = torch.zeros(P, dtype=torch.int32, device=self.device) if res_idx is None else res_idx
+        k_idx = torch.arange(P, dtype=torch.int32, device=self.device) if k_idx is None else k_idx
+        res_idx = self._dev(res_idx, torch.int32, "res_idx")
+        k_idx = self._dev(k_idx, torch.int32, "k_idx")
+        out = torch.empty(P, dtype=torch.float64, device=self.device)
+        self._sync_stream()
+        rc = self.lib.gb_loglike_matrix(self._h, _ptr(residual), residual.shape[0], _ptr(K), K.shape[0],
+                                        _ptr(res_idx), _ptr(k_idx), P, _ptr(out))
+        self._check(rc, "gb_loglike_matrix")
         return out
 
     def gb_snr(self, params, N: int, psd, psd_idx=None, data=None, data_idx=None, psd_inverse: bool = False):
