@@ -326,7 +326,7 @@ def sweep_bench(torch, dev, stream, n_sweeps, n_temps=36, n_walkers=32, n_prop=3
     n_slot = ub.shape[1]
     sc = make_config(n_temps, n_walkers, n_bands, n_slot, N, k_band0, n_prop=n_prop, n_friends=40,
                      group_every=30, seed=37)
-    sw = Sweep(ctx, sc)
+    sw = Sweep(ctx, sc, window_sums=True)
     sw.u.copy_(torch.from_numpy(ub).to(dev).expand(n_temps, n_walkers, -1, -1, -1))
     gen = torch.Generator(device=dev)
     gen.manual_seed(38)

@@ -376,6 +376,16 @@ typedef struct {
    * swaps of rungs (t-1, t) since the last adaptation (tempering adds to it,
    * the adaptation clears it); must start at zero. */
   int32_t* swap_acc;
+  /* Optional (NULL: the tempering pass rebuilds every set's templates):
+   * [n_temps][n_walkers][n_bands][2][3N] complex doubles, the sum of each
+   * source set's templates over its band's window [k_band0 + (b-1)N,
+   * k_band0 + (b+2)N) (A then E; zero outside the analysis band).  Every band
+   * pass (moves 0 and 1) writes the entries of its parity; the tempering pass
+   * of that parity reads them instead of rebuilding the templates and moves
+   * them with the source sets it swaps, so they stay valid until the sets
+   * change.  Write it with a band pass of each parity before the first
+   * tempering pass.  Results do not depend on it beyond FP64 rounding order. */
+  double* window_sums;
 } gbl_sweep_state;
 
 typedef struct gbl_graph gbl_graph;

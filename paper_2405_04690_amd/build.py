@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC_DIR = os.path.join(HERE, "csrc")
 LIB_PATH = os.path.join(HERE, "libgbl.so")
 SOURCES = ["gbl.hip"]
-HEADERS = ["gbl_device.hpp", "gbl_kernels.hpp", "gbl_sampler.hpp", "gbl_flow.hpp"]
+HEADERS = ["gbl_device.hpp", "gbl_kernels.hpp", "gbl_sampler.hpp", "gbl_flow.hpp", "gbl_search.hpp", "gbl_matrix.hpp"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

@@ -875,6 +875,7 @@ static gbl::SweepArgs sweep_args(const gbl_sweep_config* c, const gbl_sweep_stat
   a.spec_pool = (cd*)st->spec_pool;
   a.pool_flags = st->pool_flags;
   a.pool_size = st->pool_size;
+  a.wsum = (cd*)st->window_sums;
   return a;
 }
 

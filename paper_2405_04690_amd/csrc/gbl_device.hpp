@@ -36,8 +36,11 @@ constexpr double kInvSqrt6 = 0.40824829046386301637;
 
 // Complex numbers in the response precision F (double, or float in the mixed
 // mode).  Phases, their reduction and every likelihood sum stay in double.
+// Aligned to their size, so that a value moves in one 16-byte (8-byte) LDS
+// access: the LDS layouts are laid out against bank conflicts of whole-value
+// accesses, and a value split into two 8-byte halves would conflict.
 template <typename F>
-struct cx {
+struct alignas(2 * sizeof(F)) cx {
   F re, im;
 };
 using cd = cx<double>;
@@ -298,9 +301,11 @@ __device__ __forceinline__ void decode_source(const double* __restrict__ prm, co
 // for every frequency in the analysis band (u < pi f (2L/c)): Taylor series in
 // v = u^2 by Horner's rule, truncated where the next term is below 5e-18 for
 // |u| <= 1.7 (f up to ~32 mHz).  Larger |u| (sources far above the band)
-// falls back to the library sincos.
+// falls back to the library sincos.  Not inlined: the lockstep version below
+// calls it only for sources far above the band, and its constants would
+// otherwise be materialised (or hoisted out of loops) in every caller.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void sinc_cos(double u, double& sinc, double& cosu) {
+__device__ __noinline__ void sinc_cos(double u, double& sinc, double& cosu) {
   double v = u * u;
   if (v <= 2.89) {
     double s = -1.0 / 51090942171709440000.0;   // -1/21!
@@ -337,29 +342,51 @@ __device__ __forceinline__ void sinc_cos(double u, double& sinc, double& cosu) {
   }
 }
 
-// The same Taylor polynomials evaluated for K arguments in lockstep: each
-// coefficient is materialised once per step and reused K times (gfx9-class
-// VALU encodings take no 64-bit literal, so a lone Horner step costs two
-// register moves besides its FMA).  The float versions (mixed precision) use
-// the shortest truncations whose next term is below 2.5e-10 on the same
-// ranges.
+// FP64 coefficients of the Taylor series below (1/n! with alternating signs),
+// kept in the constant address space and read through a pointer that an empty
+// asm statement makes opaque at every use.  The Horner steps then take them
+// from scalar registers (scalar loads, hits in the scalar cache): gfx9-class
+// VALU encodings take no 64-bit literal, so a coefficient written in the code
+// costs two vector moves per use, or a pair of vector registers held for the
+// whole kernel when the compiler hoists it out of a loop.
+struct PolyTable {
+  double sinc[10];  // sin(u)/u:  -1/21!, +1/19!, ..., +1/3!  (Horner order, v = u^2)
+  double cosu[13];  // cos(u):    +1/24!, -1/22!, ..., -1/2!, 1
+  double osin[7];   // octant sin(x)/x - 1 over x^2: -1/15!, ..., -1/3!
+  double ocos[9];   // octant cos(x): +1/16!, ..., -1/2!, 1
+};
+
+__constant__ PolyTable kPolyTable = {
+    {-1.0 / 51090942171709440000.0, 1.0 / 121645100408832000.0, -1.0 / 355687428096000.0, 1.0 / 1307674368000.0,
+     -1.0 / 6227020800.0, 1.0 / 39916800.0, -1.0 / 362880.0, 1.0 / 5040.0, -1.0 / 120.0, 1.0 / 6.0},
+    {1.0 / 620448401733239439360000.0, -1.0 / 1124000727777607680000.0, 1.0 / 2432902008176640000.0,
+     -1.0 / 6402373705728000.0, 1.0 / 20922789888000.0, -1.0 / 87178291200.0, 1.0 / 479001600.0,
+     -1.0 / 3628800.0, 1.0 / 40320.0, -1.0 / 720.0, 1.0 / 24.0, -0.5, 1.0},
+    {-1.0 / 1307674368000.0, 1.0 / 6227020800.0, -1.0 / 39916800.0, 1.0 / 362880.0, -1.0 / 5040.0, 1.0 / 120.0,
+     -1.0 / 6.0},
+    {1.0 / 20922789888000.0, -1.0 / 87178291200.0, 1.0 / 479001600.0, -1.0 / 3628800.0, 1.0 / 40320.0,
+     -1.0 / 720.0, 1.0 / 24.0, -0.5, 1.0}};
+
+using CPoly = const __attribute__((address_space(4))) PolyTable;
+
+__device__ __forceinline__ CPoly* poly_table() {
+  CPoly* p = (CPoly*)&kPolyTable;
+  asm volatile("" : "+s"(p));
+  return p;
+}
+
+// The same Taylor polynomials evaluated for K arguments in lockstep, each
+// coefficient read once per step and reused K times.  The float versions
+// (mixed precision) use the shortest truncations whose next term is below
+// 2.5e-10 on the same ranges.
 // UC = 1: any |u| in band (above, with the library fallback); UC = 0: the
 // caller guarantees |u| <= 0.25 (templates below ~4.7 mHz), where sinc through
 // u^10 and cos through u^12 leave next terms below 1e-17 (u^12/13!, u^14/14!).
 template <int K, int UC = 1>
 __device__ __forceinline__ void sinc_cos_k(const double* u, double* sinc, double* cosu) {
-  constexpr double cs_[10] = {-1.0 / 51090942171709440000.0, 1.0 / 121645100408832000.0,
-                              -1.0 / 355687428096000.0,      1.0 / 1307674368000.0,
-                              -1.0 / 6227020800.0,           1.0 / 39916800.0,
-                              -1.0 / 362880.0,               1.0 / 5040.0,
-                              -1.0 / 120.0,                  1.0 / 6.0};
-  constexpr double cc_[13] = {1.0 / 620448401733239439360000.0, -1.0 / 1124000727777607680000.0,
-                              1.0 / 2432902008176640000.0,      -1.0 / 6402373705728000.0,
-                              1.0 / 20922789888000.0,           -1.0 / 87178291200.0,
-                              1.0 / 479001600.0,                -1.0 / 3628800.0,
-                              1.0 / 40320.0,                    -1.0 / 720.0,
-                              1.0 / 24.0,                       -0.5,
-                              1.0};
+  CPoly* const tp = poly_table();
+  const auto& cs_ = tp->sinc;
+  const auto& cc_ = tp->cosu;
   constexpr int S0 = UC == 0 ? 5 : 0;  // first sinc coefficient used
   constexpr int C0 = UC == 0 ? 6 : 0;  // first cos coefficient used
   double v[K], a[K], c[K];
@@ -443,12 +470,7 @@ template <typename F>
 struct OctantPoly;
 template <>
 struct OctantPoly<double> {
-  static constexpr int NS = 7, NC = 9;
-  static constexpr double ps[NS] = {-1.0 / 1307674368000.0, 1.0 / 6227020800.0, -1.0 / 39916800.0, 1.0 / 362880.0,
-                                    -1.0 / 5040.0,          1.0 / 120.0,        -1.0 / 6.0};
-  static constexpr double pc[NC] = {1.0 / 20922789888000.0, -1.0 / 87178291200.0, 1.0 / 479001600.0,
-                                    -1.0 / 3628800.0,       1.0 / 40320.0,        -1.0 / 720.0,
-                                    1.0 / 24.0,             -0.5,                 1.0};
+  static constexpr int NS = 7, NC = 9;  // coefficients: PolyTable::osin, PolyTable::ocos
 };
 template <>
 struct OctantPoly<float> {
@@ -463,6 +485,11 @@ struct OctantPoly<float> {
 template <int K, typename F>
 __device__ __forceinline__ void expi_cycles_k(const double* c, cx<F>* out) {
   using P = OctantPoly<F>;
+  // FP64: the coefficients from the constant table (the same values)
+  constexpr bool kTbl = std::is_same<F, double>::value;
+  CPoly* const tp = kTbl ? poly_table() : nullptr;
+  auto ps = [&](int k) -> F { if constexpr (kTbl) return tp->osin[k]; else return P::ps[k]; };
+  auto pc = [&](int k) -> F { if constexpr (kTbl) return tp->ocos[k]; else return P::pc[k]; };
   F x[K], v[K], sn[K], cs[K];
   int q[K];
 #pragma unroll
@@ -472,18 +499,18 @@ __device__ __forceinline__ void expi_cycles_k(const double* c, cx<F>* out) {
     x[i] = (F)(kTwoPi * (r - 0.25 * n4));
     v[i] = x[i] * x[i];
     q[i] = ((int)n4) & 3;
-    sn[i] = P::ps[0];
-    cs[i] = P::pc[0];
+    sn[i] = ps(0);
+    cs[i] = pc(0);
   }
 #pragma unroll
   for (int k = 1; k < P::NS; k++) {
 #pragma unroll
-    for (int i = 0; i < K; i++) sn[i] = sn[i] * v[i] + P::ps[k];
+    for (int i = 0; i < K; i++) sn[i] = sn[i] * v[i] + ps(k);
   }
 #pragma unroll
   for (int k = 1; k < P::NC; k++) {
 #pragma unroll
-    for (int i = 0; i < K; i++) cs[i] = cs[i] * v[i] + P::pc[k];
+    for (int i = 0; i < K; i++) cs[i] = cs[i] * v[i] + pc(k);
   }
 #pragma unroll
   for (int i = 0; i < K; i++) {

@@ -79,7 +79,14 @@ struct SweepArgs {
   cd* spec_pool;          // optional pool of per-slot spectra, pool_size entries of n_slot x 2N
   int32_t* pool_flags;    // [pool_size], 0 = free
   int pool_size;
+  cd* wsum;               // optional [n_t][n_w][n_b][2][3N] window sums of the source sets
 };
+
+// window-sum entry of source set (t, w) in band b
+template <int N>
+__device__ __forceinline__ cd* wsum_entry(const SweepArgs& a, int t, int w, int b) {
+  return a.wsum + (((int64_t)t * a.n_w + w) * a.n_b + b) * 6 * N;
+}
 
 __device__ __forceinline__ int64_t uidx(const SweepArgs& a, int t, int w, int b, int s) {
   return (((int64_t)t * a.n_w + w) * a.n_b + b) * a.n_slot + s;
@@ -89,8 +96,17 @@ __device__ __forceinline__ double period_of(int i) {
   return i == 3 ? kTwoPi : i == 5 ? kPi : i == 6 ? kTwoPi : 0.0;
 }
 
+// x reduced into [0, P).  The remainder is fmod's (exact); for |x| < 2P it
+// is formed directly: x itself for |x| < P, and x - P (exact, Sterbenz) for
+// P <= x < 2P, which covers every use in the moves.
 __device__ __forceinline__ double wrap_p(double x, double P) {
-  double y = fmod(x, P);
+  double y;
+  if (fabs(x) < P)
+    y = x;
+  else if (x >= P && x < 2.0 * P)
+    y = x - P;
+  else
+    y = fmod(x, P);
   return y < 0 ? y + P : y;
 }
 
@@ -129,32 +145,23 @@ __device__ __forceinline__ bool in_prior(const Geo& g, const SweepArgs& a, int b
   return true;
 }
 
-// LDS of one band loop
+// LDS of the tempering kernel's band likelihoods
 template <int N>
 struct BandSmem {
   cd win[2][3 * N];         // residual window r' (channels A, E)
   double wts[2][3 * N];     // 1/S over the window (0 outside the analysis band)
   cd buf[4 * series_pitch<N>()];
-  cd rwin[2 * N];           // spectrum of the template being removed
   double red[2 * (block_threads<N>() / kWave)];
-  double u_old[8], u_new[8], prm[8];
+  double prm[8];
   Src src;
-  double su[kMaxSlots][8];  // the band's slot coordinates during the loop
   int32_t ex[kMaxSlots];
-  int32_t order[kMaxSlots];  // RJ: the slots' flip order; in-model: the occupied slots
-  int32_t draw[kMaxSlots];   // the slot-order draws of the reversible-jump pass
-  double rdraw[kMaxSlots][9];  // RJ, per flip: acceptance draw, prior birth's coordinates;
-                               // in-model, per proposal: its four draws
-  int n_occ;                 // in-model: number of occupied slots
-  int64_t sq[kMaxSlots];    // carrier bin of each slot's cached spectrum
   int entry;                // spectrum pool entry held by the block (-1: none)
 };
 
 // Build the template of sampling coordinates u (shared) into the FFT workspace;
 // sm.src holds its decode afterwards.  Block-uniform; contains barriers.
-// Not inlined: the band loops call it from several places, and one shared
-// body keeps the kernels' register allocation at two waves per SIMD (measured
-// 1.6x faster sweeps than the inlined copies at one wave per SIMD).
+// Not inlined: the tempering kernel calls it from several places, and one
+// shared body keeps its register allocation at two waves per SIMD.
 template <int N>
 __device__ __noinline__ void band_template(const Geo& g, const WaveTables<double>& tb, const double* u,
                                            BandSmem<N>& sm) {
@@ -245,94 +252,6 @@ __device__ __forceinline__ void band_add_template(const Geo& g, const WaveTables
   __syncthreads();
 }
 
-// same for the spectrum held in sm.rwin (start bin kr)
-template <int N>
-__device__ __forceinline__ void band_add_rwin(const Geo& g, BandSmem<N>& sm, int64_t k0w, int64_t kr, double s,
-                                              cd* global_buf) {
-  constexpr int NT = block_threads<N>();
-  for (int j = threadIdx.x; j < N; j += NT) {
-    int64_t i = kr + j - k0w;
-    if (i < 0 || i >= 3 * N) continue;
-#pragma unroll
-    for (int c = 0; c < 2; c++) {
-      cd v = sm.rwin[c * N + j];
-      sm.win[c][i] = sm.win[c][i] + cd{s * v.re, s * v.im};
-      if (global_buf) {
-        int64_t k = k0w + i - g.k_min;
-        if (k >= 0 && k < g.n_bins) {
-          double* dst = reinterpret_cast<double*>(global_buf + c * g.n_bins + k);
-          atomicAdd(dst, s * v.re);
-          atomicAdd(dst + 1, s * v.im);
-        }
-      }
-    }
-  }
-  __syncthreads();
-}
-
-// dlnL = 4 df [<R|d> - 1/2 <d|d>], d = a - r, R = window; a = template in the
-// FFT workspace (if has_a), r = sm.rwin (if has_r).  Block-uniform result.
-template <int N>
-__device__ __forceinline__ double band_dlogl(const Geo& g, const WaveTables<double>& tb, BandSmem<N>& sm,
-                                             int64_t k0w, bool has_a, int64_t ka, bool has_r, int64_t kr) {
-  constexpr int NT = block_threads<N>();
-  double rd = 0.0, dd = 0.0;
-  auto acc = [&](int64_t i, cd d0, cd d1) {
-    if (i < 0 || i >= 3 * N) return;
-    double w0 = sm.wts[0][i], w1 = sm.wts[1][i];
-    cd R0 = sm.win[0][i], R1 = sm.win[1][i];
-    rd += (R0.re * d0.re + R0.im * d0.im) * w0 + (R1.re * d1.re + R1.im * d1.im) * w1;
-    dd += (d0.re * d0.re + d0.im * d0.im) * w0 + (d1.re * d1.re + d1.im * d1.im) * w1;
-  };
-  if (has_a) {
-    for (int j = threadIdx.x; j < N; j += NT) {
-      cd v[2];
-      bin_spectrum<N, 2, double>(sm.src, g, tb, sm.buf, j, v);
-      int64_t k = ka + j;
-      int64_t jr = k - kr;
-      if (has_r && jr >= 0 && jr < N) {
-        v[0] = v[0] - sm.rwin[jr];
-        v[1] = v[1] - sm.rwin[N + jr];
-      }
-      acc(k - k0w, v[0], v[1]);
-    }
-  }
-  if (has_r) {
-    for (int j = threadIdx.x; j < N; j += NT) {
-      int64_t k = kr + j;
-      if (has_a && k >= ka && k < ka + N) continue;
-      cd r0 = sm.rwin[j], r1 = sm.rwin[N + j];
-      acc(k - k0w, cd{-r0.re, -r0.im}, cd{-r1.re, -r1.im});
-    }
-  }
-  double sums[2] = {rd, dd};
-  block_allsum<NT>(sums, sm.red);
-  rd = sums[0];
-  dd = sums[1];
-  return g.df4 * rd - 0.5 * g.df4 * dd;
-}
-
-// spectrum of the template in the workspace into sm.rwin
-template <int N>
-__device__ __forceinline__ void band_store_rwin(const Geo& g, const WaveTables<double>& tb, BandSmem<N>& sm) {
-  constexpr int NT = block_threads<N>();
-  for (int j = threadIdx.x; j < N; j += NT) {
-    cd v[2];
-    bin_spectrum<N, 2, double>(sm.src, g, tb, sm.buf, j, v);
-    sm.rwin[j] = v[0];
-    sm.rwin[N + j] = v[1];
-  }
-  __syncthreads();
-}
-
-// a cached spectrum into sm.rwin
-template <int N>
-__device__ __forceinline__ void band_load_rwin(BandSmem<N>& sm, const cd* spec) {
-  constexpr int NT = block_threads<N>();
-  for (int j = threadIdx.x; j < 2 * N; j += NT) sm.rwin[j] = spec[j];
-  __syncthreads();
-}
-
 // load walker w's window from the opposite-parity buffer, and its weights
 template <int N>
 __device__ __forceinline__ void band_load_window(const Geo& g, const SweepArgs& a, int w, int b, int64_t k0w,
@@ -375,257 +294,615 @@ __device__ __forceinline__ int pool_acquire(const SweepArgs& a) {
 // ---------------------------------------------------------------------------
 // Alg. gb1 for every (t, w, b) of one parity: in-model group-stretch moves
 // (move 0) or the reversible-jump pass that flips every slot (move 1).
+//
+// The loop body builds at most one template per pass, so that the template
+// build has a single call site and is inlined once; with the residual window
+// as the only large LDS array the kernel holds three blocks per CU at
+// N = 256 (below 168 VGPRs and 54 KB of LDS).  The spectra of the template
+// being added (a) and removed (r) stay in registers at the bins each thread
+// owns (j = tid + NT m); r goes through the FFT workspace only for the bins
+// of a's window that need it at another offset.  The weights 1/S come from
+// HBM, fetched while the template is built.
 // ---------------------------------------------------------------------------
 template <int N>
-__global__ __launch_bounds__(block_threads<N>()) void k_sweep_band(Geo g, WaveTables<double> tb, SweepArgs a,
-                                                                   int move, int parity) {
-  __shared__ BandSmem<N> sm;
+struct LoopSmem {
+  cd win[2][3 * N];               // residual window r' (channels A, E)
+  cd buf[4 * series_pitch<N>()];  // FFT workspace; afterwards r's spectrum (A at [0, N), E at [N, 2N))
+  double su[kMaxSlots][8];        // the band's slot coordinates during the loop
+  double rdraw[kMaxSlots][9];     // RJ, per flip: acceptance draw, prior birth's coordinates;
+                                  // in-model, per proposal: its four draws
+  double red[2 * (block_threads<N>() / kWave)];
+  double u_old[8], u_new[8], prm[8];
+  double blo[8], bhi[8];      // the band's prior box in sampling coordinates (f0: the band's range,
+                              // angles: one period)
+  Src src;
+  int64_t sq[kMaxSlots];      // carrier bin of each slot's cached spectrum
+  int32_t ex[kMaxSlots];
+  int32_t order[kMaxSlots];   // RJ: the slots' flip order; in-model: the occupied slots
+  int32_t draw[kMaxSlots];    // the slot-order draws of the reversible-jump pass
+  int32_t fstart[kMaxSlots];  // in-model: first friend of each occupied slot's window in the group
+  int n_occ;                  // in-model: number of occupied slots
+  int entry;                  // spectrum pool entry held by the block (-1: none)
+};
+
+// u inside the band's prior box (kept in LDS rather than in registers across
+// the band loop); the same tests as in_prior
+template <int N>
+__device__ __forceinline__ bool loop_in_prior(const LoopSmem<N>& sm, const double* u) {
+  if (!(u[1] >= sm.blo[1] && u[1] < sm.bhi[1])) return false;
+#pragma unroll
+  for (int i = 0; i < 8; i++) {
+    if (i == 1 || period_of(i) > 0) continue;
+    if (!(u[i] >= sm.blo[i] && u[i] <= sm.bhi[i])) return false;
+  }
+  return true;
+}
+
+// natural logarithm, not inlined: inside the band loop the library
+// function's constants would be hoisted out of the loop and held in vector
+// registers across it
+__device__ __noinline__ double log_ni(double x) { return log(x); }
+
+// first friend of key f in the band's group (G entries sorted by f0, the key
+// at word 1 of each): the lower bound of f by a 64-way search of the calling
+// wave (every lane takes part: lane l tests the key at lo + l n / 64, and the
+// ballot, a prefix since the keys are sorted, narrows [lo, hi] 64-fold per
+// step), then the start of the nf entries around it
+__device__ __forceinline__ int friend_start(const double* __restrict__ grp, int G, int nf, double f) {
+  int lo = 0, hi = G;
+  const int lane = threadIdx.x & (kWave - 1);
+  while (lo < hi) {
+    const int n = hi - lo;
+    const int pl = n >= kWave ? lo + (int)(((int64_t)lane * n) / kWave) : lo + lane;
+    const bool less = (n >= kWave || lane < n) && grp[8 * (int64_t)pl + 1] < f;
+    const int c = __popcll(__ballot(less));
+    if (n < kWave) {
+      lo += c;
+      break;
+    }
+    if (c == 0) break;  // key[lo] >= f
+    const int lo2 = lo + (int)(((int64_t)(c - 1) * n) / kWave) + 1;
+    hi = c < kWave ? lo + (int)(((int64_t)c * n) / kWave) : hi;
+    lo = lo2;
+  }
+  int start = lo - nf / 2;
+  if (start < 0) start = 0;
+  if (start > G - nf) start = G - nf;
+  return start;
+}
+
+// weights 1/S (0 outside the analysis band) at the thread's bins k0 + j
+template <int N, int BPT>
+__device__ __forceinline__ void loop_weights(const Geo& g, const double* __restrict__ wts, int64_t k0,
+                                             double (&wh)[BPT][2], int tid) {
+  constexpr int NT = block_threads<N>();
+#pragma unroll
+  for (int m = 0; m < BPT; m++) {
+    const int64_t k = k0 + tid + NT * m - g.k_min;
+    const bool in = k >= 0 && k < g.n_bins;
+    wh[m][0] = in ? wts[k] : 0.0;
+    wh[m][1] = in ? wts[g.n_bins + k] : 0.0;
+  }
+}
+
+// sampling coordinates u (LDS) -> physical parameters -> decode in sm.src.
+// Not inlined: the library functions' constants would otherwise be hoisted
+// out of the band loop and held in vector registers across it.
+// Block-uniform; contains barriers.
+template <int N>
+__device__ __noinline__ void loop_decode(const Geo& g, const double* u, LoopSmem<N>& sm) {
+  constexpr int NT = block_threads<N>();
+  static_assert(NT >= kWave, "band loops use whole waves");
+  const int tid = threadIdx.x;
+  // sampling -> physical coordinates: the three transcendental maps on lane 0
+  // of different waves, so that they run side by side
+  if ((tid & (kWave - 1)) == 0) {
+    for (int r = tid / kWave; r < 4; r += NT / kWave) {
+      if (r == 0) {
+        sm.prm[0] = exp10(u[0]);
+      } else if (r == 1) {
+        sm.prm[4] = acos(u[4]);
+      } else if (r == 2) {
+        sm.prm[7] = asin(u[7]);
+      } else {
+        sm.prm[1] = u[1];
+        sm.prm[2] = u[2];
+        sm.prm[3] = u[3];
+        sm.prm[5] = u[5];
+        sm.prm[6] = u[6];
+      }
+    }
+  }
+  __syncthreads();
+  if (tid < kWave) decode_sources<1>(sm.prm, sm.prm, g, &sm.src);
+  __syncthreads();
+}
+
+// sampling coordinates u (LDS) -> template in sm.buf, its decode in sm.src;
+// with wts, also the weights at the thread's bins of the template's window,
+// requested before the response and the FFT so that their latency hides
+// behind them.  Block-uniform; contains barriers.
+template <int N, int BPT>
+__device__ __forceinline__ void loop_build(const Geo& g, const WaveTables<double>& tb, const double* u,
+                                           LoopSmem<N>& sm, const double* __restrict__ wts, double (&wh)[BPT][2],
+                                           int tid) {
+  loop_decode<N>(g, u, sm);
+  if (wts) loop_weights<N, BPT>(g, wts, sm.src.q - N / 2, wh, tid);
+  template_transform<N, 4, double>(sm.src, g, tb, sm.buf, tid);
+}
+
+// spectrum of the built template at the thread's bins
+template <int N, int BPT>
+__device__ __forceinline__ void loop_bins(const Geo& g, const WaveTables<double>& tb, const LoopSmem<N>& sm,
+                                          cd (&h)[BPT][2], int tid) {
+  constexpr int NT = block_threads<N>();
+#pragma unroll
+  for (int m = 0; m < BPT; m++) bin_spectrum<N, 2, double>(sm.src, g, tb, sm.buf, tid + NT * m, h[m]);
+}
+
+// a spectrum (all N bins, A then E) to or from a pool slot
+template <int N, int BPT>
+__device__ __forceinline__ void loop_store(cd* dst, const cd (&h)[BPT][2], int tid) {
+  constexpr int NT = block_threads<N>();
+#pragma unroll
+  for (int m = 0; m < BPT; m++) {
+    const int j = tid + NT * m;
+    dst[j] = h[m][0];
+    dst[N + j] = h[m][1];
+  }
+}
+
+template <int N, int BPT>
+__device__ __forceinline__ void loop_load(const cd* src, cd (&h)[BPT][2], int tid) {
+  constexpr int NT = block_threads<N>();
+#pragma unroll
+  for (int m = 0; m < BPT; m++) {
+    const int j = tid + NT * m;
+    h[m][0] = src[j];
+    h[m][1] = src[N + j];
+  }
+}
+
+// window += s h at the bins k0 + j inside it; with own, the same change also
+// goes (atomically) to that cold-chain buffer.  No closing barrier.
+template <int N, int BPT>
+__device__ __forceinline__ void loop_add(const Geo& g, LoopSmem<N>& sm, int64_t k0w, int64_t k0, double s,
+                                         const cd (&h)[BPT][2], cd* own, int tid) {
+  constexpr int NT = block_threads<N>();
+#pragma unroll
+  for (int m = 0; m < BPT; m++) {
+    const int64_t i = k0 + tid + NT * m - k0w;
+    if (i < 0 || i >= 3 * N) continue;
+#pragma unroll
+    for (int c = 0; c < 2; c++) {
+      sm.win[c][i] = sm.win[c][i] + cd{s * h[m][c].re, s * h[m][c].im};
+      if (own) {
+        const int64_t k = k0w + i - g.k_min;
+        if (k >= 0 && k < g.n_bins) {
+          double* dst = reinterpret_cast<double*>(own + c * g.n_bins + k);
+          atomicAdd(dst, s * h[m][c].re);
+          atomicAdd(dst + 1, s * h[m][c].im);
+        }
+      }
+    }
+  }
+}
+
+// dlnL = 4 df [<R|d> - 1/2 <d|d>], d = a - r, R = window, from the spectra at
+// the thread's bins: a (if has_a) at ka + j with weights wa, r (if has_r) at
+// kr + j with weights wr; with both, r's spectrum must also sit in sm.buf.
+// Block-uniform result.
+template <int N, int BPT>
+__device__ __forceinline__ double loop_dlogl(const Geo& g, LoopSmem<N>& sm, int64_t k0w, bool has_a, int64_t ka,
+                                             const cd (&av)[BPT][2], const double (&wa)[BPT][2], bool has_r,
+                                             int64_t kr, const cd (&rv)[BPT][2], const double (&wr)[BPT][2],
+                                             int tid) {
+  constexpr int NT = block_threads<N>();
+  double rd = 0.0, dd = 0.0;
+  auto acc = [&](int64_t i, cd d0, cd d1, double w0, double w1) {
+    if (i < 0 || i >= 3 * N) return;
+    const cd R0 = sm.win[0][i], R1 = sm.win[1][i];
+    rd += (R0.re * d0.re + R0.im * d0.im) * w0 + (R1.re * d1.re + R1.im * d1.im) * w1;
+    dd += (d0.re * d0.re + d0.im * d0.im) * w0 + (d1.re * d1.re + d1.im * d1.im) * w1;
+  };
+  if (has_a) {
+#pragma unroll
+    for (int m = 0; m < BPT; m++) {
+      const int64_t k = ka + tid + NT * m;
+      cd v0 = av[m][0], v1 = av[m][1];
+      const int64_t jr = k - kr;
+      if (has_r && jr >= 0 && jr < N) {
+        v0 = v0 - sm.buf[jr];
+        v1 = v1 - sm.buf[N + jr];
+      }
+      acc(k - k0w, v0, v1, wa[m][0], wa[m][1]);
+    }
+  }
+  if (has_r) {
+#pragma unroll
+    for (int m = 0; m < BPT; m++) {
+      const int64_t k = kr + tid + NT * m;
+      if (has_a && k >= ka && k < ka + N) continue;
+      acc(k - k0w, cd{-rv[m][0].re, -rv[m][0].im}, cd{-rv[m][1].re, -rv[m][1].im}, wr[m][0], wr[m][1]);
+    }
+  }
+  double sums[2] = {rd, dd};
+  block_allsum<NT>(sums, sm.red);
+  return g.df4 * sums[0] - 0.5 * g.df4 * sums[1];
+}
+
+template <int N>
+__global__ __launch_bounds__(block_threads<N>(), 3) void k_sweep_band(Geo g, WaveTables<double> tb, SweepArgs a,
+                                                                      int move, int parity) {
+  constexpr int NT = block_threads<N>();
+  constexpr int BPT = N / NT;  // window bins per thread
+  __shared__ LoopSmem<N> sm;
   const int nbp = (a.n_b - parity + 1) / 2;  // bands of this parity
   const int bi = blockIdx.x % nbp;
   const int tw = blockIdx.x / nbp;
   const int w = tw % a.n_w;
   const int t = tw / a.n_w;
   const int b = parity + 2 * bi;
-  const int tid = threadIdx.x;
+  int tid = threadIdx.x;
   const int S = a.n_slot;
   const int64_t sweep = *a.sweep_ctr;
   const int64_t k0w = a.k_band0 + (int64_t)(b - 1) * N;
   const double beta = a.betas[(int64_t)b * a.n_t + t];
   const uint64_t unit = ((uint64_t)t * a.n_w + w) * a.n_b + b;
   cd* own = (t == 0) ? a.resid + ((int64_t)(b & 1) * a.n_w + w) * 2 * g.n_bins : nullptr;
+  const double* wts = a.inv_psd + (int64_t)w * 2 * g.n_bins;
+  const bool inmodel = move == kMoveInModel;
 
-  band_load_window<N>(g, a, w, b, k0w, sm);
-  for (int s = tid; s < S; s += block_threads<N>()) {
+  // walker w's window from the opposite-parity buffer, the band's slots and a
+  // pool entry for the slots' spectra (a bounded scan; without one the
+  // spectra are recomputed)
+  {
+    const cd* opp = a.resid + ((int64_t)(1 - (b & 1)) * a.n_w + w) * 2 * g.n_bins;
+    for (int i = tid; i < 3 * N; i += NT) {
+      const int64_t k = k0w + i - g.k_min;
+      const bool inb = k >= 0 && k < g.n_bins;
+#pragma unroll
+      for (int c = 0; c < 2; c++) sm.win[c][i] = inb ? opp[c * g.n_bins + k] : cd{0.0, 0.0};
+    }
+  }
+  for (int s = tid; s < S; s += NT) {
     sm.ex[s] = a.exists[uidx(a, t, w, b, s)];
     for (int k = 0; k < 8; k++) sm.su[s][k] = a.u[8 * uidx(a, t, w, b, s) + k];
   }
-  // a pool entry for the slots' spectra (a bounded scan; without one the
-  // spectra are recomputed)
   if (tid == 0) sm.entry = pool_acquire(a);
-  __syncthreads();
-  cd* const spec = sm.entry >= 0 ? a.spec_pool + (int64_t)sm.entry * pool_entry(S, a.n_t, N) : nullptr;
-  // the band's residual: remove its current sources (keeping their spectra)
-  for (int s = 0; s < S; s++) {
-    if (!sm.ex[s]) continue;
-    band_template<N>(g, tb, sm.su[s], sm);
-    band_add_template<N>(g, tb, sm, k0w, -1.0, nullptr, spec ? spec + (int64_t)s * 2 * N : nullptr);
-    if (tid == 0) sm.sq[s] = sm.src.q;
+  if (tid < 8) {
+    const int k = tid;
+    double lo = a.lo[k], hi = a.hi[k];
+    if (k == 1) {
+      band_f0_range<N>(g, a, b, lo, hi);
+    } else if (period_of(k) > 0) {
+      lo = 0.0;
+      hi = period_of(k);
+    }
+    sm.blo[k] = lo;
+    sm.bhi[k] = hi;
   }
   __syncthreads();
+  cd* const spec = sm.entry >= 0 ? a.spec_pool + (int64_t)sm.entry * pool_entry(S, a.n_t, N) : nullptr;
 
+  const double* grp = a.group + (int64_t)b * a.n_w * S * 8;
+  const int G = a.group_count[b];
+  const int nf = a.n_friends < G ? a.n_friends : G;
+  const double lvol = (!inmodel && a.prop_u) ? log_box_volume<N>(g, a, b) : 0.0;
+
+  // spectra and weights at the thread's bins: a (being added), r (being
+  // removed) and the template just built; each is written before it is read
+  cd av[BPT][2], rv[BPT][2], hv[BPT][2];
+  double wa[BPT][2], wr[BPT][2], wh[BPT][2];
+  int64_t ka = 0, kr = 0;
   unsigned long long n_prop = 0, n_acc = 0, n_bprop = 0, n_bacc = 0, n_dprop = 0, n_dacc = 0;
-  if (move == kMoveInModel) {
-    const double* grp = a.group + (int64_t)b * a.n_w * S * 8;
-    const int G = a.group_count[b];
-    // the occupied slots in slot order (in-model moves keep the occupancy)
-    if (tid == 0) {
-      int c = 0;
-      for (int s = 0; s < S; s++)
-        if (sm.ex[s]) sm.order[c++] = s;
-      sm.n_occ = c;
+
+  // the reversible-jump death of slot s, r's spectrum in rv (start kr,
+  // weights wr); lra = ln of the acceptance draw
+  auto death = [&](int s, double lra) {
+    const double dl = loop_dlogl<N, BPT>(g, sm, k0w, false, 0, av, wa, true, kr, rv, wr, tid);
+    const double lpq = a.prop_u ? a.rj_logq[uidx(a, t, w, b, s)] + lvol : 0.0;
+    if (lra < beta * dl + lpq) {
+      loop_add<N, BPT>(g, sm, k0w, kr, 1.0, rv, own, tid);
+      if (tid == 0) sm.ex[s] = 0;
+      n_dacc++;
     }
     __syncthreads();
-    const int gcount = sm.n_occ;
-    for (int p = 0; p < a.n_prop; p++) {
-      if ((p & (kMaxSlots - 1)) == 0) {
-        // the next kMaxSlots proposals' four draws (words 8 p + k), one per
-        // thread, into the RJ draw rows (free during in-model moves)
-        const int pe = a.n_prop - p < kMaxSlots ? a.n_prop - p : kMaxSlots;
-        __syncthreads();
-        for (int q = tid; q < 4 * pe; q += block_threads<N>())
-          sm.rdraw[q >> 2][q & 3] = rng_uniform(a.seed, sweep, move, unit, 8 * (uint64_t)(p + (q >> 2)) + (q & 3));
-        __syncthreads();
-      }
-      const double* rp = sm.rdraw[p & (kMaxSlots - 1)];
-      const double r_pick = rp[0], r_friend = rp[1], r_z = rp[2], r_acc = rp[3];
-      if (gcount == 0) continue;
-      const int sk = sm.order[(int)floor(r_pick * gcount)];
-      const double* uk = sm.su[sk];
-      n_prop++;
-      if (G <= 0) continue;
-      // friend: the n_friends sorted group entries around the current f0.
-      // Lower bound of f0 among the group keys by a 64-way search of each
-      // wave: lane l tests the key at lo + l n / 64, and the ballot (a prefix,
-      // the keys being sorted) narrows [lo, hi] 64-fold per step.
-      int lo = 0, hi = G;
-      {
-        const int lane = tid & (kWave - 1);
-        while (lo < hi) {
-          const int n = hi - lo;
-          const int pl = n >= kWave ? lo + (int)(((int64_t)lane * n) / kWave) : lo + lane;
-          const bool less = (n >= kWave || lane < n) && grp[8 * (int64_t)pl + 1] < uk[1];
-          const int c = __popcll(__ballot(less));
-          if (n < kWave) {
-            lo += c;
-            break;
+  };
+
+  // Block-uniform control: every thread runs the same plan on the same LDS
+  // values.  phase 0 removes the band's sources (one build per occupied
+  // slot), phase 1 runs the moves, phase 2 ends.  A move builds the removed
+  // template first when there is no pool entry (pend then marks it built).
+  enum { kSetup = 0, kOld = 1, kNew = 2 };
+  int phase = 0, cur = 0, sk = 0;
+  bool pend = false;
+  double lr_acc = 0.0, lr = 0.0;  // ln of the acceptance draw; in-model: ln z^7
+  for (;;) {
+    // The thread index and the table pointers pass through an empty asm
+    // statement at the top of every pass: the per-thread values derived from
+    // them (addresses, twiddles, basis samples) are then recomputed in every
+    // pass instead of being hoisted out of the loop, where they would stay
+    // live across the whole kernel.
+    WaveTables<double> tbl = tb;
+    asm volatile("" : "+v"(tid), "+s"(tbl.basis), "+s"(tbl.fft_tw), "+s"(tbl.bin_F), "+s"(tbl.bin_W));
+    // ---- plan: advance the moves up to the next template build
+    const double* ub = nullptr;
+    int kind = kSetup;
+    while (phase < 2) {
+      if (phase == 0) {
+        while (cur < S && !sm.ex[cur]) cur++;
+        if (cur < S) {
+          ub = sm.su[cur];
+          kind = kSetup;
+          break;
+        }
+        if (inmodel) {
+          // the occupied slots in slot order (in-model moves keep the
+          // occupancy) and their friend windows, one wave per slot
+          if (tid == 0) {
+            int c = 0;
+            for (int s = 0; s < S; s++)
+              if (sm.ex[s]) sm.order[c++] = s;
+            sm.n_occ = c;
           }
-          if (c == 0) break;  // key[lo] >= f0
-          const int lo2 = lo + (int)(((int64_t)(c - 1) * n) / kWave) + 1;
-          hi = c < kWave ? lo + (int)(((int64_t)c * n) / kWave) : hi;
-          lo = lo2;
-        }
-      }
-      const int nf = a.n_friends < G ? a.n_friends : G;
-      int start = lo - nf / 2;
-      if (start < 0) start = 0;
-      if (start > G - nf) start = G - nf;
-      const double* X = grp + 8 * (start + (int)floor(r_friend * nf));
-      const double am = a.stretch_a;
-      const double z = ((am - 1.0) * r_z + 1.0) * ((am - 1.0) * r_z + 1.0) / am;
-      // periodic angles move on the circle: the difference to the friend is
-      // taken in (-P/2, P/2] and the stretched difference must stay inside
-      // (-P/2, P/2), so that the reverse move (same friend, 1/z) returns to
-      // the start; otherwise the proposal is rejected (the pair of moves is
-      // then an exact involution with Jacobian z^8)
-      double un[8];
-      bool reversible = true;
-#pragma unroll
-      for (int i = 0; i < 8; i++) {
-        double diff = uk[i] - X[i];
-        double P = period_of(i);
-        if (P > 0) {
-          diff = wrap_p(diff + 0.5 * P, P) - 0.5 * P;
-          const double zd = z * diff;
-          if (!(fabs(zd) < 0.5 * P)) reversible = false;
-          un[i] = wrap_p(X[i] + zd, P);
-        } else {
-          un[i] = X[i] + z * diff;
-        }
-      }
-      if (!reversible || !in_prior<N>(g, a, b, un)) continue;
-      const double lr = 7.0 * log(z);
-      if (tid < 8) {
-        sm.u_old[tid] = uk[tid];
-        sm.u_new[tid] = un[tid];
-      }
-      __syncthreads();
-      int64_t kr;
-      if (spec) {
-        band_load_rwin<N>(sm, spec + (int64_t)sk * 2 * N);
-        kr = sm.sq[sk] - N / 2;
-      } else {
-        band_template<N>(g, tb, sm.u_old, sm);
-        band_store_rwin<N>(g, tb, sm);
-        kr = sm.src.q - N / 2;
-      }
-      band_template<N>(g, tb, sm.u_new, sm);
-      const int64_t ka = sm.src.q - N / 2;
-      const double dl = band_dlogl<N>(g, tb, sm, k0w, true, ka, true, kr);
-      if (log(r_acc) < beta * dl + lr) {
-        band_add_template<N>(g, tb, sm, k0w, -1.0, own, spec ? spec + (int64_t)sk * 2 * N : nullptr);
-        band_add_rwin<N>(g, sm, k0w, kr, 1.0, own);
-        if (tid < 8) sm.su[sk][tid] = sm.u_new[tid];
-        if (tid == 0) sm.sq[sk] = sm.src.q;
-        n_acc++;
-      }
-      __syncthreads();
-    }
-  } else {
-    // flip every slot once in a random order (Fisher-Yates from the top:
-    // position j swaps with r_j <= j); the draws in parallel, the swaps on one
-    // thread
-    for (int j = tid; j < S; j += block_threads<N>())
-      sm.draw[j] = j ? (int)floor(rng_uniform(a.seed, sweep, move, unit, (uint64_t)j) * (j + 1)) : 0;
-    __syncthreads();
-    if (tid == 0) {
-      for (int s = 0; s < S; s++) sm.order[s] = s;
-      for (int j = S - 1; j >= 1; j--) {
-        const int r = sm.draw[j];
-        const int tmp = sm.order[j];
-        sm.order[j] = sm.order[r];
-        sm.order[r] = tmp;
-      }
-    }
-    // every flip's uniform draws (words 64 + 16 i + k: k = 0 acceptance,
-    // k = 1..8 a prior birth's coordinates) one per thread ahead of the loop
-    for (int q = tid; q < S * 9; q += block_threads<N>()) {
-      const int i = q / 9, k = q - 9 * (q / 9);
-      sm.rdraw[i][k] = rng_uniform(a.seed, sweep, move, unit, 64 + 16 * (uint64_t)i + k);
-    }
-    __syncthreads();
-    double flo, fhi;
-    band_f0_range<N>(g, a, b, flo, fhi);
-    const double lvol = a.prop_u ? log_box_volume<N>(g, a, b) : 0.0;
-    for (int i = 0; i < S; i++) {
-      const int s = sm.order[i];
-      const double r_acc = sm.rdraw[i][0];
-      const int64_t ui = uidx(a, t, w, b, s);
-      double* us = sm.su[s];
-      if (sm.ex[s]) {
-        // death: the new template is zero; with the prior proposal (q = p) only
-        // the likelihood enters, otherwise ln q - ln p as well
-        n_dprop++;
-        int64_t kr;
-        if (spec) {
-          band_load_rwin<N>(sm, spec + (int64_t)s * 2 * N);
-          kr = sm.sq[s] - N / 2;
-        } else {
-          if (tid < 8) sm.u_old[tid] = us[tid];
           __syncthreads();
-          band_template<N>(g, tb, sm.u_old, sm);
-          band_store_rwin<N>(g, tb, sm);
-          kr = sm.src.q - N / 2;
-        }
-        const double dl = band_dlogl<N>(g, tb, sm, k0w, false, 0, true, kr);
-        const double lpq = a.prop_u ? a.rj_logq[ui] + lvol : 0.0;
-        if (log(r_acc) < beta * dl + lpq) {
-          band_add_rwin<N>(g, sm, k0w, kr, 1.0, own);
-          if (tid == 0) sm.ex[s] = 0;
-          n_dacc++;
-        }
-      } else if (a.prop_u) {
-        // birth from the given proposal: ln p - ln q enters
-        n_bprop++;
-        if (tid < 8) sm.u_new[tid] = a.prop_u[8 * ui + tid];
-        __syncthreads();
-        if (in_prior<N>(g, a, b, sm.u_new)) {
-          band_template<N>(g, tb, sm.u_new, sm);
-          const int64_t ka = sm.src.q - N / 2;
-          const double dl = band_dlogl<N>(g, tb, sm, k0w, true, ka, false, 0);
-          if (log(r_acc) < beta * dl - lvol - a.rj_logq[ui]) {
-            band_add_template<N>(g, tb, sm, k0w, -1.0, own, spec ? spec + (int64_t)s * 2 * N : nullptr);
-            if (tid < 8) us[tid] = sm.u_new[tid];
-            if (tid == 0) {
-              sm.ex[s] = 1;
-              sm.sq[s] = sm.src.q;
+          if (G > 0) {
+            for (int o = tid / kWave; o < sm.n_occ; o += NT / kWave) {
+              const int s = sm.order[o];
+              const int st = friend_start(grp, G, nf, sm.su[s][1]);
+              if ((tid & (kWave - 1)) == 0) sm.fstart[s] = st;
             }
-            n_bacc++;
           }
+          __syncthreads();
+        } else {
+          // flip every slot once in a random order (Fisher-Yates from the
+          // top: position j swaps with r_j <= j); the draws in parallel, the
+          // swaps on one thread; every flip's uniform draws (words 64 + 16 i
+          // + k: k = 0 acceptance, k = 1..8 a prior birth's coordinates)
+          for (int j = tid; j < S; j += NT)
+            sm.draw[j] = j ? (int)floor(rng_uniform(a.seed, sweep, move, unit, (uint64_t)j) * (j + 1)) : 0;
+          __syncthreads();
+          if (tid == 0) {
+            for (int s = 0; s < S; s++) sm.order[s] = s;
+            for (int j = S - 1; j >= 1; j--) {
+              const int r = sm.draw[j];
+              const int tmp = sm.order[j];
+              sm.order[j] = sm.order[r];
+              sm.order[r] = tmp;
+            }
+          }
+          // (the acceptance draw is kept as its logarithm)
+          for (int q = tid; q < S * 9; q += NT) {
+            const int i = q / 9, k = q - 9 * (q / 9);
+            const double r = rng_uniform(a.seed, sweep, move, unit, 64 + 16 * (uint64_t)i + k);
+            sm.rdraw[i][k] = k == 0 ? log_ni(r) : r;
+          }
+          __syncthreads();
+        }
+        phase = 1;
+        cur = 0;
+        continue;
+      }
+      if (inmodel) {
+        if (cur >= a.n_prop) {
+          phase = 2;
+          break;
+        }
+        if (pend) {
+          ub = sm.u_new;
+          kind = kNew;
+          break;
+        }
+        const int p = cur;
+        if ((p & (kMaxSlots - 1)) == 0) {
+          // the next kMaxSlots proposals' four draws (words 8 p + k), one per
+          // thread; the acceptance draw is kept as its logarithm, and the
+          // stretch draw also gives ln z^7 (column 4)
+          const int pe = a.n_prop - p < kMaxSlots ? a.n_prop - p : kMaxSlots;
+          __syncthreads();
+          for (int q = tid; q < 4 * pe; q += NT) {
+            const double r = rng_uniform(a.seed, sweep, move, unit, 8 * (uint64_t)(p + (q >> 2)) + (q & 3));
+            if ((q & 3) == 2) {
+              const double am = a.stretch_a;
+              const double z = ((am - 1.0) * r + 1.0) * ((am - 1.0) * r + 1.0) / am;
+              sm.rdraw[q >> 2][4] = 7.0 * log_ni(z);
+            }
+            sm.rdraw[q >> 2][q & 3] = (q & 3) == 3 ? log_ni(r) : r;
+          }
+          __syncthreads();
+        }
+        const double* rp = sm.rdraw[p & (kMaxSlots - 1)];
+        const double r_pick = rp[0], r_friend = rp[1], r_z = rp[2];
+        lr_acc = rp[3];
+        const int gcount = sm.n_occ;
+        cur++;
+        if (gcount == 0) continue;
+        sk = sm.order[(int)floor(r_pick * gcount)];
+        const double* uk = sm.su[sk];
+        n_prop++;
+        if (G <= 0) continue;
+        const double* X = grp + 8 * (sm.fstart[sk] + (int)floor(r_friend * nf));
+        const double am = a.stretch_a;
+        const double z = ((am - 1.0) * r_z + 1.0) * ((am - 1.0) * r_z + 1.0) / am;
+        // periodic angles move on the circle: the difference to the friend is
+        // taken in (-P/2, P/2] and the stretched difference must stay inside
+        // (-P/2, P/2), so that the reverse move (same friend, 1/z) returns to
+        // the start; otherwise the proposal is rejected (the pair of moves is
+        // then an exact involution with Jacobian z^8)
+        double un[8];
+        bool reversible = true;
+#pragma unroll
+        for (int i = 0; i < 8; i++) {
+          double diff = uk[i] - X[i];
+          const double P = period_of(i);
+          if (P > 0) {
+            diff = wrap_p(diff + 0.5 * P, P) - 0.5 * P;
+            const double zd = z * diff;
+            if (!(fabs(zd) < 0.5 * P)) reversible = false;
+            un[i] = wrap_p(X[i] + zd, P);
+          } else {
+            un[i] = X[i] + z * diff;
+          }
+        }
+        if (!reversible || !loop_in_prior<N>(sm, un)) continue;
+        lr = rp[4];
+        cur--;  // the move is under way
+        if (tid < 8) {
+          sm.u_old[tid] = uk[tid];
+          sm.u_new[tid] = un[tid];
+        }
+        __syncthreads();
+        if (spec) {
+          loop_load<N, BPT>(spec + (int64_t)sk * 2 * N, rv, tid);
+          kr = sm.sq[sk] - N / 2;
+          loop_weights<N, BPT>(g, wts, kr, wr, tid);
+          ub = sm.u_new;
+          kind = kNew;
+        } else {
+          ub = sm.u_old;
+          kind = kOld;
+        }
+        break;
+      }
+      // reversible jump
+      if (cur >= S) {
+        phase = 2;
+        break;
+      }
+      const int s = sm.order[cur];
+      lr_acc = sm.rdraw[cur][0];
+      sk = s;
+      if (sm.ex[s]) {
+        // death: the new template is zero; with the prior proposal (q = p)
+        // only the likelihood enters, otherwise ln q - ln p as well
+        n_dprop++;
+        if (spec) {
+          loop_load<N, BPT>(spec + (int64_t)s * 2 * N, rv, tid);
+          kr = sm.sq[s] - N / 2;
+          loop_weights<N, BPT>(g, wts, kr, wr, tid);
+          death(s, lr_acc);
+          cur++;
+          continue;
+        }
+        if (tid < 8) sm.u_old[tid] = sm.su[s][tid];
+        __syncthreads();
+        ub = sm.u_old;
+        kind = kOld;
+        break;
+      }
+      n_bprop++;
+      if (a.prop_u) {
+        // birth from the given proposal: ln p - ln q enters
+        if (tid < 8) sm.u_new[tid] = a.prop_u[8 * uidx(a, t, w, b, s) + tid];
+        __syncthreads();
+        if (!loop_in_prior<N>(sm, sm.u_new)) {
+          __syncthreads();
+          cur++;
+          continue;
         }
       } else {
         // birth drawn from the prior
-        n_bprop++;
-        if (tid < 8) {
-          const int k = tid;
-          const double r = sm.rdraw[i][1 + k];
-          double lo = a.lo[k], hi = a.hi[k];
-          if (k == 1) {
-            lo = flo;
-            hi = fhi;
-          } else if (period_of(k) > 0) {
-            lo = 0.0;
-            hi = period_of(k);
-          }
-          sm.u_new[k] = lo + (hi - lo) * r;
-        }
+        if (tid < 8) sm.u_new[tid] = sm.blo[tid] + (sm.bhi[tid] - sm.blo[tid]) * sm.rdraw[cur][1 + tid];
         __syncthreads();
-        band_template<N>(g, tb, sm.u_new, sm);
-        const int64_t ka = sm.src.q - N / 2;
-        const double dl = band_dlogl<N>(g, tb, sm, k0w, true, ka, false, 0);
-        if (log(r_acc) < beta * dl) {
-          band_add_template<N>(g, tb, sm, k0w, -1.0, own, spec ? spec + (int64_t)s * 2 * N : nullptr);
-          if (tid < 8) us[tid] = sm.u_new[tid];
-          if (tid == 0) {
-            sm.ex[s] = 1;
-            sm.sq[s] = sm.src.q;
-          }
-          n_bacc++;
+      }
+      ub = sm.u_new;
+      kind = kNew;
+      break;
+    }
+    if (phase == 2) break;
+
+    // ---- the template build (the only one)
+    loop_build<N, BPT>(g, tbl, ub, sm, kind == kSetup ? nullptr : wts, wh, tid);
+    loop_bins<N, BPT>(g, tbl, sm, hv, tid);
+    const int64_t kh = sm.src.q - N / 2;
+    if (kind == kSetup) {
+      // the band's residual: remove the slot's source, keep its spectrum
+      if (spec) loop_store<N, BPT>(spec + (int64_t)cur * 2 * N, hv, tid);
+      loop_add<N, BPT>(g, sm, k0w, kh, -1.0, hv, nullptr, tid);
+      if (tid == 0) sm.sq[cur] = sm.src.q;
+      __syncthreads();
+      cur++;
+      continue;
+    }
+#pragma unroll
+    for (int m = 0; m < BPT; m++)
+      for (int c = 0; c < 2; c++) {
+        if (kind == kOld) {
+          rv[m][c] = hv[m][c];
+          wr[m][c] = wh[m][c];
+        } else {
+          av[m][c] = hv[m][c];
+          wa[m][c] = wh[m][c];
         }
       }
+    if (kind == kOld) {
+      kr = kh;
+      if (inmodel) {
+        pend = true;  // the new template next
+        continue;
+      }
+      death(sk, lr_acc);
+      cur++;
+      continue;
+    }
+    ka = kh;
+    pend = false;
+    double dl;
+    if (inmodel) {
+      // r's spectrum into the workspace for the bins of a's window that need
+      // it at another offset
       __syncthreads();
+#pragma unroll
+      for (int m = 0; m < BPT; m++) {
+        sm.buf[tid + NT * m] = rv[m][0];
+        sm.buf[N + tid + NT * m] = rv[m][1];
+      }
+      __syncthreads();
+      dl = loop_dlogl<N, BPT>(g, sm, k0w, true, ka, av, wa, true, kr, rv, wr, tid);
+    } else {
+      dl = loop_dlogl<N, BPT>(g, sm, k0w, true, ka, av, wa, false, 0, rv, wr, tid);
+    }
+    double thr;
+    if (inmodel)
+      thr = beta * dl + lr;
+    else if (a.prop_u)
+      thr = beta * dl - lvol - a.rj_logq[uidx(a, t, w, b, sk)];
+    else
+      thr = beta * dl;
+    if (lr_acc < thr) {
+      if (spec) loop_store<N, BPT>(spec + (int64_t)sk * 2 * N, av, tid);
+      loop_add<N, BPT>(g, sm, k0w, ka, -1.0, av, own, tid);
+      __syncthreads();
+      if (inmodel) {
+        loop_add<N, BPT>(g, sm, k0w, kr, 1.0, rv, own, tid);
+        // the moved slot's friend window (every wave searches, one thread writes)
+        const int st = friend_start(grp, G, nf, sm.u_new[1]);
+        if (tid == 0) sm.fstart[sk] = st;
+        n_acc++;
+      } else {
+        if (tid == 0) sm.ex[sk] = 1;
+        n_bacc++;
+      }
+      if (tid < 8) sm.su[sk][tid] = sm.u_new[tid];
+      if (tid == 0) sm.sq[sk] = sm.src.q;
+    }
+    __syncthreads();
+    cur++;
+  }
+  // the set's window sum for the tempering pass: H = (opposite-parity
+  // window) - (final window); that buffer does not change during the pass
+  if (a.wsum) {
+    const cd* opp = a.resid + ((int64_t)(1 - (b & 1)) * a.n_w + w) * 2 * g.n_bins;
+    cd* H = wsum_entry<N>(a, t, w, b);
+    for (int i = tid; i < 3 * N; i += NT) {
+      const int64_t k = k0w + i - g.k_min;
+      const bool inb = k >= 0 && k < g.n_bins;
+#pragma unroll
+      for (int c = 0; c < 2; c++) H[c * 3 * N + i] = inb ? opp[c * g.n_bins + k] - sm.win[c][i] : cd{0.0, 0.0};
     }
   }
-  for (int s = tid; s < S; s += block_threads<N>()) {
+  for (int s = tid; s < S; s += NT) {
     a.exists[uidx(a, t, w, b, s)] = sm.ex[s];
     for (int k = 0; k < 8; k++) a.u[8 * uidx(a, t, w, b, s) + k] = sm.su[s][k];
   }
@@ -751,14 +1028,21 @@ __global__ __launch_bounds__(block_threads<N>()) void k_sweep_pt(Geo g, WaveTabl
     }
     wt[t] = p;
   }
-  if (tid == 0) sm.entry = pool_acquire(a);
+  // window sums of the sets: from the band passes (wsum, entries that move
+  // with the sets), else built here into a pool entry (hidx maps a
+  // temperature to its set's sum), else recomputed on every evaluation
+  const bool ws = a.wsum != nullptr;
+  if (tid == 0) sm.entry = ws ? -1 : pool_acquire(a);
   for (int t = tid; t < nt; t += block_threads<N>()) hidx[t] = t;
   __syncthreads();
-  cd* const Hs = sm.entry >= 0 ? a.spec_pool + (int64_t)sm.entry * pool_entry(a.n_slot, nt, N) : nullptr;
-  auto Hof = [&](int t) { return Hs + (int64_t)hidx[t] * 6 * N; };
+  cd* const Hp = sm.entry >= 0 ? a.spec_pool + (int64_t)sm.entry * pool_entry(a.n_slot, nt, N) : nullptr;
+  const bool Hs = ws || Hp;
+  auto Hof = [&](int t) { return ws ? wsum_entry<N>(a, t, wt[t], b) : Hp + (int64_t)hidx[t] * 6 * N; };
   for (int t = 0; t < nt; t++) {
     double L;
-    if (Hs) {
+    if (ws) {
+      L = band_set_loglike_h<N>(g, a, b, wt[t], k0w, Hof(t), sm);
+    } else if (Hs) {
       band_set_sum<N>(g, tb, a, t, wt[t], b, k0w, sm, Hof(t));
       L = band_set_loglike_h<N>(g, a, b, wt[t], k0w, Hof(t), sm);
     } else {
@@ -811,7 +1095,17 @@ __global__ __launch_bounds__(block_threads<N>()) void k_sweep_pt(Geo g, WaveTabl
           }
         }
       }
-      // exchange the source sets of (t, w_t) and (t-1, w_(t-1))
+      // exchange the source sets of (t, w_t) and (t-1, w_(t-1)), with their
+      // window sums
+      if (ws) {
+        cd* h1 = Hof(t);
+        cd* h2 = Hof(t - 1);
+        for (int i2 = tid; i2 < 6 * N; i2 += block_threads<N>()) {
+          const cd tmp = h1[i2];
+          h1[i2] = h2[i2];
+          h2[i2] = tmp;
+        }
+      }
       for (int s = tid; s < a.n_slot; s += block_threads<N>()) {
         int64_t i1 = uidx(a, t, wt[t], b, s), i2 = uidx(a, t - 1, wt[t - 1], b, s);
         for (int k = 0; k < 8; k++) {

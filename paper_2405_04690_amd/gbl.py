@@ -69,7 +69,8 @@ class SweepState(ctypes.Structure):
     _fields_ = [(n, ctypes.c_void_p) for n in ("u", "exists", "betas", "resid", "inv_psd", "group", "group_count",
                                               "stats", "sweep_counter", "prop_u", "rj_logq", "cold_logl",
                                               "rj_mode", "spec_pool", "pool_flags")] + [("pool_size", ctypes.c_int32),
-                                                                                        ("swap_acc", ctypes.c_void_p)]
+                                                                                        ("swap_acc", ctypes.c_void_p),
+                                                                                        ("window_sums", ctypes.c_void_p)]
 
 
 class Tuning(ctypes.Structure):

@@ -39,7 +39,7 @@ def make_config(n_temps, n_walkers, n_bands, n_slots, N, k_band0, n_prop=10, n_f
 
 
 class Sweep:
-    def __init__(self, ctx: Context, cfg: SweepConfig, spectrum_pool: int = 1024):
+    def __init__(self, ctx: Context, cfg: SweepConfig, spectrum_pool: int = 1024, window_sums: bool = False):
         self.ctx, self.cfg = ctx, cfg
         dev = ctx.device
         nt, nw, nb, ns = cfg.n_temps, cfg.n_walkers, cfg.n_bands, cfg.n_slots
@@ -66,6 +66,11 @@ class Sweep:
             entry = max(ns * 2 * cfg.N, nt * 6 * cfg.N)
             self.spec_pool = torch.zeros((spectrum_pool, entry), dtype=torch.complex128, device=dev)
             self.pool_flags = torch.zeros(spectrum_pool, dtype=torch.int32, device=dev)
+        # window sums of the source sets, written by the band passes for the
+        # tempering pass (n_temps x n_walkers x n_bands x 6N complex doubles)
+        self.window_sums = None
+        if window_sums:
+            self.window_sums = torch.zeros((nt, nw, nb, 6 * cfg.N), dtype=torch.complex128, device=dev)
         self._graph = None
 
     def enable_proposals(self):
@@ -89,7 +94,7 @@ class Sweep:
     def _state(self):
         st = SweepState()
         for n in ("u", "exists", "betas", "resid", "inv_psd", "group", "group_count", "stats", "sweep_counter",
-                  "prop_u", "rj_logq", "cold_logl", "rj_mode", "spec_pool", "pool_flags", "swap_acc"):
+                  "prop_u", "rj_logq", "cold_logl", "rj_mode", "spec_pool", "pool_flags", "swap_acc", "window_sums"):
             t = getattr(self, n)
             setattr(st, n, t.data_ptr() if t is not None else None)
         st.pool_size = self.spec_pool.shape[0] if self.spec_pool is not None else 0

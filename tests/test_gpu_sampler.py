@@ -17,7 +17,7 @@ from paper_2405_04690_amd.sampler import Sweep
 pytestmark = pytest.mark.gpu
 
 
-def _gpu_sweep(cfg, sc, st, stream=None, pool=1024):
+def _gpu_sweep(cfg, sc, st, stream=None, pool=1024, window_sums=False):
     ctx = Context(T=cfg.T, dt=cfg.dt, L=cfg.L, f_lo=cfg.f_lo, f_hi=cfg.f_hi, stream=stream)
     gc = SweepConfig()
     for name, _ in oracle.SweepConfig._fields_:
@@ -27,7 +27,7 @@ def _gpu_sweep(cfg, sc, st, stream=None, pool=1024):
                 getattr(gc, name)[i] = v[i]
         else:
             setattr(gc, name, v)
-    sw = Sweep(ctx, gc, spectrum_pool=pool)
+    sw = Sweep(ctx, gc, spectrum_pool=pool, window_sums=window_sums)
     for name in ("u", "exists", "betas", "resid", "inv_psd", "group", "group_count", "stats", "swap_acc"):
         getattr(sw, name).copy_(torch.from_numpy(np.ascontiguousarray(getattr(st, name))))
     return ctx, sw
@@ -49,12 +49,14 @@ def _compare(sw, st, what, T=None):
     assert np.max(np.abs(r - st.resid)) <= 1e-10 * np.abs(st.resid).max(), f"{what}: residual buffers differ"
 
 
-@pytest.mark.parametrize("N,pool", [(128, 1024), (256, 1024), (512, 1024), (128, 0), (256, 2)])
-def test_sweep_parity_each_move(N, pool):
+@pytest.mark.parametrize("N,pool,ws", [(128, 1024, False), (256, 1024, False), (512, 1024, False), (128, 0, False),
+                                       (256, 2, False), (256, 1024, True), (128, 0, True), (512, 1024, True)])
+def test_sweep_parity_each_move(N, pool, ws):
     """pool: the per-slot spectrum cache (0: recomputed spectra; 2: most band
-    loops find no free entry and recompute, the others use the cache)"""
+    loops find no free entry and recompute, the others use the cache); ws:
+    the tempering pass takes the window sums the band passes leave"""
     cfg, orc, sc, st = sampler_setup.problem(N=N, n_b=6 if N == 128 else 4)
-    ctx, sw = _gpu_sweep(cfg, sc, st, pool=pool)
+    ctx, sw = _gpu_sweep(cfg, sc, st, pool=pool, window_sums=ws)
     s0 = 11
     sw.sweep_counter.fill_(s0)
     oracle.sweep_group(sc, st)
@@ -403,7 +405,7 @@ def test_sweep_parity_at_the_bench_shape():
     cfg, orc, sc, st = sampler_setup.problem(n_t=36, n_w=32, n_b=4, n_slots=60, n_prop=4, n_friends=40,
                                              group_every=1, seed=91, beta_top=0.02, N=256, cfg=inputs.PAPER,
                                              per_band=60)
-    ctx, sw = _gpu_sweep(cfg, sc, st)
+    ctx, sw = _gpu_sweep(cfg, sc, st, window_sums=True)   # the benchmark's configuration
     s0 = 5
     sw.sweep_counter.fill_(s0)
     oracle.sweep_group(sc, st)
