@@ -691,6 +691,22 @@ __global__ void k_make_noise(int64_t total, double scale, const double* __restri
 
 
 // ---------------------------------------------------------------------------
+// XCD-aware block order: the dispatcher deals workgroups round-robin to the
+// eight XCDs, each with its own L2, so consecutive blocks run on different
+// L2s.  The logical block index below gives each XCD one contiguous run of
+// the grid instead (XCD x takes blocks x, x + 8, ...; with G = 8q + r blocks
+// the first r XCDs take q + 1), so templates that are close in the batch, and
+// share residual and PSD windows, also share an L2.  A bijection on [0, G).
+// ---------------------------------------------------------------------------
+constexpr unsigned kXcds = 8;
+
+__device__ __forceinline__ unsigned xcd_block() {
+  const unsigned G = gridDim.x, x = blockIdx.x % kXcds, i = blockIdx.x / kXcds;
+  const unsigned q = G / kXcds, r = G % kXcds;
+  return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
+}
+
+// ---------------------------------------------------------------------------
 // gb_inner: PSD-weighted inner products of stored band slices (Sec. 2 eq.
 // inner over channels A, E):
 //   out[b] = (<h|h>, <R|h>) = 4 df sum_{c,k} (|h|^2, Re(conj(R) h)) / S
@@ -709,7 +725,7 @@ __global__ __launch_bounds__(kInnerWaves * kWave) void k_inner(Geo g, const cd* 
                                                                const int32_t* __restrict__ res_idx,
                                                                const int32_t* __restrict__ psd_idx, int64_t B,
                                                                double* __restrict__ out) {
-  const int64_t b = (int64_t)blockIdx.x * kInnerWaves + threadIdx.x / kWave;
+  const int64_t b = (int64_t)xcd_block() * kInnerWaves + threadIdx.x / kWave;
   if (b >= B) return;  // uniform over the wave
   const int lane = threadIdx.x & (kWave - 1);
   const int ri = res_idx[b], pi = psd_idx[b];
