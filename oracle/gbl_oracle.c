@@ -752,8 +752,11 @@ double gblo_rng_uniform(uint64_t seed, int64_t sweep, int move, uint64_t unit, u
 }
 
 /* Sampler configuration (readings where the paper is silent):
- *  - sub-band b covers bins [k_band0 + b W, k_band0 + (b+1) W) with W = N,
- *    the template width; its analysis window is bands b-1..b+1;
+ *  - sub-band b covers bins [k_band0 + b W, k_band0 + (b+1) W); W is the
+ *    sub-band width (band_width, even; 0 means W = N, the template width);
+ *    the analysis window of band b holds every bin a template of the band can
+ *    reach: [k_band0 + b W - W/2 - N/2, k_band0 + (b+1) W + W/2 + N/2),
+ *    2W + N bins (bands b-1..b+1 when W = N);
  *  - sampling coordinates u = (log10 A, f0, fdot, phi0, cos iota, psi,
  *    lambda, sin beta) with a uniform prior on a box; f0 of band b ranges over
  *    the band widened by W/2 on each side (samples may move halfway into the
@@ -780,7 +783,11 @@ typedef struct {
   int32_t shift_ownership; /* 1: move cold-chain sources to the band their f0 now lies in */
   double adapt_lag;        /* t0 of the adaptation's decay t0 / (t + t0) */
   double adapt_time;       /* nu: the adaptation's time scale */
+  int32_t band_width;      /* W, even; 0: W = N */
 } gblo_sweep_config;
+
+/* sub-band width W */
+static int64_t band_w(const gblo_sweep_config* sc) { return sc->band_width > 0 ? sc->band_width : sc->N; }
 
 #define MOVE_INMODEL 0
 #define MOVE_RJ 1
@@ -790,7 +797,7 @@ typedef struct {
 static const double PERIOD[8] = {0, 0, 0, 2.0 * ORC_PI, 0, ORC_PI, 2.0 * ORC_PI, 0};
 
 static void band_f0_range(const gblo_config* cfg, const gblo_sweep_config* sc, int b, double* lo, double* hi) {
-  double W = (double)sc->N;
+  double W = (double)band_w(sc);
   *lo = ((double)sc->k_band0 + ((double)b - 0.5) * W) / cfg->T;
   *hi = ((double)sc->k_band0 + ((double)b + 1.5) * W) / cfg->T;
 }
@@ -818,20 +825,26 @@ static int in_prior(const gblo_config* cfg, const gblo_sweep_config* sc, int b, 
   return 1;
 }
 
-/* Residual window of one walker: bins [k_band0 + (b-1) W, k_band0 + (b+2) W)
- * clipped to the analysis band, channels A and E. */
+/* Residual window of one walker: bins [k_band0 + b W - W/2 - N/2,
+ * k_band0 + (b+1) W + W/2 + N/2) clipped to the analysis band, channels A and
+ * E; its templates have width N. */
 typedef struct {
   int64_t k0;   /* first global bin of the window */
-  int len;      /* 3 W */
+  int len;      /* 2 W + N */
+  int N;        /* template width */
   cplx* r[2];   /* per channel */
 } window_t;
 
-static int64_t win_start(const gblo_sweep_config* sc, int b) { return sc->k_band0 + (int64_t)(b - 1) * sc->N; }
+static int64_t win_start(const gblo_sweep_config* sc, int b) {
+  return sc->k_band0 + (int64_t)b * band_w(sc) - band_w(sc) / 2 - sc->N / 2;
+}
+
+static int win_len(const gblo_sweep_config* sc) { return (int)(2 * band_w(sc) + sc->N); }
 
 /* add s * template(u) to the window (bins outside the window or the band are dropped) */
 static void window_add_template(const gblo_config* cfg, int64_t k_min, int64_t nb, window_t* w, const double* u,
                                 double s) {
-  int N = w->len / 3;
+  int N = w->N;
   double p[8];
   u_to_params(u, p);
   cplx* a = (cplx*)malloc(sizeof(cplx) * 2 * N);
@@ -851,10 +864,10 @@ static void window_add_template(const gblo_config* cfg, int64_t k_min, int64_t n
  * zero template (birth / death). */
 static double window_dlogl(const gblo_config* cfg, int64_t k_min, int64_t nb, const window_t* w,
                            const double* inv_psd /*[2][nb]*/, const double* u_old, const double* u_new) {
-  int N = w->len / 3;
   window_t d;
   d.k0 = w->k0;
   d.len = w->len;
+  d.N = w->N;
   d.r[0] = (cplx*)calloc(w->len, sizeof(cplx));
   d.r[1] = (cplx*)calloc(w->len, sizeof(cplx));
   if (u_new) window_add_template(cfg, k_min, nb, &d, u_new, 1.0);
@@ -870,7 +883,6 @@ static double window_dlogl(const gblo_config* cfg, int64_t k_min, int64_t nb, co
     }
   free(d.r[0]);
   free(d.r[1]);
-  (void)N;
   return 4.0 / cfg->T * (Rd - 0.5 * dd);
 }
 
@@ -981,10 +993,12 @@ static void band_loop(const gblo_config* cfg, const gblo_sweep_config* sc, int m
   int S = sc->n_slots;
   window_t win;
   win.k0 = win_start(sc, b);
-  win.len = 3 * sc->N;
+  win.len = win_len(sc);
+  win.N = sc->N;
   win.r[0] = (cplx*)malloc(sizeof(cplx) * win.len);
   win.r[1] = (cplx*)malloc(sizeof(cplx) * win.len);
-  window_t dsum = {win.k0, win.len, {(cplx*)calloc(win.len, sizeof(cplx)), (cplx*)calloc(win.len, sizeof(cplx))}};
+  window_t dsum = {win.k0, win.len, win.N,
+                   {(cplx*)calloc(win.len, sizeof(cplx)), (cplx*)calloc(win.len, sizeof(cplx))}};
   const cplx* opp = (const cplx*)(resid + ((int64_t)(1 - par) * sc->n_walkers + w) * 2 * nb * 2);
   window_load(k_min, nb, &win, opp);
   /* residual of the band: subtract the band's current sources */
@@ -1121,7 +1135,8 @@ static double band_loglike(const gblo_config* cfg, const gblo_sweep_config* sc, 
   gblo_band(cfg, &k_min, &nb);
   window_t win;
   win.k0 = win_start(sc, b);
-  win.len = 3 * sc->N;
+  win.len = win_len(sc);
+  win.N = sc->N;
   win.r[0] = (cplx*)malloc(sizeof(cplx) * win.len);
   win.r[1] = (cplx*)malloc(sizeof(cplx) * win.len);
   int par = b & 1;
@@ -1219,7 +1234,8 @@ static void pt_chain(const gblo_config* cfg, const gblo_sweep_config* sc, int64_
         /* new cold-chain sources for walker w_0: update its own-parity buffer */
         window_t dw;
         dw.k0 = win_start(sc, b);
-        dw.len = 3 * sc->N;
+        dw.len = win_len(sc);
+        dw.N = sc->N;
         dw.r[0] = (cplx*)calloc(dw.len, sizeof(cplx));
         dw.r[1] = (cplx*)calloc(dw.len, sizeof(cplx));
         for (int s = 0; s < sc->n_slots; s++) {
@@ -1258,6 +1274,7 @@ int gblo_sweep_step(const gblo_config* cfg, const gblo_sweep_config* sc, int mov
                     const double* rj_logq, double* cold_logl, int32_t* swap_acc) {
   if (sc->n_slots > 64 || sc->n_slots < 1) return -1;
   if ((prop_u == NULL) != (rj_logq == NULL)) return -1;
+  if (sc->band_width < 0 || (sc->band_width & 1)) return -1;
   int64_t k_min, nb;
   gblo_band(cfg, &k_min, &nb);
   /* The units of one step -- band loops (t, w, b), or tempering chains
@@ -1348,7 +1365,7 @@ int gblo_sweep_adapt_ladder(const gblo_sweep_config* sc, int64_t sweep, double* 
  * Sub-band ownership (Sec. 4 "Galactic binary search and parameter
  * estimation"): samples may roam half a band into the neighbours; a
  * cold-chain source whose f0 has left its band's nominal range [k_band0 +
- * b N, k_band0 + (b+1) N) / T moves to the neighbouring band it now lies in,
+ * b W, k_band0 + (b+1) W) / T moves to the neighbouring band it now lies in,
  * into that band's lowest free cold-chain slot (it stays if there is none).
  * The source then belongs to the opposite parity: it is added back to the
  * old parity's buffer and removed from the new one's.  Per walker, bands in
@@ -1366,8 +1383,8 @@ int gblo_sweep_shift_ownership(const gblo_config* cfg, const gblo_sweep_config* 
         const int64_t ui = UIDX(sc, 0, w, b, s);
         if (!exists[ui]) continue;
         const double f0 = u[8 * ui + 1];
-        const double lo = (double)(sc->k_band0 + (int64_t)b * sc->N) / cfg->T;
-        const double hi = (double)(sc->k_band0 + (int64_t)(b + 1) * sc->N) / cfg->T;
+        const double lo = (double)(sc->k_band0 + (int64_t)b * band_w(sc)) / cfg->T;
+        const double hi = (double)(sc->k_band0 + (int64_t)(b + 1) * band_w(sc)) / cfg->T;
         int bb = f0 < lo ? b - 1 : (f0 >= hi ? b + 1 : b);
         if (bb == b || bb < 0 || bb >= sc->n_bands) continue;
         int s2 = -1;

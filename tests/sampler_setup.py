@@ -15,9 +15,10 @@ N = 128
 
 
 def problem(n_t=3, n_w=4, n_b=6, n_slots=4, n_prop=6, n_friends=4, group_every=1, seed=77, beta_top=0.3, N=N,
-            cfg=None, per_band=2, f_band0=3e-3):
+            cfg=None, per_band=2, f_band0=3e-3, W=None):
     """per_band injections per sub-band, each held by one slot of every chain
-    (jittered); cfg defaults to the 0.25 yr configuration"""
+    (jittered); cfg defaults to the 0.25 yr configuration; W: sub-band width
+    in bins (None: the template width N)"""
     cfg = inputs.TINY if cfg is None else cfg
     orc = oracle.Oracle(T=cfg.T, dt=cfg.dt, L=cfg.L, f_lo=cfg.f_lo, f_hi=cfg.f_hi)
     k_band0 = int(f_band0 * cfg.T)
@@ -25,6 +26,8 @@ def problem(n_t=3, n_w=4, n_b=6, n_slots=4, n_prop=6, n_friends=4, group_every=1
     sc.n_temps, sc.n_walkers, sc.n_bands, sc.n_slots = n_t, n_w, n_b, n_slots
     sc.N, sc.n_prop, sc.n_friends, sc.group_every = N, n_prop, n_friends, group_every
     sc.k_band0, sc.stretch_a, sc.seed = k_band0, 2.0, seed
+    sc.band_width = 0 if W is None else W
+    Wb = N if W is None else W
     lo = (-23.0, 0.0, -1e-16, 0.0, -1.0, 0.0, 0.0, -1.0)
     hi = (-20.5, 0.0, 1e-15, 0.0, 1.0, 0.0, 0.0, 1.0)
     for i in range(8):
@@ -35,7 +38,7 @@ def problem(n_t=3, n_w=4, n_b=6, n_slots=4, n_prop=6, n_friends=4, group_every=1
     src = []
     for b in range(n_b):
         for _ in range(per_band):
-            f0 = (k_band0 + (b + rng.uniform(0.1, 0.9)) * N) / cfg.T
+            f0 = (k_band0 + (b + rng.uniform(0.1, 0.9)) * Wb) / cfg.T
             src.append([10 ** rng.uniform(-22.0, -21.3), f0, 0.0, rng.uniform(0, 2 * np.pi),
                         np.arccos(rng.uniform(-1, 1)), rng.uniform(0, np.pi), rng.uniform(0, 2 * np.pi),
                         np.arcsin(rng.uniform(-1, 1))])

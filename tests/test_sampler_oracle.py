@@ -65,10 +65,11 @@ def test_rj_pass_keeps_the_prior_at_zero_inverse_temperature():
 # coordinate uniform, the periodic angles included.
 # --------------------------------------------------------------------------
 def _band_box(sc, T, b):
+    W = sc.band_width or sc.N
     lo = np.array(list(sc.prior_lo))
     hi = np.array(list(sc.prior_hi))
-    lo[1] = (sc.k_band0 + (b - 0.5) * sc.N) / T
-    hi[1] = (sc.k_band0 + (b + 1.5) * sc.N) / T
+    lo[1] = (sc.k_band0 + (b - 0.5) * W) / T
+    hi[1] = (sc.k_band0 + (b + 1.5) * W) / T
     for k, P in ((3, 2 * np.pi), (5, np.pi), (6, 2 * np.pi)):
         lo[k], hi[k] = 0.0, P
     return lo, hi
@@ -129,7 +130,8 @@ def test_stretch_proposal_is_an_involution():
     assert 0 < n_rej < 2000
 
 
-def test_inmodel_band_loop_keeps_the_prior_at_zero_inverse_temperature():
+@pytest.mark.parametrize("W", [None, 200])
+def test_inmodel_band_loop_keeps_the_prior_at_zero_inverse_temperature(W):
     """the band loop's wiring of the move (slot pick, friend window, prior box,
     acceptance) at beta = 0 with a fixed group no larger than n_friends: all
     eight coordinates of 768 independent slot chains stay uniform (one final
@@ -137,7 +139,7 @@ def test_inmodel_band_loop_keeps_the_prior_at_zero_inverse_temperature():
     not allow for; the exactness itself is pinned with more power by the
     stand-alone chain test above)"""
     from scipy import stats as sps
-    cfg, orc, sc, st = sampler_setup.problem(n_t=16, n_w=4, n_b=4, n_slots=3, n_prop=6, n_friends=16, seed=9)
+    cfg, orc, sc, st = sampler_setup.problem(n_t=16, n_w=4, n_b=4, n_slots=3, n_prop=6, n_friends=16, seed=9, W=W)
     rng = np.random.default_rng(2)
     for b in range(sc.n_bands):
         lo, hi = _band_box(sc, cfg.T, b)
@@ -172,19 +174,23 @@ def _full_lnl(orc, sc, R, inv_psd, U, ex):
     return -0.5 * 4 * orc.df * np.sum((x.real ** 2 + x.imag ** 2) * inv_psd)
 
 
-def test_band_loglike_differences_equal_full_band_likelihood_differences():
-    """band_loglike over the three-sub-band window differs between two source
-    sets by exactly what the full-band eq. like does (every template of band b
-    lies inside the window); it reads walker w_res's opposite-parity buffer"""
-    cfg, orc, sc, st = sampler_setup.problem(n_t=2, n_w=3, n_b=4, n_slots=4, seed=13)
+@pytest.mark.parametrize("W", [None, 384, 200])
+def test_band_loglike_differences_equal_full_band_likelihood_differences(W):
+    """band_loglike over the band's window (2W + N bins) differs between two
+    source sets by exactly what the full-band eq. like does (every template
+    of band b lies inside the window, also at the ends of the f0 range); it
+    reads walker w_res's opposite-parity buffer"""
+    cfg, orc, sc, st = sampler_setup.problem(n_t=2, n_w=3, n_b=4, n_slots=4, seed=13, W=W)
     rng = np.random.default_rng(14)
     for b in (1, 2):
         par = b & 1
-        for (t1, w1), (t2, w2), wr in (((0, 0), (1, 2), 1), ((1, 1), (0, 2), 0)):
+        for k, ((t1, w1), (t2, w2), wr) in enumerate((((0, 0), (1, 2), 1), ((1, 1), (0, 2), 0))):
             st.exists[t1, w1, b, 2] = 1  # a third source in one set
             lo, hi = _band_box(sc, cfg.T, b)
             st.u[t1, w1, b, 2] = lo + (hi - lo) * rng.uniform(size=8)
             st.u[t1, w1, b, 2, 0] = -21.5
+            # at the lowest f0 of the band's range, or just below its top
+            st.u[t1, w1, b, 2, 1] = lo[1] if k == 0 else hi[1] - 0.01 / cfg.T
             l1 = oracle.band_loglike(orc, sc, st, t1, w1, b, wr)
             l2 = oracle.band_loglike(orc, sc, st, t2, w2, b, wr)
             R = st.resid[1 - par, wr]
@@ -194,10 +200,11 @@ def test_band_loglike_differences_equal_full_band_likelihood_differences():
             assert abs(l1 - l2) > 1.0  # the sets differ measurably
 
 
-def test_cold_chain_buffers_stay_consistent_through_every_move():
+@pytest.mark.parametrize("W", [None, 384])
+def test_cold_chain_buffers_stay_consistent_through_every_move(W):
     """after in-model, RJ and tempering steps each parity buffer equals the data
     minus the current cold-chain sources of its bands (rebuilt from scratch)"""
-    cfg, orc, sc, st = sampler_setup.problem(n_t=3, n_w=3, n_b=4, n_slots=4, n_prop=6, seed=17, beta_top=0.5)
+    cfg, orc, sc, st = sampler_setup.problem(n_t=3, n_w=3, n_b=4, n_slots=4, n_prop=6, seed=17, beta_top=0.5, W=W)
     oracle.sweep_group(sc, st)
     for move in (oracle.MOVE_INMODEL, oracle.MOVE_RJ, oracle.MOVE_PT):
         for parity in (1, 0):
@@ -453,14 +460,16 @@ def test_ladder_adaptation_leaves_an_equal_acceptance_ladder_and_decays():
     assert moved[0] > 0.3 and moved[1] < 1e-7
 
 
-def test_ownership_shift_moves_cold_sources_and_keeps_the_buffers():
+@pytest.mark.parametrize("W", [None, 200])
+def test_ownership_shift_moves_cold_sources_and_keeps_the_buffers(W):
     """cold-chain sources pushed past their band edge move to the
     neighbouring band's lowest free slot; the multiset of cold sources is
     unchanged, hot chains are untouched, moved sources sit in their new
     band's nominal range, and both parity buffers equal a rebuild from the
     data minus every cold source of that parity"""
-    cfg, orc, sc, st = sampler_setup.problem(n_t=2, n_w=3, n_b=5, n_slots=4, seed=131)
-    T, N, kb = cfg.T, sc.N, sc.k_band0
+    cfg, orc, sc, st = sampler_setup.problem(n_t=2, n_w=3, n_b=5, n_slots=4, seed=131, W=W)
+    T, kb = cfg.T, sc.k_band0
+    N = sc.band_width or sc.N   # the sub-band width
     rng = np.random.default_rng(132)
     # move some cold sources across an edge: up to 0.45 band into the neighbour
     pushed = []
