@@ -328,7 +328,7 @@ int gb_make_noise(gbl_ctx* ctx, const double* S, const double* normals, int64_t 
 
 typedef struct {
   int32_t n_temps, n_walkers, n_bands, n_slots; /* n_slots <= 64, n_temps and n_walkers <= 256 */
-  int32_t N;                                   /* template width = sub-band width */
+  int32_t N;                                   /* template width */
   int32_t n_prop;                              /* in-model proposals per band per sweep */
   int32_t n_friends;                           /* group-stretch friends */
   int32_t group_every;                         /* stationary-group refresh period (sweeps); 0 = never */
@@ -341,6 +341,13 @@ typedef struct {
   int32_t shift_ownership; /* 1: move strayed cold-chain sources (gb_sweep_shift_ownership) */
   double adapt_lag;        /* t0 of the adaptation's decay t0 / (t + t0), > 0 when adapting */
   double adapt_time;       /* nu, the adaptation's time scale, > 0 when adapting */
+  /* Sub-band width W in bins (even; 0: W = N).  Sub-band b covers bins
+   * [k_band0 + bW, k_band0 + (b+1)W); its sources' f0 range over the band
+   * widened by W/2 on each side, and its window, [k_band0 + bW - W/2 - N/2,
+   * k_band0 + (b+1)W + W/2 + N/2) (2W + N bins), holds every bin one of its
+   * templates reaches.  W != N needs window_sums in the state: the band
+   * loops keep their windows there (in LDS when W = N). */
+  int32_t band_width;
 } gbl_sweep_config;
 
 /* Sampler state: caller-owned device arrays (checkpointable as they are). */
@@ -376,10 +383,11 @@ typedef struct {
    * swaps of rungs (t-1, t) since the last adaptation (tempering adds to it,
    * the adaptation clears it); must start at zero. */
   int32_t* swap_acc;
-  /* Optional (NULL: the tempering pass rebuilds every set's templates):
-   * [n_temps][n_walkers][n_bands][2][3N] complex doubles, the sum of each
-   * source set's templates over its band's window [k_band0 + (b-1)N,
-   * k_band0 + (b+2)N) (A then E; zero outside the analysis band).  Every band
+  /* Optional (NULL: the tempering pass rebuilds every set's templates;
+   * required when band_width != N):
+   * [n_temps][n_walkers][n_bands][2][2W + N] complex doubles, the sum of each
+   * source set's templates over its band's window (A then E; zero outside the
+   * analysis band).  Every band
    * pass (moves 0 and 1) writes the entries of its parity; the tempering pass
    * of that parity reads them instead of rebuilding the templates and moves
    * them with the source sets it swaps, so they stay valid until the sets

@@ -840,6 +840,10 @@ static int sweep_check(gbl_ctx* ctx, const gbl_sweep_config* c, const gbl_sweep_
     return fail(ctx, GBL_EINVAL, "sweep: spectrum pool without flags or size%s");
   if (c->adapt_ladder && (!st->swap_acc || !(c->adapt_lag > 0.0) || !(c->adapt_time > 0.0)))
     return fail(ctx, GBL_EINVAL, "sweep: ladder adaptation needs swap_acc and positive adapt_lag, adapt_time%s");
+  if (c->band_width < 0 || (c->band_width & 1))
+    return fail(ctx, GBL_EINVAL, "sweep: band_width must be even and non-negative%s");
+  if (c->band_width != 0 && c->band_width != c->N && !st->window_sums)
+    return fail(ctx, GBL_EINVAL, "sweep: a band width other than N needs window_sums (the windows live there)%s");
   if (ctx->cfg.precision != GBL_FP64) return fail(ctx, GBL_EUNSUPPORTED, "sweep: FP64 contexts only%s");
   return GBL_OK;
 }
@@ -852,6 +856,7 @@ static gbl::SweepArgs sweep_args(const gbl_sweep_config* c, const gbl_sweep_stat
   a.n_slot = c->n_slots;
   a.n_prop = c->n_prop;
   a.n_friends = c->n_friends;
+  a.band_w = c->band_width > 0 ? c->band_width : c->N;
   a.k_band0 = c->k_band0;
   a.stretch_a = c->stretch_a;
   a.seed = c->seed;
@@ -887,9 +892,12 @@ static void launch_sweep_step(gbl_ctx* ctx, const gbl::SweepArgs& a, int move, i
   if (move == GBL_MOVE_PT)
     hipLaunchKernelGGL((gbl::k_sweep_pt<N>), dim3((unsigned)(nbp * a.n_w)), dim3(gbl::block_threads<N>()), 0,
                        ctx->stream, ctx->geo, tb, a, parity);
+  else if (a.band_w != N)  // the windows (2W + N bins) in global memory
+    hipLaunchKernelGGL((gbl::k_sweep_band<N, true>), dim3((unsigned)(nbp * a.n_w * a.n_t)),
+                       dim3(gbl::block_threads<N>()), 0, ctx->stream, ctx->geo, tb, a, move, parity);
   else
-    hipLaunchKernelGGL((gbl::k_sweep_band<N>), dim3((unsigned)(nbp * a.n_w * a.n_t)), dim3(gbl::block_threads<N>()),
-                       0, ctx->stream, ctx->geo, tb, a, move, parity);
+    hipLaunchKernelGGL((gbl::k_sweep_band<N, false>), dim3((unsigned)(nbp * a.n_w * a.n_t)),
+                       dim3(gbl::block_threads<N>()), 0, ctx->stream, ctx->geo, tb, a, move, parity);
 }
 
 static void sweep_adapt(gbl_ctx* ctx, const gbl_sweep_config* c, const gbl::SweepArgs& a) {

@@ -59,6 +59,7 @@ enum { kMoveInModel = 0, kMoveRJ = 1, kMovePT = 2, kMovePTPerm = 3 };
 
 struct SweepArgs {
   int n_t, n_w, n_b, n_slot, n_prop, n_friends;
+  int band_w;             // sub-band width W (bins)
   int64_t k_band0;
   double stretch_a;
   uint64_t seed;
@@ -79,13 +80,27 @@ struct SweepArgs {
   cd* spec_pool;          // optional pool of per-slot spectra, pool_size entries of n_slot x 2N
   int32_t* pool_flags;    // [pool_size], 0 = free
   int pool_size;
-  cd* wsum;               // optional [n_t][n_w][n_b][2][3N] window sums of the source sets
+  cd* wsum;               // optional [n_t][n_w][n_b][2][2W + N] window sums of the source sets
 };
 
-// window-sum entry of source set (t, w) in band b
+// Band b's window: every bin a template of the band can reach (f0 ranges over
+// [(b - 1/2) W, (b + 3/2) W) past k_band0, a template spans N bins around its
+// carrier): [k_band0 + bW - W/2 - N/2, ...), 2W + N bins; bands b-1..b+1 when
+// W = N.
+template <int N>
+__device__ __forceinline__ int64_t win_k0(const SweepArgs& a, int b) {
+  return a.k_band0 + (int64_t)b * a.band_w - a.band_w / 2 - N / 2;
+}
+
+template <int N>
+__host__ __device__ __forceinline__ int win_len(int band_w) {
+  return 2 * band_w + N;
+}
+
+// window-sum entry of source set (t, w) in band b (A, then E)
 template <int N>
 __device__ __forceinline__ cd* wsum_entry(const SweepArgs& a, int t, int w, int b) {
-  return a.wsum + (((int64_t)t * a.n_w + w) * a.n_b + b) * 6 * N;
+  return a.wsum + (((int64_t)t * a.n_w + w) * a.n_b + b) * 2 * win_len<N>(a.band_w);
 }
 
 __device__ __forceinline__ int64_t uidx(const SweepArgs& a, int t, int w, int b, int s) {
@@ -112,8 +127,9 @@ __device__ __forceinline__ double wrap_p(double x, double P) {
 
 template <int N>
 __device__ __forceinline__ void band_f0_range(const Geo& g, const SweepArgs& a, int b, double& lo, double& hi) {
-  lo = ((double)a.k_band0 + ((double)b - 0.5) * N) / g.T;
-  hi = ((double)a.k_band0 + ((double)b + 1.5) * N) / g.T;
+  const double W = (double)a.band_w;
+  lo = ((double)a.k_band0 + ((double)b - 0.5) * W) / g.T;
+  hi = ((double)a.k_band0 + ((double)b + 1.5) * W) / g.T;
 }
 
 // ln of the prior box volume of band b in sampling coordinates
@@ -304,9 +320,11 @@ __device__ __forceinline__ int pool_acquire(const SweepArgs& a) {
 // of a's window that need it at another offset.  The weights 1/S come from
 // HBM, fetched while the template is built.
 // ---------------------------------------------------------------------------
-template <int N>
+// GW: the window lives in global memory (the set's window-sum entry) instead
+// of LDS, for sub-bands wider than the template (2W + N bins) or N = 1024
+template <int N, bool GW>
 struct LoopSmem {
-  cd win[2][3 * N];               // residual window r' (channels A, E)
+  cd win[2][GW ? 1 : 3 * N];      // residual window r' (channels A, E), W = N in LDS
   cd buf[4 * series_pitch<N>()];  // FFT workspace; afterwards r's spectrum (A at [0, N), E at [N, 2N))
   double su[kMaxSlots][8];        // the band's slot coordinates during the loop
   double rdraw[kMaxSlots][9];     // RJ, per flip: acceptance draw, prior birth's coordinates;
@@ -327,8 +345,8 @@ struct LoopSmem {
 
 // u inside the band's prior box (kept in LDS rather than in registers across
 // the band loop); the same tests as in_prior
-template <int N>
-__device__ __forceinline__ bool loop_in_prior(const LoopSmem<N>& sm, const double* u) {
+template <int N, bool GW>
+__device__ __forceinline__ bool loop_in_prior(const LoopSmem<N, GW>& sm, const double* u) {
   if (!(u[1] >= sm.blo[1] && u[1] < sm.bhi[1])) return false;
 #pragma unroll
   for (int i = 0; i < 8; i++) {
@@ -389,8 +407,8 @@ __device__ __forceinline__ void loop_weights(const Geo& g, const double* __restr
 // Not inlined: the library functions' constants would otherwise be hoisted
 // out of the band loop and held in vector registers across it.
 // Block-uniform; contains barriers.
-template <int N>
-__device__ __noinline__ void loop_decode(const Geo& g, const double* u, LoopSmem<N>& sm) {
+template <int N, bool GW>
+__device__ __noinline__ void loop_decode(const Geo& g, const double* u, LoopSmem<N, GW>& sm) {
   constexpr int NT = block_threads<N>();
   static_assert(NT >= kWave, "band loops use whole waves");
   const int tid = threadIdx.x;
@@ -422,18 +440,18 @@ __device__ __noinline__ void loop_decode(const Geo& g, const double* u, LoopSmem
 // with wts, also the weights at the thread's bins of the template's window,
 // requested before the response and the FFT so that their latency hides
 // behind them.  Block-uniform; contains barriers.
-template <int N, int BPT>
+template <int N, int BPT, bool GW>
 __device__ __forceinline__ void loop_build(const Geo& g, const WaveTables<double>& tb, const double* u,
-                                           LoopSmem<N>& sm, const double* __restrict__ wts, double (&wh)[BPT][2],
+                                           LoopSmem<N, GW>& sm, const double* __restrict__ wts, double (&wh)[BPT][2],
                                            int tid) {
-  loop_decode<N>(g, u, sm);
+  loop_decode<N, GW>(g, u, sm);
   if (wts) loop_weights<N, BPT>(g, wts, sm.src.q - N / 2, wh, tid);
   template_transform<N, 4, double>(sm.src, g, tb, sm.buf, tid);
 }
 
 // spectrum of the built template at the thread's bins
-template <int N, int BPT>
-__device__ __forceinline__ void loop_bins(const Geo& g, const WaveTables<double>& tb, const LoopSmem<N>& sm,
+template <int N, int BPT, bool GW>
+__device__ __forceinline__ void loop_bins(const Geo& g, const WaveTables<double>& tb, const LoopSmem<N, GW>& sm,
                                           cd (&h)[BPT][2], int tid) {
   constexpr int NT = block_threads<N>();
 #pragma unroll
@@ -463,19 +481,31 @@ __device__ __forceinline__ void loop_load(const cd* src, cd (&h)[BPT][2], int ti
   }
 }
 
-// window += s h at the bins k0 + j inside it; with own, the same change also
-// goes (atomically) to that cold-chain buffer.  No closing barrier.
-template <int N, int BPT>
-__device__ __forceinline__ void loop_add(const Geo& g, LoopSmem<N>& sm, int64_t k0w, int64_t k0, double s,
-                                         const cd (&h)[BPT][2], cd* own, int tid) {
+// the window's element i of channel c: in LDS, or in global memory at
+// gw + c L + i
+template <int N, bool GW>
+__device__ __forceinline__ cd& win_at(LoopSmem<N, GW>& sm, cd* gw, int L, int c, int64_t i) {
+  if constexpr (GW)
+    return gw[c * L + i];
+  else
+    return sm.win[c][i];
+}
+
+// window += s h at the bins k0 + j inside it (window [k0w, k0w + L)); with
+// own, the same change also goes (atomically) to that cold-chain buffer.  No
+// closing barrier.
+template <int N, int BPT, bool GW>
+__device__ __forceinline__ void loop_add(const Geo& g, LoopSmem<N, GW>& sm, cd* gw, int L, int64_t k0w, int64_t k0,
+                                         double s, const cd (&h)[BPT][2], cd* own, int tid) {
   constexpr int NT = block_threads<N>();
 #pragma unroll
   for (int m = 0; m < BPT; m++) {
     const int64_t i = k0 + tid + NT * m - k0w;
-    if (i < 0 || i >= 3 * N) continue;
+    if (i < 0 || i >= L) continue;
 #pragma unroll
     for (int c = 0; c < 2; c++) {
-      sm.win[c][i] = sm.win[c][i] + cd{s * h[m][c].re, s * h[m][c].im};
+      cd& x = win_at<N, GW>(sm, gw, L, c, i);
+      x = x + cd{s * h[m][c].re, s * h[m][c].im};
       if (own) {
         const int64_t k = k0w + i - g.k_min;
         if (k >= 0 && k < g.n_bins) {
@@ -492,16 +522,16 @@ __device__ __forceinline__ void loop_add(const Geo& g, LoopSmem<N>& sm, int64_t 
 // the thread's bins: a (if has_a) at ka + j with weights wa, r (if has_r) at
 // kr + j with weights wr; with both, r's spectrum must also sit in sm.buf.
 // Block-uniform result.
-template <int N, int BPT>
-__device__ __forceinline__ double loop_dlogl(const Geo& g, LoopSmem<N>& sm, int64_t k0w, bool has_a, int64_t ka,
-                                             const cd (&av)[BPT][2], const double (&wa)[BPT][2], bool has_r,
-                                             int64_t kr, const cd (&rv)[BPT][2], const double (&wr)[BPT][2],
-                                             int tid) {
+template <int N, int BPT, bool GW>
+__device__ __forceinline__ double loop_dlogl(const Geo& g, LoopSmem<N, GW>& sm, cd* gw, int L, int64_t k0w,
+                                             bool has_a, int64_t ka, const cd (&av)[BPT][2],
+                                             const double (&wa)[BPT][2], bool has_r, int64_t kr,
+                                             const cd (&rv)[BPT][2], const double (&wr)[BPT][2], int tid) {
   constexpr int NT = block_threads<N>();
   double rd = 0.0, dd = 0.0;
   auto acc = [&](int64_t i, cd d0, cd d1, double w0, double w1) {
-    if (i < 0 || i >= 3 * N) return;
-    const cd R0 = sm.win[0][i], R1 = sm.win[1][i];
+    if (i < 0 || i >= L) return;
+    const cd R0 = win_at<N, GW>(sm, gw, L, 0, i), R1 = win_at<N, GW>(sm, gw, L, 1, i);
     rd += (R0.re * d0.re + R0.im * d0.im) * w0 + (R1.re * d1.re + R1.im * d1.im) * w1;
     dd += (d0.re * d0.re + d0.im * d0.im) * w0 + (d1.re * d1.re + d1.im * d1.im) * w1;
   };
@@ -531,12 +561,12 @@ __device__ __forceinline__ double loop_dlogl(const Geo& g, LoopSmem<N>& sm, int6
   return g.df4 * sums[0] - 0.5 * g.df4 * sums[1];
 }
 
-template <int N>
+template <int N, bool GW>
 __global__ __launch_bounds__(block_threads<N>(), 3) void k_sweep_band(Geo g, WaveTables<double> tb, SweepArgs a,
                                                                       int move, int parity) {
   constexpr int NT = block_threads<N>();
   constexpr int BPT = N / NT;  // window bins per thread
-  __shared__ LoopSmem<N> sm;
+  __shared__ LoopSmem<N, GW> sm;
   const int nbp = (a.n_b - parity + 1) / 2;  // bands of this parity
   const int bi = blockIdx.x % nbp;
   const int tw = blockIdx.x / nbp;
@@ -546,7 +576,9 @@ __global__ __launch_bounds__(block_threads<N>(), 3) void k_sweep_band(Geo g, Wav
   int tid = threadIdx.x;
   const int S = a.n_slot;
   const int64_t sweep = *a.sweep_ctr;
-  const int64_t k0w = a.k_band0 + (int64_t)(b - 1) * N;
+  const int64_t k0w = win_k0<N>(a, b);
+  const int L = win_len<N>(a.band_w);
+  cd* const gw = GW ? wsum_entry<N>(a, t, w, b) : nullptr;  // the window in global memory
   const double beta = a.betas[(int64_t)b * a.n_t + t];
   const uint64_t unit = ((uint64_t)t * a.n_w + w) * a.n_b + b;
   cd* own = (t == 0) ? a.resid + ((int64_t)(b & 1) * a.n_w + w) * 2 * g.n_bins : nullptr;
@@ -558,11 +590,11 @@ __global__ __launch_bounds__(block_threads<N>(), 3) void k_sweep_band(Geo g, Wav
   // spectra are recomputed)
   {
     const cd* opp = a.resid + ((int64_t)(1 - (b & 1)) * a.n_w + w) * 2 * g.n_bins;
-    for (int i = tid; i < 3 * N; i += NT) {
+    for (int i = tid; i < L; i += NT) {
       const int64_t k = k0w + i - g.k_min;
       const bool inb = k >= 0 && k < g.n_bins;
 #pragma unroll
-      for (int c = 0; c < 2; c++) sm.win[c][i] = inb ? opp[c * g.n_bins + k] : cd{0.0, 0.0};
+      for (int c = 0; c < 2; c++) win_at<N, GW>(sm, gw, L, c, i) = inb ? opp[c * g.n_bins + k] : cd{0.0, 0.0};
     }
   }
   for (int s = tid; s < S; s += NT) {
@@ -600,10 +632,10 @@ __global__ __launch_bounds__(block_threads<N>(), 3) void k_sweep_band(Geo g, Wav
   // the reversible-jump death of slot s, r's spectrum in rv (start kr,
   // weights wr); lra = ln of the acceptance draw
   auto death = [&](int s, double lra) {
-    const double dl = loop_dlogl<N, BPT>(g, sm, k0w, false, 0, av, wa, true, kr, rv, wr, tid);
+    const double dl = loop_dlogl<N, BPT, GW>(g, sm, gw, L, k0w, false, 0, av, wa, true, kr, rv, wr, tid);
     const double lpq = a.prop_u ? a.rj_logq[uidx(a, t, w, b, s)] + lvol : 0.0;
     if (lra < beta * dl + lpq) {
-      loop_add<N, BPT>(g, sm, k0w, kr, 1.0, rv, own, tid);
+      loop_add<N, BPT, GW>(g, sm, gw, L, k0w, kr, 1.0, rv, own, tid);
       if (tid == 0) sm.ex[s] = 0;
       n_dacc++;
     }
@@ -745,7 +777,7 @@ __global__ __launch_bounds__(block_threads<N>(), 3) void k_sweep_band(Geo g, Wav
             un[i] = X[i] + z * diff;
           }
         }
-        if (!reversible || !loop_in_prior<N>(sm, un)) continue;
+        if (!reversible || !loop_in_prior<N, GW>(sm, un)) continue;
         lr = rp[4];
         cur--;  // the move is under way
         if (tid < 8) {
@@ -796,7 +828,7 @@ __global__ __launch_bounds__(block_threads<N>(), 3) void k_sweep_band(Geo g, Wav
         // birth from the given proposal: ln p - ln q enters
         if (tid < 8) sm.u_new[tid] = a.prop_u[8 * uidx(a, t, w, b, s) + tid];
         __syncthreads();
-        if (!loop_in_prior<N>(sm, sm.u_new)) {
+        if (!loop_in_prior<N, GW>(sm, sm.u_new)) {
           __syncthreads();
           cur++;
           continue;
@@ -813,13 +845,13 @@ __global__ __launch_bounds__(block_threads<N>(), 3) void k_sweep_band(Geo g, Wav
     if (phase == 2) break;
 
     // ---- the template build (the only one)
-    loop_build<N, BPT>(g, tbl, ub, sm, kind == kSetup ? nullptr : wts, wh, tid);
-    loop_bins<N, BPT>(g, tbl, sm, hv, tid);
+    loop_build<N, BPT, GW>(g, tbl, ub, sm, kind == kSetup ? nullptr : wts, wh, tid);
+    loop_bins<N, BPT, GW>(g, tbl, sm, hv, tid);
     const int64_t kh = sm.src.q - N / 2;
     if (kind == kSetup) {
       // the band's residual: remove the slot's source, keep its spectrum
       if (spec) loop_store<N, BPT>(spec + (int64_t)cur * 2 * N, hv, tid);
-      loop_add<N, BPT>(g, sm, k0w, kh, -1.0, hv, nullptr, tid);
+      loop_add<N, BPT, GW>(g, sm, gw, L, k0w, kh, -1.0, hv, nullptr, tid);
       if (tid == 0) sm.sq[cur] = sm.src.q;
       __syncthreads();
       cur++;
@@ -859,9 +891,9 @@ __global__ __launch_bounds__(block_threads<N>(), 3) void k_sweep_band(Geo g, Wav
         sm.buf[N + tid + NT * m] = rv[m][1];
       }
       __syncthreads();
-      dl = loop_dlogl<N, BPT>(g, sm, k0w, true, ka, av, wa, true, kr, rv, wr, tid);
+      dl = loop_dlogl<N, BPT, GW>(g, sm, gw, L, k0w, true, ka, av, wa, true, kr, rv, wr, tid);
     } else {
-      dl = loop_dlogl<N, BPT>(g, sm, k0w, true, ka, av, wa, false, 0, rv, wr, tid);
+      dl = loop_dlogl<N, BPT, GW>(g, sm, gw, L, k0w, true, ka, av, wa, false, 0, rv, wr, tid);
     }
     double thr;
     if (inmodel)
@@ -872,10 +904,10 @@ __global__ __launch_bounds__(block_threads<N>(), 3) void k_sweep_band(Geo g, Wav
       thr = beta * dl;
     if (lr_acc < thr) {
       if (spec) loop_store<N, BPT>(spec + (int64_t)sk * 2 * N, av, tid);
-      loop_add<N, BPT>(g, sm, k0w, ka, -1.0, av, own, tid);
+      loop_add<N, BPT, GW>(g, sm, gw, L, k0w, ka, -1.0, av, own, tid);
       __syncthreads();
       if (inmodel) {
-        loop_add<N, BPT>(g, sm, k0w, kr, 1.0, rv, own, tid);
+        loop_add<N, BPT, GW>(g, sm, gw, L, k0w, kr, 1.0, rv, own, tid);
         // the moved slot's friend window (every wave searches, one thread writes)
         const int st = friend_start(grp, G, nf, sm.u_new[1]);
         if (tid == 0) sm.fstart[sk] = st;
@@ -892,14 +924,16 @@ __global__ __launch_bounds__(block_threads<N>(), 3) void k_sweep_band(Geo g, Wav
   }
   // the set's window sum for the tempering pass: H = (opposite-parity
   // window) - (final window); that buffer does not change during the pass
+  // (in place when the window is the entry itself)
   if (a.wsum) {
     const cd* opp = a.resid + ((int64_t)(1 - (b & 1)) * a.n_w + w) * 2 * g.n_bins;
     cd* H = wsum_entry<N>(a, t, w, b);
-    for (int i = tid; i < 3 * N; i += NT) {
+    for (int i = tid; i < L; i += NT) {
       const int64_t k = k0w + i - g.k_min;
       const bool inb = k >= 0 && k < g.n_bins;
 #pragma unroll
-      for (int c = 0; c < 2; c++) H[c * 3 * N + i] = inb ? opp[c * g.n_bins + k] - sm.win[c][i] : cd{0.0, 0.0};
+      for (int c = 0; c < 2; c++)
+        H[c * L + i] = inb ? opp[c * g.n_bins + k] - win_at<N, GW>(sm, gw, L, c, i) : cd{0.0, 0.0};
     }
   }
   for (int s = tid; s < S; s += NT) {
@@ -973,21 +1007,21 @@ __device__ __forceinline__ void band_set_sum(const Geo& g, const WaveTables<doub
   }
 }
 
-// band log-likelihood -1/2 <R - H | R - H> over band b's window, R = walker
-// w_res's opposite-parity buffer, weights 1/S of w_res
+// band log-likelihood -1/2 <R - H | R - H> over band b's window [k0w, k0w +
+// L), R = walker w_res's opposite-parity buffer, weights 1/S of w_res
 template <int N>
 __device__ __forceinline__ double band_set_loglike_h(const Geo& g, const SweepArgs& a, int b, int w_res, int64_t k0w,
-                                                     const cd* H, BandSmem<N>& sm) {
+                                                     int L, const cd* H, BandSmem<N>& sm) {
   constexpr int NT = block_threads<N>();
   const cd* opp = a.resid + ((int64_t)(1 - (b & 1)) * a.n_w + w_res) * 2 * g.n_bins;
   const double* ip = a.inv_psd + (int64_t)w_res * 2 * g.n_bins;
   double rr = 0.0;
-  for (int i = threadIdx.x; i < 3 * N; i += NT) {
+  for (int i = threadIdx.x; i < L; i += NT) {
     const int64_t k = k0w + i - g.k_min;
     if (k < 0 || k >= g.n_bins) continue;
 #pragma unroll
     for (int c = 0; c < 2; c++) {
-      const cd r = opp[c * g.n_bins + k] - H[c * 3 * N + i];
+      const cd r = opp[c * g.n_bins + k] - H[c * L + i];
       rr += (r.re * r.re + r.im * r.im) * ip[c * g.n_bins + k];
     }
   }
@@ -1011,7 +1045,8 @@ __global__ __launch_bounds__(block_threads<N>()) void k_sweep_pt(Geo g, WaveTabl
   const int tid = threadIdx.x;
   const int nt = a.n_t;
   const int64_t sweep = *a.sweep_ctr;
-  const int64_t k0w = a.k_band0 + (int64_t)(b - 1) * N;
+  const int64_t k0w = win_k0<N>(a, b);
+  const int L = win_len<N>(a.band_w);  // 3N unless the window sums carry wider windows
   // walker of pairing i at temperature t: entry i of a uniform permutation of
   // the walkers (Fisher-Yates from the top: position j swaps with r_j <= j).
   // Each temperature's thread follows position i back through the swaps
@@ -1039,24 +1074,24 @@ __global__ __launch_bounds__(block_threads<N>()) void k_sweep_pt(Geo g, WaveTabl
   const bool Hs = ws || Hp;
   auto Hof = [&](int t) { return ws ? wsum_entry<N>(a, t, wt[t], b) : Hp + (int64_t)hidx[t] * 6 * N; };
   for (int t = 0; t < nt; t++) {
-    double L;
+    double lnl;
     if (ws) {
-      L = band_set_loglike_h<N>(g, a, b, wt[t], k0w, Hof(t), sm);
+      lnl = band_set_loglike_h<N>(g, a, b, wt[t], k0w, L, Hof(t), sm);
     } else if (Hs) {
       band_set_sum<N>(g, tb, a, t, wt[t], b, k0w, sm, Hof(t));
-      L = band_set_loglike_h<N>(g, a, b, wt[t], k0w, Hof(t), sm);
+      lnl = band_set_loglike_h<N>(g, a, b, wt[t], k0w, L, Hof(t), sm);
     } else {
-      L = band_set_loglike<N>(g, tb, a, t, wt[t], b, wt[t], k0w, sm);
+      lnl = band_set_loglike<N>(g, tb, a, t, wt[t], b, wt[t], k0w, sm);
     }
-    if (tid == 0) Lc[t] = L;
+    if (tid == 0) Lc[t] = lnl;
   }
   __syncthreads();
   const double* bt = a.betas + (int64_t)b * nt;
   unsigned long long n_prop = 0, n_acc = 0;
   for (int t = nt - 1; t >= 1; t--) {
-    const double L1 = Hs ? band_set_loglike_h<N>(g, a, b, wt[t], k0w, Hof(t - 1), sm)
+    const double L1 = Hs ? band_set_loglike_h<N>(g, a, b, wt[t], k0w, L, Hof(t - 1), sm)
                          : band_set_loglike<N>(g, tb, a, t - 1, wt[t - 1], b, wt[t], k0w, sm);
-    const double L2 = Hs ? band_set_loglike_h<N>(g, a, b, wt[t - 1], k0w, Hof(t), sm)
+    const double L2 = Hs ? band_set_loglike_h<N>(g, a, b, wt[t - 1], k0w, L, Hof(t), sm)
                          : band_set_loglike<N>(g, tb, a, t, wt[t], b, wt[t - 1], k0w, sm);
     const double la = bt[t] * (L1 - Lc[t]) + bt[t - 1] * (L2 - Lc[t - 1]);
     const double r = rng_uniform(a.seed, sweep, kMovePT, (uint64_t)b * a.n_w + i, (uint64_t)t);
@@ -1069,12 +1104,12 @@ __global__ __launch_bounds__(block_threads<N>()) void k_sweep_pt(Geo g, WaveTabl
         cd* own = a.resid + ((int64_t)(b & 1) * a.n_w + wt[0]) * 2 * g.n_bins;
         const cd* H0 = Hof(0);
         const cd* H1 = Hof(1);
-        for (int i2 = tid; i2 < 3 * N; i2 += block_threads<N>()) {
+        for (int i2 = tid; i2 < L; i2 += block_threads<N>()) {
           const int64_t k = k0w + i2 - g.k_min;
           if (k < 0 || k >= g.n_bins) continue;
 #pragma unroll
           for (int c = 0; c < 2; c++) {
-            const cd d = H0[c * 3 * N + i2] - H1[c * 3 * N + i2];
+            const cd d = H0[c * L + i2] - H1[c * L + i2];
             double* dst = reinterpret_cast<double*>(own + c * g.n_bins + k);
             atomicAdd(dst, d.re);
             atomicAdd(dst + 1, d.im);
@@ -1100,7 +1135,7 @@ __global__ __launch_bounds__(block_threads<N>()) void k_sweep_pt(Geo g, WaveTabl
       if (ws) {
         cd* h1 = Hof(t);
         cd* h2 = Hof(t - 1);
-        for (int i2 = tid; i2 < 6 * N; i2 += block_threads<N>()) {
+        for (int i2 = tid; i2 < 2 * L; i2 += block_threads<N>()) {
           const cd tmp = h1[i2];
           h1[i2] = h2[i2];
           h2[i2] = tmp;
@@ -1429,8 +1464,8 @@ __global__ __launch_bounds__(block_threads<N>()) void k_sweep_shift(Geo g, WaveT
       const int64_t ui = uidx(a, 0, w, b, s);
       if (!a.exists[ui]) continue;  // uniform: every thread reads the same flag
       const double f0 = a.u[8 * ui + 1];
-      const double lo = (double)(a.k_band0 + (int64_t)b * N) / g.T;
-      const double hi = (double)(a.k_band0 + (int64_t)(b + 1) * N) / g.T;
+      const double lo = (double)(a.k_band0 + (int64_t)b * a.band_w) / g.T;
+      const double hi = (double)(a.k_band0 + (int64_t)(b + 1) * a.band_w) / g.T;
       const int bb = f0 < lo ? b - 1 : (f0 >= hi ? b + 1 : b);
       if (bb == b || bb < 0 || bb >= a.n_b) continue;
       int s2 = -1;

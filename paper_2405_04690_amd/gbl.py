@@ -61,7 +61,7 @@ class SweepConfig(ctypes.Structure):
                 ("stretch_a", ctypes.c_double), ("seed", ctypes.c_uint64),
                 ("prior_lo", ctypes.c_double * 8), ("prior_hi", ctypes.c_double * 8),
                 ("adapt_ladder", ctypes.c_int32), ("shift_ownership", ctypes.c_int32),
-                ("adapt_lag", ctypes.c_double), ("adapt_time", ctypes.c_double)]
+                ("adapt_lag", ctypes.c_double), ("adapt_time", ctypes.c_double), ("band_width", ctypes.c_int32)]
 
 
 class SweepState(ctypes.Structure):

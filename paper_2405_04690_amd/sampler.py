@@ -23,15 +23,17 @@ DEFAULT_PRIOR_HI = (-21.0, 0.0, 1e-15, 0.0, 1.0, 0.0, 0.0, 1.0)
 
 def make_config(n_temps, n_walkers, n_bands, n_slots, N, k_band0, n_prop=10, n_friends=8, group_every=30,
                 stretch_a=2.0, seed=1234, prior_lo=DEFAULT_PRIOR_LO, prior_hi=DEFAULT_PRIOR_HI, cls=SweepConfig,
-                adapt_ladder=False, shift_ownership=False, adapt_lag=10000.0, adapt_time=100.0):
+                adapt_ladder=False, shift_ownership=False, adapt_lag=10000.0, adapt_time=100.0, band_width=0):
     """adapt_lag / adapt_time: t0 and nu of the ladder adaptation's step
-    t0 / (nu (t + t0)) (defaults as commonly used with the Vousden scheme)"""
+    t0 / (nu (t + t0)) (defaults as commonly used with the Vousden scheme);
+    band_width: sub-band width W in bins (even; 0: W = N)"""
     c = cls()
     c.n_temps, c.n_walkers, c.n_bands, c.n_slots = n_temps, n_walkers, n_bands, n_slots
     c.N, c.n_prop, c.n_friends, c.group_every = N, n_prop, n_friends, group_every
     c.k_band0, c.stretch_a, c.seed = k_band0, stretch_a, seed
     c.adapt_ladder, c.shift_ownership = int(bool(adapt_ladder)), int(bool(shift_ownership))
     c.adapt_lag, c.adapt_time = float(adapt_lag), float(adapt_time)
+    c.band_width = int(band_width)
     for i in range(8):
         c.prior_lo[i] = prior_lo[i]
         c.prior_hi[i] = prior_hi[i]
@@ -67,10 +69,14 @@ class Sweep:
             self.spec_pool = torch.zeros((spectrum_pool, entry), dtype=torch.complex128, device=dev)
             self.pool_flags = torch.zeros(spectrum_pool, dtype=torch.int32, device=dev)
         # window sums of the source sets, written by the band passes for the
-        # tempering pass (n_temps x n_walkers x n_bands x 6N complex doubles)
+        # tempering pass (n_temps x n_walkers x n_bands x 2 (2W + N) complex
+        # doubles); required for sub-bands wider than the template, whose
+        # windows live there during the band passes
+        self.band_width = cfg.band_width if cfg.band_width > 0 else cfg.N
         self.window_sums = None
-        if window_sums:
-            self.window_sums = torch.zeros((nt, nw, nb, 6 * cfg.N), dtype=torch.complex128, device=dev)
+        if window_sums or self.band_width != cfg.N:
+            L = 2 * self.band_width + cfg.N
+            self.window_sums = torch.zeros((nt, nw, nb, 2 * L), dtype=torch.complex128, device=dev)
         self._graph = None
 
     def enable_proposals(self):

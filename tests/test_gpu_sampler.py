@@ -75,6 +75,28 @@ def test_sweep_parity_each_move(N, pool, ws):
     ctx.close()
 
 
+@pytest.mark.parametrize("N,W,pool", [(128, 384, 1024), (256, 200, 0), (256, 1000, 1024)])
+def test_sweep_parity_wide_subbands(N, W, pool):
+    """sub-bands of W bins with templates of N bins (the band loops keep their
+    2W + N-bin windows in global memory, in the window-sum entries): every
+    move against the oracle, decisions and counters exact"""
+    cfg, orc, sc, st = sampler_setup.problem(N=N, n_b=4, W=W)
+    ctx, sw = _gpu_sweep(cfg, sc, st, pool=pool)
+    assert sw.window_sums is not None and sw.window_sums.shape[-1] == 2 * (2 * W + N)
+    s0 = 12
+    sw.sweep_counter.fill_(s0)
+    oracle.sweep_group(sc, st)
+    sw.group_refresh()
+    for move, name in ((0, "in-model"), (1, "rj"), (2, "tempering")):
+        for parity in (1, 0):
+            print(f"wide sub-bands N={N} W={W}: {name} parity {parity}", flush=True)
+            oracle.sweep_step(orc, sc, st, move, parity, s0)
+            sw.step(move, parity)
+            _compare(sw, st, f"W={W} {name}/{parity}")
+    assert st.stats[1] > 0 and st.stats[3] + st.stats[5] > 0 and st.stats[7] > 0
+    ctx.close()
+
+
 def test_sweep_run_and_graph_replay():
     cfg, orc, sc, st = sampler_setup.problem(n_t=2, n_w=3, n_b=4, n_slots=3, n_prop=4, group_every=2, seed=5)
     st_ref = oracle.SweepState(sc, orc.n_bins)
