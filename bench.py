@@ -35,14 +35,14 @@ def measured_traffic():
     rocprofv3 counter runs recorded under profiles/ (FETCH_SIZE, WRITE_SIZE,
     scaled by a plain copy of known size), or None once the kernel sources
     differ from the profiled ones."""
-    import glob
     import hashlib
     path = os.path.join(HERE, "profiles", "k_delta_loglike_fp64_N256_traffic.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    files = sorted(glob.glob(os.path.join(HERE, "paper_2405_04690_amd", "csrc", "*.hpp")) +
-                   glob.glob(os.path.join(HERE, "paper_2405_04690_amd", "csrc", "*.hip")))
+    # the sources the two kernels and their launch are built from
+    files = [os.path.join(HERE, "paper_2405_04690_amd", "csrc", f)
+             for f in ("gbl_device.hpp", "gbl_kernels.hpp", "gbl.hip")]
     h = hashlib.sha256()
     for f in files:
         h.update(os.path.basename(f).encode())
@@ -417,16 +417,22 @@ def sweep_bench(torch, dev, stream, n_sweeps, n_temps=36, n_walkers=32, n_prop=3
     return out
 
 
+LEARNED_RJ_BAND_HZ = 1e-4   # sub-band width of the learned-proposal configuration
+
+
 def rj_bench(torch, dev, stream):
     """Learned (flow) versus prior RJ proposal on the same problem: 1 yr,
-    N = 256 sub-bands from 3 mHz, one loud (SNR 20) and one near-threshold
-    (SNR 7) source per sub-band, 8 temperatures x 32 walkers; flow trained on
-    the prior-RJ chain's cold samples with the library's BF16 kernels; then
-    the same number of sweeps from the same state with each proposal."""
+    1e-4 Hz sub-bands (3,156 bins) from 3 mHz with N = 256 templates, one loud
+    (SNR 20) and one near-threshold (SNR 7) source per sub-band, 8
+    temperatures x 32 walkers; flow trained on the prior-RJ chain's cold
+    samples with the library's BF16 kernels; then the same number of sweeps
+    from the same state with each proposal.  Three problem seeds, and the
+    first seed once more with sub-bands as wide as the template."""
     from paper_2405_04690_amd import inputs, learned_rj
+    W = 2 * int(round(0.5 * LEARNED_RJ_BAND_HZ * inputs.PAPER.T))
     with torch.cuda.stream(stream):
         prob = learned_rj.build(cfg=inputs.PAPER, N=256, n_temps=8, n_walkers=32, n_bands=16, n_slots=6, seed=60,
-                                stream=stream)
+                                stream=stream, W=W)
         res, flow = learned_rj.compare(prob, burn=50, collect_sweeps=100, train_steps=300, measure_sweeps=600,
                                        equilibrate=1000)
         for m in ("plain", "learned"):
@@ -452,7 +458,8 @@ def rj_bench(torch, dev, stream):
         res["flow_samples_per_s"] = round(2 * n_slots / (ms / 1e3), 1)
         res["flow_mfma_tflops"] = round(flops / (ms / 1e3) / 1e12, 3)
         res["flow_mfma_frac_bf16_peak"] = round(flops / (ms / 1e3) / 1e12 / 2500.0, 5)
-        res["workload"] = ("1 yr, 16 sub-bands of N=256 from 3 mHz, SNR 20 + SNR 7 source per sub-band, "
+        res["workload"] = (f"1 yr, 16 sub-bands of 1e-4 Hz ({W} bins) from 3 mHz, templates of N=256, "
+                           "SNR 20 + SNR 7 source per sub-band, "
                            "amplitude prior from SNR 5, 8 temps x 32 walkers x 6 slots; burn 50, collect 100, "
                            "train 300 x 4096, 1000 sweeps of equilibration with the flow mixture, then 600 "
                            "sweeps per proposal from that state (ESS; stationarity: both chains' mean k and "
@@ -470,7 +477,7 @@ def rj_bench(torch, dev, stream):
                     "mean_k": [[res["plain"]["mean_k"], res["learned"]["mean_k"]]]}
         for seed in (61, 62):
             p2 = learned_rj.build(cfg=inputs.PAPER, N=256, n_temps=8, n_walkers=32, n_bands=16, n_slots=6,
-                                  seed=seed, stream=stream)
+                                  seed=seed, stream=stream, W=W)
             r2, _ = learned_rj.compare(p2, burn=50, collect_sweeps=100, train_steps=300, measure_sweeps=600,
                                        equilibrate=1000)
             per_seed["seed"].append(seed)
@@ -486,6 +493,17 @@ def rj_bench(torch, dev, stream):
         for k in ("discovery_learned_mean", "discovery_plain_mean"):
             per_seed[k] = [[round(x, 4) for x in v] for v in per_seed[k]]
         res["seeds"] = per_seed
+        # the first seed with sub-bands as wide as the template (N = 256 bins)
+        p3 = learned_rj.build(cfg=inputs.PAPER, N=256, n_temps=8, n_walkers=32, n_bands=16, n_slots=6, seed=60,
+                              stream=stream)
+        r3, _ = learned_rj.compare(p3, burn=50, collect_sweeps=100, train_steps=300, measure_sweeps=600,
+                                   equilibrate=1000)
+        res["narrow_subbands_seed60"] = {
+            "band_bins": 256, "gain_ess_k_per_s": round(r3["gain_ess_k_per_s"], 4),
+            "gain_ess_logl_per_s": round(r3["gain_ess_logl_per_s"], 4), "stationarity": r3["stationarity"],
+            "discovery_mean": {m: [round(x, 4) for x in r3["discovery"][m]["mean"]] for m in ("plain", "learned")}}
+        p3.ctx.close()
+        res["band_bins"] = W
     return res
 
 
@@ -505,6 +523,8 @@ def _rj_summary(r):
     out["discovery_mean_recovered"] = {
         "plain": [round(float(np.mean([d[j] for d in sd["discovery_plain_mean"]])), 4) for j in (0, 1)],
         "learned": [round(float(np.mean([d[j] for d in sd["discovery_learned_mean"]])), 4) for j in (0, 1)]}
+    out["band_bins"] = r.get("band_bins")
+    out["narrow_subbands_seed60"] = r.get("narrow_subbands_seed60")
     return out
 
 

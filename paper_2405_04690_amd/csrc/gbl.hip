@@ -1211,7 +1211,8 @@ static int rj_prepare(gbl_ctx* ctx, const gbl_sweep_config* cfg, const gbl_sweep
   int rc = flow_check(ctx, fcfg, fl);
   if (rc) return rc;
   if (!st->prop_u || !st->rj_logq) return fail(ctx, GBL_EINVAL, "gb_sweep_rj_prepare: prop_u / rj_logq not set%s");
-  if (fcfg->n_emb != cfg->n_bands || fcfg->width != cfg->N || fcfg->k_band0 != cfg->k_band0)
+  const int32_t band_w = cfg->band_width > 0 ? cfg->band_width : cfg->N;
+  if (fcfg->n_emb != cfg->n_bands || fcfg->width != band_w || fcfg->k_band0 != cfg->k_band0)
     return fail(ctx, GBL_EINVAL, "gb_sweep_rj_prepare: flow box differs from the sweep's sub-bands%s");
   const int dims[4] = {0, 2, 4, 7};
   for (int i : dims)

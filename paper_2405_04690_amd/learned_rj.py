@@ -2,9 +2,10 @@
 RJ acceptance and effective samples per second (Sec. 4 "Online updating of RJ
 sampling distributions"; the flow replaces the paper's fitted mixtures).
 
-Problem: sub-bands of width N from bin k_band0, each holding one loud and one
-near-threshold injected source in stationary Gaussian noise; every chain
-starts from the injections.  The sampler first runs with prior RJ draws and
+Problem: sub-bands of W bins from bin k_band0 (templates of N bins; W = N, or
+wider, e.g. 1e-4 Hz as in the learned-proposal configuration), each holding
+one loud and one near-threshold injected source in stationary Gaussian noise;
+every chain starts from the injections.  The sampler first runs with prior RJ draws and
 collects cold-chain samples; the flow is trained on them with the library's
 own training kernels.  Two measurements follow, each once with prior RJ
 draws and once with the flow mixture (prior share 0.2) as the RJ proposal:
@@ -14,7 +15,9 @@ sweeps runs with each proposal, recording per sweep the cold chain's source
 count and band log-likelihood per (walker, band) for their ESS per second;
 both chains must then agree on the mean source count and mean cold
 log-likelihood within their Monte Carlo errors (the check that the
-comparison is stationary is reported next to the ratios); (2) discovery: from every slot
+comparison is stationary is reported next to the ratios; the error is the
+larger of the autocorrelation-based one and the spread of the per-walker
+means, the walkers being independent chains); (2) discovery: from every slot
 empty, the fraction of (walker, injected source) pairs the cold chain has
 recovered per sweep.  Everything runs through the C ABI; only the
 bookkeeping (trace copies, ESS, recovery fractions) is host-side.
@@ -66,12 +69,14 @@ def _physical(u):
 
 
 def build(cfg=inputs.TINY, N=128, n_temps=4, n_walkers=32, n_bands=8, n_slots=6, snr=(20.0, 7.0), seed=60,
-          f_start=3e-3, stream=None, snr_min: float = SNR_MIN) -> Problem:
+          f_start=3e-3, stream=None, snr_min: float = SNR_MIN, W: int | None = None) -> Problem:
+    """W: sub-band width in bins (even; None: the template width N)"""
     dev = torch.device("cuda", torch.cuda.current_device())
     ctx = Context(T=cfg.T, dt=cfg.dt, L=cfg.L, f_lo=cfg.f_lo, f_hi=cfg.f_hi, device=dev, stream=stream)
     T = cfg.T
     k_band0 = int(f_start * T)
-    src = inputs.band_sources(seed, n_bands, len(snr), T, k_band0, N)
+    W = N if W is None else int(W)
+    src = inputs.band_sources(seed, n_bands, len(snr), T, k_band0, W)
     noise = torch.tensor([[cfg.sqrt_oms, cfg.sqrt_acc, cfg.sqrt_oms, cfg.sqrt_acc]], dtype=torch.float64, device=dev)
     S = ctx.gb_psd_eval(noise)
     invS = ctx.gb_psd_eval(noise, inverse=True)
@@ -90,7 +95,7 @@ def build(cfg=inputs.TINY, N=128, n_temps=4, n_walkers=32, n_bands=8, n_slots=6,
     d = ctx.gb_make_noise(S, torch.from_numpy(inputs.complex_normals(seed + 1, (1, 2, ctx.n_bins))).to(dev))
     ctx.gb_scatter_add(torch.from_numpy(src).to(dev), N, 1.0, d)
     sc = make_config(n_temps, n_walkers, n_bands, n_slots, N, k_band0, n_prop=20, n_friends=8, group_every=10,
-                     seed=seed + 2, prior_lo=prior_lo, prior_hi=prior_hi)
+                     seed=seed + 2, prior_lo=prior_lo, prior_hi=prior_hi, band_width=0 if W == N else W)
     sw = Sweep(ctx, sc)
     u0 = np.zeros((n_bands, n_slots, 8))
     e0 = np.zeros((n_bands, n_slots), np.int32)
@@ -110,7 +115,7 @@ def build(cfg=inputs.TINY, N=128, n_temps=4, n_walkers=32, n_bands=8, n_slots=6,
         sel = (sw.exists[0] != 0) & (band_par == par)
         ctx.gb_scatter_add(_physical(sw.u[0][sel].contiguous()), N, -1.0, sw.resid[par], walker[sel].contiguous())
     sw.enable_logl_trace()
-    fcfg = flow_config(n_bands, N, k_band0, prior_lo, prior_hi)
+    fcfg = flow_config(n_bands, W, k_band0, prior_lo, prior_hi)
     torch.cuda.synchronize()
     return Problem(ctx, sw, fcfg, src, target, d)
 
@@ -196,10 +201,14 @@ def measure(sw: Sweep, n_sweeps: int, flow: Flow | None = None):
     ess_k = float(sum(ess_kb))
     ess_l = float(sum(ess_lb))
     # Monte Carlo error of the band-summed means: per band var / ESS, summed
-    # over the (independent) bands, then divided by the band count squared
-    nb = k.shape[1]
+    # over the (independent) bands, then divided by the band count squared;
+    # and from the spread of the per-walker means (independent chains); the
+    # larger of the two is reported
+    nb, nw = k.shape[1], k.shape[0]
     se_k = float(np.sqrt(sum(k[:, b, :].var() / max(e, 1.0) for b, e in enumerate(ess_kb))) / nb)
     se_l = float(np.sqrt(sum(lnl[:, b, :].var() / max(e, 1.0) for b, e in enumerate(ess_lb))) / nb)
+    se_k = max(se_k, float(k.mean(axis=(1, 2)).std(ddof=1) / np.sqrt(nw)))
+    se_l = max(se_l, float(lnl.mean(axis=(1, 2)).std(ddof=1) / np.sqrt(nw)))
     return {"sweeps": n_sweeps, "wall_s": wall,
             "birth_acceptance": float(dst[3]) / max(1.0, float(dst[2])),
             "death_acceptance": float(dst[5]) / max(1.0, float(dst[4])),
