@@ -328,7 +328,7 @@ int gb_make_noise(gbl_ctx* ctx, const double* S, const double* normals, int64_t 
 
 typedef struct {
   int32_t n_temps, n_walkers, n_bands, n_slots; /* n_slots <= 64, n_temps and n_walkers <= 256 */
-  int32_t N;                                   /* template width */
+  int32_t N;                                   /* template width: 128, 256, 512 or 1024 */
   int32_t n_prop;                              /* in-model proposals per band per sweep */
   int32_t n_friends;                           /* group-stretch friends */
   int32_t group_every;                         /* stationary-group refresh period (sweeps); 0 = never */
@@ -345,8 +345,8 @@ typedef struct {
    * [k_band0 + bW, k_band0 + (b+1)W); its sources' f0 range over the band
    * widened by W/2 on each side, and its window, [k_band0 + bW - W/2 - N/2,
    * k_band0 + (b+1)W + W/2 + N/2) (2W + N bins), holds every bin one of its
-   * templates reaches.  W != N needs window_sums in the state: the band
-   * loops keep their windows there (in LDS when W = N). */
+   * templates reaches.  W != N, and N = 1024, need window_sums in the
+   * state: the band loops keep their windows there (in LDS otherwise). */
   int32_t band_width;
 } gbl_sweep_config;
 

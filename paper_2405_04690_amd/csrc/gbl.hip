@@ -827,7 +827,8 @@ extern "C" int gb_make_noise(gbl_ctx* ctx, const double* S, const double* normal
 // ---------------------------------------------------------------------------
 static int sweep_check(gbl_ctx* ctx, const gbl_sweep_config* c, const gbl_sweep_state* st) {
   if (!c || !st) return fail(ctx, GBL_EINVAL, "sweep: null config or state%s");
-  if (c->N != 128 && c->N != 256 && c->N != 512) return fail(ctx, GBL_EUNSUPPORTED, "sweep: N must be 128, 256 or 512%s");
+  if (c->N != 128 && c->N != 256 && c->N != 512 && c->N != 1024)
+    return fail(ctx, GBL_EUNSUPPORTED, "sweep: N must be 128, 256, 512 or 1024%s");
   if (c->n_temps < 1 || c->n_temps > 256 || c->n_walkers < 1 || c->n_walkers > 256 || c->n_bands < 1 ||
       c->n_slots < 1 || c->n_slots > gbl::kMaxSlots || c->n_prop < 0 || c->n_friends < 1 || !(c->stretch_a > 1.0))
     return fail(ctx, GBL_EINVAL, "sweep: configuration out of range%s");
@@ -842,8 +843,9 @@ static int sweep_check(gbl_ctx* ctx, const gbl_sweep_config* c, const gbl_sweep_
     return fail(ctx, GBL_EINVAL, "sweep: ladder adaptation needs swap_acc and positive adapt_lag, adapt_time%s");
   if (c->band_width < 0 || (c->band_width & 1))
     return fail(ctx, GBL_EINVAL, "sweep: band_width must be even and non-negative%s");
-  if (c->band_width != 0 && c->band_width != c->N && !st->window_sums)
-    return fail(ctx, GBL_EINVAL, "sweep: a band width other than N needs window_sums (the windows live there)%s");
+  if (((c->band_width != 0 && c->band_width != c->N) || c->N == 1024) && !st->window_sums)
+    return fail(ctx, GBL_EINVAL,
+                "sweep: a band width other than N, or N = 1024, needs window_sums (the windows live there)%s");
   if (ctx->cfg.precision != GBL_FP64) return fail(ctx, GBL_EUNSUPPORTED, "sweep: FP64 contexts only%s");
   return GBL_OK;
 }
@@ -892,12 +894,12 @@ static void launch_sweep_step(gbl_ctx* ctx, const gbl::SweepArgs& a, int move, i
   if (move == GBL_MOVE_PT)
     hipLaunchKernelGGL((gbl::k_sweep_pt<N>), dim3((unsigned)(nbp * a.n_w)), dim3(gbl::block_threads<N>()), 0,
                        ctx->stream, ctx->geo, tb, a, parity);
-  else if (a.band_w != N)  // the windows (2W + N bins) in global memory
+  else if (a.band_w != N || N == 1024)  // the windows (2W + N bins) in global memory
     hipLaunchKernelGGL((gbl::k_sweep_band<N, true>), dim3((unsigned)(nbp * a.n_w * a.n_t)),
-                       dim3(gbl::block_threads<N>()), 0, ctx->stream, ctx->geo, tb, a, move, parity);
-  else
+                       dim3(gbl::loop_threads<N>()), 0, ctx->stream, ctx->geo, tb, a, move, parity);
+  else if constexpr (N <= 512)
     hipLaunchKernelGGL((gbl::k_sweep_band<N, false>), dim3((unsigned)(nbp * a.n_w * a.n_t)),
-                       dim3(gbl::block_threads<N>()), 0, ctx->stream, ctx->geo, tb, a, move, parity);
+                       dim3(gbl::loop_threads<N>()), 0, ctx->stream, ctx->geo, tb, a, move, parity);
 }
 
 static void sweep_adapt(gbl_ctx* ctx, const gbl_sweep_config* c, const gbl::SweepArgs& a) {
@@ -919,6 +921,10 @@ static void sweep_shift(gbl_ctx* ctx, const gbl_sweep_config* c, const gbl::Swee
       hipLaunchKernelGGL(gbl::k_sweep_shift<512>, dim3((unsigned)a.n_w), dim3(gbl::block_threads<512>()), 0,
                          ctx->stream, ctx->geo, tables_for<512, double>(ctx), a);
       break;
+    case 1024:
+      hipLaunchKernelGGL(gbl::k_sweep_shift<1024>, dim3((unsigned)a.n_w), dim3(gbl::block_threads<1024>()), 0,
+                         ctx->stream, ctx->geo, tables_for<1024, double>(ctx), a);
+      break;
     default: break;
   }
 }
@@ -928,6 +934,7 @@ static void sweep_step(gbl_ctx* ctx, const gbl_sweep_config* c, const gbl::Sweep
     case 128: launch_sweep_step<128>(ctx, a, move, parity); break;
     case 256: launch_sweep_step<256>(ctx, a, move, parity); break;
     case 512: launch_sweep_step<512>(ctx, a, move, parity); break;
+    case 1024: launch_sweep_step<1024>(ctx, a, move, parity); break;
     default: break;
   }
 }

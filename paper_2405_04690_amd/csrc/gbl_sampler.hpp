@@ -161,11 +161,17 @@ __device__ __forceinline__ bool in_prior(const Geo& g, const SweepArgs& a, int b
   return true;
 }
 
-// LDS of the tempering kernel's band likelihoods
+// LDS of the tempering kernel's band likelihoods (the window arrays serve the
+// path without window sums or pool entry, which N = 1024 does not take)
+template <int N>
+constexpr bool pt_lds_window() {
+  return N <= 512;
+}
+
 template <int N>
 struct BandSmem {
-  cd win[2][3 * N];         // residual window r' (channels A, E)
-  double wts[2][3 * N];     // 1/S over the window (0 outside the analysis band)
+  cd win[2][pt_lds_window<N>() ? 3 * N : 1];      // residual window r' (channels A, E)
+  double wts[2][pt_lds_window<N>() ? 3 * N : 1];  // 1/S over the window (0 outside the analysis band)
   cd buf[4 * series_pitch<N>()];
   double red[2 * (block_threads<N>() / kWave)];
   double prm[8];
@@ -320,6 +326,14 @@ __device__ __forceinline__ int pool_acquire(const SweepArgs& a) {
 // of a's window that need it at another offset.  The weights 1/S come from
 // HBM, fetched while the template is built.
 // ---------------------------------------------------------------------------
+// threads per block of the band loops: as for the other kernels, except at
+// N = 1024, where 512 threads (two bins each) keep the spectra and weights
+// of the loop within the register budget
+template <int N>
+constexpr int loop_threads() {
+  return N == 1024 ? 512 : block_threads<N>();
+}
+
 // GW: the window lives in global memory (the set's window-sum entry) instead
 // of LDS, for sub-bands wider than the template (2W + N bins) or N = 1024
 template <int N, bool GW>
@@ -329,7 +343,7 @@ struct LoopSmem {
   double su[kMaxSlots][8];        // the band's slot coordinates during the loop
   double rdraw[kMaxSlots][9];     // RJ, per flip: acceptance draw, prior birth's coordinates;
                                   // in-model, per proposal: its four draws
-  double red[2 * (block_threads<N>() / kWave)];
+  double red[2 * (loop_threads<N>() / kWave)];
   double u_old[8], u_new[8], prm[8];
   double blo[8], bhi[8];      // the band's prior box in sampling coordinates (f0: the band's range,
                               // angles: one period)
@@ -393,7 +407,7 @@ __device__ __forceinline__ int friend_start(const double* __restrict__ grp, int 
 template <int N, int BPT>
 __device__ __forceinline__ void loop_weights(const Geo& g, const double* __restrict__ wts, int64_t k0,
                                              double (&wh)[BPT][2], int tid) {
-  constexpr int NT = block_threads<N>();
+  constexpr int NT = loop_threads<N>();
 #pragma unroll
   for (int m = 0; m < BPT; m++) {
     const int64_t k = k0 + tid + NT * m - g.k_min;
@@ -409,7 +423,7 @@ __device__ __forceinline__ void loop_weights(const Geo& g, const double* __restr
 // Block-uniform; contains barriers.
 template <int N, bool GW>
 __device__ __noinline__ void loop_decode(const Geo& g, const double* u, LoopSmem<N, GW>& sm) {
-  constexpr int NT = block_threads<N>();
+  constexpr int NT = loop_threads<N>();
   static_assert(NT >= kWave, "band loops use whole waves");
   const int tid = threadIdx.x;
   // sampling -> physical coordinates: the three transcendental maps on lane 0
@@ -446,14 +460,14 @@ __device__ __forceinline__ void loop_build(const Geo& g, const WaveTables<double
                                            int tid) {
   loop_decode<N, GW>(g, u, sm);
   if (wts) loop_weights<N, BPT>(g, wts, sm.src.q - N / 2, wh, tid);
-  template_transform<N, 4, double>(sm.src, g, tb, sm.buf, tid);
+  template_transform<N, 4, double, loop_threads<N>()>(sm.src, g, tb, sm.buf, tid);
 }
 
 // spectrum of the built template at the thread's bins
 template <int N, int BPT, bool GW>
 __device__ __forceinline__ void loop_bins(const Geo& g, const WaveTables<double>& tb, const LoopSmem<N, GW>& sm,
                                           cd (&h)[BPT][2], int tid) {
-  constexpr int NT = block_threads<N>();
+  constexpr int NT = loop_threads<N>();
 #pragma unroll
   for (int m = 0; m < BPT; m++) bin_spectrum<N, 2, double>(sm.src, g, tb, sm.buf, tid + NT * m, h[m]);
 }
@@ -461,7 +475,7 @@ __device__ __forceinline__ void loop_bins(const Geo& g, const WaveTables<double>
 // a spectrum (all N bins, A then E) to or from a pool slot
 template <int N, int BPT>
 __device__ __forceinline__ void loop_store(cd* dst, const cd (&h)[BPT][2], int tid) {
-  constexpr int NT = block_threads<N>();
+  constexpr int NT = loop_threads<N>();
 #pragma unroll
   for (int m = 0; m < BPT; m++) {
     const int j = tid + NT * m;
@@ -472,7 +486,7 @@ __device__ __forceinline__ void loop_store(cd* dst, const cd (&h)[BPT][2], int t
 
 template <int N, int BPT>
 __device__ __forceinline__ void loop_load(const cd* src, cd (&h)[BPT][2], int tid) {
-  constexpr int NT = block_threads<N>();
+  constexpr int NT = loop_threads<N>();
 #pragma unroll
   for (int m = 0; m < BPT; m++) {
     const int j = tid + NT * m;
@@ -497,7 +511,7 @@ __device__ __forceinline__ cd& win_at(LoopSmem<N, GW>& sm, cd* gw, int L, int c,
 template <int N, int BPT, bool GW>
 __device__ __forceinline__ void loop_add(const Geo& g, LoopSmem<N, GW>& sm, cd* gw, int L, int64_t k0w, int64_t k0,
                                          double s, const cd (&h)[BPT][2], cd* own, int tid) {
-  constexpr int NT = block_threads<N>();
+  constexpr int NT = loop_threads<N>();
 #pragma unroll
   for (int m = 0; m < BPT; m++) {
     const int64_t i = k0 + tid + NT * m - k0w;
@@ -527,7 +541,7 @@ __device__ __forceinline__ double loop_dlogl(const Geo& g, LoopSmem<N, GW>& sm, 
                                              bool has_a, int64_t ka, const cd (&av)[BPT][2],
                                              const double (&wa)[BPT][2], bool has_r, int64_t kr,
                                              const cd (&rv)[BPT][2], const double (&wr)[BPT][2], int tid) {
-  constexpr int NT = block_threads<N>();
+  constexpr int NT = loop_threads<N>();
   double rd = 0.0, dd = 0.0;
   auto acc = [&](int64_t i, cd d0, cd d1, double w0, double w1) {
     if (i < 0 || i >= L) return;
@@ -562,9 +576,9 @@ __device__ __forceinline__ double loop_dlogl(const Geo& g, LoopSmem<N, GW>& sm, 
 }
 
 template <int N, bool GW>
-__global__ __launch_bounds__(block_threads<N>(), 3) void k_sweep_band(Geo g, WaveTables<double> tb, SweepArgs a,
+__global__ __launch_bounds__(loop_threads<N>(), 3) void k_sweep_band(Geo g, WaveTables<double> tb, SweepArgs a,
                                                                       int move, int parity) {
-  constexpr int NT = block_threads<N>();
+  constexpr int NT = loop_threads<N>();
   constexpr int BPT = N / NT;  // window bins per thread
   __shared__ LoopSmem<N, GW> sm;
   const int nbp = (a.n_b - parity + 1) / 2;  // bands of this parity
@@ -1081,7 +1095,10 @@ __global__ __launch_bounds__(block_threads<N>()) void k_sweep_pt(Geo g, WaveTabl
       band_set_sum<N>(g, tb, a, t, wt[t], b, k0w, sm, Hof(t));
       lnl = band_set_loglike_h<N>(g, a, b, wt[t], k0w, L, Hof(t), sm);
     } else {
-      lnl = band_set_loglike<N>(g, tb, a, t, wt[t], b, wt[t], k0w, sm);
+      if constexpr (pt_lds_window<N>())
+        lnl = band_set_loglike<N>(g, tb, a, t, wt[t], b, wt[t], k0w, sm);
+      else
+        lnl = qnan();  // not reached: N = 1024 sweeps carry window sums
     }
     if (tid == 0) Lc[t] = lnl;
   }
@@ -1089,10 +1106,16 @@ __global__ __launch_bounds__(block_threads<N>()) void k_sweep_pt(Geo g, WaveTabl
   const double* bt = a.betas + (int64_t)b * nt;
   unsigned long long n_prop = 0, n_acc = 0;
   for (int t = nt - 1; t >= 1; t--) {
-    const double L1 = Hs ? band_set_loglike_h<N>(g, a, b, wt[t], k0w, L, Hof(t - 1), sm)
-                         : band_set_loglike<N>(g, tb, a, t - 1, wt[t - 1], b, wt[t], k0w, sm);
-    const double L2 = Hs ? band_set_loglike_h<N>(g, a, b, wt[t - 1], k0w, L, Hof(t), sm)
-                         : band_set_loglike<N>(g, tb, a, t, wt[t], b, wt[t - 1], k0w, sm);
+    // log-likelihood of the set at temperature ts against walker w_res's residual
+    auto set_ll = [&](int ts, int w_res) -> double {
+      if (Hs) return band_set_loglike_h<N>(g, a, b, w_res, k0w, L, Hof(ts), sm);
+      if constexpr (pt_lds_window<N>())
+        return band_set_loglike<N>(g, tb, a, ts, wt[ts], b, w_res, k0w, sm);
+      else
+        return qnan();  // not reached: N = 1024 sweeps carry window sums
+    };
+    const double L1 = set_ll(t - 1, wt[t]);
+    const double L2 = set_ll(t, wt[t - 1]);
     const double la = bt[t] * (L1 - Lc[t]) + bt[t - 1] * (L2 - Lc[t - 1]);
     const double r = rng_uniform(a.seed, sweep, kMovePT, (uint64_t)b * a.n_w + i, (uint64_t)t);
     n_prop++;
@@ -1117,16 +1140,18 @@ __global__ __launch_bounds__(block_threads<N>()) void k_sweep_pt(Geo g, WaveTabl
         }
         __syncthreads();
       } else if (t == 1) {
-        // the cold chain of walker w_0 changes: own-parity buffer += old - new
-        cd* own = a.resid + ((int64_t)(b & 1) * a.n_w + wt[0]) * 2 * g.n_bins;
-        for (int s = 0; s < a.n_slot; s++) {
-          if (a.exists[uidx(a, 0, wt[0], b, s)]) {
-            band_template<N>(g, tb, a.u + 8 * uidx(a, 0, wt[0], b, s), sm);
-            band_add_template<N>(g, tb, sm, k0w, 1.0, own);
-          }
-          if (a.exists[uidx(a, 1, wt[1], b, s)]) {
-            band_template<N>(g, tb, a.u + 8 * uidx(a, 1, wt[1], b, s), sm);
-            band_add_template<N>(g, tb, sm, k0w, -1.0, own);
+        if constexpr (pt_lds_window<N>()) {
+          // the cold chain of walker w_0 changes: own-parity buffer += old - new
+          cd* own = a.resid + ((int64_t)(b & 1) * a.n_w + wt[0]) * 2 * g.n_bins;
+          for (int s = 0; s < a.n_slot; s++) {
+            if (a.exists[uidx(a, 0, wt[0], b, s)]) {
+              band_template<N>(g, tb, a.u + 8 * uidx(a, 0, wt[0], b, s), sm);
+              band_add_template<N>(g, tb, sm, k0w, 1.0, own);
+            }
+            if (a.exists[uidx(a, 1, wt[1], b, s)]) {
+              band_template<N>(g, tb, a.u + 8 * uidx(a, 1, wt[1], b, s), sm);
+              band_add_template<N>(g, tb, sm, k0w, -1.0, own);
+            }
           }
         }
       }

@@ -70,11 +70,11 @@ class Sweep:
             self.pool_flags = torch.zeros(spectrum_pool, dtype=torch.int32, device=dev)
         # window sums of the source sets, written by the band passes for the
         # tempering pass (n_temps x n_walkers x n_bands x 2 (2W + N) complex
-        # doubles); required for sub-bands wider than the template, whose
-        # windows live there during the band passes
+        # doubles); required for sub-bands wider than the template and for
+        # N = 1024, whose windows live there during the band passes
         self.band_width = cfg.band_width if cfg.band_width > 0 else cfg.N
         self.window_sums = None
-        if window_sums or self.band_width != cfg.N:
+        if window_sums or self.band_width != cfg.N or cfg.N == 1024:
             L = 2 * self.band_width + cfg.N
             self.window_sums = torch.zeros((nt, nw, nb, 2 * L), dtype=torch.complex128, device=dev)
         self._graph = None

@@ -75,11 +75,13 @@ def test_sweep_parity_each_move(N, pool, ws):
     ctx.close()
 
 
-@pytest.mark.parametrize("N,W,pool", [(128, 384, 1024), (256, 200, 0), (256, 1000, 1024)])
+@pytest.mark.parametrize("N,W,pool", [(128, 384, 1024), (256, 200, 0), (256, 1000, 1024), (1024, 1024, 1024),
+                                     (1024, 1024, 0)])
 def test_sweep_parity_wide_subbands(N, W, pool):
     """sub-bands of W bins with templates of N bins (the band loops keep their
-    2W + N-bin windows in global memory, in the window-sum entries): every
-    move against the oracle, decisions and counters exact"""
+    2W + N-bin windows in global memory, in the window-sum entries), and N =
+    1024 sub-bands (512 threads per band loop): every move against the
+    oracle, decisions and counters exact"""
     cfg, orc, sc, st = sampler_setup.problem(N=N, n_b=4, W=W)
     ctx, sw = _gpu_sweep(cfg, sc, st, pool=pool)
     assert sw.window_sums is not None and sw.window_sums.shape[-1] == 2 * (2 * W + N)
