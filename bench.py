@@ -417,6 +417,87 @@ def sweep_bench(torch, dev, stream, n_sweeps, n_temps=36, n_walkers=32, n_prop=3
     return out
 
 
+def multiwidth_bench(torch, dev, stream, n_sweeps=1, n_temps=36, n_walkers=32, n_prop=30):
+    """Full sweeps over 0.1-10 mHz with sub-band widths by frequency, N = 128
+    below 1 mHz, 256 to 3 mHz, 512 to 6 mHz and 1024 above: four band sets
+    sharing the walkers' cold-chain buffers, run one after another (the same
+    chain shape as the N = 256 sweep: 36 temperatures x 32 walkers, up to 64
+    slots per sub-band), 12,000 sources log-uniform over the band, every
+    walker starting from the injected catalogue (f0 jittered)."""
+    from paper_2405_04690_amd import inputs
+    from paper_2405_04690_amd.gbl import Context
+    from paper_2405_04690_amd.sampler import Sweep, make_config, run_band_sets
+    cfg = inputs.PAPER
+    T = cfg.T
+    ctx = Context(T=T, dt=cfg.dt, L=cfg.L, f_lo=cfg.f_lo, f_hi=cfg.f_hi, device=dev, stream=stream)
+    src = inputs.draw_sources(45, 12000, (1e-4, 1e-2), (-19.0, -15.0))
+    noise = torch.tensor([[cfg.sqrt_oms, cfg.sqrt_acc, cfg.sqrt_oms, cfg.sqrt_acc]], dtype=torch.float64,
+                         device=dev)
+    S = ctx.gb_psd_eval(noise)
+    d = ctx.gb_make_noise(S, torch.from_numpy(inputs.complex_normals(46, (1, 2, ctx.n_bins))).to(dev))
+    resid = torch.zeros((2, n_walkers, 2, ctx.n_bins), dtype=torch.complex128, device=dev)
+    inv_psd = ctx.gb_psd_eval(noise, inverse=True).expand(n_walkers, -1, -1).contiguous()
+    ranges = ((1e-3, 128), (3e-3, 256), (6e-3, 512), (1e-2, 1024))
+    k0 = int(np.floor(1e-4 * T))
+    sets, info = [], []
+    for idx, (f_end, N) in enumerate(ranges):
+        n_b = int(np.ceil((f_end * T - k0) / N))
+        if idx < len(ranges) - 1 and n_b % 2:
+            n_b += 1       # an even count keeps the odd/even scheme going into the next set
+        ub, eb, _ = inputs.band_slots(src, T, k0, N, n_b, 64)
+        n_slot = ub.shape[1]
+        sc = make_config(n_temps, n_walkers, n_b, n_slot, N, k0, n_prop=n_prop, n_friends=40, group_every=30,
+                         seed=47 + idx)
+        sw = Sweep(ctx, sc, window_sums=True, resid=resid, inv_psd=inv_psd)
+        sw.u.copy_(torch.from_numpy(ub).to(dev).expand(n_temps, n_walkers, -1, -1, -1))
+        gen = torch.Generator(device=dev)
+        gen.manual_seed(48 + idx)
+        sw.u[..., 1] += torch.randn(sw.u.shape[:-1], generator=gen, device=dev, dtype=torch.float64) * (0.1 / T)
+        sw.exists.copy_(torch.from_numpy(eb).to(dev).expand(n_temps, n_walkers, -1, -1))
+        sw.betas.copy_(torch.from_numpy(Sweep.geometric_ladder(n_temps)).to(dev).expand(n_b, -1))
+        keep = eb.astype(bool)
+        ctx.gb_scatter_add(_physical(torch.from_numpy(ub[keep]).to(dev)), N, 1.0, d)
+        sets.append(sw)
+        info.append({"N": N, "f_range_hz": [round(k0 / T, 6), round((k0 + n_b * N) / T, 6)], "sub_bands": n_b,
+                     "slots": n_slot, "sources": int(keep.sum())})
+        k0 += n_b * N
+    # the shared buffers: the data minus the cold-chain sources of every
+    # sub-band of that parity, over all sets
+    for par in (0, 1):
+        resid[par].copy_(d.expand(n_walkers, -1, -1))
+        for sw in sets:
+            nb, ns = sw.cfg.n_bands, sw.cfg.n_slots
+            band_par = (torch.arange(nb, device=dev) % 2).view(1, nb, 1).expand(n_walkers, -1, ns)
+            walker = torch.arange(n_walkers, device=dev, dtype=torch.int32).view(n_walkers, 1, 1).expand(-1, nb, ns)
+            sel = (sw.exists[0] != 0) & (band_par == par)
+            ctx.gb_scatter_add(_physical(sw.u[0][sel].contiguous()), sw.cfg.N, -1.0, resid[par],
+                               walker[sel].contiguous())
+    torch.cuda.synchronize()
+    run_band_sets(sets, 1)      # warm-up (builds the groups at sweep 0)
+    torch.cuda.synchronize()
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+    marks = [ev() for _ in range(len(sets) * n_sweeps + 1)]
+    marks[0].record(stream)
+    for k in range(n_sweeps):
+        for j, sw in enumerate(sets):
+            sw.run(1)
+            marks[k * len(sets) + j + 1].record(stream)
+    torch.cuda.synchronize()
+    per_set = [[marks[k * len(sets) + j].elapsed_time(marks[k * len(sets) + j + 1]) for k in range(n_sweeps)]
+               for j in range(len(sets))]
+    for j, x in enumerate(info):
+        x["ms_per_sweep"] = round(float(np.mean(per_set[j])), 1)
+    total = marks[0].elapsed_time(marks[-1]) / n_sweeps
+    out = {"workload": "1 yr, 12000 sources log-uniform in 0.1-10 mHz, sub-bands of N = 128 / 256 / 512 / 1024 "
+                       "bins by frequency (four band sets sharing the cold-chain buffers), 36 temps x 32 walkers, "
+                       "up to 64 slots, n_prop=30, FP64",
+           "sweeps": n_sweeps, "ms_per_sweep": round(total, 1), "sweeps_per_s": round(1e3 / total, 4),
+           "sources_dropped_beyond_slots": len(src) - sum(x["sources"] for x in info), "sets": info}
+    del sets
+    ctx.close()
+    return out
+
+
 LEARNED_RJ_BAND_HZ = 1e-4   # sub-band width of the learned-proposal configuration
 
 
@@ -680,6 +761,9 @@ def main():
             torch.cuda.empty_cache()
             sec = dict(sec or {})
             sec["sweep"] = sweep_bench(torch, dev, stream, args.sweeps)
+            torch.cuda.empty_cache()
+            sec["sweep_multiwidth"] = multiwidth_bench(torch, dev, stream, 1)
+            torch.cuda.empty_cache()
         if not args.no_rj:
             sec = dict(sec or {})
             sec["learned_rj"] = rj_bench(torch, dev, stream)

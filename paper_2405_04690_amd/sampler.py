@@ -40,8 +40,27 @@ def make_config(n_temps, n_walkers, n_bands, n_slots, N, k_band0, n_prop=10, n_f
     return c
 
 
+def run_band_sets(sweeps, n_sweeps: int = 1):
+    """Full sweeps of several band sets that cover adjacent frequency ranges
+    with their own template and sub-band widths (the paper's widths by
+    frequency) and share the walkers' cold-chain buffers: in every sweep each
+    set runs one full sweep in turn, seeing the others' current cold-chain
+    sources as subtracted.  For the odd/even scheme to continue across a
+    boundary, every set but the last has an even number of sub-bands."""
+    for sw in sweeps[:-1]:
+        if sw.cfg.n_bands % 2:
+            raise ValueError("every band set but the last needs an even number of sub-bands")
+    for _ in range(n_sweeps):
+        for sw in sweeps:
+            sw.run(1)
+
 class Sweep:
-    def __init__(self, ctx: Context, cfg: SweepConfig, spectrum_pool: int = 1024, window_sums: bool = False):
+    """Device state of one set of sub-bands (gbl_sweep_state) and the calls on
+    it.  resid / inv_psd: the walkers' cold-chain buffers and weights to share
+    with other band sets (None: allocated here)."""
+
+    def __init__(self, ctx: Context, cfg: SweepConfig, spectrum_pool: int = 1024, window_sums: bool = False,
+                 resid=None, inv_psd=None):
         self.ctx, self.cfg = ctx, cfg
         dev = ctx.device
         nt, nw, nb, ns = cfg.n_temps, cfg.n_walkers, cfg.n_bands, cfg.n_slots
@@ -49,8 +68,13 @@ class Sweep:
         self.u = torch.zeros((nt, nw, nb, ns, 8), **f64)
         self.exists = torch.zeros((nt, nw, nb, ns), dtype=torch.int32, device=dev)
         self.betas = torch.ones((nb, nt), **f64)
-        self.resid = torch.zeros((2, nw, 2, ctx.n_bins), dtype=torch.complex128, device=dev)
-        self.inv_psd = torch.zeros((nw, 2, ctx.n_bins), **f64)
+        if resid is None:
+            resid = torch.zeros((2, nw, 2, ctx.n_bins), dtype=torch.complex128, device=dev)
+        if inv_psd is None:
+            inv_psd = torch.zeros((nw, 2, ctx.n_bins), **f64)
+        if tuple(resid.shape) != (2, nw, 2, ctx.n_bins) or tuple(inv_psd.shape) != (nw, 2, ctx.n_bins):
+            raise ValueError("shared buffers must have shapes [2, n_walkers, 2, n_bins] and [n_walkers, 2, n_bins]")
+        self.resid, self.inv_psd = resid, inv_psd
         self.group = torch.zeros((nb, nw * ns, 8), **f64)
         self.group_count = torch.zeros(nb, dtype=torch.int32, device=dev)
         self.stats = torch.zeros(10, dtype=torch.int64, device=dev)

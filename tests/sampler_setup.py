@@ -65,6 +65,7 @@ def problem(n_t=3, n_w=4, n_b=6, n_slots=4, n_prop=6, n_friends=4, group_every=1
     ladder = np.geomspace(1.0, beta_top, n_t) if n_t > 1 else np.ones(1)
     st.betas[:] = ladder[None, :]
     st.data = data
+    st.src = src
     return cfg, orc, sc, st
 
 

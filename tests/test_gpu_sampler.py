@@ -517,3 +517,53 @@ def test_ladder_adaptation_and_ownership_shift_match_the_oracle():
     assert np.array_equal(sw.swap_acc.cpu().numpy(), st.swap_acc)
     assert st.stats[8] > 0 and st.stats[7] > 0
     ctx.close()
+
+
+def test_band_sets_share_the_cold_chain_buffers():
+    """two band sets over adjacent ranges -- four N = 128 sub-bands, then two
+    of N = 256 from where the first set ends -- sharing the walkers'
+    cold-chain buffers: full sweeps of one set after the other against the
+    oracle doing the same on one shared buffer array"""
+    from paper_2405_04690_amd.sampler import run_band_sets
+    cfg, orc, scA, stA = sampler_setup.problem(N=128, n_b=4, n_t=2, n_w=3, n_slots=3, seed=71)
+    kB = scA.k_band0 + 4 * 128
+    _, _, scB, stB = sampler_setup.problem(N=256, n_b=2, n_t=2, n_w=3, n_slots=3, seed=72, f_band0=(kB + 0.5) / cfg.T)
+    assert scB.k_band0 == kB
+    # one data set holding both sets' injections; the shared buffers: the
+    # data minus the cold-chain sources of every band of that parity
+    data = stA.data.copy()
+    orc.scatter_add(stB.src, 256, 1.0, data)
+    for par in (0, 1):
+        for w in range(scA.n_walkers):
+            buf = data.copy()
+            for st, sc in ((stA, scA), (stB, scB)):
+                for b in range(par, sc.n_bands, 2):
+                    occ = [sampler_setup._phys(st.u[0, w, b, s]) for s in range(sc.n_slots) if st.exists[0, w, b, s]]
+                    if occ:
+                        orc.scatter_add(np.array(occ), sc.N, -1.0, buf)
+            stA.resid[par, w] = buf
+    stB.resid = stA.resid                     # one array for both oracle states
+    stB.inv_psd = stA.inv_psd
+    ctx, swA = _gpu_sweep(cfg, scA, stA)
+    gcB = SweepConfig()
+    for name, _ in oracle.SweepConfig._fields_:
+        v = getattr(scB, name)
+        if name in ("prior_lo", "prior_hi"):
+            for i in range(8):
+                getattr(gcB, name)[i] = v[i]
+        else:
+            setattr(gcB, name, v)
+    swB = Sweep(ctx, gcB, resid=swA.resid, inv_psd=swA.inv_psd)
+    for name in ("u", "exists", "betas", "group", "group_count", "stats", "swap_acc"):
+        getattr(swB, name).copy_(torch.from_numpy(np.ascontiguousarray(getattr(stB, name))))
+    for sw in (swA, swB):
+        sw.sweep_counter.fill_(4)
+    for s in range(4, 7):
+        print(f"band sets: sweep {s}", flush=True)
+        oracle.sweep_full(orc, scA, stA, s)
+        oracle.sweep_full(orc, scB, stB, s)
+        run_band_sets([swA, swB], 1)
+        _compare(swA, stA, f"set A, sweep {s}")
+        _compare(swB, stB, f"set B, sweep {s}")
+    assert stA.stats[1] > 0 and stB.stats[1] > 0 and stA.stats[7] > 0
+    ctx.close()
