@@ -894,7 +894,10 @@ static void launch_sweep_step(gbl_ctx* ctx, const gbl::SweepArgs& a, int move, i
   if (move == GBL_MOVE_PT)
     hipLaunchKernelGGL((gbl::k_sweep_pt<N>), dim3((unsigned)(nbp * a.n_w)), dim3(gbl::block_threads<N>()), 0,
                        ctx->stream, ctx->geo, tb, a, parity);
-  else if (a.band_w != N || N == 1024)  // the windows (2W + N bins) in global memory
+  else if (a.band_w != N || N == 1024 || (N == 512 && a.wsum))
+    // the windows (2W + N bins) in global memory; at N = 512 also whenever the
+    // window sums are there to hold them (the LDS window would leave room
+    // for one block per CU, the global one for two)
     hipLaunchKernelGGL((gbl::k_sweep_band<N, true>), dim3((unsigned)(nbp * a.n_w * a.n_t)),
                        dim3(gbl::loop_threads<N>()), 0, ctx->stream, ctx->geo, tb, a, move, parity);
   else if constexpr (N <= 512)

@@ -334,6 +334,16 @@ constexpr int loop_threads() {
   return N == 1024 ? 512 : block_threads<N>();
 }
 
+// waves per SIMD the band loop is compiled for (the register budget): three
+// at one bin per thread (168 VGPRs, three blocks per CU); at two bins per
+// thread the loop's spectra need more, and two waves (256 VGPRs) keep them
+// out of scratch memory, whose spill stores inside the loop would otherwise
+// reach HBM on every pass
+template <int N>
+constexpr int loop_waves() {
+  return N / loop_threads<N>() == 1 ? 3 : 2;
+}
+
 // GW: the window lives in global memory (the set's window-sum entry) instead
 // of LDS, for sub-bands wider than the template (2W + N bins) or N = 1024
 template <int N, bool GW>
@@ -576,7 +586,7 @@ __device__ __forceinline__ double loop_dlogl(const Geo& g, LoopSmem<N, GW>& sm, 
 }
 
 template <int N, bool GW>
-__global__ __launch_bounds__(loop_threads<N>(), 3) void k_sweep_band(Geo g, WaveTables<double> tb, SweepArgs a,
+__global__ __launch_bounds__(loop_threads<N>(), loop_waves<N>()) void k_sweep_band(Geo g, WaveTables<double> tb, SweepArgs a,
                                                                       int move, int parity) {
   constexpr int NT = loop_threads<N>();
   constexpr int BPT = N / NT;  // window bins per thread
@@ -636,17 +646,20 @@ __global__ __launch_bounds__(loop_threads<N>(), 3) void k_sweep_band(Geo g, Wave
   const int nf = a.n_friends < G ? a.n_friends : G;
   const double lvol = (!inmodel && a.prop_u) ? log_box_volume<N>(g, a, b) : 0.0;
 
-  // spectra and weights at the thread's bins: a (being added), r (being
-  // removed) and the template just built; each is written before it is read
-  cd av[BPT][2], rv[BPT][2], hv[BPT][2];
-  double wa[BPT][2], wr[BPT][2], wh[BPT][2];
-  int64_t ka = 0, kr = 0;
+  // spectra and weights at the thread's bins: r (being removed), carried
+  // from the plan or the previous pass, and the template just built (h, the
+  // one being added when the move is a birth or an in-model move's new
+  // template); each is written before it is read.  Only r lives across
+  // passes: the added template is consumed in the pass that builds it.
+  cd rv[BPT][2], hv[BPT][2];
+  double wr[BPT][2], wh[BPT][2];
+  int64_t kr = 0;
   unsigned long long n_prop = 0, n_acc = 0, n_bprop = 0, n_bacc = 0, n_dprop = 0, n_dacc = 0;
 
   // the reversible-jump death of slot s, r's spectrum in rv (start kr,
   // weights wr); lra = ln of the acceptance draw
   auto death = [&](int s, double lra) {
-    const double dl = loop_dlogl<N, BPT, GW>(g, sm, gw, L, k0w, false, 0, av, wa, true, kr, rv, wr, tid);
+    const double dl = loop_dlogl<N, BPT, GW>(g, sm, gw, L, k0w, false, 0, rv, wr, true, kr, rv, wr, tid);
     const double lpq = a.prop_u ? a.rj_logq[uidx(a, t, w, b, s)] + lvol : 0.0;
     if (lra < beta * dl + lpq) {
       loop_add<N, BPT, GW>(g, sm, gw, L, k0w, kr, 1.0, rv, own, tid);
@@ -871,18 +884,13 @@ __global__ __launch_bounds__(loop_threads<N>(), 3) void k_sweep_band(Geo g, Wave
       cur++;
       continue;
     }
+    if (kind == kOld) {
 #pragma unroll
-    for (int m = 0; m < BPT; m++)
-      for (int c = 0; c < 2; c++) {
-        if (kind == kOld) {
+      for (int m = 0; m < BPT; m++)
+        for (int c = 0; c < 2; c++) {
           rv[m][c] = hv[m][c];
           wr[m][c] = wh[m][c];
-        } else {
-          av[m][c] = hv[m][c];
-          wa[m][c] = wh[m][c];
         }
-      }
-    if (kind == kOld) {
       kr = kh;
       if (inmodel) {
         pend = true;  // the new template next
@@ -892,7 +900,6 @@ __global__ __launch_bounds__(loop_threads<N>(), 3) void k_sweep_band(Geo g, Wave
       cur++;
       continue;
     }
-    ka = kh;
     pend = false;
     double dl;
     if (inmodel) {
@@ -905,9 +912,9 @@ __global__ __launch_bounds__(loop_threads<N>(), 3) void k_sweep_band(Geo g, Wave
         sm.buf[N + tid + NT * m] = rv[m][1];
       }
       __syncthreads();
-      dl = loop_dlogl<N, BPT, GW>(g, sm, gw, L, k0w, true, ka, av, wa, true, kr, rv, wr, tid);
+      dl = loop_dlogl<N, BPT, GW>(g, sm, gw, L, k0w, true, kh, hv, wh, true, kr, rv, wr, tid);
     } else {
-      dl = loop_dlogl<N, BPT, GW>(g, sm, gw, L, k0w, true, ka, av, wa, false, 0, rv, wr, tid);
+      dl = loop_dlogl<N, BPT, GW>(g, sm, gw, L, k0w, true, kh, hv, wh, false, 0, rv, wr, tid);
     }
     double thr;
     if (inmodel)
@@ -917,8 +924,8 @@ __global__ __launch_bounds__(loop_threads<N>(), 3) void k_sweep_band(Geo g, Wave
     else
       thr = beta * dl;
     if (lr_acc < thr) {
-      if (spec) loop_store<N, BPT>(spec + (int64_t)sk * 2 * N, av, tid);
-      loop_add<N, BPT, GW>(g, sm, gw, L, k0w, ka, -1.0, av, own, tid);
+      if (spec) loop_store<N, BPT>(spec + (int64_t)sk * 2 * N, hv, tid);
+      loop_add<N, BPT, GW>(g, sm, gw, L, k0w, kh, -1.0, hv, own, tid);
       __syncthreads();
       if (inmodel) {
         loop_add<N, BPT, GW>(g, sm, gw, L, k0w, kr, 1.0, rv, own, tid);

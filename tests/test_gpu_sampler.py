@@ -50,7 +50,8 @@ def _compare(sw, st, what, T=None):
 
 
 @pytest.mark.parametrize("N,pool,ws", [(128, 1024, False), (256, 1024, False), (512, 1024, False), (128, 0, False),
-                                       (256, 2, False), (256, 1024, True), (128, 0, True), (512, 1024, True)])
+                                       (256, 2, False), (256, 1024, True), (128, 0, True), (512, 1024, True),
+                                       (512, 0, True)])
 def test_sweep_parity_each_move(N, pool, ws):
     """pool: the per-slot spectrum cache (0: recomputed spectra; 2: most band
     loops find no free entry and recompute, the others use the cache); ws:
@@ -75,8 +76,8 @@ def test_sweep_parity_each_move(N, pool, ws):
     ctx.close()
 
 
-@pytest.mark.parametrize("N,W,pool", [(128, 384, 1024), (256, 200, 0), (256, 1000, 1024), (1024, 1024, 1024),
-                                     (1024, 1024, 0)])
+@pytest.mark.parametrize("N,W,pool", [(128, 384, 1024), (256, 200, 0), (256, 1000, 1024), (512, 640, 0),
+                                     (1024, 1024, 1024), (1024, 1024, 0)])
 def test_sweep_parity_wide_subbands(N, W, pool):
     """sub-bands of W bins with templates of N bins (the band loops keep their
     2W + N-bin windows in global memory, in the window-sum entries), and N =
