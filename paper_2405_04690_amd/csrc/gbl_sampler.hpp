@@ -313,6 +313,29 @@ __device__ __forceinline__ int pool_acquire(const SweepArgs& a) {
   return -1;
 }
 
+// Block order of the per-band kernels (band loops and tempering): each XCD
+// takes one contiguous run of the logical grid (xcd_block), and the logical
+// grid is band-major, so that the blocks in flight on an XCD share one band's
+// group, residual windows and weights in its L2.  Bands are ordered by class
+// bi mod 8 (bands 0, 8, 16, ..., then 1, 9, ...), so that every XCD's run
+// spreads over the whole frequency range and the XCDs carry similar source
+// counts.  Returns the band index bi of this parity (0 <= bi < nbp) and the
+// index j of the block within its band (0 <= j < per_band); a bijection from
+// the grid of nbp * per_band blocks.
+__device__ __forceinline__ void band_block(int nbp, int per_band, int& bi, int& j) {
+  const int L = (int)xcd_block();
+  const int lb = L / per_band;
+  j = L - lb * per_band;
+  int off = 0;
+  bi = 0;
+#pragma unroll
+  for (int c = 0; c < (int)kXcds; c++) {
+    const int nc = (nbp - c + (int)kXcds - 1) / (int)kXcds;  // bands bi = c mod 8
+    if (lb >= off && lb < off + nc) bi = c + (int)kXcds * (lb - off);
+    off += nc;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Alg. gb1 for every (t, w, b) of one parity: in-model group-stretch moves
 // (move 0) or the reversible-jump pass that flips every slot (move 1).
@@ -427,61 +450,6 @@ __device__ __forceinline__ void loop_weights(const Geo& g, const double* __restr
   }
 }
 
-// sampling coordinates u (LDS) -> physical parameters -> decode in sm.src.
-// Not inlined: the library functions' constants would otherwise be hoisted
-// out of the band loop and held in vector registers across it.
-// Block-uniform; contains barriers.
-template <int N, bool GW>
-__device__ __noinline__ void loop_decode(const Geo& g, const double* u, LoopSmem<N, GW>& sm) {
-  constexpr int NT = loop_threads<N>();
-  static_assert(NT >= kWave, "band loops use whole waves");
-  const int tid = threadIdx.x;
-  // sampling -> physical coordinates: the three transcendental maps on lane 0
-  // of different waves, so that they run side by side
-  if ((tid & (kWave - 1)) == 0) {
-    for (int r = tid / kWave; r < 4; r += NT / kWave) {
-      if (r == 0) {
-        sm.prm[0] = exp10(u[0]);
-      } else if (r == 1) {
-        sm.prm[4] = acos(u[4]);
-      } else if (r == 2) {
-        sm.prm[7] = asin(u[7]);
-      } else {
-        sm.prm[1] = u[1];
-        sm.prm[2] = u[2];
-        sm.prm[3] = u[3];
-        sm.prm[5] = u[5];
-        sm.prm[6] = u[6];
-      }
-    }
-  }
-  __syncthreads();
-  if (tid < kWave) decode_sources<1>(sm.prm, sm.prm, g, &sm.src);
-  __syncthreads();
-}
-
-// sampling coordinates u (LDS) -> template in sm.buf, its decode in sm.src;
-// with wts, also the weights at the thread's bins of the template's window,
-// requested before the response and the FFT so that their latency hides
-// behind them.  Block-uniform; contains barriers.
-template <int N, int BPT, bool GW>
-__device__ __forceinline__ void loop_build(const Geo& g, const WaveTables<double>& tb, const double* u,
-                                           LoopSmem<N, GW>& sm, const double* __restrict__ wts, double (&wh)[BPT][2],
-                                           int tid) {
-  loop_decode<N, GW>(g, u, sm);
-  if (wts) loop_weights<N, BPT>(g, wts, sm.src.q - N / 2, wh, tid);
-  template_transform<N, 4, double, loop_threads<N>()>(sm.src, g, tb, sm.buf, tid);
-}
-
-// spectrum of the built template at the thread's bins
-template <int N, int BPT, bool GW>
-__device__ __forceinline__ void loop_bins(const Geo& g, const WaveTables<double>& tb, const LoopSmem<N, GW>& sm,
-                                          cd (&h)[BPT][2], int tid) {
-  constexpr int NT = loop_threads<N>();
-#pragma unroll
-  for (int m = 0; m < BPT; m++) bin_spectrum<N, 2, double>(sm.src, g, tb, sm.buf, tid + NT * m, h[m]);
-}
-
 // a spectrum (all N bins, A then E) to or from a pool slot
 template <int N, int BPT>
 __device__ __forceinline__ void loop_store(cd* dst, const cd (&h)[BPT][2], int tid) {
@@ -507,6 +475,98 @@ __device__ __forceinline__ void loop_load(const cd* src, cd (&h)[BPT][2], int ti
 
 // the window's element i of channel c: in LDS, or in global memory at
 // gw + c L + i
+// Full decode of one source from its sampling coordinates (log10 A, f0,
+// fdot, phi0, cos iota, psi, lambda, sin beta) by the block's first two
+// waves side by side (every lane of both takes part).  The sky and
+// inclination angles enter the response only through sin beta, cos beta and
+// cos iota, so those come from the coordinates themselves (cos beta =
+// sqrt((1 - sin beta)(1 + sin beta)) >= 0 on |beta| <= pi/2) instead of
+// through acos/asin and back, and the phases lambda, 2 psi and the carrier's
+// delay take the exactly reduced polynomial exp(2 pi i c) in cycles.  Wave 0
+// writes output groups 0..8 (lane a: group a, the projections, which need
+// lambda and beta only); wave 1 the amplitude 10^u0 (the one library call),
+// the polarisation amplitudes, carrier, phases, delay factor and state.
+__device__ __forceinline__ void decode_sampled(const double* __restrict__ u, const Geo& g, Src& s) {
+  const int wid = (int)(threadIdx.x / kWave);
+  const int lane = (int)(threadIdx.x & (kWave - 1));
+  if (wid == 0) {
+    const cd el = expi_cycles(u[6] * (1.0 / kTwoPi));  // (cos lambda, sin lambda)
+    SrcTrig tr;
+    tr.sl = el.im;
+    tr.cl = el.re;
+    tr.sb = u[7];
+    tr.cb = sqrt((1.0 - u[7]) * (1.0 + u[7]));
+    tr.ci = u[4];
+    tr.s2p = 0.0;  // (groups 0..8 read neither)
+    tr.c2p = 1.0;
+    if (lane < 9) decode_group(lane, u, tr, g, s);
+  } else if (wid == 1) {
+    const bool finite_u = isfinite(u[0]) && isfinite(u[1]) && isfinite(u[2]) && isfinite(u[3]) &&
+                          isfinite(u[4]) && isfinite(u[5]) && isfinite(u[6]) && isfinite(u[7]) &&
+                          fabs(u[4]) <= 1.0 && fabs(u[7]) <= 1.0 && fabs(u[1] * g.T) < 4503599627370496.0;
+    const double A = exp10(u[0]);
+    const bool finite = finite_u && isfinite(A);
+    const double f0 = finite ? u[1] : 0.0;  // keep the arithmetic below well defined
+    const double qd = floor(f0 * g.T);
+    const cd dq = expi_cycles(-qd * (g.Lc / g.T));
+    const cd e2p = expi_cycles(u[5] * (1.0 / kPi));  // (cos 2 psi, sin 2 psi)
+    if (lane == 0) {
+      s.state = finite ? (A == 0.0 ? 1 : 0) : 2;
+      s.f0 = f0;
+      s.fdot = u[2];
+      s.phi0_cyc = u[3] / kTwoPi;
+      s.q = (int64_t)qd;
+      s.dfq = f0 - qd / g.T;
+      const double ci = u[4];
+      const double ap = A * (1.0 + ci * ci);
+      const double ax = 2.0 * A * ci;
+      s.cp = {ap * e2p.re, -ax * e2p.im};
+      s.cx2 = {2.0 * ap * e2p.im, 2.0 * ax * e2p.re};
+      s.dq = dq;
+    }
+  }
+}
+
+// sampling coordinates u (LDS) -> decode in sm.src, on the first two waves.
+// Not inlined: the library function's and the polynomials' constants would
+// otherwise be hoisted out of the band loop and held in vector registers
+// across it.  Block-uniform; contains a barrier.
+template <int N, bool GW>
+__device__ __noinline__ void loop_decode(const Geo& g, const double* u, LoopSmem<N, GW>& sm) {
+  static_assert(loop_threads<N>() >= 2 * kWave, "the decode takes two waves");
+  decode_sampled(u, g, sm.src);
+  __syncthreads();
+}
+
+// sampling coordinates u (LDS) -> template in sm.buf, its decode in sm.src;
+// with wts, also the weights at the thread's bins of the template's window,
+// and with rsrc the removed template's cached spectrum (rv) and its weights
+// (wr, window start kr): all requested after the decode (a call, which waits
+// for every outstanding load) and before the response and the FFT, so that
+// their latency hides behind them.  Block-uniform; contains barriers.
+template <int N, int BPT, bool GW>
+__device__ __forceinline__ void loop_build(const Geo& g, const WaveTables<double>& tb, const double* u,
+                                           LoopSmem<N, GW>& sm, const double* __restrict__ wts, double (&wh)[BPT][2],
+                                           const cd* rsrc, int64_t kr, cd (&rv)[BPT][2], double (&wr)[BPT][2],
+                                           int tid) {
+  loop_decode<N, GW>(g, u, sm);
+  if (wts) loop_weights<N, BPT>(g, wts, sm.src.q - N / 2, wh, tid);
+  if (rsrc) {
+    loop_load<N, BPT>(rsrc, rv, tid);
+    loop_weights<N, BPT>(g, wts, kr, wr, tid);
+  }
+  template_transform<N, 4, double, loop_threads<N>()>(sm.src, g, tb, sm.buf, tid);
+}
+
+// spectrum of the built template at the thread's bins
+template <int N, int BPT, bool GW>
+__device__ __forceinline__ void loop_bins(const Geo& g, const WaveTables<double>& tb, const LoopSmem<N, GW>& sm,
+                                          cd (&h)[BPT][2], int tid) {
+  constexpr int NT = loop_threads<N>();
+#pragma unroll
+  for (int m = 0; m < BPT; m++) bin_spectrum<N, 2, double>(sm.src, g, tb, sm.buf, tid + NT * m, h[m]);
+}
+
 template <int N, bool GW>
 __device__ __forceinline__ cd& win_at(LoopSmem<N, GW>& sm, cd* gw, int L, int c, int64_t i) {
   if constexpr (GW)
@@ -592,8 +652,8 @@ __global__ __launch_bounds__(loop_threads<N>(), loop_waves<N>()) void k_sweep_ba
   constexpr int BPT = N / NT;  // window bins per thread
   __shared__ LoopSmem<N, GW> sm;
   const int nbp = (a.n_b - parity + 1) / 2;  // bands of this parity
-  const int bi = blockIdx.x % nbp;
-  const int tw = blockIdx.x / nbp;
+  int bi, tw;
+  band_block(nbp, a.n_t * a.n_w, bi, tw);
   const int w = tw % a.n_w;
   const int t = tw / a.n_w;
   const int b = parity + 2 * bi;
@@ -687,6 +747,7 @@ __global__ __launch_bounds__(loop_threads<N>(), loop_waves<N>()) void k_sweep_ba
     asm volatile("" : "+v"(tid), "+s"(tbl.basis), "+s"(tbl.fft_tw), "+s"(tbl.bin_F), "+s"(tbl.bin_W));
     // ---- plan: advance the moves up to the next template build
     const double* ub = nullptr;
+    const cd* rsrc = nullptr;  // a cached spectrum of r to load during the build
     int kind = kSetup;
     while (phase < 2) {
       if (phase == 0) {
@@ -813,9 +874,9 @@ __global__ __launch_bounds__(loop_threads<N>(), loop_waves<N>()) void k_sweep_ba
         }
         __syncthreads();
         if (spec) {
-          loop_load<N, BPT>(spec + (int64_t)sk * 2 * N, rv, tid);
+          // r's cached spectrum and weights: loaded during the build of the new template
+          rsrc = spec + (int64_t)sk * 2 * N;
           kr = sm.sq[sk] - N / 2;
-          loop_weights<N, BPT>(g, wts, kr, wr, tid);
           ub = sm.u_new;
           kind = kNew;
         } else {
@@ -872,7 +933,7 @@ __global__ __launch_bounds__(loop_threads<N>(), loop_waves<N>()) void k_sweep_ba
     if (phase == 2) break;
 
     // ---- the template build (the only one)
-    loop_build<N, BPT, GW>(g, tbl, ub, sm, kind == kSetup ? nullptr : wts, wh, tid);
+    loop_build<N, BPT, GW>(g, tbl, ub, sm, kind == kSetup ? nullptr : wts, wh, rsrc, kr, rv, wr, tid);
     loop_bins<N, BPT, GW>(g, tbl, sm, hv, tid);
     const int64_t kh = sm.src.q - N / 2;
     if (kind == kSetup) {
@@ -1060,8 +1121,8 @@ __global__ __launch_bounds__(block_threads<N>()) void k_sweep_pt(Geo g, WaveTabl
   __shared__ double Lc[256];
   __shared__ int hidx[256];  // window sum of the set at temperature t: entry slot hidx[t]
   const int nbp = (a.n_b - parity + 1) / 2;
-  const int bi = blockIdx.x % nbp;
-  const int i = blockIdx.x / nbp;
+  int bi, i;
+  band_block(nbp, a.n_w, bi, i);
   const int b = parity + 2 * bi;
   const int tid = threadIdx.x;
   const int nt = a.n_t;
