@@ -61,6 +61,8 @@ def parse():
     ap.add_argument("--no-secondary", action="store_true", help="skip the secondary measurements")
     ap.add_argument("--no-sweep", action="store_true", help="skip the sampler-sweep measurement")
     ap.add_argument("--sweeps", type=int, default=2, help="timed sampler sweeps")
+    ap.add_argument("--ess-sweeps", type=int, default=24,
+                    help="sweeps per RJ proposal for the effective-sample rate of the full sweep (0: skip)")
     ap.add_argument("--no-rj", action="store_true", help="skip the learned-vs-prior RJ comparison")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 512 MiB device copy (counter calibration for profiles)")
@@ -308,7 +310,7 @@ def _physical(u):
     return p
 
 
-def sweep_bench(torch, dev, stream, n_sweeps, n_temps=36, n_walkers=32, n_prop=30):
+def sweep_bench(torch, dev, stream, n_sweeps, n_temps=36, n_walkers=32, n_prop=30, ess_sweeps=32):
     """Full sampler sweeps (group refresh when due, in-model, RJ, tempering;
     odd then even sub-bands) over a 12,000-source 1 yr data set, N = 256
     sub-bands, 36 temperatures x 32 walkers, every walker starting from the
@@ -397,7 +399,7 @@ def sweep_bench(torch, dev, stream, n_sweeps, n_temps=36, n_walkers=32, n_prop=3
             if len(qa) and len(qb):
                 n_pairs += int((np.abs(qa[:, None] - qb[None, :]) < N).sum())
     overlap = {"cold_sources": int(ex0.sum()), "pairs_b_b2_overlapping": n_pairs}
-    full = _full_sweep(torch, ctx, sw, stream, d, n_bands, k_band0, N, n_temps, n_walkers)
+    full = _full_sweep(torch, ctx, sw, stream, d, n_bands, k_band0, N, n_temps, n_walkers, ess_sweeps)
     dst = st1 - st0
     rate = lambda k: round(float(dst[k]) / (direct_ms * n_sweeps / 1e3), 1)
     acc = lambda p, q: round(float(dst[q]) / max(1.0, float(dst[p])), 4)
@@ -609,12 +611,15 @@ def _rj_summary(r):
     return out
 
 
-def _full_sweep(torch, ctx, sw, stream, d, n_bands, k_band0, N, n_temps, n_walkers):
+def _full_sweep(torch, ctx, sw, stream, d, n_bands, k_band0, N, n_temps, n_walkers, ess_sweeps=0):
     """The full GB + noise sweep: the sweep with the flow mixture as RJ
     proposal (flow trained for 200 steps on the chain's current cold samples)
     followed by the noise-PSD step (stretch moves over the four noise
     parameters of 36 x 32 vertically tempered chains); timed directly and as
-    one captured graph."""
+    one captured graph.  With ess_sweeps, then the effective samples per
+    second of the GB sweep at this scale: ess_sweeps sweeps with prior RJ
+    draws (the plain FP64 batched form) and, from the same state, as many
+    with the flow mixture."""
     from paper_2405_04690_amd.flow import Flow, flow_config, init_params
     from paper_2405_04690_amd.learned_rj import train
     from paper_2405_04690_amd.sampler import DEFAULT_PRIOR_HI, DEFAULT_PRIOR_LO, PsdSweep, psd_config
@@ -660,6 +665,7 @@ def _full_sweep(torch, ctx, sw, stream, d, n_bands, k_band0, N, n_temps, n_walke
     g.destroy()
     st = sw.stats.cpu().numpy()
     pst = ps.stats.cpu().numpy()
+    ess = _sweep_ess(sw, fl, ess_sweeps) if ess_sweeps > 0 else None
     sets = n_temps * n_walkers * 2   # refresh of every chain + one proposal per chain
     # residual A+E per set evaluation (32 B/bin) and the shared PSD basis per pass
     # (16 B/bin, three passes); the full-residual build (two buffers read and one
@@ -673,7 +679,39 @@ def _full_sweep(torch, ctx, sw, stream, d, n_bands, k_band0, N, n_temps, n_walke
             "psd_step_algorithmic_gbs": round(psd_bytes / (psd_ms / 1e3) / 1e9, 1),
             "psd_acceptance": round(float(pst[1]) / max(1.0, float(pst[0])), 4),
             "psd_swap_acceptance": round(float(pst[3]) / max(1.0, float(pst[2])), 4),
-            "birth_acceptance_total": round(float(st[3]) / max(1.0, float(st[2])), 4)}
+            "birth_acceptance_total": round(float(st[3]) / max(1.0, float(st[2])), 4),
+            "ess": ess}
+
+
+def _sweep_ess(sw, fl, n_sweeps):
+    """Effective samples per second of the GB sweep on the full problem: the
+    cold chains' source count k and log-likelihood per sub-band (every walker
+    a chain; ESS summed over the sub-bands) over n_sweeps sweeps with prior
+    RJ draws, then from the same starting state over n_sweeps with the flow
+    mixture.  Short traces: where a sub-band's autocorrelation time exceeds
+    n_sweeps / 5 the estimator caps it at the trace length."""
+    from paper_2405_04690_amd.learned_rj import measure, restore, save, stationarity
+    st0 = save(sw)
+    sw.enable_logl_trace()
+    k_mean = lambda: round(float(sw.exists[0].sum(dim=-1).double().mean()), 4)
+    k_start = k_mean()
+    plain = measure(sw, n_sweeps, None)
+    k_plain_end = k_mean()
+    restore(sw, st0)
+    learned = measure(sw, n_sweeps, fl)
+    k_learned_end = k_mean()
+    keys = ("wall_s", "ess_k", "ess_logl", "ess_k_per_s", "ess_logl_per_s", "birth_acceptance",
+            "death_acceptance", "mean_k", "se_mean_k", "mean_logl", "se_mean_logl")
+    pick = lambda r: {k: round(float(r[k]), 4) for k in keys}
+    n_chains = sw.cfg.n_walkers * sw.cfg.n_bands
+    return {"sweeps": n_sweeps, "chains": n_chains,
+            "plain_prior_rj": pick(plain), "flow_mixture_rj": pick(learned),
+            "tau_k_mean_sweeps": [round(n_chains * n_sweeps / max(plain["ess_k"], 1e-300), 2),
+                                  round(n_chains * n_sweeps / max(learned["ess_k"], 1e-300), 2)],
+            "mean_k_start_end": {"start": k_start, "plain_end": k_plain_end, "flow_mixture_end": k_learned_end},
+            "gain_ess_k_per_s": round(learned["ess_k_per_s"] / max(plain["ess_k_per_s"], 1e-300), 4),
+            "gain_ess_logl_per_s": round(learned["ess_logl_per_s"] / max(plain["ess_logl_per_s"], 1e-300), 4),
+            "stationarity": stationarity(plain, learned)}
 
 
 def cpu_baseline(batch, cfg, target_s):
@@ -760,7 +798,7 @@ def main():
             del R
             torch.cuda.empty_cache()
             sec = dict(sec or {})
-            sec["sweep"] = sweep_bench(torch, dev, stream, args.sweeps)
+            sec["sweep"] = sweep_bench(torch, dev, stream, args.sweeps, ess_sweeps=args.ess_sweeps)
             torch.cuda.empty_cache()
             sec["sweep_multiwidth"] = multiwidth_bench(torch, dev, stream, 1)
             torch.cuda.empty_cache()
