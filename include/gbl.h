@@ -399,8 +399,14 @@ typedef struct {
 typedef struct gbl_graph gbl_graph;
 
 /* One move type over the bands of one parity, using *sweep_counter for the
- * random streams.  Errors: GBL_EINVAL (null pointers, out-of-range config),
- * GBL_EUNSUPPORTED (N = 1024 or a mixed-precision context). */
+ * random streams.  In a GBL_MIXED context the band passes (moves 0 and 1)
+ * build their templates with the FP32 response and FFT (source decode,
+ * phases, the spectra at the bins, the windows and every likelihood sum stay
+ * FP64), so a decision can differ from the FP64 one where the FP32 template
+ * error moves the log acceptance ratio across the draw; such a context needs
+ * window_sums (the tempering pass then builds no template).  Errors:
+ * GBL_EINVAL (null pointers, out-of-range config), GBL_EUNSUPPORTED (a
+ * mixed-precision context without window_sums). */
 int gb_sweep_step(gbl_ctx* ctx, const gbl_sweep_config* cfg, const gbl_sweep_state* st, int32_t move,
                   int32_t parity);
 

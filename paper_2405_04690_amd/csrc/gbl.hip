@@ -846,7 +846,10 @@ static int sweep_check(gbl_ctx* ctx, const gbl_sweep_config* c, const gbl_sweep_
   if (((c->band_width != 0 && c->band_width != c->N) || c->N == 1024) && !st->window_sums)
     return fail(ctx, GBL_EINVAL,
                 "sweep: a band width other than N, or N = 1024, needs window_sums (the windows live there)%s");
-  if (ctx->cfg.precision != GBL_FP64) return fail(ctx, GBL_EUNSUPPORTED, "sweep: FP64 contexts only%s");
+  if (ctx->cfg.precision != GBL_FP64 && !(ctx->cfg.precision == GBL_MIXED && st->window_sums))
+    return fail(ctx, GBL_EUNSUPPORTED,
+                "sweep: FP64 contexts, or mixed-precision contexts with window_sums (tempering then builds no "
+                "template)%s");
   return GBL_OK;
 }
 
@@ -886,23 +889,33 @@ static gbl::SweepArgs sweep_args(const gbl_sweep_config* c, const gbl_sweep_stat
   return a;
 }
 
+// the band loops of one parity; F: precision of their template response and
+// FFT (float in mixed-precision contexts)
+template <int N, typename F>
+static void launch_band_loops(gbl_ctx* ctx, const gbl::SweepArgs& a, int move, int parity, int nbp) {
+  const gbl::WaveTables<F>& tb = tables_for<N, F>(ctx);
+  if (a.band_w != N || N == 1024 || (N == 512 && a.wsum))
+    // the windows (2W + N bins) in global memory; at N = 512 also whenever the
+    // window sums are there to hold them (the LDS window would leave room
+    // for one block per CU, the global one for two)
+    hipLaunchKernelGGL((gbl::k_sweep_band<N, true, F>), dim3((unsigned)(nbp * a.n_w * a.n_t)),
+                       dim3(gbl::loop_threads<N>()), 0, ctx->stream, ctx->geo, tb, a, move, parity);
+  else if constexpr (N <= 512)
+    hipLaunchKernelGGL((gbl::k_sweep_band<N, false, F>), dim3((unsigned)(nbp * a.n_w * a.n_t)),
+                       dim3(gbl::loop_threads<N>()), 0, ctx->stream, ctx->geo, tb, a, move, parity);
+}
+
 template <int N>
 static void launch_sweep_step(gbl_ctx* ctx, const gbl::SweepArgs& a, int move, int parity) {
   const int nbp = (a.n_b - parity + 1) / 2;
   if (nbp <= 0) return;
-  const gbl::WaveTables<double>& tb = tables_for<N, double>(ctx);
   if (move == GBL_MOVE_PT)
     hipLaunchKernelGGL((gbl::k_sweep_pt<N>), dim3((unsigned)(nbp * a.n_w)), dim3(gbl::block_threads<N>()), 0,
-                       ctx->stream, ctx->geo, tb, a, parity);
-  else if (a.band_w != N || N == 1024 || (N == 512 && a.wsum))
-    // the windows (2W + N bins) in global memory; at N = 512 also whenever the
-    // window sums are there to hold them (the LDS window would leave room
-    // for one block per CU, the global one for two)
-    hipLaunchKernelGGL((gbl::k_sweep_band<N, true>), dim3((unsigned)(nbp * a.n_w * a.n_t)),
-                       dim3(gbl::loop_threads<N>()), 0, ctx->stream, ctx->geo, tb, a, move, parity);
-  else if constexpr (N <= 512)
-    hipLaunchKernelGGL((gbl::k_sweep_band<N, false>), dim3((unsigned)(nbp * a.n_w * a.n_t)),
-                       dim3(gbl::loop_threads<N>()), 0, ctx->stream, ctx->geo, tb, a, move, parity);
+                       ctx->stream, ctx->geo, tables_for<N, double>(ctx), a, parity);
+  else if (ctx->cfg.precision == GBL_MIXED)
+    launch_band_loops<N, float>(ctx, a, move, parity, nbp);
+  else
+    launch_band_loops<N, double>(ctx, a, move, parity, nbp);
 }
 
 static void sweep_adapt(gbl_ctx* ctx, const gbl_sweep_config* c, const gbl::SweepArgs& a) {

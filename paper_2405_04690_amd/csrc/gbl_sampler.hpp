@@ -543,9 +543,11 @@ __device__ __noinline__ void loop_decode(const Geo& g, const double* u, LoopSmem
 // and with rsrc the removed template's cached spectrum (rv) and its weights
 // (wr, window start kr): all requested after the decode (a call, which waits
 // for every outstanding load) and before the response and the FFT, so that
-// their latency hides behind them.  Block-uniform; contains barriers.
-template <int N, int BPT, bool GW>
-__device__ __forceinline__ void loop_build(const Geo& g, const WaveTables<double>& tb, const double* u,
+// their latency hides behind them.  F: precision of the response and the FFT
+// (float: the mixed-precision sweep; the decode, the phases and every sum
+// stay FP64).  Block-uniform; contains barriers.
+template <int N, int BPT, bool GW, typename F>
+__device__ __forceinline__ void loop_build(const Geo& g, const WaveTables<F>& tb, const double* u,
                                            LoopSmem<N, GW>& sm, const double* __restrict__ wts, double (&wh)[BPT][2],
                                            const cd* rsrc, int64_t kr, cd (&rv)[BPT][2], double (&wr)[BPT][2],
                                            int tid) {
@@ -555,16 +557,26 @@ __device__ __forceinline__ void loop_build(const Geo& g, const WaveTables<double
     loop_load<N, BPT>(rsrc, rv, tid);
     loop_weights<N, BPT>(g, wts, kr, wr, tid);
   }
-  template_transform<N, 4, double, loop_threads<N>()>(sm.src, g, tb, sm.buf, tid);
+  template_transform<N, 4, F, loop_threads<N>()>(sm.src, g, tb, reinterpret_cast<cx<F>*>(sm.buf), tid);
 }
 
-// spectrum of the built template at the thread's bins
-template <int N, int BPT, bool GW>
-__device__ __forceinline__ void loop_bins(const Geo& g, const WaveTables<double>& tb, const LoopSmem<N, GW>& sm,
+// spectrum of the built template at the thread's bins (in FP64 whatever the
+// precision of the build)
+template <int N, int BPT, bool GW, typename F>
+__device__ __forceinline__ void loop_bins(const Geo& g, const WaveTables<F>& tb, const LoopSmem<N, GW>& sm,
                                           cd (&h)[BPT][2], int tid) {
   constexpr int NT = loop_threads<N>();
 #pragma unroll
-  for (int m = 0; m < BPT; m++) bin_spectrum<N, 2, double>(sm.src, g, tb, sm.buf, tid + NT * m, h[m]);
+  for (int m = 0; m < BPT; m++) {
+    if constexpr (std::is_same<F, double>::value) {
+      bin_spectrum<N, 2, double>(sm.src, g, tb, sm.buf, tid + NT * m, h[m]);
+    } else {
+      cx<F> hf[2];
+      bin_spectrum<N, 2, F>(sm.src, g, tb, reinterpret_cast<const cx<F>*>(sm.buf), tid + NT * m, hf);
+#pragma unroll
+      for (int c = 0; c < 2; c++) h[m][c] = cd{(double)hf[c].re, (double)hf[c].im};
+    }
+  }
 }
 
 template <int N, bool GW>
@@ -645,9 +657,10 @@ __device__ __forceinline__ double loop_dlogl(const Geo& g, LoopSmem<N, GW>& sm, 
   return g.df4 * sums[0] - 0.5 * g.df4 * sums[1];
 }
 
-template <int N, bool GW>
-__global__ __launch_bounds__(loop_threads<N>(), loop_waves<N>()) void k_sweep_band(Geo g, WaveTables<double> tb, SweepArgs a,
-                                                                      int move, int parity) {
+template <int N, bool GW, typename F>
+__global__ __launch_bounds__(loop_threads<N>(), loop_waves<N>()) void k_sweep_band(Geo g, WaveTables<F> tb,
+                                                                                    SweepArgs a, int move,
+                                                                                    int parity) {
   constexpr int NT = loop_threads<N>();
   constexpr int BPT = N / NT;  // window bins per thread
   __shared__ LoopSmem<N, GW> sm;
@@ -743,7 +756,7 @@ __global__ __launch_bounds__(loop_threads<N>(), loop_waves<N>()) void k_sweep_ba
     // them (addresses, twiddles, basis samples) are then recomputed in every
     // pass instead of being hoisted out of the loop, where they would stay
     // live across the whole kernel.
-    WaveTables<double> tbl = tb;
+    WaveTables<F> tbl = tb;
     asm volatile("" : "+v"(tid), "+s"(tbl.basis), "+s"(tbl.fft_tw), "+s"(tbl.bin_F), "+s"(tbl.bin_W));
     // ---- plan: advance the moves up to the next template build
     const double* ub = nullptr;
@@ -933,8 +946,8 @@ __global__ __launch_bounds__(loop_threads<N>(), loop_waves<N>()) void k_sweep_ba
     if (phase == 2) break;
 
     // ---- the template build (the only one)
-    loop_build<N, BPT, GW>(g, tbl, ub, sm, kind == kSetup ? nullptr : wts, wh, rsrc, kr, rv, wr, tid);
-    loop_bins<N, BPT, GW>(g, tbl, sm, hv, tid);
+    loop_build<N, BPT, GW, F>(g, tbl, ub, sm, kind == kSetup ? nullptr : wts, wh, rsrc, kr, rv, wr, tid);
+    loop_bins<N, BPT, GW, F>(g, tbl, sm, hv, tid);
     const int64_t kh = sm.src.q - N / 2;
     if (kind == kSetup) {
       // the band's residual: remove the slot's source, keep its spectrum

@@ -17,8 +17,9 @@ from paper_2405_04690_amd.sampler import Sweep
 pytestmark = pytest.mark.gpu
 
 
-def _gpu_sweep(cfg, sc, st, stream=None, pool=1024, window_sums=False):
-    ctx = Context(T=cfg.T, dt=cfg.dt, L=cfg.L, f_lo=cfg.f_lo, f_hi=cfg.f_hi, stream=stream)
+def _gpu_sweep(cfg, sc, st, stream=None, pool=1024, window_sums=False, precision=None):
+    kw = {} if precision is None else {"precision": precision}
+    ctx = Context(T=cfg.T, dt=cfg.dt, L=cfg.L, f_lo=cfg.f_lo, f_hi=cfg.f_hi, stream=stream, **kw)
     gc = SweepConfig()
     for name, _ in oracle.SweepConfig._fields_:
         v = getattr(sc, name)
@@ -568,3 +569,52 @@ def test_band_sets_share_the_cold_chain_buffers():
         _compare(swB, stB, f"set B, sweep {s}")
     assert stA.stats[1] > 0 and stB.stats[1] > 0 and stA.stats[7] > 0
     ctx.close()
+
+
+def test_mixed_precision_sweep_takes_the_fp64_decisions_but_near_the_threshold():
+    """Mixed-precision band loops (FP32 response and FFT; decode, phases,
+    spectra at the bins, windows and every sum in FP64) at the bench shape
+    (36 temperatures x 32 walkers x 60 slots, 1 yr): one full sweep from the
+    same state as the FP64 sweep.  A decision can differ only where the FP32
+    template error moves the log acceptance ratio across the draw, so almost
+    every (temperature, walker, sub-band) unit ends in the same state, the
+    acceptance counts agree closely, and a walker whose cold-chain units all
+    agree holds the same cold-chain buffers up to the FP32 template error."""
+    from paper_2405_04690_amd import inputs
+    from paper_2405_04690_amd.gbl import GBL_MIXED
+    print("mixed sweep: building the problem on the host", flush=True)
+    cfg, orc, sc, st = sampler_setup.problem(n_t=36, n_w=32, n_b=4, n_slots=60, n_prop=8, n_friends=40,
+                                             group_every=1, seed=92, beta_top=0.02, N=256, cfg=inputs.PAPER,
+                                             per_band=60)
+    ctx_bad, sw_bad = _gpu_sweep(cfg, sc, st, precision=GBL_MIXED)   # no window sums: refused
+    with pytest.raises(RuntimeError, match="window_sums"):
+        sw_bad.step(0, 1)
+    ctx_bad.close()
+    runs = {}
+    for name, prec in (("fp64", None), ("mixed", GBL_MIXED)):
+        print(f"mixed sweep: {name} sweep", flush=True)
+        ctx, sw = _gpu_sweep(cfg, sc, st, window_sums=True, precision=prec)
+        sw.sweep_counter.fill_(7)
+        sw.group_refresh()
+        for move in (0, 1, 2):
+            for parity in (1, 0):
+                sw.step(move, parity)
+        torch.cuda.synchronize()
+        runs[name] = {k: getattr(sw, k).cpu().numpy() for k in ("u", "exists", "resid", "stats")}
+        ctx.close()
+    a, b = runs["fp64"], runs["mixed"]
+    same = np.all(a["exists"] == b["exists"], axis=-1) & np.all(a["u"] == b["u"], axis=(-1, -2))  # [t][w][b]
+    frac = float(same.mean())
+    print(f"mixed sweep: identical units {frac:.4f}, stats fp64 {a['stats'][:8]} mixed {b['stats'][:8]}", flush=True)
+    assert frac >= 0.95
+    sa, sb = a["stats"].astype(np.float64), b["stats"].astype(np.float64)
+    # proposal counts follow the occupancy the RJ pass starts from, which the
+    # in-model pass does not change: equal; acceptance counts close
+    assert np.array_equal(sa[[0, 2, 4, 6]], sb[[0, 2, 4, 6]])
+    for acc in (1, 3, 5, 7):
+        assert abs(sa[acc] - sb[acc]) <= max(3.0, 0.02 * sa[acc]), acc
+    cold_same = np.all(same[0], axis=-1)  # walkers whose cold-chain units all agree
+    assert cold_same.sum() >= 0.75 * cold_same.size
+    for w in np.nonzero(cold_same)[0]:
+        ra, rb = a["resid"][:, w], b["resid"][:, w]
+        assert np.max(np.abs(ra - rb)) <= 1e-3 * np.max(np.abs(ra)), w
