@@ -30,24 +30,37 @@ FP64_PEAK_TFLOPS = 78.6   # MI355X FP64 vector (256 CU x 4 SIMD x 16 lanes x 2 f
 HBM_PEAK_GBS = 8000.0
 
 
+# first line of the library source's sampler section: the fused likelihood
+# kernels' launch code and the context set-up come before it
+SAMPLER_SECTION = b"// sampler sweep (Sec. 4"
+
+
+def traffic_source_sha256():
+    """sha256 over the sources the fused kernels (decode pass, FP64 N=256
+    likelihood change) and their launch are built from: the two kernel
+    headers and the library source up to its sampler section."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("gbl_device.hpp", "gbl_kernels.hpp", "gbl.hip"):
+        data = open(os.path.join(HERE, "paper_2405_04690_amd", "csrc", f), "rb").read()
+        if f == "gbl.hip":
+            cut = data.find(SAMPLER_SECTION)
+            data = data if cut < 0 else data[:cut]
+        h.update(f.encode())
+        h.update(data)
+    return h.hexdigest()
+
+
 def measured_traffic():
     """HBM-side bytes per launch of the fused FP64 N=256 kernel from the two
     rocprofv3 counter runs recorded under profiles/ (FETCH_SIZE, WRITE_SIZE,
     scaled by a plain copy of known size), or None once the kernel sources
     differ from the profiled ones."""
-    import hashlib
     path = os.path.join(HERE, "profiles", "k_delta_loglike_fp64_N256_traffic.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    # the sources the two kernels and their launch are built from
-    files = [os.path.join(HERE, "paper_2405_04690_amd", "csrc", f)
-             for f in ("gbl_device.hpp", "gbl_kernels.hpp", "gbl.hip")]
-    h = hashlib.sha256()
-    for f in files:
-        h.update(os.path.basename(f).encode())
-        h.update(open(f, "rb").read())
-    return rec["traffic_bytes_per_launch"] if h.hexdigest() == rec["source_sha256"] else None
+    return rec["traffic_bytes_per_launch"] if traffic_source_sha256() == rec["source_sha256"] else None
 
 
 def parse():
