@@ -161,10 +161,26 @@ def secondary(ctx, torch, stream, cfg, R, invS, po, pn, ri, pi):
     ms = _time_launches(torch, stream, lambda: ctx_m.gb_delta_loglike(R, invS, po, pn, cfg.N, ri, pi,
                                                                        psd_inverse=True, out=resm), 10)
     err = (resm - ref).abs()
+    # the error against the optimal SNR of the larger of the pair's two templates
+    snr_o, _ = ctx.gb_snr(po, cfg.N, invS, psd_inverse=True)
+    snr_n, _ = ctx.gb_snr(pn, cfg.N, invS, psd_inverse=True)
+    snr = torch.maximum(snr_o, snr_n)
+    edges = (0.0, 10.0, 30.0, 100.0, 300.0, float("inf"))
+
+    def by_snr(e):
+        rows = []
+        for lo, hi in zip(edges[:-1], edges[1:]):
+            m = (snr >= lo) & (snr < hi)
+            n = int(m.sum())
+            rows.append({"snr": [lo, hi if hi != float("inf") else None], "pairs": n,
+                         "max_abs_err": float(e[m].max()) if n else None,
+                         "median_abs_err": float(e[m].median()) if n else None})
+        return rows
     out["mixed_precision_N256"] = {"evals_per_s": round(B / (ms / 1e3), 1), "ms": round(ms, 4),
                                    "max_abs_err_vs_fp64": float(err.max()),
                                    "median_abs_err_vs_fp64": float(err.median()),
-                                   "frac_err_le_1e-3": float((err <= 1e-3).double().mean())}
+                                   "frac_err_le_1e-3": float((err <= 1e-3).double().mean()),
+                                   "err_by_snr": by_snr(err)}
     ctx_m.set_tuning(exact_grids=1)
     ms = _time_launches(torch, stream, lambda: ctx_m.gb_delta_loglike(R, invS, po, pn, cfg.N, ri, pi,
                                                                        psd_inverse=True, out=resm), 10)
@@ -180,7 +196,8 @@ def secondary(ctx, torch, stream, cfg, R, invS, po, pn, ri, pi):
     out["mixed_precision_N256_unrouted"] = {"evals_per_s": round(B / (ms / 1e3), 1), "ms": round(ms, 4),
                                             "max_abs_err_vs_fp64": float(err.max()),
                                             "median_abs_err_vs_fp64": float(err.median()),
-                                            "frac_err_le_1e-3": float((err <= 1e-3).double().mean())}
+                                            "frac_err_le_1e-3": float((err <= 1e-3).double().mean()),
+                                            "err_by_snr": by_snr(err)}
     ctx_u.close()
     # the band likelihood alone over stored slices (gb_inner): the new templates of
     # the headline batch written to HBM by gb_waveform, then <h|h> and <R|h>
@@ -505,11 +522,38 @@ def multiwidth_bench(torch, dev, stream, n_sweeps=1, n_temps=36, n_walkers=32, n
     for j, x in enumerate(info):
         x["ms_per_sweep"] = round(float(np.mean(per_set[j])), 1)
     total = marks[0].elapsed_time(marks[-1]) / n_sweeps
+    # the same band sets with mixed-precision band loops, from the current
+    # state on a context of their own (own copy of the shared buffers)
+    from paper_2405_04690_amd.gbl import GBL_MIXED
+    ctx_m = Context(T=T, dt=cfg.dt, L=cfg.L, f_lo=cfg.f_lo, f_hi=cfg.f_hi, precision=GBL_MIXED, device=dev,
+                    stream=stream)
+    resid_m = resid.clone()
+    msets = []
+    for sw in sets:
+        sm = Sweep(ctx_m, sw.cfg, window_sums=True, resid=resid_m, inv_psd=inv_psd)
+        for k in ("u", "exists", "betas", "group", "group_count", "sweep_counter"):
+            getattr(sm, k).copy_(getattr(sw, k))
+        msets.append(sm)
+    run_band_sets(msets, 1)
+    torch.cuda.synchronize()
+    mm = [ev() for _ in range(len(msets) * n_sweeps + 1)]
+    mm[0].record(stream)
+    for k in range(n_sweeps):
+        for j, sm in enumerate(msets):
+            sm.run(1)
+            mm[k * len(msets) + j + 1].record(stream)
+    torch.cuda.synchronize()
+    mixed = {"ms_per_sweep": round(mm[0].elapsed_time(mm[-1]) / n_sweeps, 1),
+             "sets_ms_per_sweep": [round(float(np.mean([mm[k * len(msets) + j].elapsed_time(mm[k * len(msets) + j + 1])
+                                                         for k in range(n_sweeps)])), 1) for j in range(len(msets))]}
+    del msets, resid_m
+    ctx_m.close()
     out = {"workload": "1 yr, 12000 sources log-uniform in 0.1-10 mHz, sub-bands of N = 128 / 256 / 512 / 1024 "
                        "bins by frequency (four band sets sharing the cold-chain buffers), 36 temps x 32 walkers, "
                        "up to 64 slots, n_prop=30, FP64",
            "sweeps": n_sweeps, "ms_per_sweep": round(total, 1), "sweeps_per_s": round(1e3 / total, 4),
-           "sources_dropped_beyond_slots": len(src) - sum(x["sources"] for x in info), "sets": info}
+           "sources_dropped_beyond_slots": len(src) - sum(x["sources"] for x in info), "sets": info,
+           "mixed_precision": mixed}
     del sets
     ctx.close()
     return out
