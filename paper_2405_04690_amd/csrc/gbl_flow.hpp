@@ -234,95 +234,143 @@ __device__ __forceinline__ void kept_of(const double* x, int parity, double* xc)
 // inference: ln q_u at given u (kSample = false) or samples from normals z
 // (kSample = true).  One wave per 16 samples; lanes with g = 0 own the state.
 // ---------------------------------------------------------------------------
+// One tile of 16 samples on the calling wave (every lane takes part): lane
+// (c, g) works on sample idx (the same for the four lanes of column c);
+// inb = false marks a column without a sample (no output).  `in` and `u_out`
+// may be the same buffer (each sample is read, then written, by the same
+// lane).
 template <bool kSample>
-// `in` and `u_out` may be the same buffer (each sample is read, then written,
-// by the same lane).
+__device__ __forceinline__ void flow_tile(const FlowArgs& fa, const double* in, const int32_t* __restrict__ band,
+                                          int64_t idx, bool inb, double* u_out, double* __restrict__ logq,
+                                          int lane) {
+  const int c = lane & 15, g = lane >> 4;
+  int b = inb ? (band ? band[idx] : (int)((idx / fa.band_div) % fa.band_mod)) : 0;
+  bool valid = inb && b >= 0 && b < fa.n_emb;
+  if (!valid) b = 0;
+  double lo[8], hi[8];
+  box_of(fa, b, lo, hi);
+  double x[8], lz = 0.0, logjac = 0.0, logdet = 0.0;
+#pragma unroll
+  for (int i = 0; i < 8; i++) {
+    const double v = valid ? in[idx * 8 + i] : 0.0;
+    if (kSample) {
+      x[i] = v;
+      lz += -0.5 * v * v;
+    } else {
+      const double w = hi[i] - lo[i];
+      const double p = (v - lo[i]) / w;
+      x[i] = log(p) - log1p(-p);
+      logjac += -log(w) - log(p) - log1p(-p);
+      if (!(p > 0.0 && p < 1.0)) valid = false;
+    }
+  }
+  if (!valid) {
+#pragma unroll
+    for (int i = 0; i < 8; i++) x[i] = 0.0;
+  }
+  float emb[16];
+  const float* E = fa.params + (int64_t)kLayers * kLayerParams + (int64_t)b * kEmb;
+#pragma unroll
+  for (int i = 0; i < 16; i++) emb[i] = E[i];
+  for (int step = 0; step < kLayers; step++) {
+    const int l = kSample ? kLayers - 1 - step : step;
+    const int par = l & 1;
+    double xc[4];
+    kept_of(x, par, xc);
+    CondOut co;
+    conditioner(fa.params + (int64_t)l * kLayerParams, fa.packed + (int64_t)l * kFragPerLayer * 64, lane,
+                h0_operand(g, xc, emb), co);
+    float tt[4];
+#pragma unroll
+    for (int j = 0; j < 4; j++) tt[j] = __shfl(co.o[j], c + 16, 64);
+    if (g == 0) {
+#pragma unroll
+      for (int j = 0; j < 4; j++) {
+        const double s = (double)(2.0f * tanhf(co.o[j]));
+        const double es = exp(s);
+        const int d = 2 * j + 1 - par;
+        double xd = par ? x[2 * j] : x[2 * j + 1];
+        xd = kSample ? (xd - (double)tt[j]) / es : xd * es + (double)tt[j];
+        if (par)
+          x[2 * j] = xd;
+        else
+          x[2 * j + 1] = xd;
+        (void)d;
+        logdet += s;
+      }
+    }
+  }
+  if (g == 0 && inb) {
+    if (!valid) {
+      if (kSample)
+        for (int i = 0; i < 8; i++) u_out[idx * 8 + i] = __builtin_nan("");
+      logq[idx] = __builtin_nan("");
+      return;
+    }
+    const double ln2pi_half = 0.91893853320467274178032973640562;
+    if (kSample) {
+      for (int i = 0; i < 8; i++) {
+        const double p = 1.0 / (1.0 + exp(-x[i]));
+        const double w = hi[i] - lo[i];
+        u_out[idx * 8 + i] = lo[i] + w * p;
+        logjac += -log(w) - log(p) - log1p(-p);
+      }
+      logq[idx] = lz - 8.0 * ln2pi_half + logdet + logjac;
+    } else {
+      double s2 = 0.0;
+      for (int i = 0; i < 8; i++) s2 += x[i] * x[i];
+      logq[idx] = -0.5 * s2 - 8.0 * ln2pi_half + logdet + logjac;
+    }
+  }
+}
+
+// Samples [0, B), or with a mask only those with mask[i] == mask_want.  Large
+// masked passes (one kind of RJ candidate out of all slots) gather their
+// samples first: each wave takes windows of up to 256 indices, collects the
+// matching ones in LDS by ballot and runs full tiles of 16 over them, so a
+// pass costs tiles in proportion to its samples, not to all slots; small
+// ones keep one tile per 16 slots, which spreads them over more waves.  A
+// sample's result does not depend on its tile-mates (each MFMA output column
+// belongs to one sample).
+template <bool kSample>
 __global__ __launch_bounds__(256) void k_flow_apply(FlowArgs fa, const double* in, const int32_t* __restrict__ band,
                                                    int64_t B, double* u_out, double* __restrict__ logq) {
   const int lane = threadIdx.x & 63;
-  const int c = lane & 15, g = lane >> 4;
-  const int64_t n_tiles = (B + 15) / 16;
-  for (int64_t tile = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); tile < n_tiles; tile += (int64_t)gridDim.x * 4) {
-    const int64_t idx = tile * 16 + c;
-    bool inb = idx < B;
-    if (inb && fa.mask && fa.mask[idx] != fa.mask_want) inb = false;  // not ours: no output
-    int b = inb ? (band ? band[idx] : (int)((idx / fa.band_div) % fa.band_mod)) : 0;
-    bool valid = inb && b >= 0 && b < fa.n_emb;
-    if (!valid) b = 0;
-    double lo[8], hi[8];
-    box_of(fa, b, lo, hi);
-    double x[8], lz = 0.0, logjac = 0.0, logdet = 0.0;
-#pragma unroll
-    for (int i = 0; i < 8; i++) {
-      const double v = valid ? in[idx * 8 + i] : 0.0;
-      if (kSample) {
-        x[i] = v;
-        lz += -0.5 * v * v;
-      } else {
-        const double w = hi[i] - lo[i];
-        const double p = (v - lo[i]) / w;
-        x[i] = log(p) - log1p(-p);
-        logjac += -log(w) - log(p) - log1p(-p);
-        if (!(p > 0.0 && p < 1.0)) valid = false;
-      }
+  const int wv = threadIdx.x >> 6;
+  constexpr int64_t kGatherMin = 4096LL * 64;  // below: too few windows to fill the chip
+  if (!fa.mask || B < kGatherMin) {
+    // tiles of 16 consecutive samples (masked-out samples ride along unwritten)
+    const int64_t n_tiles = (B + 15) / 16;
+    for (int64_t tile = (int64_t)blockIdx.x * 4 + wv; tile < n_tiles; tile += (int64_t)gridDim.x * 4) {
+      const int64_t idx = tile * 16 + (lane & 15);
+      const bool inb = idx < B && (!fa.mask || fa.mask[idx] == fa.mask_want);
+      flow_tile<kSample>(fa, in, band, idx, inb, u_out, logq, lane);
     }
-    if (!valid) {
-#pragma unroll
-      for (int i = 0; i < 8; i++) x[i] = 0.0;
+    return;
+  }
+  constexpr int kMaxWin = 256;
+  __shared__ int32_t found[4][kMaxWin];  // per wave: offsets of the window's matching samples
+  const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));  // lanes under this one
+  // windows of 64 k indices, k = 1, 2 or 4: as wide as leaves at least 4,096
+  // windows (16 per CU) to spread over the chip
+  const int nk = B >= 4096LL * 256 ? 4 : (B >= 4096LL * 128 ? 2 : 1);
+  const int64_t n_win = (B + 64 * nk - 1) / (64 * nk);
+  for (int64_t win = (int64_t)blockIdx.x * 4 + wv; win < n_win; win += (int64_t)gridDim.x * 4) {
+    const int64_t base = win * 64 * nk;
+    int cnt = 0;  // uniform over the wave
+    for (int k = 0; k < nk; k++) {
+      const int64_t i = base + 64 * k + lane;
+      const bool m = i < B && fa.mask[i] == fa.mask_want;
+      const uint64_t bal = __ballot(m);
+      if (m) found[wv][cnt + __popcll(bal & below)] = 64 * k + lane;
+      cnt += __popcll(bal);
     }
-    float emb[16];
-    const float* E = fa.params + (int64_t)kLayers * kLayerParams + (int64_t)b * kEmb;
-#pragma unroll
-    for (int i = 0; i < 16; i++) emb[i] = E[i];
-    for (int step = 0; step < kLayers; step++) {
-      const int l = kSample ? kLayers - 1 - step : step;
-      const int par = l & 1;
-      double xc[4];
-      kept_of(x, par, xc);
-      CondOut co;
-      conditioner(fa.params + (int64_t)l * kLayerParams, fa.packed + (int64_t)l * kFragPerLayer * 64, lane,
-                  h0_operand(g, xc, emb), co);
-      float tt[4];
-#pragma unroll
-      for (int j = 0; j < 4; j++) tt[j] = __shfl(co.o[j], c + 16, 64);
-      if (g == 0) {
-#pragma unroll
-        for (int j = 0; j < 4; j++) {
-          const double s = (double)(2.0f * tanhf(co.o[j]));
-          const double es = exp(s);
-          const int d = 2 * j + 1 - par;
-          double xd = par ? x[2 * j] : x[2 * j + 1];
-          xd = kSample ? (xd - (double)tt[j]) / es : xd * es + (double)tt[j];
-          if (par)
-            x[2 * j] = xd;
-          else
-            x[2 * j + 1] = xd;
-          (void)d;
-          logdet += s;
-        }
-      }
-    }
-    if (g == 0 && inb) {
-      if (!valid) {
-        if (kSample)
-          for (int i = 0; i < 8; i++) u_out[idx * 8 + i] = __builtin_nan("");
-        logq[idx] = __builtin_nan("");
-        continue;
-      }
-      const double ln2pi_half = 0.91893853320467274178032973640562;
-      if (kSample) {
-        for (int i = 0; i < 8; i++) {
-          const double p = 1.0 / (1.0 + exp(-x[i]));
-          const double w = hi[i] - lo[i];
-          u_out[idx * 8 + i] = lo[i] + w * p;
-          logjac += -log(w) - log(p) - log1p(-p);
-        }
-        logq[idx] = lz - 8.0 * ln2pi_half + logdet + logjac;
-      } else {
-        double s2 = 0.0;
-        for (int i = 0; i < 8; i++) s2 += x[i] * x[i];
-        logq[idx] = -0.5 * s2 - 8.0 * ln2pi_half + logdet + logjac;
-      }
+    // (a wave's LDS accesses complete in order: the reads below see the writes above)
+    for (int t0 = 0; t0 < cnt; t0 += 16) {
+      const int j = t0 + (lane & 15);
+      const bool inb = j < cnt;
+      const int64_t idx = inb ? base + found[wv][j] : 0;
+      flow_tile<kSample>(fa, in, band, idx, inb, u_out, logq, lane);
     }
   }
 }

@@ -618,3 +618,42 @@ def test_mixed_precision_sweep_takes_the_fp64_decisions_but_near_the_threshold()
     for w in np.nonzero(cold_same)[0]:
         ra, rb = a["resid"][:, w], b["resid"][:, w]
         assert np.max(np.abs(ra - rb)) <= 1e-3 * np.max(np.abs(ra)), w
+
+
+@pytest.mark.parametrize("shape", [(3, 4, 6, 4), (16, 32, 16, 40), (32, 32, 16, 40), (36, 32, 16, 60)])
+def test_rj_prepare_densities_equal_the_flow_density_call(shape):
+    """The RJ preparation's masked flow passes (current sources; prior
+    candidates) gather their slots into tiles by ballot before the flow runs
+    when there are at least 2^18 slots; each slot must still get the flow
+    density that the plain density call gives at its point (a non-identity
+    flow, mixed with the prior as in the sweep).  Shapes: 288 slots (no
+    gathering), 327,680 / 655,360 / 1,105,920 slots (gathering windows of 64,
+    128 and 256 slots)."""
+    from oracle import flow as oflow
+    from paper_2405_04690_amd.flow import Flow
+    n_t, n_w, n_b, n_s = shape
+    print(f"rj_prepare densities: shape {shape}", flush=True)
+    cfg, orc, sc, st = sampler_setup.problem(n_t=n_t, n_w=n_w, n_b=n_b, n_slots=n_s, seed=43)
+    ctx, sw = _gpu_sweep(cfg, sc, st)
+    w = 0.2
+    fc, th = _flow_for(sc, cfg, prior_weight=w)
+    fl = Flow(ctx, fc, th.astype(np.float32))
+    sw.sweep_counter.fill_(5)
+    sw.rj_prepare(fl)
+    torch.cuda.synchronize()
+    lo8, hi8 = np.array(list(sc.prior_lo)), np.array(list(sc.prior_hi))
+    lnV = np.array([np.sum(np.log(np.subtract(*oflow.box(np.array([b]), cfg.T, sc.k_band0, sc.N, lo8, hi8)[::-1])))
+                    for b in range(n_b)])
+    dev = sw.u.device
+    band = torch.arange(n_b, device=dev, dtype=torch.int32).view(1, 1, n_b, 1).expand(n_t, n_w, n_b, n_s)
+    mode, lq = sw.rj_mode, sw.rj_logq
+    for m, pts in ((0, sw.u), (2, sw.prop_u)):
+        sel = mode == m
+        assert int(sel.sum()) > 0
+        bb = band[sel].contiguous()
+        lf = fl.log_prob(pts[sel].contiguous(), bb).cpu().numpy()
+        lv = lnV[bb.cpu().numpy()]
+        ref = np.where(np.isnan(lf), np.log(w) - lv, np.logaddexp(np.log1p(-w) + lf, np.log(w) - lv))
+        got = lq[sel].cpu().numpy()
+        assert np.allclose(got, ref, rtol=1e-10, atol=1e-10), m
+    ctx.close()
