@@ -15,10 +15,12 @@ N = 128
 
 
 def problem(n_t=3, n_w=4, n_b=6, n_slots=4, n_prop=6, n_friends=4, group_every=1, seed=77, beta_top=0.3, N=N,
-            cfg=None, per_band=2, f_band0=3e-3, W=None):
+            cfg=None, per_band=2, f_band0=3e-3, W=None, edge=False):
     """per_band injections per sub-band, each held by one slot of every chain
     (jittered); cfg defaults to the 0.25 yr configuration; W: sub-band width
-    in bins (None: the template width N)"""
+    in bins (None: the template width N); edge: the injections' angles on the
+    edges of their ranges (cos iota = +-1, sin beta = +-1, phi0 = psi =
+    lambda = 0), which the chains' slots then hold exactly"""
     cfg = inputs.TINY if cfg is None else cfg
     orc = oracle.Oracle(T=cfg.T, dt=cfg.dt, L=cfg.L, f_lo=cfg.f_lo, f_hi=cfg.f_hi)
     k_band0 = int(f_band0 * cfg.T)
@@ -43,6 +45,11 @@ def problem(n_t=3, n_w=4, n_b=6, n_slots=4, n_prop=6, n_friends=4, group_every=1
                         np.arccos(rng.uniform(-1, 1)), rng.uniform(0, np.pi), rng.uniform(0, 2 * np.pi),
                         np.arcsin(rng.uniform(-1, 1))])
     src = np.array(src)
+    if edge:
+        for i in range(len(src)):
+            src[i, 3] = src[i, 5] = src[i, 6] = 0.0
+            src[i, 4] = 0.0 if i % 2 == 0 else np.pi             # cos iota = +1, -1
+            src[i, 7] = np.pi / 2 if (i // 2) % 2 == 0 else -np.pi / 2  # sin beta = +1, -1
     S = orc.psd_eval(np.array([cfg.sqrt_oms, cfg.sqrt_acc, cfg.sqrt_oms, cfg.sqrt_acc]))[0]
     data = np.sqrt(S / (4 * orc.df)) * inputs.complex_normals(seed + 1, (2, orc.n_bins))
     orc.scatter_add(src, N, 1.0, data)

@@ -657,3 +657,57 @@ def test_rj_prepare_densities_equal_the_flow_density_call(shape):
         got = lq[sel].cpu().numpy()
         assert np.allclose(got, ref, rtol=1e-10, atol=1e-10), m
     ctx.close()
+
+
+def test_sweep_parity_with_sources_on_the_prior_edges():
+    """every injected source and every slot holding it sits on the edges of
+    the angle ranges (cos iota = +-1, sin beta = +-1, phi0 = psi = lambda =
+    0): the band loops decode such coordinates directly (cos beta = 0 at sin
+    beta = +-1), and the stretch moves from them leave the box or wrap; one
+    full sweep against the oracle, decisions exact"""
+    cfg, orc, sc, st = sampler_setup.problem(seed=95, edge=True)
+    u = st.u[st.exists.astype(bool)]
+    assert np.all(np.abs(u[:, 4]) == 1.0) and np.all(np.abs(u[:, 7]) == 1.0) and np.all(u[:, [3, 5, 6]] == 0.0)
+    ctx, sw = _gpu_sweep(cfg, sc, st)
+    s0 = 13
+    sw.sweep_counter.fill_(s0)
+    oracle.sweep_group(sc, st)
+    sw.group_refresh()
+    for move, name in ((0, "in-model"), (1, "rj"), (2, "tempering")):
+        for parity in (1, 0):
+            print(f"prior edges: {name} parity {parity}", flush=True)
+            oracle.sweep_step(orc, sc, st, move, parity, s0)
+            sw.step(move, parity)
+            _compare(sw, st, f"edges {name}/{parity}")
+    assert st.stats[0] > 0 and st.stats[2] + st.stats[4] > 0
+    ctx.close()
+
+
+@pytest.mark.parametrize("N", [128, 512, 1024])
+def test_mixed_precision_band_loops_at_every_template_width(N):
+    """the FP32-response band loops at the other template widths (N = 512 and
+    1024 keep their windows in global memory), one full sweep against the
+    FP64 one from the same state: the same proposal counts, acceptance counts
+    within two, and at most one (temperature, walker, sub-band) unit in ten
+    ending elsewhere"""
+    from paper_2405_04690_amd.gbl import GBL_MIXED
+    cfg, orc, sc, st = sampler_setup.problem(N=N, n_b=4, n_t=3, n_w=8, n_slots=4, seed=97)
+    runs = {}
+    for name, prec in (("fp64", None), ("mixed", GBL_MIXED)):
+        print(f"mixed band loops N={N}: {name}", flush=True)
+        ctx, sw = _gpu_sweep(cfg, sc, st, window_sums=True, precision=prec)
+        sw.sweep_counter.fill_(3)
+        sw.group_refresh()
+        for move in (0, 1, 2):
+            for parity in (1, 0):
+                sw.step(move, parity)
+        torch.cuda.synchronize()
+        runs[name] = {k: getattr(sw, k).cpu().numpy() for k in ("u", "exists", "stats")}
+        ctx.close()
+    a, b = runs["fp64"], runs["mixed"]
+    same = np.all(a["exists"] == b["exists"], axis=-1) & np.all(a["u"] == b["u"], axis=(-1, -2))
+    assert same.mean() >= 0.9
+    sa, sb = a["stats"].astype(np.int64), b["stats"].astype(np.int64)
+    assert np.array_equal(sa[[0, 2, 4, 6]], sb[[0, 2, 4, 6]])
+    assert np.all(np.abs(sa[[1, 3, 5, 7]] - sb[[1, 3, 5, 7]]) <= 2)
+    assert sa[1] > 0 and sa[3] + sa[5] > 0
