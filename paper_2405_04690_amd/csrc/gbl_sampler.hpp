@@ -377,7 +377,7 @@ struct LoopSmem {
   double rdraw[kMaxSlots][9];     // RJ, per flip: acceptance draw, prior birth's coordinates;
                                   // in-model, per proposal: its four draws
   double red[2 * (loop_threads<N>() / kWave)];
-  double u_old[8], u_new[8], prm[8];
+  double u_old[8], u_new[8];
   double blo[8], bhi[8];      // the band's prior box in sampling coordinates (f0: the band's range,
                               // angles: one period)
   Src src;
