@@ -658,7 +658,13 @@ def _rj_summary(r):
         v = sd[k]
         out[name] = round(float(np.mean(v)), 4)
         out[name + "_range"] = [min(v), max(v)]
-    out["stationary_all_seeds"] = all(x["stationary"] for x in sd["stationarity"])
+    # both chains start from one state after the flow-mixture equilibration;
+    # their mean source count and cold logL over the measurement window are
+    # compared in units of the combined Monte Carlo error
+    out["means_agree_within_3_errors_all_seeds"] = all(x["stationary"] for x in sd["stationarity"])
+    out["means_note"] = ("the mean source count still drifts slowly after the equilibration (weak sources "
+                         "accumulate over thousands of sweeps), so the two proposals are compared over the same "
+                         "stretch of that drift")
     out["z_mean_k"] = [round(x["z_mean_k"], 2) for x in sd["stationarity"]]
     out["z_mean_logl"] = [round(x["z_mean_logl"], 2) for x in sd["stationarity"]]
     out["mean_k_plain_learned"] = sd["mean_k"]
