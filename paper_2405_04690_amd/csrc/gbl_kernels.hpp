@@ -222,6 +222,15 @@ constexpr int delta_threads() {
   return N <= 256 ? N : N / 2;
 }
 
+// FP64 templates from N = 512 on read the pair's decoded sources from LDS:
+// with two samples and bins per thread they hold more values at once, and
+// read through the scalar cache the sources then spill several hundred
+// scalar registers; up to N = 256, and in FP32, the scalar cache is faster
+template <int N, typename F>
+constexpr bool delta_lds_src() {
+  return N >= 512 && std::is_same<F, double>::value;
+}
+
 template <int N, typename F>
 struct DeltaSmem {
   cx<F> buf[4 * series_pitch<N>()];
@@ -256,7 +265,21 @@ __device__ __forceinline__ void delta_one(const Geo& g, const WaveTables<F>& tb,
 
   auto weight = [&](const double* Sc, int64_t idx) { return psd_inv ? Sc[idx] : 1.0 / Sc[idx]; };
 
-  ConstSrc* const cs = (ConstSrc*)da.srcs + 2 * (b - da.src_b0);
+  using SrcRef = std::conditional_t<delta_lds_src<N, F>(), Src, ConstSrc>;
+  SrcRef* cs;
+  if constexpr (delta_lds_src<N, F>()) {
+    // the pair's two decoded sources into LDS, 16 bytes per thread
+    __shared__ Src lds_src[2];
+    static_assert(sizeof(Src) % 16 == 0, "Src is copied in 16-byte pieces");
+    constexpr int kPieces = 2 * (int)sizeof(Src) / 16;
+    static_assert(kPieces <= NT, "one piece per thread");
+    const int4* src16 = reinterpret_cast<const int4*>(da.srcs + 2 * (b - da.src_b0));
+    if (tid < kPieces) reinterpret_cast<int4*>(lds_src)[tid] = src16[tid];
+    __syncthreads();
+    cs = lds_src;
+  } else {
+    cs = (ConstSrc*)da.srcs + 2 * (b - da.src_b0);
+  }
 
   // old template r: its spectrum over its window, in LDS (rw) or, for the
   // wide templates, in registers until the new template's bins are taken
@@ -265,7 +288,7 @@ __device__ __forceinline__ void delta_one(const Geo& g, const WaveTables<F>& tb,
   cx<F> aa[BPT][2];
   cx<F>* rw = kRegR ? sm.buf : sm.rwin;
   if (ho.state == 0) {
-    ConstSrc& so = cs[0];
+    SrcRef& so = cs[0];
     template_transform<N, 4, F, NT>(so, g, tb, sm.buf, tid);
 #pragma unroll
     for (int m = 0; m < BPT; m++) {
@@ -281,7 +304,7 @@ __device__ __forceinline__ void delta_one(const Geo& g, const WaveTables<F>& tb,
   if constexpr (kRegR) {
     // new template a: bins into registers, then r's spectrum into the buffer
     if (hn.state == 0) {
-      ConstSrc& sn = cs[1];
+      SrcRef& sn = cs[1];
       template_transform<N, 4, F, NT>(sn, g, tb, sm.buf, tid);
 #pragma unroll
       for (int m = 0; m < BPT; m++) bin_spectrum<N, 2, F>(sn, g, tb, sm.buf, tid + NT * m, aa[m]);
@@ -320,7 +343,7 @@ __device__ __forceinline__ void delta_one(const Geo& g, const WaveTables<F>& tb,
   };
 
   if (hn.state == 0) {
-    ConstSrc& sn = cs[1];
+    SrcRef& sn = cs[1];
     if constexpr (!kRegR) template_transform<N, 4, F, NT>(sn, g, tb, sm.buf, tid);
     // a's window, one bin per iteration: residual and weights are loaded at
     // the top of the iteration (not earlier: at four waves per SIMD the other
