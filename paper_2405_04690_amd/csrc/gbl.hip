@@ -909,9 +909,12 @@ template <int N>
 static void launch_sweep_step(gbl_ctx* ctx, const gbl::SweepArgs& a, int move, int parity) {
   const int nbp = (a.n_b - parity + 1) / 2;
   if (nbp <= 0) return;
-  if (move == GBL_MOVE_PT)
-    hipLaunchKernelGGL((gbl::k_sweep_pt<N>), dim3((unsigned)(nbp * a.n_w)), dim3(gbl::block_threads<N>()), 0,
+  if (move == GBL_MOVE_PT && a.wsum)
+    hipLaunchKernelGGL((gbl::k_sweep_pt<N, true>), dim3((unsigned)(nbp * a.n_w)), dim3(gbl::block_threads<N>()), 0,
                        ctx->stream, ctx->geo, tables_for<N, double>(ctx), a, parity);
+  else if (move == GBL_MOVE_PT)
+    hipLaunchKernelGGL((gbl::k_sweep_pt<N, false>), dim3((unsigned)(nbp * a.n_w)), dim3(gbl::block_threads<N>()),
+                       0, ctx->stream, ctx->geo, tables_for<N, double>(ctx), a, parity);
   else if (ctx->cfg.precision == GBL_MIXED)
     launch_band_loops<N, float>(ctx, a, move, parity, nbp);
   else

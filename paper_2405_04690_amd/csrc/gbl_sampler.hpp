@@ -1106,7 +1106,7 @@ __device__ __forceinline__ void band_set_sum(const Geo& g, const WaveTables<doub
 // L), R = walker w_res's opposite-parity buffer, weights 1/S of w_res
 template <int N>
 __device__ __forceinline__ double band_set_loglike_h(const Geo& g, const SweepArgs& a, int b, int w_res, int64_t k0w,
-                                                     int L, const cd* H, BandSmem<N>& sm) {
+                                                     int L, const cd* H, double* red) {
   constexpr int NT = block_threads<N>();
   const cd* opp = a.resid + ((int64_t)(1 - (b & 1)) * a.n_w + w_res) * 2 * g.n_bins;
   const double* ip = a.inv_psd + (int64_t)w_res * 2 * g.n_bins;
@@ -1121,15 +1121,24 @@ __device__ __forceinline__ double band_set_loglike_h(const Geo& g, const SweepAr
     }
   }
   double sums[1] = {rr};
-  block_allsum<NT>(sums, sm.red);
+  block_allsum<NT>(sums, red);
   rr = sums[0];
   return -0.5 * g.df4 * rr;
 }
 
+// LDS of the tempering kernel with window sums: the block reduction only
 template <int N>
+struct PtSumsSmem {
+  double red[2 * (block_threads<N>() / kWave)];
+  int entry;
+};
+
+// WS: the sweep carries window sums (every set's sum comes from the band
+// passes, no template is built here, and the LDS shrinks to the reduction)
+template <int N, bool WS>
 __global__ __launch_bounds__(block_threads<N>()) void k_sweep_pt(Geo g, WaveTables<double> tb, SweepArgs a,
                                                                  int parity) {
-  __shared__ BandSmem<N> sm;
+  __shared__ std::conditional_t<WS, PtSumsSmem<N>, BandSmem<N>> sm;
   __shared__ int wt[256];
   __shared__ double Lc[256];
   __shared__ int hidx[256];  // window sum of the set at temperature t: entry slot hidx[t]
@@ -1161,7 +1170,7 @@ __global__ __launch_bounds__(block_threads<N>()) void k_sweep_pt(Geo g, WaveTabl
   // window sums of the sets: from the band passes (wsum, entries that move
   // with the sets), else built here into a pool entry (hidx maps a
   // temperature to its set's sum), else recomputed on every evaluation
-  const bool ws = a.wsum != nullptr;
+  constexpr bool ws = WS;  // (the launch picks WS by a.wsum != nullptr)
   if (tid == 0) sm.entry = ws ? -1 : pool_acquire(a);
   for (int t = tid; t < nt; t += block_threads<N>()) hidx[t] = t;
   __syncthreads();
@@ -1170,11 +1179,11 @@ __global__ __launch_bounds__(block_threads<N>()) void k_sweep_pt(Geo g, WaveTabl
   auto Hof = [&](int t) { return ws ? wsum_entry<N>(a, t, wt[t], b) : Hp + (int64_t)hidx[t] * 6 * N; };
   for (int t = 0; t < nt; t++) {
     double lnl;
-    if (ws) {
-      lnl = band_set_loglike_h<N>(g, a, b, wt[t], k0w, L, Hof(t), sm);
+    if constexpr (WS) {
+      lnl = band_set_loglike_h<N>(g, a, b, wt[t], k0w, L, Hof(t), sm.red);
     } else if (Hs) {
       band_set_sum<N>(g, tb, a, t, wt[t], b, k0w, sm, Hof(t));
-      lnl = band_set_loglike_h<N>(g, a, b, wt[t], k0w, L, Hof(t), sm);
+      lnl = band_set_loglike_h<N>(g, a, b, wt[t], k0w, L, Hof(t), sm.red);
     } else {
       if constexpr (pt_lds_window<N>())
         lnl = band_set_loglike<N>(g, tb, a, t, wt[t], b, wt[t], k0w, sm);
@@ -1189,8 +1198,8 @@ __global__ __launch_bounds__(block_threads<N>()) void k_sweep_pt(Geo g, WaveTabl
   for (int t = nt - 1; t >= 1; t--) {
     // log-likelihood of the set at temperature ts against walker w_res's residual
     auto set_ll = [&](int ts, int w_res) -> double {
-      if (Hs) return band_set_loglike_h<N>(g, a, b, w_res, k0w, L, Hof(ts), sm);
-      if constexpr (pt_lds_window<N>())
+      if (Hs) return band_set_loglike_h<N>(g, a, b, w_res, k0w, L, Hof(ts), sm.red);
+      if constexpr (!WS && pt_lds_window<N>())
         return band_set_loglike<N>(g, tb, a, ts, wt[ts], b, w_res, k0w, sm);
       else
         return qnan();  // not reached: N = 1024 sweeps carry window sums
@@ -1221,7 +1230,7 @@ __global__ __launch_bounds__(block_threads<N>()) void k_sweep_pt(Geo g, WaveTabl
         }
         __syncthreads();
       } else if (t == 1) {
-        if constexpr (pt_lds_window<N>()) {
+        if constexpr (!WS && pt_lds_window<N>()) {
           // the cold chain of walker w_0 changes: own-parity buffer += old - new
           cd* own = a.resid + ((int64_t)(b & 1) * a.n_w + wt[0]) * 2 * g.n_bins;
           for (int s = 0; s < a.n_slot; s++) {
