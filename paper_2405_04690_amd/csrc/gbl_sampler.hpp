@@ -823,6 +823,10 @@ __global__ __launch_bounds__(loop_threads<N>(), loop_waves<N>()) void k_sweep_ba
           break;
         }
         if (pend) {
+          // every wave has read the removed template's decode and bins before
+          // the next decode overwrites them (this path has no other barrier
+          // since the removed template's build)
+          __syncthreads();
           ub = sm.u_new;
           kind = kNew;
           break;
