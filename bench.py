@@ -777,17 +777,19 @@ def _full_sweep(torch, ctx, sw, stream, d, n_bands, k_band0, N, n_temps, n_walke
     st = sw.stats.cpu().numpy()
     pst = ps.stats.cpu().numpy()
     ess = _sweep_ess(sw, fl, ess_sweeps) if ess_sweeps > 0 else None
-    sets = n_temps * n_walkers * 2   # refresh of every chain + one proposal per chain
-    # residual A+E per set evaluation (32 B/bin) and the shared PSD basis per pass
-    # (16 B/bin, three passes); the full-residual build (two buffers read and one
-    # written per walker, the data once: 32 B/bin each); the cold chains' 1/S (16 B/bin)
-    psd_bytes = (sets * 32 + 3 * 16 + (3 * n_walkers + 1) * 32 + n_walkers * 16) * ctx.n_bins
+    # distinct bytes: each walker's residual A+E (32 B/bin) once per pass over
+    # its chains (every chain, then two halves of the walkers), the shared PSD
+    # basis per pass (16 B/bin, three passes); the full-residual build (two
+    # buffers read and one written per walker, the data once: 32 B/bin each);
+    # the cold chains' 1/S (16 B/bin).  The sets of one walker's temperatures
+    # share its residual row, so per-set reads would count it n_temps times.
+    psd_bytes = (2 * n_walkers * 32 + 3 * 16 + (3 * n_walkers + 1) * 32 + n_walkers * 16) * ctx.n_bins
     return {"flow_train_s": round(train_s, 3), "flow_loss_first_last": [round(float(losses[0]), 3),
                                                                        round(float(losses[-1]), 3)],
             "gb_sweep_with_flow_ms": round(gb_ms, 3), "psd_step_ms": round(psd_ms, 3),
             "ms_per_sweep": round(gb_ms + psd_ms, 3), "graph_ms_per_sweep": round(graph_ms, 3),
             "sweeps_per_s": round(1e3 / (gb_ms + psd_ms), 4),
-            "psd_step_algorithmic_gbs": round(psd_bytes / (psd_ms / 1e3) / 1e9, 1),
+            "psd_step_distinct_gbs": round(psd_bytes / (psd_ms / 1e3) / 1e9, 1),
             "psd_acceptance": round(float(pst[1]) / max(1.0, float(pst[0])), 4),
             "psd_swap_acceptance": round(float(pst[3]) / max(1.0, float(pst[2])), 4),
             "birth_acceptance_total": round(float(st[3]) / max(1.0, float(st[2])), 4),

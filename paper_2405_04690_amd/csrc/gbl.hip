@@ -676,29 +676,38 @@ extern "C" int gb_psd_eval(gbl_ctx* ctx, const double* noise, int64_t P, int32_t
 // remainder one set per block), then the fixed-order final sum per set.
 template <int NP>
 static void psd_partial_launch(gbl_ctx* ctx, const cd* residual, int n_res, const double* noise,
-                               const int32_t* res_idx, int64_t p0, int64_t np, double* work) {
+                               const int32_t* res_idx, int64_t p0, int64_t np, double* work, int map_nt,
+                               int map_nw) {
   const int64_t ng = np / gbl::kPsdSets, rest = np - ng * gbl::kPsdSets;
   if (ng > 0)
     hipLaunchKernelGGL((gbl::k_psd_partial<gbl::kPsdSets, NP>), dim3(gbl::kPsdChunks, (unsigned)ng),
                        dim3(gbl::kPsdBlock), 0, ctx->stream, ctx->geo.n_bins, psd_basis(ctx), residual, n_res, noise,
-                       res_idx, p0, p0, work);
+                       res_idx, p0, p0, work, map_nt, map_nw);
   if (rest > 0)
     hipLaunchKernelGGL((gbl::k_psd_partial<1, NP>), dim3(gbl::kPsdChunks, (unsigned)rest), dim3(gbl::kPsdBlock), 0,
                        ctx->stream, ctx->geo.n_bins, psd_basis(ctx), residual, n_res, noise, res_idx, p0,
-                       p0 + ng * gbl::kPsdSets, work);
+                       p0 + ng * gbl::kPsdSets, work, map_nt, map_nw);
 }
 
 // work: [kPsdBatch][kPsdChunks][2] partial sums (the context's workspace, or
 // the static scratch for batches of at most kScratchSets sets)
+// tn_major_nt > 0: the P sets are tn_major_nt temperatures x P / tn_major_nt
+// walkers, temperature-major, each walker's sets on one residual row; the
+// blocks then take them walker-major (one row read per block of sets)
 static void psd_loglike_launch(gbl_ctx* ctx, const cd* residual, int n_res, const double* noise, int n_par,
-                               const int32_t* res_idx, int64_t P, double* logl, double* work = nullptr) {
+                               const int32_t* res_idx, int64_t P, double* logl, double* work = nullptr,
+                               int tn_major_nt = 0) {
   if (!work) work = ctx->psd_work;
+  const bool mapped = tn_major_nt > 0 && P <= kPsdBatch && P % tn_major_nt == 0 &&
+                      tn_major_nt % gbl::kPsdSets == 0;
+  const int map_nt = mapped ? tn_major_nt : 0;
+  const int map_nw = mapped ? (int)(P / tn_major_nt) : 0;
   for (int64_t p0 = 0; p0 < P; p0 += kPsdBatch) {
     const int64_t np = P - p0 < kPsdBatch ? P - p0 : kPsdBatch;
     if (n_par == 9)
-      psd_partial_launch<9>(ctx, residual, n_res, noise, res_idx, p0, np, work);
+      psd_partial_launch<9>(ctx, residual, n_res, noise, res_idx, p0, np, work, map_nt, map_nw);
     else
-      psd_partial_launch<4>(ctx, residual, n_res, noise, res_idx, p0, np, work);
+      psd_partial_launch<4>(ctx, residual, n_res, noise, res_idx, p0, np, work, map_nt, map_nw);
     hipLaunchKernelGGL(gbl::k_psd_final, dim3((unsigned)np), dim3(64), 0, ctx->stream, 1.0 / ctx->cfg.T, work, p0,
                        logl);
   }
@@ -1363,7 +1372,7 @@ extern "C" int gb_psd_sweep_step(gbl_ctx* ctx, const gbl_psd_sweep_config* c, co
   const int n_all = nt * nw, n_half = nt * half;
   hipLaunchKernelGGL(gbl::k_psd_res_idx, dim3((n_all + 255) / 256), dim3(256), 0, ctx->stream, nt, nw, -1,
                      st->res_idx);
-  psd_loglike_launch(ctx, full, nw, st->theta, p.np, st->res_idx, n_all, st->logl);
+  psd_loglike_launch(ctx, full, nw, st->theta, p.np, st->res_idx, n_all, st->logl, nullptr, nt);
   // 3. stretch moves, half by half
   double* prop = st->work;
   double* lprop = prop + (int64_t)p.np * n_half;
@@ -1373,7 +1382,7 @@ extern "C" int gb_psd_sweep_step(gbl_ctx* ctx, const gbl_psd_sweep_config* c, co
     hipLaunchKernelGGL(gbl::k_psd_propose, dim3((n_half + 255) / 256), dim3(256), 0, ctx->stream, p, h, prop, lz, ok);
     hipLaunchKernelGGL(gbl::k_psd_res_idx, dim3((n_half + 255) / 256), dim3(256), 0, ctx->stream, nt, nw, h,
                        st->res_idx);
-    psd_loglike_launch(ctx, full, nw, prop, p.np, st->res_idx, n_half, lprop);
+    psd_loglike_launch(ctx, full, nw, prop, p.np, st->res_idx, n_half, lprop, nullptr, nt);
     hipLaunchKernelGGL(gbl::k_psd_accept, dim3((n_half + 255) / 256), dim3(256), 0, ctx->stream, p, h,
                        (const double*)prop, (const double*)lprop, (const double*)lz, (const double*)ok);
   }

@@ -610,8 +610,16 @@ template <int G, int NP>
 __global__ __launch_bounds__(kPsdBlock) void k_psd_partial(int64_t nb, PsdBasis pb, const cd* __restrict__ residual,
                                                            int n_res, const double* __restrict__ noise,
                                                            const int32_t* __restrict__ res_idx, int64_t p0,
-                                                           int64_t p1st, double* __restrict__ work) {
+                                                           int64_t p1st, double* __restrict__ work, int map_nt,
+                                                           int map_nw) {
   const int64_t pg = p1st + (int64_t)blockIdx.y * G;
+  // set of slot s: pg + s, or with map_nt > 0 the batch's sets taken
+  // walker-major (the batch holds map_nt x map_nw sets, temperature-major),
+  // so that a block's sets share one residual row and read it once
+  auto set_of = [&](int s) -> int64_t {
+    const int64_t q = pg + s - p0;
+    return map_nt > 0 ? p0 + (q % map_nt) * map_nw + q / map_nt : pg + s;
+  };
   const int chunk = blockIdx.x;
   const int64_t cs = (nb + kPsdChunks - 1) / kPsdChunks;
   const int64_t lo = chunk * cs;
@@ -622,7 +630,7 @@ __global__ __launch_bounds__(kPsdBlock) void k_psd_partial(int64_t nb, PsdBasis 
   int le[G];
 #pragma unroll
   for (int s = 0; s < G; s++) {
-    const int64_t p = pg + s;
+    const int64_t p = set_of(s);
     const int ri = res_idx[p];
     R[s] = residual + (int64_t)(ri >= 0 && ri < n_res ? ri : 0) * 2 * nb;  // a bad index reports NaN below
     oA[s] = noise[NP * p] * noise[NP * p];
@@ -678,13 +686,14 @@ __global__ __launch_bounds__(kPsdBlock) void k_psd_partial(int64_t nb, PsdBasis 
   __syncthreads();
   if (threadIdx.x < G) {
     const int s = threadIdx.x;
-    const int ri = res_idx[pg + s];
+    const int64_t p = set_of(s);
+    const int ri = res_idx[p];
     double a = 0.0, c = 0.0;
     for (int i = 0; i < kPsdBlock / kWave; i++) {
       a += sq[s][i];
       c += sl[s][i];
     }
-    double* dst = work + 2 * ((pg + s - p0) * kPsdChunks + chunk);
+    double* dst = work + 2 * ((p - p0) * kPsdChunks + chunk);
     dst[0] = ri >= 0 && ri < n_res ? a : qnan();
     dst[1] = c;
   }
