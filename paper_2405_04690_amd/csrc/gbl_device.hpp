@@ -369,6 +369,17 @@ __constant__ PolyTable kPolyTable = {
 
 using CPoly = const __attribute__((address_space(4))) PolyTable;
 
+// One Horner step a v + c with the coefficient c in a scalar register pair,
+// as the three-operand FMA that reads it there.  Written out because the
+// compiler otherwise picks the two-operand form, whose addend is also its
+// destination: two vector moves copy the coefficient in before every step
+// of every lane's polynomial.  The rounding is that of fma(a, v, c).
+__device__ __forceinline__ double fma_sc(double a, double v, double c) {
+  double r;
+  asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(v), "s"(c));
+  return r;
+}
+
 __device__ __forceinline__ CPoly* poly_table() {
   CPoly* p = (CPoly*)&kPolyTable;
   asm volatile("" : "+s"(p));
@@ -382,46 +393,51 @@ __device__ __forceinline__ CPoly* poly_table() {
 // UC = 1: any |u| in band (above, with the library fallback); UC = 0: the
 // caller guarantees |u| <= 0.25 (templates below ~4.7 mHz), where sinc through
 // u^10 and cos through u^12 leave next terms below 1e-17 (u^12/13!, u^14/14!).
+// check = false: the caller guarantees |u| < 1.7 for every lane (no range
+// test; the result is the same, as the fallback would not be taken).
 template <int K, int UC = 1>
-__device__ __forceinline__ void sinc_cos_k(const double* u, double* sinc, double* cosu) {
+__device__ __forceinline__ void sinc_cos_k(const double* u, double* sinc, double* cosu, bool check = true) {
   CPoly* const tp = poly_table();
   const auto& cs_ = tp->sinc;
   const auto& cc_ = tp->cosu;
   constexpr int S0 = UC == 0 ? 5 : 0;  // first sinc coefficient used
   constexpr int C0 = UC == 0 ? 6 : 0;  // first cos coefficient used
   double v[K], a[K], c[K];
-  bool in_range = true;
 #pragma unroll
   for (int i = 0; i < K; i++) {
     v[i] = u[i] * u[i];
-    in_range = in_range && (v[i] <= 2.89);
     a[i] = cs_[S0];
     c[i] = cc_[C0];
   }
 #pragma unroll
   for (int k = S0 + 1; k < 10; k++) {
 #pragma unroll
-    for (int i = 0; i < K; i++) a[i] = a[i] * v[i] + cs_[k];
+    for (int i = 0; i < K; i++) a[i] = fma_sc(a[i], v[i], cs_[k]);
   }
 #pragma unroll
   for (int k = C0 + 1; k < 13; k++) {
 #pragma unroll
-    for (int i = 0; i < K; i++) c[i] = c[i] * v[i] + cc_[k];
+    for (int i = 0; i < K; i++) c[i] = fma_sc(c[i], v[i], cc_[k]);
   }
 #pragma unroll
   for (int i = 0; i < K; i++) {
     sinc[i] = 1.0 - a[i] * v[i];
     cosu[i] = c[i];
   }
-  if (UC != 0 && !in_range) {
-    // sources far above the band: exact library evaluation
+  if (UC != 0 && check) {
+    bool in_range = true;
 #pragma unroll
-    for (int i = 0; i < K; i++) sinc_cos(u[i], sinc[i], cosu[i]);
+    for (int i = 0; i < K; i++) in_range = in_range && (v[i] <= 2.89);
+    if (!in_range) {
+      // sources far above the band: exact library evaluation
+#pragma unroll
+      for (int i = 0; i < K; i++) sinc_cos(u[i], sinc[i], cosu[i]);
+    }
   }
 }
 
 template <int K, int UC = 1>
-__device__ __forceinline__ void sinc_cos_k(const float* u, float* sinc, float* cosu) {
+__device__ __forceinline__ void sinc_cos_k(const float* u, float* sinc, float* cosu, bool check = true) {
   // sinc through u^14 (next 1.7^16/17! < 1.4e-11), cos through u^14 (next < 2.3e-10)
   constexpr float cs_[7] = {-1.0f / 1307674368000.0f, 1.0f / 6227020800.0f, -1.0f / 39916800.0f,
                             1.0f / 362880.0f,         -1.0f / 5040.0f,      1.0f / 120.0f,
@@ -429,11 +445,9 @@ __device__ __forceinline__ void sinc_cos_k(const float* u, float* sinc, float* c
   constexpr float cc_[8] = {-1.0f / 87178291200.0f, 1.0f / 479001600.0f, -1.0f / 3628800.0f, 1.0f / 40320.0f,
                             -1.0f / 720.0f,         1.0f / 24.0f,        -0.5f,              1.0f};
   float v[K], a[K], c[K];
-  bool in_range = true;
 #pragma unroll
   for (int i = 0; i < K; i++) {
     v[i] = u[i] * u[i];
-    in_range = in_range && (v[i] <= 2.89f);
     a[i] = cs_[0];
     c[i] = cc_[0];
   }
@@ -451,6 +465,11 @@ __device__ __forceinline__ void sinc_cos_k(const float* u, float* sinc, float* c
   for (int i = 0; i < K; i++) {
     sinc[i] = a[i] * v[i] + 1.0f;
     cosu[i] = c[i];
+  }
+  bool in_range = true;
+  if (check) {
+#pragma unroll
+    for (int i = 0; i < K; i++) in_range = in_range && (v[i] <= 2.89f);
   }
   if (!in_range) {
 #pragma unroll
@@ -502,15 +521,19 @@ __device__ __forceinline__ void expi_cycles_k(const double* c, cx<F>* out) {
     sn[i] = ps(0);
     cs[i] = pc(0);
   }
+  // FP64: the coefficients stay in scalar registers (fma_sc)
+  auto step = [&](F a, F x2, F c) -> F {
+    if constexpr (kTbl) return fma_sc(a, x2, c); else return a * x2 + c;
+  };
 #pragma unroll
   for (int k = 1; k < P::NS; k++) {
 #pragma unroll
-    for (int i = 0; i < K; i++) sn[i] = sn[i] * v[i] + ps(k);
+    for (int i = 0; i < K; i++) sn[i] = step(sn[i], v[i], ps(k));
   }
 #pragma unroll
   for (int k = 1; k < P::NC; k++) {
 #pragma unroll
-    for (int i = 0; i < K; i++) cs[i] = cs[i] * v[i] + pc(k);
+    for (int i = 0; i < K; i++) cs[i] = step(cs[i], v[i], pc(k));
   }
 #pragma unroll
   for (int i = 0; i < K; i++) {
@@ -539,7 +562,7 @@ __device__ __forceinline__ void expi_cycles_k(const double* c, cx<F>* out) {
 // through the scalar cache)
 template <int NSER, typename F, int UC = 1, typename S = Src>
 __device__ __forceinline__ void slow_sample(const S& s, const Geo& g, const double* __restrict__ basis, int n,
-                                            double t, cx<F>* out) {
+                                            double t, cx<F>* out, bool check = true) {
   const double ca = basis[4 * n + 0], sa = basis[4 * n + 1];
   const double c2a = basis[4 * n + 2], s2a = basis[4 * n + 3];
   auto affine = [&](const auto* c) { return c[4] + c[0] * ca + c[1] * sa + c[2] * c2a + c[3] * s2a; };
@@ -583,7 +606,7 @@ __device__ __forceinline__ void slow_sample(const S& s, const Geo& g, const doub
     amp[l] = piLc * fr[l / 2] - dterm * om;
     u[l] = om * amp[l];
   }
-  sinc_cos_k<6, UC>(u, sc, cu);
+  sinc_cos_k<6, UC>(u, sc, cu, check);
   // w exp(-i u) with w = amp sinc(u)
   cx<F> wz[6];
 #pragma unroll
@@ -778,16 +801,35 @@ template <int N, int R, int ST, int NSER, int NT, typename F>
 __device__ __forceinline__ void fft_pass(cx<F>* buf, const cx<F>* __restrict__ tw, int tid) {
   constexpr int NB = N / R;  // butterflies per series
   constexpr int SP = series_pitch<N>();
+  // where the butterflies divide evenly over the lanes, every lane runs the
+  // same number of them: a uniform loop without per-lane exit masks
   if constexpr (fft_wave_local<NSER, NT>()) {
     constexpr int SPW = NSER / (NT / kWave);  // series per wave
     const int w = tid / kWave, lane = tid % kWave;
+    if constexpr ((SPW * NB) % kWave == 0) {
 #pragma unroll 1
-    for (int item = lane; item < SPW * NB; item += kWave)
-      fft_butterfly<N, R, ST>(buf + (w * SPW + item / NB) * SP, tw, item % NB);
+      for (int it = 0; it < SPW * NB / kWave; it++) {
+        const int item = lane + it * kWave;
+        fft_butterfly<N, R, ST>(buf + (w * SPW + item / NB) * SP, tw, item % NB);
+      }
+    } else {
+#pragma unroll 1
+      for (int item = lane; item < SPW * NB; item += kWave)
+        fft_butterfly<N, R, ST>(buf + (w * SPW + item / NB) * SP, tw, item % NB);
+    }
     wave_sync();
   } else {
+    if constexpr ((NSER * NB) % NT == 0) {
 #pragma unroll 1
-    for (int item = tid; item < NSER * NB; item += NT) fft_butterfly<N, R, ST>(buf + (item / NB) * SP, tw, item % NB);
+      for (int it = 0; it < NSER * NB / NT; it++) {
+        const int item = tid + it * NT;
+        fft_butterfly<N, R, ST>(buf + (item / NB) * SP, tw, item % NB);
+      }
+    } else {
+#pragma unroll 1
+      for (int item = tid; item < NSER * NB; item += NT)
+        fft_butterfly<N, R, ST>(buf + (item / NB) * SP, tw, item % NB);
+    }
     __syncthreads();
   }
 }
@@ -809,31 +851,40 @@ __device__ __forceinline__ void fft_stages(cx<F>* buf, const cx<F>* __restrict__
 // spectrum at any window bin j from the transformed U/V series in LDS.
 // Ends with a barrier, so the caller may read the workspace immediately.
 // ---------------------------------------------------------------------------
-template <int N, int NSER, typename F, int NT = block_threads<N>(), typename S = Src>
+template <int N, int NSER, typename F, int NT = block_threads<N>(), bool kUniform = false, typename S = Src>
 __device__ __forceinline__ void template_transform(const S& s, const Geo& g, const WaveTables<F>& tb,
                                                    cx<F>* buf, int tid) {
   constexpr int SP = series_pitch<N>();
+  // kUniform: where N divides evenly over the block, every thread runs the
+  // same number of samples (a loop without per-lane exit masks; the FFT
+  // passes already take every thread id below NT).  It pays in the sampler's
+  // band loops; the fused likelihood kernel runs faster with the per-lane
+  // loop, which the compiler schedules differently.
+  constexpr bool kEven = kUniform && N % NT == 0;
+  constexpr int NIT = (N + NT - 1) / NT;
   // link phases u = (1 -+ k.n) (pi f L/c - ...) stay below 2 pi (L/c) f_max plus
   // a tiny fdot term, and so do the receiver phase offsets
   // 2 pi (cyc_r - cyc_0) = 2 pi (k.x_r - k.x_0)/c (-f + fdot (k.x_r + k.x_0)/(2c))
   // with |k.x_r - k.x_0| <= L and |k.x_r| <= AU + 2L: block-uniform choice of
   // the short series for both (FP64 only; the FP32 series are short already)
   const double f_max = fabs(s.f0) + fabs(s.fdot) * (g.T + 1100.0);
-  const bool small_u = std::is_same<F, double>::value &&
-                       2.0 * kPi * g.Lc * (f_max + fabs(s.fdot) * (kAU / kC + 2.0 * g.Lc)) <= 0.25;
+  const double u_max = 2.0 * kPi * g.Lc * (f_max + fabs(s.fdot) * (kAU / kC + 2.0 * g.Lc));
+  const bool small_u = std::is_same<F, double>::value && u_max <= 0.25;
+  // every link phase below 1.7 (sources in band): no per-lane range test
+  const bool check = !(u_max <= 1.69);
   if constexpr (!std::is_same<F, double>::value) {
 #pragma unroll 1
-    for (int n = tid; n < N; n += NT) {
+    for (int it = 0, n = tid; kEven ? it < NIT : n < N; it++, n += NT) {
       double t = ((double)n + 0.5) * g.T / (double)N;
       cx<F> v[6];
-      slow_sample<NSER, F, 1, S>(s, g, tb.basis, n, t, v);
+      slow_sample<NSER, F, 1, S>(s, g, tb.basis, n, t, v, check);
       const int a = lds_pad<N>(n);
 #pragma unroll
       for (int c = 0; c < NSER; c++) buf[c * SP + a] = v[c];
     }
   } else if (small_u) {
 #pragma unroll 1
-    for (int n = tid; n < N; n += NT) {
+    for (int it = 0, n = tid; kEven ? it < NIT : n < N; it++, n += NT) {
       double t = ((double)n + 0.5) * g.T / (double)N;
       cx<F> v[6];
       slow_sample<NSER, F, 0, S>(s, g, tb.basis, n, t, v);
@@ -843,10 +894,10 @@ __device__ __forceinline__ void template_transform(const S& s, const Geo& g, con
     }
   } else {
 #pragma unroll 1
-    for (int n = tid; n < N; n += NT) {
+    for (int it = 0, n = tid; kEven ? it < NIT : n < N; it++, n += NT) {
       double t = ((double)n + 0.5) * g.T / (double)N;
       cx<F> v[6];
-      slow_sample<NSER, F, 1, S>(s, g, tb.basis, n, t, v);
+      slow_sample<NSER, F, 1, S>(s, g, tb.basis, n, t, v, check);
       const int a = lds_pad<N>(n);
 #pragma unroll
       for (int c = 0; c < NSER; c++) buf[c * SP + a] = v[c];

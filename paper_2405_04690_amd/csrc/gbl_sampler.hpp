@@ -557,7 +557,7 @@ __device__ __forceinline__ void loop_build(const Geo& g, const WaveTables<F>& tb
     loop_load<N, BPT>(rsrc, rv, tid);
     loop_weights<N, BPT>(g, wts, kr, wr, tid);
   }
-  template_transform<N, 4, F, loop_threads<N>()>(sm.src, g, tb, reinterpret_cast<cx<F>*>(sm.buf), tid);
+  template_transform<N, 4, F, loop_threads<N>(), true>(sm.src, g, tb, reinterpret_cast<cx<F>*>(sm.buf), tid);
 }
 
 // spectrum of the built template at the thread's bins (in FP64 whatever the
