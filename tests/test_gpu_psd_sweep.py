@@ -16,8 +16,12 @@ LO = (10e-12, 2e-15, 10e-12, 2e-15)
 HI = (20e-12, 4e-15, 20e-12, 4e-15)
 
 
-def test_psd_step_matches_oracle():
-    nt, nw = 3, 6
+# (3, 6): sets in launch order; (8, 6) and the benchmark's 36 x 32: the
+# temperature count is a multiple of four, so the likelihood launches hand
+# each block four temperatures of one walker (sets taken walker-major)
+@pytest.mark.parametrize("nt,nw", [(3, 6), (8, 6), (36, 32)])
+def test_psd_step_matches_oracle(nt, nw):
+    print(f"psd step parity nt={nt} nw={nw}", flush=True)
     orc = oracle.Oracle(T=CFG.T, dt=CFG.dt, L=CFG.L, f_lo=CFG.f_lo, f_hi=CFG.f_hi)
     S = orc.psd_eval(np.array([CFG.sqrt_oms, CFG.sqrt_acc, CFG.sqrt_oms, CFG.sqrt_acc]))[0]
     amp = np.sqrt(S / (4 * orc.df))
@@ -27,7 +31,7 @@ def test_psd_step_matches_oracle():
     resid = np.stack([data[None] + x, data[None] - x + y])       # full residual = data + y
     rng = np.random.default_rng(804)
     theta = np.array(LO) + (np.array(HI) - np.array(LO)) * rng.uniform(size=(nt, nw, 4))
-    betas = np.array([1.0, 0.5, 0.2])
+    betas = np.array([1.0, 0.5, 0.2]) if nt == 3 else np.geomspace(1.0, 0.05, nt)
     pco = oracle.PsdSweepConfig()
     pco.n_tn, pco.n_walkers, pco.n_par, pco.stretch_a, pco.seed = nt, nw, 4, 2.0, 805
     for k in range(4):
